@@ -1,0 +1,259 @@
+/*
+ * invaskit.h -- C ABI of the MI355X (gfx950) INV-ASKIT factor/solve library.
+ *
+ * The library factors A = lambda*I + K~ and solves A x = b, where K~ is the
+ * ASKIT hierarchical (HODLR-type) approximation of a Gaussian kernel matrix
+ * (Yu, March, Xiao, Biros, "INV-ASKIT: A Parallel Fast Direct Solver for
+ * Kernel Matrices", Section II).  The tree, skeletons and interpolation
+ * matrices P are inputs, produced by a separate setup step.
+ *
+ * Conventions shared by every entry point:
+ *  - Every function returns an int status: INVASKIT_OK (0) or a negative
+ *    INVASKIT_E_* code.  Nothing throws or aborts across the ABI.  The text
+ *    of the last error is available from invaskit_last_error().
+ *  - "DEVICE" pointers are HIP device memory on the current device; "HOST"
+ *    pointers are ordinary host memory.  Matrices are column-major unless
+ *    stated otherwise; all point and vector data is in tree order (the order
+ *    in which every tree node owns a contiguous range).
+ *  - Nodes use heap numbering: root 0, children of node i are 2i+1 (left)
+ *    and 2i+2 (right); level k holds nodes 2^k-1 .. 2^(k+1)-2; every leaf is
+ *    at level `depth`.
+ *  - All GPU work is enqueued on the stream given to invaskit_factor(); the
+ *    calls that must read results back (factor: pivot status; solve: refine
+ *    residuals) synchronize that stream before returning.
+ *  - One handle may be used by one host thread at a time.
+ */
+#ifndef INVASKIT_H
+#define INVASKIT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define INVASKIT_OK               0
+#define INVASKIT_E_ARG           -1 /* invalid argument; nothing was launched  */
+#define INVASKIT_E_MEMORY        -2 /* device allocation failed                */
+#define INVASKIT_E_HIP           -3 /* a HIP runtime call failed               */
+#define INVASKIT_E_SINGULAR      -4 /* zero or non-finite pivot (node named)   */
+#define INVASKIT_E_NOT_CONVERGED -5 /* refinement stalled or hit its cap       */
+#define INVASKIT_E_DEVICE        -6 /* no usable gfx950 device                 */
+
+/* element types */
+#define INVASKIT_F64 0
+#define INVASKIT_F32 1
+
+/* precision modes */
+#define INVASKIT_PREC_FP64  0 /* every step in FP64                               */
+#define INVASKIT_PREC_MIXED 1 /* FP32 factors, FP64 top-level reduced systems,
+                                 FP64 residuals and updates, iterative refinement */
+
+/*
+ * Problem description (Section II-B, II-C).  N points in d dimensions,
+ * ordered by a complete binary tree of depth L with 2^L leaves.
+ *
+ *  points        DEVICE, n x d row-major, element type points_dtype.
+ *                Borrowed: must stay valid and unchanged until
+ *                invaskit_destroy(), because solve/matvec re-read it.
+ *  leaf_offsets  HOST, 2^L + 1 entries: leaf j owns points
+ *                [leaf_offsets[j], leaf_offsets[j+1]); [0] = 0, last = n,
+ *                every leaf non-empty and at most 4096 points.  Copied.
+ *  skel_offsets  HOST, 2^(L+1) entries (n_nodes + 1): node c's skeleton is
+ *                skel_index[skel_offsets[c] .. skel_offsets[c+1]).  The root
+ *                has none; every other node has 1..1024 skeleton points.
+ *                Copied.
+ *  skel_index    HOST, tree-order point ids.  A leaf's skeleton lies in the
+ *                leaf; an internal node's skeleton is a subset of its
+ *                children's skeletons (nested skeletons).  Copied.
+ *  p_offsets     HOST, n_nodes + 1 entries into p_values.  Copied.
+ *  p_values      DEVICE, FP64.  Leaf c: P_{c~ c}, s_c x |c| row-major, columns
+ *                in the leaf's point order.  Internal c: P_{c~ [l~ r~]},
+ *                s_c x (s_l + s_r) row-major, columns [l~ | r~].  Borrowed
+ *                like `points`.
+ *  h             Gaussian bandwidth, K(x,y) = exp(-|x-y|^2 / (2 h^2)).
+ */
+typedef struct invaskit_problem {
+  int64_t n;
+  int32_t d;
+  int32_t depth;
+  int32_t points_dtype; /* INVASKIT_F64 or INVASKIT_F32 */
+  int32_t reserved0;
+  const void* points;
+  const int64_t* leaf_offsets;
+  const int64_t* skel_offsets;
+  const int32_t* skel_index;
+  const int64_t* p_offsets;
+  const double* p_values;
+  double h;
+} invaskit_problem;
+
+typedef struct invaskit_options {
+  int32_t precision;        /* INVASKIT_PREC_FP64 (default) or _MIXED            */
+  int32_t fp64_top_levels;  /* mixed mode: reduced systems at levels < this are
+                               factored in FP64 (default 4)                       */
+  double refine_tol;        /* mixed mode: stop when |b - A x|_2 / |b|_2 <= tol
+                               for every column (default 1e-10)                   */
+  int32_t max_refine_iters; /* mixed mode: iteration cap (default 30)             */
+  int32_t reserved0;
+} invaskit_options;
+
+typedef struct invaskit_solve_info {
+  int32_t iterations;            /* refinement iterations taken (0 in FP64 mode) */
+  int32_t converged;             /* 1 when every column met refine_tol           */
+  double final_rel_residual;     /* max over columns of |b - A x| / |b|, FP64   */
+  double unrefined_rel_residual; /* same after the first low-precision solve     */
+} invaskit_solve_info;
+
+typedef struct invaskit_handle_s* invaskit_handle;
+
+/* Fill *opt with the defaults listed above. */
+int invaskit_default_options(invaskit_options* opt);
+
+/*
+ * Factor lambda*I + K~ (Algorithm 1, Factorize, done level by level
+ * bottom-up): LU with partial pivoting of every leaf block
+ * lambda*I + K_{aa}; for every level k = L..1 the skeleton blocks
+ * K_{c, sibling~} (eq. e:offdiag-askit) solved through c's subtree
+ * (Algorithm 2) to give W; the reduced systems
+ * [[I, P_{r~r} W_{r l~}], [P_{l~l} W_{l r~}, I]] of eq. (e:blocksmw) and
+ * their LU.  lambda enters only the leaf diagonal blocks.
+ *
+ * Validates every input on the host before any launch (E_ARG).  Allocates
+ * the factorization's device memory itself (its size: invaskit_device_bytes);
+ * the handle owns it until invaskit_destroy().  hip_stream may be NULL (the
+ * null stream).  Synchronizes the stream once at the end to read the pivot
+ * status: a zero or non-finite pivot returns E_SINGULAR, names the node in
+ * invaskit_last_error(), and still returns the handle in *out.
+ */
+int invaskit_factor(const invaskit_problem* problem, double lambda,
+                    const invaskit_options* options, void* hip_stream,
+                    invaskit_handle* out);
+
+/*
+ * Refactor an existing handle for a new lambda (Section II-C, refactoring
+ * for a different lambda): skeletons and P are reused, leaf LU, W and the
+ * reduced systems are recomputed.  Same errors as invaskit_factor.
+ */
+int invaskit_refactor(invaskit_handle handle, double lambda);
+
+/*
+ * x = (lambda*I + K~)^-1 b (Algorithm 2, Solve, done bottom-up).
+ * b, x: DEVICE, FP64, n x nrhs column-major with leading dimensions
+ * ldb, ldx >= n; they must not overlap.  In mixed mode the solve is
+ * iterative refinement: FP32 solves against the FP32 factors, residuals
+ * b - (lambda*I + K~) x by the FP64 hierarchical product (invaskit_matvec),
+ * FP64 updates, until every column satisfies refine_tol; E_NOT_CONVERGED if
+ * the cap is hit or the residual stops shrinking (x then holds the best
+ * iterate).  In FP64 mode the solve is direct and info->final_rel_residual
+ * is computed with the same FP64 product.  info may be NULL.
+ */
+int invaskit_solve(invaskit_handle handle, const double* b, int64_t nrhs, int64_t ldb,
+                   double* x, int64_t ldx, invaskit_solve_info* info);
+
+/*
+ * y = (lambda*I + K~) x in FP64, by the ASKIT Skeletonize upward pass and
+ * the Evaluate traversal with separation "i not in node" (Section II-B):
+ * exact leaf blocks plus K_{i, c~} P_{c~ c} x_c for every node c that
+ * does not contain i but whose parent does.  x, y: DEVICE FP64,
+ * n x nrhs column-major, must not overlap.
+ */
+int invaskit_matvec(invaskit_handle handle, const double* x, int64_t nrhs, int64_t ldx,
+                    double* y, int64_t ldy);
+
+/* Device bytes held by the handle (factors, tables, scratch). */
+int invaskit_device_bytes(invaskit_handle handle, size_t* bytes);
+
+/*
+ * Milliseconds spent in the phases of the last factor (HIP events, stream
+ * time): [0] leaf blocks + LU, [1] skeleton blocks, [2] leaf solves,
+ * [3] leaf projections, [4] skeleton sweep, [5] deferred corrections,
+ * [6] reduced systems + LU, [7] total.  Writes min(n, 8) values.
+ */
+int invaskit_phase_times(invaskit_handle handle, double* ms, int32_t n);
+
+/* Release the handle and its device memory.  Borrowed buffers are untouched. */
+int invaskit_destroy(invaskit_handle handle);
+
+/* Static text for a status code. */
+const char* invaskit_status_string(int status);
+
+/* Copy the last error message of `handle` (or of the calling thread's last
+ * handle-less call when handle is NULL) into buf (NUL-terminated). */
+int invaskit_last_error(invaskit_handle handle, char* buf, size_t n);
+
+/* ---------------------------------------------------------------------------
+ * Batched building blocks, exposed for unit testing and for callers that
+ * assemble their own hierarchy.  All run on `hip_stream` and return after
+ * enqueueing (no synchronization) unless noted.
+ * ------------------------------------------------------------------------- */
+
+/*
+ * LU with partial pivoting (LAPACK getrf semantics: pivot = first row of
+ * largest magnitude) of `count` square matrices of uneven order in one
+ * launch -- the leaf LU of Algorithm 1 and the LU of the reduced systems.
+ *  a        DEVICE, element type dtype; matrix i is n[i] x n[i] column-major
+ *           with leading dimension n[i], starting at element a_offsets[i];
+ *           overwritten by L (unit lower, below the diagonal) and U.
+ *  a_offsets, n  HOST, count entries; 1 <= n[i] <= 1024.
+ *  perm     DEVICE int32, sum(n) entries; matrix i's block starts at the sum
+ *           of the preceding n: perm[j] = original row placed at row j.
+ *  info     DEVICE int32, count entries: 0, or j+1 for the first zero or
+ *           non-finite pivot in column j.
+ */
+int invaskit_getrf_batched(int32_t dtype, void* a, const int64_t* a_offsets,
+                           const int32_t* n, int32_t count, int32_t* perm,
+                           int32_t* info, void* hip_stream);
+
+/*
+ * Solve A_i X_i = B_i in place with the factors of invaskit_getrf_batched
+ * (row permutation, unit-lower L, upper U).  b: DEVICE, element type dtype;
+ * system i has nrhs[i] columns with leading dimension ldb[i] >= n[i] and
+ * starts at element b_offsets[i].  a_offsets, n, nrhs, ldb, b_offsets: HOST.
+ */
+int invaskit_getrs_batched(int32_t dtype, const void* a, const int64_t* a_offsets,
+                           const int32_t* n, const int32_t* perm, void* b,
+                           const int64_t* b_offsets, const int32_t* nrhs,
+                           const int64_t* ldb, int32_t count, void* hip_stream);
+
+/*
+ * Gaussian kernel blocks (eq. e:gaussian): out_i[r, c] =
+ * K(x[row0_i + r], x[col_i(c)]) + (diag_i && r == c ? shift : 0), where
+ * col_i(c) = cols[cols_offsets[i] + c].  Squared distances are formed by
+ * direct differences in FP64.  points: DEVICE n x d row-major of
+ * points_dtype; cols: DEVICE int32; out: DEVICE element type out_dtype,
+ * block i is rows_i x ncols_i column-major (ld = rows_i) at element
+ * out_offsets[i].  All other arrays HOST, count entries.
+ */
+int invaskit_kernel_blocks(int32_t points_dtype, const void* points, int32_t d, double h,
+                           int32_t out_dtype, void* out, const int64_t* out_offsets,
+                           const int64_t* row0, const int32_t* rows,
+                           const int32_t* cols, const int64_t* cols_offsets,
+                           const int32_t* ncols, const int32_t* diag, double shift,
+                           int32_t count, void* hip_stream);
+
+/*
+ * Grouped GEMM on the matrix cores, C_i = beta*C_i + alpha*A_i B_i for
+ * `count` products of different shapes in one launch (the level-synchronous
+ * GEMMs of the SMW updates, eq. (e:blocksmw), and of eq. (e:innerid)).
+ * a, b, c: DEVICE, element type dtype.  Product i: A_i is m[i] x k[i],
+ * column-major with leading dimension lda[i] (row-major when a_rowmajor[i]
+ * != 0, lda = row stride); B_i is k[i] x n[i] column-major (ldb[i]); C_i is
+ * m[i] x n[i] column-major (ldc[i]); element offsets a_off, b_off, c_off.
+ * beta == 0 never reads C.  All size arrays HOST, count entries.
+ * Synchronizes the stream before returning.
+ */
+int invaskit_gemm_batched(int32_t dtype, const void* a, const void* b, void* c,
+                          const int64_t* a_off, const int64_t* b_off, const int64_t* c_off,
+                          const int32_t* m, const int32_t* n, const int32_t* k,
+                          const int64_t* lda, const int32_t* a_rowmajor, const int64_t* ldb,
+                          const int64_t* ldc, double alpha, double beta, int32_t count,
+                          void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* INVASKIT_H */

@@ -1,0 +1,355 @@
+"""ctypes binding of libinvaskit.so (include/invaskit.h).
+
+Argument marshalling only: every step of the factorization, solve and
+product runs in the library's HIP kernels.  PyTorch supplies device memory
+and the current HIP stream.  Importing this module loads the library and
+fails loudly if it has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libinvaskit.so")
+
+OK = 0
+E_ARG, E_MEMORY, E_HIP, E_SINGULAR, E_NOT_CONVERGED, E_DEVICE = -1, -2, -3, -4, -5, -6
+F64, F32 = 0, 1
+PREC_FP64, PREC_MIXED = 0, 1
+
+
+class InvaskitError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{message} (status {status})")
+        self.status = status
+
+
+class _Problem(C.Structure):
+    _fields_ = [("n", C.c_int64), ("d", C.c_int32), ("depth", C.c_int32),
+                ("points_dtype", C.c_int32), ("reserved0", C.c_int32),
+                ("points", C.c_void_p), ("leaf_offsets", C.c_void_p),
+                ("skel_offsets", C.c_void_p), ("skel_index", C.c_void_p),
+                ("p_offsets", C.c_void_p), ("p_values", C.c_void_p), ("h", C.c_double)]
+
+
+class _Options(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("fp64_top_levels", C.c_int32),
+                ("refine_tol", C.c_double), ("max_refine_iters", C.c_int32),
+                ("reserved0", C.c_int32)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("converged", C.c_int32),
+                ("final_rel_residual", C.c_double), ("unrefined_rel_residual", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+def _load():
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"{_LIB_PATH} is missing: build it with "
+                          "`python -m paper_1602_01376_amd.build` (hipcc, gfx950)")
+    lib = C.CDLL(_LIB_PATH)
+    vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    sig = {
+        "invaskit_default_options": (C.c_int, [vp]),
+        "invaskit_factor": (C.c_int, [vp, dbl, vp, vp, vp]),
+        "invaskit_refactor": (C.c_int, [vp, dbl]),
+        "invaskit_solve": (C.c_int, [vp, vp, i64, i64, vp, i64, vp]),
+        "invaskit_matvec": (C.c_int, [vp, vp, i64, i64, vp, i64]),
+        "invaskit_device_bytes": (C.c_int, [vp, vp]),
+        "invaskit_phase_times": (C.c_int, [vp, vp, i32]),
+        "invaskit_destroy": (C.c_int, [vp]),
+        "invaskit_status_string": (C.c_char_p, [C.c_int]),
+        "invaskit_last_error": (C.c_int, [vp, vp, C.c_size_t]),
+        "invaskit_getrf_batched": (C.c_int, [i32, vp, vp, vp, i32, vp, vp, vp]),
+        "invaskit_getrs_batched": (C.c_int, [i32, vp, vp, vp, vp, vp, vp, vp, vp, i32, vp]),
+        "invaskit_kernel_blocks": (C.c_int, [i32, vp, i32, dbl, i32, vp, vp, vp, vp, vp, vp,
+                                             vp, vp, dbl, i32, vp]),
+        "invaskit_gemm_batched": (C.c_int, [i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
+                                            vp, dbl, dbl, i32, vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+_lib = _load()
+EXPORTED = ("invaskit_default_options", "invaskit_factor", "invaskit_refactor", "invaskit_solve",
+            "invaskit_matvec", "invaskit_device_bytes", "invaskit_phase_times",
+            "invaskit_destroy", "invaskit_status_string", "invaskit_last_error",
+            "invaskit_getrf_batched", "invaskit_getrs_batched", "invaskit_kernel_blocks",
+            "invaskit_gemm_batched")
+
+
+def library():
+    return _lib
+
+
+def last_error(handle=None) -> str:
+    buf = C.create_string_buffer(1024)
+    _lib.invaskit_last_error(handle, buf, 1024)
+    return buf.value.decode(errors="replace")
+
+
+def _check(status, handle=None):
+    if status != OK:
+        raise InvaskitError(status, last_error(handle) or
+                            _lib.invaskit_status_string(status).decode())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _colmajor(t: torch.Tensor):
+    """(N,) or (N, r) tensor -> (r, N) contiguous float64 on the GPU (its
+    memory is the column-major N x r matrix)."""
+    if t.dim() == 1:
+        t = t[:, None]
+    return t.to(device="cuda", dtype=torch.float64).t().contiguous()
+
+
+class Factorization:
+    """A factored lambda*I + K~ on the GPU (one library handle).
+
+    `points` and `p_values` are borrowed by the library: this object keeps
+    the device tensors alive for as long as the handle exists.
+    """
+
+    def __init__(self, problem, lam: float, precision: str = "fp64",
+                 fp64_top_levels: int = 4, refine_tol: float = 1e-10,
+                 max_refine_iters: int = 30, points=None, p_values=None):
+        self.n = problem.n
+        self.lam = float(lam)
+        self.precision = precision
+        pdt = F32 if problem.X.dtype == np.float32 else F64
+        if points is None:
+            points = torch.from_numpy(np.ascontiguousarray(problem.X)).cuda()
+        if p_values is None:
+            p_values = torch.from_numpy(np.ascontiguousarray(problem.p_values, dtype=np.float64)).cuda()
+        self._points = points
+        self._p = p_values
+        self._leaf = np.ascontiguousarray(problem.leaf_offsets, dtype=np.int64)
+        self._so = np.ascontiguousarray(problem.skel_offsets, dtype=np.int64)
+        self._si = np.ascontiguousarray(problem.skel_index, dtype=np.int32)
+        self._po = np.ascontiguousarray(problem.p_offsets, dtype=np.int64)
+        pb = _Problem(n=problem.n, d=problem.d, depth=problem.depth, points_dtype=pdt,
+                      reserved0=0, points=points.data_ptr(), leaf_offsets=_ptr(self._leaf).value,
+                      skel_offsets=_ptr(self._so).value, skel_index=_ptr(self._si).value,
+                      p_offsets=_ptr(self._po).value, p_values=p_values.data_ptr(),
+                      h=float(problem.h))
+        opt = _Options()
+        _lib.invaskit_default_options(C.byref(opt))
+        opt.precision = PREC_MIXED if precision == "mixed" else PREC_FP64
+        opt.fp64_top_levels = int(fp64_top_levels)
+        opt.refine_tol = float(refine_tol)
+        opt.max_refine_iters = int(max_refine_iters)
+        self._handle = C.c_void_p()
+        st = _lib.invaskit_factor(C.byref(pb), self.lam, C.byref(opt), _stream(),
+                                  C.byref(self._handle))
+        if st != OK:
+            msg = last_error(self._handle if self._handle.value else None)
+            if self._handle.value:
+                _lib.invaskit_destroy(self._handle)
+                self._handle = C.c_void_p()
+            raise InvaskitError(st, msg)
+
+    @property
+    def handle(self):
+        return self._handle
+
+    def refactor(self, lam: float):
+        self.lam = float(lam)
+        _check(_lib.invaskit_refactor(self._handle, self.lam), self._handle)
+
+    def solve(self, b: torch.Tensor, return_info: bool = False, check: bool = True):
+        """x = (lambda I + K~)^-1 b for b of shape (N,) or (N, r) (tree order)."""
+        vec = b.dim() == 1
+        bc = _colmajor(b)
+        r = bc.shape[0]
+        xc = torch.empty_like(bc)
+        info = SolveInfo()
+        st = _lib.invaskit_solve(self._handle, C.c_void_p(bc.data_ptr()), r, self.n,
+                                 C.c_void_p(xc.data_ptr()), self.n,
+                                 C.byref(info) if return_info else None)
+        if check:
+            _check(st, self._handle)
+        x = xc.t()
+        if vec:
+            x = x[:, 0]
+        if return_info:
+            return x, info.as_dict(), st
+        return x
+
+    def matvec(self, x: torch.Tensor):
+        """y = (lambda I + K~) x in FP64."""
+        vec = x.dim() == 1
+        xc = _colmajor(x)
+        r = xc.shape[0]
+        yc = torch.empty_like(xc)
+        _check(_lib.invaskit_matvec(self._handle, C.c_void_p(xc.data_ptr()), r, self.n,
+                                    C.c_void_p(yc.data_ptr()), self.n), self._handle)
+        y = yc.t()
+        return y[:, 0] if vec else y
+
+    def phase_times(self):
+        out = (C.c_double * 8)()
+        _check(_lib.invaskit_phase_times(self._handle, out, 8), self._handle)
+        keys = ["leaf_lu", "skeleton_blocks", "leaf_solves", "leaf_projections",
+                "skeleton_sweep", "deferred_corrections", "reduced_systems", "total"]
+        return dict(zip(keys, list(out)))
+
+    def device_bytes(self):
+        v = C.c_size_t()
+        _check(_lib.invaskit_device_bytes(self._handle, C.byref(v)), self._handle)
+        return v.value
+
+    def close(self):
+        if getattr(self, "_handle", None) is not None and self._handle.value:
+            _lib.invaskit_destroy(self._handle)
+            self._handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------ batched building blocks
+def getrf_batched(mats, dtype=torch.float64):
+    """LU with partial pivoting of a list of square matrices (numpy or torch,
+    any size 1..1024) in one launch.  Returns (lu list, perm list, info)."""
+    ns = [int(m.shape[0]) for m in mats]
+    offs = np.zeros(len(mats), dtype=np.int64)
+    off = 0
+    parts = []
+    for i, m in enumerate(mats):
+        offs[i] = off
+        off += ns[i] * ns[i]
+        parts.append(torch.as_tensor(np.asarray(m)).to(dtype).t().contiguous().reshape(-1))
+    buf = torch.cat(parts).cuda()
+    perm = torch.empty(sum(ns), dtype=torch.int32, device="cuda")
+    info = torch.empty(len(mats), dtype=torch.int32, device="cuda")
+    n_arr = np.asarray(ns, dtype=np.int32)
+    dt = F64 if dtype == torch.float64 else F32
+    _check(_lib.invaskit_getrf_batched(dt, C.c_void_p(buf.data_ptr()), _ptr(offs), _ptr(n_arr),
+                                       len(mats), C.c_void_p(perm.data_ptr()),
+                                       C.c_void_p(info.data_ptr()), _stream()))
+    return buf, offs, n_arr, perm, info
+
+
+def getrs_batched(buf, offs, n_arr, perm, rhs_list, dtype=torch.float64):
+    """Solve with factors from getrf_batched; rhs_list[i] is (n_i, r_i)."""
+    boffs = np.zeros(len(rhs_list), dtype=np.int64)
+    nr = np.zeros(len(rhs_list), dtype=np.int32)
+    ld = np.zeros(len(rhs_list), dtype=np.int64)
+    parts = []
+    off = 0
+    for i, b in enumerate(rhs_list):
+        bt = torch.as_tensor(np.asarray(b)).to(dtype)
+        if bt.dim() == 1:
+            bt = bt[:, None]
+        boffs[i] = off
+        nr[i] = bt.shape[1]
+        ld[i] = bt.shape[0]
+        off += bt.numel()
+        parts.append(bt.t().contiguous().reshape(-1))
+    bb = torch.cat(parts).cuda()
+    dt = F64 if dtype == torch.float64 else F32
+    _check(_lib.invaskit_getrs_batched(dt, C.c_void_p(buf.data_ptr()), _ptr(offs), _ptr(n_arr),
+                                       C.c_void_p(perm.data_ptr()), C.c_void_p(bb.data_ptr()),
+                                       _ptr(boffs), _ptr(nr), _ptr(ld), len(rhs_list), _stream()))
+    out = []
+    for i in range(len(rhs_list)):
+        seg = bb[boffs[i]:boffs[i] + nr[i] * ld[i]].reshape(int(nr[i]), int(ld[i])).t()
+        out.append(seg)
+    return out
+
+
+def kernel_blocks(points: torch.Tensor, h: float, blocks, out_dtype=torch.float64, shift=0.0):
+    """Evaluate Gaussian kernel blocks; blocks = [(row0, rows, col_ids, diag)]."""
+    d = int(points.shape[1])
+    pdt = F32 if points.dtype == torch.float32 else F64
+    odt = F64 if out_dtype == torch.float64 else F32
+    cnt = len(blocks)
+    out_off = np.zeros(cnt, np.int64)
+    row0 = np.zeros(cnt, np.int64)
+    rows = np.zeros(cnt, np.int32)
+    ncols = np.zeros(cnt, np.int32)
+    coff = np.zeros(cnt, np.int64)
+    diag = np.zeros(cnt, np.int32)
+    cols = []
+    o = c = 0
+    for i, (r0, nr, cid, dg) in enumerate(blocks):
+        out_off[i], row0[i], rows[i], ncols[i], coff[i], diag[i] = o, r0, nr, len(cid), c, int(dg)
+        o += nr * len(cid)
+        c += len(cid)
+        cols.append(np.asarray(cid, dtype=np.int32))
+    cols_t = torch.from_numpy(np.concatenate(cols) if cols else np.zeros(1, np.int32)).cuda()
+    out = torch.empty(max(o, 1), dtype=out_dtype, device="cuda")
+    _check(_lib.invaskit_kernel_blocks(pdt, C.c_void_p(points.data_ptr()), d, float(h), odt,
+                                       C.c_void_p(out.data_ptr()), _ptr(out_off), _ptr(row0),
+                                       _ptr(rows), C.c_void_p(cols_t.data_ptr()), _ptr(coff),
+                                       _ptr(ncols), _ptr(diag), float(shift), cnt, _stream()))
+    res = []
+    for i in range(cnt):
+        res.append(out[out_off[i]:out_off[i] + rows[i] * ncols[i]]
+                   .reshape(int(ncols[i]), int(rows[i])).t())
+    return res
+
+
+def gemm_batched(problems, dtype=torch.float64, alpha=1.0, beta=0.0):
+    """problems = [(A, B, C0, a_rowmajor)] with numpy A (m x k), B (k x n),
+    C0 (m x n or None).  Returns the list of C = beta*C0 + alpha*A B."""
+    cnt = len(problems)
+    a_off, b_off, c_off = (np.zeros(cnt, np.int64) for _ in range(3))
+    m, n, k, arm = (np.zeros(cnt, np.int32) for _ in range(4))
+    lda, ldb, ldc = (np.zeros(cnt, np.int64) for _ in range(3))
+    pa, pb_, pc = [], [], []
+    oa = ob = oc = 0
+    for i, (A, B, C0, rm) in enumerate(problems):
+        A = np.asarray(A)
+        B = np.asarray(B)
+        m[i], k[i] = A.shape
+        n[i] = B.shape[1]
+        arm[i] = int(rm)
+        a_off[i], b_off[i], c_off[i] = oa, ob, oc
+        if rm:
+            pa.append(torch.as_tensor(A).to(dtype).contiguous().reshape(-1))
+            lda[i] = max(k[i], 1)
+        else:
+            pa.append(torch.as_tensor(A).to(dtype).t().contiguous().reshape(-1))
+            lda[i] = max(m[i], 1)
+        pb_.append(torch.as_tensor(B).to(dtype).t().contiguous().reshape(-1))
+        ldb[i] = max(k[i], 1)
+        C0 = np.zeros((m[i], n[i])) if C0 is None else np.asarray(C0)
+        pc.append(torch.as_tensor(C0).to(dtype).t().contiguous().reshape(-1))
+        ldc[i] = max(m[i], 1)
+        oa += A.size
+        ob += B.size
+        oc += m[i] * n[i]
+    ta = torch.cat(pa + [torch.zeros(1, dtype=dtype)]).cuda()
+    tb = torch.cat(pb_ + [torch.zeros(1, dtype=dtype)]).cuda()
+    tc = torch.cat(pc + [torch.zeros(1, dtype=dtype)]).cuda()
+    dt = F64 if dtype == torch.float64 else F32
+    _check(_lib.invaskit_gemm_batched(dt, C.c_void_p(ta.data_ptr()), C.c_void_p(tb.data_ptr()),
+                                      C.c_void_p(tc.data_ptr()), _ptr(a_off), _ptr(b_off),
+                                      _ptr(c_off), _ptr(m), _ptr(n), _ptr(k), _ptr(lda), _ptr(arm),
+                                      _ptr(ldb), _ptr(ldc), float(alpha), float(beta), cnt,
+                                      _stream()))
+    out = []
+    for i in range(cnt):
+        out.append(tc[c_off[i]:c_off[i] + m[i] * n[i]].reshape(int(n[i]), int(m[i])).t())
+    return out

@@ -1,0 +1,149 @@
+// Internal interfaces of libinvaskit: work descriptors consumed by the
+// batched HIP kernels and the host launchers that enqueue them.
+//
+// Every batched kernel reads a device-resident table of problems ("probs")
+// plus a table of work tiles; one workgroup handles one tile.  The tables are
+// built on the host when a factorization is planned and uploaded once, so
+// each launch only passes table pointers and a tile count.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace invaskit {
+
+// C[M x N] = beta * C + alpha * sum_s A_s B_s.  B_s is column-major
+// (k x N, ldb); A_s is column-major (M x k, lda) or row-major when a_rm.
+// C is column-major (ldc).  beta == 0 never reads C.
+struct GemmSeg {
+  const void* A;
+  const void* B;
+  int64_t lda, ldb;
+  int32_t k;
+  int32_t a_rm;
+};
+
+struct GemmProb {
+  void* C;
+  int64_t ldc;
+  int32_t M, N;
+  int32_t seg0, nseg;
+  double alpha, beta;
+};
+
+struct Tile3 {
+  int32_t prob, tm, tn;
+};
+
+struct Tile2 {
+  int32_t prob, tn;
+};
+
+// In-place style triangular solve with an LU factor (row permutation, unit
+// lower L, upper U).  Right-hand-side rows [0, split) come from in0 (ldin0),
+// rows [split, n) from in1 (ldin1); the solution goes to out (ldout).  Input
+// and output may be the same buffer.
+struct TrsmProb {
+  const void* lu;
+  const int32_t* perm;
+  int32_t n, nrhs;
+  const void* in0;
+  const void* in1;
+  int64_t ldin0, ldin1;
+  int32_t split, pad;
+  void* out;
+  int64_t ldout;
+};
+
+struct LuProb {
+  void* a;
+  int32_t* perm;
+  int32_t* info;
+  int32_t n, pad;
+};
+
+// out[r + c*ld] = K(x[row0 + r], x[col(c)]) (+ shift on the diagonal when
+// diag != 0); col(c) = cols ? cols[c] : col0 + c.
+struct EvalBlock {
+  void* out;
+  int64_t ld;
+  int64_t row0;
+  const int32_t* cols;
+  int64_t col0;
+  int32_t rows, ncols;
+  int32_t diag, pad;
+};
+
+// Reduced system Z (n = sr + sl, column-major) = [[I, pr], [pl, I]] with
+// pr: sr x sl (ld sr) and pl: sl x sr (ld sl).
+struct ZformProb {
+  void* Z;
+  const void* pr;
+  const void* pl;
+  int32_t sr, sl;
+};
+
+// Fused FP64 kernel-times-weights evaluation for one block of targets:
+// y[i] (+)= sum over segments of sum_j K(x_i, x_src(j)) w[j, :].
+struct MvSeg {
+  const int32_t* idx;  // source point ids, or nullptr for p0 + j
+  int64_t p0;
+  const double* w;
+  int64_t ldw;
+  int32_t count, pad;
+};
+
+struct MvTile {
+  int64_t row0;  // first target point
+  int32_t rows;  // targets in this tile (<= block size)
+  int32_t seg0, nseg, pad;
+};
+
+// ---------------------------------------------------------------- launchers
+template <typename T>
+hipError_t launch_gemm(const GemmProb* probs, const GemmSeg* segs, const Tile3* tiles,
+                       int ntiles, hipStream_t s);
+
+template <typename TZ, typename TV>
+hipError_t launch_getrs(const TrsmProb* probs, const Tile2* tiles, int ntiles, int nmax,
+                        hipStream_t s);
+int getrs_cols_per_tile();
+
+template <typename T>
+hipError_t launch_getrf(const LuProb* probs, int count, int nmax, hipStream_t s);
+
+template <typename PT, typename T>
+hipError_t launch_eval(const PT* X, int d, double h, double shift, const EvalBlock* blocks,
+                       const Tile3* tiles, int ntiles, hipStream_t s);
+constexpr int kEvalTile = 64;
+constexpr int kGemmTileM = 64;
+constexpr int kGemmTileN = 64;
+
+template <typename TZ, typename TV>
+hipError_t launch_zform(const ZformProb* probs, int count, hipStream_t s);
+
+// y = lam*x + sum K w  (or b - that, when b != nullptr), columns [c0, c0+nc)
+template <typename PT>
+hipError_t launch_mv_eval(const PT* X, int d, double h, double lam, const MvTile* tiles,
+                          int ntiles, const MvSeg* segs, const double* x, int64_t ldx,
+                          double* y, int64_t ldy, const double* b, int64_t ldb, int nrhs,
+                          hipStream_t s);
+constexpr int kMvBlock = 128;
+constexpr int kMvMaxDim = 64;
+
+// elementwise helpers
+hipError_t launch_convert_f64_f32(const double* in, float* out, int64_t n, hipStream_t s);
+// out[i + c*ldo] = (TO) (in[i + c*ldi] * scale[c])  (scale may be nullptr = 1)
+template <typename TI, typename TO>
+hipError_t launch_copy_cols(const TI* in, int64_t ldi, TO* out, int64_t ldo, int64_t n,
+                            int ncols, const double* scale, bool invert_scale, hipStream_t s);
+// x[i + c*ldx] += scale[c] * d[i + c*ldd]
+hipError_t launch_axpy_cols(double* x, int64_t ldx, const float* d, int64_t ldd, int64_t n,
+                            int ncols, const double* scale, hipStream_t s);
+// out[c] = sum_i v[i + c*ld]^2 (out must be zeroed by the launcher)
+hipError_t launch_colsumsq(const double* v, int64_t ld, int64_t n, int ncols, double* out,
+                           hipStream_t s);
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
+
+}  // namespace invaskit

@@ -1,0 +1,1434 @@
+// libinvaskit host side: input validation, memory plan, level-synchronous
+// launch schedule and the C ABI of include/invaskit.h.
+//
+// Factorization (Algorithm 1, done bottom-up with one batched launch per
+// step and tree level instead of a recursion):
+//   F1  every leaf block lambda*I + K_aa is evaluated and LU-factored;
+//   for k = L .. 1, for every node c at level k at once:
+//   F2a the skeleton block B_c = K(X_c, X_{c'~}) (c' = sibling) is written
+//       into the leaf-major W storage, split into the row blocks of c's
+//       leaves;
+//   F2b every leaf applies its LU to its rows of B_c;
+//   F2c every leaf projects its rows onto its skeleton, p = P_{leaf} v;
+//   F2d skeleton-level sweep over the levels L-1 .. k of c's subtree:
+//       y_b = Z_b^-1 [p_right; p_left] and p_b = P_{b~[l~ r~]} [y_l~; y_r~];
+//   F2e deferred correction of every leaf row block,
+//       W_c rows -= sum_{j > k} W^{(j)} rows * y-blocks of the ancestors;
+//   F2f the reduced systems of the level-(k-1) parents are assembled from
+//       the children's projections p_c = P_{c~ c} W_c;
+//   F2g and LU-factored.
+//
+// F2c-F2e replace the per-node "w = v - W Z V v" of Algorithm 2 by an
+// algebraically identical schedule: after that update the children's
+// skeleton projections of w equal y itself (V w = V v - V W y = y because
+// (I + V W) y = V v), so the projection needed one level up is
+// P_{b~[l~ r~]} y (eq. (e:innerid)) and never touches N-sized data; the
+// N-sized corrections of all levels are then applied in one grouped GEMM per
+// leaf.  The solve (Algorithm 2) uses the same four steps with the user's
+// right-hand sides.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <unordered_set>
+#include <vector>
+
+#include "../../include/invaskit.h"
+#include "internal.hpp"
+
+using namespace invaskit;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+constexpr int kMaxLeaf = 1024;
+constexpr int kMaxSkel = 512;
+constexpr int kMaxDepth = 24;
+constexpr int kEvents = 8;
+
+// -------------------------------------------------------------- small utils
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  void release() {
+    if (p) hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+};
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Host staging area for descriptor tables; uploaded to one device buffer.
+struct Arena {
+  std::vector<unsigned char> host;
+  template <typename T>
+  size_t add(const std::vector<T>& v) {
+    const size_t off = align_up(host.size(), 256);
+    host.resize(off + v.size() * sizeof(T));
+    if (!v.empty()) std::memcpy(host.data() + off, v.data(), v.size() * sizeof(T));
+    return off;
+  }
+};
+
+template <typename T>
+const T* at(const DevBuf& b, size_t off) {
+  return reinterpret_cast<const T*>(static_cast<unsigned char*>(b.p) + off);
+}
+
+// One batched launch, described by table offsets into a table buffer.
+struct GemmL {
+  size_t probs = 0, segs = 0, tiles = 0;
+  int ntiles = 0;
+};
+struct TrsmL {
+  size_t probs = 0, tiles = 0;
+  int ntiles = 0, nmax = 0;
+  int tz64 = 1, tv64 = 1;
+};
+struct LuL {
+  size_t probs = 0;
+  int count = 0, nmax = 0, t64 = 1;
+};
+struct EvalL {
+  size_t blocks = 0, tiles = 0;
+  int ntiles = 0;
+};
+struct ZformL {
+  size_t probs = 0;
+  int count = 0, tz64 = 1, tv64 = 1;
+};
+
+struct LevelPlan {
+  EvalL panels;
+  TrsmL leaf_trsm;
+  GemmL leaf_proj;
+  std::vector<TrsmL> zsolve;  // sublevels L-1 .. k
+  std::vector<GemmL> pgemm;
+  GemmL deferred;
+  ZformL zform;
+  LuL zlu;
+};
+
+struct SolvePlan {
+  int r = 0;
+  DevBuf tables, xbuf, sbuf;  // xbuf/sbuf in the factor precision
+  DevBuf x64, r64, sc;        // refinement vectors (mixed mode)
+  TrsmL leaf_trsm;
+  GemmL leaf_proj;
+  std::vector<TrsmL> zsolve;  // levels L-1 .. 0
+  std::vector<GemmL> pgemm;   // levels L-1 .. 1
+  GemmL final_;
+  ~SolvePlan() {
+    tables.release();
+    xbuf.release();
+    sbuf.release();
+    x64.release();
+    r64.release();
+    sc.release();
+  }
+};
+
+struct MatvecPlan {
+  int r = 0;
+  DevBuf tables, xm, q, nrm;
+  std::vector<GemmL> skel;  // levels L .. 1
+  size_t mv_tiles = 0, mv_segs = 0;
+  int n_mv_tiles = 0;
+  ~MatvecPlan() {
+    tables.release();
+    xm.release();
+    q.release();
+    nrm.release();
+  }
+};
+
+}  // namespace
+
+struct invaskit_handle_s {
+  // options
+  int prec = INVASKIT_PREC_FP64;
+  int top64 = 4;
+  double tol = 1e-10;
+  int maxit = 30;
+  hipStream_t stream = nullptr;
+  // problem (device data borrowed)
+  int64_t N = 0;
+  int d = 0, L = 0, pdt = INVASKIT_F64;
+  const void* X = nullptr;
+  const double* P64 = nullptr;
+  double h = 1.0, lam = 0.0;
+  std::vector<int64_t> leaf_off, skel_off, p_off;
+  std::vector<int32_t> skel_idx;
+  // derived tree data
+  int nn = 0, nleaves = 0;
+  std::vector<int64_t> na, nb;  // node point ranges
+  std::vector<int> s, w, z;
+  // layout
+  std::vector<int64_t> lu_off, slab_off, z_off, zperm_off;
+  std::vector<int> S;
+  std::vector<std::vector<int>> colk;  // [leaf][level]
+  std::vector<int> zis64;              // per level
+  std::vector<std::vector<int64_t>> fp_off, fy_off;
+  int64_t fsweep_elems = 0;
+  // device buffers
+  DevBuf skel_d, P32, leafLU, leafPerm, leafInfo, slab, Z64, ZT, zperm, zinfo, fsweep, ftables;
+  // schedule
+  EvalL leaf_eval;
+  LuL leaf_lu;
+  std::vector<LevelPlan> levels;  // index k = 1..L
+  std::map<int, std::unique_ptr<SolvePlan>> solve_plans;
+  std::map<int, std::unique_ptr<MatvecPlan>> mv_plans;
+  double phase_ms[8] = {0};
+  hipEvent_t ev[kEvents + 2] = {};
+  bool have_events = false;
+  std::string err;
+
+  int level(int node) const {
+    int k = 0;
+    while ((2 << k) - 1 <= node) ++k;
+    return k;
+  }
+  bool is_leaf(int node) const { return level(node) == L; }
+  int sib(int c) const { return (c & 1) ? c + 1 : c - 1; }
+  int anc(int node, int k) const {  // ancestor of `node` at level k (<= level(node))
+    const int j = level(node);
+    const int idx = node - ((1 << j) - 1);
+    return (1 << k) - 1 + (idx >> (j - k));
+  }
+  int leaf_node(int j) const { return (1 << L) - 1 + j; }
+  size_t tsize() const { return prec == INVASKIT_PREC_FP64 ? 8 : 4; }
+  const void* Pt() const {  // P in the factor precision
+    return prec == INVASKIT_PREC_FP64 ? static_cast<const void*>(P64) : P32.p;
+  }
+  const void* Z(int node) const {
+    const int k = level(node);
+    const DevBuf& b = zis64[k] ? Z64 : ZT;
+    return static_cast<unsigned char*>(b.p) + z_off[node] * (zis64[k] ? 8 : 4);
+  }
+  void* Zm(int node) { return const_cast<void*>(Z(node)); }
+
+  ~invaskit_handle_s() {
+    solve_plans.clear();
+    mv_plans.clear();
+    for (DevBuf* b : {&skel_d, &P32, &leafLU, &leafPerm, &leafInfo, &slab, &Z64, &ZT, &zperm,
+                      &zinfo, &fsweep, &ftables})
+      b->release();
+    if (have_events)
+      for (auto& e : ev) hipEventDestroy(e);
+  }
+};
+
+using H = invaskit_handle_s;
+
+namespace {
+
+int fail_h(H* h, int code, const std::string& msg) {
+  if (h) h->err = msg;
+  g_last_error = msg;
+  return code;
+}
+
+#define HIP_TRY(h, ...)                                                                  \
+  do {                                                                                   \
+    hipError_t e_ = (__VA_ARGS__);                                                       \
+    if (e_ != hipSuccess)                                                                \
+      return fail_h((h), INVASKIT_E_HIP,                                                 \
+                    std::string(#__VA_ARGS__) + ": " + hipGetErrorString(e_));           \
+  } while (0)
+
+int dev_alloc(H* h, DevBuf& b, size_t bytes) {
+  b.release();
+  if (bytes == 0) bytes = 256;
+  hipError_t e = hipMalloc(&b.p, bytes);
+  if (e != hipSuccess) {
+    b.p = nullptr;
+    return fail_h(h, INVASKIT_E_MEMORY,
+                  "hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
+  }
+  b.bytes = bytes;
+  return INVASKIT_OK;
+}
+
+int check_device(H* h) {
+  int dev = 0;
+  HIP_TRY(h, hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  HIP_TRY(h, hipGetDeviceProperties(&prop, dev));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail_h(h, INVASKIT_E_DEVICE,
+                  std::string("device is ") + prop.gcnArchName + ", this library is built for gfx950");
+  return INVASKIT_OK;
+}
+
+// ------------------------------------------------------------- validation
+int validate(H* h, const invaskit_problem* pb, double lambda, const invaskit_options* opt) {
+  if (!pb) return fail_h(h, INVASKIT_E_ARG, "problem is NULL");
+  if (pb->n < 1) return fail_h(h, INVASKIT_E_ARG, "n must be >= 1");
+  if (pb->d < 1) return fail_h(h, INVASKIT_E_ARG, "d must be >= 1");
+  if (pb->depth < 0 || pb->depth > kMaxDepth)
+    return fail_h(h, INVASKIT_E_ARG, "depth must be in [0, 24]");
+  if (pb->points_dtype != INVASKIT_F64 && pb->points_dtype != INVASKIT_F32)
+    return fail_h(h, INVASKIT_E_ARG, "points_dtype must be INVASKIT_F64 or INVASKIT_F32");
+  if (!pb->points) return fail_h(h, INVASKIT_E_ARG, "points is NULL");
+  if (!pb->leaf_offsets || !pb->skel_offsets || !pb->p_offsets)
+    return fail_h(h, INVASKIT_E_ARG, "leaf_offsets, skel_offsets and p_offsets are required");
+  if (!(pb->h > 0.0) || !std::isfinite(pb->h))
+    return fail_h(h, INVASKIT_E_ARG, "h must be finite and > 0");
+  if (!std::isfinite(lambda)) return fail_h(h, INVASKIT_E_ARG, "lambda must be finite");
+  if (opt) {
+    if (opt->precision != INVASKIT_PREC_FP64 && opt->precision != INVASKIT_PREC_MIXED)
+      return fail_h(h, INVASKIT_E_ARG, "precision must be INVASKIT_PREC_FP64 or _MIXED");
+    if (opt->fp64_top_levels < 0) return fail_h(h, INVASKIT_E_ARG, "fp64_top_levels < 0");
+    if (!(opt->refine_tol > 0.0)) return fail_h(h, INVASKIT_E_ARG, "refine_tol must be > 0");
+    if (opt->max_refine_iters < 1) return fail_h(h, INVASKIT_E_ARG, "max_refine_iters < 1");
+  }
+  const int L = pb->depth;
+  const int nleaves = 1 << L;
+  const int nn = (1 << (L + 1)) - 1;
+  const int64_t* lo = pb->leaf_offsets;
+  if (lo[0] != 0 || lo[nleaves] != pb->n)
+    return fail_h(h, INVASKIT_E_ARG, "leaf_offsets must start at 0 and end at n");
+  for (int j = 0; j < nleaves; ++j) {
+    const int64_t m = lo[j + 1] - lo[j];
+    if (m < 1 || m > kMaxLeaf)
+      return fail_h(h, INVASKIT_E_ARG,
+                    "leaf " + std::to_string(j) + " has " + std::to_string(m) +
+                        " points; leaves must hold 1.." + std::to_string(kMaxLeaf));
+  }
+  const int64_t* so = pb->skel_offsets;
+  if (so[0] != 0 || so[1] != 0) return fail_h(h, INVASKIT_E_ARG, "the root must have no skeleton");
+  for (int c = 1; c < nn; ++c) {
+    const int64_t sc = so[c + 1] - so[c];
+    if (sc < 1 || sc > kMaxSkel)
+      return fail_h(h, INVASKIT_E_ARG,
+                    "node " + std::to_string(c) + " has " + std::to_string(sc) +
+                        " skeleton points; allowed 1.." + std::to_string(kMaxSkel));
+  }
+  if (L > 0 && (!pb->skel_index || !pb->p_values))
+    return fail_h(h, INVASKIT_E_ARG, "skel_index and p_values are required when depth > 0");
+  const int64_t* po = pb->p_offsets;
+  if (po[0] != 0 || po[1] != 0) return fail_h(h, INVASKIT_E_ARG, "the root has no P");
+  // node ranges, nesting and P sizes
+  auto range = [&](int c, int64_t& a, int64_t& b) {
+    int k = 0;
+    while ((2 << k) - 1 <= c) ++k;
+    const int idx = c - ((1 << k) - 1);
+    const int span = 1 << (L - k);
+    a = lo[idx * span];
+    b = lo[(idx + 1) * span];
+  };
+  for (int c = nn - 1; c >= 1; --c) {
+    int64_t a, b;
+    range(c, a, b);
+    const int64_t sc = so[c + 1] - so[c];
+    const bool leaf = (c >= (1 << L) - 1);
+    int64_t cols;
+    if (leaf) {
+      cols = b - a;
+      for (int64_t t = so[c]; t < so[c + 1]; ++t)
+        if (pb->skel_index[t] < a || pb->skel_index[t] >= b)
+          return fail_h(h, INVASKIT_E_ARG,
+                        "skeleton of leaf node " + std::to_string(c) + " leaves the leaf");
+    } else {
+      const int l = 2 * c + 1, r = 2 * c + 2;
+      cols = (so[l + 1] - so[l]) + (so[r + 1] - so[r]);
+      std::unordered_set<int32_t> child;
+      for (int64_t t = so[l]; t < so[r + 1]; ++t) child.insert(pb->skel_index[t]);
+      for (int64_t t = so[c]; t < so[c + 1]; ++t)
+        if (!child.count(pb->skel_index[t]))
+          return fail_h(h, INVASKIT_E_ARG,
+                        "skeleton of node " + std::to_string(c) +
+                            " is not nested in its children's skeletons");
+    }
+    if (po[c + 1] - po[c] != sc * cols)
+      return fail_h(h, INVASKIT_E_ARG,
+                    "P of node " + std::to_string(c) + " must have " + std::to_string(sc) + " x " +
+                        std::to_string(cols) + " entries");
+  }
+  return INVASKIT_OK;
+}
+
+// ----------------------------------------------------------- table builders
+void gemm_tiles(std::vector<Tile3>& tiles, int prob, int M, int N) {
+  for (int tn = 0; tn < (N + kGemmTileN - 1) / kGemmTileN; ++tn)
+    for (int tm = 0; tm < (M + kGemmTileM - 1) / kGemmTileM; ++tm) tiles.push_back({prob, tm, tn});
+}
+
+struct GemmBuilder {
+  std::vector<GemmProb> probs;
+  std::vector<GemmSeg> segs;
+  std::vector<Tile3> tiles;
+  int begin(void* C, int64_t ldc, int M, int N, double alpha, double beta) {
+    GemmProb p{};
+    p.C = C;
+    p.ldc = ldc;
+    p.M = M;
+    p.N = N;
+    p.seg0 = (int)segs.size();
+    p.nseg = 0;
+    p.alpha = alpha;
+    p.beta = beta;
+    probs.push_back(p);
+    if (M > 0 && N > 0) gemm_tiles(tiles, (int)probs.size() - 1, M, N);
+    return (int)probs.size() - 1;
+  }
+  void seg(const void* A, int64_t lda, bool a_rm, const void* B, int64_t ldb, int k) {
+    if (k <= 0) return;
+    GemmSeg g{};
+    g.A = A;
+    g.B = B;
+    g.lda = lda;
+    g.ldb = ldb;
+    g.k = k;
+    g.a_rm = a_rm ? 1 : 0;
+    segs.push_back(g);
+    probs.back().nseg++;
+  }
+  GemmL emit(Arena& ar) {
+    GemmL l;
+    l.probs = ar.add(probs);
+    l.segs = ar.add(segs);
+    l.tiles = ar.add(tiles);
+    l.ntiles = (int)tiles.size();
+    return l;
+  }
+};
+
+struct TrsmBuilder {
+  std::vector<TrsmProb> probs;
+  std::vector<Tile2> tiles;
+  int nmax = 0;
+  void add(const void* lu, const int32_t* perm, int n, int nrhs, const void* in0, int64_t ld0,
+           int split, const void* in1, int64_t ld1, void* out, int64_t ldo) {
+    TrsmProb p{};
+    p.lu = lu;
+    p.perm = perm;
+    p.n = n;
+    p.nrhs = nrhs;
+    p.in0 = in0;
+    p.in1 = in1;
+    p.ldin0 = ld0;
+    p.ldin1 = ld1;
+    p.split = split;
+    p.out = out;
+    p.ldout = ldo;
+    probs.push_back(p);
+    const int rt = getrs_cols_per_tile();
+    for (int tn = 0; tn < (nrhs + rt - 1) / rt; ++tn) tiles.push_back({(int)probs.size() - 1, tn});
+    nmax = std::max(nmax, n);
+  }
+  TrsmL emit(Arena& ar, int tz64, int tv64) {
+    TrsmL l;
+    l.probs = ar.add(probs);
+    l.tiles = ar.add(tiles);
+    l.ntiles = (int)tiles.size();
+    l.nmax = nmax;
+    l.tz64 = tz64;
+    l.tv64 = tv64;
+    return l;
+  }
+};
+
+template <typename T>
+T* offp(void* base, int64_t elems) {
+  return static_cast<T*>(base) + elems;
+}
+inline void* offv(void* base, int64_t elems, size_t esz) {
+  return static_cast<unsigned char*>(base) + elems * esz;
+}
+
+// ----------------------------------------------------------------- planning
+int plan_factor(H* h) {
+  const int L = h->L;
+  const int nn = h->nn;
+  const size_t es = h->tsize();
+  h->na.assign(nn, 0);
+  h->nb.assign(nn, 0);
+  h->s.assign(nn, 0);
+  h->w.assign(nn, 0);
+  h->z.assign(nn, 0);
+  for (int c = 0; c < nn; ++c) {
+    const int k = h->level(c);
+    const int idx = c - ((1 << k) - 1);
+    const int span = 1 << (L - k);
+    h->na[c] = h->leaf_off[idx * span];
+    h->nb[c] = h->leaf_off[(idx + 1) * span];
+    h->s[c] = (int)(h->skel_off[c + 1] - h->skel_off[c]);
+  }
+  for (int c = 1; c < nn; ++c) h->w[c] = h->s[h->sib(c)];
+  for (int c = 0; c < nn; ++c)
+    if (!h->is_leaf(c)) h->z[c] = h->s[2 * c + 1] + h->s[2 * c + 2];
+
+  // leaf LU and leaf-major W storage
+  h->lu_off.assign(h->nleaves + 1, 0);
+  h->slab_off.assign(h->nleaves + 1, 0);
+  h->S.assign(h->nleaves, 0);
+  h->colk.assign(h->nleaves, std::vector<int>(L + 1, 0));
+  for (int j = 0; j < h->nleaves; ++j) {
+    const int lf = h->leaf_node(j);
+    const int64_t m = h->nb[lf] - h->na[lf];
+    h->lu_off[j + 1] = h->lu_off[j] + m * m;
+    int run = 0;
+    for (int k = L; k >= 1; --k) {
+      h->colk[j][k] = run;
+      run += h->w[h->anc(lf, k)];
+    }
+    h->S[j] = run;
+    h->slab_off[j + 1] = h->slab_off[j] + m * run;
+  }
+  // reduced systems
+  h->zis64.assign(L + 1, 1);
+  if (h->prec == INVASKIT_PREC_MIXED)
+    for (int k = 0; k <= L; ++k) h->zis64[k] = (k < h->top64) ? 1 : 0;
+  h->z_off.assign(nn, 0);
+  h->zperm_off.assign(nn + 1, 0);
+  int64_t z64n = 0, zTn = 0, zpn = 0;
+  int ninternal = (1 << L) - 1;
+  for (int c = 0; c < ninternal; ++c) {
+    const int64_t zz = (int64_t)h->z[c] * h->z[c];
+    if (h->zis64[h->level(c)]) {
+      h->z_off[c] = z64n;
+      z64n += zz;
+    } else {
+      h->z_off[c] = zTn;
+      zTn += zz;
+    }
+    h->zperm_off[c] = zpn;
+    zpn += h->z[c];
+  }
+  // skeleton sweep buffers of each factor level
+  h->fp_off.assign(L + 1, std::vector<int64_t>(nn, 0));
+  h->fy_off.assign(L + 1, std::vector<int64_t>(nn, 0));
+  h->fsweep_elems = 0;
+  for (int k = L; k >= 1; --k) {
+    int64_t off = 0;
+    for (int c = (1 << k) - 1; c < nn; ++c) {
+      const int wk = h->w[h->anc(c, k)];
+      h->fp_off[k][c] = off;
+      off += (int64_t)h->s[c] * wk;
+      if (!h->is_leaf(c)) {
+        h->fy_off[k][c] = off;
+        off += (int64_t)h->z[c] * wk;
+      }
+    }
+    h->fsweep_elems = std::max(h->fsweep_elems, off);
+  }
+
+  // allocations
+  int rc;
+  if ((rc = dev_alloc(h, h->leafLU, h->lu_off[h->nleaves] * es))) return rc;
+  if ((rc = dev_alloc(h, h->leafPerm, sizeof(int32_t) * h->N))) return rc;
+  if ((rc = dev_alloc(h, h->leafInfo, sizeof(int32_t) * h->nleaves))) return rc;
+  if ((rc = dev_alloc(h, h->slab, h->slab_off[h->nleaves] * es))) return rc;
+  if ((rc = dev_alloc(h, h->Z64, z64n * 8))) return rc;
+  if ((rc = dev_alloc(h, h->ZT, zTn * es))) return rc;
+  if ((rc = dev_alloc(h, h->zperm, sizeof(int32_t) * std::max<int64_t>(zpn, 1)))) return rc;
+  if ((rc = dev_alloc(h, h->zinfo, sizeof(int32_t) * std::max(ninternal, 1)))) return rc;
+  if ((rc = dev_alloc(h, h->fsweep, h->fsweep_elems * es))) return rc;
+  if ((rc = dev_alloc(h, h->skel_d, sizeof(int32_t) * std::max<size_t>(h->skel_idx.size(), 1))))
+    return rc;
+  if (!h->skel_idx.empty())
+    HIP_TRY(h, hipMemcpy(h->skel_d.p, h->skel_idx.data(), sizeof(int32_t) * h->skel_idx.size(),
+                         hipMemcpyHostToDevice));
+  if (h->prec == INVASKIT_PREC_MIXED) {
+    const int64_t np = h->p_off[nn];
+    if ((rc = dev_alloc(h, h->P32, sizeof(float) * std::max<int64_t>(np, 1)))) return rc;
+  }
+
+  // ---- tables
+  Arena ar;
+  const int T64 = (h->prec == INVASKIT_PREC_FP64) ? 1 : 0;
+  const int32_t* skd = static_cast<const int32_t*>(h->skel_d.p);
+  const int32_t* lperm = static_cast<const int32_t*>(h->leafPerm.p);
+  int32_t* zpm = static_cast<int32_t*>(h->zperm.p);
+  // F1: leaf blocks and their LU
+  {
+    std::vector<EvalBlock> blocks;
+    std::vector<Tile3> tiles;
+    std::vector<LuProb> lus;
+    int nmax = 0;
+    for (int j = 0; j < h->nleaves; ++j) {
+      const int lf = h->leaf_node(j);
+      const int m = (int)(h->nb[lf] - h->na[lf]);
+      EvalBlock b{};
+      b.out = offv(h->leafLU.p, h->lu_off[j], es);
+      b.ld = m;
+      b.row0 = h->na[lf];
+      b.cols = nullptr;
+      b.col0 = h->na[lf];
+      b.rows = m;
+      b.ncols = m;
+      b.diag = 1;
+      blocks.push_back(b);
+      for (int tn = 0; tn < (m + kEvalTile - 1) / kEvalTile; ++tn)
+        for (int tm = 0; tm < (m + kEvalTile - 1) / kEvalTile; ++tm)
+          tiles.push_back({(int)blocks.size() - 1, tm, tn});
+      LuProb p{};
+      p.a = b.out;
+      p.perm = static_cast<int32_t*>(h->leafPerm.p) + h->na[lf];
+      p.info = static_cast<int32_t*>(h->leafInfo.p) + j;
+      p.n = m;
+      lus.push_back(p);
+      nmax = std::max(nmax, m);
+    }
+    h->leaf_eval.blocks = ar.add(blocks);
+    h->leaf_eval.tiles = ar.add(tiles);
+    h->leaf_eval.ntiles = (int)tiles.size();
+    h->leaf_lu.probs = ar.add(lus);
+    h->leaf_lu.count = (int)lus.size();
+    h->leaf_lu.nmax = nmax;
+    h->leaf_lu.t64 = T64;
+  }
+  h->levels.assign(L + 1, LevelPlan());
+  for (int k = L; k >= 1; --k) {
+    LevelPlan& lp = h->levels[k];
+    void* fs = h->fsweep.p;
+    // F2a panels, F2b leaf solves, F2c leaf projections, F2e deferred corrections
+    std::vector<EvalBlock> blocks;
+    std::vector<Tile3> etiles;
+    TrsmBuilder tb;
+    GemmBuilder proj, defer;
+    for (int j = 0; j < h->nleaves; ++j) {
+      const int lf = h->leaf_node(j);
+      const int m = (int)(h->nb[lf] - h->na[lf]);
+      const int c = h->anc(lf, k);
+      const int wk = h->w[c];
+      void* seg = offv(h->slab.p, h->slab_off[j] + (int64_t)h->colk[j][k] * m, es);
+      EvalBlock b{};
+      b.out = seg;
+      b.ld = m;
+      b.row0 = h->na[lf];
+      b.cols = skd + h->skel_off[h->sib(c)];
+      b.rows = m;
+      b.ncols = wk;
+      b.diag = 0;
+      blocks.push_back(b);
+      for (int tn = 0; tn < (wk + kEvalTile - 1) / kEvalTile; ++tn)
+        for (int tm = 0; tm < (m + kEvalTile - 1) / kEvalTile; ++tm)
+          etiles.push_back({(int)blocks.size() - 1, tm, tn});
+      tb.add(offv(h->leafLU.p, h->lu_off[j], es), lperm + h->na[lf], m, wk, seg, m, m, seg, m,
+             seg, m);
+      proj.begin(offv(fs, h->fp_off[k][lf], es), h->s[lf], h->s[lf], wk, 1.0, 0.0);
+      proj.seg(offv(const_cast<void*>(h->Pt()), h->p_off[lf], es), m, true, seg, m, m);
+      if (k < L) {
+        defer.begin(seg, m, m, wk, -1.0, 1.0);
+        for (int jl = L; jl > k; --jl) {
+          const int cj = h->anc(lf, jl);
+          const int par = h->anc(lf, jl - 1);
+          const int yoff = (cj & 1) ? 0 : h->s[cj];  // left child takes the r~ rows
+          defer.seg(offv(h->slab.p, h->slab_off[j] + (int64_t)h->colk[j][jl] * m, es), m, false,
+                    offv(fs, h->fy_off[k][par] + yoff, es), h->z[par], h->w[cj]);
+        }
+      }
+    }
+    lp.panels.blocks = ar.add(blocks);
+    lp.panels.tiles = ar.add(etiles);
+    lp.panels.ntiles = (int)etiles.size();
+    lp.leaf_trsm = tb.emit(ar, T64, T64);
+    lp.leaf_proj = proj.emit(ar);
+    if (k < L) lp.deferred = defer.emit(ar);
+    // F2d skeleton sweep over sublevels L-1 .. k
+    for (int jl = L - 1; jl >= k; --jl) {
+      TrsmBuilder zs;
+      GemmBuilder pg;
+      for (int bnode = (1 << jl) - 1; bnode < (2 << jl) - 1; ++bnode) {
+        const int l = 2 * bnode + 1, r = 2 * bnode + 2;
+        const int wk = h->w[h->anc(bnode, k)];
+        void* y = offv(fs, h->fy_off[k][bnode], es);
+        zs.add(h->Z(bnode), zpm + h->zperm_off[bnode], h->z[bnode], wk,
+               offv(fs, h->fp_off[k][r], es), h->s[r], h->s[r], offv(fs, h->fp_off[k][l], es),
+               h->s[l], y, h->z[bnode]);
+        pg.begin(offv(fs, h->fp_off[k][bnode], es), h->s[bnode], h->s[bnode], wk, 1.0, 0.0);
+        const void* Pb = offv(const_cast<void*>(h->Pt()), h->p_off[bnode], es);
+        pg.seg(Pb, h->z[bnode], true, offv(y, h->s[r], es), h->z[bnode], h->s[l]);
+        pg.seg(offv(const_cast<void*>(Pb), h->s[l], es), h->z[bnode], true, y, h->z[bnode],
+               h->s[r]);
+      }
+      lp.zsolve.push_back(zs.emit(ar, h->zis64[jl], T64));
+      lp.pgemm.push_back(pg.emit(ar));
+    }
+    // F2f/F2g reduced systems of the level k-1 parents
+    std::vector<ZformProb> zf;
+    std::vector<LuProb> zl;
+    int nmax = 0;
+    for (int a = (1 << (k - 1)) - 1; a < (1 << k) - 1; ++a) {
+      const int l = 2 * a + 1, r = 2 * a + 2;
+      ZformProb p{};
+      p.Z = h->Zm(a);
+      p.pr = offv(fs, h->fp_off[k][r], es);
+      p.pl = offv(fs, h->fp_off[k][l], es);
+      p.sr = h->s[r];
+      p.sl = h->s[l];
+      zf.push_back(p);
+      LuProb q{};
+      q.a = h->Zm(a);
+      q.perm = zpm + h->zperm_off[a];
+      q.info = static_cast<int32_t*>(h->zinfo.p) + a;
+      q.n = h->z[a];
+      zl.push_back(q);
+      nmax = std::max(nmax, h->z[a]);
+    }
+    lp.zform.probs = ar.add(zf);
+    lp.zform.count = (int)zf.size();
+    lp.zform.tz64 = h->zis64[k - 1];
+    lp.zform.tv64 = T64;
+    lp.zlu.probs = ar.add(zl);
+    lp.zlu.count = (int)zl.size();
+    lp.zlu.nmax = nmax;
+    lp.zlu.t64 = h->zis64[k - 1];
+  }
+  if ((rc = dev_alloc(h, h->ftables, ar.host.size()))) return rc;
+  HIP_TRY(h, hipMemcpy(h->ftables.p, ar.host.data(), ar.host.size(), hipMemcpyHostToDevice));
+  return INVASKIT_OK;
+}
+
+// ---------------------------------------------------------------- launching
+hipError_t run_gemm(const DevBuf& tb, const GemmL& l, bool f64, hipStream_t s) {
+  if (l.ntiles == 0) return hipSuccess;
+  if (f64)
+    return launch_gemm<double>(at<GemmProb>(tb, l.probs), at<GemmSeg>(tb, l.segs),
+                               at<Tile3>(tb, l.tiles), l.ntiles, s);
+  return launch_gemm<float>(at<GemmProb>(tb, l.probs), at<GemmSeg>(tb, l.segs),
+                            at<Tile3>(tb, l.tiles), l.ntiles, s);
+}
+
+hipError_t run_trsm(const DevBuf& tb, const TrsmL& l, hipStream_t s) {
+  if (l.ntiles == 0) return hipSuccess;
+  const TrsmProb* p = at<TrsmProb>(tb, l.probs);
+  const Tile2* t = at<Tile2>(tb, l.tiles);
+  if (l.tz64 && l.tv64) return launch_getrs<double, double>(p, t, l.ntiles, l.nmax, s);
+  if (l.tz64) return launch_getrs<double, float>(p, t, l.ntiles, l.nmax, s);
+  return launch_getrs<float, float>(p, t, l.ntiles, l.nmax, s);
+}
+
+hipError_t run_lu(const DevBuf& tb, const LuL& l, hipStream_t s) {
+  if (l.count == 0) return hipSuccess;
+  if (l.t64) return launch_getrf<double>(at<LuProb>(tb, l.probs), l.count, l.nmax, s);
+  return launch_getrf<float>(at<LuProb>(tb, l.probs), l.count, l.nmax, s);
+}
+
+hipError_t run_zform(const DevBuf& tb, const ZformL& l, hipStream_t s) {
+  if (l.count == 0) return hipSuccess;
+  const ZformProb* p = at<ZformProb>(tb, l.probs);
+  if (l.tz64 && l.tv64) return launch_zform<double, double>(p, l.count, s);
+  if (l.tz64) return launch_zform<double, float>(p, l.count, s);
+  return launch_zform<float, float>(p, l.count, s);
+}
+
+hipError_t run_eval(H* h, const DevBuf& tb, const EvalL& l, double shift, hipStream_t s) {
+  if (l.ntiles == 0) return hipSuccess;
+  const EvalBlock* b = at<EvalBlock>(tb, l.blocks);
+  const Tile3* t = at<Tile3>(tb, l.tiles);
+  const bool f64 = h->prec == INVASKIT_PREC_FP64;
+  if (h->pdt == INVASKIT_F64) {
+    const double* X = static_cast<const double*>(h->X);
+    return f64 ? launch_eval<double, double>(X, h->d, h->h, shift, b, t, l.ntiles, s)
+               : launch_eval<double, float>(X, h->d, h->h, shift, b, t, l.ntiles, s);
+  }
+  const float* X = static_cast<const float*>(h->X);
+  return f64 ? launch_eval<float, double>(X, h->d, h->h, shift, b, t, l.ntiles, s)
+             : launch_eval<float, float>(X, h->d, h->h, shift, b, t, l.ntiles, s);
+}
+
+int run_factor(H* h) {
+  hipStream_t s = h->stream;
+  const bool f64 = h->prec == INVASKIT_PREC_FP64;
+  const DevBuf& tb = h->ftables;
+  if (!h->have_events) {
+    for (auto& e : h->ev) HIP_TRY(h, hipEventCreate(&e));
+    h->have_events = true;
+  }
+  // phase accumulation: events bracket each phase of each level
+  std::vector<hipEvent_t> marks;
+  std::vector<int> phase_of;
+  std::vector<hipEvent_t> pool;
+  auto mark = [&](int phase) -> int {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return -1;
+    pool.push_back(e);
+    if (hipEventRecord(e, s) != hipSuccess) return -1;
+    marks.push_back(e);
+    phase_of.push_back(phase);
+    return 0;
+  };
+  auto cleanup = [&]() {
+    for (auto e : pool) hipEventDestroy(e);
+  };
+#define STEP(...)                                                                 \
+  do {                                                                            \
+    hipError_t e_ = (__VA_ARGS__);                                                \
+    if (e_ != hipSuccess) {                                                       \
+      cleanup();                                                                  \
+      return fail_h(h, INVASKIT_E_HIP,                                            \
+                    std::string(#__VA_ARGS__) + ": " + hipGetErrorString(e_));    \
+    }                                                                             \
+  } while (0)
+
+  mark(-1);
+  if (!f64 && h->P32.p && h->p_off[h->nn] > 0)
+    STEP(launch_convert_f64_f32(h->P64, static_cast<float*>(h->P32.p), h->p_off[h->nn], s));
+  STEP(run_eval(h, tb, h->leaf_eval, h->lam, s));
+  STEP(run_lu(tb, h->leaf_lu, s));
+  mark(0);
+  for (int k = h->L; k >= 1; --k) {
+    const LevelPlan& lp = h->levels[k];
+    STEP(run_eval(h, tb, lp.panels, 0.0, s));
+    mark(1);
+    STEP(run_trsm(tb, lp.leaf_trsm, s));
+    mark(2);
+    STEP(run_gemm(tb, lp.leaf_proj, f64, s));
+    mark(3);
+    for (size_t q = 0; q < lp.zsolve.size(); ++q) {
+      STEP(run_trsm(tb, lp.zsolve[q], s));
+      STEP(run_gemm(tb, lp.pgemm[q], f64, s));
+    }
+    mark(4);
+    STEP(run_gemm(tb, lp.deferred, f64, s));
+    mark(5);
+    STEP(run_zform(tb, lp.zform, s));
+    STEP(run_lu(tb, lp.zlu, s));
+    mark(6);
+  }
+  STEP(hipStreamSynchronize(s));
+  for (double& v : h->phase_ms) v = 0.0;
+  for (size_t i = 1; i < marks.size(); ++i) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, marks[i - 1], marks[i]) == hipSuccess && phase_of[i] >= 0)
+      h->phase_ms[phase_of[i]] += ms;
+  }
+  {
+    float ms = 0.f;
+    if (marks.size() > 1 && hipEventElapsedTime(&ms, marks.front(), marks.back()) == hipSuccess)
+      h->phase_ms[7] = ms;
+  }
+  cleanup();
+#undef STEP
+  // pivot status
+  std::vector<int32_t> li(h->nleaves), zi(std::max((1 << h->L) - 1, 0));
+  HIP_TRY(h, hipMemcpy(li.data(), h->leafInfo.p, sizeof(int32_t) * li.size(), hipMemcpyDeviceToHost));
+  if (!zi.empty())
+    HIP_TRY(h, hipMemcpy(zi.data(), h->zinfo.p, sizeof(int32_t) * zi.size(), hipMemcpyDeviceToHost));
+  for (int j = 0; j < h->nleaves; ++j)
+    if (li[j])
+      return fail_h(h, INVASKIT_E_SINGULAR,
+                    "zero pivot: leaf block of node " + std::to_string(h->leaf_node(j)) + " column " +
+                        std::to_string(li[j] - 1));
+  for (size_t a = 0; a < zi.size(); ++a)
+    if (zi[a])
+      return fail_h(h, INVASKIT_E_SINGULAR,
+                    "zero pivot: reduced system of node " + std::to_string(a) + " column " +
+                        std::to_string(zi[a] - 1));
+  return INVASKIT_OK;
+}
+
+// ------------------------------------------------------------ solve plans
+int build_solve_plan(H* h, int r, SolvePlan*& out) {
+  auto it = h->solve_plans.find(r);
+  if (it != h->solve_plans.end()) {
+    out = it->second.get();
+    return INVASKIT_OK;
+  }
+  auto sp = std::make_unique<SolvePlan>();
+  sp->r = r;
+  const int L = h->L;
+  const size_t es = h->tsize();
+  const int T64 = (h->prec == INVASKIT_PREC_FP64) ? 1 : 0;
+  std::vector<int64_t> sp_off(h->nn, 0), sy_off(h->nn, 0);
+  int64_t off = 0;
+  for (int c = 1; c < h->nn; ++c) {
+    sp_off[c] = off;
+    off += (int64_t)h->s[c] * r;
+  }
+  for (int c = 0; c < (1 << L) - 1; ++c) {
+    sy_off[c] = off;
+    off += (int64_t)h->z[c] * r;
+  }
+  int rc;
+  if ((rc = dev_alloc(h, sp->xbuf, (size_t)h->N * r * es))) return rc;
+  if ((rc = dev_alloc(h, sp->sbuf, std::max<int64_t>(off, 1) * es))) return rc;
+  if (!T64) {
+    if ((rc = dev_alloc(h, sp->x64, (size_t)h->N * r * 8))) return rc;
+    if ((rc = dev_alloc(h, sp->r64, (size_t)h->N * r * 8))) return rc;
+  }
+  if ((rc = dev_alloc(h, sp->sc, sizeof(double) * r))) return rc;
+  void* xb = sp->xbuf.p;
+  void* sb = sp->sbuf.p;
+  const int32_t* lperm = static_cast<const int32_t*>(h->leafPerm.p);
+  int32_t* zpm = static_cast<int32_t*>(h->zperm.p);
+  Arena ar;
+  TrsmBuilder lt;
+  GemmBuilder lpj, fin;
+  for (int j = 0; j < h->nleaves; ++j) {
+    const int lf = h->leaf_node(j);
+    const int m = (int)(h->nb[lf] - h->na[lf]);
+    void* xr = offv(xb, h->na[lf], es);
+    lt.add(offv(h->leafLU.p, h->lu_off[j], es), lperm + h->na[lf], m, r, xr, h->N, m, xr, h->N, xr,
+           h->N);
+    if (L > 0) {
+      lpj.begin(offv(sb, sp_off[lf], es), h->s[lf], h->s[lf], r, 1.0, 0.0);
+      lpj.seg(offv(const_cast<void*>(h->Pt()), h->p_off[lf], es), m, true, xr, h->N, m);
+      fin.begin(xr, h->N, m, r, -1.0, 1.0);
+      for (int jl = L; jl >= 1; --jl) {
+        const int cj = h->anc(lf, jl);
+        const int par = h->anc(lf, jl - 1);
+        const int yoff = (cj & 1) ? 0 : h->s[cj];
+        fin.seg(offv(h->slab.p, h->slab_off[j] + (int64_t)h->colk[j][jl] * m, es), m, false,
+                offv(sb, sy_off[par] + yoff, es), h->z[par], h->w[cj]);
+      }
+    }
+  }
+  sp->leaf_trsm = lt.emit(ar, T64, T64);
+  sp->leaf_proj = lpj.emit(ar);
+  for (int jl = L - 1; jl >= 0; --jl) {
+    TrsmBuilder zs;
+    GemmBuilder pg;
+    for (int bnode = (1 << jl) - 1; bnode < (2 << jl) - 1; ++bnode) {
+      const int l = 2 * bnode + 1, rr = 2 * bnode + 2;
+      void* y = offv(sb, sy_off[bnode], es);
+      zs.add(h->Z(bnode), zpm + h->zperm_off[bnode], h->z[bnode], r, offv(sb, sp_off[rr], es),
+             h->s[rr], h->s[rr], offv(sb, sp_off[l], es), h->s[l], y, h->z[bnode]);
+      if (jl > 0) {
+        pg.begin(offv(sb, sp_off[bnode], es), h->s[bnode], h->s[bnode], r, 1.0, 0.0);
+        const void* Pb = offv(const_cast<void*>(h->Pt()), h->p_off[bnode], es);
+        pg.seg(Pb, h->z[bnode], true, offv(y, h->s[rr], es), h->z[bnode], h->s[l]);
+        pg.seg(offv(const_cast<void*>(Pb), h->s[l], es), h->z[bnode], true, y, h->z[bnode],
+               h->s[rr]);
+      }
+    }
+    sp->zsolve.push_back(zs.emit(ar, h->zis64[jl], T64));
+    sp->pgemm.push_back(pg.emit(ar));
+  }
+  sp->final_ = fin.emit(ar);
+  if ((rc = dev_alloc(h, sp->tables, ar.host.size()))) return rc;
+  HIP_TRY(h, hipMemcpy(sp->tables.p, ar.host.data(), ar.host.size(), hipMemcpyHostToDevice));
+  out = sp.get();
+  h->solve_plans[r] = std::move(sp);
+  return INVASKIT_OK;
+}
+
+// the direct solve on sp->xbuf, in place, in the factor precision
+int run_solve_plan(H* h, SolvePlan* sp) {
+  hipStream_t s = h->stream;
+  const bool f64 = h->prec == INVASKIT_PREC_FP64;
+  const DevBuf& tb = sp->tables;
+  HIP_TRY(h, run_trsm(tb, sp->leaf_trsm, s));
+  if (h->L == 0) return INVASKIT_OK;
+  HIP_TRY(h, run_gemm(tb, sp->leaf_proj, f64, s));
+  for (size_t q = 0; q < sp->zsolve.size(); ++q) {
+    HIP_TRY(h, run_trsm(tb, sp->zsolve[q], s));
+    HIP_TRY(h, run_gemm(tb, sp->pgemm[q], f64, s));
+  }
+  HIP_TRY(h, run_gemm(tb, sp->final_, f64, s));
+  return INVASKIT_OK;
+}
+
+// ------------------------------------------------------------ matvec plans
+int build_mv_plan(H* h, int r, MatvecPlan*& out) {
+  auto it = h->mv_plans.find(r);
+  if (it != h->mv_plans.end()) {
+    out = it->second.get();
+    return INVASKIT_OK;
+  }
+  if (h->d > kMvMaxDim)
+    return fail_h(h, INVASKIT_E_ARG,
+                  "the fused FP64 hierarchical product supports d <= " + std::to_string(kMvMaxDim));
+  auto mp = std::make_unique<MatvecPlan>();
+  mp->r = r;
+  const int L = h->L;
+  std::vector<int64_t> q_off(h->nn, 0);
+  int64_t off = 0;
+  for (int c = 1; c < h->nn; ++c) {
+    q_off[c] = off;
+    off += (int64_t)h->s[c] * r;
+  }
+  int rc;
+  if ((rc = dev_alloc(h, mp->xm, (size_t)h->N * r * 8))) return rc;
+  if ((rc = dev_alloc(h, mp->q, std::max<int64_t>(off, 1) * 8))) return rc;
+  if ((rc = dev_alloc(h, mp->nrm, 2 * sizeof(double) * r))) return rc;
+  double* xm = static_cast<double*>(mp->xm.p);
+  double* q = static_cast<double*>(mp->q.p);
+  const int32_t* skd = static_cast<const int32_t*>(h->skel_d.p);
+  Arena ar;
+  // Skeletonize (weight part), levels L .. 1
+  for (int k = L; k >= 1; --k) {
+    GemmBuilder gb;
+    for (int c = (1 << k) - 1; c < (2 << k) - 1; ++c) {
+      gb.begin(q + q_off[c], h->s[c], h->s[c], r, 1.0, 0.0);
+      const double* Pc = h->P64 + h->p_off[c];
+      if (k == L) {
+        const int m = (int)(h->nb[c] - h->na[c]);
+        gb.seg(Pc, m, true, xm + h->na[c], h->N, m);
+      } else {
+        const int l = 2 * c + 1, rr = 2 * c + 2;
+        gb.seg(Pc, h->z[c], true, q + q_off[l], h->s[l], h->s[l]);
+        gb.seg(Pc + h->s[l], h->z[c], true, q + q_off[rr], h->s[rr], h->s[rr]);
+      }
+    }
+    mp->skel.push_back(gb.emit(ar));
+  }
+  // Evaluate: per leaf, its own block plus one skeleton segment per level
+  std::vector<MvSeg> segs;
+  std::vector<MvTile> tiles;
+  for (int j = 0; j < h->nleaves; ++j) {
+    const int lf = h->leaf_node(j);
+    const int m = (int)(h->nb[lf] - h->na[lf]);
+    const int seg0 = (int)segs.size();
+    MvSeg g{};
+    g.idx = nullptr;
+    g.p0 = h->na[lf];
+    g.w = xm + h->na[lf];
+    g.ldw = h->N;
+    g.count = m;
+    segs.push_back(g);
+    for (int k = 1; k <= L; ++k) {
+      const int c = h->anc(lf, k);
+      const int cs = h->sib(c);
+      MvSeg t{};
+      t.idx = skd + h->skel_off[cs];
+      t.p0 = 0;
+      t.w = q + q_off[cs];
+      t.ldw = h->s[cs];
+      t.count = h->s[cs];
+      segs.push_back(t);
+    }
+    for (int t0 = 0; t0 < m; t0 += kMvBlock) {
+      MvTile t{};
+      t.row0 = h->na[lf] + t0;
+      t.rows = std::min(kMvBlock, m - t0);
+      t.seg0 = seg0;
+      t.nseg = L + 1;
+      tiles.push_back(t);
+    }
+  }
+  mp->mv_segs = ar.add(segs);
+  mp->mv_tiles = ar.add(tiles);
+  mp->n_mv_tiles = (int)tiles.size();
+  if ((rc = dev_alloc(h, mp->tables, ar.host.size()))) return rc;
+  HIP_TRY(h, hipMemcpy(mp->tables.p, ar.host.data(), ar.host.size(), hipMemcpyHostToDevice));
+  out = mp.get();
+  h->mv_plans[r] = std::move(mp);
+  return INVASKIT_OK;
+}
+
+// y = (lam I + K~) x  (or b - that when b != nullptr); x is copied first
+int run_matvec(H* h, MatvecPlan* mp, const double* x, int64_t ldx, double* y, int64_t ldy,
+               const double* b, int64_t ldb) {
+  hipStream_t s = h->stream;
+  const int r = mp->r;
+  double* xm = static_cast<double*>(mp->xm.p);
+  HIP_TRY(h, launch_copy_cols<double, double>(x, ldx, xm, h->N, h->N, r, nullptr, false, s));
+  for (const GemmL& g : mp->skel) HIP_TRY(h, run_gemm(mp->tables, g, true, s));
+  const MvTile* t = at<MvTile>(mp->tables, mp->mv_tiles);
+  const MvSeg* g = at<MvSeg>(mp->tables, mp->mv_segs);
+  if (h->pdt == INVASKIT_F64)
+    HIP_TRY(h, launch_mv_eval<double>(static_cast<const double*>(h->X), h->d, h->h, h->lam, t,
+                                      mp->n_mv_tiles, g, xm, h->N, y, ldy, b, ldb, r, s));
+  else
+    HIP_TRY(h, launch_mv_eval<float>(static_cast<const float*>(h->X), h->d, h->h, h->lam, t,
+                                     mp->n_mv_tiles, g, xm, h->N, y, ldy, b, ldb, r, s));
+  return INVASKIT_OK;
+}
+
+int col_norms2(H* h, const double* v, int64_t ld, int r, double* dev_out, std::vector<double>& host) {
+  HIP_TRY(h, launch_colsumsq(v, ld, h->N, r, dev_out, h->stream));
+  host.assign(r, 0.0);
+  HIP_TRY(h, hipMemcpyAsync(host.data(), dev_out, sizeof(double) * r, hipMemcpyDeviceToHost,
+                            h->stream));
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  return INVASKIT_OK;
+}
+
+int do_solve(H* h, const double* b, int64_t r64v, int64_t ldb, double* x, int64_t ldx,
+             invaskit_solve_info* info) {
+  const int r = (int)r64v;
+  hipStream_t s = h->stream;
+  SolvePlan* sp = nullptr;
+  int rc;
+  if ((rc = build_solve_plan(h, r, sp))) return rc;
+  const bool need_res = (h->prec == INVASKIT_PREC_MIXED) || info != nullptr;
+  MatvecPlan* mp = nullptr;
+  if (need_res && (rc = build_mv_plan(h, r, mp))) return rc;
+  invaskit_solve_info loc{};
+  if (h->prec == INVASKIT_PREC_FP64) {
+    double* xb = static_cast<double*>(sp->xbuf.p);
+    HIP_TRY(h, launch_copy_cols<double, double>(b, ldb, xb, h->N, h->N, r, nullptr, false, s));
+    if ((rc = run_solve_plan(h, sp))) return rc;
+    HIP_TRY(h, launch_copy_cols<double, double>(xb, h->N, x, ldx, h->N, r, nullptr, false, s));
+    if (info) {
+      // residual b - A x with the FP64 hierarchical product, into xbuf
+      double* nrm = static_cast<double*>(mp->nrm.p);
+      std::vector<double> bn, rn;
+      if ((rc = col_norms2(h, b, ldb, r, nrm, bn))) return rc;
+      if ((rc = run_matvec(h, mp, x, ldx, xb, h->N, b, ldb))) return rc;
+      if ((rc = col_norms2(h, xb, h->N, r, nrm + r, rn))) return rc;
+      double worst = 0.0;
+      for (int c = 0; c < r; ++c)
+        worst = std::max(worst, bn[c] > 0 ? std::sqrt(rn[c] / bn[c]) : std::sqrt(rn[c]));
+      loc.iterations = 0;
+      loc.converged = 1;
+      loc.final_rel_residual = worst;
+      loc.unrefined_rel_residual = worst;
+      *info = loc;
+    }
+    return INVASKIT_OK;
+  }
+  // mixed precision: iterative refinement
+  double* x64 = static_cast<double*>(sp->x64.p);
+  double* r64 = static_cast<double*>(sp->r64.p);
+  float* xb = static_cast<float*>(sp->xbuf.p);
+  double* sc = static_cast<double*>(sp->sc.p);
+  double* nrm = static_cast<double*>(mp->nrm.p);
+  std::vector<double> bn, rn, scale(r);
+  if ((rc = col_norms2(h, b, ldb, r, nrm, bn))) return rc;
+  HIP_TRY(h, launch_fill_zero(x64, sizeof(double) * h->N * r, s));
+  HIP_TRY(h, launch_copy_cols<double, double>(b, ldb, r64, h->N, h->N, r, nullptr, false, s));
+  rn = bn;
+  double best = INFINITY, hist[3] = {INFINITY, INFINITY, INFINITY};
+  int it = 0;
+  bool conv = false;
+  for (it = 1; it <= h->maxit; ++it) {
+    for (int c = 0; c < r; ++c) scale[c] = std::sqrt(rn[c]);
+    HIP_TRY(h, hipMemcpyAsync(sc, scale.data(), sizeof(double) * r, hipMemcpyHostToDevice, s));
+    HIP_TRY(h, launch_copy_cols<double, float>(r64, h->N, xb, h->N, h->N, r, sc, true, s));
+    if ((rc = run_solve_plan(h, sp))) return rc;
+    HIP_TRY(h, launch_axpy_cols(x64, h->N, xb, h->N, h->N, r, sc, s));
+    if ((rc = run_matvec(h, mp, x64, h->N, r64, h->N, b, ldb))) return rc;
+    if ((rc = col_norms2(h, r64, h->N, r, nrm + r, rn))) return rc;
+    double worst = 0.0;
+    for (int c = 0; c < r; ++c)
+      worst = std::max(worst, bn[c] > 0 ? std::sqrt(rn[c] / bn[c]) : std::sqrt(rn[c]));
+    if (it == 1) loc.unrefined_rel_residual = worst;
+    loc.final_rel_residual = worst;
+    best = std::min(best, worst);
+    if (worst <= h->tol) {
+      conv = true;
+      break;
+    }
+    if (!std::isfinite(worst)) break;
+    // stall: no halving over the last three iterations
+    if (it > 3 && worst > 0.5 * hist[0]) break;
+    hist[0] = hist[1];
+    hist[1] = hist[2];
+    hist[2] = worst;
+  }
+  loc.iterations = std::min(it, h->maxit);
+  loc.converged = conv ? 1 : 0;
+  HIP_TRY(h, launch_copy_cols<double, double>(x64, h->N, x, ldx, h->N, r, nullptr, false, s));
+  HIP_TRY(h, hipStreamSynchronize(s));
+  if (info) *info = loc;
+  if (!conv)
+    return fail_h(h, INVASKIT_E_NOT_CONVERGED,
+                  "refinement stopped after " + std::to_string(loc.iterations) +
+                      " iterations at relative residual " + std::to_string(loc.final_rel_residual));
+  return INVASKIT_OK;
+}
+
+}  // namespace
+
+// ===================================================================== C ABI
+extern "C" {
+
+int invaskit_default_options(invaskit_options* opt) {
+  if (!opt) return INVASKIT_E_ARG;
+  opt->precision = INVASKIT_PREC_FP64;
+  opt->fp64_top_levels = 4;
+  opt->refine_tol = 1e-10;
+  opt->max_refine_iters = 30;
+  opt->reserved0 = 0;
+  return INVASKIT_OK;
+}
+
+int invaskit_factor(const invaskit_problem* pb, double lambda, const invaskit_options* opt,
+                    void* hip_stream, invaskit_handle* out) {
+  if (!out) return fail_h(nullptr, INVASKIT_E_ARG, "out is NULL");
+  *out = nullptr;
+  int rc = validate(nullptr, pb, lambda, opt);
+  if (rc) return rc;
+  if ((rc = check_device(nullptr))) return rc;
+  std::unique_ptr<H> h(new H());
+  invaskit_options o;
+  invaskit_default_options(&o);
+  if (opt) o = *opt;
+  h->prec = o.precision;
+  h->top64 = o.fp64_top_levels;
+  h->tol = o.refine_tol;
+  h->maxit = o.max_refine_iters;
+  h->stream = static_cast<hipStream_t>(hip_stream);
+  h->N = pb->n;
+  h->d = pb->d;
+  h->L = pb->depth;
+  h->pdt = pb->points_dtype;
+  h->X = pb->points;
+  h->P64 = pb->p_values;
+  h->h = pb->h;
+  h->lam = lambda;
+  h->nleaves = 1 << h->L;
+  h->nn = (1 << (h->L + 1)) - 1;
+  h->leaf_off.assign(pb->leaf_offsets, pb->leaf_offsets + h->nleaves + 1);
+  h->skel_off.assign(pb->skel_offsets, pb->skel_offsets + h->nn + 1);
+  h->p_off.assign(pb->p_offsets, pb->p_offsets + h->nn + 1);
+  if (h->skel_off[h->nn] > 0)
+    h->skel_idx.assign(pb->skel_index, pb->skel_index + h->skel_off[h->nn]);
+  if ((rc = plan_factor(h.get()))) return rc;
+  rc = run_factor(h.get());
+  *out = h.release();
+  return rc;
+}
+
+int invaskit_refactor(invaskit_handle h, double lambda) {
+  if (!h) return fail_h(nullptr, INVASKIT_E_ARG, "handle is NULL");
+  if (!std::isfinite(lambda)) return fail_h(h, INVASKIT_E_ARG, "lambda must be finite");
+  h->lam = lambda;
+  return run_factor(h);
+}
+
+int invaskit_solve(invaskit_handle h, const double* b, int64_t nrhs, int64_t ldb, double* x,
+                   int64_t ldx, invaskit_solve_info* info) {
+  if (!h) return fail_h(nullptr, INVASKIT_E_ARG, "handle is NULL");
+  if (!b || !x) return fail_h(h, INVASKIT_E_ARG, "b and x are required");
+  if (nrhs < 1 || nrhs > 4096) return fail_h(h, INVASKIT_E_ARG, "nrhs must be in [1, 4096]");
+  if (ldb < h->N || ldx < h->N) return fail_h(h, INVASKIT_E_ARG, "ldb and ldx must be >= n");
+  const char* b0 = reinterpret_cast<const char*>(b);
+  const char* b1 = reinterpret_cast<const char*>(b + (nrhs - 1) * ldb + h->N);
+  const char* x0 = reinterpret_cast<const char*>(x);
+  const char* x1 = reinterpret_cast<const char*>(x + (nrhs - 1) * ldx + h->N);
+  if (b0 < x1 && x0 < b1) return fail_h(h, INVASKIT_E_ARG, "b and x overlap");
+  return do_solve(h, b, nrhs, ldb, x, ldx, info);
+}
+
+int invaskit_matvec(invaskit_handle h, const double* x, int64_t nrhs, int64_t ldx, double* y,
+                    int64_t ldy) {
+  if (!h) return fail_h(nullptr, INVASKIT_E_ARG, "handle is NULL");
+  if (!x || !y) return fail_h(h, INVASKIT_E_ARG, "x and y are required");
+  if (nrhs < 1 || nrhs > 4096) return fail_h(h, INVASKIT_E_ARG, "nrhs must be in [1, 4096]");
+  if (ldx < h->N || ldy < h->N) return fail_h(h, INVASKIT_E_ARG, "ldx and ldy must be >= n");
+  MatvecPlan* mp = nullptr;
+  int rc = build_mv_plan(h, (int)nrhs, mp);
+  if (rc) return rc;
+  return run_matvec(h, mp, x, ldx, y, ldy, nullptr, 0);
+}
+
+int invaskit_device_bytes(invaskit_handle h, size_t* bytes) {
+  if (!h || !bytes) return fail_h(h, INVASKIT_E_ARG, "handle and bytes are required");
+  size_t t = 0;
+  for (const DevBuf* b : {&h->skel_d, &h->P32, &h->leafLU, &h->leafPerm, &h->leafInfo, &h->slab,
+                          &h->Z64, &h->ZT, &h->zperm, &h->zinfo, &h->fsweep, &h->ftables})
+    t += b->bytes;
+  for (auto& kv : h->solve_plans)
+    for (const DevBuf* b : {&kv.second->tables, &kv.second->xbuf, &kv.second->sbuf,
+                            &kv.second->x64, &kv.second->r64, &kv.second->sc})
+      t += b->bytes;
+  for (auto& kv : h->mv_plans)
+    for (const DevBuf* b : {&kv.second->tables, &kv.second->xm, &kv.second->q, &kv.second->nrm})
+      t += b->bytes;
+  *bytes = t;
+  return INVASKIT_OK;
+}
+
+int invaskit_phase_times(invaskit_handle h, double* ms, int32_t n) {
+  if (!h || !ms) return fail_h(h, INVASKIT_E_ARG, "handle and ms are required");
+  for (int i = 0; i < std::min(n, 8); ++i) ms[i] = h->phase_ms[i];
+  return INVASKIT_OK;
+}
+
+int invaskit_destroy(invaskit_handle h) {
+  if (!h) return INVASKIT_OK;
+  (void)hipStreamSynchronize(h->stream);
+  delete h;
+  return INVASKIT_OK;
+}
+
+const char* invaskit_status_string(int status) {
+  switch (status) {
+    case INVASKIT_OK: return "ok";
+    case INVASKIT_E_ARG: return "invalid argument";
+    case INVASKIT_E_MEMORY: return "device allocation failed";
+    case INVASKIT_E_HIP: return "HIP runtime error";
+    case INVASKIT_E_SINGULAR: return "singular pivot";
+    case INVASKIT_E_NOT_CONVERGED: return "refinement did not converge";
+    case INVASKIT_E_DEVICE: return "no usable gfx950 device";
+    default: return "unknown status";
+  }
+}
+
+int invaskit_last_error(invaskit_handle h, char* buf, size_t n) {
+  if (!buf || n == 0) return INVASKIT_E_ARG;
+  const std::string& m = h ? h->err : g_last_error;
+  const size_t k = std::min(n - 1, m.size());
+  std::memcpy(buf, m.data(), k);
+  buf[k] = 0;
+  return INVASKIT_OK;
+}
+
+// ----------------------------------------------------- batched building blocks
+int invaskit_getrf_batched(int32_t dtype, void* a, const int64_t* a_offsets, const int32_t* n,
+                           int32_t count, int32_t* perm, int32_t* info, void* hip_stream) {
+  if (count < 0 || (count > 0 && (!a || !a_offsets || !n || !perm || !info)))
+    return fail_h(nullptr, INVASKIT_E_ARG, "invalid getrf_batched arguments");
+  if (dtype != INVASKIT_F64 && dtype != INVASKIT_F32)
+    return fail_h(nullptr, INVASKIT_E_ARG, "dtype must be INVASKIT_F64 or INVASKIT_F32");
+  if (count == 0) return INVASKIT_OK;
+  const size_t es = dtype == INVASKIT_F64 ? 8 : 4;
+  std::vector<LuProb> probs(count);
+  int nmax = 0;
+  int64_t poff = 0;
+  for (int i = 0; i < count; ++i) {
+    if (n[i] < 1 || n[i] > kMaxLeaf) return fail_h(nullptr, INVASKIT_E_ARG, "n out of range");
+    probs[i].a = static_cast<unsigned char*>(a) + a_offsets[i] * es;
+    probs[i].perm = perm + poff;
+    probs[i].info = info + i;
+    probs[i].n = n[i];
+    poff += n[i];
+    nmax = std::max(nmax, n[i]);
+  }
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  DevBuf t;
+  int rc = dev_alloc(nullptr, t, sizeof(LuProb) * count);
+  if (rc) return rc;
+  hipError_t e = hipMemcpy(t.p, probs.data(), sizeof(LuProb) * count, hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = (dtype == INVASKIT_F64) ? launch_getrf<double>(static_cast<LuProb*>(t.p), count, nmax, s)
+                                : launch_getrf<float>(static_cast<LuProb*>(t.p), count, nmax, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  t.release();
+  if (e != hipSuccess) return fail_h(nullptr, INVASKIT_E_HIP, hipGetErrorString(e));
+  return INVASKIT_OK;
+}
+
+int invaskit_getrs_batched(int32_t dtype, const void* a, const int64_t* a_offsets,
+                           const int32_t* n, const int32_t* perm, void* b,
+                           const int64_t* b_offsets, const int32_t* nrhs, const int64_t* ldb,
+                           int32_t count, void* hip_stream) {
+  if (count < 0 || (count > 0 && (!a || !a_offsets || !n || !perm || !b || !b_offsets || !nrhs ||
+                                  !ldb)))
+    return fail_h(nullptr, INVASKIT_E_ARG, "invalid getrs_batched arguments");
+  if (dtype != INVASKIT_F64 && dtype != INVASKIT_F32)
+    return fail_h(nullptr, INVASKIT_E_ARG, "dtype must be INVASKIT_F64 or INVASKIT_F32");
+  if (count == 0) return INVASKIT_OK;
+  const size_t es = dtype == INVASKIT_F64 ? 8 : 4;
+  TrsmBuilder tb;
+  int64_t poff = 0;
+  for (int i = 0; i < count; ++i) {
+    if (n[i] < 1 || n[i] > kMaxLeaf || nrhs[i] < 0 || ldb[i] < n[i])
+      return fail_h(nullptr, INVASKIT_E_ARG, "getrs_batched sizes out of range");
+    void* bi = static_cast<unsigned char*>(b) + b_offsets[i] * es;
+    tb.add(static_cast<const unsigned char*>(a) + a_offsets[i] * es, perm + poff, n[i], nrhs[i],
+           bi, ldb[i], n[i], bi, ldb[i], bi, ldb[i]);
+    poff += n[i];
+  }
+  Arena ar;
+  const int f = dtype == INVASKIT_F64 ? 1 : 0;
+  TrsmL l = tb.emit(ar, f, f);
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  DevBuf t;
+  int rc = dev_alloc(nullptr, t, ar.host.size());
+  if (rc) return rc;
+  hipError_t e = hipMemcpy(t.p, ar.host.data(), ar.host.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = run_trsm(t, l, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  t.release();
+  if (e != hipSuccess) return fail_h(nullptr, INVASKIT_E_HIP, hipGetErrorString(e));
+  return INVASKIT_OK;
+}
+
+int invaskit_kernel_blocks(int32_t points_dtype, const void* points, int32_t d, double hbw,
+                           int32_t out_dtype, void* out, const int64_t* out_offsets,
+                           const int64_t* row0, const int32_t* rows, const int32_t* cols,
+                           const int64_t* cols_offsets, const int32_t* ncols, const int32_t* diag,
+                           double shift, int32_t count, void* hip_stream) {
+  if (count < 0 || d < 1 || !(hbw > 0) ||
+      (count > 0 && (!points || !out || !out_offsets || !row0 || !rows || !cols ||
+                     !cols_offsets || !ncols || !diag)))
+    return fail_h(nullptr, INVASKIT_E_ARG, "invalid kernel_blocks arguments");
+  if ((points_dtype != INVASKIT_F64 && points_dtype != INVASKIT_F32) ||
+      (out_dtype != INVASKIT_F64 && out_dtype != INVASKIT_F32))
+    return fail_h(nullptr, INVASKIT_E_ARG, "dtypes must be INVASKIT_F64 or INVASKIT_F32");
+  if (count == 0) return INVASKIT_OK;
+  const size_t es = out_dtype == INVASKIT_F64 ? 8 : 4;
+  std::vector<EvalBlock> blocks(count);
+  std::vector<Tile3> tiles;
+  for (int i = 0; i < count; ++i) {
+    if (rows[i] < 0 || ncols[i] < 0) return fail_h(nullptr, INVASKIT_E_ARG, "negative block size");
+    EvalBlock& b = blocks[i];
+    b.out = static_cast<unsigned char*>(out) + out_offsets[i] * es;
+    b.ld = rows[i];
+    b.row0 = row0[i];
+    b.cols = cols + cols_offsets[i];
+    b.col0 = 0;
+    b.rows = rows[i];
+    b.ncols = ncols[i];
+    b.diag = diag[i];
+    for (int tn = 0; tn < (ncols[i] + kEvalTile - 1) / kEvalTile; ++tn)
+      for (int tm = 0; tm < (rows[i] + kEvalTile - 1) / kEvalTile; ++tm) tiles.push_back({i, tm, tn});
+  }
+  Arena ar;
+  const size_t ob = ar.add(blocks), ot = ar.add(tiles);
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  DevBuf t;
+  int rc = dev_alloc(nullptr, t, ar.host.size());
+  if (rc) return rc;
+  hipError_t e = hipMemcpy(t.p, ar.host.data(), ar.host.size(), hipMemcpyHostToDevice);
+  const int nt = (int)tiles.size();
+  if (e == hipSuccess) {
+    const EvalBlock* pb = at<EvalBlock>(t, ob);
+    const Tile3* pt = at<Tile3>(t, ot);
+    if (points_dtype == INVASKIT_F64) {
+      const double* X = static_cast<const double*>(points);
+      e = out_dtype == INVASKIT_F64 ? launch_eval<double, double>(X, d, hbw, shift, pb, pt, nt, s)
+                                    : launch_eval<double, float>(X, d, hbw, shift, pb, pt, nt, s);
+    } else {
+      const float* X = static_cast<const float*>(points);
+      e = out_dtype == INVASKIT_F64 ? launch_eval<float, double>(X, d, hbw, shift, pb, pt, nt, s)
+                                    : launch_eval<float, float>(X, d, hbw, shift, pb, pt, nt, s);
+    }
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  t.release();
+  if (e != hipSuccess) return fail_h(nullptr, INVASKIT_E_HIP, hipGetErrorString(e));
+  return INVASKIT_OK;
+}
+
+int invaskit_gemm_batched(int32_t dtype, const void* a, const void* b, void* c,
+                          const int64_t* a_off, const int64_t* b_off, const int64_t* c_off,
+                          const int32_t* m, const int32_t* n, const int32_t* k,
+                          const int64_t* lda, const int32_t* a_rm, const int64_t* ldb,
+                          const int64_t* ldc, double alpha, double beta, int32_t count,
+                          void* hip_stream) {
+  if (count < 0 || (count > 0 && (!a || !b || !c || !a_off || !b_off || !c_off || !m || !n ||
+                                  !k || !lda || !a_rm || !ldb || !ldc)))
+    return fail_h(nullptr, INVASKIT_E_ARG, "invalid gemm_batched arguments");
+  if (dtype != INVASKIT_F64 && dtype != INVASKIT_F32)
+    return fail_h(nullptr, INVASKIT_E_ARG, "dtype must be INVASKIT_F64 or INVASKIT_F32");
+  if (count == 0) return INVASKIT_OK;
+  const size_t es = dtype == INVASKIT_F64 ? 8 : 4;
+  GemmBuilder gb;
+  for (int i = 0; i < count; ++i) {
+    if (m[i] < 0 || n[i] < 0 || k[i] < 0 || ldc[i] < m[i] || ldb[i] < k[i] ||
+        lda[i] < (a_rm[i] ? k[i] : m[i]))
+      return fail_h(nullptr, INVASKIT_E_ARG, "gemm_batched sizes out of range");
+    gb.begin(static_cast<unsigned char*>(c) + c_off[i] * es, ldc[i], m[i], n[i], alpha, beta);
+    gb.seg(static_cast<const unsigned char*>(a) + a_off[i] * es, lda[i], a_rm[i] != 0,
+           static_cast<const unsigned char*>(b) + b_off[i] * es, ldb[i], k[i]);
+  }
+  Arena ar;
+  GemmL l = gb.emit(ar);
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  DevBuf t;
+  int rc = dev_alloc(nullptr, t, ar.host.size());
+  if (rc) return rc;
+  hipError_t e = hipMemcpy(t.p, ar.host.data(), ar.host.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = run_gemm(t, l, dtype == INVASKIT_F64, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  t.release();
+  if (e != hipSuccess) return fail_h(nullptr, INVASKIT_E_HIP, hipGetErrorString(e));
+  return INVASKIT_OK;
+}
+
+}  // extern "C"

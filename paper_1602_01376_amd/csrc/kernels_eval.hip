@@ -1,0 +1,217 @@
+// Gaussian kernel evaluation (eq. (e:gaussian)), K(x,y) = exp(-|x-y|^2/(2h^2)).
+//
+// k_eval writes blocks of K: the leaf blocks lambda*I + K_{aa} of
+// Algorithm 1 and the skeleton blocks K_{c, sibling~} of eq.
+// (e:offdiag-askit), straight into the factor storage.  A workgroup computes
+// a 64 x 64 tile: the 64 row points and 64 column points are staged through
+// LDS in chunks of 8 coordinates and every thread accumulates a 4 x 4 block
+// of squared distances by direct differences in FP64 (no |x|^2+|y|^2-2x.y
+// cancellation), then applies exp and stores in the factor precision.
+//
+// k_mv_eval is the fused FP64 evaluate step of the hierarchical product
+// (Section II-B, Evaluate): one thread per target point keeps its
+// coordinates in registers; source points and their weights are staged
+// through LDS 64 at a time and K(x_i, x_j) is consumed immediately, so the
+// kernel matrix is never stored.
+#include <cmath>
+
+#include "internal.hpp"
+
+namespace invaskit {
+namespace {
+
+constexpr int ET = kEvalTile;  // 64
+constexpr int DC = 8;          // coordinates per LDS chunk
+
+template <typename PT, typename T>
+__global__ __launch_bounds__(256) void k_eval(const PT* __restrict__ X, int d, double nhalf_inv_h2,
+                                              double shift, const EvalBlock* __restrict__ blocks,
+                                              const Tile3* __restrict__ tiles) {
+  __shared__ double xr[DC][ET + 1];
+  __shared__ double xc[DC][ET + 1];
+  __shared__ int64_t cidx[ET];
+  const Tile3 t = tiles[blockIdx.x];
+  const EvalBlock b = blocks[t.prob];
+  const int r0 = t.tm * ET, c0 = t.tn * ET;
+  const int tid = threadIdx.x;
+  const int tr = tid & 15, tc = tid >> 4;
+
+  if (tid < ET) {
+    const int c = c0 + tid;
+    int64_t g = -1;
+    if (c < b.ncols) g = b.cols ? (int64_t)b.cols[c] : b.col0 + c;
+    cidx[tid] = g;
+  }
+  __syncthreads();
+
+  double acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+
+  for (int dd = 0; dd < d; dd += DC) {
+    for (int idx = tid; idx < ET * DC; idx += 256) {
+      const int p = idx / DC, k = idx % DC;
+      const int r = r0 + p;
+      const bool kin = dd + k < d;
+      xr[k][p] = (r < b.rows && kin) ? (double)X[(b.row0 + r) * d + dd + k] : 0.0;
+      const int64_t g = cidx[p];
+      xc[k][p] = (g >= 0 && kin) ? (double)X[g * d + dd + k] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < DC; ++k) {
+      double a[4], c[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = xr[k][tr + 16 * i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) c[j] = xc[k][tc + 16 * j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const double df = a[i] - c[j];
+          acc[i][j] = fma(df, df, acc[i][j]);
+        }
+    }
+    __syncthreads();
+  }
+
+  T* __restrict__ out = static_cast<T*>(b.out);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int c = c0 + tc + 16 * j;
+    if (c >= b.ncols) continue;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = r0 + tr + 16 * i;
+      if (r >= b.rows) continue;
+      double v = exp(acc[i][j] * nhalf_inv_h2);
+      if (b.diag && r == c) v += shift;
+      out[(int64_t)c * b.ld + r] = (T)v;
+    }
+  }
+}
+
+constexpr int MB = kMvBlock;  // targets per workgroup (one per thread)
+constexpr int MS = 64;        // sources per LDS stage
+constexpr int RC = 4;         // right-hand sides per pass
+
+template <typename PT, int DM>
+__global__ __launch_bounds__(MB) void k_mv_eval(const PT* __restrict__ X, int d, double nhalf_inv_h2,
+                                                double lam, const MvTile* __restrict__ tiles,
+                                                const MvSeg* __restrict__ segs,
+                                                const double* __restrict__ x, int64_t ldx,
+                                                double* __restrict__ y, int64_t ldy,
+                                                const double* __restrict__ bsub, int64_t ldb,
+                                                int nrhs) {
+  __shared__ double sx[MS][DM + 1];
+  __shared__ double sw[MS][RC];
+  const MvTile t = tiles[blockIdx.x];
+  const int tid = threadIdx.x;
+  const bool active = tid < t.rows;
+  const int64_t i = t.row0 + tid;
+  double xi[DM];
+#pragma unroll
+  for (int k = 0; k < DM; ++k) xi[k] = (active && k < d) ? (double)X[i * d + k] : 0.0;
+
+  for (int cb = 0; cb < nrhs; cb += RC) {
+    const int ncol = min(RC, nrhs - cb);
+    double acc[RC];
+#pragma unroll
+    for (int c = 0; c < RC; ++c) acc[c] = 0.0;
+    for (int s = t.seg0; s < t.seg0 + t.nseg; ++s) {
+      const MvSeg g = segs[s];
+      for (int j0 = 0; j0 < g.count; j0 += MS) {
+        const int nj = min(MS, g.count - j0);
+        __syncthreads();
+        for (int idx = tid; idx < MS * DM; idx += MB) {
+          const int j = idx / DM, k = idx % DM;
+          double v = 0.0;
+          if (j < nj && k < d) {
+            const int64_t p = g.idx ? (int64_t)g.idx[j0 + j] : g.p0 + j0 + j;
+            v = (double)X[p * d + k];
+          }
+          sx[j][k] = v;
+        }
+        for (int idx = tid; idx < MS * RC; idx += MB) {
+          const int j = idx / RC, c = idx % RC;
+          sw[j][c] = (j < nj && c < ncol) ? g.w[(int64_t)(cb + c) * g.ldw + j0 + j] : 0.0;
+        }
+        __syncthreads();
+        for (int j = 0; j < nj; ++j) {
+          double d2 = 0.0;
+#pragma unroll
+          for (int k = 0; k < DM; ++k) {
+            const double df = xi[k] - sx[j][k];
+            d2 = fma(df, df, d2);
+          }
+          const double kv = exp(d2 * nhalf_inv_h2);
+#pragma unroll
+          for (int c = 0; c < RC; ++c) acc[c] = fma(kv, sw[j][c], acc[c]);
+        }
+      }
+    }
+    if (active) {
+      for (int c = 0; c < ncol; ++c) {
+        const double ax = lam * x[(int64_t)(cb + c) * ldx + i] + acc[c];
+        y[(int64_t)(cb + c) * ldy + i] =
+            bsub ? bsub[(int64_t)(cb + c) * ldb + i] - ax : ax;
+      }
+    }
+  }
+}
+
+}  // namespace
+
+template <typename PT, typename T>
+hipError_t launch_eval(const PT* X, int d, double h, double shift, const EvalBlock* blocks,
+                       const Tile3* tiles, int ntiles, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  const double c = -0.5 / (h * h);
+  hipLaunchKernelGGL((k_eval<PT, T>), dim3(ntiles), dim3(256), 0, s, X, d, c, shift, blocks,
+                     tiles);
+  return hipGetLastError();
+}
+
+template <typename PT>
+hipError_t launch_mv_eval(const PT* X, int d, double h, double lam, const MvTile* tiles,
+                          int ntiles, const MvSeg* segs, const double* x, int64_t ldx,
+                          double* y, int64_t ldy, const double* b, int64_t ldb, int nrhs,
+                          hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  const double c = -0.5 / (h * h);
+#define INVASKIT_MV(DMV)                                                                    \
+  hipLaunchKernelGGL((k_mv_eval<PT, DMV>), dim3(ntiles), dim3(MB), 0, s, X, d, c, lam,     \
+                     tiles, segs, x, ldx, y, ldy, b, ldb, nrhs)
+  if (d <= 8)
+    INVASKIT_MV(8);
+  else if (d <= 16)
+    INVASKIT_MV(16);
+  else if (d <= 32)
+    INVASKIT_MV(32);
+  else if (d <= 64)
+    INVASKIT_MV(64);
+  else
+    return hipErrorInvalidValue;
+#undef INVASKIT_MV
+  return hipGetLastError();
+}
+
+template hipError_t launch_eval<double, double>(const double*, int, double, double,
+                                                const EvalBlock*, const Tile3*, int, hipStream_t);
+template hipError_t launch_eval<double, float>(const double*, int, double, double,
+                                               const EvalBlock*, const Tile3*, int, hipStream_t);
+template hipError_t launch_eval<float, double>(const float*, int, double, double,
+                                               const EvalBlock*, const Tile3*, int, hipStream_t);
+template hipError_t launch_eval<float, float>(const float*, int, double, double,
+                                              const EvalBlock*, const Tile3*, int, hipStream_t);
+template hipError_t launch_mv_eval<double>(const double*, int, double, double, const MvTile*,
+                                           int, const MvSeg*, const double*, int64_t, double*,
+                                           int64_t, const double*, int64_t, int, hipStream_t);
+template hipError_t launch_mv_eval<float>(const float*, int, double, double, const MvTile*, int,
+                                          const MvSeg*, const double*, int64_t, double*, int64_t,
+                                          const double*, int64_t, int, hipStream_t);
+
+}  // namespace invaskit

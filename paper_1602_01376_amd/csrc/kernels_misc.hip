@@ -1,0 +1,145 @@
+// Small element-wise kernels: reduced-system assembly (eq. (e:blocksmw)),
+// precision conversions and the FP64 vector steps of iterative refinement.
+#include "internal.hpp"
+
+namespace invaskit {
+namespace {
+
+template <typename TZ, typename TV>
+__global__ __launch_bounds__(256) void k_zform(const ZformProb* __restrict__ probs) {
+  const ZformProb p = probs[blockIdx.x];
+  const int n = p.sr + p.sl;
+  TZ* __restrict__ Z = static_cast<TZ*>(p.Z);
+  const TV* __restrict__ pr = static_cast<const TV*>(p.pr);
+  const TV* __restrict__ pl = static_cast<const TV*>(p.pl);
+  for (int64_t idx = threadIdx.x; idx < (int64_t)n * n; idx += 256) {
+    const int i = (int)(idx % n), j = (int)(idx / n);
+    TZ v;
+    if (i < p.sr) {
+      v = (j < p.sr) ? TZ(i == j) : (TZ)pr[(int64_t)(j - p.sr) * p.sr + i];
+    } else {
+      v = (j < p.sr) ? (TZ)pl[(int64_t)j * p.sl + (i - p.sr)] : TZ(i == j);
+    }
+    Z[idx] = v;
+  }
+}
+
+__global__ void k_convert(const double* __restrict__ in, float* __restrict__ out, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = (float)in[i];
+}
+
+template <typename TI, typename TO>
+__global__ void k_copy_cols(const TI* __restrict__ in, int64_t ldi, TO* __restrict__ out,
+                            int64_t ldo, int64_t n, const double* __restrict__ scale, int inv) {
+  const int c = blockIdx.y;
+  double s = 1.0;
+  if (scale) s = inv ? (scale[c] > 0 ? 1.0 / scale[c] : 0.0) : scale[c];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    out[c * ldo + i] = (TO)((double)in[c * ldi + i] * s);
+}
+
+__global__ void k_axpy_cols(double* __restrict__ x, int64_t ldx, const float* __restrict__ d,
+                            int64_t ldd, int64_t n, const double* __restrict__ scale) {
+  const int c = blockIdx.y;
+  const double s = scale[c];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    x[c * ldx + i] += s * (double)d[c * ldd + i];
+}
+
+__global__ __launch_bounds__(256) void k_colsumsq(const double* __restrict__ v, int64_t ld,
+                                                  int64_t n, double* __restrict__ out) {
+  __shared__ double part[4];
+  const int c = blockIdx.y;
+  double acc = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double a = v[c * ld + i];
+    acc = fma(a, a, acc);
+  }
+  for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(out + c, part[0] + part[1] + part[2] + part[3]);
+}
+
+__global__ void k_zero(unsigned char* __restrict__ p, size_t bytes) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < bytes;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+
+int grid_for(int64_t n) {
+  int64_t g = (n + 255) / 256;
+  if (g > 4096) g = 4096;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+}  // namespace
+
+template <typename TZ, typename TV>
+hipError_t launch_zform(const ZformProb* probs, int count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_zform<TZ, TV>), dim3(count), dim3(256), 0, s, probs);
+  return hipGetLastError();
+}
+template hipError_t launch_zform<double, double>(const ZformProb*, int, hipStream_t);
+template hipError_t launch_zform<float, float>(const ZformProb*, int, hipStream_t);
+template hipError_t launch_zform<double, float>(const ZformProb*, int, hipStream_t);
+
+hipError_t launch_convert_f64_f32(const double* in, float* out, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_convert, dim3(grid_for(n)), dim3(256), 0, s, in, out, n);
+  return hipGetLastError();
+}
+
+template <typename TI, typename TO>
+hipError_t launch_copy_cols(const TI* in, int64_t ldi, TO* out, int64_t ldo, int64_t n,
+                            int ncols, const double* scale, bool invert_scale, hipStream_t s) {
+  if (n <= 0 || ncols <= 0) return hipSuccess;
+  const int g = (grid_for(n) + ncols - 1) / ncols + 1;
+  hipLaunchKernelGGL((k_copy_cols<TI, TO>), dim3(g, ncols), dim3(256), 0, s, in, ldi, out, ldo, n,
+                     scale, invert_scale ? 1 : 0);
+  return hipGetLastError();
+}
+template hipError_t launch_copy_cols<double, double>(const double*, int64_t, double*, int64_t,
+                                                     int64_t, int, const double*, bool,
+                                                     hipStream_t);
+template hipError_t launch_copy_cols<double, float>(const double*, int64_t, float*, int64_t,
+                                                    int64_t, int, const double*, bool,
+                                                    hipStream_t);
+template hipError_t launch_copy_cols<float, double>(const float*, int64_t, double*, int64_t,
+                                                    int64_t, int, const double*, bool,
+                                                    hipStream_t);
+
+hipError_t launch_axpy_cols(double* x, int64_t ldx, const float* d, int64_t ldd, int64_t n,
+                            int ncols, const double* scale, hipStream_t s) {
+  if (n <= 0 || ncols <= 0) return hipSuccess;
+  const int g = (grid_for(n) + ncols - 1) / ncols + 1;
+  hipLaunchKernelGGL(k_axpy_cols, dim3(g, ncols), dim3(256), 0, s, x, ldx, d, ldd, n, scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_colsumsq(const double* v, int64_t ld, int64_t n, int ncols, double* out,
+                           hipStream_t s) {
+  if (ncols <= 0) return hipSuccess;
+  hipError_t e = launch_fill_zero(out, sizeof(double) * ncols, s);
+  if (e != hipSuccess || n <= 0) return e;
+  const int g = (grid_for(n) + ncols - 1) / ncols + 1;
+  hipLaunchKernelGGL(k_colsumsq, dim3(g, ncols), dim3(256), 0, s, v, ld, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return hipSuccess;
+  int64_t g = (int64_t)((bytes + 255) / 256);
+  if (g > 4096) g = 4096;
+  hipLaunchKernelGGL(k_zero, dim3((int)g), dim3(256), 0, s, static_cast<unsigned char*>(p), bytes);
+  return hipGetLastError();
+}
+
+}  // namespace invaskit

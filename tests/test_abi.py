@@ -1,0 +1,158 @@
+"""Host-only checks of the C ABI: the library loads, exports every symbol the
+header declares, and rejects invalid input before touching a GPU."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "invaskit.h")
+LIB = os.path.join(ROOT, "paper_1602_01376_amd", "libinvaskit.so")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(invaskit_\w+)\s*\(", txt, re.M)))
+
+
+def test_header_declares_entry_points():
+    names = _declared()
+    for n in ("invaskit_factor", "invaskit_solve", "invaskit_matvec", "invaskit_destroy",
+              "invaskit_refactor", "invaskit_getrf_batched", "invaskit_getrs_batched",
+              "invaskit_kernel_blocks", "invaskit_status_string", "invaskit_last_error"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = C.CDLL(LIB)
+    for n in _declared():
+        assert hasattr(lib, n), n
+
+
+def test_binding_covers_header():
+    from paper_1602_01376_amd import binding
+    assert sorted(binding.EXPORTED) == _declared()
+
+
+def test_status_strings():
+    from paper_1602_01376_amd import binding
+    lib = binding.library()
+    assert lib.invaskit_status_string(0) == b"ok"
+    assert lib.invaskit_status_string(-4) == b"singular pivot"
+    assert lib.invaskit_status_string(-99) == b"unknown status"
+
+
+def _raw_problem(pb, **over):
+    from paper_1602_01376_amd import binding
+    arrs = dict(leaf=np.ascontiguousarray(pb.leaf_offsets, np.int64),
+                so=np.ascontiguousarray(pb.skel_offsets, np.int64),
+                si=np.ascontiguousarray(pb.skel_index, np.int32),
+                po=np.ascontiguousarray(pb.p_offsets, np.int64))
+    arrs.update({k: v for k, v in over.items() if k in arrs})
+    fields = dict(n=pb.n, d=pb.d, depth=pb.depth, points_dtype=0, reserved0=0,
+                  points=0x1000, leaf_offsets=arrs["leaf"].ctypes.data,
+                  skel_offsets=arrs["so"].ctypes.data, skel_index=arrs["si"].ctypes.data,
+                  p_offsets=arrs["po"].ctypes.data, p_values=0x2000, h=pb.h)
+    fields.update({k: v for k, v in over.items() if k not in arrs})
+    return binding._Problem(**fields), arrs
+
+
+@pytest.fixture(scope="module")
+def small_problem():
+    from paper_1602_01376_amd.setup import make_problem
+    return make_problem("tiny", n=512, depth=2)
+
+
+def _factor_status(raw, lam=1e-2, opt=None):
+    from paper_1602_01376_amd import binding
+    h = C.c_void_p()
+    st = binding.library().invaskit_factor(C.byref(raw), lam, C.byref(opt) if opt else None,
+                                           None, C.byref(h))
+    return st, binding.last_error()
+
+
+@pytest.mark.parametrize("case,expect", [
+    (dict(n=0), "n must be"),
+    (dict(d=0), "d must be"),
+    (dict(depth=-1), "depth"),
+    (dict(points_dtype=7), "points_dtype"),
+    (dict(points=0), "points is NULL"),
+    (dict(h=-1.0), "h must be"),
+    (dict(h=float("nan")), "h must be"),
+])
+def test_invalid_scalars_rejected(small_problem, case, expect):
+    raw, keep = _raw_problem(small_problem, **case)
+    st, msg = _factor_status(raw)
+    assert st == -1 and expect in msg
+
+
+def test_bad_offsets_rejected(small_problem):
+    leaf = np.array(small_problem.leaf_offsets, np.int64)
+    leaf[-1] += 1
+    raw, keep = _raw_problem(small_problem, leaf=leaf)
+    st, msg = _factor_status(raw)
+    assert st == -1 and "end at n" in msg
+    leaf = np.array(small_problem.leaf_offsets, np.int64)
+    leaf[2] = leaf[1]
+    raw, keep = _raw_problem(small_problem, leaf=leaf)
+    st, msg = _factor_status(raw)
+    assert st == -1 and "points" in msg
+
+
+def test_non_nested_skeleton_rejected(small_problem):
+    si = np.array(small_problem.skel_index, np.int32)
+    so = small_problem.skel_offsets
+    si[so[1]] = 10**6  # node 1 (internal) gets a point that is in no child skeleton
+    raw, keep = _raw_problem(small_problem, si=si)
+    st, msg = _factor_status(raw)
+    assert st == -1 and "not nested" in msg
+
+
+def test_leaf_skeleton_outside_leaf_rejected(small_problem):
+    si = np.array(small_problem.skel_index, np.int32)
+    so = small_problem.skel_offsets
+    leaf_node = 3
+    si[so[leaf_node]] = small_problem.n - 1  # belongs to the last leaf
+    raw, keep = _raw_problem(small_problem, si=si)
+    st, msg = _factor_status(raw)
+    assert st == -1 and "leaves the leaf" in msg
+
+
+def test_wrong_p_size_rejected(small_problem):
+    po = np.array(small_problem.p_offsets, np.int64)
+    po[2:] += 1
+    raw, keep = _raw_problem(small_problem, po=po)
+    st, msg = _factor_status(raw)
+    assert st == -1 and "P of node" in msg
+
+
+def test_bad_options_rejected(small_problem):
+    from paper_1602_01376_amd import binding
+    raw, keep = _raw_problem(small_problem)
+    opt = binding._Options()
+    binding.library().invaskit_default_options(C.byref(opt))
+    assert opt.precision == 0 and opt.fp64_top_levels == 4 and opt.refine_tol == 1e-10
+    opt.precision = 5
+    st, msg = _factor_status(raw, opt=opt)
+    assert st == -1 and "precision" in msg
+    binding.library().invaskit_default_options(C.byref(opt))
+    opt.max_refine_iters = 0
+    st, msg = _factor_status(raw, opt=opt)
+    assert st == -1
+
+
+def test_nonfinite_lambda_rejected(small_problem):
+    raw, keep = _raw_problem(small_problem)
+    st, msg = _factor_status(raw, lam=float("inf"))
+    assert st == -1 and "lambda" in msg
+
+
+def test_null_handle_calls_are_rejected():
+    from paper_1602_01376_amd import binding
+    lib = binding.library()
+    assert lib.invaskit_solve(None, None, 1, 1, None, 1, None) == -1
+    assert lib.invaskit_matvec(None, None, 1, 1, None, 1) == -1
+    assert lib.invaskit_refactor(None, 1.0) == -1
+    assert lib.invaskit_destroy(None) == 0
