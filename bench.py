@@ -1,0 +1,281 @@
+"""Benchmark: INV-ASKIT factor + solve of lambda*I + K~ on one MI355X.
+
+One step = refactor (every factorization phase: leaf blocks and LU, skeleton
+blocks, leaf solves, projections, skeleton sweep, deferred corrections,
+reduced systems and their LU) + solve of the right-hand sides, in the
+precision under test, to relative residual <= 1e-10 checked with the FP64
+hierarchical product.  The headline `value` is the mixed-precision path
+(FP32 factors, FP64 top-level reduced systems, FP64 refinement); the plain
+FP64 path is timed on the same inputs and reported beside it.
+
+Workload (default): N = 1,048,576 points in d = 8 from a 16-component unit
+Gaussian mixture, depth-12 ball tree with uneven leaves of 64..512 points,
+adaptive skeleton ranks 32..256 (ID tolerance 1e-5), h = 0.5, lambda = 1e-4,
+one right-hand side.  All inputs are seeded and synthetic and resident in
+HBM before the timed region.
+
+    python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--nrhs 1]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "factor+solve sec, FP32+refine vs FP64, N=1M d=8, rel residual ≤1e-10"
+HBM_PEAK_GBS = 8000.0
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+# ----------------------------------------------------------- work accounting
+def tree_sizes(pb):
+    L = pb.depth
+    nn = pb.n_nodes
+    s = np.diff(pb.skel_offsets).astype(np.int64)
+    size = np.zeros(nn, np.int64)
+    for c in range(nn):
+        a, b = pb.node_range(c)
+        size[c] = b - a
+    sib = lambda c: c + 1 if c & 1 else c - 1
+    w = np.zeros(nn, np.int64)
+    for c in range(1, nn):
+        w[c] = s[sib(c)]
+    return L, nn, s, size, w
+
+
+def algorithmic_work(pb, esize):
+    """Flops and bytes per factorization phase for the schedule the library
+    runs (exact sizes of this tree).  esize = bytes per factor element."""
+    L, nn, s, size, w = tree_sizes(pb)
+    first_leaf = (1 << L) - 1
+    leaves = range(first_leaf, nn)
+
+    def anc(node, k):
+        j = int(np.floor(np.log2(node + 1)))
+        return (1 << k) - 1 + ((node - ((1 << j) - 1)) >> (j - k))
+
+    z = np.zeros(nn, np.int64)
+    for c in range(first_leaf):
+        z[c] = s[2 * c + 1] + s[2 * c + 2]
+    W = {k: dict(flops=0.0, bytes=0.0, launches=0) for k in
+         ("leaf_lu", "skeleton_blocks", "leaf_solves", "leaf_projections", "skeleton_sweep",
+          "deferred_corrections", "reduced_systems")}
+    for lf in leaves:
+        m = size[lf]
+        W["leaf_lu"]["flops"] += 2.0 / 3.0 * m ** 3
+        W["leaf_lu"]["bytes"] += 2.0 * m * m * esize
+    W["leaf_lu"]["launches"] = 2
+    for k in range(L, 0, -1):
+        for lf in leaves:
+            m = size[lf]
+            c = anc(lf, k)
+            wk = w[c]
+            W["skeleton_blocks"]["bytes"] += m * wk * esize
+            W["leaf_solves"]["flops"] += 2.0 * m * m * wk
+            W["leaf_solves"]["bytes"] += (m * m + 2 * m * wk) * esize
+            W["leaf_projections"]["flops"] += 2.0 * s[lf] * m * wk
+            W["leaf_projections"]["bytes"] += (s[lf] * m + m * wk + s[lf] * wk) * esize
+            if k < L:
+                K = sum(w[anc(lf, j)] for j in range(k + 1, L + 1))
+                W["deferred_corrections"]["flops"] += 2.0 * m * K * wk
+                W["deferred_corrections"]["bytes"] += (m * K + 2 * m * wk + K * wk) * esize
+        W["skeleton_blocks"]["launches"] += 1
+        W["leaf_solves"]["launches"] += 1
+        W["leaf_projections"]["launches"] += 1
+        if k < L:
+            W["deferred_corrections"]["launches"] += 1
+        for j in range(L - 1, k - 1, -1):
+            for bn in range((1 << j) - 1, (2 << j) - 1):
+                wk = w[anc(bn, k)]
+                W["skeleton_sweep"]["flops"] += 2.0 * z[bn] ** 2 * wk + 2.0 * s[bn] * z[bn] * wk
+                W["skeleton_sweep"]["bytes"] += (z[bn] ** 2 + s[bn] * z[bn] + 3 * z[bn] * wk) * esize
+            W["skeleton_sweep"]["launches"] += 2
+        for a in range((1 << (k - 1)) - 1, (1 << k) - 1):
+            W["reduced_systems"]["flops"] += 2.0 / 3.0 * z[a] ** 3
+            W["reduced_systems"]["bytes"] += 3.0 * z[a] ** 2 * esize
+        W["reduced_systems"]["launches"] += 2
+    return W
+
+
+def paper_literal_flops(pb):
+    """Flops of Algorithms 1-2 as the oracle runs them (explicit full P,
+    W = Solve(child, K block) through the whole subtree)."""
+    L, nn, s, size, w = tree_sizes(pb)
+    first_leaf = (1 << L) - 1
+    z = np.zeros(nn, np.int64)
+    for c in range(first_leaf):
+        z[c] = s[2 * c + 1] + s[2 * c + 2]
+
+    def solve_cost(node, r):
+        if node >= first_leaf:
+            return 2.0 * size[node] ** 2 * r
+        l, rr = 2 * node + 1, 2 * node + 2
+        return (solve_cost(l, r) + solve_cost(rr, r) + 4.0 * (s[rr] * size[rr] + s[l] * size[l]) * r
+                + 2.0 * z[node] ** 2 * r)
+
+    f = sum(2.0 / 3.0 * size[lf] ** 3 for lf in range(first_leaf, nn))
+    for a in range(first_leaf):
+        l, r = 2 * a + 1, 2 * a + 2
+        f += solve_cost(l, s[r]) + solve_cost(r, s[l])
+        f += 2.0 * (s[r] * size[r] * s[l] + s[l] * size[l] * s[r]) + 2.0 / 3.0 * z[a] ** 3
+        if a > 0:
+            f += 2.0 * s[a] * (s[l] * size[l] + s[r] * size[r])
+    return f + solve_cost(0, 1)
+
+
+# --------------------------------------------------------------- CPU baseline
+def cpu_baseline(full_pb, n_sample=65536, depth_sample=8):
+    import oracle
+    from paper_1602_01376_amd.setup import make_problem, rhs_for
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([t.get("num_threads", 1) for t in threadpool_info()] or [os.cpu_count() or 1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    pb = make_problem("susy", n=n_sample, depth=depth_sample)
+    b = rhs_for(pb, nrhs=1)
+    t0 = time.perf_counter()
+    F = oracle.factorize(pb, pb.lam)
+    oracle.solve(F, b)
+    t = time.perf_counter() - t0
+    ratio = paper_literal_flops(full_pb) / paper_literal_flops(pb)
+    return {"value": t * ratio, "unit": "s", "cores": int(cores), "kind": "oracle",
+            "sample": (f"FP64 oracle factor+solve (Algorithms 1-2, NumPy/SciPy LAPACK) on the same "
+                       f"generator at N={n_sample}, depth {depth_sample}: {t:.2f} s, scaled by the "
+                       f"paper-literal flop ratio {ratio:.1f} of the full workload")}
+
+
+# ----------------------------------------------------------------------- main
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--nrhs", type=int, default=1)
+    ap.add_argument("--n", type=int, default=None, help="scale the workload down (testing)")
+    ap.add_argument("--depth", type=int, default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", choices=["mixed", "fp64", "both"], default="both")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: the multi-GPU sharding of the tree is a design "
+              "note, not part of this build (use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1602_01376_amd import binding
+    from paper_1602_01376_amd.setup import make_problem, rhs_for
+
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    pb = make_problem("susy", n=args.n, depth=args.depth)
+    log(f"setup {time.perf_counter() - t0:.1f} s: N={pb.n} d={pb.d} L={pb.depth} "
+        f"ranks {np.diff(pb.skel_offsets)[1:].min()}..{np.diff(pb.skel_offsets)[1:].max()}")
+    X = torch.from_numpy(pb.X).cuda()
+    P = torch.from_numpy(pb.p_values).cuda()
+    b = torch.from_numpy(rhs_for(pb, nrhs=args.nrhs)).cuda()
+    lam = pb.lam
+
+    results = {}
+    modes = ["mixed", "fp64"] if args.only == "both" else [args.only]
+    for mode in modes:
+        fac = binding.Factorization(pb, lam, precision=mode, points=X, p_values=P)
+        log(f"{mode}: device bytes {fac.device_bytes() / 2**30:.2f} GiB")
+        for _ in range(args.warmup):
+            fac.refactor(lam)
+            fac.solve(b, return_info=True, check=False)
+        phases = {}
+        tf = ts = 0.0
+        info = None
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        for _ in range(args.steps):
+            a = time.perf_counter()
+            fac.refactor(lam)       # synchronizes at its end (pivot status)
+            bpt = time.perf_counter()
+            x, info, st = fac.solve(b, return_info=True, check=False)
+            torch.cuda.synchronize()
+            c = time.perf_counter()
+            tf += bpt - a
+            ts += c - bpt
+            for k, v in fac.phase_times().items():
+                phases[k] = phases.get(k, 0.0) + v
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t_start) / args.steps
+        results[mode] = dict(
+            seconds=wall, factor_s=tf / args.steps, solve_s=ts / args.steps,
+            final_rel_residual=info["final_rel_residual"],
+            unrefined_rel_residual=info["unrefined_rel_residual"],
+            iterations=info["iterations"], converged=bool(info["converged"] or mode == "fp64"),
+            status=st, phase_ms={k: v / args.steps for k, v in phases.items()},
+            device_gib=fac.device_bytes() / 2**30)
+        log(mode, json.dumps(results[mode]))
+        fac.close()
+        del fac
+        torch.cuda.empty_cache()
+
+    head = results.get("mixed") or results["fp64"]
+    esize = 4 if "mixed" in results else 8
+    dtype = "f32" if "mixed" in results else "f64"
+    work = algorithmic_work(pb, esize)
+    # dominant kernel: the phase with the largest measured time
+    ph = head["phase_ms"]
+    cand = {k: ph.get(k, 0.0) for k in work}
+    dom = max(cand, key=cand.get)
+    wk = work[dom]
+    per_launch_ms = ph[dom] / max(wk["launches"], 1)
+    if wk["flops"] > 0 and dom != "skeleton_blocks":
+        achieved = wk["flops"] / wk["launches"] / (per_launch_ms * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[dtype],
+                "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS[dtype], "traffic": None,
+                "kernel": dom, "launches": wk["launches"], "avg_launch_ms": per_launch_ms}
+    else:
+        achieved = wk["bytes"] / wk["launches"] / (per_launch_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dom,
+                "launches": wk["launches"], "avg_launch_ms": per_launch_ms}
+    out = {
+        "metric": METRIC,
+        "value": head["seconds"],
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["seconds"] * 1e3,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if "mixed" in results else "f64",
+        "data": "synthetic",
+        "config": {"workload": (f"gaussian-mixture N={pb.n} d={pb.d} (16 unit Gaussians), "
+                                f"ball tree depth {pb.depth}, leaves 64..512, adaptive ranks "
+                                f"32..256 tau=1e-5, h={pb.h}, lambda={lam}"),
+                   "nrhs": args.nrhs, "precision": "mixed" if "mixed" in results else "fp64"},
+        "roofline": roof,
+        "paths": results,
+        "work_tflop": {k: v["flops"] / 1e12 for k, v in work.items()},
+    }
+    if "mixed" in results and "fp64" in results:
+        out["speedup_vs_fp64"] = results["fp64"]["seconds"] / results["mixed"]["seconds"]
+    if not args.no_cpu_baseline:
+        t0 = time.perf_counter()
+        out["cpu_baseline"] = cpu_baseline(pb)
+        log(f"cpu baseline {time.perf_counter() - t0:.1f} s")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
