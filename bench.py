@@ -84,28 +84,35 @@ def algorithmic_work(pb, esize):
             wk = w[c]
             W["skeleton_blocks"]["bytes"] += m * wk * esize
             W["leaf_solves"]["flops"] += 2.0 * m * m * wk
-            W["leaf_solves"]["bytes"] += (m * m + 2 * m * wk) * esize
+            W["leaf_solves"]["bytes"] += 2 * m * wk * esize
             W["leaf_projections"]["flops"] += 2.0 * s[lf] * m * wk
             W["leaf_projections"]["bytes"] += (s[lf] * m + m * wk + s[lf] * wk) * esize
             if k < L:
                 K = sum(w[anc(lf, j)] for j in range(k + 1, L + 1))
                 W["deferred_corrections"]["flops"] += 2.0 * m * K * wk
                 W["deferred_corrections"]["bytes"] += (m * K + 2 * m * wk + K * wk) * esize
-        W["skeleton_blocks"]["launches"] += 1
-        W["leaf_solves"]["launches"] += 1
-        W["leaf_projections"]["launches"] += 1
         if k < L:
             W["deferred_corrections"]["launches"] += 1
         for j in range(L - 1, k - 1, -1):
             for bn in range((1 << j) - 1, (2 << j) - 1):
                 wk = w[anc(bn, k)]
                 W["skeleton_sweep"]["flops"] += 2.0 * z[bn] ** 2 * wk + 2.0 * s[bn] * z[bn] * wk
-                W["skeleton_sweep"]["bytes"] += (z[bn] ** 2 + s[bn] * z[bn] + 3 * z[bn] * wk) * esize
-            W["skeleton_sweep"]["launches"] += 2
+                W["skeleton_sweep"]["bytes"] += (s[bn] * z[bn] + 3 * z[bn] * wk) * esize
         for a in range((1 << (k - 1)) - 1, (1 << k) - 1):
             W["reduced_systems"]["flops"] += 2.0 / 3.0 * z[a] ** 3
             W["reduced_systems"]["bytes"] += 3.0 * z[a] ** 2 * esize
-        W["reduced_systems"]["launches"] += 2
+    # one launch each over every level's columns; the sweep and the reduced
+    # systems run as one wavefront step (two launches) per level
+    for key in ("skeleton_blocks", "leaf_solves", "leaf_projections"):
+        W[key]["launches"] = 1
+    # the reduced-system factor is read once per sweep step (all factor levels)
+    for j in range(1, L):
+        for bn in range((1 << j) - 1, (2 << j) - 1):
+            W["skeleton_sweep"]["bytes"] += z[bn] ** 2 * esize
+    W["skeleton_sweep"]["launches"] = 2 * max(L - 1, 0)
+    W["reduced_systems"]["launches"] = 2 * L
+    for lf in leaves:  # the leaf LU is read once by the all-level leaf solve
+        W["leaf_solves"]["bytes"] += size[lf] ** 2 * esize
     return W
 
 

@@ -105,10 +105,11 @@ template <typename T>
 hipError_t launch_gemm(const GemmProb* probs, const GemmSeg* segs, const Tile3* tiles,
                        int ntiles, hipStream_t s);
 
+// kind: 0 leaf panels of the factorization, 1 reduced systems, 2 solve phase
 template <typename TZ, typename TV>
-hipError_t launch_getrs(const TrsmProb* probs, const Tile2* tiles, int ntiles, int nmax,
+hipError_t launch_getrs(const TrsmProb* probs, const Tile2* tiles, int ntiles, int nmax, int kind,
                         hipStream_t s);
-int getrs_cols_per_tile();
+int getrs_cols_per_tile(bool tz64);
 
 template <typename T>
 hipError_t launch_getrf(const LuProb* probs, int count, int nmax, hipStream_t s);

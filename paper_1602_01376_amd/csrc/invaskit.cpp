@@ -91,6 +91,7 @@ struct TrsmL {
   size_t probs = 0, tiles = 0;
   int ntiles = 0, nmax = 0;
   int tz64 = 1, tv64 = 1;
+  int kind = 0;
 };
 struct LuL {
   size_t probs = 0;
@@ -105,15 +106,20 @@ struct ZformL {
   int count = 0, tz64 = 1, tv64 = 1;
 };
 
-struct LevelPlan {
-  EvalL panels;
-  TrsmL leaf_trsm;
-  GemmL leaf_proj;
-  std::vector<TrsmL> zsolve;  // sublevels L-1 .. k
+// The factorization schedule: leaf-level passes over every tree level at
+// once, then one wavefront step per level for the reduced systems and the
+// skeleton sweep, then the deferred corrections.
+struct FactorPlan {
+  EvalL leaf_eval;
+  LuL leaf_lu;
+  EvalL panels;      // skeleton blocks of every level
+  TrsmL leaf_trsm;   // leaf solves of every level's panel columns
+  GemmL leaf_proj;   // leaf projections of every level's panel columns
+  std::vector<ZformL> zform;   // index j: reduced systems of level j
+  std::vector<LuL> zlu;
+  std::vector<TrsmL> zsolve;   // index j >= 1: sweep step at level j
   std::vector<GemmL> pgemm;
-  GemmL deferred;
-  ZformL zform;
-  LuL zlu;
+  std::vector<GemmL> deferred; // index k = 1 .. L-1
 };
 
 struct SolvePlan {
@@ -175,14 +181,13 @@ struct invaskit_handle_s {
   std::vector<int> S;
   std::vector<std::vector<int>> colk;  // [leaf][level]
   std::vector<int> zis64;              // per level
-  std::vector<std::vector<int64_t>> fp_off, fy_off;
-  int64_t fsweep_elems = 0;
+  std::vector<std::vector<int>> colp;  // [node][k]: first column of factor level k
+  std::vector<int> Ssw;                // sweep columns of a node (sum of its w over k)
+  std::vector<int64_t> psw_off, ysw_off;
   // device buffers
-  DevBuf skel_d, P32, leafLU, leafPerm, leafInfo, slab, Z64, ZT, zperm, zinfo, fsweep, ftables;
+  DevBuf skel_d, P32, leafLU, leafPerm, leafInfo, slab, Z64, ZT, zperm, zinfo, psw, ysw, ftables;
   // schedule
-  EvalL leaf_eval;
-  LuL leaf_lu;
-  std::vector<LevelPlan> levels;  // index k = 1..L
+  FactorPlan fp;
   std::map<int, std::unique_ptr<SolvePlan>> solve_plans;
   std::map<int, std::unique_ptr<MatvecPlan>> mv_plans;
   double phase_ms[8] = {0};
@@ -218,7 +223,7 @@ struct invaskit_handle_s {
     solve_plans.clear();
     mv_plans.clear();
     for (DevBuf* b : {&skel_d, &P32, &leafLU, &leafPerm, &leafInfo, &slab, &Z64, &ZT, &zperm,
-                      &zinfo, &fsweep, &ftables})
+                      &zinfo, &psw, &ysw, &ftables})
       b->release();
     if (have_events)
       for (auto& e : ev) hipEventDestroy(e);
@@ -403,7 +408,6 @@ struct GemmBuilder {
 
 struct TrsmBuilder {
   std::vector<TrsmProb> probs;
-  std::vector<Tile2> tiles;
   int nmax = 0;
   void add(const void* lu, const int32_t* perm, int n, int nrhs, const void* in0, int64_t ld0,
            int split, const void* in1, int64_t ld1, void* out, int64_t ldo) {
@@ -420,11 +424,13 @@ struct TrsmBuilder {
     p.out = out;
     p.ldout = ldo;
     probs.push_back(p);
-    const int rt = getrs_cols_per_tile();
-    for (int tn = 0; tn < (nrhs + rt - 1) / rt; ++tn) tiles.push_back({(int)probs.size() - 1, tn});
     nmax = std::max(nmax, n);
   }
-  TrsmL emit(Arena& ar, int tz64, int tv64) {
+  TrsmL emit(Arena& ar, int tz64, int tv64, int kind) {
+    std::vector<Tile2> tiles;
+    const int rt = getrs_cols_per_tile(tz64 != 0);
+    for (size_t i = 0; i < probs.size(); ++i)
+      for (int tn = 0; tn < (probs[i].nrhs + rt - 1) / rt; ++tn) tiles.push_back({(int)i, tn});
     TrsmL l;
     l.probs = ar.add(probs);
     l.tiles = ar.add(tiles);
@@ -432,6 +438,7 @@ struct TrsmBuilder {
     l.nmax = nmax;
     l.tz64 = tz64;
     l.tv64 = tv64;
+    l.kind = kind;
     return l;
   }
 };
@@ -466,7 +473,21 @@ int plan_factor(H* h) {
   for (int c = 0; c < nn; ++c)
     if (!h->is_leaf(c)) h->z[c] = h->s[2 * c + 1] + h->s[2 * c + 2];
 
-  // leaf LU and leaf-major W storage
+  // Sweep columns of every node: factor levels k = level(c) .. 1, each
+  // w_{anc_k(c)} wide, in that order (a leaf's are its W storage columns).
+  h->colp.assign(nn, std::vector<int>());
+  h->Ssw.assign(nn, 0);
+  for (int c = 1; c < nn; ++c) {
+    const int lev = h->level(c);
+    h->colp[c].assign(lev + 1, 0);
+    int run = 0;
+    for (int k = lev; k >= 1; --k) {
+      h->colp[c][k] = run;
+      run += h->w[h->anc(c, k)];
+    }
+    h->Ssw[c] = run;
+  }
+  // leaf LU and leaf-major W storage (m x Ssw[leaf], column-major)
   h->lu_off.assign(h->nleaves + 1, 0);
   h->slab_off.assign(h->nleaves + 1, 0);
   h->S.assign(h->nleaves, 0);
@@ -475,13 +496,9 @@ int plan_factor(H* h) {
     const int lf = h->leaf_node(j);
     const int64_t m = h->nb[lf] - h->na[lf];
     h->lu_off[j + 1] = h->lu_off[j] + m * m;
-    int run = 0;
-    for (int k = L; k >= 1; --k) {
-      h->colk[j][k] = run;
-      run += h->w[h->anc(lf, k)];
-    }
-    h->S[j] = run;
-    h->slab_off[j + 1] = h->slab_off[j] + m * run;
+    for (int k = L; k >= 1; --k) h->colk[j][k] = h->colp[lf][k];
+    h->S[j] = L > 0 ? h->Ssw[lf] : 0;
+    h->slab_off[j + 1] = h->slab_off[j] + m * h->S[j];
   }
   // reduced systems
   h->zis64.assign(L + 1, 1);
@@ -490,7 +507,7 @@ int plan_factor(H* h) {
   h->z_off.assign(nn, 0);
   h->zperm_off.assign(nn + 1, 0);
   int64_t z64n = 0, zTn = 0, zpn = 0;
-  int ninternal = (1 << L) - 1;
+  const int ninternal = (1 << L) - 1;
   for (int c = 0; c < ninternal; ++c) {
     const int64_t zz = (int64_t)h->z[c] * h->z[c];
     if (h->zis64[h->level(c)]) {
@@ -503,22 +520,18 @@ int plan_factor(H* h) {
     h->zperm_off[c] = zpn;
     zpn += h->z[c];
   }
-  // skeleton sweep buffers of each factor level
-  h->fp_off.assign(L + 1, std::vector<int64_t>(nn, 0));
-  h->fy_off.assign(L + 1, std::vector<int64_t>(nn, 0));
-  h->fsweep_elems = 0;
-  for (int k = L; k >= 1; --k) {
-    int64_t off = 0;
-    for (int c = (1 << k) - 1; c < nn; ++c) {
-      const int wk = h->w[h->anc(c, k)];
-      h->fp_off[k][c] = off;
-      off += (int64_t)h->s[c] * wk;
-      if (!h->is_leaf(c)) {
-        h->fy_off[k][c] = off;
-        off += (int64_t)h->z[c] * wk;
-      }
+  // skeleton projections (every non-root node) and sweep solutions (internal
+  // nodes below the root) for all factor levels at once
+  h->psw_off.assign(nn, 0);
+  h->ysw_off.assign(nn, 0);
+  int64_t pn = 0, yn = 0;
+  for (int c = 1; c < nn; ++c) {
+    h->psw_off[c] = pn;
+    pn += (int64_t)h->s[c] * h->Ssw[c];
+    if (!h->is_leaf(c)) {
+      h->ysw_off[c] = yn;
+      yn += (int64_t)h->z[c] * h->Ssw[c];
     }
-    h->fsweep_elems = std::max(h->fsweep_elems, off);
   }
 
   // allocations
@@ -531,7 +544,8 @@ int plan_factor(H* h) {
   if ((rc = dev_alloc(h, h->ZT, zTn * es))) return rc;
   if ((rc = dev_alloc(h, h->zperm, sizeof(int32_t) * std::max<int64_t>(zpn, 1)))) return rc;
   if ((rc = dev_alloc(h, h->zinfo, sizeof(int32_t) * std::max(ninternal, 1)))) return rc;
-  if ((rc = dev_alloc(h, h->fsweep, h->fsweep_elems * es))) return rc;
+  if ((rc = dev_alloc(h, h->psw, pn * es))) return rc;
+  if ((rc = dev_alloc(h, h->ysw, yn * es))) return rc;
   if ((rc = dev_alloc(h, h->skel_d, sizeof(int32_t) * std::max<size_t>(h->skel_idx.size(), 1))))
     return rc;
   if (!h->skel_idx.empty())
@@ -544,15 +558,23 @@ int plan_factor(H* h) {
 
   // ---- tables
   Arena ar;
+  FactorPlan& fp = h->fp;
+  fp = FactorPlan();
   const int T64 = (h->prec == INVASKIT_PREC_FP64) ? 1 : 0;
   const int32_t* skd = static_cast<const int32_t*>(h->skel_d.p);
   const int32_t* lperm = static_cast<const int32_t*>(h->leafPerm.p);
   int32_t* zpm = static_cast<int32_t*>(h->zperm.p);
-  // F1: leaf blocks and their LU
+  void* PS = h->psw.p;
+  void* YS = h->ysw.p;
+  void* Pt = const_cast<void*>(h->Pt());
+  // leaf blocks and their LU; skeleton blocks, leaf solves and leaf
+  // projections of every level
   {
-    std::vector<EvalBlock> blocks;
-    std::vector<Tile3> tiles;
+    std::vector<EvalBlock> lblocks, pblocks;
+    std::vector<Tile3> ltiles, ptiles;
     std::vector<LuProb> lus;
+    TrsmBuilder tb;
+    GemmBuilder proj;
     int nmax = 0;
     for (int j = 0; j < h->nleaves; ++j) {
       const int lf = h->leaf_node(j);
@@ -566,10 +588,10 @@ int plan_factor(H* h) {
       b.rows = m;
       b.ncols = m;
       b.diag = 1;
-      blocks.push_back(b);
+      lblocks.push_back(b);
       for (int tn = 0; tn < (m + kEvalTile - 1) / kEvalTile; ++tn)
         for (int tm = 0; tm < (m + kEvalTile - 1) / kEvalTile; ++tm)
-          tiles.push_back({(int)blocks.size() - 1, tm, tn});
+          ltiles.push_back({(int)lblocks.size() - 1, tm, tn});
       LuProb p{};
       p.a = b.out;
       p.perm = static_cast<int32_t*>(h->leafPerm.p) + h->na[lf];
@@ -577,93 +599,59 @@ int plan_factor(H* h) {
       p.n = m;
       lus.push_back(p);
       nmax = std::max(nmax, m);
+      if (L == 0) continue;
+      void* slab = offv(h->slab.p, h->slab_off[j], es);
+      for (int k = L; k >= 1; --k) {
+        const int c = h->anc(lf, k);
+        const int wk = h->w[c];
+        EvalBlock e{};
+        e.out = offv(slab, (int64_t)h->colk[j][k] * m, es);
+        e.ld = m;
+        e.row0 = h->na[lf];
+        e.cols = skd + h->skel_off[h->sib(c)];
+        e.rows = m;
+        e.ncols = wk;
+        e.diag = 0;
+        pblocks.push_back(e);
+        for (int tn = 0; tn < (wk + kEvalTile - 1) / kEvalTile; ++tn)
+          for (int tm = 0; tm < (m + kEvalTile - 1) / kEvalTile; ++tm)
+            ptiles.push_back({(int)pblocks.size() - 1, tm, tn});
+      }
+      tb.add(offv(h->leafLU.p, h->lu_off[j], es), lperm + h->na[lf], m, h->S[j], slab, m, m, slab,
+             m, slab, m);
+      proj.begin(offv(PS, h->psw_off[lf], es), h->s[lf], h->s[lf], h->S[j], 1.0, 0.0);
+      proj.seg(offv(Pt, h->p_off[lf], es), m, true, slab, m, m);
     }
-    h->leaf_eval.blocks = ar.add(blocks);
-    h->leaf_eval.tiles = ar.add(tiles);
-    h->leaf_eval.ntiles = (int)tiles.size();
-    h->leaf_lu.probs = ar.add(lus);
-    h->leaf_lu.count = (int)lus.size();
-    h->leaf_lu.nmax = nmax;
-    h->leaf_lu.t64 = T64;
+    fp.leaf_eval.blocks = ar.add(lblocks);
+    fp.leaf_eval.tiles = ar.add(ltiles);
+    fp.leaf_eval.ntiles = (int)ltiles.size();
+    fp.leaf_lu.probs = ar.add(lus);
+    fp.leaf_lu.count = (int)lus.size();
+    fp.leaf_lu.nmax = nmax;
+    fp.leaf_lu.t64 = T64;
+    fp.panels.blocks = ar.add(pblocks);
+    fp.panels.tiles = ar.add(ptiles);
+    fp.panels.ntiles = (int)ptiles.size();
+    fp.leaf_trsm = tb.emit(ar, T64, T64, 0);
+    fp.leaf_proj = proj.emit(ar);
   }
-  h->levels.assign(L + 1, LevelPlan());
-  for (int k = L; k >= 1; --k) {
-    LevelPlan& lp = h->levels[k];
-    void* fs = h->fsweep.p;
-    // F2a panels, F2b leaf solves, F2c leaf projections, F2e deferred corrections
-    std::vector<EvalBlock> blocks;
-    std::vector<Tile3> etiles;
-    TrsmBuilder tb;
-    GemmBuilder proj, defer;
-    for (int j = 0; j < h->nleaves; ++j) {
-      const int lf = h->leaf_node(j);
-      const int m = (int)(h->nb[lf] - h->na[lf]);
-      const int c = h->anc(lf, k);
-      const int wk = h->w[c];
-      void* seg = offv(h->slab.p, h->slab_off[j] + (int64_t)h->colk[j][k] * m, es);
-      EvalBlock b{};
-      b.out = seg;
-      b.ld = m;
-      b.row0 = h->na[lf];
-      b.cols = skd + h->skel_off[h->sib(c)];
-      b.rows = m;
-      b.ncols = wk;
-      b.diag = 0;
-      blocks.push_back(b);
-      for (int tn = 0; tn < (wk + kEvalTile - 1) / kEvalTile; ++tn)
-        for (int tm = 0; tm < (m + kEvalTile - 1) / kEvalTile; ++tm)
-          etiles.push_back({(int)blocks.size() - 1, tm, tn});
-      tb.add(offv(h->leafLU.p, h->lu_off[j], es), lperm + h->na[lf], m, wk, seg, m, m, seg, m,
-             seg, m);
-      proj.begin(offv(fs, h->fp_off[k][lf], es), h->s[lf], h->s[lf], wk, 1.0, 0.0);
-      proj.seg(offv(const_cast<void*>(h->Pt()), h->p_off[lf], es), m, true, seg, m, m);
-      if (k < L) {
-        defer.begin(seg, m, m, wk, -1.0, 1.0);
-        for (int jl = L; jl > k; --jl) {
-          const int cj = h->anc(lf, jl);
-          const int par = h->anc(lf, jl - 1);
-          const int yoff = (cj & 1) ? 0 : h->s[cj];  // left child takes the r~ rows
-          defer.seg(offv(h->slab.p, h->slab_off[j] + (int64_t)h->colk[j][jl] * m, es), m, false,
-                    offv(fs, h->fy_off[k][par] + yoff, es), h->z[par], h->w[cj]);
-        }
-      }
-    }
-    lp.panels.blocks = ar.add(blocks);
-    lp.panels.tiles = ar.add(etiles);
-    lp.panels.ntiles = (int)etiles.size();
-    lp.leaf_trsm = tb.emit(ar, T64, T64);
-    lp.leaf_proj = proj.emit(ar);
-    if (k < L) lp.deferred = defer.emit(ar);
-    // F2d skeleton sweep over sublevels L-1 .. k
-    for (int jl = L - 1; jl >= k; --jl) {
-      TrsmBuilder zs;
-      GemmBuilder pg;
-      for (int bnode = (1 << jl) - 1; bnode < (2 << jl) - 1; ++bnode) {
-        const int l = 2 * bnode + 1, r = 2 * bnode + 2;
-        const int wk = h->w[h->anc(bnode, k)];
-        void* y = offv(fs, h->fy_off[k][bnode], es);
-        zs.add(h->Z(bnode), zpm + h->zperm_off[bnode], h->z[bnode], wk,
-               offv(fs, h->fp_off[k][r], es), h->s[r], h->s[r], offv(fs, h->fp_off[k][l], es),
-               h->s[l], y, h->z[bnode]);
-        pg.begin(offv(fs, h->fp_off[k][bnode], es), h->s[bnode], h->s[bnode], wk, 1.0, 0.0);
-        const void* Pb = offv(const_cast<void*>(h->Pt()), h->p_off[bnode], es);
-        pg.seg(Pb, h->z[bnode], true, offv(y, h->s[r], es), h->z[bnode], h->s[l]);
-        pg.seg(offv(const_cast<void*>(Pb), h->s[l], es), h->z[bnode], true, y, h->z[bnode],
-               h->s[r]);
-      }
-      lp.zsolve.push_back(zs.emit(ar, h->zis64[jl], T64));
-      lp.pgemm.push_back(pg.emit(ar));
-    }
-    // F2f/F2g reduced systems of the level k-1 parents
+  // wavefront over levels j = L-1 .. 0
+  fp.zform.assign(std::max(L, 1), ZformL());
+  fp.zlu.assign(std::max(L, 1), LuL());
+  fp.zsolve.assign(std::max(L, 1), TrsmL());
+  fp.pgemm.assign(std::max(L, 1), GemmL());
+  for (int jl = L - 1; jl >= 0; --jl) {
     std::vector<ZformProb> zf;
     std::vector<LuProb> zl;
+    TrsmBuilder zs;
+    GemmBuilder pg;
     int nmax = 0;
-    for (int a = (1 << (k - 1)) - 1; a < (1 << k) - 1; ++a) {
+    for (int a = (1 << jl) - 1; a < (2 << jl) - 1; ++a) {
       const int l = 2 * a + 1, r = 2 * a + 2;
       ZformProb p{};
       p.Z = h->Zm(a);
-      p.pr = offv(fs, h->fp_off[k][r], es);
-      p.pl = offv(fs, h->fp_off[k][l], es);
+      p.pr = offv(PS, h->psw_off[r], es);  // first columns: factor level jl+1
+      p.pl = offv(PS, h->psw_off[l], es);
       p.sr = h->s[r];
       p.sl = h->s[l];
       zf.push_back(p);
@@ -674,15 +662,53 @@ int plan_factor(H* h) {
       q.n = h->z[a];
       zl.push_back(q);
       nmax = std::max(nmax, h->z[a]);
+      if (jl >= 1) {
+        void* y = offv(YS, h->ysw_off[a], es);
+        zs.add(h->Z(a), zpm + h->zperm_off[a], h->z[a], h->Ssw[a],
+               offv(PS, h->psw_off[r] + (int64_t)h->colp[r][jl] * h->s[r], es), h->s[r], h->s[r],
+               offv(PS, h->psw_off[l] + (int64_t)h->colp[l][jl] * h->s[l], es), h->s[l], y,
+               h->z[a]);
+        pg.begin(offv(PS, h->psw_off[a], es), h->s[a], h->s[a], h->Ssw[a], 1.0, 0.0);
+        const void* Pa = offv(Pt, h->p_off[a], es);
+        pg.seg(Pa, h->z[a], true, offv(y, h->s[r], es), h->z[a], h->s[l]);
+        pg.seg(offv(const_cast<void*>(Pa), h->s[l], es), h->z[a], true, y, h->z[a], h->s[r]);
+      }
     }
-    lp.zform.probs = ar.add(zf);
-    lp.zform.count = (int)zf.size();
-    lp.zform.tz64 = h->zis64[k - 1];
-    lp.zform.tv64 = T64;
-    lp.zlu.probs = ar.add(zl);
-    lp.zlu.count = (int)zl.size();
-    lp.zlu.nmax = nmax;
-    lp.zlu.t64 = h->zis64[k - 1];
+    ZformL& zfl = fp.zform[jl];
+    zfl.probs = ar.add(zf);
+    zfl.count = (int)zf.size();
+    zfl.tz64 = h->zis64[jl];
+    zfl.tv64 = T64;
+    LuL& lul = fp.zlu[jl];
+    lul.probs = ar.add(zl);
+    lul.count = (int)zl.size();
+    lul.nmax = nmax;
+    lul.t64 = h->zis64[jl];
+    if (jl >= 1) {
+      fp.zsolve[jl] = zs.emit(ar, h->zis64[jl], T64, 1);
+      fp.pgemm[jl] = pg.emit(ar);
+    }
+  }
+  // deferred corrections, factor levels k = L-1 .. 1
+  fp.deferred.assign(std::max(L, 1), GemmL());
+  for (int k = L - 1; k >= 1; --k) {
+    GemmBuilder defer;
+    for (int j = 0; j < h->nleaves; ++j) {
+      const int lf = h->leaf_node(j);
+      const int m = (int)(h->nb[lf] - h->na[lf]);
+      void* slab = offv(h->slab.p, h->slab_off[j], es);
+      defer.begin(offv(slab, (int64_t)h->colk[j][k] * m, es), m, m, h->w[h->anc(lf, k)], -1.0,
+                  1.0);
+      for (int jl = L; jl > k; --jl) {
+        const int cj = h->anc(lf, jl);
+        const int par = h->anc(lf, jl - 1);
+        const int yoff = (cj & 1) ? 0 : h->s[cj];  // a left child takes the r~ rows
+        defer.seg(offv(slab, (int64_t)h->colk[j][jl] * m, es), m, false,
+                  offv(YS, h->ysw_off[par] + (int64_t)h->colp[par][k] * h->z[par] + yoff, es),
+                  h->z[par], h->w[cj]);
+      }
+    }
+    fp.deferred[k] = defer.emit(ar);
   }
   if ((rc = dev_alloc(h, h->ftables, ar.host.size()))) return rc;
   HIP_TRY(h, hipMemcpy(h->ftables.p, ar.host.data(), ar.host.size(), hipMemcpyHostToDevice));
@@ -703,9 +729,9 @@ hipError_t run_trsm(const DevBuf& tb, const TrsmL& l, hipStream_t s) {
   if (l.ntiles == 0) return hipSuccess;
   const TrsmProb* p = at<TrsmProb>(tb, l.probs);
   const Tile2* t = at<Tile2>(tb, l.tiles);
-  if (l.tz64 && l.tv64) return launch_getrs<double, double>(p, t, l.ntiles, l.nmax, s);
-  if (l.tz64) return launch_getrs<double, float>(p, t, l.ntiles, l.nmax, s);
-  return launch_getrs<float, float>(p, t, l.ntiles, l.nmax, s);
+  if (l.tz64 && l.tv64) return launch_getrs<double, double>(p, t, l.ntiles, l.nmax, l.kind, s);
+  if (l.tz64) return launch_getrs<double, float>(p, t, l.ntiles, l.nmax, l.kind, s);
+  return launch_getrs<float, float>(p, t, l.ntiles, l.nmax, l.kind, s);
 }
 
 hipError_t run_lu(const DevBuf& tb, const LuL& l, hipStream_t s) {
@@ -771,30 +797,32 @@ int run_factor(H* h) {
     }                                                                             \
   } while (0)
 
+  const FactorPlan& fp = h->fp;
   mark(-1);
   if (!f64 && h->P32.p && h->p_off[h->nn] > 0)
     STEP(launch_convert_f64_f32(h->P64, static_cast<float*>(h->P32.p), h->p_off[h->nn], s));
-  STEP(run_eval(h, tb, h->leaf_eval, h->lam, s));
-  STEP(run_lu(tb, h->leaf_lu, s));
+  STEP(run_eval(h, tb, fp.leaf_eval, h->lam, s));
+  STEP(run_lu(tb, fp.leaf_lu, s));
   mark(0);
-  for (int k = h->L; k >= 1; --k) {
-    const LevelPlan& lp = h->levels[k];
-    STEP(run_eval(h, tb, lp.panels, 0.0, s));
+  if (h->L > 0) {
+    STEP(run_eval(h, tb, fp.panels, 0.0, s));
     mark(1);
-    STEP(run_trsm(tb, lp.leaf_trsm, s));
+    STEP(run_trsm(tb, fp.leaf_trsm, s));
     mark(2);
-    STEP(run_gemm(tb, lp.leaf_proj, f64, s));
+    STEP(run_gemm(tb, fp.leaf_proj, f64, s));
     mark(3);
-    for (size_t q = 0; q < lp.zsolve.size(); ++q) {
-      STEP(run_trsm(tb, lp.zsolve[q], s));
-      STEP(run_gemm(tb, lp.pgemm[q], f64, s));
+    for (int j = h->L - 1; j >= 0; --j) {
+      STEP(run_zform(tb, fp.zform[j], s));
+      STEP(run_lu(tb, fp.zlu[j], s));
+      mark(6);
+      if (j >= 1) {
+        STEP(run_trsm(tb, fp.zsolve[j], s));
+        STEP(run_gemm(tb, fp.pgemm[j], f64, s));
+        mark(4);
+      }
     }
-    mark(4);
-    STEP(run_gemm(tb, lp.deferred, f64, s));
+    for (int k = h->L - 1; k >= 1; --k) STEP(run_gemm(tb, fp.deferred[k], f64, s));
     mark(5);
-    STEP(run_zform(tb, lp.zform, s));
-    STEP(run_lu(tb, lp.zlu, s));
-    mark(6);
   }
   STEP(hipStreamSynchronize(s));
   for (double& v : h->phase_ms) v = 0.0;
@@ -884,7 +912,7 @@ int build_solve_plan(H* h, int r, SolvePlan*& out) {
       }
     }
   }
-  sp->leaf_trsm = lt.emit(ar, T64, T64);
+  sp->leaf_trsm = lt.emit(ar, T64, T64, 2);
   sp->leaf_proj = lpj.emit(ar);
   for (int jl = L - 1; jl >= 0; --jl) {
     TrsmBuilder zs;
@@ -902,7 +930,7 @@ int build_solve_plan(H* h, int r, SolvePlan*& out) {
                h->s[rr]);
       }
     }
-    sp->zsolve.push_back(zs.emit(ar, h->zis64[jl], T64));
+    sp->zsolve.push_back(zs.emit(ar, h->zis64[jl], T64, 2));
     sp->pgemm.push_back(pg.emit(ar));
   }
   sp->final_ = fin.emit(ar);
@@ -1219,7 +1247,7 @@ int invaskit_device_bytes(invaskit_handle h, size_t* bytes) {
   if (!h || !bytes) return fail_h(h, INVASKIT_E_ARG, "handle and bytes are required");
   size_t t = 0;
   for (const DevBuf* b : {&h->skel_d, &h->P32, &h->leafLU, &h->leafPerm, &h->leafInfo, &h->slab,
-                          &h->Z64, &h->ZT, &h->zperm, &h->zinfo, &h->fsweep, &h->ftables})
+                          &h->Z64, &h->ZT, &h->zperm, &h->zinfo, &h->psw, &h->ysw, &h->ftables})
     t += b->bytes;
   for (auto& kv : h->solve_plans)
     for (const DevBuf* b : {&kv.second->tables, &kv.second->xbuf, &kv.second->sbuf,
@@ -1325,7 +1353,7 @@ int invaskit_getrs_batched(int32_t dtype, const void* a, const int64_t* a_offset
   }
   Arena ar;
   const int f = dtype == INVASKIT_F64 ? 1 : 0;
-  TrsmL l = tb.emit(ar, f, f);
+  TrsmL l = tb.emit(ar, f, f, 1);
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   DevBuf t;
   int rc = dev_alloc(nullptr, t, ar.host.size());

@@ -7,7 +7,8 @@
 //      column by column; the pivot is the first row of largest magnitude
 //      (LAPACK getrf semantics), found by a wavefront max-reduction
 //      followed by a cross-wave reduction through LDS;
-//   2. the panel's row interchanges are applied to the other columns;
+//   2. the panel's row interchanges, composed into one permutation of the
+//      touched rows, are applied to the other columns (independent loads);
 //   3. U12 = L11^-1 A12 (one thread per column) is written to global memory
 //      and kept in LDS;
 //   4. the trailing matrix is updated, A22 -= L21 U12, with 4 x 4 register
@@ -41,9 +42,12 @@ __global__ __launch_bounds__(256) void k_getrf(const LuProb* __restrict__ probs)
   T* Pn = reinterpret_cast<T*>(smem);           // panel, (n - j0) x NB, ld = n - j0
   T* Us = Pn + (size_t)n * NB;                    // U12, NB x n, row-major (ld n)
   int* Ps = reinterpret_cast<int*>(Us + (size_t)NB * n);  // permutation
+  int* Loc = Ps + n;  // composed interchanges of one panel
   __shared__ T red_v[4];
   __shared__ int red_i[4];
   __shared__ int s_piv[NB];
+  __shared__ int s_tl[2 * NB];
+  __shared__ int s_cnt;
   __shared__ int s_info;
 
   for (int i = tid; i < n; i += 256) Ps[i] = i;
@@ -134,18 +138,45 @@ __global__ __launch_bounds__(256) void k_getrf(const LuProb* __restrict__ probs)
       const int r = idx % mr, c = idx / mr;
       A[(int64_t)(j0 + c) * n + j0 + r] = Pn[r + c * mr];
     }
-    // row interchanges on the columns outside the panel
-    const int nout = n - jb;
-    for (int q = tid; q < nout; q += 256) {
-      const int c = (q < j0) ? q : q + jb;
-      T* col = A + (int64_t)c * n;
+    // row interchanges on the columns outside the panel: compose the panel's
+    // swaps into Loc (new row t takes old row Loc[t]) and move only the
+    // touched rows
+    for (int i = tid; i < mr; i += 256) Loc[i] = i;
+    __syncthreads();
+    if (tid == 0) {
       for (int jj = 0; jj < jb; ++jj) {
         const int p = s_piv[jj];
-        if (p != jj) {
-          const T a = col[j0 + jj];
-          col[j0 + jj] = col[j0 + p];
-          col[j0 + p] = a;
+        const int a = Loc[jj];
+        Loc[jj] = Loc[p];
+        Loc[p] = a;
+      }
+      int cnt = 0;
+      for (int jj = 0; jj < jb; ++jj) {
+        const int cand[2] = {jj, s_piv[jj]};
+        for (int q = 0; q < 2; ++q) {
+          const int t = cand[q];
+          if (Loc[t] == t) continue;
+          bool dup = false;
+          for (int u = 0; u < cnt; ++u) dup |= (s_tl[u] == t);
+          if (!dup) s_tl[cnt++] = t;
         }
+      }
+      s_cnt = cnt;
+    }
+    __syncthreads();
+    const int ncnt = s_cnt;
+    const int nout = n - jb;
+    if (ncnt > 0) {
+      for (int q = tid; q < nout; q += 256) {
+        const int c = (q < j0) ? q : q + jb;
+        T* col = A + (int64_t)c * n + j0;
+        T v[2 * NB];
+#pragma unroll
+        for (int u = 0; u < 2 * NB; ++u)
+          if (u < ncnt) v[u] = col[Loc[s_tl[u]]];
+#pragma unroll
+        for (int u = 0; u < 2 * NB; ++u)
+          if (u < ncnt) col[s_tl[u]] = v[u];
       }
     }
     __syncthreads();
@@ -224,7 +255,7 @@ __global__ __launch_bounds__(256) void k_getrf(const LuProb* __restrict__ probs)
 
 template <typename T, int NB>
 size_t getrf_smem(int nmax) {
-  return (size_t)2 * nmax * NB * sizeof(T) + (size_t)nmax * sizeof(int) + 16;
+  return (size_t)2 * nmax * NB * sizeof(T) + (size_t)2 * nmax * sizeof(int) + 16;
 }
 
 template <typename T, int NB>
