@@ -86,15 +86,17 @@ __global__ __launch_bounds__(256) void k_getrs(const TrsmProb* __restrict__ prob
   TZ* Ld = reinterpret_cast<TZ*>(smem);  // 64 x 64 diagonal block, column-major
   TZ* X = Ld + NBK * NBK;                // n x RT, row-major
 
-  for (int idx = tid; idx < n * RT; idx += 256) {
-    const int i = idx % n, c = idx / n;
-    TZ v = 0;
-    if (c < nc) {
-      const int src = pr.perm[i];
-      v = (src < pr.split) ? (TZ)in0[(int64_t)(c0 + c) * pr.ldin0 + src]
-                           : (TZ)in1[(int64_t)(c0 + c) * pr.ldin1 + (src - pr.split)];
-    }
-    X[i * RT + c] = v;
+  // gather the permuted right-hand sides: one thread per row, all RT column
+  // loads of a row in flight together
+  for (int i = tid; i < n; i += 256) {
+    const int src = pr.perm[i];
+    const TV* base = (src < pr.split) ? in0 + src : in1 + (src - pr.split);
+    const int64_t ld = (src < pr.split) ? pr.ldin0 : pr.ldin1;
+    TZ v[RT];
+#pragma unroll
+    for (int c = 0; c < RT; ++c) v[c] = (c < nc) ? (TZ)base[(int64_t)(c0 + c) * ld] : TZ(0);
+#pragma unroll
+    for (int c = 0; c < RT; ++c) X[i * RT + c] = v[c];
   }
 
   const int nblocks = (n + NBK - 1) / NBK;
@@ -105,6 +107,7 @@ __global__ __launch_bounds__(256) void k_getrs(const TrsmProb* __restrict__ prob
       const int jb = b * NBK;
       const int nb = min(NBK, n - jb);
       // stage the diagonal block
+#pragma unroll
       for (int idx = tid; idx < NBK * NBK; idx += 256) {
         const int r = idx % NBK, j = idx / NBK;
         Ld[idx] = (r < nb && j < nb) ? LU[(int64_t)(jb + j) * n + jb + r] : TZ(0);
@@ -180,9 +183,10 @@ __global__ __launch_bounds__(256) void k_getrs(const TrsmProb* __restrict__ prob
     }
   }
 
-  for (int idx = tid; idx < n * nc; idx += 256) {
-    const int i = idx % n, c = idx / n;
-    out[(int64_t)(c0 + c) * pr.ldout + i] = (TV)X[i * RT + c];
+  for (int i = tid; i < n; i += 256) {
+#pragma unroll
+    for (int c = 0; c < RT; ++c)
+      if (c < nc) out[(int64_t)(c0 + c) * pr.ldout + i] = (TV)X[i * RT + c];
   }
 }
 
