@@ -46,6 +46,7 @@ struct Tile2 {
 // and output may be the same buffer.
 struct TrsmProb {
   const void* lu;
+  const void* dinv;  // inverses of the 64 x 64 diagonal blocks (k_diag_inv layout)
   const int32_t* perm;
   int32_t n, nrhs;
   const void* in0;
@@ -55,6 +56,17 @@ struct TrsmProb {
   void* out;
   int64_t ldout;
 };
+
+// One 64 x 64 diagonal block of an LU factor (rows/columns jb .. jb+63):
+// out receives inv(L_bb) then inv(U_bb), each 64 x 64 column-major, zero
+// beyond the matrix order.
+struct DiagInvProb {
+  const void* lu;
+  void* out;
+  int32_t n, jb;
+};
+constexpr int kDiagBlock = 64;
+constexpr int kTrsmCols = 16;
 
 struct LuProb {
   void* a;
@@ -110,6 +122,8 @@ template <typename TZ, typename TV>
 hipError_t launch_getrs(const TrsmProb* probs, const Tile2* tiles, int ntiles, int nmax, int kind,
                         hipStream_t s);
 int getrs_cols_per_tile(bool tz64);
+template <typename TZ>
+hipError_t launch_diag_inv(const DiagInvProb* probs, int count, hipStream_t s);
 
 template <typename T>
 hipError_t launch_getrf(const LuProb* probs, int count, int nmax, hipStream_t s);

@@ -97,6 +97,10 @@ struct LuL {
   size_t probs = 0;
   int count = 0, nmax = 0, t64 = 1;
 };
+struct DinvL {
+  size_t probs = 0;
+  int count = 0, t64 = 1;
+};
 struct EvalL {
   size_t blocks = 0, tiles = 0;
   int ntiles = 0;
@@ -112,11 +116,13 @@ struct ZformL {
 struct FactorPlan {
   EvalL leaf_eval;
   LuL leaf_lu;
+  DinvL leaf_dinv;
   EvalL panels;      // skeleton blocks of every level
   TrsmL leaf_trsm;   // leaf solves of every level's panel columns
   GemmL leaf_proj;   // leaf projections of every level's panel columns
   std::vector<ZformL> zform;   // index j: reduced systems of level j
   std::vector<LuL> zlu;
+  std::vector<DinvL> zdinv;
   std::vector<TrsmL> zsolve;   // index j >= 1: sweep step at level j
   std::vector<GemmL> pgemm;
   std::vector<GemmL> deferred; // index k = 1 .. L-1
@@ -186,6 +192,8 @@ struct invaskit_handle_s {
   std::vector<int64_t> psw_off, ysw_off;
   // device buffers
   DevBuf skel_d, P32, leafLU, leafPerm, leafInfo, slab, Z64, ZT, zperm, zinfo, psw, ysw, ftables;
+  DevBuf dinvLeaf, dinvZ64, dinvZT;   // inverses of the 64 x 64 diagonal blocks
+  std::vector<int64_t> dleaf_off, dz_off;
   // schedule
   FactorPlan fp;
   std::map<int, std::unique_ptr<SolvePlan>> solve_plans;
@@ -218,12 +226,20 @@ struct invaskit_handle_s {
     return static_cast<unsigned char*>(b.p) + z_off[node] * (zis64[k] ? 8 : 4);
   }
   void* Zm(int node) { return const_cast<void*>(Z(node)); }
+  const void* DZ(int node) const {  // diagonal-block inverses of a reduced system
+    const int k = level(node);
+    const DevBuf& b = zis64[k] ? dinvZ64 : dinvZT;
+    return static_cast<unsigned char*>(b.p) + dz_off[node] * (zis64[k] ? 8 : 4);
+  }
+  const void* DL(int leaf) const {
+    return static_cast<unsigned char*>(dinvLeaf.p) + dleaf_off[leaf] * tsize();
+  }
 
   ~invaskit_handle_s() {
     solve_plans.clear();
     mv_plans.clear();
     for (DevBuf* b : {&skel_d, &P32, &leafLU, &leafPerm, &leafInfo, &slab, &Z64, &ZT, &zperm,
-                      &zinfo, &psw, &ysw, &ftables})
+                      &zinfo, &psw, &ysw, &ftables, &dinvLeaf, &dinvZ64, &dinvZT})
       b->release();
     if (have_events)
       for (auto& e : ev) hipEventDestroy(e);
@@ -409,10 +425,11 @@ struct GemmBuilder {
 struct TrsmBuilder {
   std::vector<TrsmProb> probs;
   int nmax = 0;
-  void add(const void* lu, const int32_t* perm, int n, int nrhs, const void* in0, int64_t ld0,
-           int split, const void* in1, int64_t ld1, void* out, int64_t ldo) {
+  void add(const void* lu, const void* dinv, const int32_t* perm, int n, int nrhs, const void* in0,
+           int64_t ld0, int split, const void* in1, int64_t ld1, void* out, int64_t ldo) {
     TrsmProb p{};
     p.lu = lu;
+    p.dinv = dinv;
     p.perm = perm;
     p.n = n;
     p.nrhs = nrhs;
@@ -520,6 +537,26 @@ int plan_factor(H* h) {
     h->zperm_off[c] = zpn;
     zpn += h->z[c];
   }
+  // inverses of the 64 x 64 diagonal blocks of every LU factor
+  auto nblk = [](int64_t m) { return (m + kDiagBlock - 1) / kDiagBlock; };
+  constexpr int64_t kDB2 = 2 * kDiagBlock * kDiagBlock;
+  h->dleaf_off.assign(h->nleaves + 1, 0);
+  for (int j = 0; j < h->nleaves; ++j) {
+    const int lf = h->leaf_node(j);
+    h->dleaf_off[j + 1] = h->dleaf_off[j] + nblk(h->nb[lf] - h->na[lf]) * kDB2;
+  }
+  h->dz_off.assign(nn, 0);
+  int64_t dz64 = 0, dzT = 0;
+  for (int c = 0; c < ninternal; ++c) {
+    const int64_t e = nblk(h->z[c]) * kDB2;
+    if (h->zis64[h->level(c)]) {
+      h->dz_off[c] = dz64;
+      dz64 += e;
+    } else {
+      h->dz_off[c] = dzT;
+      dzT += e;
+    }
+  }
   // skeleton projections (every non-root node) and sweep solutions (internal
   // nodes below the root) for all factor levels at once
   h->psw_off.assign(nn, 0);
@@ -544,6 +581,9 @@ int plan_factor(H* h) {
   if ((rc = dev_alloc(h, h->ZT, zTn * es))) return rc;
   if ((rc = dev_alloc(h, h->zperm, sizeof(int32_t) * std::max<int64_t>(zpn, 1)))) return rc;
   if ((rc = dev_alloc(h, h->zinfo, sizeof(int32_t) * std::max(ninternal, 1)))) return rc;
+  if ((rc = dev_alloc(h, h->dinvLeaf, h->dleaf_off[h->nleaves] * es))) return rc;
+  if ((rc = dev_alloc(h, h->dinvZ64, dz64 * 8))) return rc;
+  if ((rc = dev_alloc(h, h->dinvZT, dzT * es))) return rc;
   if ((rc = dev_alloc(h, h->psw, pn * es))) return rc;
   if ((rc = dev_alloc(h, h->ysw, yn * es))) return rc;
   if ((rc = dev_alloc(h, h->skel_d, sizeof(int32_t) * std::max<size_t>(h->skel_idx.size(), 1))))
@@ -573,6 +613,7 @@ int plan_factor(H* h) {
     std::vector<EvalBlock> lblocks, pblocks;
     std::vector<Tile3> ltiles, ptiles;
     std::vector<LuProb> lus;
+    std::vector<DiagInvProb> dis;
     TrsmBuilder tb;
     GemmBuilder proj;
     int nmax = 0;
@@ -599,6 +640,14 @@ int plan_factor(H* h) {
       p.n = m;
       lus.push_back(p);
       nmax = std::max(nmax, m);
+      for (int jb = 0; jb < m; jb += kDiagBlock) {
+        DiagInvProb d{};
+        d.lu = b.out;
+        d.out = offv(h->dinvLeaf.p, h->dleaf_off[j] + (jb / kDiagBlock) * kDB2, es);
+        d.n = m;
+        d.jb = jb;
+        dis.push_back(d);
+      }
       if (L == 0) continue;
       void* slab = offv(h->slab.p, h->slab_off[j], es);
       for (int k = L; k >= 1; --k) {
@@ -617,8 +666,8 @@ int plan_factor(H* h) {
           for (int tm = 0; tm < (m + kEvalTile - 1) / kEvalTile; ++tm)
             ptiles.push_back({(int)pblocks.size() - 1, tm, tn});
       }
-      tb.add(offv(h->leafLU.p, h->lu_off[j], es), lperm + h->na[lf], m, h->S[j], slab, m, m, slab,
-             m, slab, m);
+      tb.add(offv(h->leafLU.p, h->lu_off[j], es), h->DL(j), lperm + h->na[lf], m, h->S[j], slab, m,
+             m, slab, m, slab, m);
       proj.begin(offv(PS, h->psw_off[lf], es), h->s[lf], h->s[lf], h->S[j], 1.0, 0.0);
       proj.seg(offv(Pt, h->p_off[lf], es), m, true, slab, m, m);
     }
@@ -629,6 +678,9 @@ int plan_factor(H* h) {
     fp.leaf_lu.count = (int)lus.size();
     fp.leaf_lu.nmax = nmax;
     fp.leaf_lu.t64 = T64;
+    fp.leaf_dinv.probs = ar.add(dis);
+    fp.leaf_dinv.count = (int)dis.size();
+    fp.leaf_dinv.t64 = T64;
     fp.panels.blocks = ar.add(pblocks);
     fp.panels.tiles = ar.add(ptiles);
     fp.panels.ntiles = (int)ptiles.size();
@@ -638,15 +690,26 @@ int plan_factor(H* h) {
   // wavefront over levels j = L-1 .. 0
   fp.zform.assign(std::max(L, 1), ZformL());
   fp.zlu.assign(std::max(L, 1), LuL());
+  fp.zdinv.assign(std::max(L, 1), DinvL());
   fp.zsolve.assign(std::max(L, 1), TrsmL());
   fp.pgemm.assign(std::max(L, 1), GemmL());
   for (int jl = L - 1; jl >= 0; --jl) {
     std::vector<ZformProb> zf;
     std::vector<LuProb> zl;
+    std::vector<DiagInvProb> zd;
     TrsmBuilder zs;
     GemmBuilder pg;
     int nmax = 0;
+    const size_t zes = h->zis64[jl] ? 8 : es;
     for (int a = (1 << jl) - 1; a < (2 << jl) - 1; ++a) {
+      for (int jb = 0; jb < h->z[a]; jb += kDiagBlock) {
+        DiagInvProb d{};
+        d.lu = h->Z(a);
+        d.out = offv(const_cast<void*>(h->DZ(a)), (jb / kDiagBlock) * kDB2, zes);
+        d.n = h->z[a];
+        d.jb = jb;
+        zd.push_back(d);
+      }
       const int l = 2 * a + 1, r = 2 * a + 2;
       ZformProb p{};
       p.Z = h->Zm(a);
@@ -664,7 +727,7 @@ int plan_factor(H* h) {
       nmax = std::max(nmax, h->z[a]);
       if (jl >= 1) {
         void* y = offv(YS, h->ysw_off[a], es);
-        zs.add(h->Z(a), zpm + h->zperm_off[a], h->z[a], h->Ssw[a],
+        zs.add(h->Z(a), h->DZ(a), zpm + h->zperm_off[a], h->z[a], h->Ssw[a],
                offv(PS, h->psw_off[r] + (int64_t)h->colp[r][jl] * h->s[r], es), h->s[r], h->s[r],
                offv(PS, h->psw_off[l] + (int64_t)h->colp[l][jl] * h->s[l], es), h->s[l], y,
                h->z[a]);
@@ -684,6 +747,10 @@ int plan_factor(H* h) {
     lul.count = (int)zl.size();
     lul.nmax = nmax;
     lul.t64 = h->zis64[jl];
+    DinvL& dl = fp.zdinv[jl];
+    dl.probs = ar.add(zd);
+    dl.count = (int)zd.size();
+    dl.t64 = h->zis64[jl];
     if (jl >= 1) {
       fp.zsolve[jl] = zs.emit(ar, h->zis64[jl], T64, 1);
       fp.pgemm[jl] = pg.emit(ar);
@@ -738,6 +805,12 @@ hipError_t run_lu(const DevBuf& tb, const LuL& l, hipStream_t s) {
   if (l.count == 0) return hipSuccess;
   if (l.t64) return launch_getrf<double>(at<LuProb>(tb, l.probs), l.count, l.nmax, s);
   return launch_getrf<float>(at<LuProb>(tb, l.probs), l.count, l.nmax, s);
+}
+
+hipError_t run_dinv(const DevBuf& tb, const DinvL& l, hipStream_t s) {
+  if (l.count == 0) return hipSuccess;
+  if (l.t64) return launch_diag_inv<double>(at<DiagInvProb>(tb, l.probs), l.count, s);
+  return launch_diag_inv<float>(at<DiagInvProb>(tb, l.probs), l.count, s);
 }
 
 hipError_t run_zform(const DevBuf& tb, const ZformL& l, hipStream_t s) {
@@ -803,6 +876,7 @@ int run_factor(H* h) {
     STEP(launch_convert_f64_f32(h->P64, static_cast<float*>(h->P32.p), h->p_off[h->nn], s));
   STEP(run_eval(h, tb, fp.leaf_eval, h->lam, s));
   STEP(run_lu(tb, fp.leaf_lu, s));
+  STEP(run_dinv(tb, fp.leaf_dinv, s));
   mark(0);
   if (h->L > 0) {
     STEP(run_eval(h, tb, fp.panels, 0.0, s));
@@ -814,6 +888,7 @@ int run_factor(H* h) {
     for (int j = h->L - 1; j >= 0; --j) {
       STEP(run_zform(tb, fp.zform[j], s));
       STEP(run_lu(tb, fp.zlu[j], s));
+      STEP(run_dinv(tb, fp.zdinv[j], s));
       mark(6);
       if (j >= 1) {
         STEP(run_trsm(tb, fp.zsolve[j], s));
@@ -897,7 +972,8 @@ int build_solve_plan(H* h, int r, SolvePlan*& out) {
     const int lf = h->leaf_node(j);
     const int m = (int)(h->nb[lf] - h->na[lf]);
     void* xr = offv(xb, h->na[lf], es);
-    lt.add(offv(h->leafLU.p, h->lu_off[j], es), lperm + h->na[lf], m, r, xr, h->N, m, xr, h->N, xr,
+    lt.add(offv(h->leafLU.p, h->lu_off[j], es), h->DL(j), lperm + h->na[lf], m, r, xr, h->N, m, xr,
+           h->N, xr,
            h->N);
     if (L > 0) {
       lpj.begin(offv(sb, sp_off[lf], es), h->s[lf], h->s[lf], r, 1.0, 0.0);
@@ -920,7 +996,8 @@ int build_solve_plan(H* h, int r, SolvePlan*& out) {
     for (int bnode = (1 << jl) - 1; bnode < (2 << jl) - 1; ++bnode) {
       const int l = 2 * bnode + 1, rr = 2 * bnode + 2;
       void* y = offv(sb, sy_off[bnode], es);
-      zs.add(h->Z(bnode), zpm + h->zperm_off[bnode], h->z[bnode], r, offv(sb, sp_off[rr], es),
+      zs.add(h->Z(bnode), h->DZ(bnode), zpm + h->zperm_off[bnode], h->z[bnode], r,
+             offv(sb, sp_off[rr], es),
              h->s[rr], h->s[rr], offv(sb, sp_off[l], es), h->s[l], y, h->z[bnode]);
       if (jl > 0) {
         pg.begin(offv(sb, sp_off[bnode], es), h->s[bnode], h->s[bnode], r, 1.0, 0.0);
@@ -1247,7 +1324,8 @@ int invaskit_device_bytes(invaskit_handle h, size_t* bytes) {
   if (!h || !bytes) return fail_h(h, INVASKIT_E_ARG, "handle and bytes are required");
   size_t t = 0;
   for (const DevBuf* b : {&h->skel_d, &h->P32, &h->leafLU, &h->leafPerm, &h->leafInfo, &h->slab,
-                          &h->Z64, &h->ZT, &h->zperm, &h->zinfo, &h->psw, &h->ysw, &h->ftables})
+                          &h->Z64, &h->ZT, &h->zperm, &h->zinfo, &h->psw, &h->ysw, &h->ftables,
+                          &h->dinvLeaf, &h->dinvZ64, &h->dinvZT})
     t += b->bytes;
   for (auto& kv : h->solve_plans)
     for (const DevBuf* b : {&kv.second->tables, &kv.second->xbuf, &kv.second->sbuf,
@@ -1341,27 +1419,55 @@ int invaskit_getrs_batched(int32_t dtype, const void* a, const int64_t* a_offset
     return fail_h(nullptr, INVASKIT_E_ARG, "dtype must be INVASKIT_F64 or INVASKIT_F32");
   if (count == 0) return INVASKIT_OK;
   const size_t es = dtype == INVASKIT_F64 ? 8 : 4;
-  TrsmBuilder tb;
-  int64_t poff = 0;
+  constexpr int64_t kDB2 = 2 * kDiagBlock * kDiagBlock;
+  int64_t dn = 0;
   for (int i = 0; i < count; ++i) {
     if (n[i] < 1 || n[i] > kMaxLeaf || nrhs[i] < 0 || ldb[i] < n[i])
       return fail_h(nullptr, INVASKIT_E_ARG, "getrs_batched sizes out of range");
+    dn += (n[i] + kDiagBlock - 1) / kDiagBlock * kDB2;
+  }
+  DevBuf dinv;
+  int rc = dev_alloc(nullptr, dinv, dn * es);
+  if (rc) return rc;
+  TrsmBuilder tb;
+  std::vector<DiagInvProb> dis;
+  int64_t poff = 0, doff = 0;
+  for (int i = 0; i < count; ++i) {
+    const unsigned char* ai = static_cast<const unsigned char*>(a) + a_offsets[i] * es;
+    void* di = static_cast<unsigned char*>(dinv.p) + doff * es;
+    for (int jb = 0; jb < n[i]; jb += kDiagBlock) {
+      DiagInvProb d{};
+      d.lu = ai;
+      d.out = static_cast<unsigned char*>(di) + (jb / kDiagBlock) * kDB2 * es;
+      d.n = n[i];
+      d.jb = jb;
+      dis.push_back(d);
+    }
     void* bi = static_cast<unsigned char*>(b) + b_offsets[i] * es;
-    tb.add(static_cast<const unsigned char*>(a) + a_offsets[i] * es, perm + poff, n[i], nrhs[i],
-           bi, ldb[i], n[i], bi, ldb[i], bi, ldb[i]);
+    tb.add(ai, di, perm + poff, n[i], nrhs[i], bi, ldb[i], n[i], bi, ldb[i], bi, ldb[i]);
     poff += n[i];
+    doff += (n[i] + kDiagBlock - 1) / kDiagBlock * kDB2;
   }
   Arena ar;
   const int f = dtype == INVASKIT_F64 ? 1 : 0;
   TrsmL l = tb.emit(ar, f, f, 1);
+  DinvL dl;
+  dl.probs = ar.add(dis);
+  dl.count = (int)dis.size();
+  dl.t64 = f;
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   DevBuf t;
-  int rc = dev_alloc(nullptr, t, ar.host.size());
-  if (rc) return rc;
+  rc = dev_alloc(nullptr, t, ar.host.size());
+  if (rc) {
+    dinv.release();
+    return rc;
+  }
   hipError_t e = hipMemcpy(t.p, ar.host.data(), ar.host.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = run_dinv(t, dl, s);
   if (e == hipSuccess) e = run_trsm(t, l, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   t.release();
+  dinv.release();
   if (e != hipSuccess) return fail_h(nullptr, INVASKIT_E_HIP, hipGetErrorString(e));
   return INVASKIT_OK;
 }

@@ -2,17 +2,19 @@
 // leaf solves of Algorithm 2 and the reduced-system solves of eq.
 // (e:blocksmw)), every system of a launch in one grid.
 //
-// One workgroup (4 waves) takes RT right-hand-side columns of one system.
-// The permuted right-hand sides live in LDS (row-major, RT values per row).
-// Forward substitution with the unit-lower L and back substitution with U
-// proceed by 64-row blocks:
-//   diagonal block: the 64 x 64 triangle is staged in LDS; each wave solves
-//     RT/4 columns with lane = row, the finished value of row j broadcast by
-//     a cross-lane read (no workgroup barrier inside the block);
-//   off-diagonal update: the rows below (above) the block are updated on the
-//     matrix cores, X_rows -= L[rows, block] X[block], in 16 x 16 tiles with
-//     K = 64; the L operand streams from global memory, the solved block
-//     rows from LDS.
+// k_diag_inv runs once per factorization: for every 64 x 64 diagonal block
+// of every factor it forms the inverses of the unit-lower block of L and of
+// the upper block of U (column by column against the identity, one wave per
+// 16 columns, the diagonal of U inverted once).
+//
+// k_getrs: one workgroup (4 waves) takes 16 right-hand-side columns of one
+// system; the permuted right-hand sides live in LDS (row stride 17 to spread
+// the banks).  Forward substitution with L and back substitution with U go
+// by 64-row blocks, both steps on the matrix cores:
+//   diagonal block:  X_b = inv(L_bb) X_b   (inv(U_bb) going back),
+//   off-diagonal:    X_rows -= L[rows, block] X_b   (U[rows, block] going back),
+// in 16 x 16 output tiles with K = 64, the factor operands streamed from
+// global memory with a tile's 16 loads in flight together.
 // TZ is the type of the factors and of the arithmetic, TV the type of the
 // right-hand sides in memory.  KIND only separates the kernel names of the
 // three uses (leaf panels of the factorization, reduced systems, solve).
@@ -21,7 +23,9 @@
 namespace invaskit {
 namespace {
 
-constexpr int NBK = 64;  // row block
+constexpr int NBK = kDiagBlock;  // 64-row block
+constexpr int RT = kTrsmCols;    // right-hand sides per workgroup
+constexpr int RTP = RT + 1;      // LDS row stride
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -56,38 +60,83 @@ __device__ __forceinline__ float lane_bcast(float v, int l) {
   return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
 }
 
+// ------------------------------------------------------------ block inverses
 template <typename TZ>
-constexpr int cols_per_tile() {
-  return sizeof(TZ) == 8 ? 16 : 32;
+__global__ __launch_bounds__(256) void k_diag_inv(const DiagInvProb* __restrict__ probs) {
+  const DiagInvProb p = probs[blockIdx.x];
+  const TZ* __restrict__ LU = static_cast<const TZ*>(p.lu);
+  TZ* __restrict__ out = static_cast<TZ*>(p.out);  // inv(L_bb) then inv(U_bb), 64 x 64 each
+  const int n = p.n, jb = p.jb;
+  const int nb = min(NBK, n - jb);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __shared__ TZ B[NBK][NBK + 1];  // B[c][r] = block entry (row r, column c)
+  __shared__ TZ rdiag[NBK];
+  for (int idx = tid; idx < NBK * NBK; idx += 256) {
+    const int r = idx % NBK, c = idx / NBK;
+    B[c][r] = (r < nb && c < nb) ? LU[(int64_t)(jb + c) * n + jb + r] : TZ(0);
+  }
+  __syncthreads();
+  if (tid < NBK) rdiag[tid] = (tid < nb) ? TZ(1) / B[tid][tid] : TZ(0);
+  __syncthreads();
+  constexpr int CQ = NBK / 4;  // identity columns per wave
+  // inv(L): L X = I, L unit lower
+  {
+    TZ x[CQ];
+#pragma unroll
+    for (int q = 0; q < CQ; ++q) x[q] = (lane == wave * CQ + q && lane < nb) ? TZ(1) : TZ(0);
+    for (int j = 0; j < nb - 1; ++j) {
+      const TZ l = (lane > j) ? B[j][lane] : TZ(0);
+#pragma unroll
+      for (int q = 0; q < CQ; ++q) x[q] -= l * lane_bcast(x[q], j);
+    }
+#pragma unroll
+    for (int q = 0; q < CQ; ++q) out[(wave * CQ + q) * NBK + lane] = (lane < nb) ? x[q] : TZ(0);
+  }
+  // inv(U): U X = I, U upper
+  {
+    TZ x[CQ];
+#pragma unroll
+    for (int q = 0; q < CQ; ++q) x[q] = (lane == wave * CQ + q && lane < nb) ? TZ(1) : TZ(0);
+    for (int j = nb - 1; j >= 0; --j) {
+      const TZ u = (lane < j) ? B[j][lane] : TZ(0);
+      const TZ rd = rdiag[j];
+#pragma unroll
+      for (int q = 0; q < CQ; ++q) {
+        if (lane == j) x[q] *= rd;
+        x[q] -= u * lane_bcast(x[q], j);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < CQ; ++q)
+      out[NBK * NBK + (wave * CQ + q) * NBK + lane] = (lane < nb) ? x[q] : TZ(0);
+  }
 }
 
+// ------------------------------------------------------------------- solves
 template <typename TZ, typename TV, int KIND>
 __global__ __launch_bounds__(256) void k_getrs(const TrsmProb* __restrict__ probs,
                                                const Tile2* __restrict__ tiles) {
   using V4 = typename Vec4<TZ>::type;
-  constexpr int RT = cols_per_tile<TZ>();
-  constexpr int CW = RT / 4;  // columns per wave in the diagonal solve
-  constexpr int CT = RT / 16; // 16-wide column tiles in the update
   const Tile2 t = tiles[blockIdx.x];
   const TrsmProb pr = probs[t.prob];
   const int n = pr.n;
   const int c0 = t.tn * RT;
   const int nc = min(RT, pr.nrhs - c0);
   const TZ* __restrict__ LU = static_cast<const TZ*>(pr.lu);
+  const TZ* __restrict__ DI = static_cast<const TZ*>(pr.dinv);
   const TV* __restrict__ in0 = static_cast<const TV*>(pr.in0);
   const TV* __restrict__ in1 = static_cast<const TV*>(pr.in1);
   TV* __restrict__ out = static_cast<TV*>(pr.out);
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int lr = lane & 15, lk = lane >> 4;
+  const int lr = lane & 15, lg = lane >> 4;
 
   extern __shared__ __align__(16) unsigned char smem[];
-  TZ* Ld = reinterpret_cast<TZ*>(smem);  // 64 x 64 diagonal block, column-major
-  TZ* X = Ld + NBK * NBK;                // n x RT, row-major
+  TZ* X = reinterpret_cast<TZ*>(smem);  // n x RT, row stride RTP
 
-  // gather the permuted right-hand sides: one thread per row, all RT column
-  // loads of a row in flight together
+  // gather the permuted right-hand sides: one thread per row, the row's RT
+  // column loads in flight together
   for (int i = tid; i < n; i += 256) {
     const int src = pr.perm[i];
     const TV* base = (src < pr.split) ? in0 + src : in1 + (src - pr.split);
@@ -96,8 +145,9 @@ __global__ __launch_bounds__(256) void k_getrs(const TrsmProb* __restrict__ prob
 #pragma unroll
     for (int c = 0; c < RT; ++c) v[c] = (c < nc) ? (TZ)base[(int64_t)(c0 + c) * ld] : TZ(0);
 #pragma unroll
-    for (int c = 0; c < RT; ++c) X[i * RT + c] = v[c];
+    for (int c = 0; c < RT; ++c) X[i * RTP + c] = v[c];
   }
+  __syncthreads();
 
   const int nblocks = (n + NBK - 1) / NBK;
   for (int pass = 0; pass < 2; ++pass) {
@@ -106,46 +156,28 @@ __global__ __launch_bounds__(256) void k_getrs(const TrsmProb* __restrict__ prob
       const int b = fwd ? bi : nblocks - 1 - bi;
       const int jb = b * NBK;
       const int nb = min(NBK, n - jb);
-      // stage the diagonal block
-#pragma unroll
-      for (int idx = tid; idx < NBK * NBK; idx += 256) {
-        const int r = idx % NBK, j = idx / NBK;
-        Ld[idx] = (r < nb && j < nb) ? LU[(int64_t)(jb + j) * n + jb + r] : TZ(0);
-      }
-      __syncthreads();
+      // X_b = inv(diagonal block) X_b: wave w computes rows 16w .. 16w+15
       {
-        const int r = jb + lane;
-        TZ x[CW];
+        const TZ* D = DI + (int64_t)(2 * b + (fwd ? 0 : 1)) * NBK * NBK;
+        TZ a[NBK / 4];
 #pragma unroll
-        for (int q = 0; q < CW; ++q) x[q] = (lane < nb) ? X[r * RT + wave * CW + q] : TZ(0);
-        if (fwd) {
-          for (int j = 0; j < nb - 1; ++j) {
-            const TZ l = (lane > j) ? Ld[j * NBK + lane] : TZ(0);
+        for (int kk = 0; kk < NBK / 4; ++kk) a[kk] = D[(4 * kk + lg) * NBK + 16 * wave + lr];
+        V4 acc = V4{0, 0, 0, 0};
 #pragma unroll
-            for (int q = 0; q < CW; ++q) x[q] -= l * lane_bcast(x[q], j);
-          }
-        } else {
-          for (int j = nb - 1; j >= 0; --j) {
-            const TZ u = (lane <= j) ? Ld[j * NBK + lane] : TZ(1);
-            if (lane == j) {
-#pragma unroll
-              for (int q = 0; q < CW; ++q) x[q] /= u;
-            }
-#pragma unroll
-            for (int q = 0; q < CW; ++q) {
-              const TZ xj = lane_bcast(x[q], j);
-              if (lane < j) x[q] -= u * xj;
-            }
-          }
+        for (int kk = 0; kk < NBK / 4; ++kk) {
+          const int k = 4 * kk + lg;
+          const TZ bb = (k < nb) ? X[(jb + k) * RTP + lr] : TZ(0);
+          acc = mfma16(a[kk], bb, acc);
         }
-        if (lane < nb) {
+        __syncthreads();
 #pragma unroll
-          for (int q = 0; q < CW; ++q) X[r * RT + wave * CW + q] = x[q];
+        for (int v = 0; v < 4; ++v) {
+          const int r = 16 * wave + acc_row(TZ(0), lg, v);
+          if (r < nb) X[(jb + r) * RTP + lr] = acc[v];
         }
       }
       __syncthreads();
-      // off-diagonal update on the matrix cores: one 16-row tile per item,
-      // its 16 x 64 slice of the factor loaded into registers up front
+      // rows below (above) the block: X_rows -= F[rows, block] X_b
       const int r0 = fwd ? jb + nb : 0;
       const int r1 = fwd ? n : jb;
       const int nrt = (r1 - r0 + 15) / 16;
@@ -154,30 +186,23 @@ __global__ __launch_bounds__(256) void k_getrs(const TrsmProb* __restrict__ prob
         const bool rin = row < r1;
         TZ a[NBK / 4];
 #pragma unroll
-        for (int q = 0; q < NBK / 4; ++q) {
-          const int j = 4 * q + lk;
-          a[q] = (rin && j < nb) ? LU[(int64_t)(jb + j) * n + row] : TZ(0);
+        for (int kk = 0; kk < NBK / 4; ++kk) {
+          const int j = 4 * kk + lg;
+          a[kk] = (rin && j < nb) ? LU[(int64_t)(jb + j) * n + row] : TZ(0);
         }
-        V4 acc[CT];
+        V4 acc = V4{0, 0, 0, 0};
 #pragma unroll
-        for (int ct = 0; ct < CT; ++ct) acc[ct] = V4{0, 0, 0, 0};
-#pragma unroll
-        for (int q = 0; q < NBK / 4; ++q) {
-          const int j = 4 * q + lk;
-#pragma unroll
-          for (int ct = 0; ct < CT; ++ct) {
-            const TZ bb = (j < nb) ? X[(jb + j) * RT + ct * 16 + lr] : TZ(0);
-            acc[ct] = mfma16(a[q], bb, acc[ct]);
-          }
+        for (int kk = 0; kk < NBK / 4; ++kk) {
+          const int j = 4 * kk + lg;
+          const TZ bb = (j < nb) ? X[(jb + j) * RTP + lr] : TZ(0);
+          acc = mfma16(a[kk], bb, acc);
         }
         const int i0 = r0 + item * 16;
 #pragma unroll
-        for (int ct = 0; ct < CT; ++ct)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int rr = i0 + acc_row(TZ(0), lk, v);
-            if (rr < r1) X[rr * RT + ct * 16 + lr] -= acc[ct][v];
-          }
+        for (int v = 0; v < 4; ++v) {
+          const int rr = i0 + acc_row(TZ(0), lg, v);
+          if (rr < r1) X[rr * RTP + lr] -= acc[v];
+        }
       }
       __syncthreads();
     }
@@ -186,14 +211,13 @@ __global__ __launch_bounds__(256) void k_getrs(const TrsmProb* __restrict__ prob
   for (int i = tid; i < n; i += 256) {
 #pragma unroll
     for (int c = 0; c < RT; ++c)
-      if (c < nc) out[(int64_t)(c0 + c) * pr.ldout + i] = (TV)X[i * RT + c];
+      if (c < nc) out[(int64_t)(c0 + c) * pr.ldout + i] = (TV)X[i * RTP + c];
   }
 }
 
 template <typename TZ, typename TV, int KIND>
 hipError_t run(const TrsmProb* probs, const Tile2* tiles, int ntiles, int nmax, hipStream_t s) {
-  constexpr int RT = cols_per_tile<TZ>();
-  const size_t sm = ((size_t)NBK * NBK + (size_t)nmax * RT) * sizeof(TZ);
+  const size_t sm = (size_t)nmax * RTP * sizeof(TZ);
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_getrs<TZ, TV, KIND>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
   if (e != hipSuccess) return e;
@@ -203,7 +227,14 @@ hipError_t run(const TrsmProb* probs, const Tile2* tiles, int ntiles, int nmax, 
 
 }  // namespace
 
-int getrs_cols_per_tile(bool tz64) { return tz64 ? cols_per_tile<double>() : cols_per_tile<float>(); }
+int getrs_cols_per_tile(bool) { return RT; }
+
+template <typename TZ>
+hipError_t launch_diag_inv(const DiagInvProb* probs, int count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_diag_inv<TZ>), dim3(count), dim3(256), 0, s, probs);
+  return hipGetLastError();
+}
 
 template <typename TZ, typename TV>
 hipError_t launch_getrs(const TrsmProb* probs, const Tile2* tiles, int ntiles, int nmax, int kind,
@@ -216,6 +247,8 @@ hipError_t launch_getrs(const TrsmProb* probs, const Tile2* tiles, int ntiles, i
   }
 }
 
+template hipError_t launch_diag_inv<double>(const DiagInvProb*, int, hipStream_t);
+template hipError_t launch_diag_inv<float>(const DiagInvProb*, int, hipStream_t);
 template hipError_t launch_getrs<double, double>(const TrsmProb*, const Tile2*, int, int, int,
                                                  hipStream_t);
 template hipError_t launch_getrs<float, float>(const TrsmProb*, const Tile2*, int, int, int,
