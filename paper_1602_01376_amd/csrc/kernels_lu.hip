@@ -1,52 +1,105 @@
-// Batched LU with partial pivoting for square matrices of uneven order, one
-// workgroup per matrix, all matrices of a tree level in one launch (the leaf
-// LU of Algorithm 1 and the LU of the reduced systems of eq. (e:blocksmw)).
+// Batched LU with partial pivoting for square matrices of uneven order (the
+// leaf LU of Algorithm 1 and the LU of the reduced systems of eq.
+// (e:blocksmw)), one workgroup of four waves per matrix, every matrix of a
+// launch in one grid.
 //
-// Right-looking blocked algorithm with panel width NB:
-//   1. the panel (rows j0..n, NB columns) is loaded into LDS and factored
-//      column by column; the pivot is the first row of largest magnitude
-//      (LAPACK getrf semantics), found by a wavefront max-reduction
-//      followed by a cross-wave reduction through LDS;
-//   2. the panel's row interchanges, composed into one permutation of the
-//      touched rows, are applied to the other columns (independent loads);
-//   3. U12 = L11^-1 A12 (one thread per column) is written to global memory
-//      and kept in LDS;
-//   4. the trailing matrix is updated, A22 -= L21 U12, with 4 x 4 register
-//      blocks fed from LDS.
-// The row permutation is returned as perm[j] = original row now at row j;
-// info = j+1 for the first zero or non-finite pivot in column j (the
-// factorization continues without dividing, as LAPACK does).
+// Right-looking blocked algorithm with panels of W columns (32 in FP32, 16 in
+// FP64):
+//   1. Panel.  The panel's rows are held in registers across the workgroup
+//      (row r in thread r % 256, slot r / 256).  Rows never move; each carries
+//      its logical position.  Per column: every wave finds its candidate (the
+//      first row of largest magnitude: LAPACK getrf semantics) and the owning
+//      lane publishes that row in LDS; one barrier; every thread picks the
+//      winner of the four, exchanges the two logical positions, scales by the
+//      pivot's reciprocal and updates its rows -- one barrier per column (the
+//      candidate rows are double-buffered).
+//   2. The panel goes back to memory in logical order; the rows that moved
+//      (at most 2W) form a move list that is applied to every other column
+//      (all loads of a column before its stores); inv(L11) is formed in LDS.
+//   3. For each chunk of 64 columns to the right: U12 = inv(L11) A12 and
+//      A22 -= L21 U12, both on the matrix cores (16 x 16 tiles).
+// perm[j] = original row now at row j; info = j+1 for the first zero or
+// non-finite pivot in column j (the column is left unscaled and the
+// factorization continues, as LAPACK does).
 #include <cmath>
+#include <utility>
 
 #include "internal.hpp"
 
 namespace invaskit {
 namespace {
 
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+template <typename T>
+struct Vec4;
+template <>
+struct Vec4<double> {
+  using type = f64x4;
+};
+template <>
+struct Vec4<float> {
+  using type = f32x4;
+};
+__device__ __forceinline__ f64x4 mfma16(double a, double b, f64x4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f32x4 mfma16(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+// accumulator row of element v in lane group g (16x16x4 forms, gfx950)
+__device__ __forceinline__ constexpr int acc_row(double, int g, int v) { return g + 4 * v; }
+__device__ __forceinline__ constexpr int acc_row(float, int g, int v) { return 4 * g + v; }
+
+__device__ __forceinline__ double lane_bcast(double v, int l) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ float lane_bcast(float v, int l) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+
 template <typename T>
 __device__ __forceinline__ bool better(T v, int i, T bv, int bi) {
-  // larger magnitude wins; ties go to the smaller row index
+  // larger magnitude wins; ties go to the smaller logical row
   return (v > bv) || (v == bv && i < bi);
 }
 
-template <typename T, int NB>
+constexpr int CH = 64;  // column chunk of the U12 / trailing update
+
+// f(integral_constant<int, I>) for I = 0 .. N-1, unrolled at compile time
+template <typename F, int... I>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+template <typename T, int W, int RPS>
 __global__ __launch_bounds__(256) void k_getrf(const LuProb* __restrict__ probs) {
+  using V4 = typename Vec4<T>::type;
+  constexpr int MQ = 2 * W / 4;  // move-list entries per wave
   const LuProb pr = probs[blockIdx.x];
   T* __restrict__ A = static_cast<T*>(pr.a);
   const int n = pr.n;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
+  const int lr = lane & 15, lg = lane >> 4;
 
   extern __shared__ __align__(16) unsigned char smem[];
-  T* Pn = reinterpret_cast<T*>(smem);           // panel, (n - j0) x NB, ld = n - j0
-  T* Us = Pn + (size_t)n * NB;                    // U12, NB x n, row-major (ld n)
-  int* Ps = reinterpret_cast<int*>(Us + (size_t)NB * n);  // permutation
-  int* Loc = Ps + n;  // composed interchanges of one panel
-  __shared__ T red_v[4];
-  __shared__ int red_i[4];
-  __shared__ int s_piv[NB];
-  __shared__ int s_tl[2 * NB];
+  int* Ps = reinterpret_cast<int*>(smem);  // permutation, n entries
+  __shared__ T s_row[2][4][W];             // each wave's candidate pivot row
+  __shared__ T s_bv[2][4];
+  __shared__ int s_bl[2][4];
+  __shared__ T L11[W][W + 1];
+  __shared__ T Li[W][W + 1];              // inv(L11), row-major
+  __shared__ T Uc[W][CH];                 // U12 chunk
+  __shared__ int s_src[2 * W], s_dst[2 * W];
   __shared__ int s_cnt;
   __shared__ int s_info;
 
@@ -54,217 +107,250 @@ __global__ __launch_bounds__(256) void k_getrf(const LuProb* __restrict__ probs)
   if (tid == 0) s_info = 0;
   __syncthreads();
 
-  for (int j0 = 0; j0 < n; j0 += NB) {
-    const int jb = min(NB, n - j0);
-    const int mr = n - j0;  // panel rows
-    for (int idx = tid; idx < mr * jb; idx += 256) {
-      const int r = idx % mr, c = idx / mr;
-      Pn[r + c * mr] = A[(int64_t)(j0 + c) * n + j0 + r];
+  for (int j0 = 0; j0 < n; j0 += W) {
+    const int jb = min(W, n - j0);
+    const int mr = n - j0;
+    // ------------------------------------------------------------ 1. panel
+    T P[RPS][W];
+    int lpos[RPS];
+#pragma unroll
+    for (int t = 0; t < RPS; ++t) {
+      const int r = tid + 256 * t;
+      lpos[t] = (r < mr) ? r : -1;
+#pragma unroll
+      for (int c = 0; c < W; ++c)
+        P[t][c] = (r < mr && c < jb) ? A[(int64_t)(j0 + c) * n + j0 + r] : T(0);
     }
-    __syncthreads();
-
-    for (int jj = 0; jj < jb; ++jj) {
-      // ---- pivot search in column jj, rows jj..mr
+    int info = 0;
+    static_for<W>([&](auto JJ) {
+      constexpr int jj = decltype(JJ)::value;
+      if (jj < jb) {
+      const int buf = jj & 1;
       T bv = T(-1);
-      int bi = 0x7fffffff;
-      for (int r = jj + tid; r < mr; r += 256) {
-        const T v = fabs(Pn[r + jj * mr]);
-        const T vv = (v == v) ? v : T(INFINITY);  // a NaN is taken as pivot (flagged below)
-        if (better(vv, r, bv, bi)) {
-          bv = vv;
-          bi = r;
+      int bl = 0x7fffffff, bw = 0;
+#pragma unroll
+      for (int t = 0; t < RPS; ++t) {
+        if (lpos[t] >= jj) {
+          T v = fabs(P[t][jj]);
+          v = (v == v) ? v : T(INFINITY);  // a NaN is taken as pivot (flagged below)
+          if (better(v, lpos[t], bv, bl)) {
+            bv = v;
+            bl = lpos[t];
+            bw = (t << 6) | lane;
+          }
         }
       }
 #pragma unroll
       for (int off = 32; off >= 1; off >>= 1) {
         const T ov = __shfl_xor(bv, off, 64);
-        const int oi = __shfl_xor(bi, off, 64);
-        if (better(ov, oi, bv, bi)) {
+        const int ol = __shfl_xor(bl, off, 64);
+        const int ow = __shfl_xor(bw, off, 64);
+        if (better(ov, ol, bv, bl)) {
           bv = ov;
-          bi = oi;
+          bl = ol;
+          bw = ow;
         }
       }
-      if (lane == 0) {
-        red_v[wave] = bv;
-        red_i[wave] = bi;
-      }
-      __syncthreads();
-      if (tid == 0) {
-        T v = red_v[0];
-        int i = red_i[0];
-        for (int w = 1; w < 4; ++w)
-          if (better(red_v[w], red_i[w], v, i)) {
-            v = red_v[w];
-            i = red_i[w];
+      {
+        const int wl = bw & 63, wt = bw >> 6;
+        // predicated stores per slot (a select over slots would become an
+        // indexed load from P and push P out of registers)
+#pragma unroll
+        for (int t = 0; t < RPS; ++t) {
+          if (lane == wl && t == wt) {
+#pragma unroll
+            for (int c = 0; c < W; ++c) s_row[buf][wave][c] = P[t][c];
           }
-        s_piv[jj] = i;
-        const int p = i;
-        // swap the permutation entries
-        const int a = Ps[j0 + jj];
-        Ps[j0 + jj] = Ps[j0 + p];
-        Ps[j0 + p] = a;
-      }
-      __syncthreads();
-      const int p = s_piv[jj];
-      if (p != jj) {
-        for (int c = tid; c < jb; c += 256) {
-          const T a = Pn[jj + c * mr];
-          Pn[jj + c * mr] = Pn[p + c * mr];
-          Pn[p + c * mr] = a;
+        }
+        if (lane == 0) {
+          s_bv[buf][wave] = bv;
+          s_bl[buf][wave] = bl;
         }
       }
       __syncthreads();
-      const T pv = Pn[jj + jj * mr];
+      int w = 0;
+      T v = s_bv[buf][0];
+      int pl = s_bl[buf][0];
+#pragma unroll
+      for (int ww = 1; ww < 4; ++ww)
+        if (better(s_bv[buf][ww], s_bl[buf][ww], v, pl)) {
+          v = s_bv[buf][ww];
+          pl = s_bl[buf][ww];
+          w = ww;
+        }
+      const T* prow = s_row[buf][w];
+      const T pv = prow[jj];
       const bool ok = (pv != T(0)) && isfinite(pv);
-      if (!ok) {
-        if (tid == 0 && s_info == 0) s_info = j0 + jj + 1;
-      } else {
-        for (int r = jj + 1 + tid; r < mr; r += 256) Pn[r + jj * mr] /= pv;
+      if (!ok && info == 0) info = j0 + jj + 1;
+      if (tid == 0) {
+        const int a = Ps[j0 + jj];
+        Ps[j0 + jj] = Ps[j0 + pl];
+        Ps[j0 + pl] = a;
       }
-      __syncthreads();
-      // rank-1 update of the rest of the panel
-      const int rows = mr - jj - 1;
-      const int cols = jb - jj - 1;
-      for (int idx = tid; idx < rows * cols; idx += 256) {
-        const int r = jj + 1 + idx % rows;
-        const int c = jj + 1 + idx / rows;
-        Pn[r + c * mr] -= Pn[r + jj * mr] * Pn[jj + c * mr];
+#pragma unroll
+      for (int t = 0; t < RPS; ++t) {
+        if (lpos[t] == pl)
+          lpos[t] = jj;
+        else if (lpos[t] == jj)
+          lpos[t] = pl;
       }
-      __syncthreads();
-    }
-
-    // write the panel back
-    for (int idx = tid; idx < mr * jb; idx += 256) {
-      const int r = idx % mr, c = idx / mr;
-      A[(int64_t)(j0 + c) * n + j0 + r] = Pn[r + c * mr];
-    }
-    // row interchanges on the columns outside the panel: compose the panel's
-    // swaps into Loc (new row t takes old row Loc[t]) and move only the
-    // touched rows
-    for (int i = tid; i < mr; i += 256) Loc[i] = i;
-    __syncthreads();
+      if (ok) {
+        const T inv = T(1) / pv;
+#pragma unroll
+        for (int t = 0; t < RPS; ++t) {
+          if (lpos[t] > jj) {
+            const T l = P[t][jj] * inv;
+            P[t][jj] = l;
+#pragma unroll
+            for (int c = jj + 1; c < W; ++c) P[t][c] -= l * prow[c];
+          }
+        }
+      }
+      }
+    });
+    // --------------------------- 2. write back, move list, inverse of L11
     if (tid == 0) {
-      for (int jj = 0; jj < jb; ++jj) {
-        const int p = s_piv[jj];
-        const int a = Loc[jj];
-        Loc[jj] = Loc[p];
-        Loc[p] = a;
-      }
-      int cnt = 0;
-      for (int jj = 0; jj < jb; ++jj) {
-        const int cand[2] = {jj, s_piv[jj]};
-        for (int q = 0; q < 2; ++q) {
-          const int t = cand[q];
-          if (Loc[t] == t) continue;
-          bool dup = false;
-          for (int u = 0; u < cnt; ++u) dup |= (s_tl[u] == t);
-          if (!dup) s_tl[cnt++] = t;
-        }
-      }
-      s_cnt = cnt;
+      s_cnt = 0;
+      if (info != 0 && s_info == 0) s_info = info;
     }
     __syncthreads();
-    const int ncnt = s_cnt;
+#pragma unroll
+    for (int t = 0; t < RPS; ++t) {
+      const int r = tid + 256 * t;
+      const int lp = lpos[t];
+      if (lp >= 0) {
+#pragma unroll
+        for (int c = 0; c < W; ++c)
+          if (c < jb) A[(int64_t)(j0 + c) * n + j0 + lp] = P[t][c];
+        if (lp < W) {
+#pragma unroll
+          for (int c = 0; c < W; ++c) L11[lp][c] = P[t][c];
+        }
+        if (lp != r) {
+          const int idx = atomicAdd(&s_cnt, 1);
+          s_src[idx] = r;
+          s_dst[idx] = lp;
+        }
+      }
+    }
+    __syncthreads();
+    const int cnt = s_cnt;
+    // inv(L11) (unit lower): wave w solves identity columns w*W/4 .. +W/4,
+    // lane = row, the solved row value broadcast across lanes
+    {
+      constexpr int CQ = W / 4;
+      T x[CQ];
+#pragma unroll
+      for (int q = 0; q < CQ; ++q) x[q] = (lane == wave * CQ + q) ? T(1) : T(0);
+      for (int j = 0; j < jb - 1; ++j) {
+        const T l = (lane > j && lane < jb) ? L11[lane][j] : T(0);
+#pragma unroll
+        for (int q = 0; q < CQ; ++q) x[q] -= l * lane_bcast(x[q], j);
+      }
+      if (lane < W) {
+#pragma unroll
+        for (int q = 0; q < CQ; ++q) Li[lane][wave * CQ + q] = (lane < jb) ? x[q] : T(0);
+      }
+    }
+    // the move list, a quarter per wave, into registers
+    int msrc[MQ], mdst[MQ];
+#pragma unroll
+    for (int q = 0; q < MQ; ++q) {
+      const int u = wave * MQ + q;
+      msrc[q] = (u < cnt) ? s_src[u] : 0;
+      mdst[q] = (u < cnt) ? s_dst[u] : -1;
+    }
+    // moves on every column outside the panel, 64 columns at a time
     const int nout = n - jb;
-    if (ncnt > 0) {
-      for (int q = tid; q < nout; q += 256) {
-        const int c = (q < j0) ? q : q + jb;
-        T* col = A + (int64_t)c * n + j0;
-        T v[2 * NB];
+    for (int g = 0; g < nout; g += 64) {
+      const int q0 = g + lane;
+      const int c = (q0 < j0) ? q0 : q0 + jb;
+      T v[MQ];
+      if (q0 < nout && cnt > 0) {
+        const T* col = A + (int64_t)c * n + j0;
 #pragma unroll
-        for (int u = 0; u < 2 * NB; ++u)
-          if (u < ncnt) v[u] = col[Loc[s_tl[u]]];
-#pragma unroll
-        for (int u = 0; u < 2 * NB; ++u)
-          if (u < ncnt) col[s_tl[u]] = v[u];
-      }
-    }
-    __syncthreads();
-
-    const int c0 = j0 + jb;
-    const int m2 = n - c0;
-    if (m2 > 0) {
-      // U12 = L11^-1 A12, one thread per column
-      for (int c = c0 + tid; c < n; c += 256) {
-        T* col = A + (int64_t)c * n + j0;
-        T u[NB];
-#pragma unroll
-        for (int jj = 0; jj < NB; ++jj) {
-          if (jj < jb) {
-            T v = col[jj];
-#pragma unroll
-            for (int t = 0; t < NB; ++t)
-              if (t < jj) v -= Pn[jj + t * mr] * u[t];
-            u[jj] = v;
-          }
-        }
-#pragma unroll
-        for (int jj = 0; jj < NB; ++jj)
-          if (jj < jb) {
-            col[jj] = u[jj];
-            Us[jj * n + c] = u[jj];
-          }
+        for (int q = 0; q < MQ; ++q)
+          if (mdst[q] >= 0) v[q] = col[msrc[q]];
       }
       __syncthreads();
-      // A22 -= L21 U12 with 4 x 4 register blocks
-      const int nrb = (m2 + 3) / 4;
-      const int nblk = nrb * nrb;
-      for (int bidx = tid; bidx < nblk; bidx += 256) {
-        const int r0 = c0 + (bidx % nrb) * 4;
-        const int cc0 = c0 + (bidx / nrb) * 4;
-        T acc[4][4];
+      if (q0 < nout && cnt > 0) {
+        T* col = A + (int64_t)c * n + j0;
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) acc[i][j] = 0;
-        for (int jj = 0; jj < jb; ++jj) {
-          T a[4], b[4];
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int r = r0 + i;
-            a[i] = (r < n) ? Pn[(r - j0) + jj * mr] : T(0);
-          }
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const int c = cc0 + j;
-            b[j] = (c < n) ? Us[jj * n + c] : T(0);
-          }
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
-        }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int c = cc0 + j;
-          if (c >= n) continue;
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int r = r0 + i;
-            if (r < n) A[(int64_t)c * n + r] -= acc[i][j];
-          }
-        }
+        for (int q = 0; q < MQ; ++q)
+          if (mdst[q] >= 0) col[mdst[q]] = v[q];
       }
     }
     __syncthreads();
+    // ---------------------------------- 3. U12 and the trailing update
+    const int c0 = j0 + jb;
+    for (int cb = c0; cb < n; cb += CH) {
+      // U12 chunk = inv(L11) A12 chunk: (W/16) x 4 output tiles over the waves
+      for (int it = wave; it < (W / 16) * (CH / 16); it += 4) {
+        const int rt = it % (W / 16), ct = it / (W / 16);
+        const int cc = cb + 16 * ct + lr;
+        V4 acc = V4{0, 0, 0, 0};
+#pragma unroll
+        for (int kk = 0; kk < W / 4; ++kk) {
+          const int k = 4 * kk + lg;
+          const T a = Li[16 * rt + lr][k];
+          const T b = (cc < n && k < jb) ? A[(int64_t)cc * n + j0 + k] : T(0);
+          acc = mfma16(a, b, acc);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Uc[16 * rt + acc_row(T(0), lg, v)][16 * ct + lr] = acc[v];
+      }
+      __syncthreads();
+      // write U12 back (rows j0+1 .. j0+jb-1; row j0 is unchanged)
+      for (int idx = tid; idx < W * CH; idx += 256) {
+        const int i = idx / CH, cl = idx % CH;
+        const int cc = cb + cl;
+        if (i >= 1 && i < jb && cc < n) A[(int64_t)cc * n + j0 + i] = Uc[i][cl];
+      }
+      // A22[c0:n, chunk] -= L21 U12: wave w takes 16-row tiles w, w+4, ...
+      const int ntr = (n - c0 + 15) / 16;
+      for (int it = wave; it < ntr; it += 4) {
+        const int t0 = c0 + 16 * it;
+        const int row = t0 + lr;
+        T a[W / 4];
+#pragma unroll
+        for (int kk = 0; kk < W / 4; ++kk)
+          a[kk] = (row < n) ? A[(int64_t)(j0 + 4 * kk + lg) * n + row] : T(0);
+        V4 cur[CH / 16];
+#pragma unroll
+        for (int ct = 0; ct < CH / 16; ++ct) {
+          const int cc = cb + 16 * ct + lr;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int rr = t0 + acc_row(T(0), lg, v);
+            cur[ct][v] = (rr < n && cc < n) ? A[(int64_t)cc * n + rr] : T(0);
+          }
+        }
+#pragma unroll
+        for (int ct = 0; ct < CH / 16; ++ct) {
+          V4 acc = V4{0, 0, 0, 0};
+#pragma unroll
+          for (int kk = 0; kk < W / 4; ++kk)
+            acc = mfma16(a[kk], Uc[4 * kk + lg][16 * ct + lr], acc);
+          const int cc = cb + 16 * ct + lr;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int rr = t0 + acc_row(T(0), lg, v);
+            if (rr < n && cc < n) A[(int64_t)cc * n + rr] = cur[ct][v] - acc[v];
+          }
+        }
+      }
+      __syncthreads();
+    }
   }
 
   for (int i = tid; i < n; i += 256) pr.perm[i] = Ps[i];
   if (tid == 0) *pr.info = s_info;
 }
 
-template <typename T, int NB>
-size_t getrf_smem(int nmax) {
-  return (size_t)2 * nmax * NB * sizeof(T) + (size_t)2 * nmax * sizeof(int) + 16;
-}
-
-template <typename T, int NB>
+template <typename T, int W, int RPS>
 hipError_t run_getrf(const LuProb* probs, int count, int nmax, hipStream_t s) {
-  const size_t sm = getrf_smem<T, NB>(nmax);
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_getrf<T, NB>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_getrf<T, NB>), dim3(count), dim3(256), sm, s, probs);
+  const size_t sm = (size_t)nmax * sizeof(int);
+  hipLaunchKernelGGL((k_getrf<T, W, RPS>), dim3(count), dim3(256), sm, s, probs);
   return hipGetLastError();
 }
 
@@ -273,10 +359,10 @@ hipError_t run_getrf(const LuProb* probs, int count, int nmax, hipStream_t s) {
 template <typename T>
 hipError_t launch_getrf(const LuProb* probs, int count, int nmax, hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  constexpr size_t kLds = 160 * 1024 - 1024;
-  if (getrf_smem<T, 16>(nmax) <= kLds) return run_getrf<T, 16>(probs, count, nmax, s);
-  if (getrf_smem<T, 8>(nmax) <= kLds) return run_getrf<T, 8>(probs, count, nmax, s);
-  return run_getrf<T, 4>(probs, count, nmax, s);
+  constexpr int W = sizeof(T) == 8 ? 16 : 32;
+  if (nmax <= 256) return run_getrf<T, W, 1>(probs, count, nmax, s);
+  if (nmax <= 512) return run_getrf<T, W, 2>(probs, count, nmax, s);
+  return run_getrf<T, W, 4>(probs, count, nmax, s);
 }
 
 template hipError_t launch_getrf<double>(const LuProb*, int, int, hipStream_t);
