@@ -194,9 +194,10 @@ int invaskit_last_error(invaskit_handle handle, char* buf, size_t n);
  * LU with partial pivoting (LAPACK getrf semantics: pivot = first row of
  * largest magnitude) of `count` square matrices of uneven order in one
  * launch -- the leaf LU of Algorithm 1 and the LU of the reduced systems.
- *  a        DEVICE, element type dtype; matrix i is n[i] x n[i] column-major
- *           with leading dimension n[i], starting at element a_offsets[i];
+ *  a        DEVICE, element type dtype; matrix i is n[i] x n[i] row-major
+ *           with row stride n[i], starting at element a_offsets[i];
  *           overwritten by L (unit lower, below the diagonal) and U.
+ *           Row-major storage makes each row interchange a contiguous move.
  *  a_offsets, n  HOST, count entries; 1 <= n[i] <= 1024.
  *  perm     DEVICE int32, sum(n) entries; matrix i's block starts at the sum
  *           of the preceding n: perm[j] = original row placed at row j.
@@ -208,8 +209,9 @@ int invaskit_getrf_batched(int32_t dtype, void* a, const int64_t* a_offsets,
                            int32_t* info, void* hip_stream);
 
 /*
- * Solve A_i X_i = B_i in place with the factors of invaskit_getrf_batched
- * (row permutation, unit-lower L, upper U).  b: DEVICE, element type dtype;
+ * Solve A_i X_i = B_i in place with the row-major factors of
+ * invaskit_getrf_batched (row permutation, unit-lower L, upper U); the
+ * inverses of the factors' 64 x 64 diagonal blocks are formed first.  b: DEVICE, element type dtype;
  * system i has nrhs[i] columns with leading dimension ldb[i] >= n[i] and
  * starts at element b_offsets[i].  a_offsets, n, nrhs, ldb, b_offsets: HOST.
  */

@@ -230,7 +230,8 @@ class Factorization:
 # ------------------------------------------------------ batched building blocks
 def getrf_batched(mats, dtype=torch.float64):
     """LU with partial pivoting of a list of square matrices (numpy or torch,
-    any size 1..1024) in one launch.  Returns (lu list, perm list, info)."""
+    any size 1..1024) in one launch.  Returns (packed row-major factors,
+    offsets, sizes, perm, info)."""
     ns = [int(m.shape[0]) for m in mats]
     offs = np.zeros(len(mats), dtype=np.int64)
     off = 0
@@ -238,7 +239,7 @@ def getrf_batched(mats, dtype=torch.float64):
     for i, m in enumerate(mats):
         offs[i] = off
         off += ns[i] * ns[i]
-        parts.append(torch.as_tensor(np.asarray(m)).to(dtype).t().contiguous().reshape(-1))
+        parts.append(torch.as_tensor(np.asarray(m)).to(dtype).contiguous().reshape(-1))  # row-major
     buf = torch.cat(parts).cuda()
     perm = torch.empty(sum(ns), dtype=torch.int32, device="cuda")
     info = torch.empty(len(mats), dtype=torch.int32, device="cuda")

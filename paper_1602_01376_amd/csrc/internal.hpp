@@ -41,7 +41,7 @@ struct Tile2 {
 };
 
 // In-place style triangular solve with an LU factor (row permutation, unit
-// lower L, upper U).  Right-hand-side rows [0, split) come from in0 (ldin0),
+// lower L, upper U; the factor is stored row-major).  Right-hand-side rows [0, split) come from in0 (ldin0),
 // rows [split, n) from in1 (ldin1); the solution goes to out (ldout).  Input
 // and output may be the same buffer.
 struct TrsmProb {
@@ -57,9 +57,9 @@ struct TrsmProb {
   int64_t ldout;
 };
 
-// One 64 x 64 diagonal block of an LU factor (rows/columns jb .. jb+63):
-// out receives inv(L_bb) then inv(U_bb), each 64 x 64 column-major, zero
-// beyond the matrix order.
+// One 64 x 64 diagonal block of a row-major LU factor (rows/columns
+// jb .. jb+63): out receives inv(L_bb) then inv(U_bb), each 64 x 64
+// row-major, zero beyond the matrix order.
 struct DiagInvProb {
   const void* lu;
   void* out;
@@ -87,7 +87,7 @@ struct EvalBlock {
   int32_t diag, pad;
 };
 
-// Reduced system Z (n = sr + sl, column-major) = [[I, pr], [pl, I]] with
+// Reduced system Z (n = sr + sl, row-major) = [[I, pr], [pl, I]] with
 // pr: sr x sl (ld sr) and pl: sl x sr (ld sl).
 struct ZformProb {
   void* Z;

@@ -3,8 +3,9 @@
 // (e:blocksmw)), one workgroup of four waves per matrix, every matrix of a
 // launch in one grid.
 //
-// Right-looking blocked algorithm with panels of W columns (32 in FP32, 16 in
-// FP64):
+// Matrices are stored row-major, so that a row interchange moves contiguous
+// memory.  Right-looking blocked algorithm with panels of W columns (32 in
+// FP32, 16 in FP64):
 //   1. Panel.  The panel's rows are held in registers across the workgroup
 //      (row r in thread r % 256, slot r / 256).  Rows never move; each carries
 //      its logical position.  Per column: every wave finds its candidate (the
@@ -17,7 +18,8 @@
 //      (at most 2W) form a move list that is applied to every other column
 //      (all loads of a column before its stores); inv(L11) is formed in LDS.
 //   3. For each chunk of 64 columns to the right: U12 = inv(L11) A12 and
-//      A22 -= L21 U12, both on the matrix cores (16 x 16 tiles).
+//      A22 -= L21 U12, both on the matrix cores (16 x 16 tiles), L21 read as
+//      16-byte row segments (see load_row_sigma).
 // perm[j] = original row now at row j; info = j+1 for the first zero or
 // non-finite pivot in column j (the column is left unscaled and the
 // factorization continues, as LAPACK does).
@@ -59,6 +61,37 @@ __device__ __forceinline__ double lane_bcast(double v, int l) {
 }
 __device__ __forceinline__ float lane_bcast(float v, int l) {
   return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+
+
+// Row-segment loads for an MFMA A operand from row-major memory.  The MFMA's
+// reduction order over K is free as long as both operands use the same
+// order; here lane group g (lane / 16) at MFMA step kk covers
+//   k = sigma(kk, g) = 4 VE (kk / VE) + VE g + kk % VE,   VE = 16 / sizeof(T),
+// so the four lane groups of a row read one contiguous 64-byte segment per
+// 16-byte vector load.  Elements at k >= klim read as zero.
+template <typename T>
+__device__ __forceinline__ constexpr int sigma_k(int kk, int g) {
+  constexpr int VE = 16 / sizeof(T);
+  return 4 * VE * (kk / VE) + VE * g + kk % VE;
+}
+template <typename T, int KQ>
+__device__ __forceinline__ void load_row_sigma(const T* __restrict__ rowp, int klim, int g,
+                                               T (&a)[KQ]) {
+  constexpr int VE = 16 / sizeof(T);
+  typedef T vec __attribute__((ext_vector_type(VE), aligned(sizeof(T))));
+#pragma unroll
+  for (int i = 0; i < KQ / VE; ++i) {
+    const int k0 = 4 * VE * i + VE * g;
+    if (k0 + VE <= klim) {
+      const vec v = *reinterpret_cast<const vec*>(rowp + k0);
+#pragma unroll
+      for (int e = 0; e < VE; ++e) a[VE * i + e] = v[e];
+    } else {
+#pragma unroll
+      for (int e = 0; e < VE; ++e) a[VE * i + e] = (k0 + e < klim) ? rowp[k0 + e] : T(0);
+    }
+  }
 }
 
 template <typename T>
@@ -119,7 +152,7 @@ __global__ __launch_bounds__(256) void k_getrf(const LuProb* __restrict__ probs)
       lpos[t] = (r < mr) ? r : -1;
 #pragma unroll
       for (int c = 0; c < W; ++c)
-        P[t][c] = (r < mr && c < jb) ? A[(int64_t)(j0 + c) * n + j0 + r] : T(0);
+        P[t][c] = (r < mr && c < jb) ? A[(int64_t)(j0 + r) * n + j0 + c] : T(0);
     }
     int info = 0;
     static_for<W>([&](auto JJ) {
@@ -221,7 +254,7 @@ __global__ __launch_bounds__(256) void k_getrf(const LuProb* __restrict__ probs)
       if (lp >= 0) {
 #pragma unroll
         for (int c = 0; c < W; ++c)
-          if (c < jb) A[(int64_t)(j0 + c) * n + j0 + lp] = P[t][c];
+          if (c < jb) A[(int64_t)(j0 + lp) * n + j0 + c] = P[t][c];
         if (lp < W) {
 #pragma unroll
           for (int c = 0; c < W; ++c) L11[lp][c] = P[t][c];
@@ -260,24 +293,23 @@ __global__ __launch_bounds__(256) void k_getrf(const LuProb* __restrict__ probs)
       msrc[q] = (u < cnt) ? s_src[u] : 0;
       mdst[q] = (u < cnt) ? s_dst[u] : -1;
     }
-    // moves on every column outside the panel, 64 columns at a time
+    // moves on every column outside the panel: 64 consecutive columns per
+    // step (coalesced row segments), all loads before any store
     const int nout = n - jb;
     for (int g = 0; g < nout; g += 64) {
       const int q0 = g + lane;
       const int c = (q0 < j0) ? q0 : q0 + jb;
       T v[MQ];
       if (q0 < nout && cnt > 0) {
-        const T* col = A + (int64_t)c * n + j0;
 #pragma unroll
         for (int q = 0; q < MQ; ++q)
-          if (mdst[q] >= 0) v[q] = col[msrc[q]];
+          if (mdst[q] >= 0) v[q] = A[(int64_t)(j0 + msrc[q]) * n + c];
       }
       __syncthreads();
       if (q0 < nout && cnt > 0) {
-        T* col = A + (int64_t)c * n + j0;
 #pragma unroll
         for (int q = 0; q < MQ; ++q)
-          if (mdst[q] >= 0) col[mdst[q]] = v[q];
+          if (mdst[q] >= 0) A[(int64_t)(j0 + mdst[q]) * n + c] = v[q];
       }
     }
     __syncthreads();
@@ -293,7 +325,7 @@ __global__ __launch_bounds__(256) void k_getrf(const LuProb* __restrict__ probs)
         for (int kk = 0; kk < W / 4; ++kk) {
           const int k = 4 * kk + lg;
           const T a = Li[16 * rt + lr][k];
-          const T b = (cc < n && k < jb) ? A[(int64_t)cc * n + j0 + k] : T(0);
+          const T b = (cc < n && k < jb) ? A[(int64_t)(j0 + k) * n + cc] : T(0);
           acc = mfma16(a, b, acc);
         }
 #pragma unroll
@@ -304,17 +336,16 @@ __global__ __launch_bounds__(256) void k_getrf(const LuProb* __restrict__ probs)
       for (int idx = tid; idx < W * CH; idx += 256) {
         const int i = idx / CH, cl = idx % CH;
         const int cc = cb + cl;
-        if (i >= 1 && i < jb && cc < n) A[(int64_t)cc * n + j0 + i] = Uc[i][cl];
+        if (i >= 1 && i < jb && cc < n) A[(int64_t)(j0 + i) * n + cc] = Uc[i][cl];
       }
       // A22[c0:n, chunk] -= L21 U12: wave w takes 16-row tiles w, w+4, ...
       const int ntr = (n - c0 + 15) / 16;
       for (int it = wave; it < ntr; it += 4) {
         const int t0 = c0 + 16 * it;
         const int row = t0 + lr;
-        T a[W / 4];
-#pragma unroll
-        for (int kk = 0; kk < W / 4; ++kk)
-          a[kk] = (row < n) ? A[(int64_t)(j0 + 4 * kk + lg) * n + row] : T(0);
+        constexpr int KG = W / 4;
+        T a[KG];
+        load_row_sigma(A + (int64_t)(row < n ? row : 0) * n + j0, row < n ? W : 0, lg, a);
         V4 cur[CH / 16];
 #pragma unroll
         for (int ct = 0; ct < CH / 16; ++ct) {
@@ -322,20 +353,20 @@ __global__ __launch_bounds__(256) void k_getrf(const LuProb* __restrict__ probs)
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int rr = t0 + acc_row(T(0), lg, v);
-            cur[ct][v] = (rr < n && cc < n) ? A[(int64_t)cc * n + rr] : T(0);
+            cur[ct][v] = (rr < n && cc < n) ? A[(int64_t)rr * n + cc] : T(0);
           }
         }
 #pragma unroll
         for (int ct = 0; ct < CH / 16; ++ct) {
           V4 acc = V4{0, 0, 0, 0};
 #pragma unroll
-          for (int kk = 0; kk < W / 4; ++kk)
-            acc = mfma16(a[kk], Uc[4 * kk + lg][16 * ct + lr], acc);
+          for (int kk = 0; kk < KG; ++kk)
+            acc = mfma16(a[kk], Uc[sigma_k<T>(kk, lg)][16 * ct + lr], acc);
           const int cc = cb + 16 * ct + lr;
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int rr = t0 + acc_row(T(0), lg, v);
-            if (rr < n && cc < n) A[(int64_t)cc * n + rr] = cur[ct][v] - acc[v];
+            if (rr < n && cc < n) A[(int64_t)rr * n + cc] = cur[ct][v] - acc[v];
           }
         }
       }

@@ -1,4 +1,5 @@
-// Small element-wise kernels: reduced-system assembly (eq. (e:blocksmw)),
+// Small element-wise kernels: reduced-system assembly (eq. (e:blocksmw),
+// written row-major as the batched LU expects),
 // precision conversions and the FP64 vector steps of iterative refinement.
 #include "internal.hpp"
 
@@ -13,7 +14,7 @@ __global__ __launch_bounds__(256) void k_zform(const ZformProb* __restrict__ pro
   const TV* __restrict__ pr = static_cast<const TV*>(p.pr);
   const TV* __restrict__ pl = static_cast<const TV*>(p.pl);
   for (int64_t idx = threadIdx.x; idx < (int64_t)n * n; idx += 256) {
-    const int i = (int)(idx % n), j = (int)(idx / n);
+    const int i = (int)(idx / n), j = (int)(idx % n);  // row-major
     TZ v;
     if (i < p.sr) {
       v = (j < p.sr) ? TZ(i == j) : (TZ)pr[(int64_t)(j - p.sr) * p.sr + i];

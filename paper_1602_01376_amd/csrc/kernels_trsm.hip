@@ -2,10 +2,12 @@
 // leaf solves of Algorithm 2 and the reduced-system solves of eq.
 // (e:blocksmw)), every system of a launch in one grid.
 //
+// Factors are stored row-major (as the batched LU writes them).
+//
 // k_diag_inv runs once per factorization: for every 64 x 64 diagonal block
 // of every factor it forms the inverses of the unit-lower block of L and of
 // the upper block of U (column by column against the identity, one wave per
-// 16 columns, the diagonal of U inverted once).
+// 16 columns, the diagonal of U inverted once), stored row-major.
 //
 // k_getrs: one workgroup (4 waves) takes 16 right-hand-side columns of one
 // system; the permuted right-hand sides live in LDS (row stride 17 to spread
@@ -14,7 +16,7 @@
 //   diagonal block:  X_b = inv(L_bb) X_b   (inv(U_bb) going back),
 //   off-diagonal:    X_rows -= L[rows, block] X_b   (U[rows, block] going back),
 // in 16 x 16 output tiles with K = 64, the factor operands streamed from
-// global memory with a tile's 16 loads in flight together.
+// global memory as 16-byte row segments (see load_row_sigma).
 // TZ is the type of the factors and of the arithmetic, TV the type of the
 // right-hand sides in memory.  KIND only separates the kernel names of the
 // three uses (leaf panels of the factorization, reduced systems, solve).
@@ -50,6 +52,37 @@ __device__ __forceinline__ f32x4 mfma16(float a, float b, f32x4 c) {
 __device__ __forceinline__ constexpr int acc_row(double, int g, int v) { return g + 4 * v; }
 __device__ __forceinline__ constexpr int acc_row(float, int g, int v) { return 4 * g + v; }
 
+
+// Row-segment loads for an MFMA A operand from row-major memory.  The MFMA's
+// reduction order over K is free as long as both operands use the same
+// order; here lane group g (lane / 16) at MFMA step kk covers
+//   k = sigma(kk, g) = 4 VE (kk / VE) + VE g + kk % VE,   VE = 16 / sizeof(T),
+// so the four lane groups of a row read one contiguous 64-byte segment per
+// 16-byte vector load.  Elements at k >= klim read as zero.
+template <typename T>
+__device__ __forceinline__ constexpr int sigma_k(int kk, int g) {
+  constexpr int VE = 16 / sizeof(T);
+  return 4 * VE * (kk / VE) + VE * g + kk % VE;
+}
+template <typename T, int KQ>
+__device__ __forceinline__ void load_row_sigma(const T* __restrict__ rowp, int klim, int g,
+                                               T (&a)[KQ]) {
+  constexpr int VE = 16 / sizeof(T);
+  typedef T vec __attribute__((ext_vector_type(VE), aligned(sizeof(T))));
+#pragma unroll
+  for (int i = 0; i < KQ / VE; ++i) {
+    const int k0 = 4 * VE * i + VE * g;
+    if (k0 + VE <= klim) {
+      const vec v = *reinterpret_cast<const vec*>(rowp + k0);
+#pragma unroll
+      for (int e = 0; e < VE; ++e) a[VE * i + e] = v[e];
+    } else {
+#pragma unroll
+      for (int e = 0; e < VE; ++e) a[VE * i + e] = (k0 + e < klim) ? rowp[k0 + e] : T(0);
+    }
+  }
+}
+
 __device__ __forceinline__ double lane_bcast(double v, int l) {
   const long long b = __builtin_bit_cast(long long, v);
   const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
@@ -73,7 +106,7 @@ __global__ __launch_bounds__(256) void k_diag_inv(const DiagInvProb* __restrict_
   __shared__ TZ rdiag[NBK];
   for (int idx = tid; idx < NBK * NBK; idx += 256) {
     const int r = idx % NBK, c = idx / NBK;
-    B[c][r] = (r < nb && c < nb) ? LU[(int64_t)(jb + c) * n + jb + r] : TZ(0);
+    B[c][r] = (r < nb && c < nb) ? LU[(int64_t)(jb + r) * n + jb + c] : TZ(0);
   }
   __syncthreads();
   if (tid < NBK) rdiag[tid] = (tid < nb) ? TZ(1) / B[tid][tid] : TZ(0);
@@ -90,7 +123,7 @@ __global__ __launch_bounds__(256) void k_diag_inv(const DiagInvProb* __restrict_
       for (int q = 0; q < CQ; ++q) x[q] -= l * lane_bcast(x[q], j);
     }
 #pragma unroll
-    for (int q = 0; q < CQ; ++q) out[(wave * CQ + q) * NBK + lane] = (lane < nb) ? x[q] : TZ(0);
+    for (int q = 0; q < CQ; ++q) out[lane * NBK + wave * CQ + q] = (lane < nb) ? x[q] : TZ(0);
   }
   // inv(U): U X = I, U upper
   {
@@ -108,7 +141,7 @@ __global__ __launch_bounds__(256) void k_diag_inv(const DiagInvProb* __restrict_
     }
 #pragma unroll
     for (int q = 0; q < CQ; ++q)
-      out[NBK * NBK + (wave * CQ + q) * NBK + lane] = (lane < nb) ? x[q] : TZ(0);
+      out[NBK * NBK + lane * NBK + wave * CQ + q] = (lane < nb) ? x[q] : TZ(0);
   }
 }
 
@@ -160,12 +193,11 @@ __global__ __launch_bounds__(256) void k_getrs(const TrsmProb* __restrict__ prob
       {
         const TZ* D = DI + (int64_t)(2 * b + (fwd ? 0 : 1)) * NBK * NBK;
         TZ a[NBK / 4];
-#pragma unroll
-        for (int kk = 0; kk < NBK / 4; ++kk) a[kk] = D[(4 * kk + lg) * NBK + 16 * wave + lr];
+        load_row_sigma(D + (16 * wave + lr) * NBK, NBK, lg, a);
         V4 acc = V4{0, 0, 0, 0};
 #pragma unroll
         for (int kk = 0; kk < NBK / 4; ++kk) {
-          const int k = 4 * kk + lg;
+          const int k = sigma_k<TZ>(kk, lg);
           const TZ bb = (k < nb) ? X[(jb + k) * RTP + lr] : TZ(0);
           acc = mfma16(a[kk], bb, acc);
         }
@@ -185,15 +217,11 @@ __global__ __launch_bounds__(256) void k_getrs(const TrsmProb* __restrict__ prob
         const int row = r0 + item * 16 + lr;
         const bool rin = row < r1;
         TZ a[NBK / 4];
-#pragma unroll
-        for (int kk = 0; kk < NBK / 4; ++kk) {
-          const int j = 4 * kk + lg;
-          a[kk] = (rin && j < nb) ? LU[(int64_t)(jb + j) * n + row] : TZ(0);
-        }
+        load_row_sigma(LU + (int64_t)(rin ? row : 0) * n + jb, rin ? nb : 0, lg, a);
         V4 acc = V4{0, 0, 0, 0};
 #pragma unroll
         for (int kk = 0; kk < NBK / 4; ++kk) {
-          const int j = 4 * kk + lg;
+          const int j = sigma_k<TZ>(kk, lg);
           const TZ bb = (j < nb) ? X[(jb + j) * RTP + lr] : TZ(0);
           acc = mfma16(a[kk], bb, acc);
         }

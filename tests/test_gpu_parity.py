@@ -74,7 +74,7 @@ def test_batched_lu_and_solve(bind, dtype):
     pm = perm.cpu().numpy()
     po = 0
     for i, (n, A) in enumerate(zip(sizes, mats)):
-        LU = lu_all[offs[i]:offs[i] + n * n].reshape(n, n).T
+        LU = lu_all[offs[i]:offs[i] + n * n].reshape(n, n)  # row-major factors
         L = np.tril(LU, -1) + np.eye(n)
         U = np.triu(LU)
         p = pm[po:po + n]
