@@ -167,10 +167,12 @@ int invaskit_matvec(invaskit_handle handle, const double* x, int64_t nrhs, int64
 int invaskit_device_bytes(invaskit_handle handle, size_t* bytes);
 
 /*
- * Milliseconds spent in the phases of the last factor (HIP events, stream
- * time): [0] leaf blocks + LU, [1] skeleton blocks, [2] leaf solves,
- * [3] leaf projections, [4] skeleton sweep, [5] deferred corrections,
- * [6] reduced systems + LU, [7] total.  Writes min(n, 8) values.
+ * Milliseconds spent in the phases of the last factor (HIP events on the
+ * factor's stream): [0] leaf block evaluation, [1] leaf LU, [2] inverses of
+ * the factors' 64 x 64 diagonal blocks (leaves), [3] skeleton blocks,
+ * [4] leaf solves, [5] leaf projections, [6] skeleton sweep, [7] deferred
+ * corrections, [8] reduced systems (assembly, LU, diagonal-block
+ * inverses), [9] total.  Writes min(n, 10) values.
  */
 int invaskit_phase_times(invaskit_handle handle, double* ms, int32_t n);
 

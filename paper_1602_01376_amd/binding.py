@@ -204,10 +204,11 @@ class Factorization:
         return y[:, 0] if vec else y
 
     def phase_times(self):
-        out = (C.c_double * 8)()
-        _check(_lib.invaskit_phase_times(self._handle, out, 8), self._handle)
-        keys = ["leaf_lu", "skeleton_blocks", "leaf_solves", "leaf_projections",
-                "skeleton_sweep", "deferred_corrections", "reduced_systems", "total"]
+        out = (C.c_double * 10)()
+        _check(_lib.invaskit_phase_times(self._handle, out, 10), self._handle)
+        keys = ["leaf_blocks", "leaf_lu", "leaf_diag_inverses", "skeleton_blocks", "leaf_solves",
+                "leaf_projections", "skeleton_sweep", "deferred_corrections", "reduced_systems",
+                "total"]
         return dict(zip(keys, list(out)))
 
     def device_bytes(self):

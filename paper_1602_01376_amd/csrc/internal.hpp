@@ -112,10 +112,30 @@ struct MvTile {
   int32_t seg0, nseg, pad;
 };
 
+// Workgroup -> tile mapping that keeps runs of consecutive tiles on one XCD.
+// The hardware places workgroup b on XCD b % 8; each XCD has its own L2.
+// Tile tables list the tiles of one problem (one leaf, one node)
+// consecutively, so a run of kXcdRun tiles on one XCD shares the problem's
+// operands in that L2.  The runs themselves are dealt round-robin, so the
+// XCDs stay balanced when tile cost drifts along the table (leaf sizes follow
+// the tree's random splits).  Tiles past the last whole round of runs keep
+// the hardware order.  Bijective for any grid size.
+constexpr int kXcds = 8;
+constexpr int kXcdRun = 8;
+__device__ __host__ __forceinline__ int xcd_tile(int b, int nb) {
+  const int full = nb / (kXcds * kXcdRun) * (kXcds * kXcdRun);
+  if (b >= full) return b;
+  const int x = b % kXcds, slot = b / kXcds;
+  return ((slot / kXcdRun) * kXcds + x) * kXcdRun + slot % kXcdRun;
+}
+
 // ---------------------------------------------------------------- launchers
+// shape: kGemmSquare (64 x 64 tiles) or kGemmNarrow (128 x 32, for N <= 32)
+constexpr int kGemmSquare = 0;
+constexpr int kGemmNarrow = 1;
 template <typename T>
 hipError_t launch_gemm(const GemmProb* probs, const GemmSeg* segs, const Tile3* tiles,
-                       int ntiles, hipStream_t s);
+                       int ntiles, int shape, hipStream_t s);
 
 // kind: 0 leaf panels of the factorization, 1 reduced systems, 2 solve phase
 template <typename TZ, typename TV>
@@ -125,15 +145,14 @@ int getrs_cols_per_tile(bool tz64);
 template <typename TZ>
 hipError_t launch_diag_inv(const DiagInvProb* probs, int count, hipStream_t s);
 
+// kind: 0 leaf blocks, 1 reduced systems
 template <typename T>
-hipError_t launch_getrf(const LuProb* probs, int count, int nmax, hipStream_t s);
+hipError_t launch_getrf(const LuProb* probs, int count, int nmax, int kind, hipStream_t s);
 
 template <typename PT, typename T>
 hipError_t launch_eval(const PT* X, int d, double h, double shift, const EvalBlock* blocks,
                        const Tile3* tiles, int ntiles, hipStream_t s);
 constexpr int kEvalTile = 64;
-constexpr int kGemmTileM = 64;
-constexpr int kGemmTileN = 64;
 
 template <typename TZ, typename TV>
 hipError_t launch_zform(const ZformProb* probs, int count, hipStream_t s);

@@ -51,6 +51,7 @@ constexpr int kMaxLeaf = 1024;
 constexpr int kMaxSkel = 512;
 constexpr int kMaxDepth = 24;
 constexpr int kEvents = 8;
+constexpr int kPhases = 10;  // see invaskit_phase_times
 
 // -------------------------------------------------------------- small utils
 struct DevBuf {
@@ -83,9 +84,11 @@ const T* at(const DevBuf& b, size_t off) {
 }
 
 // One batched launch, described by table offsets into a table buffer.
+// A grouped GEMM launch: products with N <= 32 run on 128 x 32 tiles, the
+// others on 64 x 64 tiles (two kernels over one problem table).
 struct GemmL {
-  size_t probs = 0, segs = 0, tiles = 0;
-  int ntiles = 0;
+  size_t probs = 0, segs = 0, tiles = 0, tiles_n = 0;
+  int ntiles = 0, ntiles_n = 0;
 };
 struct TrsmL {
   size_t probs = 0, tiles = 0;
@@ -95,7 +98,7 @@ struct TrsmL {
 };
 struct LuL {
   size_t probs = 0;
-  int count = 0, nmax = 0, t64 = 1;
+  int count = 0, nmax = 0, t64 = 1, kind = 0;
 };
 struct DinvL {
   size_t probs = 0;
@@ -198,7 +201,7 @@ struct invaskit_handle_s {
   FactorPlan fp;
   std::map<int, std::unique_ptr<SolvePlan>> solve_plans;
   std::map<int, std::unique_ptr<MatvecPlan>> mv_plans;
-  double phase_ms[8] = {0};
+  double phase_ms[kPhases] = {0};
   hipEvent_t ev[kEvents + 2] = {};
   bool have_events = false;
   std::string err;
@@ -377,15 +380,15 @@ int validate(H* h, const invaskit_problem* pb, double lambda, const invaskit_opt
 }
 
 // ----------------------------------------------------------- table builders
-void gemm_tiles(std::vector<Tile3>& tiles, int prob, int M, int N) {
-  for (int tn = 0; tn < (N + kGemmTileN - 1) / kGemmTileN; ++tn)
-    for (int tm = 0; tm < (M + kGemmTileM - 1) / kGemmTileM; ++tm) tiles.push_back({prob, tm, tn});
+void gemm_tiles(std::vector<Tile3>& tiles, int prob, int M, int N, int bm, int bn) {
+  for (int tn = 0; tn < (N + bn - 1) / bn; ++tn)
+    for (int tm = 0; tm < (M + bm - 1) / bm; ++tm) tiles.push_back({prob, tm, tn});
 }
 
 struct GemmBuilder {
   std::vector<GemmProb> probs;
   std::vector<GemmSeg> segs;
-  std::vector<Tile3> tiles;
+  std::vector<Tile3> tiles, tiles_n;
   int begin(void* C, int64_t ldc, int M, int N, double alpha, double beta) {
     GemmProb p{};
     p.C = C;
@@ -397,7 +400,12 @@ struct GemmBuilder {
     p.alpha = alpha;
     p.beta = beta;
     probs.push_back(p);
-    if (M > 0 && N > 0) gemm_tiles(tiles, (int)probs.size() - 1, M, N);
+    if (M > 0 && N > 0) {
+      if (N <= 32)
+        gemm_tiles(tiles_n, (int)probs.size() - 1, M, N, 128, 32);
+      else
+        gemm_tiles(tiles, (int)probs.size() - 1, M, N, 64, 64);
+    }
     return (int)probs.size() - 1;
   }
   void seg(const void* A, int64_t lda, bool a_rm, const void* B, int64_t ldb, int k) {
@@ -418,6 +426,8 @@ struct GemmBuilder {
     l.segs = ar.add(segs);
     l.tiles = ar.add(tiles);
     l.ntiles = (int)tiles.size();
+    l.tiles_n = ar.add(tiles_n);
+    l.ntiles_n = (int)tiles_n.size();
     return l;
   }
 };
@@ -747,6 +757,7 @@ int plan_factor(H* h) {
     lul.count = (int)zl.size();
     lul.nmax = nmax;
     lul.t64 = h->zis64[jl];
+    lul.kind = 1;
     DinvL& dl = fp.zdinv[jl];
     dl.probs = ar.add(zd);
     dl.count = (int)zd.size();
@@ -784,12 +795,16 @@ int plan_factor(H* h) {
 
 // ---------------------------------------------------------------- launching
 hipError_t run_gemm(const DevBuf& tb, const GemmL& l, bool f64, hipStream_t s) {
-  if (l.ntiles == 0) return hipSuccess;
-  if (f64)
-    return launch_gemm<double>(at<GemmProb>(tb, l.probs), at<GemmSeg>(tb, l.segs),
-                               at<Tile3>(tb, l.tiles), l.ntiles, s);
-  return launch_gemm<float>(at<GemmProb>(tb, l.probs), at<GemmSeg>(tb, l.segs),
-                            at<Tile3>(tb, l.tiles), l.ntiles, s);
+  const GemmProb* p = at<GemmProb>(tb, l.probs);
+  const GemmSeg* g = at<GemmSeg>(tb, l.segs);
+  hipError_t e = hipSuccess;
+  if (l.ntiles > 0)
+    e = f64 ? launch_gemm<double>(p, g, at<Tile3>(tb, l.tiles), l.ntiles, kGemmSquare, s)
+            : launch_gemm<float>(p, g, at<Tile3>(tb, l.tiles), l.ntiles, kGemmSquare, s);
+  if (e == hipSuccess && l.ntiles_n > 0)
+    e = f64 ? launch_gemm<double>(p, g, at<Tile3>(tb, l.tiles_n), l.ntiles_n, kGemmNarrow, s)
+            : launch_gemm<float>(p, g, at<Tile3>(tb, l.tiles_n), l.ntiles_n, kGemmNarrow, s);
+  return e;
 }
 
 hipError_t run_trsm(const DevBuf& tb, const TrsmL& l, hipStream_t s) {
@@ -803,8 +818,8 @@ hipError_t run_trsm(const DevBuf& tb, const TrsmL& l, hipStream_t s) {
 
 hipError_t run_lu(const DevBuf& tb, const LuL& l, hipStream_t s) {
   if (l.count == 0) return hipSuccess;
-  if (l.t64) return launch_getrf<double>(at<LuProb>(tb, l.probs), l.count, l.nmax, s);
-  return launch_getrf<float>(at<LuProb>(tb, l.probs), l.count, l.nmax, s);
+  if (l.t64) return launch_getrf<double>(at<LuProb>(tb, l.probs), l.count, l.nmax, l.kind, s);
+  return launch_getrf<float>(at<LuProb>(tb, l.probs), l.count, l.nmax, l.kind, s);
 }
 
 hipError_t run_dinv(const DevBuf& tb, const DinvL& l, hipStream_t s) {
@@ -874,30 +889,33 @@ int run_factor(H* h) {
   mark(-1);
   if (!f64 && h->P32.p && h->p_off[h->nn] > 0)
     STEP(launch_convert_f64_f32(h->P64, static_cast<float*>(h->P32.p), h->p_off[h->nn], s));
+  mark(-1);
   STEP(run_eval(h, tb, fp.leaf_eval, h->lam, s));
-  STEP(run_lu(tb, fp.leaf_lu, s));
-  STEP(run_dinv(tb, fp.leaf_dinv, s));
   mark(0);
+  STEP(run_lu(tb, fp.leaf_lu, s));
+  mark(1);
+  STEP(run_dinv(tb, fp.leaf_dinv, s));
+  mark(2);
   if (h->L > 0) {
     STEP(run_eval(h, tb, fp.panels, 0.0, s));
-    mark(1);
-    STEP(run_trsm(tb, fp.leaf_trsm, s));
-    mark(2);
-    STEP(run_gemm(tb, fp.leaf_proj, f64, s));
     mark(3);
+    STEP(run_trsm(tb, fp.leaf_trsm, s));
+    mark(4);
+    STEP(run_gemm(tb, fp.leaf_proj, f64, s));
+    mark(5);
     for (int j = h->L - 1; j >= 0; --j) {
       STEP(run_zform(tb, fp.zform[j], s));
       STEP(run_lu(tb, fp.zlu[j], s));
       STEP(run_dinv(tb, fp.zdinv[j], s));
-      mark(6);
+      mark(8);
       if (j >= 1) {
         STEP(run_trsm(tb, fp.zsolve[j], s));
         STEP(run_gemm(tb, fp.pgemm[j], f64, s));
-        mark(4);
+        mark(6);
       }
     }
     for (int k = h->L - 1; k >= 1; --k) STEP(run_gemm(tb, fp.deferred[k], f64, s));
-    mark(5);
+    mark(7);
   }
   STEP(hipStreamSynchronize(s));
   for (double& v : h->phase_ms) v = 0.0;
@@ -909,7 +927,7 @@ int run_factor(H* h) {
   {
     float ms = 0.f;
     if (marks.size() > 1 && hipEventElapsedTime(&ms, marks.front(), marks.back()) == hipSuccess)
-      h->phase_ms[7] = ms;
+      h->phase_ms[kPhases - 1] = ms;
   }
   cleanup();
 #undef STEP
@@ -1340,7 +1358,7 @@ int invaskit_device_bytes(invaskit_handle h, size_t* bytes) {
 
 int invaskit_phase_times(invaskit_handle h, double* ms, int32_t n) {
   if (!h || !ms) return fail_h(h, INVASKIT_E_ARG, "handle and ms are required");
-  for (int i = 0; i < std::min(n, 8); ++i) ms[i] = h->phase_ms[i];
+  for (int i = 0; i < std::min(n, kPhases); ++i) ms[i] = h->phase_ms[i];
   return INVASKIT_OK;
 }
 
@@ -1400,8 +1418,8 @@ int invaskit_getrf_batched(int32_t dtype, void* a, const int64_t* a_offsets, con
   if (rc) return rc;
   hipError_t e = hipMemcpy(t.p, probs.data(), sizeof(LuProb) * count, hipMemcpyHostToDevice);
   if (e == hipSuccess)
-    e = (dtype == INVASKIT_F64) ? launch_getrf<double>(static_cast<LuProb*>(t.p), count, nmax, s)
-                                : launch_getrf<float>(static_cast<LuProb*>(t.p), count, nmax, s);
+    e = (dtype == INVASKIT_F64) ? launch_getrf<double>(static_cast<LuProb*>(t.p), count, nmax, 1, s)
+                                : launch_getrf<float>(static_cast<LuProb*>(t.p), count, nmax, 1, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   t.release();
   if (e != hipSuccess) return fail_h(nullptr, INVASKIT_E_HIP, hipGetErrorString(e));

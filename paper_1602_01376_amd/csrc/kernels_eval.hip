@@ -30,7 +30,7 @@ __global__ __launch_bounds__(256) void k_eval(const PT* __restrict__ X, int d, d
   __shared__ double xr[DC][ET + 1];
   __shared__ double xc[DC][ET + 1];
   __shared__ int64_t cidx[ET];
-  const Tile3 t = tiles[blockIdx.x];
+  const Tile3 t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
   const EvalBlock b = blocks[t.prob];
   const int r0 = t.tm * ET, c0 = t.tn * ET;
   const int tid = threadIdx.x;
@@ -108,7 +108,7 @@ __global__ __launch_bounds__(MB) void k_mv_eval(const PT* __restrict__ X, int d,
                                                 int nrhs) {
   __shared__ double sx[MS][DM + 1];
   __shared__ double sw[MS][RC];
-  const MvTile t = tiles[blockIdx.x];
+  const MvTile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
   const int tid = threadIdx.x;
   const bool active = tid < t.rows;
   const int64_t i = t.row0 + tid;

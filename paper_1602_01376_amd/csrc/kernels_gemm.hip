@@ -7,8 +7,10 @@
 // operands live at unrelated addresses: that is how the deferred correction
 // gathers the per-level y blocks of a leaf's ancestors without copying them.
 //
-// Tile: 64 x 64 outputs per workgroup of 4 waves; each wave owns a 32 x 32
-// quadrant computed as 2 x 2 MFMA 16x16x4 blocks (f64 or f32 accumulate).
+// Tiles: BM x BN outputs per workgroup of 4 waves, each wave a 32 x 32 block
+// computed as 2 x 2 MFMA 16x16x4 blocks (f64 or f32 accumulate).  Two shapes:
+// 64 x 64, and 128 x 32 for products with at most 32 columns (the deferred
+// corrections and skeleton projections, whose N is a skeleton rank).
 // K is staged through LDS in steps of 16.  The MFMA is issued with the B
 // fragment as its first operand so that the accumulator layout puts 16
 // consecutive lanes on 16 consecutive rows of column-major C (coalesced
@@ -46,28 +48,29 @@ __device__ __forceinline__ f32x4 mfma16(float a, float b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-constexpr int BM = kGemmTileM;
-constexpr int BN = kGemmTileN;
 constexpr int BK = 16;
 constexpr int PAD = 1;
 
-template <typename T>
+template <typename T, int BM, int BN>
 __global__ __launch_bounds__(256) void k_gemm(const GemmProb* __restrict__ probs,
                                               const GemmSeg* __restrict__ segs,
                                               const Tile3* __restrict__ tiles) {
   using V4 = typename Vec4<T>::type;
+  constexpr int WN = BN / 32;              // waves along N
+  constexpr int NA = BM * BK / 256;        // A elements per thread
+  constexpr int NB = BN * BK / 256;        // B elements per thread
   __shared__ T As[BK][BM + PAD];
   __shared__ T Bs[BK][BN + PAD];
 
-  const Tile3 t = tiles[blockIdx.x];
+  const Tile3 t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
   const GemmProb P = probs[t.prob];
   const int m0 = t.tm * BM;
   const int n0 = t.tn * BN;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int wm = (wave >> 1) * 32;
-  const int wn = (wave & 1) * 32;
+  const int wm = (wave / WN) * 32;
+  const int wn = (wave % WN) * 32;
   const int lr = lane & 15;  // fragment row / column
   const int lk = lane >> 4;  // fragment k
 
@@ -82,10 +85,10 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmProb* __restrict__ probs
     const T* __restrict__ A = static_cast<const T*>(g.A);
     const T* __restrict__ B = static_cast<const T*>(g.B);
     for (int k0 = 0; k0 < g.k; k0 += BK) {
-      T av[4], bv[4];
+      T av[NA], bv[NB];
       // A tile: BM x BK
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < NA; ++q) {
         const int idx = tid + q * 256;
         int i, kk;
         if (g.a_rm) {
@@ -103,7 +106,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmProb* __restrict__ probs
       }
       // B tile: BK x BN (column-major source)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < NB; ++q) {
         const int idx = tid + q * 256;
         const int kk = idx % BK;
         const int j = idx / BK;
@@ -112,12 +115,16 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmProb* __restrict__ probs
       }
       __syncthreads();
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < NA; ++q) {
         const int idx = tid + q * 256;
         if (g.a_rm)
           As[idx % BK][idx / BK] = av[q];
         else
           As[idx / BM][idx % BM] = av[q];
+      }
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        const int idx = tid + q * 256;
         Bs[idx % BK][idx / BK] = bv[q];
       }
       __syncthreads();
@@ -163,15 +170,18 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmProb* __restrict__ probs
 
 template <typename T>
 hipError_t launch_gemm(const GemmProb* probs, const GemmSeg* segs, const Tile3* tiles,
-                       int ntiles, hipStream_t s) {
+                       int ntiles, int shape, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gemm<T>, dim3(ntiles), dim3(256), 0, s, probs, segs, tiles);
+  if (shape == kGemmNarrow)
+    hipLaunchKernelGGL((k_gemm<T, 128, 32>), dim3(ntiles), dim3(256), 0, s, probs, segs, tiles);
+  else
+    hipLaunchKernelGGL((k_gemm<T, 64, 64>), dim3(ntiles), dim3(256), 0, s, probs, segs, tiles);
   return hipGetLastError();
 }
 
-template hipError_t launch_gemm<double>(const GemmProb*, const GemmSeg*, const Tile3*, int,
+template hipError_t launch_gemm<double>(const GemmProb*, const GemmSeg*, const Tile3*, int, int,
                                         hipStream_t);
-template hipError_t launch_gemm<float>(const GemmProb*, const GemmSeg*, const Tile3*, int,
+template hipError_t launch_gemm<float>(const GemmProb*, const GemmSeg*, const Tile3*, int, int,
                                        hipStream_t);
 
 }  // namespace invaskit

@@ -22,7 +22,8 @@
 //      16-byte row segments (see load_row_sigma).
 // perm[j] = original row now at row j; info = j+1 for the first zero or
 // non-finite pivot in column j (the column is left unscaled and the
-// factorization continues, as LAPACK does).
+// factorization continues, as LAPACK does).  KIND only separates the kernel
+// names of the two uses (leaf blocks, reduced systems).
 #include <cmath>
 #include <utility>
 
@@ -112,7 +113,7 @@ __device__ __forceinline__ void static_for(F&& f) {
   static_for_impl(f, std::make_integer_sequence<int, N>{});
 }
 
-template <typename T, int W, int RPS>
+template <typename T, int W, int RPS, int KIND>
 __global__ __launch_bounds__(256) void k_getrf(const LuProb* __restrict__ probs) {
   using V4 = typename Vec4<T>::type;
   constexpr int MQ = 2 * W / 4;  // move-list entries per wave
@@ -378,25 +379,30 @@ __global__ __launch_bounds__(256) void k_getrf(const LuProb* __restrict__ probs)
   if (tid == 0) *pr.info = s_info;
 }
 
-template <typename T, int W, int RPS>
+template <typename T, int W, int RPS, int KIND>
 hipError_t run_getrf(const LuProb* probs, int count, int nmax, hipStream_t s) {
   const size_t sm = (size_t)nmax * sizeof(int);
-  hipLaunchKernelGGL((k_getrf<T, W, RPS>), dim3(count), dim3(256), sm, s, probs);
+  hipLaunchKernelGGL((k_getrf<T, W, RPS, KIND>), dim3(count), dim3(256), sm, s, probs);
   return hipGetLastError();
+}
+
+template <typename T, int KIND>
+hipError_t pick(const LuProb* probs, int count, int nmax, hipStream_t s) {
+  constexpr int W = sizeof(T) == 8 ? 16 : 32;
+  if (nmax <= 256) return run_getrf<T, W, 1, KIND>(probs, count, nmax, s);
+  if (nmax <= 512) return run_getrf<T, W, 2, KIND>(probs, count, nmax, s);
+  return run_getrf<T, W, 4, KIND>(probs, count, nmax, s);
 }
 
 }  // namespace
 
 template <typename T>
-hipError_t launch_getrf(const LuProb* probs, int count, int nmax, hipStream_t s) {
+hipError_t launch_getrf(const LuProb* probs, int count, int nmax, int kind, hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  constexpr int W = sizeof(T) == 8 ? 16 : 32;
-  if (nmax <= 256) return run_getrf<T, W, 1>(probs, count, nmax, s);
-  if (nmax <= 512) return run_getrf<T, W, 2>(probs, count, nmax, s);
-  return run_getrf<T, W, 4>(probs, count, nmax, s);
+  return kind == 0 ? pick<T, 0>(probs, count, nmax, s) : pick<T, 1>(probs, count, nmax, s);
 }
 
-template hipError_t launch_getrf<double>(const LuProb*, int, int, hipStream_t);
-template hipError_t launch_getrf<float>(const LuProb*, int, int, hipStream_t);
+template hipError_t launch_getrf<double>(const LuProb*, int, int, int, hipStream_t);
+template hipError_t launch_getrf<float>(const LuProb*, int, int, int, hipStream_t);
 
 }  // namespace invaskit

@@ -150,7 +150,7 @@ template <typename TZ, typename TV, int KIND>
 __global__ __launch_bounds__(256) void k_getrs(const TrsmProb* __restrict__ probs,
                                                const Tile2* __restrict__ tiles) {
   using V4 = typename Vec4<TZ>::type;
-  const Tile2 t = tiles[blockIdx.x];
+  const Tile2 t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
   const TrsmProb pr = probs[t.prob];
   const int n = pr.n;
   const int c0 = t.tn * RT;
