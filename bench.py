@@ -19,8 +19,11 @@ HBM before the timed region.
 from __future__ import annotations
 
 import argparse
+import csv
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -37,6 +40,98 @@ PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+# ---------------------------------------------------------------- HBM traffic
+# Measured HBM bytes per launch come from two rocprofv3 counter runs of this
+# script (FETCH_SIZE, then WRITE_SIZE), scaled by what the same counters read
+# for a plain copy of known size in the same run (the FP64 copy of the
+# right-hand side, N * nrhs * 8 bytes each way).  They are stored with the
+# digest of the kernel's sources and reported only while that digest holds.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_susy_1m.json")
+CSRC = os.path.join(ROOT, "paper_1602_01376_amd", "csrc")
+COPY_KERNEL = "k_copy_cols<double, double>"
+# phases whose time is one launch of a uniquely named kernel: name pattern
+# (t = element type) and the source file that holds it
+PHASE_KERNEL = {
+    "leaf_lu": (r"k_getrf<{t}, \d+, \d+, 0>", "kernels_lu.hip"),
+    "leaf_solves": (r"k_getrs<{t}, {t}, 0>", "kernels_trsm.hip"),
+}
+
+
+def source_digest(src):
+    h = hashlib.sha256()
+    for f in (src, "internal.hpp"):
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def short_kernel_name(name):
+    name = re.sub(r"^void ", "", name)
+    name = name.replace("invaskit::(anonymous namespace)::", "").replace("invaskit::", "")
+    depth, out = 0, []
+    for ch in name:  # drop the argument list, keep template arguments
+        if ch == "(" and depth == 0:
+            break
+        depth += ch == "<"
+        depth -= ch == ">"
+        out.append(ch)
+    return "".join(out).strip()
+
+
+def read_counter_csv(path, counter):
+    per = {}
+    with open(path) as fh:
+        for r in csv.DictReader(fh):
+            if r["Counter_Name"] != counter:
+                continue
+            per.setdefault(short_kernel_name(r["Kernel_Name"]), []).append(float(r["Counter_Value"]))
+    return per
+
+
+def write_traffic(fetch_csv, write_csv, copy_bytes, command):
+    fetch = read_counter_csv(fetch_csv, "FETCH_SIZE")
+    write = read_counter_csv(write_csv, "WRITE_SIZE")
+    kib = copy_bytes / 1024.0
+    f_scale = kib / np.mean(fetch[COPY_KERNEL])
+    w_scale = kib / np.mean(write[COPY_KERNEL])
+    entries = {}
+    for phase, (pat, src) in PHASE_KERNEL.items():
+        for t in ("float", "double"):
+            rx = re.compile(pat.format(t=t) + "$")
+            names = [k for k in fetch if rx.match(k)]
+            for k in names:
+                fk, wk = float(np.mean(fetch[k])), float(np.mean(write.get(k, [0.0])))
+                entries[k] = {"phase": phase, "dispatches": len(fetch[k]),
+                              "fetch_kib": fk, "write_kib": wk,
+                              "bytes": float((fk * f_scale + wk * w_scale) * 1024.0),
+                              "source": src, "sha256": source_digest(src)}
+    out = {"command": command, "calibration": {
+        "kernel": COPY_KERNEL, "bytes_each_way": copy_bytes,
+        "fetch_kib": float(np.mean(fetch[COPY_KERNEL])),
+        "write_kib": float(np.mean(write[COPY_KERNEL])),
+        "fetch_scale": float(f_scale), "write_scale": float(w_scale)}, "kernels": entries}
+    os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(out, fh, indent=1)
+    return out
+
+
+def traffic_for(phase, t):
+    """Scaled HBM bytes per launch of the phase's kernel, or None when no
+    counters were taken or the kernel's sources changed since."""
+    if phase not in PHASE_KERNEL or not os.path.exists(TRAFFIC_FILE):
+        return None
+    pat, src = PHASE_KERNEL[phase]
+    rx = re.compile(pat.format(t=t) + "$")
+    with open(TRAFFIC_FILE) as fh:
+        data = json.load(fh)
+    digest = source_digest(src)
+    for name, e in data.get("kernels", {}).items():
+        if rx.match(name) and e.get("sha256") == digest:
+            return e["bytes"]
+    return None
 
 
 # ----------------------------------------------------------- work accounting
@@ -180,7 +275,17 @@ def main():
     ap.add_argument("--depth", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["mixed", "fp64", "both"], default="both")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the HBM traffic record from two rocprofv3 counter runs of "
+                         "this script (FETCH_SIZE, WRITE_SIZE) and exit")
+    ap.add_argument("--traffic-command", default="", help="the counter command, recorded")
     args = ap.parse_args()
+    if args.traffic_from:
+        n = args.n or (1 << 20)
+        out = write_traffic(*args.traffic_from, copy_bytes=8 * n * args.nrhs,
+                            command=args.traffic_command)
+        print(json.dumps(out, indent=1))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: the multi-GPU sharding of the tree is a design "
               "note, not part of this build (use --gpus 1)", file=sys.stderr)
@@ -242,6 +347,7 @@ def main():
     head = results.get("mixed") or results["fp64"]
     esize = 4 if "mixed" in results else 8
     dtype = "f32" if "mixed" in results else "f64"
+    ctype = "float" if dtype == "f32" else "double"
     work = algorithmic_work(pb, esize)
     # dominant kernel: the single-launch phase with the largest measured time
     ph = head["phase_ms"]
@@ -249,15 +355,16 @@ def main():
     dom = max(cand, key=cand.get)
     wk = work[dom]
     per_launch_ms = ph[dom] / max(wk["launches"], 1)
+    traffic = traffic_for(dom, ctype) if (args.n is None and args.nrhs == 1) else None
     if wk["flops"] > 0:
         achieved = wk["flops"] / wk["launches"] / (per_launch_ms * 1e-3) / 1e12
         roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[dtype],
-                "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS[dtype], "traffic": None,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS[dtype], "traffic": traffic,
                 "kernel": dom, "launches": wk["launches"], "avg_launch_ms": per_launch_ms}
     else:
         achieved = wk["bytes"] / wk["launches"] / (per_launch_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dom,
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom,
                 "launches": wk["launches"], "avg_launch_ms": per_launch_ms}
     out = {
         "metric": METRIC,

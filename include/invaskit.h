@@ -116,9 +116,9 @@ int invaskit_default_options(invaskit_options* opt);
  * Factor lambda*I + K~ (Algorithm 1, Factorize, done level by level
  * bottom-up): LU with partial pivoting of every leaf block
  * lambda*I + K_{aa}; for every level k = L..1 the skeleton blocks
- * K_{c, sibling~} (eq. e:offdiag-askit) solved through c's subtree
+ * K_{c, sibling~} (eq. (7)) solved through c's subtree
  * (Algorithm 2) to give W; the reduced systems
- * [[I, P_{r~r} W_{r l~}], [P_{l~l} W_{l r~}, I]] of eq. (e:blocksmw) and
+ * [[I, P_{r~r} W_{r l~}], [P_{l~l} W_{l r~}, I]] of eq. (11) and
  * their LU.  lambda enters only the leaf diagonal blocks.
  *
  * Validates every input on the host before any launch (E_ARG).  Allocates
@@ -223,7 +223,7 @@ int invaskit_getrs_batched(int32_t dtype, const void* a, const int64_t* a_offset
                            const int64_t* ldb, int32_t count, void* hip_stream);
 
 /*
- * Gaussian kernel blocks (eq. e:gaussian): out_i[r, c] =
+ * Gaussian kernel blocks (eq. (1)): out_i[r, c] =
  * K(x[row0_i + r], x[col_i(c)]) + (diag_i && r == c ? shift : 0), where
  * col_i(c) = cols[cols_offsets[i] + c].  Squared distances are formed by
  * direct differences in FP64.  points: DEVICE n x d row-major of
@@ -241,7 +241,7 @@ int invaskit_kernel_blocks(int32_t points_dtype, const void* points, int32_t d, 
 /*
  * Grouped GEMM on the matrix cores, C_i = beta*C_i + alpha*A_i B_i for
  * `count` products of different shapes in one launch (the level-synchronous
- * GEMMs of the SMW updates, eq. (e:blocksmw), and of eq. (e:innerid)).
+ * GEMMs of the SMW updates, eq. (11), and of eq. (12)).
  * a, b, c: DEVICE, element type dtype.  Product i: A_i is m[i] x k[i],
  * column-major with leading dimension lda[i] (row-major when a_rowmajor[i]
  * != 0, lda = row stride); B_i is k[i] x n[i] column-major (ldb[i]); C_i is

@@ -10,17 +10,17 @@ numbering: root 0, children of i are 2i+1 and 2i+2).
 What it computes, following the paper (Yu, March, Xiao, Biros, "INV-ASKIT:
 A Parallel Fast Direct Solver for Kernel Matrices"):
 
-  gaussian          the kernel of eq. (e:gaussian), by direct differences
+  gaussian          the kernel of eq. (1), by direct differences
   factorize         Algorithm 1 (post-order Factorize), with the block forms
-                    of eqs. (e:hodlr) and (e:blocksmw) and the full P of
-                    eq. (e:innerid)
+                    of eqs. (10) and (11) and the full P of
+                    eq. (12)
   solve             Algorithm 2 (Solve), w = v - W Z V v per internal node
   matvec            the Skeletonize upward pass and the Evaluate traversal of
                     Section II-B with separation "i not in alpha", which is
-                    exactly lambda*I + K~ (eqs. (e:partitioning-node),
-                    (e:offdiag-askit))
+                    exactly lambda*I + K~ (eqs. (3),
+                    (7))
   dense_assemble    K~ written out block by block from eqs.
-                    (e:partitioning-node), (e:offdiag-askit), (e:uv-askit)
+                    (3), (7), (8)
 
 Readings where the paper is silent: lambda sits only on the diagonal of the
 leaf blocks (the paper calls the extension to lambda*I + K trivial); the
@@ -78,7 +78,7 @@ def _P(pb, node):
 
 # --------------------------------------------------------------------- kernel
 def gaussian(XA, XB, h):
-    """K(x, y) = exp(-||x - y||^2 / (2 h^2)), eq. (e:gaussian), in FP64 with
+    """K(x, y) = exp(-||x - y||^2 / (2 h^2)), eq. (1), in FP64 with
     squared distances taken by direct differences."""
     A = np.asarray(XA, dtype=np.float64)
     B = np.asarray(XB, dtype=np.float64)
@@ -113,15 +113,15 @@ def factorize(pb, lam):
 
     Leaf: LU with partial pivoting of lambda*I + K_aa.  Internal node a with
     children l, r: factor both children; form K_{l r~}, K_{r l~} and the full
-    P_{l~ l}, P_{r~ r} (eq. (e:innerid)); W_{l r~} = Solve(l, K_{l r~}) and
+    P_{l~ l}, P_{r~ r} (eq. (12)); W_{l r~} = Solve(l, K_{l r~}) and
     W_{r l~} = Solve(r, K_{r l~}); LU of the reduced system
-    [[I, P_{r~r} W_{r l~}], [P_{l~l} W_{l r~}, I]] of eq. (e:blocksmw).
+    [[I, P_{r~r} W_{r l~}], [P_{l~l} W_{l r~}, I]] of eq. (11).
     """
     F = Factorization(pb, lam)
     X = pb.X
 
     def full_p(node):
-        # eq. (e:innerid): P_{a~ a} = P_{a~[l~ r~]} blkdiag(P_{l~ l}, P_{r~ r});
+        # eq. (12): P_{a~ a} = P_{a~[l~ r~]} blkdiag(P_{l~ l}, P_{r~ r});
         # leaves store P_{a~ a} directly.
         if _is_leaf(pb, node):
             return _P(pb, node)
@@ -165,7 +165,7 @@ def solve_node(F, node, U):
     to the rows of U owned by `node` (U has one row per point of the node).
 
     Leaf: LU solve.  Internal: v_l = Solve(l, U_l), v_r = Solve(r, U_r);
-    w = v - W Z V v with the blocks of eq. (e:blocksmw):
+    w = v - W Z V v with the blocks of eq. (11):
     t = [P_{r~r} v_r ; P_{l~l} v_l], y = Z^-1 t,
     w_l = v_l - W_{l r~} y[:s_r], w_r = v_r - W_{r l~} y[s_r:].
     """
@@ -265,8 +265,8 @@ def dense_assemble(pb):
     """K~ as a dense N x N matrix (tiny N only): leaf diagonal blocks are
     exact, and for every internal node with children l, r the blocks are
     K~[l, r] = K_{l r~} P_{r~ r} and K~[r, l] = K_{r l~} P_{l~ l}
-    (eqs. (e:offdiag-askit), (e:uv-askit)), with the full P built level by
-    level as stated in eq. (e:innerid)."""
+    (eqs. (7), (8)), with the full P built level by
+    level as stated in eq. (12)."""
     N = pb.X.shape[0]
     X = pb.X
     Kt = np.zeros((N, N))
@@ -300,7 +300,7 @@ def dense_solve(pb, lam, b):
 
 def panel_blocks(pb, level):
     """For every node c at `level` (>= 1), the skeleton block
-    K(X_c, X_{sibling~}) of eq. (e:offdiag-askit); returns {node: block}."""
+    K(X_c, X_{sibling~}) of eq. (7); returns {node: block}."""
     out = {}
     for c in range((1 << level) - 1, (1 << (level + 1)) - 1):
         sib = c + 1 if c % 2 == 1 else c - 1

@@ -1,31 +1,36 @@
 // libinvaskit host side: input validation, memory plan, level-synchronous
 // launch schedule and the C ABI of include/invaskit.h.
 //
-// Factorization (Algorithm 1, done bottom-up with one batched launch per
-// step and tree level instead of a recursion):
-//   F1  every leaf block lambda*I + K_aa is evaluated and LU-factored;
-//   for k = L .. 1, for every node c at level k at once:
-//   F2a the skeleton block B_c = K(X_c, X_{c'~}) (c' = sibling) is written
-//       into the leaf-major W storage, split into the row blocks of c's
-//       leaves;
-//   F2b every leaf applies its LU to its rows of B_c;
-//   F2c every leaf projects its rows onto its skeleton, p = P_{leaf} v;
-//   F2d skeleton-level sweep over the levels L-1 .. k of c's subtree:
-//       y_b = Z_b^-1 [p_right; p_left] and p_b = P_{b~[l~ r~]} [y_l~; y_r~];
-//   F2e deferred correction of every leaf row block,
-//       W_c rows -= sum_{j > k} W^{(j)} rows * y-blocks of the ancestors;
-//   F2f the reduced systems of the level-(k-1) parents are assembled from
-//       the children's projections p_c = P_{c~ c} W_c;
-//   F2g and LU-factored.
+// Factorization (Algorithm 1), bottom-up, each step one batched launch over
+// every node it touches instead of a recursion.  Notation: L = depth, c' =
+// sibling of c, anc_k(i) = level-k ancestor, W^(k) = the rows of
+// (lambda I + K~_cc)^-1 K(X_c, X_{c'~}) for the level-k nodes c.
+//   F1  every leaf block lambda*I + K_aa is evaluated, LU-factored, and the
+//       64 x 64 diagonal blocks of its factors are inverted;
+//   F2  for every leaf and every level k = L .. 1 at once, the leaf's rows of
+//       the skeleton block K(X_c, X_{c'~}), c = anc_k(leaf), are written
+//       into the leaf-major W storage;
+//   F3  every leaf applies its LU to all those columns and projects them
+//       onto its skeleton, p = P_{leaf~ leaf} v;
+//   F4  wavefront over the levels j = L-1 .. 0: the reduced systems
+//       Z_a = I + V_a W_a of the level-j nodes are assembled from their
+//       children's projections (eq. (11)), LU-factored and their diagonal
+//       blocks inverted; then, for j >= 1, the skeleton sweep of level j for
+//       every factor level k <= j at once:
+//       y_a = Z_a^-1 [p_r; p_l] and p_a = P_{a~[l~ r~]} [y_l; y_r];
+//   F5  deferred corrections, k = L-1 .. 1: every leaf's level-k columns
+//       v -= sum_{j > k} W^(j) rows * (the y-block of anc_{j-1} paired with
+//       anc_j's sibling skeleton), one grouped GEMM per level.
 //
-// F2c-F2e replace the per-node "w = v - W Z V v" of Algorithm 2 by an
+// F3-F5 replace the per-node "w = v - W Z V v" of Algorithm 2 by an
 // algebraically identical schedule: after that update the children's
 // skeleton projections of w equal y itself (V w = V v - V W y = y because
 // (I + V W) y = V v), so the projection needed one level up is
-// P_{b~[l~ r~]} y (eq. (e:innerid)) and never touches N-sized data; the
-// N-sized corrections of all levels are then applied in one grouped GEMM per
-// leaf.  The solve (Algorithm 2) uses the same four steps with the user's
-// right-hand sides.
+// P_{b~[l~ r~]} y (eq. (12)) and never touches N-sized data; the N-sized
+// corrections are applied afterwards, once per level.  The solve
+// (Algorithm 2) runs the same steps with the user's right-hand sides: leaf
+// solves, leaf projections, the sweep for j = L-1 .. 0, and one grouped
+// GEMM x = v - sum_j W^(j) rows * y-blocks.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

@@ -1,8 +1,8 @@
-// Gaussian kernel evaluation (eq. (e:gaussian)), K(x,y) = exp(-|x-y|^2/(2h^2)).
+// Gaussian kernel evaluation (eq. (1)), K(x,y) = exp(-|x-y|^2/(2h^2)).
 //
 // k_eval writes blocks of K: the leaf blocks lambda*I + K_{aa} of
 // Algorithm 1 and the skeleton blocks K_{c, sibling~} of eq.
-// (e:offdiag-askit), straight into the factor storage.  A workgroup computes
+// (7), straight into the factor storage.  A workgroup computes
 // a 64 x 64 tile: the 64 row points and 64 column points are staged through
 // LDS in chunks of 8 coordinates and every thread accumulates a 4 x 4 block
 // of squared distances by direct differences in FP64 (no |x|^2+|y|^2-2x.y

@@ -2,7 +2,7 @@
 //
 // One launch runs many independent products C = beta*C + alpha*sum_s A_s B_s
 // of different shapes (the level-synchronous GEMMs of the SMW updates,
-// eq. (e:blocksmw), and the interpolation products of eq. (e:innerid) and
+// eq. (11), and the interpolation products of eq. (12) and
 // the Skeletonize pass).  A product may have several K segments whose B
 // operands live at unrelated addresses: that is how the deferred correction
 // gathers the per-level y blocks of a leaf's ancestors without copying them.

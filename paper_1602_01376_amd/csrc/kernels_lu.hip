@@ -1,6 +1,6 @@
 // Batched LU with partial pivoting for square matrices of uneven order (the
 // leaf LU of Algorithm 1 and the LU of the reduced systems of eq.
-// (e:blocksmw)), one workgroup of four waves per matrix, every matrix of a
+// (11)), one workgroup of four waves per matrix, every matrix of a
 // launch in one grid.
 //
 // Matrices are stored row-major, so that a row interchange moves contiguous

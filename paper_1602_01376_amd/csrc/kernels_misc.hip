@@ -1,4 +1,4 @@
-// Small element-wise kernels: reduced-system assembly (eq. (e:blocksmw),
+// Small element-wise kernels: reduced-system assembly (eq. (11),
 // written row-major as the batched LU expects),
 // precision conversions and the FP64 vector steps of iterative refinement.
 #include "internal.hpp"

@@ -1,6 +1,6 @@
 // Batched multi-right-hand-side solves with LU factors of uneven order (the
 // leaf solves of Algorithm 2 and the reduced-system solves of eq.
-// (e:blocksmw)), every system of a launch in one grid.
+// (11)), every system of a launch in one grid.
 //
 // Factors are stored row-major (as the batched LU writes them).
 //

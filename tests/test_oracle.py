@@ -1,14 +1,14 @@
 """Pins of the FP64 CPU oracle against what the paper and the mathematics fix.
 
 Every check here is independent of the oracle's own code path:
-  * the kernel against its closed form (eq. e:gaussian) written out with math.exp;
+  * the kernel against its closed form (eq. (1)) written out with math.exp;
   * the whole solve against dense LAPACK on the assembled lambda*I + K~;
   * the exact case s = |node| (every P a permutation, K~ = K) against a dense
     solve with K built entry by entry;
   * one leaf (L = 0) = dense LU; one split (L = 1) = an explicit
-    Sherman-Morrison-Woodbury step (eq. e:smw) with D, U, V of eq. e:uv-askit;
+    Sherman-Morrison-Woodbury step (eq. (5)) with D, U, V of eq. (8);
   * the residual bound ||(lambda I + K~) x - b|| / ||b|| <= 1e-12 and the
-    eps_I invariant of eq. (e:error);
+    eps_I invariant of eq. (17);
   * a zero pivot (duplicated point, lambda = 0) is reported.
 """
 import math
@@ -40,7 +40,7 @@ def test_kernel_closed_form():
     y = np.array([[3.0, 4.0]])
     assert oracle.gaussian(x, x, 0.7)[0, 0] == 1.0
     assert abs(oracle.gaussian(x, y, 5.0)[0, 0] - math.exp(-0.5)) < 1e-16
-    # squared distance 2 h^2 gives exp(-1); the 1/2 of eq. (e:gaussian) matters
+    # squared distance 2 h^2 gives exp(-1); the 1/2 of eq. (1) matters
     z = np.array([[1.0, 1.0]])
     assert abs(oracle.gaussian(x, z, 1.0)[0, 0] - math.exp(-1.0)) < 1e-16
     rng = np.random.default_rng(0)
@@ -115,7 +115,7 @@ def test_one_split_is_one_woodbury_step():
     Dinv = np.linalg.inv(D)
     W = Dinv @ U
     Z = np.linalg.inv(np.eye(2) + V @ W)
-    x_smw = (np.eye(6) - W @ Z @ V) @ Dinv @ b          # eq. (e:smw)
+    x_smw = (np.eye(6) - W @ Z @ V) @ Dinv @ b          # eq. (5)
     x_dense = np.linalg.solve(D + U @ V, b)
     np.testing.assert_allclose(x_smw, x_dense, rtol=1e-12)
     F = oracle.factorize(pb, lam)
