@@ -198,11 +198,14 @@ int invaskit_last_error(invaskit_handle handle, char* buf, size_t n);
  * launch -- the leaf LU of Algorithm 1 and the LU of the reduced systems.
  *  a        DEVICE, element type dtype; matrix i is n[i] x n[i] row-major
  *           with row stride n[i], starting at element a_offsets[i];
- *           overwritten by L (unit lower, below the diagonal) and U.
- *           Row-major storage makes each row interchange a contiguous move.
+ *           overwritten by the factors of P A = L U with rows left in place:
+ *           logical row j of the packed L\U (L unit lower below the
+ *           diagonal, U on and above it) is stored in row perm[j].  No row
+ *           is moved; invaskit_getrs_batched reads this layout.
  *  a_offsets, n  HOST, count entries; 1 <= n[i] <= 1024.
  *  perm     DEVICE int32, sum(n) entries; matrix i's block starts at the sum
- *           of the preceding n: perm[j] = original row placed at row j.
+ *           of the preceding n: perm[j] = original row pivoted to position j
+ *           (also the storage row of the factors' row j).
  *  info     DEVICE int32, count entries: 0, or j+1 for the first zero or
  *           non-finite pivot in column j.
  */

@@ -62,6 +62,7 @@ struct TrsmProb {
 // row-major, zero beyond the matrix order.
 struct DiagInvProb {
   const void* lu;
+  const int32_t* perm;  // factor row j is stored in row perm[j]
   void* out;
   int32_t n, jb;
 };

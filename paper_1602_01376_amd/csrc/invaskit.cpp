@@ -658,6 +658,7 @@ int plan_factor(H* h) {
       for (int jb = 0; jb < m; jb += kDiagBlock) {
         DiagInvProb d{};
         d.lu = b.out;
+        d.perm = p.perm;
         d.out = offv(h->dinvLeaf.p, h->dleaf_off[j] + (jb / kDiagBlock) * kDB2, es);
         d.n = m;
         d.jb = jb;
@@ -720,6 +721,7 @@ int plan_factor(H* h) {
       for (int jb = 0; jb < h->z[a]; jb += kDiagBlock) {
         DiagInvProb d{};
         d.lu = h->Z(a);
+        d.perm = zpm + h->zperm_off[a];
         d.out = offv(const_cast<void*>(h->DZ(a)), (jb / kDiagBlock) * kDB2, zes);
         d.n = h->z[a];
         d.jb = jb;
@@ -1461,6 +1463,7 @@ int invaskit_getrs_batched(int32_t dtype, const void* a, const int64_t* a_offset
     for (int jb = 0; jb < n[i]; jb += kDiagBlock) {
       DiagInvProb d{};
       d.lu = ai;
+      d.perm = perm + poff;
       d.out = static_cast<unsigned char*>(di) + (jb / kDiagBlock) * kDB2 * es;
       d.n = n[i];
       d.jb = jb;

@@ -1,29 +1,32 @@
 // Batched LU with partial pivoting for square matrices of uneven order (the
-// leaf LU of Algorithm 1 and the LU of the reduced systems of eq.
-// (11)), one workgroup of four waves per matrix, every matrix of a
-// launch in one grid.
+// leaf LU of Algorithm 1 and the LU of the reduced systems of eq. (11)), one
+// workgroup of four waves per matrix, every matrix of a launch in one grid.
 //
-// Matrices are stored row-major, so that a row interchange moves contiguous
-// memory.  Right-looking blocked algorithm with panels of W columns (32 in
-// FP32, 16 in FP64):
-//   1. Panel.  The panel's rows are held in registers across the workgroup
-//      (row r in thread r % 256, slot r / 256).  Rows never move; each carries
-//      its logical position.  Per column: every wave finds its candidate (the
-//      first row of largest magnitude: LAPACK getrf semantics) and the owning
-//      lane publishes that row in LDS; one barrier; every thread picks the
-//      winner of the four, exchanges the two logical positions, scales by the
-//      pivot's reciprocal and updates its rows -- one barrier per column (the
-//      candidate rows are double-buffered).
-//   2. The panel goes back to memory in logical order; the rows that moved
-//      (at most 2W) form a move list that is applied to every other column
-//      (all loads of a column before its stores); inv(L11) is formed in LDS.
+// Matrices are row-major and rows never move: P A = L U is stored with
+// logical row j of the packed L\U (unit-lower L below the diagonal, U on and
+// above) in physical row perm[j], which is also the original row that the
+// pivoting placed at position j.  Consumers read factor rows through perm,
+// which costs nothing extra for row-wise operand loads and removes every
+// row interchange from the factorization.  Right-looking blocked algorithm
+// with panels of W columns (32 in FP32, 16 in FP64):
+//   1. Panel.  The panel's rows are gathered into registers across the
+//      workgroup (logical row j0 + r in thread r % 256, slot r / 256), each
+//      carrying its logical position.  Per column: every wave finds its
+//      candidate (the first row of largest magnitude: LAPACK getrf
+//      semantics) and the owning lane publishes that row in LDS; one
+//      barrier; every thread picks the winner of the four, exchanges the two
+//      logical positions, scales by the pivot's reciprocal and updates its
+//      rows -- one barrier per column (the candidate rows are
+//      double-buffered).
+//   2. The panel goes back to the rows it came from, the permutation takes
+//      the panel's logical positions, and inv(L11) is formed in LDS.
 //   3. For each chunk of 64 columns to the right: U12 = inv(L11) A12 and
 //      A22 -= L21 U12, both on the matrix cores (16 x 16 tiles), L21 read as
 //      16-byte row segments (see load_row_sigma).
-// perm[j] = original row now at row j; info = j+1 for the first zero or
-// non-finite pivot in column j (the column is left unscaled and the
-// factorization continues, as LAPACK does).  KIND only separates the kernel
-// names of the two uses (leaf blocks, reduced systems).
+// info = j+1 for the first zero or non-finite pivot in column j (the column
+// is left unscaled and the factorization continues, as LAPACK does).  KIND
+// only separates the kernel names of the two uses (leaf blocks, reduced
+// systems).
 #include <cmath>
 #include <utility>
 
@@ -116,7 +119,6 @@ __device__ __forceinline__ void static_for(F&& f) {
 template <typename T, int W, int RPS, int KIND>
 __global__ __launch_bounds__(256) void k_getrf(const LuProb* __restrict__ probs) {
   using V4 = typename Vec4<T>::type;
-  constexpr int MQ = 2 * W / 4;  // move-list entries per wave
   const LuProb pr = probs[blockIdx.x];
   T* __restrict__ A = static_cast<T*>(pr.a);
   const int n = pr.n;
@@ -126,15 +128,13 @@ __global__ __launch_bounds__(256) void k_getrf(const LuProb* __restrict__ probs)
   const int lr = lane & 15, lg = lane >> 4;
 
   extern __shared__ __align__(16) unsigned char smem[];
-  int* Ps = reinterpret_cast<int*>(smem);  // permutation, n entries
+  int* Ps = reinterpret_cast<int*>(smem);  // logical row -> physical row, n entries
   __shared__ T s_row[2][4][W];             // each wave's candidate pivot row
   __shared__ T s_bv[2][4];
   __shared__ int s_bl[2][4];
   __shared__ T L11[W][W + 1];
   __shared__ T Li[W][W + 1];              // inv(L11), row-major
   __shared__ T Uc[W][CH];                 // U12 chunk
-  __shared__ int s_src[2 * W], s_dst[2 * W];
-  __shared__ int s_cnt;
   __shared__ int s_info;
 
   for (int i = tid; i < n; i += 256) Ps[i] = i;
@@ -146,14 +146,15 @@ __global__ __launch_bounds__(256) void k_getrf(const LuProb* __restrict__ probs)
     const int mr = n - j0;
     // ------------------------------------------------------------ 1. panel
     T P[RPS][W];
-    int lpos[RPS];
+    int lpos[RPS], ph[RPS];
 #pragma unroll
     for (int t = 0; t < RPS; ++t) {
       const int r = tid + 256 * t;
       lpos[t] = (r < mr) ? r : -1;
+      ph[t] = (r < mr) ? Ps[j0 + r] : 0;
 #pragma unroll
       for (int c = 0; c < W; ++c)
-        P[t][c] = (r < mr && c < jb) ? A[(int64_t)(j0 + r) * n + j0 + c] : T(0);
+        P[t][c] = (r < mr && c < jb) ? A[(int64_t)ph[t] * n + j0 + c] : T(0);
     }
     int info = 0;
     static_for<W>([&](auto JJ) {
@@ -216,11 +217,6 @@ __global__ __launch_bounds__(256) void k_getrf(const LuProb* __restrict__ probs)
       const T pv = prow[jj];
       const bool ok = (pv != T(0)) && isfinite(pv);
       if (!ok && info == 0) info = j0 + jj + 1;
-      if (tid == 0) {
-        const int a = Ps[j0 + jj];
-        Ps[j0 + jj] = Ps[j0 + pl];
-        Ps[j0 + pl] = a;
-      }
 #pragma unroll
       for (int t = 0; t < RPS; ++t) {
         if (lpos[t] == pl)
@@ -242,33 +238,24 @@ __global__ __launch_bounds__(256) void k_getrf(const LuProb* __restrict__ probs)
       }
       }
     });
-    // --------------------------- 2. write back, move list, inverse of L11
-    if (tid == 0) {
-      s_cnt = 0;
-      if (info != 0 && s_info == 0) s_info = info;
-    }
-    __syncthreads();
+    // ---------- 2. write back in place, new logical order, inverse of L11
+    // (every thread read its Ps entries before the panel's first barrier)
+    if (tid == 0 && info != 0 && s_info == 0) s_info = info;
 #pragma unroll
     for (int t = 0; t < RPS; ++t) {
-      const int r = tid + 256 * t;
       const int lp = lpos[t];
       if (lp >= 0) {
 #pragma unroll
         for (int c = 0; c < W; ++c)
-          if (c < jb) A[(int64_t)(j0 + lp) * n + j0 + c] = P[t][c];
+          if (c < jb) A[(int64_t)ph[t] * n + j0 + c] = P[t][c];
         if (lp < W) {
 #pragma unroll
           for (int c = 0; c < W; ++c) L11[lp][c] = P[t][c];
         }
-        if (lp != r) {
-          const int idx = atomicAdd(&s_cnt, 1);
-          s_src[idx] = r;
-          s_dst[idx] = lp;
-        }
+        Ps[j0 + lp] = ph[t];
       }
     }
     __syncthreads();
-    const int cnt = s_cnt;
     // inv(L11) (unit lower): wave w solves identity columns w*W/4 .. +W/4,
     // lane = row, the solved row value broadcast across lanes
     {
@@ -286,32 +273,13 @@ __global__ __launch_bounds__(256) void k_getrf(const LuProb* __restrict__ probs)
         for (int q = 0; q < CQ; ++q) Li[lane][wave * CQ + q] = (lane < jb) ? x[q] : T(0);
       }
     }
-    // the move list, a quarter per wave, into registers
-    int msrc[MQ], mdst[MQ];
+    // physical rows of the panel's logical rows, as this lane's U12 k-steps
+    // read them
+    int uph[W / 4];
 #pragma unroll
-    for (int q = 0; q < MQ; ++q) {
-      const int u = wave * MQ + q;
-      msrc[q] = (u < cnt) ? s_src[u] : 0;
-      mdst[q] = (u < cnt) ? s_dst[u] : -1;
-    }
-    // moves on every column outside the panel: 64 consecutive columns per
-    // step (coalesced row segments), all loads before any store
-    const int nout = n - jb;
-    for (int g = 0; g < nout; g += 64) {
-      const int q0 = g + lane;
-      const int c = (q0 < j0) ? q0 : q0 + jb;
-      T v[MQ];
-      if (q0 < nout && cnt > 0) {
-#pragma unroll
-        for (int q = 0; q < MQ; ++q)
-          if (mdst[q] >= 0) v[q] = A[(int64_t)(j0 + msrc[q]) * n + c];
-      }
-      __syncthreads();
-      if (q0 < nout && cnt > 0) {
-#pragma unroll
-        for (int q = 0; q < MQ; ++q)
-          if (mdst[q] >= 0) A[(int64_t)(j0 + mdst[q]) * n + c] = v[q];
-      }
+    for (int kk = 0; kk < W / 4; ++kk) {
+      const int k = 4 * kk + lg;
+      uph[kk] = (k < jb) ? Ps[j0 + k] : 0;
     }
     __syncthreads();
     // ---------------------------------- 3. U12 and the trailing update
@@ -326,18 +294,18 @@ __global__ __launch_bounds__(256) void k_getrf(const LuProb* __restrict__ probs)
         for (int kk = 0; kk < W / 4; ++kk) {
           const int k = 4 * kk + lg;
           const T a = Li[16 * rt + lr][k];
-          const T b = (cc < n && k < jb) ? A[(int64_t)(j0 + k) * n + cc] : T(0);
+          const T b = (cc < n && k < jb) ? A[(int64_t)uph[kk] * n + cc] : T(0);
           acc = mfma16(a, b, acc);
         }
 #pragma unroll
         for (int v = 0; v < 4; ++v) Uc[16 * rt + acc_row(T(0), lg, v)][16 * ct + lr] = acc[v];
       }
       __syncthreads();
-      // write U12 back (rows j0+1 .. j0+jb-1; row j0 is unchanged)
+      // write U12 back (logical rows j0+1 .. j0+jb-1; row j0 is unchanged)
       for (int idx = tid; idx < W * CH; idx += 256) {
         const int i = idx / CH, cl = idx % CH;
         const int cc = cb + cl;
-        if (i >= 1 && i < jb && cc < n) A[(int64_t)(j0 + i) * n + cc] = Uc[i][cl];
+        if (i >= 1 && i < jb && cc < n) A[(int64_t)Ps[j0 + i] * n + cc] = Uc[i][cl];
       }
       // A22[c0:n, chunk] -= L21 U12: wave w takes 16-row tiles w, w+4, ...
       const int ntr = (n - c0 + 15) / 16;
@@ -346,16 +314,20 @@ __global__ __launch_bounds__(256) void k_getrf(const LuProb* __restrict__ probs)
         const int row = t0 + lr;
         constexpr int KG = W / 4;
         T a[KG];
-        load_row_sigma(A + (int64_t)(row < n ? row : 0) * n + j0, row < n ? W : 0, lg, a);
+        load_row_sigma(A + (int64_t)(row < n ? Ps[row] : 0) * n + j0, row < n ? W : 0, lg, a);
+        int pr4[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int rr = t0 + acc_row(T(0), lg, v);
+          pr4[v] = (rr < n) ? Ps[rr] : -1;
+        }
         V4 cur[CH / 16];
 #pragma unroll
         for (int ct = 0; ct < CH / 16; ++ct) {
           const int cc = cb + 16 * ct + lr;
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int rr = t0 + acc_row(T(0), lg, v);
-            cur[ct][v] = (rr < n && cc < n) ? A[(int64_t)rr * n + cc] : T(0);
-          }
+          for (int v = 0; v < 4; ++v)
+            cur[ct][v] = (pr4[v] >= 0 && cc < n) ? A[(int64_t)pr4[v] * n + cc] : T(0);
         }
 #pragma unroll
         for (int ct = 0; ct < CH / 16; ++ct) {
@@ -365,10 +337,8 @@ __global__ __launch_bounds__(256) void k_getrf(const LuProb* __restrict__ probs)
             acc = mfma16(a[kk], Uc[sigma_k<T>(kk, lg)][16 * ct + lr], acc);
           const int cc = cb + 16 * ct + lr;
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int rr = t0 + acc_row(T(0), lg, v);
-            if (rr < n && cc < n) A[(int64_t)rr * n + cc] = cur[ct][v] - acc[v];
-          }
+          for (int v = 0; v < 4; ++v)
+            if (pr4[v] >= 0 && cc < n) A[(int64_t)pr4[v] * n + cc] = cur[ct][v] - acc[v];
         }
       }
       __syncthreads();

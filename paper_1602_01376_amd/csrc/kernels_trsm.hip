@@ -2,7 +2,9 @@
 // leaf solves of Algorithm 2 and the reduced-system solves of eq.
 // (11)), every system of a launch in one grid.
 //
-// Factors are stored row-major (as the batched LU writes them).
+// Factors are stored row-major as the batched LU writes them: logical row j
+// of the packed L\U sits in physical row perm[j], so every factor row is
+// read through perm.
 //
 // k_diag_inv runs once per factorization: for every 64 x 64 diagonal block
 // of every factor it forms the inverses of the unit-lower block of L and of
@@ -106,7 +108,7 @@ __global__ __launch_bounds__(256) void k_diag_inv(const DiagInvProb* __restrict_
   __shared__ TZ rdiag[NBK];
   for (int idx = tid; idx < NBK * NBK; idx += 256) {
     const int r = idx % NBK, c = idx / NBK;
-    B[c][r] = (r < nb && c < nb) ? LU[(int64_t)(jb + r) * n + jb + c] : TZ(0);
+    B[c][r] = (r < nb && c < nb) ? LU[(int64_t)p.perm[jb + r] * n + jb + c] : TZ(0);
   }
   __syncthreads();
   if (tid < NBK) rdiag[tid] = (tid < nb) ? TZ(1) / B[tid][tid] : TZ(0);
@@ -167,11 +169,13 @@ __global__ __launch_bounds__(256) void k_getrs(const TrsmProb* __restrict__ prob
 
   extern __shared__ __align__(16) unsigned char smem[];
   TZ* X = reinterpret_cast<TZ*>(smem);  // n x RT, row stride RTP
+  int* Pm = reinterpret_cast<int*>(smem + (size_t)n * RTP * sizeof(TZ));  // perm, n entries
 
   // gather the permuted right-hand sides: one thread per row, the row's RT
   // column loads in flight together
   for (int i = tid; i < n; i += 256) {
     const int src = pr.perm[i];
+    Pm[i] = src;
     const TV* base = (src < pr.split) ? in0 + src : in1 + (src - pr.split);
     const int64_t ld = (src < pr.split) ? pr.ldin0 : pr.ldin1;
     TZ v[RT];
@@ -217,7 +221,7 @@ __global__ __launch_bounds__(256) void k_getrs(const TrsmProb* __restrict__ prob
         const int row = r0 + item * 16 + lr;
         const bool rin = row < r1;
         TZ a[NBK / 4];
-        load_row_sigma(LU + (int64_t)(rin ? row : 0) * n + jb, rin ? nb : 0, lg, a);
+        load_row_sigma(LU + (int64_t)(rin ? Pm[row] : 0) * n + jb, rin ? nb : 0, lg, a);
         V4 acc = V4{0, 0, 0, 0};
 #pragma unroll
         for (int kk = 0; kk < NBK / 4; ++kk) {
@@ -245,7 +249,7 @@ __global__ __launch_bounds__(256) void k_getrs(const TrsmProb* __restrict__ prob
 
 template <typename TZ, typename TV, int KIND>
 hipError_t run(const TrsmProb* probs, const Tile2* tiles, int ntiles, int nmax, hipStream_t s) {
-  const size_t sm = (size_t)nmax * RTP * sizeof(TZ);
+  const size_t sm = (size_t)nmax * (RTP * sizeof(TZ) + sizeof(int));
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_getrs<TZ, TV, KIND>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
   if (e != hipSuccess) return e;

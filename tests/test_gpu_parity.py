@@ -74,12 +74,13 @@ def test_batched_lu_and_solve(bind, dtype):
     pm = perm.cpu().numpy()
     po = 0
     for i, (n, A) in enumerate(zip(sizes, mats)):
-        LU = lu_all[offs[i]:offs[i] + n * n].reshape(n, n)  # row-major factors
-        L = np.tril(LU, -1) + np.eye(n)
-        U = np.triu(LU)
         p = pm[po:po + n]
         po += n
         assert sorted(p.tolist()) == list(range(n))
+        # row-major factors, rows left in place: logical row j is stored row p[j]
+        LU = lu_all[offs[i]:offs[i] + n * n].reshape(n, n)[p]
+        L = np.tril(LU, -1) + np.eye(n)
+        U = np.triu(LU)
         tol = 1e-13 if dtype == "f64" else 2e-5
         err = np.linalg.norm(A[p] - L @ U) / np.linalg.norm(A)
         assert err < tol * np.sqrt(n), (n, err)
