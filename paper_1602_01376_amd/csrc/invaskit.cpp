@@ -426,6 +426,14 @@ struct GemmBuilder {
     probs.back().nseg++;
   }
   GemmL emit(Arena& ar) {
+    // longest products first, so the launch does not end on a long tile;
+    // stable, so a product's tiles stay consecutive
+    std::vector<int64_t> cost(probs.size(), 0);
+    for (size_t i = 0; i < probs.size(); ++i)
+      for (int g = 0; g < probs[i].nseg; ++g) cost[i] += segs[probs[i].seg0 + g].k;
+    auto by_cost = [&](const Tile3& x, const Tile3& y) { return cost[x.prob] > cost[y.prob]; };
+    std::stable_sort(tiles.begin(), tiles.end(), by_cost);
+    std::stable_sort(tiles_n.begin(), tiles_n.end(), by_cost);
     GemmL l;
     l.probs = ar.add(probs);
     l.segs = ar.add(segs);
@@ -463,6 +471,10 @@ struct TrsmBuilder {
     const int rt = getrs_cols_per_tile(tz64 != 0);
     for (size_t i = 0; i < probs.size(); ++i)
       for (int tn = 0; tn < (probs[i].nrhs + rt - 1) / rt; ++tn) tiles.push_back({(int)i, tn});
+    // largest systems first (stable: a system's tiles stay consecutive)
+    std::stable_sort(tiles.begin(), tiles.end(), [&](const Tile2& x, const Tile2& y) {
+      return probs[x.prob].n > probs[y.prob].n;
+    });
     TrsmL l;
     l.probs = ar.add(probs);
     l.tiles = ar.add(tiles);
@@ -690,6 +702,10 @@ int plan_factor(H* h) {
     fp.leaf_eval.blocks = ar.add(lblocks);
     fp.leaf_eval.tiles = ar.add(ltiles);
     fp.leaf_eval.ntiles = (int)ltiles.size();
+    // largest matrices first: one workgroup per matrix, so the launch's tail
+    // is set by the matrices dispatched last
+    auto by_order = [](const LuProb& x, const LuProb& y) { return x.n > y.n; };
+    std::stable_sort(lus.begin(), lus.end(), by_order);
     fp.leaf_lu.probs = ar.add(lus);
     fp.leaf_lu.count = (int)lus.size();
     fp.leaf_lu.nmax = nmax;
@@ -760,6 +776,7 @@ int plan_factor(H* h) {
     zfl.tz64 = h->zis64[jl];
     zfl.tv64 = T64;
     LuL& lul = fp.zlu[jl];
+    std::stable_sort(zl.begin(), zl.end(), [](const LuProb& x, const LuProb& y) { return x.n > y.n; });
     lul.probs = ar.add(zl);
     lul.count = (int)zl.size();
     lul.nmax = nmax;

@@ -98,11 +98,70 @@ __device__ __forceinline__ void load_row_sigma(const T* __restrict__ rowp, int k
   }
 }
 
-template <typename T>
-__device__ __forceinline__ bool better(T v, int i, T bv, int bi) {
-  // larger magnitude wins; ties go to the smaller logical row
-  return (v > bv) || (v == bv && i < bi);
+// Pivot search keys.  For |a| >= 0 the IEEE bit pattern orders like an
+// unsigned integer, so the largest magnitude is an integer max; key 0 marks
+// "no candidate" (candidates carry bits + 1; a NaN counts as infinity and is
+// flagged when it becomes the pivot).
+__device__ __forceinline__ uint32_t abs_key(float v) {
+  const float a = (v == v) ? fabsf(v) : INFINITY;
+  return __builtin_bit_cast(uint32_t, a) + 1u;
 }
+__device__ __forceinline__ uint64_t abs_key(double v) {
+  const double a = (v == v) ? fabs(v) : (double)INFINITY;
+  return __builtin_bit_cast(uint64_t, a) + 1ull;
+}
+template <typename T>
+using key_t = decltype(abs_key(T(0)));
+
+// DPP lane exchanges inside each 16-lane row: xor 1, xor 2 (quad_perm),
+// half-row mirror, row mirror -- a butterfly that leaves the row's maximum
+// (minimum) in every lane.  Rows are then combined through readlane.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ uint64_t dpp(uint64_t x) {
+  const uint32_t lo = dpp<CTRL>((uint32_t)x), hi = dpp<CTRL>((uint32_t)(x >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ uint32_t rlane(uint32_t x, int l) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)x, l);
+}
+__device__ __forceinline__ uint64_t rlane(uint64_t x, int l) {
+  return ((uint64_t)rlane((uint32_t)(x >> 32), l) << 32) | rlane((uint32_t)x, l);
+}
+constexpr int kXor1 = 0xB1, kXor2 = 0x4E, kHalfMirror = 0x141, kMirror = 0x140;
+template <typename U>
+__device__ __forceinline__ U wave_max(U k) {
+  U o;
+  o = dpp<kXor1>(k); k = o > k ? o : k;
+  o = dpp<kXor2>(k); k = o > k ? o : k;
+  o = dpp<kHalfMirror>(k); k = o > k ? o : k;
+  o = dpp<kMirror>(k); k = o > k ? o : k;
+  const U a = rlane(k, 0), b = rlane(k, 16), c = rlane(k, 32), d = rlane(k, 48);
+  const U ab = a > b ? a : b, cd = c > d ? c : d;
+  return ab > cd ? ab : cd;
+}
+__device__ __forceinline__ uint32_t wave_min(uint32_t k) {
+  uint32_t o;
+  o = dpp<kXor1>(k); k = o < k ? o : k;
+  o = dpp<kXor2>(k); k = o < k ? o : k;
+  o = dpp<kHalfMirror>(k); k = o < k ? o : k;
+  o = dpp<kMirror>(k); k = o < k ? o : k;
+  const uint32_t a = rlane(k, 0), b = rlane(k, 16), c = rlane(k, 32), d = rlane(k, 48);
+  const uint32_t ab = a < b ? a : b, cd = c < d ? c : d;
+  return ab < cd ? ab : cd;
+}
+
+// 1 / p: FP32 by the hardware reciprocal and one Newton step (LAPACK also
+// scales by the reciprocal), plain division below FLT_MIN and in FP64
+__device__ __forceinline__ float recip(float p) {
+  if (fabsf(p) < 1.17549435e-38f) return 1.0f / p;
+  const float r = __builtin_amdgcn_rcpf(p);
+  return fmaf(r, fmaf(-p, r, 1.0f), r);
+}
+__device__ __forceinline__ double recip(double p) { return 1.0 / p; }
 
 constexpr int CH = 64;  // column chunk of the U12 / trailing update
 
@@ -130,8 +189,8 @@ __global__ __launch_bounds__(256) void k_getrf(const LuProb* __restrict__ probs)
   extern __shared__ __align__(16) unsigned char smem[];
   int* Ps = reinterpret_cast<int*>(smem);  // logical row -> physical row, n entries
   __shared__ T s_row[2][4][W];             // each wave's candidate pivot row
-  __shared__ T s_bv[2][4];
-  __shared__ int s_bl[2][4];
+  __shared__ key_t<T> s_bk[2][4];
+  __shared__ uint32_t s_bl[2][4];
   __shared__ T L11[W][W + 1];
   __shared__ T Li[W][W + 1];              // inv(L11), row-major
   __shared__ T Uc[W][CH];                 // U12 chunk
@@ -161,58 +220,49 @@ __global__ __launch_bounds__(256) void k_getrf(const LuProb* __restrict__ probs)
       constexpr int jj = decltype(JJ)::value;
       if (jj < jb) {
       const int buf = jj & 1;
-      T bv = T(-1);
-      int bl = 0x7fffffff, bw = 0;
+      // this thread's best candidate: largest |a|, then the smaller row
+      key_t<T> bk = 0;
+      uint32_t bl = 0xffffffffu;
 #pragma unroll
       for (int t = 0; t < RPS; ++t) {
         if (lpos[t] >= jj) {
-          T v = fabs(P[t][jj]);
-          v = (v == v) ? v : T(INFINITY);  // a NaN is taken as pivot (flagged below)
-          if (better(v, lpos[t], bv, bl)) {
-            bv = v;
-            bl = lpos[t];
-            bw = (t << 6) | lane;
+          const key_t<T> k = abs_key(P[t][jj]);
+          if (k > bk || (k == bk && (uint32_t)lpos[t] < bl)) {
+            bk = k;
+            bl = (uint32_t)lpos[t];
           }
         }
       }
+      const key_t<T> wk = wave_max(bk);
+      const uint32_t wl = wave_min(bk == wk ? bl : 0xffffffffu);
+      // the owning lane publishes the wave's candidate row (predicated
+      // stores per slot: a select over slots would index P in memory)
 #pragma unroll
-      for (int off = 32; off >= 1; off >>= 1) {
-        const T ov = __shfl_xor(bv, off, 64);
-        const int ol = __shfl_xor(bl, off, 64);
-        const int ow = __shfl_xor(bw, off, 64);
-        if (better(ov, ol, bv, bl)) {
-          bv = ov;
-          bl = ol;
-          bw = ow;
+      for (int t = 0; t < RPS; ++t) {
+        if ((uint32_t)lpos[t] == wl) {
+#pragma unroll
+          for (int c = 0; c < W; ++c) s_row[buf][wave][c] = P[t][c];
         }
       }
-      {
-        const int wl = bw & 63, wt = bw >> 6;
-        // predicated stores per slot (a select over slots would become an
-        // indexed load from P and push P out of registers)
-#pragma unroll
-        for (int t = 0; t < RPS; ++t) {
-          if (lane == wl && t == wt) {
-#pragma unroll
-            for (int c = 0; c < W; ++c) s_row[buf][wave][c] = P[t][c];
-          }
-        }
-        if (lane == 0) {
-          s_bv[buf][wave] = bv;
-          s_bl[buf][wave] = bl;
-        }
+      if (lane == 0) {
+        s_bk[buf][wave] = wk;
+        s_bl[buf][wave] = wl;
       }
       __syncthreads();
       int w = 0;
-      T v = s_bv[buf][0];
-      int pl = s_bl[buf][0];
+      key_t<T> kv = s_bk[buf][0];
+      uint32_t plu = s_bl[buf][0];
 #pragma unroll
-      for (int ww = 1; ww < 4; ++ww)
-        if (better(s_bv[buf][ww], s_bl[buf][ww], v, pl)) {
-          v = s_bv[buf][ww];
-          pl = s_bl[buf][ww];
+      for (int ww = 1; ww < 4; ++ww) {
+        const key_t<T> k = s_bk[buf][ww];
+        const uint32_t l = s_bl[buf][ww];
+        if (k > kv || (k == kv && l < plu)) {
+          kv = k;
+          plu = l;
           w = ww;
         }
+      }
+      const int pl = (int)plu;
       const T* prow = s_row[buf][w];
       const T pv = prow[jj];
       const bool ok = (pv != T(0)) && isfinite(pv);
@@ -225,7 +275,7 @@ __global__ __launch_bounds__(256) void k_getrf(const LuProb* __restrict__ probs)
           lpos[t] = pl;
       }
       if (ok) {
-        const T inv = T(1) / pv;
+        const T inv = recip(pv);
 #pragma unroll
         for (int t = 0; t < RPS; ++t) {
           if (lpos[t] > jj) {

@@ -213,28 +213,41 @@ __global__ __launch_bounds__(256) void k_getrs(const TrsmProb* __restrict__ prob
         }
       }
       __syncthreads();
-      // rows below (above) the block: X_rows -= F[rows, block] X_b
+      // rows below (above) the block: X_rows -= F[rows, block] X_b.  X_b is
+      // not written here, so its MFMA operands are read once; the factor
+      // rows of the next tile are in flight while the current one computes.
       const int r0 = fwd ? jb + nb : 0;
       const int r1 = fwd ? n : jb;
       const int nrt = (r1 - r0 + 15) / 16;
-      for (int item = wave; item < nrt; item += 4) {
+      TZ xb[NBK / 4];
+#pragma unroll
+      for (int kk = 0; kk < NBK / 4; ++kk) {
+        const int j = sigma_k<TZ>(kk, lg);
+        xb[kk] = (j < nb) ? X[(jb + j) * RTP + lr] : TZ(0);
+      }
+      auto load_f = [&](int item, TZ (&a)[NBK / 4]) {
         const int row = r0 + item * 16 + lr;
         const bool rin = row < r1;
-        TZ a[NBK / 4];
         load_row_sigma(LU + (int64_t)(rin ? Pm[row] : 0) * n + jb, rin ? nb : 0, lg, a);
+      };
+      auto update = [&](int item, const TZ (&a)[NBK / 4]) {
         V4 acc = V4{0, 0, 0, 0};
 #pragma unroll
-        for (int kk = 0; kk < NBK / 4; ++kk) {
-          const int j = sigma_k<TZ>(kk, lg);
-          const TZ bb = (j < nb) ? X[(jb + j) * RTP + lr] : TZ(0);
-          acc = mfma16(a[kk], bb, acc);
-        }
+        for (int kk = 0; kk < NBK / 4; ++kk) acc = mfma16(a[kk], xb[kk], acc);
         const int i0 = r0 + item * 16;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int rr = i0 + acc_row(TZ(0), lg, v);
           if (rr < r1) X[rr * RTP + lr] -= acc[v];
         }
+      };
+      TZ fa[NBK / 4], fb[NBK / 4];
+      if (wave < nrt) load_f(wave, fa);
+      for (int item = wave; item < nrt; item += 8) {
+        if (item + 4 < nrt) load_f(item + 4, fb);
+        update(item, fa);
+        if (item + 8 < nrt) load_f(item + 8, fa);
+        if (item + 4 < nrt) update(item + 4, fb);
       }
       __syncthreads();
     }
