@@ -11,7 +11,8 @@
 // computed as 2 x 2 MFMA 16x16x4 blocks (f64 or f32 accumulate).  Two shapes:
 // 64 x 64, and 128 x 32 for products with at most 32 columns (the deferred
 // corrections and skeleton projections, whose N is a skeleton rank).
-// K is staged through LDS in steps of 16.  The MFMA is issued with the B
+// K is staged through LDS in steps of 16, the next step's operands loaded
+// into registers while the current one computes.  The MFMA is issued with the B
 // fragment as its first operand so that the accumulator layout puts 16
 // consecutive lanes on 16 consecutive rows of column-major C (coalesced
 // stores).  Operand layout of both 16x16x4 forms: lane l supplies
@@ -80,65 +81,74 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmProb* __restrict__ probs
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = V4{0, 0, 0, 0};
 
-  for (int s = P.seg0; s < P.seg0 + P.nseg; ++s) {
-    const GemmSeg g = segs[s];
+  // K steps run over the segments in order; the next step's operands are
+  // loaded into registers while the current step computes from LDS
+  T av[NA], bv[NB];
+  int arm = 0;
+  auto fetch = [&](const GemmSeg& g, int k0) {
     const T* __restrict__ A = static_cast<const T*>(g.A);
     const T* __restrict__ B = static_cast<const T*>(g.B);
-    for (int k0 = 0; k0 < g.k; k0 += BK) {
-      T av[NA], bv[NB];
-      // A tile: BM x BK
+    arm = g.a_rm;
 #pragma unroll
-      for (int q = 0; q < NA; ++q) {
-        const int idx = tid + q * 256;
-        int i, kk;
-        if (g.a_rm) {
-          kk = idx % BK;
-          i = idx / BK;
-        } else {
-          i = idx % BM;
-          kk = idx / BM;
-        }
-        const int gi = m0 + i, gk = k0 + kk;
-        T v = 0;
-        if (gi < P.M && gk < g.k)
-          v = g.a_rm ? A[(int64_t)gi * g.lda + gk] : A[(int64_t)gk * g.lda + gi];
-        av[q] = v;
-      }
-      // B tile: BK x BN (column-major source)
+    for (int q = 0; q < NA; ++q) {
+      const int idx = tid + q * 256;
+      const int i = arm ? idx / BK : idx % BM;
+      const int kk = arm ? idx % BK : idx / BM;
+      const int gi = m0 + i, gk = k0 + kk;
+      T v = 0;
+      if (gi < P.M && gk < g.k)
+        v = arm ? A[(int64_t)gi * g.lda + gk] : A[(int64_t)gk * g.lda + gi];
+      av[q] = v;
+    }
 #pragma unroll
-      for (int q = 0; q < NB; ++q) {
-        const int idx = tid + q * 256;
-        const int kk = idx % BK;
-        const int j = idx / BK;
-        const int gj = n0 + j, gk = k0 + kk;
-        bv[q] = (gj < P.N && gk < g.k) ? B[(int64_t)gj * g.ldb + gk] : T(0);
-      }
-      __syncthreads();
+    for (int q = 0; q < NB; ++q) {
+      const int idx = tid + q * 256;
+      const int kk = idx % BK;
+      const int j = idx / BK;
+      const int gj = n0 + j, gk = k0 + kk;
+      bv[q] = (gj < P.N && gk < g.k) ? B[(int64_t)gj * g.ldb + gk] : T(0);
+    }
+  };
+  const int send = P.seg0 + P.nseg;
+  int s = P.seg0, k0 = 0;
+  GemmSeg g;
+  if (s < send) {
+    g = segs[s];
+    fetch(g, 0);
+  }
+  while (s < send) {
+    __syncthreads();  // the previous step's LDS reads are done
 #pragma unroll
-      for (int q = 0; q < NA; ++q) {
-        const int idx = tid + q * 256;
-        if (g.a_rm)
-          As[idx % BK][idx / BK] = av[q];
-        else
-          As[idx / BM][idx % BM] = av[q];
-      }
+    for (int q = 0; q < NA; ++q) {
+      const int idx = tid + q * 256;
+      if (arm)
+        As[idx % BK][idx / BK] = av[q];
+      else
+        As[idx / BM][idx % BM] = av[q];
+    }
 #pragma unroll
-      for (int q = 0; q < NB; ++q) {
-        const int idx = tid + q * 256;
-        Bs[idx % BK][idx / BK] = bv[q];
-      }
-      __syncthreads();
+    for (int q = 0; q < NB; ++q) {
+      const int idx = tid + q * 256;
+      Bs[idx % BK][idx / BK] = bv[q];
+    }
+    __syncthreads();
+    k0 += BK;
+    if (k0 >= g.k) {
+      ++s;
+      k0 = 0;
+      if (s < send) g = segs[s];
+    }
+    if (s < send) fetch(g, k0);
 #pragma unroll
-      for (int kk = 0; kk < BK; kk += 4) {
-        T a0 = As[kk + lk][wm + lr];
-        T a1 = As[kk + lk][wm + 16 + lr];
-        T b0 = Bs[kk + lk][wn + lr];
-        T b1 = Bs[kk + lk][wn + 16 + lr];
-        acc[0][0] = mfma16(b0, a0, acc[0][0]);
-        acc[0][1] = mfma16(b1, a0, acc[0][1]);
-        acc[1][0] = mfma16(b0, a1, acc[1][0]);
-        acc[1][1] = mfma16(b1, a1, acc[1][1]);
-      }
+    for (int kk = 0; kk < BK; kk += 4) {
+      T a0 = As[kk + lk][wm + lr];
+      T a1 = As[kk + lk][wm + 16 + lr];
+      T b0 = Bs[kk + lk][wn + lr];
+      T b1 = Bs[kk + lk][wn + 16 + lr];
+      acc[0][0] = mfma16(b0, a0, acc[0][0]);
+      acc[0][1] = mfma16(b1, a0, acc[0][1]);
+      acc[1][0] = mfma16(b0, a1, acc[1][0]);
+      acc[1][1] = mfma16(b1, a1, acc[1][1]);
     }
   }
 
