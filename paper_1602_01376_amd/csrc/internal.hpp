@@ -139,6 +139,7 @@ hipError_t launch_gemm(const GemmProb* probs, const GemmSeg* segs, const Tile3* 
                        int ntiles, int shape, hipStream_t s);
 
 // kind: 0 leaf panels of the factorization, 1 reduced systems, 2 solve phase
+// (library factors, padded by 64 elements), 3 caller-owned factors
 template <typename TZ, typename TV>
 hipError_t launch_getrs(const TrsmProb* probs, const Tile2* tiles, int ntiles, int nmax, int kind,
                         hipStream_t s);

@@ -600,12 +600,14 @@ int plan_factor(H* h) {
 
   // allocations
   int rc;
-  if ((rc = dev_alloc(h, h->leafLU, h->lu_off[h->nleaves] * es))) return rc;
+  // factor storage is padded by one 64-column block: the solves read factor
+  // rows as whole vectors past the last partial block
+  if ((rc = dev_alloc(h, h->leafLU, (h->lu_off[h->nleaves] + kDiagBlock) * es))) return rc;
   if ((rc = dev_alloc(h, h->leafPerm, sizeof(int32_t) * h->N))) return rc;
   if ((rc = dev_alloc(h, h->leafInfo, sizeof(int32_t) * h->nleaves))) return rc;
   if ((rc = dev_alloc(h, h->slab, h->slab_off[h->nleaves] * es))) return rc;
-  if ((rc = dev_alloc(h, h->Z64, z64n * 8))) return rc;
-  if ((rc = dev_alloc(h, h->ZT, zTn * es))) return rc;
+  if ((rc = dev_alloc(h, h->Z64, (z64n + kDiagBlock) * 8))) return rc;
+  if ((rc = dev_alloc(h, h->ZT, (zTn + kDiagBlock) * es))) return rc;
   if ((rc = dev_alloc(h, h->zperm, sizeof(int32_t) * std::max<int64_t>(zpn, 1)))) return rc;
   if ((rc = dev_alloc(h, h->zinfo, sizeof(int32_t) * std::max(ninternal, 1)))) return rc;
   if ((rc = dev_alloc(h, h->dinvLeaf, h->dleaf_off[h->nleaves] * es))) return rc;
@@ -1493,7 +1495,7 @@ int invaskit_getrs_batched(int32_t dtype, const void* a, const int64_t* a_offset
   }
   Arena ar;
   const int f = dtype == INVASKIT_F64 ? 1 : 0;
-  TrsmL l = tb.emit(ar, f, f, 1);
+  TrsmL l = tb.emit(ar, f, f, 3);  // caller-owned factors: checked loads
   DinvL dl;
   dl.probs = ar.add(dis);
   dl.count = (int)dis.size();

@@ -20,8 +20,13 @@
 // in 16 x 16 output tiles with K = 64, the factor operands streamed from
 // global memory as 16-byte row segments (see load_row_sigma).
 // TZ is the type of the factors and of the arithmetic, TV the type of the
-// right-hand sides in memory.  KIND only separates the kernel names of the
-// three uses (leaf panels of the factorization, reduced systems, solve).
+// right-hand sides in memory.  KIND 0..2 separate the kernel names of the
+// library's three uses (leaf panels of the factorization, reduced systems,
+// solve); their factor storage is padded by 64 elements, so a factor row is
+// always read as whole 16-byte vectors, masked past the block's last column
+// (no divergent paths that would drain the loads issued ahead).  KIND 3
+// reads caller-owned factors and never touches memory past a row's block.
+#include "device_util.hpp"
 #include "internal.hpp"
 
 namespace invaskit {
@@ -30,70 +35,6 @@ namespace {
 constexpr int NBK = kDiagBlock;  // 64-row block
 constexpr int RT = kTrsmCols;    // right-hand sides per workgroup
 constexpr int RTP = RT + 1;      // LDS row stride
-
-typedef double f64x4 __attribute__((ext_vector_type(4)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-template <typename T>
-struct Vec4;
-template <>
-struct Vec4<double> {
-  using type = f64x4;
-};
-template <>
-struct Vec4<float> {
-  using type = f32x4;
-};
-__device__ __forceinline__ f64x4 mfma16(double a, double b, f64x4 c) {
-  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
-__device__ __forceinline__ f32x4 mfma16(float a, float b, f32x4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-}
-// accumulator row of element v in lane group g = lane / 16 (16x16x4 forms,
-// measured on gfx950): f32 4g + v, f64 g + 4v.  Column = lane % 16.
-__device__ __forceinline__ constexpr int acc_row(double, int g, int v) { return g + 4 * v; }
-__device__ __forceinline__ constexpr int acc_row(float, int g, int v) { return 4 * g + v; }
-
-
-// Row-segment loads for an MFMA A operand from row-major memory.  The MFMA's
-// reduction order over K is free as long as both operands use the same
-// order; here lane group g (lane / 16) at MFMA step kk covers
-//   k = sigma(kk, g) = 4 VE (kk / VE) + VE g + kk % VE,   VE = 16 / sizeof(T),
-// so the four lane groups of a row read one contiguous 64-byte segment per
-// 16-byte vector load.  Elements at k >= klim read as zero.
-template <typename T>
-__device__ __forceinline__ constexpr int sigma_k(int kk, int g) {
-  constexpr int VE = 16 / sizeof(T);
-  return 4 * VE * (kk / VE) + VE * g + kk % VE;
-}
-template <typename T, int KQ>
-__device__ __forceinline__ void load_row_sigma(const T* __restrict__ rowp, int klim, int g,
-                                               T (&a)[KQ]) {
-  constexpr int VE = 16 / sizeof(T);
-  typedef T vec __attribute__((ext_vector_type(VE), aligned(sizeof(T))));
-#pragma unroll
-  for (int i = 0; i < KQ / VE; ++i) {
-    const int k0 = 4 * VE * i + VE * g;
-    if (k0 + VE <= klim) {
-      const vec v = *reinterpret_cast<const vec*>(rowp + k0);
-#pragma unroll
-      for (int e = 0; e < VE; ++e) a[VE * i + e] = v[e];
-    } else {
-#pragma unroll
-      for (int e = 0; e < VE; ++e) a[VE * i + e] = (k0 + e < klim) ? rowp[k0 + e] : T(0);
-    }
-  }
-}
-
-__device__ __forceinline__ double lane_bcast(double v, int l) {
-  const long long b = __builtin_bit_cast(long long, v);
-  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
-  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
-}
-__device__ __forceinline__ float lane_bcast(float v, int l) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
-}
 
 // ------------------------------------------------------------ block inverses
 template <typename TZ>
@@ -171,6 +112,21 @@ __global__ __launch_bounds__(256) void k_getrs(const TrsmProb* __restrict__ prob
   TZ* X = reinterpret_cast<TZ*>(smem);  // n x RT, row stride RTP
   int* Pm = reinterpret_cast<int*>(smem + (size_t)n * RTP * sizeof(TZ));  // perm, n entries
 
+  // Block steps q = 0 .. 2 nblocks - 1: forward substitution over the blocks,
+  // then back substitution in reverse.  Factor data never depends on X, so
+  // the next step's inverse diagonal rows and each step's first off-diagonal
+  // tile are loaded ahead of the barriers that separate the steps.
+  const int nblocks = (n + NBK - 1) / NBK;
+  const int nsteps = 2 * nblocks;
+  TZ da[NBK / 4];  // this wave's 16 rows of the current step's diagonal inverse
+  auto load_d = [&](int q) {
+    const bool f = q < nblocks;
+    const int bq = f ? q : nsteps - 1 - q;
+    const TZ* D = DI + (int64_t)(2 * bq + (f ? 0 : 1)) * NBK * NBK;
+    load_row_sigma_full(D + (16 * wave + lr) * NBK, NBK, lg, da);
+  };
+  load_d(0);
+
   // gather the permuted right-hand sides: one thread per row, the row's RT
   // column loads in flight together
   for (int i = tid; i < n; i += 256) {
@@ -186,71 +142,71 @@ __global__ __launch_bounds__(256) void k_getrs(const TrsmProb* __restrict__ prob
   }
   __syncthreads();
 
-  const int nblocks = (n + NBK - 1) / NBK;
-  for (int pass = 0; pass < 2; ++pass) {
-    const bool fwd = pass == 0;
-    for (int bi = 0; bi < nblocks; ++bi) {
-      const int b = fwd ? bi : nblocks - 1 - bi;
-      const int jb = b * NBK;
-      const int nb = min(NBK, n - jb);
-      // X_b = inv(diagonal block) X_b: wave w computes rows 16w .. 16w+15
-      {
-        const TZ* D = DI + (int64_t)(2 * b + (fwd ? 0 : 1)) * NBK * NBK;
-        TZ a[NBK / 4];
-        load_row_sigma(D + (16 * wave + lr) * NBK, NBK, lg, a);
-        V4 acc = V4{0, 0, 0, 0};
-#pragma unroll
-        for (int kk = 0; kk < NBK / 4; ++kk) {
-          const int k = sigma_k<TZ>(kk, lg);
-          const TZ bb = (k < nb) ? X[(jb + k) * RTP + lr] : TZ(0);
-          acc = mfma16(a[kk], bb, acc);
-        }
-        __syncthreads();
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int r = 16 * wave + acc_row(TZ(0), lg, v);
-          if (r < nb) X[(jb + r) * RTP + lr] = acc[v];
-        }
-      }
-      __syncthreads();
-      // rows below (above) the block: X_rows -= F[rows, block] X_b.  X_b is
-      // not written here, so its MFMA operands are read once; the factor
-      // rows of the next tile are in flight while the current one computes.
-      const int r0 = fwd ? jb + nb : 0;
-      const int r1 = fwd ? n : jb;
-      const int nrt = (r1 - r0 + 15) / 16;
-      TZ xb[NBK / 4];
+  for (int q = 0; q < nsteps; ++q) {
+    const bool fwd = q < nblocks;
+    const int b = fwd ? q : nsteps - 1 - q;
+    const int jb = b * NBK;
+    const int nb = min(NBK, n - jb);
+    // rows below (above) the block, updated after the diagonal step
+    const int r0 = fwd ? jb + nb : 0;
+    const int r1 = fwd ? n : jb;
+    const int nrt = (r1 - r0 + 15) / 16;
+    auto load_f = [&](int item, TZ (&a)[NBK / 4]) {
+      const int row = r0 + item * 16 + lr;
+      const bool rin = row < r1;
+      const TZ* rowp = LU + (int64_t)(rin ? Pm[row] : 0) * n + jb;
+      if constexpr (KIND == 3)
+        load_row_sigma(rowp, rin ? nb : 0, lg, a);
+      else
+        load_row_sigma_full(rowp, rin ? nb : 0, lg, a);
+    };
+    TZ fa[NBK / 4], fb[NBK / 4];
+    if (wave < nrt) load_f(wave, fa);
+    // X_b = inv(diagonal block) X_b: wave w computes rows 16w .. 16w+15
+    {
+      V4 acc = V4{0, 0, 0, 0};
 #pragma unroll
       for (int kk = 0; kk < NBK / 4; ++kk) {
-        const int j = sigma_k<TZ>(kk, lg);
-        xb[kk] = (j < nb) ? X[(jb + j) * RTP + lr] : TZ(0);
-      }
-      auto load_f = [&](int item, TZ (&a)[NBK / 4]) {
-        const int row = r0 + item * 16 + lr;
-        const bool rin = row < r1;
-        load_row_sigma(LU + (int64_t)(rin ? Pm[row] : 0) * n + jb, rin ? nb : 0, lg, a);
-      };
-      auto update = [&](int item, const TZ (&a)[NBK / 4]) {
-        V4 acc = V4{0, 0, 0, 0};
-#pragma unroll
-        for (int kk = 0; kk < NBK / 4; ++kk) acc = mfma16(a[kk], xb[kk], acc);
-        const int i0 = r0 + item * 16;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int rr = i0 + acc_row(TZ(0), lg, v);
-          if (rr < r1) X[rr * RTP + lr] -= acc[v];
-        }
-      };
-      TZ fa[NBK / 4], fb[NBK / 4];
-      if (wave < nrt) load_f(wave, fa);
-      for (int item = wave; item < nrt; item += 8) {
-        if (item + 4 < nrt) load_f(item + 4, fb);
-        update(item, fa);
-        if (item + 8 < nrt) load_f(item + 8, fa);
-        if (item + 4 < nrt) update(item + 4, fb);
+        const int k = sigma_k<TZ>(kk, lg);
+        const TZ bb = (k < nb) ? X[(jb + k) * RTP + lr] : TZ(0);
+        acc = mfma16(da[kk], bb, acc);
       }
       __syncthreads();
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 16 * wave + acc_row(TZ(0), lg, v);
+        if (r < nb) X[(jb + r) * RTP + lr] = acc[v];
+      }
     }
+    __syncthreads();
+    if (q + 1 < nsteps) load_d(q + 1);
+    // X_rows -= F[rows, block] X_b.  X_b is not written here, so its MFMA
+    // operands are read once; the next tile's factor rows are in flight
+    // while the current one computes.
+    TZ xb[NBK / 4];
+#pragma unroll
+    for (int kk = 0; kk < NBK / 4; ++kk) {
+      const int j = sigma_k<TZ>(kk, lg);
+      xb[kk] = (j < nb) ? X[(jb + j) * RTP + lr] : TZ(0);
+    }
+    auto update = [&](int item, const TZ (&a)[NBK / 4]) {
+      V4 acc = V4{0, 0, 0, 0};
+#pragma unroll
+      for (int kk = 0; kk < NBK / 4; ++kk) acc = mfma16(a[kk], xb[kk], acc);
+      const int i0 = r0 + item * 16;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int rr = i0 + acc_row(TZ(0), lg, v);
+        if (rr < r1) X[rr * RTP + lr] -= acc[v];
+      }
+    };
+    for (int item = wave; item < nrt; item += 8) {
+      if (item + 4 < nrt) load_f(item + 4, fb);
+      update(item, fa);
+      if (item + 8 < nrt) load_f(item + 8, fa);
+      if (item + 4 < nrt) update(item + 4, fb);
+    }
+    __syncthreads();
   }
 
   for (int i = tid; i < n; i += 256) {
@@ -288,7 +244,8 @@ hipError_t launch_getrs(const TrsmProb* probs, const Tile2* tiles, int ntiles, i
   switch (kind) {
     case 0: return run<TZ, TV, 0>(probs, tiles, ntiles, nmax, s);
     case 1: return run<TZ, TV, 1>(probs, tiles, ntiles, nmax, s);
-    default: return run<TZ, TV, 2>(probs, tiles, ntiles, nmax, s);
+    case 2: return run<TZ, TV, 2>(probs, tiles, ntiles, nmax, s);
+    default: return run<TZ, TV, 3>(probs, tiles, ntiles, nmax, s);
   }
 }
 
