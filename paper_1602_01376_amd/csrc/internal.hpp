@@ -166,7 +166,8 @@ hipError_t launch_mv_eval(const PT* X, int d, double h, double lam, const MvTile
                           double* y, int64_t ldy, const double* b, int64_t ldb, int nrhs,
                           hipStream_t s);
 constexpr int kMvBlock = 128;
-constexpr int kMvMaxDim = 64;
+constexpr int kMvMaxDim = 64;    // register-resident targets up to this d
+constexpr int kMvWideRows = 64;  // targets per tile of the d > kMvMaxDim form
 
 // elementwise helpers
 hipError_t launch_convert_f64_f32(const double* in, float* out, int64_t n, hipStream_t s);

@@ -1085,9 +1085,6 @@ int build_mv_plan(H* h, int r, MatvecPlan*& out) {
     out = it->second.get();
     return INVASKIT_OK;
   }
-  if (h->d > kMvMaxDim)
-    return fail_h(h, INVASKIT_E_ARG,
-                  "the fused FP64 hierarchical product supports d <= " + std::to_string(kMvMaxDim));
   auto mp = std::make_unique<MatvecPlan>();
   mp->r = r;
   const int L = h->L;
@@ -1147,10 +1144,11 @@ int build_mv_plan(H* h, int r, MatvecPlan*& out) {
       t.count = h->s[cs];
       segs.push_back(t);
     }
-    for (int t0 = 0; t0 < m; t0 += kMvBlock) {
+    const int rows = h->d > kMvMaxDim ? kMvWideRows : kMvBlock;
+    for (int t0 = 0; t0 < m; t0 += rows) {
       MvTile t{};
       t.row0 = h->na[lf] + t0;
-      t.rows = std::min(kMvBlock, m - t0);
+      t.rows = std::min(rows, m - t0);
       t.seg0 = seg0;
       t.nseg = L + 1;
       tiles.push_back(t);

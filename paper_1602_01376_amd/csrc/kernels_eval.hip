@@ -10,9 +10,9 @@
 //
 // k_mv_eval is the fused FP64 evaluate step of the hierarchical product
 // (Section II-B, Evaluate): one thread per target point keeps its
-// coordinates in registers; source points and their weights are staged
-// through LDS 64 at a time and K(x_i, x_j) is consumed immediately, so the
-// kernel matrix is never stored.
+// coordinates in registers (d <= 64); source points and their weights are
+// staged through LDS 64 at a time and K(x_i, x_j) is consumed immediately,
+// so the kernel matrix is never stored.  k_mv_eval_wide covers d > 64.
 #include <cmath>
 
 #include "internal.hpp"
@@ -163,6 +163,115 @@ __global__ __launch_bounds__(MB) void k_mv_eval(const PT* __restrict__ X, int d,
   }
 }
 
+// Wide form for d > 64: a workgroup takes kMvWideRows = 64 targets against
+// 64 sources at a time; squared distances accumulate by direct differences
+// over coordinate chunks of 16 staged through LDS (4 x 4 pairs per thread, as
+// in k_eval), then exp and the weights are applied in registers and the 16
+// threads that share a target are summed through LDS at the end.
+constexpr int WT = kMvWideRows;  // targets per workgroup
+constexpr int WS = 64;           // sources per stage
+constexpr int WD = 16;           // coordinates per LDS chunk
+
+template <typename PT>
+__global__ __launch_bounds__(256) void k_mv_eval_wide(
+    const PT* __restrict__ X, int d, double nhalf_inv_h2, double lam,
+    const MvTile* __restrict__ tiles, const MvSeg* __restrict__ segs,
+    const double* __restrict__ x, int64_t ldx, double* __restrict__ y, int64_t ldy,
+    const double* __restrict__ bsub, int64_t ldb, int nrhs) {
+  __shared__ double xt[WD][WT + 1];
+  __shared__ double xs[WD][WS + 1];
+  __shared__ double sw[WS][RC];
+  __shared__ int64_t sidx[WS];
+  __shared__ double red[16][WT][RC];
+  const MvTile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
+  const int tid = threadIdx.x;
+  const int tr = tid & 15, tc = tid >> 4;
+
+  for (int cb = 0; cb < nrhs; cb += RC) {
+    const int ncol = min(RC, nrhs - cb);
+    double acc[4][RC];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int c = 0; c < RC; ++c) acc[i][c] = 0.0;
+    for (int sg = t.seg0; sg < t.seg0 + t.nseg; ++sg) {
+      const MvSeg g = segs[sg];
+      for (int j0 = 0; j0 < g.count; j0 += WS) {
+        const int nj = min(WS, g.count - j0);
+        __syncthreads();
+        if (tid < WS)
+          sidx[tid] = (tid < nj) ? (g.idx ? (int64_t)g.idx[j0 + tid] : g.p0 + j0 + tid) : -1;
+        for (int idx = tid; idx < WS * RC; idx += 256) {
+          const int j = idx / RC, c = idx % RC;
+          sw[j][c] = (j < nj && c < ncol) ? g.w[(int64_t)(cb + c) * g.ldw + j0 + j] : 0.0;
+        }
+        double d2[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) d2[i][j] = 0.0;
+        for (int dd = 0; dd < d; dd += WD) {
+          __syncthreads();
+          for (int idx = tid; idx < WT * WD; idx += 256) {
+            const int p = idx / WD, k = idx % WD;
+            xt[k][p] = (p < t.rows && dd + k < d) ? (double)X[(t.row0 + p) * d + dd + k] : 0.0;
+          }
+          for (int idx = tid; idx < WS * WD; idx += 256) {
+            const int p = idx / WD, k = idx % WD;
+            const int64_t gp = sidx[p];
+            xs[k][p] = (gp >= 0 && dd + k < d) ? (double)X[gp * d + dd + k] : 0.0;
+          }
+          __syncthreads();
+#pragma unroll
+          for (int k = 0; k < WD; ++k) {
+            double a[4], b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i] = xt[k][tr + 16 * i];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b[j] = xs[k][tc + 16 * j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+              for (int j = 0; j < 4; ++j) {
+                const double df = a[i] - b[j];
+                d2[i][j] = fma(df, df, d2[i][j]);
+              }
+          }
+        }
+        // sources past nj carry zero weight
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          double wv[RC];
+#pragma unroll
+          for (int c = 0; c < RC; ++c) wv[c] = sw[tc + 16 * j][c];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const double kv = exp(d2[i][j] * nhalf_inv_h2);
+#pragma unroll
+            for (int c = 0; c < RC; ++c) acc[i][c] = fma(kv, wv[c], acc[i][c]);
+          }
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int c = 0; c < RC; ++c) red[tc][tr + 16 * i][c] = acc[i][c];
+    __syncthreads();
+    if (tid < t.rows) {
+      const int64_t i = t.row0 + tid;
+      for (int c = 0; c < ncol; ++c) {
+        double sum = 0.0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) sum += red[q][tid][c];
+        const double ax = lam * x[(int64_t)(cb + c) * ldx + i] + sum;
+        y[(int64_t)(cb + c) * ldy + i] = bsub ? bsub[(int64_t)(cb + c) * ldb + i] - ax : ax;
+      }
+    }
+  }
+}
+
 }  // namespace
 
 template <typename PT, typename T>
@@ -194,7 +303,8 @@ hipError_t launch_mv_eval(const PT* X, int d, double h, double lam, const MvTile
   else if (d <= 64)
     INVASKIT_MV(64);
   else
-    return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_mv_eval_wide<PT>), dim3(ntiles), dim3(256), 0, s, X, d, c, lam, tiles,
+                       segs, x, ldx, y, ldy, b, ldb, nrhs);
 #undef INVASKIT_MV
   return hipGetLastError();
 }

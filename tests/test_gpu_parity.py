@@ -133,7 +133,16 @@ CASES = [
     ("tiny", dict(n=300, depth=0), 1),            # one leaf: dense LU
     ("tiny", dict(n=600, depth=1), 1),            # one Woodbury step
     ("susy", dict(n=3000, depth=3), 1),           # ragged tail sizes
+    ("mnist", dict(n=2048, depth=2), 2),          # d = 784, FP32 points, s = 256
+    ("normal", dict(n=4096, depth=3), 2),         # d = 64, s = 256
+    ("susy", dict(n=4096, depth=4), 64),          # 64 right-hand sides
 ]
+# the matvec and mixed-precision checks: the first four cases and the last three
+MV_CASES = CASES[:4] + CASES[-3:]
+# Mixed path: the refined residual is <= 1e-10, so x can differ from the
+# oracle's by up to kappa * 1e-10; kappa(lambda I + K~) is about 1e4 for the
+# 784-dimensional case (dense estimate at this size) and below 30 elsewhere.
+MIXED_XTOL = {"mnist": 1e-5}
 
 
 @pytest.fixture(scope="module")
@@ -166,7 +175,7 @@ def test_fp64_factor_solve_matches_oracle(bind, problems, name, kw, r):
     fac.close()
 
 
-@pytest.mark.parametrize("name,kw,r", CASES[:4])
+@pytest.mark.parametrize("name,kw,r", MV_CASES)
 def test_matvec_matches_oracle(bind, problems, name, kw, r):
     _say("fp64 matvec", name, kw, r)
     pb, _ = problems(name, kw)
@@ -178,7 +187,7 @@ def test_matvec_matches_oracle(bind, problems, name, kw, r):
     fac.close()
 
 
-@pytest.mark.parametrize("name,kw,r", CASES[:4])
+@pytest.mark.parametrize("name,kw,r", MV_CASES)
 def test_mixed_refinement_reaches_tolerance(bind, problems, name, kw, r):
     _say("mixed factor/solve", name, kw, r)
     pb, F = problems(name, kw)
@@ -192,7 +201,7 @@ def test_mixed_refinement_reaches_tolerance(bind, problems, name, kw, r):
     x = x.cpu().numpy()
     res = _rel(oracle.matvec(pb, pb.lam, x), b)
     assert res <= 1e-10
-    assert _rel(x, x_ref) <= 1e-7
+    assert _rel(x, x_ref) <= MIXED_XTOL.get(name, 1e-7)
     fac.close()
 
 
