@@ -124,8 +124,11 @@ int invaskit_default_options(invaskit_options* opt);
  * Validates every input on the host before any launch (E_ARG).  Allocates
  * the factorization's device memory itself (its size: invaskit_device_bytes);
  * the handle owns it until invaskit_destroy().  hip_stream may be NULL (the
- * null stream).  Synchronizes the stream once at the end to read the pivot
- * status: a zero or non-finite pivot returns E_SINGULAR, names the node in
+ * null stream).  Part of the work runs on a second stream the handle owns
+ * (default priority), ordered after everything already enqueued on
+ * hip_stream and joined back into it before the factor's end.  Synchronizes
+ * the stream once at the end to read the pivot status: a zero or
+ * non-finite pivot returns E_SINGULAR, names the node in
  * invaskit_last_error(), and still returns the handle in *out.
  */
 int invaskit_factor(const invaskit_problem* problem, double lambda,
@@ -168,7 +171,8 @@ int invaskit_device_bytes(invaskit_handle handle, size_t* bytes);
 
 /*
  * Milliseconds spent in the phases of the last factor (HIP events on the
- * factor's stream): [0] leaf block evaluation, [1] leaf LU, [2] inverses of
+ * stream each phase runs on; [3] and [7] run beside other phases, so the
+ * phases need not add up to the total): [0] leaf block evaluation, [1] leaf LU, [2] inverses of
  * the factors' 64 x 64 diagonal blocks (leaves), [3] skeleton blocks,
  * [4] leaf solves, [5] leaf projections, [6] skeleton sweep, [7] deferred
  * corrections, [8] reduced systems (assembly, LU, diagonal-block

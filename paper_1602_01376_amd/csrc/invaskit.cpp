@@ -209,6 +209,10 @@ struct invaskit_handle_s {
   double phase_ms[kPhases] = {0};
   hipEvent_t ev[kEvents + 2] = {};
   bool have_events = false;
+  // second stream of the factorization (default priority): the skeleton
+  // blocks and the deferred corrections run on it beside the leaf LU and the
+  // level wavefront
+  hipStream_t side = nullptr;
   std::string err;
 
   int level(int node) const {
@@ -251,6 +255,7 @@ struct invaskit_handle_s {
       b->release();
     if (have_events)
       for (auto& e : ev) hipEventDestroy(e);
+    if (side) hipStreamDestroy(side);
   }
 };
 
@@ -885,18 +890,22 @@ int run_factor(H* h) {
     for (auto& e : h->ev) HIP_TRY(h, hipEventCreate(&e));
     h->have_events = true;
   }
-  // phase accumulation: events bracket each phase of each level
-  std::vector<hipEvent_t> marks;
-  std::vector<int> phase_of;
+  if (!h->side) HIP_TRY(h, hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
+  hipStream_t s2 = h->side;
+  // Phase timing: each phase is bracketed by two events on the stream it
+  // runs on; phases on the two streams overlap, so they need not sum to the
+  // total.  `sync` events order the streams.
+  struct Bracket {
+    hipEvent_t a, b;
+    int phase;
+  };
+  std::vector<Bracket> brackets;
   std::vector<hipEvent_t> pool;
-  auto mark = [&](int phase) -> int {
-    hipEvent_t e;
-    if (hipEventCreate(&e) != hipSuccess) return -1;
+  auto new_event = [&](unsigned flags) -> hipEvent_t {
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, flags) != hipSuccess) return nullptr;
     pool.push_back(e);
-    if (hipEventRecord(e, s) != hipSuccess) return -1;
-    marks.push_back(e);
-    phase_of.push_back(phase);
-    return 0;
+    return e;
   };
   auto cleanup = [&]() {
     for (auto e : pool) hipEventDestroy(e);
@@ -910,50 +919,91 @@ int run_factor(H* h) {
                     std::string(#__VA_ARGS__) + ": " + hipGetErrorString(e_));    \
     }                                                                             \
   } while (0)
+  auto open = [&](int phase, hipStream_t st) -> hipError_t {
+    hipEvent_t e = new_event(hipEventDefault);
+    if (!e) return hipErrorOutOfMemory;
+    brackets.push_back({e, nullptr, phase});
+    return hipEventRecord(e, st);
+  };
+  auto close = [&](hipStream_t st) -> hipError_t {
+    hipEvent_t e = new_event(hipEventDefault);
+    if (!e) return hipErrorOutOfMemory;
+    brackets.back().b = e;
+    return hipEventRecord(e, st);
+  };
+  // stream `to` waits for the work enqueued so far on `from`
+  auto join = [&](hipStream_t from, hipStream_t to) -> hipError_t {
+    hipEvent_t e = new_event(hipEventDisableTiming);
+    if (!e) return hipErrorOutOfMemory;
+    hipError_t r = hipEventRecord(e, from);
+    return r == hipSuccess ? hipStreamWaitEvent(to, e, 0) : r;
+  };
 
   const FactorPlan& fp = h->fp;
-  mark(-1);
+  const int L = h->L;
+  hipEvent_t t_begin = new_event(hipEventDefault), t_end = new_event(hipEventDefault);
+  if (!t_begin || !t_end) STEP(hipErrorOutOfMemory);
+  STEP(hipEventRecord(t_begin, s));
+  // the side stream starts after everything already on the caller's stream
+  STEP(join(s, s2));
+  if (L > 0) {
+    STEP(open(3, s2));
+    STEP(run_eval(h, tb, fp.panels, 0.0, s2));
+    STEP(close(s2));
+  }
   if (!f64 && h->P32.p && h->p_off[h->nn] > 0)
     STEP(launch_convert_f64_f32(h->P64, static_cast<float*>(h->P32.p), h->p_off[h->nn], s));
-  mark(-1);
+  STEP(open(0, s));
   STEP(run_eval(h, tb, fp.leaf_eval, h->lam, s));
-  mark(0);
+  STEP(close(s));
+  STEP(open(1, s));
   STEP(run_lu(tb, fp.leaf_lu, s));
-  mark(1);
+  STEP(close(s));
+  STEP(open(2, s));
   STEP(run_dinv(tb, fp.leaf_dinv, s));
-  mark(2);
-  if (h->L > 0) {
-    STEP(run_eval(h, tb, fp.panels, 0.0, s));
-    mark(3);
+  STEP(close(s));
+  if (L > 0) {
+    STEP(join(s2, s));  // skeleton blocks done
+    STEP(open(4, s));
     STEP(run_trsm(tb, fp.leaf_trsm, s));
-    mark(4);
+    STEP(close(s));
+    STEP(open(5, s));
     STEP(run_gemm(tb, fp.leaf_proj, f64, s));
-    mark(5);
-    for (int j = h->L - 1; j >= 0; --j) {
+    STEP(close(s));
+    // Level wavefront on the caller's stream.  The deferred correction of
+    // factor level k needs the sweep solutions of every level >= k and the
+    // corrected columns of level k+1, so it runs on the side stream as soon
+    // as the sweep of level k is done, beside the rest of the wavefront.
+    for (int j = L - 1; j >= 0; --j) {
+      STEP(open(8, s));
       STEP(run_zform(tb, fp.zform[j], s));
       STEP(run_lu(tb, fp.zlu[j], s));
       STEP(run_dinv(tb, fp.zdinv[j], s));
-      mark(8);
+      STEP(close(s));
       if (j >= 1) {
+        STEP(open(6, s));
         STEP(run_trsm(tb, fp.zsolve[j], s));
+        STEP(join(s, s2));
         STEP(run_gemm(tb, fp.pgemm[j], f64, s));
-        mark(6);
+        STEP(close(s));
+        STEP(open(7, s2));
+        STEP(run_gemm(tb, fp.deferred[j], f64, s2));
+        STEP(close(s2));
       }
     }
-    for (int k = h->L - 1; k >= 1; --k) STEP(run_gemm(tb, fp.deferred[k], f64, s));
-    mark(7);
+    STEP(join(s2, s));
   }
+  STEP(hipEventRecord(t_end, s));
   STEP(hipStreamSynchronize(s));
   for (double& v : h->phase_ms) v = 0.0;
-  for (size_t i = 1; i < marks.size(); ++i) {
+  for (const Bracket& br : brackets) {
     float ms = 0.f;
-    if (hipEventElapsedTime(&ms, marks[i - 1], marks[i]) == hipSuccess && phase_of[i] >= 0)
-      h->phase_ms[phase_of[i]] += ms;
+    if (br.a && br.b && hipEventElapsedTime(&ms, br.a, br.b) == hipSuccess)
+      h->phase_ms[br.phase] += ms;
   }
   {
     float ms = 0.f;
-    if (marks.size() > 1 && hipEventElapsedTime(&ms, marks.front(), marks.back()) == hipSuccess)
-      h->phase_ms[kPhases - 1] = ms;
+    if (hipEventElapsedTime(&ms, t_begin, t_end) == hipSuccess) h->phase_ms[kPhases - 1] = ms;
   }
   cleanup();
 #undef STEP

@@ -94,39 +94,51 @@ __global__ __launch_bounds__(256) void k_eval(const PT* __restrict__ X, int d, d
   }
 }
 
-constexpr int MB = kMvBlock;  // targets per workgroup (one per thread)
+constexpr int MB = kMvBlock;  // targets per workgroup
 constexpr int MS = 64;        // sources per LDS stage
 constexpr int RC = 4;         // right-hand sides per pass
 
-template <typename PT, int DM>
-__global__ __launch_bounds__(MB) void k_mv_eval(const PT* __restrict__ X, int d, double nhalf_inv_h2,
-                                                double lam, const MvTile* __restrict__ tiles,
-                                                const MvSeg* __restrict__ segs,
-                                                const double* __restrict__ x, int64_t ldx,
-                                                double* __restrict__ y, int64_t ldy,
-                                                const double* __restrict__ bsub, int64_t ldb,
-                                                int nrhs) {
-  __shared__ double sx[MS][DM + 1];
-  __shared__ double sw[MS][RC];
+// TPT targets per thread (2 for d <= 16: two independent distance/exp
+// chains per thread and half the LDS reads per pair), MB / TPT threads.
+// Source rows are read by all lanes at once (LDS broadcast), so they are
+// stored unpadded and read as 16-byte vectors.
+template <typename PT, int DM, int TPT>
+__global__ __launch_bounds__(MB / TPT) void k_mv_eval(const PT* __restrict__ X, int d,
+                                                      double nhalf_inv_h2, double lam,
+                                                      const MvTile* __restrict__ tiles,
+                                                      const MvSeg* __restrict__ segs,
+                                                      const double* __restrict__ x, int64_t ldx,
+                                                      double* __restrict__ y, int64_t ldy,
+                                                      const double* __restrict__ bsub, int64_t ldb,
+                                                      int nrhs) {
+  constexpr int NT = MB / TPT;
+  __shared__ __align__(16) double sx[MS][DM];
+  __shared__ __align__(16) double sw[MS][RC];
   const MvTile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
   const int tid = threadIdx.x;
-  const bool active = tid < t.rows;
-  const int64_t i = t.row0 + tid;
-  double xi[DM];
+  double xi[TPT][DM];
 #pragma unroll
-  for (int k = 0; k < DM; ++k) xi[k] = (active && k < d) ? (double)X[i * d + k] : 0.0;
+  for (int u = 0; u < TPT; ++u) {
+    const int r = tid + NT * u;
+    const bool active = r < t.rows;
+#pragma unroll
+    for (int k = 0; k < DM; ++k)
+      xi[u][k] = (active && k < d) ? (double)X[(t.row0 + r) * d + k] : 0.0;
+  }
 
   for (int cb = 0; cb < nrhs; cb += RC) {
     const int ncol = min(RC, nrhs - cb);
-    double acc[RC];
+    double acc[TPT][RC];
 #pragma unroll
-    for (int c = 0; c < RC; ++c) acc[c] = 0.0;
+    for (int u = 0; u < TPT; ++u)
+#pragma unroll
+      for (int c = 0; c < RC; ++c) acc[u][c] = 0.0;
     for (int s = t.seg0; s < t.seg0 + t.nseg; ++s) {
       const MvSeg g = segs[s];
       for (int j0 = 0; j0 < g.count; j0 += MS) {
         const int nj = min(MS, g.count - j0);
         __syncthreads();
-        for (int idx = tid; idx < MS * DM; idx += MB) {
+        for (int idx = tid; idx < MS * DM; idx += NT) {
           const int j = idx / DM, k = idx % DM;
           double v = 0.0;
           if (j < nj && k < d) {
@@ -135,29 +147,50 @@ __global__ __launch_bounds__(MB) void k_mv_eval(const PT* __restrict__ X, int d,
           }
           sx[j][k] = v;
         }
-        for (int idx = tid; idx < MS * RC; idx += MB) {
+        for (int idx = tid; idx < MS * RC; idx += NT) {
           const int j = idx / RC, c = idx % RC;
           sw[j][c] = (j < nj && c < ncol) ? g.w[(int64_t)(cb + c) * g.ldw + j0 + j] : 0.0;
         }
         __syncthreads();
         for (int j = 0; j < nj; ++j) {
-          double d2 = 0.0;
+          double wv[RC];
 #pragma unroll
-          for (int k = 0; k < DM; ++k) {
-            const double df = xi[k] - sx[j][k];
-            d2 = fma(df, df, d2);
+          for (int c = 0; c < RC; ++c) wv[c] = sw[j][c];
+          // two targets share one register copy of the source row; a single
+          // target reads it from LDS as it goes (a wide row would not fit)
+          double sv[TPT > 1 ? DM : 1];
+          if constexpr (TPT > 1) {
+#pragma unroll
+            for (int k = 0; k < DM; ++k) sv[k] = sx[j][k];
           }
-          const double kv = exp(d2 * nhalf_inv_h2);
 #pragma unroll
-          for (int c = 0; c < RC; ++c) acc[c] = fma(kv, sw[j][c], acc[c]);
+          for (int u = 0; u < TPT; ++u) {
+            double d2 = 0.0;
+#pragma unroll
+            for (int k = 0; k < DM; ++k) {
+              double df;
+              if constexpr (TPT > 1)
+                df = xi[u][k] - sv[k];
+              else
+                df = xi[u][k] - sx[j][k];
+              d2 = fma(df, df, d2);
+            }
+            const double kv = exp(d2 * nhalf_inv_h2);
+#pragma unroll
+            for (int c = 0; c < RC; ++c) acc[u][c] = fma(kv, wv[c], acc[u][c]);
+          }
         }
       }
     }
-    if (active) {
-      for (int c = 0; c < ncol; ++c) {
-        const double ax = lam * x[(int64_t)(cb + c) * ldx + i] + acc[c];
-        y[(int64_t)(cb + c) * ldy + i] =
-            bsub ? bsub[(int64_t)(cb + c) * ldb + i] - ax : ax;
+#pragma unroll
+    for (int u = 0; u < TPT; ++u) {
+      const int r = tid + NT * u;
+      if (r < t.rows) {
+        const int64_t i = t.row0 + r;
+        for (int c = 0; c < ncol; ++c) {
+          const double ax = lam * x[(int64_t)(cb + c) * ldx + i] + acc[u][c];
+          y[(int64_t)(cb + c) * ldy + i] = bsub ? bsub[(int64_t)(cb + c) * ldb + i] - ax : ax;
+        }
       }
     }
   }
@@ -292,8 +325,9 @@ hipError_t launch_mv_eval(const PT* X, int d, double h, double lam, const MvTile
   if (ntiles <= 0) return hipSuccess;
   const double c = -0.5 / (h * h);
 #define INVASKIT_MV(DMV)                                                                    \
-  hipLaunchKernelGGL((k_mv_eval<PT, DMV>), dim3(ntiles), dim3(MB), 0, s, X, d, c, lam,     \
-                     tiles, segs, x, ldx, y, ldy, b, ldb, nrhs)
+  hipLaunchKernelGGL((k_mv_eval<PT, DMV, (DMV <= 16 ? 2 : 1)>), dim3(ntiles),              \
+                     dim3(MB / (DMV <= 16 ? 2 : 1)), 0, s, X, d, c, lam, tiles, segs, x, ldx, y, \
+                     ldy, b, ldb, nrhs)
   if (d <= 8)
     INVASKIT_MV(8);
   else if (d <= 16)
