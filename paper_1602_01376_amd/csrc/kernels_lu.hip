@@ -339,6 +339,208 @@ __global__ __launch_bounds__(256) void k_getrf(const LuProb* __restrict__ probs)
   if (tid == 0) *pr.info = s_info;
 }
 
+// One wave per matrix, for small orders (n <= 64 RPS): the same blocked
+// algorithm and storage as k_getrf, but with no workgroup barriers -- the
+// pivot search is a wave reduction, the pivot row is broadcast by readlane
+// from the owning lane, and the panel inverse, U12 and the trailing update
+// are computed by the one wave.  This shortens the per-column chain, which
+// is what bounds the small reduced systems near the root.
+template <typename T, int W, int RPS, int KIND>
+__global__ __launch_bounds__(64) void k_getrf_w(const LuProb* __restrict__ probs) {
+  using V4 = typename Vec4<T>::type;
+  const LuProb pr = probs[blockIdx.x];
+  T* __restrict__ A = static_cast<T*>(pr.a);
+  const int n = pr.n;
+  const int lane = threadIdx.x;
+  const int lr = lane & 15, lg = lane >> 4;
+
+  extern __shared__ __align__(16) unsigned char smem[];
+  int* Ps = reinterpret_cast<int*>(smem);  // logical row -> physical row, n entries
+  __shared__ T L11[W][W + 1];
+  __shared__ T Li[W][W + 1];
+  __shared__ T Uc[W][CH];
+
+  for (int i = lane; i < n; i += 64) Ps[i] = i;
+  int info = 0;
+
+  for (int j0 = 0; j0 < n; j0 += W) {
+    const int jb = min(W, n - j0);
+    const int mr = n - j0;
+    T P[RPS][W];
+    int lpos[RPS], ph[RPS];
+#pragma unroll
+    for (int t = 0; t < RPS; ++t) {
+      const int r = lane + 64 * t;
+      lpos[t] = (r < mr) ? r : -1;
+      ph[t] = (r < mr) ? Ps[j0 + r] : 0;
+#pragma unroll
+      for (int c = 0; c < W; ++c)
+        P[t][c] = (r < mr && c < jb) ? A[(int64_t)ph[t] * n + j0 + c] : T(0);
+    }
+    static_for<W>([&](auto JJ) {
+      constexpr int jj = decltype(JJ)::value;
+      if (jj < jb) {
+        key_t<T> bk = 0;
+        uint32_t bl = 0xffffffffu;
+#pragma unroll
+        for (int t = 0; t < RPS; ++t) {
+          if (lpos[t] >= jj) {
+            const key_t<T> k = abs_key(P[t][jj]);
+            if (k > bk || (k == bk && (uint32_t)lpos[t] < bl)) {
+              bk = k;
+              bl = (uint32_t)lpos[t];
+            }
+          }
+        }
+        const key_t<T> wk = wave_max(bk);
+        const uint32_t pl = wave_min(bk == wk ? bl : 0xffffffffu);
+        // the owner: (slot, lane) of logical row pl, uniform after the reduction
+        uint32_t code = 0xffffffffu;
+#pragma unroll
+        for (int t = 0; t < RPS; ++t)
+          if ((uint32_t)lpos[t] == pl) code = ((uint32_t)t << 6) | (uint32_t)lane;
+        code = wave_min(code);
+        const int olane = (int)(code & 63u), oslot = (int)(code >> 6);
+        T prow[W];
+        static_for<RPS>([&](auto TT) {
+          constexpr int t = decltype(TT)::value;
+          if (oslot == t) {
+#pragma unroll
+            for (int c = 0; c < W; ++c) prow[c] = lane_bcast(P[t][c], olane);
+          }
+        });
+        const T pv = prow[jj];
+        const bool ok = (pv != T(0)) && isfinite(pv);
+        if (!ok && info == 0) info = j0 + jj + 1;
+#pragma unroll
+        for (int t = 0; t < RPS; ++t) {
+          if (lpos[t] == (int)pl)
+            lpos[t] = jj;
+          else if (lpos[t] == jj)
+            lpos[t] = (int)pl;
+        }
+        if (ok) {
+          const T inv = recip(pv);
+#pragma unroll
+          for (int t = 0; t < RPS; ++t) {
+            if (lpos[t] > jj) {
+              const T l = P[t][jj] * inv;
+              P[t][jj] = l;
+#pragma unroll
+              for (int c = jj + 1; c < W; ++c) P[t][c] -= l * prow[c];
+            }
+          }
+        }
+      }
+    });
+    // write back in place, new logical order, inverse of L11 (one wave: the
+    // LDS accesses of a wave complete in order, so no barrier is needed)
+#pragma unroll
+    for (int t = 0; t < RPS; ++t) {
+      const int lp = lpos[t];
+      if (lp >= 0) {
+#pragma unroll
+        for (int c = 0; c < W; ++c)
+          if (c < jb) A[(int64_t)ph[t] * n + j0 + c] = P[t][c];
+        if (lp < W) {
+#pragma unroll
+          for (int c = 0; c < W; ++c) L11[lp][c] = P[t][c];
+        }
+        Ps[j0 + lp] = ph[t];
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    {
+      T x[W];
+#pragma unroll
+      for (int q = 0; q < W; ++q) x[q] = (lane == q) ? T(1) : T(0);
+      for (int j = 0; j < jb - 1; ++j) {
+        const T l = (lane > j && lane < jb) ? L11[lane][j] : T(0);
+#pragma unroll
+        for (int q = 0; q < W; ++q) x[q] -= l * lane_bcast(x[q], j);
+      }
+      if (lane < W) {
+#pragma unroll
+        for (int q = 0; q < W; ++q) Li[lane][q] = (lane < jb) ? x[q] : T(0);
+      }
+    }
+    int uph[W / 4];
+#pragma unroll
+    for (int kk = 0; kk < W / 4; ++kk) {
+      const int k = 4 * kk + lg;
+      uph[kk] = (k < jb) ? Ps[j0 + k] : 0;
+    }
+    __builtin_amdgcn_wave_barrier();
+    const int c0 = j0 + jb;
+    for (int cb = c0; cb < n; cb += CH) {
+      for (int it = 0; it < (W / 16) * (CH / 16); ++it) {
+        const int rt = it % (W / 16), ct = it / (W / 16);
+        const int cc = cb + 16 * ct + lr;
+        V4 acc = V4{0, 0, 0, 0};
+#pragma unroll
+        for (int kk = 0; kk < W / 4; ++kk) {
+          const int k = 4 * kk + lg;
+          const T a = Li[16 * rt + lr][k];
+          const T b = (cc < n && k < jb) ? A[(int64_t)uph[kk] * n + cc] : T(0);
+          acc = mfma16(a, b, acc);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Uc[16 * rt + acc_row(T(0), lg, v)][16 * ct + lr] = acc[v];
+      }
+      __builtin_amdgcn_wave_barrier();
+      for (int idx = lane; idx < W * CH; idx += 64) {
+        const int i = idx / CH, cl = idx % CH;
+        const int cc = cb + cl;
+        if (i >= 1 && i < jb && cc < n) A[(int64_t)Ps[j0 + i] * n + cc] = Uc[i][cl];
+      }
+      const int ntr = (n - c0 + 15) / 16;
+      for (int it = 0; it < ntr; ++it) {
+        const int t0 = c0 + 16 * it;
+        const int row = t0 + lr;
+        constexpr int KG = W / 4;
+        T a[KG];
+        load_row_sigma_full(A + (int64_t)(row < n ? Ps[row] : 0) * n + j0, row < n ? W : 0, lg, a);
+        int pr4[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int rr = t0 + acc_row(T(0), lg, v);
+          pr4[v] = (rr < n) ? Ps[rr] : -1;
+        }
+        V4 cur[CH / 16];
+#pragma unroll
+        for (int ct = 0; ct < CH / 16; ++ct) {
+          const int cc = cb + 16 * ct + lr;
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            cur[ct][v] = (pr4[v] >= 0 && cc < n) ? A[(int64_t)pr4[v] * n + cc] : T(0);
+        }
+#pragma unroll
+        for (int ct = 0; ct < CH / 16; ++ct) {
+          V4 acc = V4{0, 0, 0, 0};
+#pragma unroll
+          for (int kk = 0; kk < KG; ++kk)
+            acc = mfma16(a[kk], Uc[sigma_k<T>(kk, lg)][16 * ct + lr], acc);
+          const int cc = cb + 16 * ct + lr;
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            if (pr4[v] >= 0 && cc < n) A[(int64_t)pr4[v] * n + cc] = cur[ct][v] - acc[v];
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+
+  for (int i = lane; i < n; i += 64) pr.perm[i] = Ps[i];
+  if (lane == 0) *pr.info = info;
+}
+
+template <typename T, int W, int RPS, int KIND>
+hipError_t run_getrf_w(const LuProb* probs, int count, int nmax, hipStream_t s) {
+  const size_t sm = (size_t)nmax * sizeof(int);
+  hipLaunchKernelGGL((k_getrf_w<T, W, RPS, KIND>), dim3(count), dim3(64), sm, s, probs);
+  return hipGetLastError();
+}
+
 template <typename T, int W, int RPS, int KIND>
 hipError_t run_getrf(const LuProb* probs, int count, int nmax, hipStream_t s) {
   const size_t sm = (size_t)nmax * sizeof(int);
@@ -349,6 +551,9 @@ hipError_t run_getrf(const LuProb* probs, int count, int nmax, hipStream_t s) {
 template <typename T, int KIND>
 hipError_t pick(const LuProb* probs, int count, int nmax, hipStream_t s) {
   constexpr int W = sizeof(T) == 8 ? 16 : 32;
+  if (nmax <= 64) return run_getrf_w<T, W, 1, KIND>(probs, count, nmax, s);
+  if (nmax <= 128) return run_getrf_w<T, W, 2, KIND>(probs, count, nmax, s);
+  if (nmax <= 192) return run_getrf_w<T, W, 3, KIND>(probs, count, nmax, s);
   if (nmax <= 256) return run_getrf<T, W, 1, KIND>(probs, count, nmax, s);
   if (nmax <= 512) return run_getrf<T, W, 2, KIND>(probs, count, nmax, s);
   return run_getrf<T, W, 4, KIND>(probs, count, nmax, s);

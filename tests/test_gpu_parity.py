@@ -61,11 +61,18 @@ def test_kernel_blocks(bind, pdt, odt, d):
             np.testing.assert_allclose(o.cpu().double().numpy(), ref, rtol=tol, atol=tol)
 
 
+# two batches: orders up to 1024 (four-wave kernel) and up to 192 (one wave
+# per matrix), each with ragged sizes around the 64-row blocks
+LU_SIZES = {"large": [1, 2, 17, 64, 65, 128, 200, 256, 300, 511, 512, 700, 1024],
+            "small": [1, 2, 17, 31, 33, 64, 65, 100, 128, 129, 150, 191, 192]}
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_batched_lu_and_solve(bind, dtype):
-    _say("getrf/getrs", dtype)
+@pytest.mark.parametrize("sizes_name", ["large", "small"])
+def test_batched_lu_and_solve(bind, dtype, sizes_name):
+    _say("getrf/getrs", dtype, sizes_name)
     rng = np.random.default_rng(11)
-    sizes = [1, 2, 17, 64, 65, 128, 200, 256, 300, 511, 512, 700, 1024]
+    sizes = LU_SIZES[sizes_name]
     mats = [rng.standard_normal((n, n)) for n in sizes]
     td = torch.float64 if dtype == "f64" else torch.float32
     buf, offs, n_arr, perm, info = bind.getrf_batched(mats, dtype=td)
