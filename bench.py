@@ -1,8 +1,8 @@
 """Benchmark: INV-ASKIT factor + solve of lambda*I + K~ on one MI355X.
 
 One step = refactor (every factorization phase: leaf blocks and LU, skeleton
-blocks, leaf solves, projections, skeleton sweep, deferred corrections,
-reduced systems and their LU) + solve of the right-hand sides, in the
+blocks, leaf solves, projections, skeleton sweep, reduced systems and their
+LU) + solve of the right-hand sides, in the
 precision under test, to relative residual <= 1e-10 checked with the FP64
 hierarchical product.  The headline `value` is the mixed-precision path
 (FP32 factors, FP64 top-level reduced systems, FP64 refinement); the plain
@@ -166,7 +166,7 @@ def algorithmic_work(pb, esize):
         z[c] = s[2 * c + 1] + s[2 * c + 2]
     W = {k: dict(flops=0.0, bytes=0.0, launches=0) for k in
          ("leaf_blocks", "leaf_lu", "leaf_diag_inverses", "skeleton_blocks", "leaf_solves",
-          "leaf_projections", "skeleton_sweep", "deferred_corrections", "reduced_systems")}
+          "leaf_projections", "skeleton_sweep", "reduced_systems")}
     for lf in leaves:
         m = size[lf]
         W["leaf_blocks"]["bytes"] += m * m * esize
@@ -187,12 +187,6 @@ def algorithmic_work(pb, esize):
             W["leaf_solves"]["bytes"] += 2 * m * wk * esize
             W["leaf_projections"]["flops"] += 2.0 * s[lf] * m * wk
             W["leaf_projections"]["bytes"] += (s[lf] * m + m * wk + s[lf] * wk) * esize
-            if k < L:
-                K = sum(w[anc(lf, j)] for j in range(k + 1, L + 1))
-                W["deferred_corrections"]["flops"] += 2.0 * m * K * wk
-                W["deferred_corrections"]["bytes"] += (m * K + 2 * m * wk + K * wk) * esize
-        if k < L:
-            W["deferred_corrections"]["launches"] += 1
         for j in range(L - 1, k - 1, -1):
             for bn in range((1 << j) - 1, (2 << j) - 1):
                 wk = w[anc(bn, k)]

@@ -171,12 +171,13 @@ int invaskit_device_bytes(invaskit_handle handle, size_t* bytes);
 
 /*
  * Milliseconds spent in the phases of the last factor (HIP events on the
- * stream each phase runs on; [3] and [7] run beside other phases, so the
- * phases need not add up to the total): [0] leaf block evaluation, [1] leaf LU, [2] inverses of
- * the factors' 64 x 64 diagonal blocks (leaves), [3] skeleton blocks,
- * [4] leaf solves, [5] leaf projections, [6] skeleton sweep, [7] deferred
- * corrections, [8] reduced systems (assembly, LU, diagonal-block
- * inverses), [9] total.  Writes min(n, 10) values.
+ * stream each phase runs on; [3] runs beside [0] and [1], so the phases need
+ * not add up to the total): [0] leaf block evaluation, [1] leaf LU, [2]
+ * inverses of the factors' 64 x 64 diagonal blocks (leaves), [3] skeleton
+ * blocks, [4] leaf solves, [5] leaf projections, [6] skeleton sweep, [7]
+ * unused (0: the N-sized corrections of W are applied inside each solve),
+ * [8] reduced systems (assembly, LU, diagonal-block inverses), [9] total.
+ * Writes min(n, 10) values.
  */
 int invaskit_phase_times(invaskit_handle handle, double* ms, int32_t n);
 

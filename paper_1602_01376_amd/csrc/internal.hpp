@@ -32,6 +32,14 @@ struct GemmProb {
   double alpha, beta;
 };
 
+// Grouped GEMM tiles: kGemmTileM rows (four waves of 32) by up to
+// kGemmMaxCols columns.  A product with N <= kGemmMaxCols is one column
+// tile of width 16 * ceil(N / 16); wider products are cut into tiles of
+// kGemmColChunk columns.
+constexpr int kGemmTileM = 128;
+constexpr int kGemmMaxCols = 80;
+constexpr int kGemmColChunk = 64;
+
 struct Tile3 {
   int32_t prob, tm, tn;
 };
@@ -131,12 +139,17 @@ __device__ __host__ __forceinline__ int xcd_tile(int b, int nb) {
 }
 
 // ---------------------------------------------------------------- launchers
-// shape: kGemmSquare (64 x 64 tiles) or kGemmNarrow (128 x 32, for N <= 32)
-constexpr int kGemmSquare = 0;
-constexpr int kGemmNarrow = 1;
+// transposed: the problems of this tile list compute C^T row-major (C stored
+// row-major with row stride ldc); otherwise C is column-major
 template <typename T>
 hipError_t launch_gemm(const GemmProb* probs, const GemmSeg* segs, const Tile3* tiles,
-                       int ntiles, int shape, hipStream_t s);
+                       int ntiles, bool transposed, hipStream_t s);
+// skinny form: N <= kGemvCols, M <= kGemvRows and every A column-major; one
+// workgroup per problem
+constexpr int kGemvCols = 4;
+constexpr int kGemvRows = 128;
+template <typename T>
+hipError_t launch_gemv(const GemmProb* probs, const GemmSeg* segs, int count, hipStream_t s);
 
 // kind: 0 leaf panels of the factorization, 1 reduced systems, 2 solve phase
 // (library factors, padded by 64 elements), 3 caller-owned factors

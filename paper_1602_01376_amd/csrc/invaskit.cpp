@@ -18,19 +18,22 @@
 //       blocks inverted; then, for j >= 1, the skeleton sweep of level j for
 //       every factor level k <= j at once:
 //       y_a = Z_a^-1 [p_r; p_l] and p_a = P_{a~[l~ r~]} [y_l; y_r];
-//   F5  deferred corrections, k = L-1 .. 1: every leaf's level-k columns
-//       v -= sum_{j > k} W^(j) rows * (the y-block of anc_{j-1} paired with
-//       anc_j's sibling skeleton), one grouped GEMM per level.
 //
-// F3-F5 replace the per-node "w = v - W Z V v" of Algorithm 2 by an
+// F3-F4 replace the per-node "w = v - W Z V v" of Algorithm 2 by an
 // algebraically identical schedule: after that update the children's
 // skeleton projections of w equal y itself (V w = V v - V W y = y because
 // (I + V W) y = V v), so the projection needed one level up is
-// P_{b~[l~ r~]} y (eq. (12)) and never touches N-sized data; the N-sized
-// corrections are applied afterwards, once per level.  The solve
-// (Algorithm 2) runs the same steps with the user's right-hand sides: leaf
-// solves, leaf projections, the sweep for j = L-1 .. 0, and one grouped
-// GEMM x = v - sum_j W^(j) rows * y-blocks.
+// P_{b~[l~ r~]} y (eq. (12)) and never touches N-sized data.
+//
+// The N-sized corrections are never applied to W.  Per leaf, the corrected
+// blocks satisfy W^(k) = W~^(k) - sum_{j>k} W^(j) Y^(j,k), with W~ the
+// leaf-solved skeleton blocks and Y^(j,k) blocks of the sweep solutions; in
+// matrix form W = W~ (I + U)^-1 with U strictly block-triangular.  The solve
+// needs only W y^, so it computes e = (I + U)^-1 y^ by forward substitution
+// on skeleton-sized data, top-down over the tree (e is one block per node),
+// and then x = v - W~ e.  The solve (Algorithm 2) runs: leaf solves, leaf
+// projections, the sweep for j = L-1 .. 0, the top-down pass for e, and one
+// grouped GEMM per leaf.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -89,11 +92,12 @@ const T* at(const DevBuf& b, size_t off) {
 }
 
 // One batched launch, described by table offsets into a table buffer.
-// A grouped GEMM launch: products with N <= 32 run on 128 x 32 tiles, the
-// others on 64 x 64 tiles (two kernels over one problem table).
+// A grouped GEMM launch: two tile lists over one problem table, products
+// computed as stated (tiles) and products computed transposed (tiles_n).
 struct GemmL {
   size_t probs = 0, segs = 0, tiles = 0, tiles_n = 0;
   int ntiles = 0, ntiles_n = 0;
+  int gemv = 0, nprobs = 0;  // skinny launch: one workgroup per problem
 };
 struct TrsmL {
   size_t probs = 0, tiles = 0;
@@ -120,7 +124,7 @@ struct ZformL {
 
 // The factorization schedule: leaf-level passes over every tree level at
 // once, then one wavefront step per level for the reduced systems and the
-// skeleton sweep, then the deferred corrections.
+// skeleton sweep.
 struct FactorPlan {
   EvalL leaf_eval;
   LuL leaf_lu;
@@ -133,7 +137,6 @@ struct FactorPlan {
   std::vector<DinvL> zdinv;
   std::vector<TrsmL> zsolve;   // index j >= 1: sweep step at level j
   std::vector<GemmL> pgemm;
-  std::vector<GemmL> deferred; // index k = 1 .. L-1
 };
 
 struct SolvePlan {
@@ -144,6 +147,7 @@ struct SolvePlan {
   GemmL leaf_proj;
   std::vector<TrsmL> zsolve;  // levels L-1 .. 0
   std::vector<GemmL> pgemm;   // levels L-1 .. 1
+  std::vector<GemmL> topdown; // e = (I + U)^-1 y^, levels 2 .. L
   GemmL final_;
   ~SolvePlan() {
     tables.release();
@@ -210,8 +214,7 @@ struct invaskit_handle_s {
   hipEvent_t ev[kEvents + 2] = {};
   bool have_events = false;
   // second stream of the factorization (default priority): the skeleton
-  // blocks and the deferred corrections run on it beside the leaf LU and the
-  // level wavefront
+  // blocks run on it beside the leaf block evaluation and LU
   hipStream_t side = nullptr;
   std::string err;
 
@@ -390,15 +393,20 @@ int validate(H* h, const invaskit_problem* pb, double lambda, const invaskit_opt
 }
 
 // ----------------------------------------------------------- table builders
-void gemm_tiles(std::vector<Tile3>& tiles, int prob, int M, int N, int bm, int bn) {
-  for (int tn = 0; tn < (N + bn - 1) / bn; ++tn)
-    for (int tm = 0; tm < (M + bm - 1) / bm; ++tm) tiles.push_back({prob, tm, tn});
+// padded extent of N in the grouped GEMM's column tiles
+int gemm_cols_padded(int n) {
+  if (n <= kGemmMaxCols) return 16 * ((n + 15) / 16);
+  return kGemmColChunk * ((n + kGemmColChunk - 1) / kGemmColChunk);
+}
+void gemm_tiles(std::vector<Tile3>& tiles, int prob, int M, int N) {
+  const int ntn = N <= kGemmMaxCols ? 1 : (N + kGemmColChunk - 1) / kGemmColChunk;
+  for (int tn = 0; tn < ntn; ++tn)
+    for (int tm = 0; tm < (M + kGemmTileM - 1) / kGemmTileM; ++tm) tiles.push_back({prob, tm, tn});
 }
 
 struct GemmBuilder {
   std::vector<GemmProb> probs;
   std::vector<GemmSeg> segs;
-  std::vector<Tile3> tiles, tiles_n;
   int begin(void* C, int64_t ldc, int M, int N, double alpha, double beta) {
     GemmProb p{};
     p.C = C;
@@ -410,12 +418,6 @@ struct GemmBuilder {
     p.alpha = alpha;
     p.beta = beta;
     probs.push_back(p);
-    if (M > 0 && N > 0) {
-      if (N <= 32)
-        gemm_tiles(tiles_n, (int)probs.size() - 1, M, N, 128, 32);
-      else
-        gemm_tiles(tiles, (int)probs.size() - 1, M, N, 64, 64);
-    }
     return (int)probs.size() - 1;
   }
   void seg(const void* A, int64_t lda, bool a_rm, const void* B, int64_t ldb, int k) {
@@ -431,21 +433,65 @@ struct GemmBuilder {
     probs.back().nseg++;
   }
   GemmL emit(Arena& ar) {
+    // Skinny launches (every N <= kGemvCols, M <= kGemvRows, every A
+    // column-major) take the GEMV form: one workgroup per product.
+    {
+      bool skinny = !probs.empty();
+      for (const GemmProb& p : probs) {
+        skinny = skinny && p.N <= kGemvCols && p.M <= kGemvRows;
+        for (int q = 0; q < p.nseg && skinny; ++q) skinny = segs[p.seg0 + q].a_rm == 0;
+      }
+      if (skinny) {
+        GemmL l;
+        l.gemv = 1;
+        l.nprobs = (int)probs.size();
+        l.probs = ar.add(probs);
+        l.segs = ar.add(segs);
+        return l;
+      }
+    }
+    // A product whose A operands are all row-major may be computed as
+    // C^T = B^T A^T (B^T is then a row-major operand, A^T a column-major
+    // one, and C^T is stored row-major, i.e. C column-major): chosen when
+    // that needs fewer padded tile elements (few rows, many columns).
+    std::vector<Tile3> tiles, tiles_t;
+    std::vector<int64_t> cost(probs.size(), 0);
+    auto padded = [](int M, int N) {
+      return (int64_t)((M + kGemmTileM - 1) / kGemmTileM) * kGemmTileM * gemm_cols_padded(N);
+    };
+    for (size_t i = 0; i < probs.size(); ++i) {
+      GemmProb& p = probs[i];
+      bool all_rm = p.nseg > 0;
+      for (int q = 0; q < p.nseg; ++q) {
+        cost[i] += segs[p.seg0 + q].k;
+        all_rm = all_rm && segs[p.seg0 + q].a_rm;
+      }
+      if (p.M <= 0 || p.N <= 0) continue;
+      if (all_rm && padded(p.N, p.M) < padded(p.M, p.N)) {
+        for (int q = 0; q < p.nseg; ++q) {
+          GemmSeg& g = segs[p.seg0 + q];
+          std::swap(g.A, g.B);
+          std::swap(g.lda, g.ldb);
+          g.a_rm = 1;  // B (column-major K x N) read as the row-major N x K operand
+        }
+        std::swap(p.M, p.N);
+        gemm_tiles(tiles_t, (int)i, p.M, p.N);
+      } else {
+        gemm_tiles(tiles, (int)i, p.M, p.N);
+      }
+    }
     // longest products first, so the launch does not end on a long tile;
     // stable, so a product's tiles stay consecutive
-    std::vector<int64_t> cost(probs.size(), 0);
-    for (size_t i = 0; i < probs.size(); ++i)
-      for (int g = 0; g < probs[i].nseg; ++g) cost[i] += segs[probs[i].seg0 + g].k;
     auto by_cost = [&](const Tile3& x, const Tile3& y) { return cost[x.prob] > cost[y.prob]; };
     std::stable_sort(tiles.begin(), tiles.end(), by_cost);
-    std::stable_sort(tiles_n.begin(), tiles_n.end(), by_cost);
+    std::stable_sort(tiles_t.begin(), tiles_t.end(), by_cost);
     GemmL l;
     l.probs = ar.add(probs);
     l.segs = ar.add(segs);
     l.tiles = ar.add(tiles);
     l.ntiles = (int)tiles.size();
-    l.tiles_n = ar.add(tiles_n);
-    l.ntiles_n = (int)tiles_n.size();
+    l.tiles_n = ar.add(tiles_t);
+    l.ntiles_n = (int)tiles_t.size();
     return l;
   }
 };
@@ -798,27 +844,6 @@ int plan_factor(H* h) {
       fp.pgemm[jl] = pg.emit(ar);
     }
   }
-  // deferred corrections, factor levels k = L-1 .. 1
-  fp.deferred.assign(std::max(L, 1), GemmL());
-  for (int k = L - 1; k >= 1; --k) {
-    GemmBuilder defer;
-    for (int j = 0; j < h->nleaves; ++j) {
-      const int lf = h->leaf_node(j);
-      const int m = (int)(h->nb[lf] - h->na[lf]);
-      void* slab = offv(h->slab.p, h->slab_off[j], es);
-      defer.begin(offv(slab, (int64_t)h->colk[j][k] * m, es), m, m, h->w[h->anc(lf, k)], -1.0,
-                  1.0);
-      for (int jl = L; jl > k; --jl) {
-        const int cj = h->anc(lf, jl);
-        const int par = h->anc(lf, jl - 1);
-        const int yoff = (cj & 1) ? 0 : h->s[cj];  // a left child takes the r~ rows
-        defer.seg(offv(slab, (int64_t)h->colk[j][jl] * m, es), m, false,
-                  offv(YS, h->ysw_off[par] + (int64_t)h->colp[par][k] * h->z[par] + yoff, es),
-                  h->z[par], h->w[cj]);
-      }
-    }
-    fp.deferred[k] = defer.emit(ar);
-  }
   if ((rc = dev_alloc(h, h->ftables, ar.host.size()))) return rc;
   HIP_TRY(h, hipMemcpy(h->ftables.p, ar.host.data(), ar.host.size(), hipMemcpyHostToDevice));
   return INVASKIT_OK;
@@ -828,13 +853,15 @@ int plan_factor(H* h) {
 hipError_t run_gemm(const DevBuf& tb, const GemmL& l, bool f64, hipStream_t s) {
   const GemmProb* p = at<GemmProb>(tb, l.probs);
   const GemmSeg* g = at<GemmSeg>(tb, l.segs);
+  if (l.gemv)
+    return f64 ? launch_gemv<double>(p, g, l.nprobs, s) : launch_gemv<float>(p, g, l.nprobs, s);
   hipError_t e = hipSuccess;
   if (l.ntiles > 0)
-    e = f64 ? launch_gemm<double>(p, g, at<Tile3>(tb, l.tiles), l.ntiles, kGemmSquare, s)
-            : launch_gemm<float>(p, g, at<Tile3>(tb, l.tiles), l.ntiles, kGemmSquare, s);
+    e = f64 ? launch_gemm<double>(p, g, at<Tile3>(tb, l.tiles), l.ntiles, false, s)
+            : launch_gemm<float>(p, g, at<Tile3>(tb, l.tiles), l.ntiles, false, s);
   if (e == hipSuccess && l.ntiles_n > 0)
-    e = f64 ? launch_gemm<double>(p, g, at<Tile3>(tb, l.tiles_n), l.ntiles_n, kGemmNarrow, s)
-            : launch_gemm<float>(p, g, at<Tile3>(tb, l.tiles_n), l.ntiles_n, kGemmNarrow, s);
+    e = f64 ? launch_gemm<double>(p, g, at<Tile3>(tb, l.tiles_n), l.ntiles_n, true, s)
+            : launch_gemm<float>(p, g, at<Tile3>(tb, l.tiles_n), l.ntiles_n, true, s);
   return e;
 }
 
@@ -970,10 +997,7 @@ int run_factor(H* h) {
     STEP(open(5, s));
     STEP(run_gemm(tb, fp.leaf_proj, f64, s));
     STEP(close(s));
-    // Level wavefront on the caller's stream.  The deferred correction of
-    // factor level k needs the sweep solutions of every level >= k and the
-    // corrected columns of level k+1, so it runs on the side stream as soon
-    // as the sweep of level k is done, beside the rest of the wavefront.
+    // level wavefront
     for (int j = L - 1; j >= 0; --j) {
       STEP(open(8, s));
       STEP(run_zform(tb, fp.zform[j], s));
@@ -983,15 +1007,10 @@ int run_factor(H* h) {
       if (j >= 1) {
         STEP(open(6, s));
         STEP(run_trsm(tb, fp.zsolve[j], s));
-        STEP(join(s, s2));
         STEP(run_gemm(tb, fp.pgemm[j], f64, s));
         STEP(close(s));
-        STEP(open(7, s2));
-        STEP(run_gemm(tb, fp.deferred[j], f64, s2));
-        STEP(close(s2));
       }
     }
-    STEP(join(s2, s));
   }
   STEP(hipEventRecord(t_end, s));
   STEP(hipStreamSynchronize(s));
@@ -1104,6 +1123,30 @@ int build_solve_plan(H* h, int r, SolvePlan*& out) {
     sp->zsolve.push_back(zs.emit(ar, h->zis64[jl], T64, 2));
     sp->pgemm.push_back(pg.emit(ar));
   }
+  // Top-down pass, levels i = 2 .. L: e_c = y^_c - sum_{j<i} Y^(i,j) e_{anc_j(c)},
+  // in place of y^_c (the segment of the parent's solve y paired with the
+  // sibling's skeleton).  Y^(i,j): rows of c in the parent's factor sweep
+  // solution, columns of factor level j.  Level 1 needs no correction.
+  const void* YS = h->ysw.p;
+  auto yseg = [&](int c) {  // offset of c's segment inside its parent's y
+    return (c & 1) ? 0 : h->s[c];
+  };
+  for (int i = 2; i <= L; ++i) {
+    GemmBuilder td;
+    for (int c = (1 << i) - 1; c < (2 << i) - 1; ++c) {
+      const int par = (c - 1) / 2;
+      const int wc = h->w[c];
+      td.begin(offv(sb, sy_off[par] + yseg(c), es), h->z[par], wc, r, -1.0, 1.0);
+      for (int j = 1; j < i; ++j) {
+        const int cj = h->anc(c, j);
+        const int pj = h->anc(c, j - 1);
+        td.seg(offv(const_cast<void*>(YS),
+                    h->ysw_off[par] + (int64_t)h->colp[par][j] * h->z[par] + yseg(c), es),
+               h->z[par], false, offv(sb, sy_off[pj] + yseg(cj), es), h->z[pj], h->w[cj]);
+      }
+    }
+    sp->topdown.push_back(td.emit(ar));
+  }
   sp->final_ = fin.emit(ar);
   if ((rc = dev_alloc(h, sp->tables, ar.host.size()))) return rc;
   HIP_TRY(h, hipMemcpy(sp->tables.p, ar.host.data(), ar.host.size(), hipMemcpyHostToDevice));
@@ -1124,6 +1167,7 @@ int run_solve_plan(H* h, SolvePlan* sp) {
     HIP_TRY(h, run_trsm(tb, sp->zsolve[q], s));
     HIP_TRY(h, run_gemm(tb, sp->pgemm[q], f64, s));
   }
+  for (const GemmL& g : sp->topdown) HIP_TRY(h, run_gemm(tb, g, f64, s));
   HIP_TRY(h, run_gemm(tb, sp->final_, f64, s));
   return INVASKIT_OK;
 }

@@ -7,79 +7,58 @@
 // operands live at unrelated addresses: that is how the deferred correction
 // gathers the per-level y blocks of a leaf's ancestors without copying them.
 //
-// Tiles: BM x BN outputs per workgroup of 4 waves, each wave a 32 x 32 block
-// computed as 2 x 2 MFMA 16x16x4 blocks (f64 or f32 accumulate).  Two shapes:
-// 64 x 64, and 128 x 32 for products with at most 32 columns (the deferred
-// corrections and skeleton projections, whose N is a skeleton rank).
+// Tiles: 128 rows (four waves of 32 rows, each 2 x c MFMA 16x16x4 blocks,
+// f64 or f32 accumulate) by 16 c columns, c <= 5 chosen per tile from the
+// product's N, so skeleton-rank widths (32..80) waste at most 15 columns.
 // K is staged through LDS in steps of 16, the next step's operands loaded
-// into registers while the current one computes.  The MFMA is issued with the B
-// fragment as its first operand so that the accumulator layout puts 16
-// consecutive lanes on 16 consecutive rows of column-major C (coalesced
-// stores).  Operand layout of both 16x16x4 forms: lane l supplies
-// A[l % 16][l / 16] and B[l / 16][l % 16].  Accumulator element v of lane l
-// is D[4 (l / 16) + v][l % 16] for f32 but D[l / 16 + 4 v][l % 16] for f64
-// (measured on gfx950).
+// into registers while the current one computes.
+//
+// Two output layouts.  C column-major: the MFMA takes the B fragment as its
+// first operand, so 16 consecutive lanes hold 16 consecutive rows of C
+// (coalesced column-major stores).  CT (C^T row-major, used when the
+// planner transposes a product with few rows): the A fragment goes first and
+// 16 consecutive lanes hold 16 consecutive columns.  Operand layout of both
+// 16x16x4 forms: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16];
+// accumulator element v of lane l is D[acc_row(l / 16, v)][l % 16].
+#include "device_util.hpp"
 #include "internal.hpp"
 
 namespace invaskit {
 namespace {
 
-typedef double f64x4 __attribute__((ext_vector_type(4)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-
-template <typename T>
-struct Vec4;
-template <>
-struct Vec4<double> {
-  using type = f64x4;
-};
-template <>
-struct Vec4<float> {
-  using type = f32x4;
-};
-
-// accumulator row of element v in lane group g = l / 16 (see above)
-__device__ __forceinline__ constexpr int acc_row(double, int g, int v) { return g + 4 * v; }
-__device__ __forceinline__ constexpr int acc_row(float, int g, int v) { return 4 * g + v; }
-
-__device__ __forceinline__ f64x4 mfma16(double a, double b, f64x4 c) {
-  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
-__device__ __forceinline__ f32x4 mfma16(float a, float b, f32x4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-}
-
 constexpr int BK = 16;
-constexpr int PAD = 1;
+constexpr int GBM = kGemmTileM;    // 128
+constexpr int GCB = kGemmMaxCols / 16;  // column blocks per tile, at most 5
 
-template <typename T, int BM, int BN>
+template <typename T, bool CT>
 __global__ __launch_bounds__(256) void k_gemm(const GemmProb* __restrict__ probs,
                                               const GemmSeg* __restrict__ segs,
                                               const Tile3* __restrict__ tiles) {
   using V4 = typename Vec4<T>::type;
-  constexpr int WN = BN / 32;              // waves along N
-  constexpr int NA = BM * BK / 256;        // A elements per thread
-  constexpr int NB = BN * BK / 256;        // B elements per thread
-  __shared__ T As[BK][BM + PAD];
-  __shared__ T Bs[BK][BN + PAD];
+  constexpr int BN = 16 * GCB;
+  constexpr int NA = GBM * BK / 256;         // A elements per thread per K step
+  constexpr int NB = (BN * BK + 255) / 256;  // B elements per thread per K step
+  __shared__ T As[BK][GBM + 1];
+  __shared__ T Bs[BK][BN + 1];
 
   const Tile3 t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
   const GemmProb P = probs[t.prob];
-  const int m0 = t.tm * BM;
-  const int n0 = t.tn * BN;
+  const int m0 = t.tm * GBM;
+  const int n0 = t.tn * kGemmColChunk;
+  const int nw = (P.N <= kGemmMaxCols) ? P.N : min(kGemmColChunk, P.N - n0);  // tile width
+  const int nc = (nw + 15) / 16;                                            // 1 .. GCB
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int wm = (wave / WN) * 32;
-  const int wn = (wave % WN) * 32;
+  const int wm = wave * 32;
   const int lr = lane & 15;  // fragment row / column
   const int lk = lane >> 4;  // fragment k
 
-  V4 acc[2][2];
+  V4 acc[2][GCB];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = V4{0, 0, 0, 0};
+    for (int j = 0; j < GCB; ++j) acc[i][j] = V4{0, 0, 0, 0};
 
   // K steps run over the segments in order; the next step's operands are
   // loaded into registers while the current step computes from LDS
@@ -92,8 +71,8 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmProb* __restrict__ probs
 #pragma unroll
     for (int q = 0; q < NA; ++q) {
       const int idx = tid + q * 256;
-      const int i = arm ? idx / BK : idx % BM;
-      const int kk = arm ? idx % BK : idx / BM;
+      const int i = arm ? idx / BK : idx % GBM;
+      const int kk = arm ? idx % BK : idx / GBM;
       const int gi = m0 + i, gk = k0 + kk;
       T v = 0;
       if (gi < P.M && gk < g.k)
@@ -105,8 +84,8 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmProb* __restrict__ probs
       const int idx = tid + q * 256;
       const int kk = idx % BK;
       const int j = idx / BK;
-      const int gj = n0 + j, gk = k0 + kk;
-      bv[q] = (gj < P.N && gk < g.k) ? B[(int64_t)gj * g.ldb + gk] : T(0);
+      const int gk = k0 + kk;
+      bv[q] = (j < nw && gk < g.k) ? B[(int64_t)(n0 + j) * g.ldb + gk] : T(0);
     }
   };
   const int send = P.seg0 + P.nseg;
@@ -124,12 +103,12 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmProb* __restrict__ probs
       if (arm)
         As[idx % BK][idx / BK] = av[q];
       else
-        As[idx / BM][idx % BM] = av[q];
+        As[idx / GBM][idx % GBM] = av[q];
     }
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
       const int idx = tid + q * 256;
-      Bs[idx % BK][idx / BK] = bv[q];
+      if (idx < BN * BK) Bs[idx % BK][idx / BK] = bv[q];
     }
     __syncthreads();
     k0 += BK;
@@ -141,33 +120,44 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmProb* __restrict__ probs
     if (s < send) fetch(g, k0);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
-      T a0 = As[kk + lk][wm + lr];
-      T a1 = As[kk + lk][wm + 16 + lr];
-      T b0 = Bs[kk + lk][wn + lr];
-      T b1 = Bs[kk + lk][wn + 16 + lr];
-      acc[0][0] = mfma16(b0, a0, acc[0][0]);
-      acc[0][1] = mfma16(b1, a0, acc[0][1]);
-      acc[1][0] = mfma16(b0, a1, acc[1][0]);
-      acc[1][1] = mfma16(b1, a1, acc[1][1]);
+      const T a0 = As[kk + lk][wm + lr];
+      const T a1 = As[kk + lk][wm + 16 + lr];
+#pragma unroll
+      for (int j = 0; j < GCB; ++j) {
+        if (j < nc) {
+          const T b = Bs[kk + lk][16 * j + lr];
+          if constexpr (CT) {
+            acc[0][j] = mfma16(a0, b, acc[0][j]);
+            acc[1][j] = mfma16(a1, b, acc[1][j]);
+          } else {
+            acc[0][j] = mfma16(b, a0, acc[0][j]);
+            acc[1][j] = mfma16(b, a1, acc[1][j]);
+          }
+        }
+      }
     }
   }
 
-  // with the operands swapped, accumulator element v of lane l holds
-  // C[base_m + (l & 15)][base_n + acc_row(l >> 4, v)]
   T* __restrict__ C = static_cast<T*>(P.C);
   const T alpha = (T)P.alpha;
   const T beta = (T)P.beta;
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
-    const int row = m0 + wm + i * 16 + lr;
-    if (row >= P.M) continue;
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < GCB; ++j) {
+      if (j >= nc) continue;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int col = n0 + wn + j * 16 + acc_row(T(0), lk, v);
-        if (col < P.N) {
-          T* c = C + (int64_t)col * P.ldc + row;
+        int row, col;
+        if constexpr (CT) {
+          row = m0 + wm + 16 * i + acc_row(T(0), lk, v);
+          col = 16 * j + lr;
+        } else {
+          row = m0 + wm + 16 * i + lr;
+          col = 16 * j + acc_row(T(0), lk, v);
+        }
+        if (row < P.M && col < nw) {
+          T* c = CT ? C + (int64_t)row * P.ldc + n0 + col : C + (int64_t)(n0 + col) * P.ldc + row;
           const T r = alpha * acc[i][j][v];
           *c = (P.beta != 0.0) ? beta * (*c) + r : r;
         }
@@ -176,22 +166,79 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmProb* __restrict__ probs
   }
 }
 
+// Skinny products (N <= 4 columns, every A column-major, M <= 128): one
+// workgroup per product; lane = row of C (64 rows per pass), the four waves
+// take every fourth k, so each lane has a quarter of K in flight; the four
+// partial sums are added through LDS.  Used for the small right-hand-side
+// updates of the solve (the top-down pass).
+template <typename T>
+__global__ __launch_bounds__(256) void k_gemv(const GemmProb* __restrict__ probs,
+                                              const GemmSeg* __restrict__ segs) {
+  __shared__ T part[4][64][kGemvCols];
+  const GemmProb P = probs[blockIdx.x];
+  T* __restrict__ C = static_cast<T*>(P.C);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int r0 = 0; r0 < P.M; r0 += 64) {
+    const int row = r0 + lane;
+    const bool rin = row < P.M;
+    T acc[kGemvCols];
+#pragma unroll
+    for (int c = 0; c < kGemvCols; ++c) acc[c] = T(0);
+    for (int sg = P.seg0; sg < P.seg0 + P.nseg; ++sg) {
+      const GemmSeg g = segs[sg];
+      const T* __restrict__ A = static_cast<const T*>(g.A) + (rin ? row : 0);
+      const T* __restrict__ B = static_cast<const T*>(g.B);
+#pragma unroll 8
+      for (int k = wave; k < g.k; k += 4) {
+        const T a = A[(int64_t)k * g.lda];
+#pragma unroll
+        for (int c = 0; c < kGemvCols; ++c)
+          if (c < P.N) acc[c] = fma(a, B[(int64_t)c * g.ldb + k], acc[c]);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < kGemvCols; ++c) part[wave][lane][c] = rin ? acc[c] : T(0);
+    __syncthreads();
+    if (wave == 0 && rin) {
+#pragma unroll
+      for (int c = 0; c < kGemvCols; ++c) {
+        if (c < P.N) {
+          const T sum = part[0][lane][c] + part[1][lane][c] + part[2][lane][c] + part[3][lane][c];
+          T* out = C + (int64_t)c * P.ldc + row;
+          const T r = (T)P.alpha * sum;
+          *out = (P.beta != 0.0) ? (T)P.beta * (*out) + r : r;
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
 }  // namespace
 
 template <typename T>
+hipError_t launch_gemv(const GemmProb* probs, const GemmSeg* segs, int count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_gemv<T>), dim3(count), dim3(256), 0, s, probs, segs);
+  return hipGetLastError();
+}
+template hipError_t launch_gemv<double>(const GemmProb*, const GemmSeg*, int, hipStream_t);
+template hipError_t launch_gemv<float>(const GemmProb*, const GemmSeg*, int, hipStream_t);
+
+template <typename T>
 hipError_t launch_gemm(const GemmProb* probs, const GemmSeg* segs, const Tile3* tiles,
-                       int ntiles, int shape, hipStream_t s) {
+                       int ntiles, bool transposed, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-  if (shape == kGemmNarrow)
-    hipLaunchKernelGGL((k_gemm<T, 128, 32>), dim3(ntiles), dim3(256), 0, s, probs, segs, tiles);
+  if (transposed)
+    hipLaunchKernelGGL((k_gemm<T, true>), dim3(ntiles), dim3(256), 0, s, probs, segs, tiles);
   else
-    hipLaunchKernelGGL((k_gemm<T, 64, 64>), dim3(ntiles), dim3(256), 0, s, probs, segs, tiles);
+    hipLaunchKernelGGL((k_gemm<T, false>), dim3(ntiles), dim3(256), 0, s, probs, segs, tiles);
   return hipGetLastError();
 }
 
-template hipError_t launch_gemm<double>(const GemmProb*, const GemmSeg*, const Tile3*, int, int,
+template hipError_t launch_gemm<double>(const GemmProb*, const GemmSeg*, const Tile3*, int, bool,
                                         hipStream_t);
-template hipError_t launch_gemm<float>(const GemmProb*, const GemmSeg*, const Tile3*, int, int,
+template hipError_t launch_gemm<float>(const GemmProb*, const GemmSeg*, const Tile3*, int, bool,
                                        hipStream_t);
 
 }  // namespace invaskit

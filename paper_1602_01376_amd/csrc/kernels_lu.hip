@@ -339,7 +339,7 @@ __global__ __launch_bounds__(256) void k_getrf(const LuProb* __restrict__ probs)
   if (tid == 0) *pr.info = s_info;
 }
 
-// One wave per matrix, for small orders (n <= 64 RPS): the same blocked
+// One wave per matrix, for small FP32 orders (n <= 64 RPS): the same blocked
 // algorithm and storage as k_getrf, but with no workgroup barriers -- the
 // pivot search is a wave reduction, the pivot row is broadcast by readlane
 // from the owning lane, and the panel inverse, U12 and the trailing update
@@ -551,9 +551,13 @@ hipError_t run_getrf(const LuProb* probs, int count, int nmax, hipStream_t s) {
 template <typename T, int KIND>
 hipError_t pick(const LuProb* probs, int count, int nmax, hipStream_t s) {
   constexpr int W = sizeof(T) == 8 ? 16 : 32;
-  if (nmax <= 64) return run_getrf_w<T, W, 1, KIND>(probs, count, nmax, s);
-  if (nmax <= 128) return run_getrf_w<T, W, 2, KIND>(probs, count, nmax, s);
-  if (nmax <= 192) return run_getrf_w<T, W, 3, KIND>(probs, count, nmax, s);
+  // one wave per matrix for small FP32 orders; FP64's longer per-column chain
+  // (64-bit keys and reciprocal) is better spread over four waves
+  if constexpr (sizeof(T) == 4) {
+    if (nmax <= 64) return run_getrf_w<T, W, 1, KIND>(probs, count, nmax, s);
+    if (nmax <= 128) return run_getrf_w<T, W, 2, KIND>(probs, count, nmax, s);
+    if (nmax <= 192) return run_getrf_w<T, W, 3, KIND>(probs, count, nmax, s);
+  }
   if (nmax <= 256) return run_getrf<T, W, 1, KIND>(probs, count, nmax, s);
   if (nmax <= 512) return run_getrf<T, W, 2, KIND>(probs, count, nmax, s);
   return run_getrf<T, W, 4, KIND>(probs, count, nmax, s);

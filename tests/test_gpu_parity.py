@@ -102,12 +102,24 @@ def test_batched_lu_and_solve(bind, dtype, sizes_name):
         assert _rel(x.cpu().double().numpy(), ref) < 50 * kappa * eps * np.sqrt(A.shape[0])
 
 
+# (M, N, K, A row-major).  "tiles": the matrix-core kernel (row-major A with
+# M < N runs transposed); "skinny": every N <= 4 with column-major A, which
+# and M <= 128 takes the one-workgroup-per-product GEMV form
+GEMM_SHAPES = {
+    "tiles": [(1, 1, 1, False), (16, 16, 4, False), (64, 64, 16, True), (65, 63, 17, False),
+              (200, 37, 129, True), (32, 256, 300, False), (257, 5, 64, True), (3, 70, 0, False),
+              (40, 300, 70, True), (3, 81, 50, True), (71, 500, 33, True), (130, 79, 200, False)],
+    "skinny": [(1, 1, 1, False), (40, 1, 480, False), (128, 4, 33, False), (100, 2, 600, False),
+               (71, 3, 0, False), (65, 1, 17, False)],
+}
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_grouped_gemm(bind, dtype):
-    _say("gemm_batched", dtype)
+@pytest.mark.parametrize("kind", ["tiles", "skinny"])
+def test_grouped_gemm(bind, dtype, kind):
+    _say("gemm_batched", dtype, kind)
     rng = np.random.default_rng(13)
-    shapes = [(1, 1, 1, False), (16, 16, 4, False), (64, 64, 16, True), (65, 63, 17, False),
-              (200, 37, 129, True), (32, 256, 300, False), (257, 5, 64, True), (3, 70, 0, False)]
+    shapes = GEMM_SHAPES[kind]
     probs = []
     for m, n, k, rm in shapes:
         probs.append((rng.standard_normal((m, k)), rng.standard_normal((k, n)),
