@@ -20,9 +20,12 @@
 //      double-buffered).
 //   2. The panel goes back to the rows it came from, the permutation takes
 //      the panel's logical positions, and inv(L11) is formed in LDS.
-//   3. For each chunk of 64 columns to the right: U12 = inv(L11) A12 and
-//      A22 -= L21 U12, both on the matrix cores (16 x 16 tiles), L21 read as
-//      16-byte row segments (see load_row_sigma).
+//   3. Panels come in pairs (superpanels of 2W columns): after panel a only
+//      panel b's W columns are updated; after panel b the rest of the
+//      trailing matrix is updated once with K = 2W, using the inverse of the
+//      superpanel's unit-lower block.  Each update: for each chunk of 64
+//      columns, U12 = inv(L11) A12 and A22 -= L21 U12 on the matrix cores
+//      (16 x 16 tiles), L21 read as 16-byte row segments (load_row_sigma).
 // info = j+1 for the first zero or non-finite pivot in column j (the column
 // is left unscaled and the factorization continues, as LAPACK does).  KIND
 // only separates the kernel names of the two uses (leaf blocks, reduced
@@ -117,6 +120,7 @@ __device__ __forceinline__ void static_for(F&& f) {
 template <typename T, int W, int RPS, int KIND>
 __global__ __launch_bounds__(256) void k_getrf(const LuProb* __restrict__ probs) {
   using V4 = typename Vec4<T>::type;
+  constexpr int W2 = 2 * W;
   const LuProb pr = probs[blockIdx.x];
   T* __restrict__ A = static_cast<T*>(pr.a);
   const int n = pr.n;
@@ -130,19 +134,21 @@ __global__ __launch_bounds__(256) void k_getrf(const LuProb* __restrict__ probs)
   __shared__ T s_row[2][4][W];             // each wave's candidate pivot row
   __shared__ key_t<T> s_bk[2][4];
   __shared__ uint32_t s_bl[2][4];
-  __shared__ T L11[W][W + 1];
-  __shared__ T Li[W][W + 1];              // inv(L11), row-major
-  __shared__ T Uc[W][CH];                 // U12 chunk
+  __shared__ T L11[W][W + 1];              // a panel's unit-lower block, then L21_ab
+  __shared__ T Lsup[W2][W2 + 1];           // inverse of the 2W superpanel's unit-lower block
+  __shared__ T Uc[W2][CH];                 // U12 chunk
   __shared__ int s_info;
 
   for (int i = tid; i < n; i += 256) Ps[i] = i;
   if (tid == 0) s_info = 0;
   __syncthreads();
 
-  for (int j0 = 0; j0 < n; j0 += W) {
+  // ---- factor the W columns at j0 (rows >= j0), write them back in place,
+  // give the panel's rows their logical positions, and put inv(L11) in
+  // Lsup[off .. off+W)[off .. off+W).  Returns the panel width.
+  auto panel = [&](int j0, int off) -> int {
     const int jb = min(W, n - j0);
     const int mr = n - j0;
-    // ------------------------------------------------------------ 1. panel
     T P[RPS][W];
     int lpos[RPS], ph[RPS];
 #pragma unroll
@@ -227,8 +233,8 @@ __global__ __launch_bounds__(256) void k_getrf(const LuProb* __restrict__ probs)
       }
       }
     });
-    // ---------- 2. write back in place, new logical order, inverse of L11
-    // (every thread read its Ps entries before the panel's first barrier)
+    // write back in place, new logical order (every thread read its Ps
+    // entries before the panel's first barrier)
     if (tid == 0 && info != 0 && s_info == 0) s_info = info;
 #pragma unroll
     for (int t = 0; t < RPS; ++t) {
@@ -259,52 +265,50 @@ __global__ __launch_bounds__(256) void k_getrf(const LuProb* __restrict__ probs)
       }
       if (lane < W) {
 #pragma unroll
-        for (int q = 0; q < CQ; ++q) Li[lane][wave * CQ + q] = (lane < jb) ? x[q] : T(0);
+        for (int q = 0; q < CQ; ++q)
+          Lsup[off + lane][off + wave * CQ + q] = (lane < jb) ? x[q] : T(0);
       }
     }
-    // physical rows of the panel's logical rows, as this lane's U12 k-steps
-    // read them
-    int uph[W / 4];
-#pragma unroll
-    for (int kk = 0; kk < W / 4; ++kk) {
-      const int k = 4 * kk + lg;
-      uph[kk] = (k < jb) ? Ps[j0 + k] : 0;
-    }
     __syncthreads();
-    // ---------------------------------- 3. U12 and the trailing update
-    const int c0 = j0 + jb;
-    for (int cb = c0; cb < n; cb += CH) {
-      // U12 chunk = inv(L11) A12 chunk: (W/16) x 4 output tiles over the waves
-      for (int it = wave; it < (W / 16) * (CH / 16); it += 4) {
-        const int rt = it % (W / 16), ct = it / (W / 16);
+    return jb;
+  };
+
+  // ---- trailing update of the rows below logical row r0 + KW, columns
+  // [cs, ce), by the KW rows at r0: U12 = Lsup[0..KW)^2 A12 per 64-column
+  // chunk (written back as rows r0+1 .. r0+KW-1 of U), then A22 -= L21 U12,
+  // both on the matrix cores, L21 read as 16-byte row segments.
+  auto update = [&](auto KWc, int r0, int cs, int ce) {
+    constexpr int KW = decltype(KWc)::value;
+    constexpr int KG = KW / 4;
+    const int c0 = r0 + KW;
+    const int ntr = (n - c0 + 15) / 16;
+    for (int cb = cs; cb < ce; cb += CH) {
+      for (int it = wave; it < (KW / 16) * (CH / 16); it += 4) {
+        const int rt = it % (KW / 16), ct = it / (KW / 16);
         const int cc = cb + 16 * ct + lr;
         V4 acc = V4{0, 0, 0, 0};
 #pragma unroll
-        for (int kk = 0; kk < W / 4; ++kk) {
-          const int k = 4 * kk + lg;
-          const T a = Li[16 * rt + lr][k];
-          const T b = (cc < n && k < jb) ? A[(int64_t)uph[kk] * n + cc] : T(0);
+        for (int kk = 0; kk < KG; ++kk) {
+          const T a = Lsup[16 * rt + lr][4 * kk + lg];
+          const T b = (cc < ce) ? A[(int64_t)Ps[r0 + 4 * kk + lg] * n + cc] : T(0);
           acc = mfma16(a, b, acc);
         }
 #pragma unroll
         for (int v = 0; v < 4; ++v) Uc[16 * rt + acc_row(T(0), lg, v)][16 * ct + lr] = acc[v];
       }
       __syncthreads();
-      // write U12 back (logical rows j0+1 .. j0+jb-1; row j0 is unchanged)
-      for (int idx = tid; idx < W * CH; idx += 256) {
+      // write U12 back (logical rows r0+1 .. r0+KW-1; row r0 is unchanged)
+      for (int idx = tid; idx < KW * CH; idx += 256) {
         const int i = idx / CH, cl = idx % CH;
         const int cc = cb + cl;
-        if (i >= 1 && i < jb && cc < n) A[(int64_t)Ps[j0 + i] * n + cc] = Uc[i][cl];
+        if (i >= 1 && cc < ce) A[(int64_t)Ps[r0 + i] * n + cc] = Uc[i][cl];
       }
-      // A22[c0:n, chunk] -= L21 U12: wave w takes 16-row tiles w, w+4, ...
-      const int ntr = (n - c0 + 15) / 16;
       for (int it = wave; it < ntr; it += 4) {
         const int t0 = c0 + 16 * it;
         const int row = t0 + lr;
-        constexpr int KG = W / 4;
         T a[KG];
-        // a full panel (j0 + W <= n here): whole row segments, branch-free
-        load_row_sigma_full(A + (int64_t)(row < n ? Ps[row] : 0) * n + j0, row < n ? W : 0, lg, a);
+        // r0 + KW <= n here: whole row segments, branch-free
+        load_row_sigma_full(A + (int64_t)(row < n ? Ps[row] : 0) * n + r0, row < n ? KW : 0, lg, a);
         int pr4[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -317,7 +321,7 @@ __global__ __launch_bounds__(256) void k_getrf(const LuProb* __restrict__ probs)
           const int cc = cb + 16 * ct + lr;
 #pragma unroll
           for (int v = 0; v < 4; ++v)
-            cur[ct][v] = (pr4[v] >= 0 && cc < n) ? A[(int64_t)pr4[v] * n + cc] : T(0);
+            cur[ct][v] = (pr4[v] >= 0 && cc < ce) ? A[(int64_t)pr4[v] * n + cc] : T(0);
         }
 #pragma unroll
         for (int ct = 0; ct < CH / 16; ++ct) {
@@ -328,11 +332,59 @@ __global__ __launch_bounds__(256) void k_getrf(const LuProb* __restrict__ probs)
           const int cc = cb + 16 * ct + lr;
 #pragma unroll
           for (int v = 0; v < 4; ++v)
-            if (pr4[v] >= 0 && cc < n) A[(int64_t)pr4[v] * n + cc] = cur[ct][v] - acc[v];
+            if (pr4[v] >= 0 && cc < ce) A[(int64_t)pr4[v] * n + cc] = cur[ct][v] - acc[v];
         }
       }
       __syncthreads();
     }
+  };
+
+  // Superpanels of 2W columns: panel a, the update of panel b's columns by
+  // panel a, panel b, then one pass over the rest of the trailing matrix
+  // with K = 2W -- half the passes of a W-wide schedule, with the panels
+  // still W wide in registers.  Rows never move, so panel a's multipliers
+  // stay valid under panel b's pivoting.  One panel per iteration (the
+  // panel code is inlined once).
+  for (int j0 = 0; j0 < n; j0 += W) {
+    const bool second = ((j0 / W) & 1) != 0;  // panel b of its superpanel
+    panel(j0, second ? W : 0);
+    if (j0 + W >= n) break;  // nothing to the right
+    if (!second) {
+      update(std::integral_constant<int, W>{}, j0, j0 + W, min(n, j0 + W2));
+      continue;
+    }
+    // Both panels of the superpanel at J0 are full.  Its unit-lower block
+    // is [[L_a, 0], [L_ab, L_b]]; the inverse has the lower-left block
+    // X = -inv(L_b) L_ab inv(L_a), with L_ab = panel b's rows in panel a's
+    // columns.
+    const int J0 = j0 - W;
+    for (int idx = tid; idx < W * W; idx += 256) {
+      const int i = idx / W, c = idx % W;
+      L11[i][c] = A[(int64_t)Ps[J0 + W + i] * n + J0 + c];
+      Lsup[i][W + c] = T(0);
+    }
+    __syncthreads();
+    for (int it = wave; it < (W / 16) * (W / 16); it += 4) {  // Uc = L_ab inv(L_a)
+      const int rt = it % (W / 16), ct = it / (W / 16);
+      V4 acc = V4{0, 0, 0, 0};
+#pragma unroll
+      for (int kk = 0; kk < W / 4; ++kk)
+        acc = mfma16(L11[16 * rt + lr][4 * kk + lg], Lsup[4 * kk + lg][16 * ct + lr], acc);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Uc[16 * rt + acc_row(T(0), lg, v)][16 * ct + lr] = acc[v];
+    }
+    __syncthreads();
+    for (int it = wave; it < (W / 16) * (W / 16); it += 4) {  // X = -inv(L_b) Uc
+      const int rt = it % (W / 16), ct = it / (W / 16);
+      V4 acc = V4{0, 0, 0, 0};
+#pragma unroll
+      for (int kk = 0; kk < W / 4; ++kk)
+        acc = mfma16(Lsup[W + 16 * rt + lr][W + 4 * kk + lg], Uc[4 * kk + lg][16 * ct + lr], acc);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Lsup[W + 16 * rt + acc_row(T(0), lg, v)][16 * ct + lr] = -acc[v];
+    }
+    __syncthreads();
+    update(std::integral_constant<int, W2>{}, J0, J0 + W2, n);
   }
 
   for (int i = tid; i < n; i += 256) pr.perm[i] = Ps[i];
