@@ -136,6 +136,26 @@ int invaskit_factor(const invaskit_problem* problem, double lambda,
                     invaskit_handle* out);
 
 /*
+ * Factor lambda_i I + K~ for n_lambda values of lambda (Section II-C: only
+ * the leaf LU, W and the reduced systems depend on lambda).  The kernel
+ * blocks -- the leaf blocks K_aa and the skeleton blocks of every level --
+ * are evaluated once, without lambda, and reused for every lambda (and by
+ * invaskit_refactor on these handles); lambda_i is added to the leaf
+ * diagonals.  out[i] receives the handle for lambdas[i]; each owns its
+ * factors (invaskit_device_bytes) and the handles share the evaluated
+ * blocks (leaf blocks plus skeleton blocks, the size of one handle's leaf
+ * factors and W storage), which are freed with the last of them.
+ * Arguments, streams and errors as invaskit_factor; every lambda is
+ * validated before any work.  Returns the first non-OK status; a handle
+ * whose factorization reported E_SINGULAR is still returned, but if a
+ * handle cannot be created at all, the ones already made are destroyed and
+ * every out[i] is NULL.
+ */
+int invaskit_factor_sweep(const invaskit_problem* problem, const double* lambdas,
+                          int32_t n_lambda, const invaskit_options* options, void* hip_stream,
+                          invaskit_handle* out);
+
+/*
  * Refactor an existing handle for a new lambda (Section II-C, refactoring
  * for a different lambda): skeletons and P are reused, leaf LU, W and the
  * reduced systems are recomputed.  Same errors as invaskit_factor.

@@ -58,6 +58,7 @@ def _load():
     sig = {
         "invaskit_default_options": (C.c_int, [vp]),
         "invaskit_factor": (C.c_int, [vp, dbl, vp, vp, vp]),
+        "invaskit_factor_sweep": (C.c_int, [vp, vp, i32, vp, vp, vp]),
         "invaskit_refactor": (C.c_int, [vp, dbl]),
         "invaskit_solve": (C.c_int, [vp, vp, i64, i64, vp, i64, vp]),
         "invaskit_matvec": (C.c_int, [vp, vp, i64, i64, vp, i64]),
@@ -81,7 +82,8 @@ def _load():
 
 
 _lib = _load()
-EXPORTED = ("invaskit_default_options", "invaskit_factor", "invaskit_refactor", "invaskit_solve",
+EXPORTED = ("invaskit_default_options", "invaskit_factor", "invaskit_factor_sweep",
+            "invaskit_refactor", "invaskit_solve",
             "invaskit_matvec", "invaskit_device_bytes", "invaskit_phase_times",
             "invaskit_destroy", "invaskit_status_string", "invaskit_last_error",
             "invaskit_getrf_batched", "invaskit_getrs_batched", "invaskit_kernel_blocks",
@@ -130,6 +132,21 @@ class Factorization:
     def __init__(self, problem, lam: float, precision: str = "fp64",
                  fp64_top_levels: int = 4, refine_tol: float = 1e-10,
                  max_refine_iters: int = 30, points=None, p_values=None):
+        pb, opt = self._prepare(problem, lam, precision, fp64_top_levels, refine_tol,
+                                max_refine_iters, points, p_values)
+        self._handle = C.c_void_p()
+        st = _lib.invaskit_factor(C.byref(pb), self.lam, C.byref(opt), _stream(),
+                                  C.byref(self._handle))
+        if st != OK:
+            msg = last_error(self._handle if self._handle.value else None)
+            if self._handle.value:
+                _lib.invaskit_destroy(self._handle)
+                self._handle = C.c_void_p()
+            raise InvaskitError(st, msg)
+
+    def _prepare(self, problem, lam, precision, fp64_top_levels, refine_tol, max_refine_iters,
+                 points, p_values):
+        """Marshal the problem and options (the arrays stay alive with self)."""
         self.n = problem.n
         self.lam = float(lam)
         self.precision = precision
@@ -155,15 +172,7 @@ class Factorization:
         opt.fp64_top_levels = int(fp64_top_levels)
         opt.refine_tol = float(refine_tol)
         opt.max_refine_iters = int(max_refine_iters)
-        self._handle = C.c_void_p()
-        st = _lib.invaskit_factor(C.byref(pb), self.lam, C.byref(opt), _stream(),
-                                  C.byref(self._handle))
-        if st != OK:
-            msg = last_error(self._handle if self._handle.value else None)
-            if self._handle.value:
-                _lib.invaskit_destroy(self._handle)
-                self._handle = C.c_void_p()
-            raise InvaskitError(st, msg)
+        return pb, opt
 
     @property
     def handle(self):
@@ -355,3 +364,30 @@ def gemm_batched(problems, dtype=torch.float64, alpha=1.0, beta=0.0):
     for i in range(cnt):
         out.append(tc[c_off[i]:c_off[i] + m[i] * n[i]].reshape(int(n[i]), int(m[i])).t())
     return out
+
+
+def factor_sweep(problem, lams, precision: str = "fp64", fp64_top_levels: int = 4,
+                 refine_tol: float = 1e-10, max_refine_iters: int = 30, points=None,
+                 p_values=None):
+    """One Factorization per lambda in `lams` (invaskit_factor_sweep): the
+    kernel blocks are evaluated once and shared by the handles."""
+    lams = [float(v) for v in lams]
+    objs = [Factorization.__new__(Factorization) for _ in lams]
+    pb, opt = objs[0]._prepare(problem, lams[0], precision, fp64_top_levels, refine_tol,
+                               max_refine_iters, points, p_values)
+    for o, lam in zip(objs[1:], lams[1:]):
+        o.n, o.lam, o.precision = objs[0].n, lam, precision
+        o._points, o._p = objs[0]._points, objs[0]._p
+        o._keep = objs[0]
+    arr = (C.c_double * len(lams))(*lams)
+    handles = (C.c_void_p * len(lams))()
+    st = _lib.invaskit_factor_sweep(C.byref(pb), arr, len(lams), C.byref(opt), _stream(),
+                                    handles)
+    for o, hnd in zip(objs, handles):
+        o._handle = C.c_void_p(hnd)
+    if st != OK:
+        msg = last_error(next((C.c_void_p(hd) for hd in handles if hd), None))
+        for o in objs:
+            o.close()
+        raise InvaskitError(st, msg)
+    return objs

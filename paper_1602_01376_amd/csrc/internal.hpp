@@ -164,6 +164,12 @@ hipError_t launch_diag_inv(const DiagInvProb* probs, int count, hipStream_t s);
 template <typename T>
 hipError_t launch_getrf(const LuProb* probs, int count, int nmax, int kind, hipStream_t s);
 
+// adds shift to the diagonal of each square block (rows x rows, leading
+// dimension ld) of the table: the lambda of a factorization that reuses
+// kernel blocks evaluated without it
+template <typename T>
+hipError_t launch_shift_diag(const EvalBlock* blocks, int count, double shift, hipStream_t s);
+
 template <typename PT, typename T>
 hipError_t launch_eval(const PT* X, int d, double h, double shift, const EvalBlock* blocks,
                        const Tile3* tiles, int ntiles, hipStream_t s);

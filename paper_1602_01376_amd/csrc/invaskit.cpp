@@ -115,7 +115,20 @@ struct DinvL {
 };
 struct EvalL {
   size_t blocks = 0, tiles = 0;
-  int ntiles = 0;
+  int ntiles = 0, nblocks = 0;
+};
+
+// Kernel blocks of a problem evaluated without lambda (leaf blocks K_aa and
+// the skeleton blocks of every level, in the layout of the factor storage),
+// shared by the handles of a lambda sweep: only the leaf LU, W and the
+// reduced systems depend on lambda.
+struct KernelCache {
+  DevBuf leaf, slab;
+  bool valid = false;
+  ~KernelCache() {
+    leaf.release();
+    slab.release();
+  }
 };
 struct ZformL {
   size_t probs = 0;
@@ -216,6 +229,7 @@ struct invaskit_handle_s {
   // second stream of the factorization (default priority): the skeleton
   // blocks run on it beside the leaf block evaluation and LU
   hipStream_t side = nullptr;
+  std::shared_ptr<KernelCache> kcache;  // set for the handles of a lambda sweep
   std::string err;
 
   int level(int node) const {
@@ -657,6 +671,11 @@ int plan_factor(H* h) {
   if ((rc = dev_alloc(h, h->leafPerm, sizeof(int32_t) * h->N))) return rc;
   if ((rc = dev_alloc(h, h->leafInfo, sizeof(int32_t) * h->nleaves))) return rc;
   if ((rc = dev_alloc(h, h->slab, h->slab_off[h->nleaves] * es))) return rc;
+  if (h->kcache && !h->kcache->leaf.p) {
+    if ((rc = dev_alloc(h, h->kcache->leaf, h->lu_off[h->nleaves] * es))) return rc;
+    if ((rc = dev_alloc(h, h->kcache->slab, std::max<int64_t>(h->slab_off[h->nleaves], 1) * es)))
+      return rc;
+  }
   if ((rc = dev_alloc(h, h->Z64, (z64n + kDiagBlock) * 8))) return rc;
   if ((rc = dev_alloc(h, h->ZT, (zTn + kDiagBlock) * es))) return rc;
   if ((rc = dev_alloc(h, h->zperm, sizeof(int32_t) * std::max<int64_t>(zpn, 1)))) return rc;
@@ -755,6 +774,7 @@ int plan_factor(H* h) {
     fp.leaf_eval.blocks = ar.add(lblocks);
     fp.leaf_eval.tiles = ar.add(ltiles);
     fp.leaf_eval.ntiles = (int)ltiles.size();
+    fp.leaf_eval.nblocks = (int)lblocks.size();
     // largest matrices first: one workgroup per matrix, so the launch's tail
     // is set by the matrices dispatched last
     auto by_order = [](const LuProb& x, const LuProb& y) { return x.n > y.n; };
@@ -973,15 +993,42 @@ int run_factor(H* h) {
   STEP(hipEventRecord(t_begin, s));
   // the side stream starts after everything already on the caller's stream
   STEP(join(s, s2));
+  // Kernel blocks.  A sweep handle evaluates them without lambda once into
+  // the shared cache and afterwards copies them back; lambda is then added
+  // to the leaf diagonals.
+  KernelCache* kc = h->kcache.get();
+  const bool cached = kc && kc->valid;
+  const size_t es = h->tsize();
   if (L > 0) {
     STEP(open(3, s2));
-    STEP(run_eval(h, tb, fp.panels, 0.0, s2));
+    if (cached) {
+      STEP(hipMemcpyAsync(h->slab.p, kc->slab.p, h->slab_off[h->nleaves] * es,
+                          hipMemcpyDeviceToDevice, s2));
+    } else {
+      STEP(run_eval(h, tb, fp.panels, 0.0, s2));
+      if (kc)
+        STEP(hipMemcpyAsync(kc->slab.p, h->slab.p, h->slab_off[h->nleaves] * es,
+                            hipMemcpyDeviceToDevice, s2));
+    }
     STEP(close(s2));
   }
   if (!f64 && h->P32.p && h->p_off[h->nn] > 0)
     STEP(launch_convert_f64_f32(h->P64, static_cast<float*>(h->P32.p), h->p_off[h->nn], s));
   STEP(open(0, s));
-  STEP(run_eval(h, tb, fp.leaf_eval, h->lam, s));
+  if (!kc) {
+    STEP(run_eval(h, tb, fp.leaf_eval, h->lam, s));
+  } else {
+    const size_t lb = h->lu_off[h->nleaves] * es;
+    if (cached) {
+      STEP(hipMemcpyAsync(h->leafLU.p, kc->leaf.p, lb, hipMemcpyDeviceToDevice, s));
+    } else {
+      STEP(run_eval(h, tb, fp.leaf_eval, 0.0, s));
+      STEP(hipMemcpyAsync(kc->leaf.p, h->leafLU.p, lb, hipMemcpyDeviceToDevice, s));
+    }
+    const EvalBlock* lbk = at<EvalBlock>(tb, fp.leaf_eval.blocks);
+    STEP(f64 ? launch_shift_diag<double>(lbk, fp.leaf_eval.nblocks, h->lam, s)
+             : launch_shift_diag<float>(lbk, fp.leaf_eval.nblocks, h->lam, s));
+  }
   STEP(close(s));
   STEP(open(1, s));
   STEP(run_lu(tb, fp.leaf_lu, s));
@@ -1014,6 +1061,7 @@ int run_factor(H* h) {
   }
   STEP(hipEventRecord(t_end, s));
   STEP(hipStreamSynchronize(s));
+  if (kc) kc->valid = true;
   for (double& v : h->phase_ms) v = 0.0;
   for (const Bracket& br : brackets) {
     float ms = 0.f;
@@ -1386,14 +1434,17 @@ int invaskit_default_options(invaskit_options* opt) {
   return INVASKIT_OK;
 }
 
-int invaskit_factor(const invaskit_problem* pb, double lambda, const invaskit_options* opt,
-                    void* hip_stream, invaskit_handle* out) {
-  if (!out) return fail_h(nullptr, INVASKIT_E_ARG, "out is NULL");
-  *out = nullptr;
-  int rc = validate(nullptr, pb, lambda, opt);
-  if (rc) return rc;
-  if ((rc = check_device(nullptr))) return rc;
+}  // extern "C"
+
+namespace {
+// a handle for a validated problem, planned and factored; *out is set
+// whenever the handle was created (also when the factorization reports a
+// zero pivot)
+int make_handle(const invaskit_problem* pb, double lambda, const invaskit_options* opt,
+                void* hip_stream, std::shared_ptr<KernelCache> cache, invaskit_handle* out) {
+  int rc;
   std::unique_ptr<H> h(new H());
+  h->kcache = std::move(cache);
   invaskit_options o;
   invaskit_default_options(&o);
   if (opt) o = *opt;
@@ -1421,6 +1472,46 @@ int invaskit_factor(const invaskit_problem* pb, double lambda, const invaskit_op
   rc = run_factor(h.get());
   *out = h.release();
   return rc;
+}
+}  // namespace
+
+extern "C" {
+
+int invaskit_factor(const invaskit_problem* pb, double lambda, const invaskit_options* opt,
+                    void* hip_stream, invaskit_handle* out) {
+  if (!out) return fail_h(nullptr, INVASKIT_E_ARG, "out is NULL");
+  *out = nullptr;
+  int rc = validate(nullptr, pb, lambda, opt);
+  if (rc) return rc;
+  if ((rc = check_device(nullptr))) return rc;
+  return make_handle(pb, lambda, opt, hip_stream, nullptr, out);
+}
+
+int invaskit_factor_sweep(const invaskit_problem* pb, const double* lambdas, int32_t n_lambda,
+                          const invaskit_options* opt, void* hip_stream, invaskit_handle* out) {
+  if (!out || !lambdas || n_lambda < 1)
+    return fail_h(nullptr, INVASKIT_E_ARG, "out, lambdas and n_lambda >= 1 are required");
+  for (int32_t i = 0; i < n_lambda; ++i) out[i] = nullptr;
+  for (int32_t i = 0; i < n_lambda; ++i) {
+    int rc = validate(nullptr, pb, lambdas[i], opt);
+    if (rc) return rc;
+  }
+  int rc = check_device(nullptr);
+  if (rc) return rc;
+  auto cache = std::make_shared<KernelCache>();
+  int first = INVASKIT_OK;
+  for (int32_t i = 0; i < n_lambda; ++i) {
+    rc = make_handle(pb, lambdas[i], opt, hip_stream, cache, &out[i]);
+    if (rc != INVASKIT_OK && first == INVASKIT_OK) first = rc;
+    if (!out[i]) {  // not created: release the others
+      for (int32_t k = 0; k < i; ++k) {
+        delete out[k];
+        out[k] = nullptr;
+      }
+      return rc;
+    }
+  }
+  return first;
 }
 
 int invaskit_refactor(invaskit_handle h, double lambda) {

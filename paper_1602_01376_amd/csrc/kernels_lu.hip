@@ -315,24 +315,30 @@ __global__ __launch_bounds__(256) void k_getrf(const LuProb* __restrict__ probs)
           const int rr = t0 + acc_row(T(0), lg, v);
           pr4[v] = (rr < n) ? Ps[rr] : -1;
         }
-        V4 cur[CH / 16];
+        // the chunk's 16-column blocks in passes of CTB, so that K = 2W keeps
+        // about as many operands live as K = W
+        constexpr int CTB = (CH / 16) * W / KW;
 #pragma unroll
-        for (int ct = 0; ct < CH / 16; ++ct) {
-          const int cc = cb + 16 * ct + lr;
+        for (int c1 = 0; c1 < CH / 16; c1 += CTB) {
+          V4 cur[CTB];
 #pragma unroll
-          for (int v = 0; v < 4; ++v)
-            cur[ct][v] = (pr4[v] >= 0 && cc < ce) ? A[(int64_t)pr4[v] * n + cc] : T(0);
-        }
+          for (int q = 0; q < CTB; ++q) {
+            const int cc = cb + 16 * (c1 + q) + lr;
 #pragma unroll
-        for (int ct = 0; ct < CH / 16; ++ct) {
-          V4 acc = V4{0, 0, 0, 0};
+            for (int v = 0; v < 4; ++v)
+              cur[q][v] = (pr4[v] >= 0 && cc < ce) ? A[(int64_t)pr4[v] * n + cc] : T(0);
+          }
 #pragma unroll
-          for (int kk = 0; kk < KG; ++kk)
-            acc = mfma16(a[kk], Uc[sigma_k<T>(kk, lg)][16 * ct + lr], acc);
-          const int cc = cb + 16 * ct + lr;
+          for (int q = 0; q < CTB; ++q) {
+            V4 acc = V4{0, 0, 0, 0};
 #pragma unroll
-          for (int v = 0; v < 4; ++v)
-            if (pr4[v] >= 0 && cc < ce) A[(int64_t)pr4[v] * n + cc] = cur[ct][v] - acc[v];
+            for (int kk = 0; kk < KG; ++kk)
+              acc = mfma16(a[kk], Uc[sigma_k<T>(kk, lg)][16 * (c1 + q) + lr], acc);
+            const int cc = cb + 16 * (c1 + q) + lr;
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+              if (pr4[v] >= 0 && cc < ce) A[(int64_t)pr4[v] * n + cc] = cur[q][v] - acc[v];
+          }
         }
       }
       __syncthreads();

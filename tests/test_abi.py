@@ -149,6 +149,24 @@ def test_nonfinite_lambda_rejected(small_problem):
     assert st == -1 and "lambda" in msg
 
 
+def test_sweep_arguments_rejected(small_problem):
+    """invaskit_factor_sweep validates every lambda and its arrays before any
+    device work; out entries stay NULL."""
+    from paper_1602_01376_amd import binding
+    lib = binding.library()
+    raw, keep = _raw_problem(small_problem)
+    out = (C.c_void_p * 3)()
+    lams = (C.c_double * 3)(1e-2, float("inf"), 1e-1)
+    assert lib.invaskit_factor_sweep(C.byref(raw), lams, 3, None, None, out) == -1
+    assert "lambda" in binding.last_error()
+    assert all(v is None for v in out)
+    assert lib.invaskit_factor_sweep(C.byref(raw), lams, 0, None, None, out) == -1
+    assert lib.invaskit_factor_sweep(C.byref(raw), None, 3, None, None, out) == -1
+    bad, keep2 = _raw_problem(small_problem, d=0)
+    ok = (C.c_double * 2)(1e-2, 1e-1)
+    assert lib.invaskit_factor_sweep(C.byref(bad), ok, 2, None, None, out) == -1
+
+
 def test_null_handle_calls_are_rejected():
     from paper_1602_01376_amd import binding
     lib = binding.library()

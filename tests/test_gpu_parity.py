@@ -237,6 +237,35 @@ def test_refactor_new_lambda(bind, problems):
     fac.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_lambda_sweep(bind, problems, prec):
+    """Section II-C: one evaluation of the kernel blocks, one factorization
+    per lambda; every handle against the oracle at its own lambda."""
+    _say("lambda sweep", prec)
+    pb, _ = problems("susy", dict(n=8192, depth=5))
+    b = rhs_for(pb, nrhs=2)
+    lams = [1e-4, 1e-2, 0.3]
+    facs = bind.factor_sweep(pb, lams, precision=prec)
+    tol = 1e-10 if prec == "fp64" else 1e-7
+
+    def check(fac, lam):
+        x, info, st = fac.solve(torch.from_numpy(b), return_info=True)
+        assert st == 0 and info["final_rel_residual"] <= 1e-10
+        x_ref = oracle.solve(oracle.factorize(pb, lam), b)
+        assert _rel(x.cpu().numpy(), x_ref) <= tol, lam
+
+    for lam, fac in zip(lams, facs):
+        check(fac, lam)
+    # handles are independent: close one, refactor another from the shared
+    # kernel blocks at a new lambda, and use the third
+    facs[0].close()
+    facs[1].refactor(3e-3)
+    check(facs[1], 3e-3)
+    check(facs[2], lams[2])
+    for f in facs:
+        f.close()
+
+
 def test_singular_leaf_is_reported(bind):
     _say("singular leaf")
     pb = make_problem("tiny", n=256, depth=2)
