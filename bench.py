@@ -269,6 +269,12 @@ def main():
     ap.add_argument("--depth", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["mixed", "fp64", "both"], default="both")
+    ap.add_argument("--tune", choices=["auto", "off"], default="auto",
+                    help="tile autotuning of the leaf LU and leaf solves")
+    ap.add_argument("--lu-panel", type=int, default=0, choices=[0, 16, 32],
+                    help="fix the leaf LU panel width (0: per --tune)")
+    ap.add_argument("--trsm-cols", type=int, default=0, choices=[0, 16, 32],
+                    help="fix the leaf solves' right-hand sides per workgroup (0: per --tune)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the HBM traffic record from two rocprofv3 counter runs of "
                          "this script (FETCH_SIZE, WRITE_SIZE) and exit")
@@ -336,8 +342,11 @@ def main():
     results = {}
     modes = ["mixed", "fp64"] if args.only == "both" else [args.only]
     for mode in modes:
-        fac = binding.Factorization(pb, lam, precision=mode, points=X, p_values=P)
-        log(f"{mode}: device bytes {fac.device_bytes() / 2**30:.2f} GiB")
+        fac = binding.Factorization(pb, lam, precision=mode, points=X, p_values=P,
+                                    tune=args.tune, leaf_lu_panel=args.lu_panel,
+                                    leaf_trsm_cols=args.trsm_cols)
+        tiles = fac.tile_config()  # the first factor's trials, if it tuned
+        log(f"{mode}: device bytes {fac.device_bytes() / 2**30:.2f} GiB, tiles {tiles}")
         for _ in range(args.warmup):
             fac.refactor(lam)
             fac.solve(b, return_info=True, check=False)
@@ -365,7 +374,7 @@ def main():
             unrefined_rel_residual=info["unrefined_rel_residual"],
             iterations=info["iterations"], converged=bool(info["converged"] or mode == "fp64"),
             status=st, phase_ms={k: v / args.steps for k, v in phases.items()},
-            device_gib=fac.device_bytes() / 2**30)
+            device_gib=fac.device_bytes() / 2**30, tiles=tiles)
         log(mode, json.dumps(results[mode]))
         fac.close()
         del fac

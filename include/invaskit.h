@@ -97,8 +97,43 @@ typedef struct invaskit_options {
   double refine_tol;        /* mixed mode: stop when |b - A x|_2 / |b|_2 <= tol
                                for every column (default 1e-10)                   */
   int32_t max_refine_iters; /* mixed mode: iteration cap (default 30)             */
-  int32_t reserved0;
+  int32_t tune;             /* INVASKIT_TUNE_AUTO (default) or _OFF, see below   */
+  int32_t leaf_lu_panel;    /* 0 (default): per `tune`; 16 or 32: LU panel width
+                               of the leaf blocks                                 */
+  int32_t leaf_trsm_cols;   /* 0 (default): per `tune`; 16 or 32: right-hand
+                               sides per workgroup in the leaf solves of the
+                               factorization                                      */
+  int32_t reserved0;        /* set to 0                                          */
 } invaskit_options;
+
+/*
+ * Tile autotuning.  The two largest launches of a factorization, the LU of
+ * the leaf blocks (Algorithm 1's leaf factorization) and the leaf solves of
+ * every level's panel columns (Algorithm 2 at the leaves), each have two
+ * tile shapes: an LU panel width of 16 or 32, and 16 or 32 right-hand sides
+ * per workgroup (32 reuses each factor tile for twice the columns but needs
+ * twice the LDS, so fewer workgroups share a compute unit).  Which is faster
+ * depends on the leaf sizes, the ranks and the precision.
+ *
+ *  INVASKIT_TUNE_AUTO  a launch whose shape class (operation, precision,
+ *                      largest order, number of systems and total work, in
+ *                      half-octave bins) is not yet in the process-wide
+ *                      tuning table is timed with each candidate, twice, on
+ *                      the factorization's own data (inputs re-evaluated
+ *                      before every trial: both launches work in place);
+ *                      the faster is recorded and used from then on by every
+ *                      handle.  The first factorization of a new shape class
+ *                      therefore takes longer (about four extra leaf LUs and
+ *                      leaf solves).
+ *  INVASKIT_TUNE_OFF   the built-in defaults (LU panel 32 in FP32 and 16 in
+ *                      FP64; 16 right-hand sides), no timing.
+ * A nonzero leaf_lu_panel or leaf_trsm_cols fixes that choice whatever
+ * `tune` says.  32 right-hand sides need (32 + 1) * elem + 4 bytes of LDS
+ * per row of the largest leaf; if that exceeds 160 KiB (FP64 leaves above
+ * 611 points) AUTO keeps 16 and a fixed 32 fails with INVASKIT_E_ARG.
+ */
+#define INVASKIT_TUNE_AUTO 0
+#define INVASKIT_TUNE_OFF  1
 
 typedef struct invaskit_solve_info {
   int32_t iterations;            /* refinement iterations taken (0 in FP64 mode) */
@@ -200,6 +235,30 @@ int invaskit_device_bytes(invaskit_handle handle, size_t* bytes);
  * Writes min(n, 10) values.
  */
 int invaskit_phase_times(invaskit_handle handle, double* ms, int32_t n);
+
+/* The tile shapes the last factor of `handle` used (see Tile autotuning). */
+typedef struct invaskit_tile_config {
+  int32_t leaf_lu_panel;   /* 16 or 32                                          */
+  int32_t leaf_trsm_cols;  /* 16 or 32                                          */
+  int32_t tuned;           /* 1 if that factor timed the candidates itself      */
+  int32_t reserved0;
+  float lu_ms[2];          /* its trial times (best of two) for panels 16, 32   */
+  float trsm_ms[2];        /* and for 16, 32 right-hand sides; 0 if not timed   */
+} invaskit_tile_config;
+int invaskit_tile_config_get(invaskit_handle handle, invaskit_tile_config* out);
+
+/*
+ * The process-wide tuning table as text, one "key value" line per entry
+ * (key: shape class, value: the chosen tile parameter), so that a caller can
+ * keep it across processes.  export: writes at most `n` bytes including the
+ * terminating NUL into buf (buf may be NULL when n == 0) and sets *needed to
+ * the full size including the NUL.  import: adds (or replaces) the entries of
+ * `text` in that format; a malformed line or a value other than 16 or 32
+ * fails with INVASKIT_E_ARG and changes nothing.  clear: empties the table.
+ */
+int invaskit_tuning_export(char* buf, size_t n, size_t* needed);
+int invaskit_tuning_import(const char* text);
+int invaskit_tuning_clear(void);
 
 /* Release the handle and its device memory.  Borrowed buffers are untouched. */
 int invaskit_destroy(invaskit_handle handle);

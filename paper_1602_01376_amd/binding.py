@@ -38,7 +38,17 @@ class _Problem(C.Structure):
 class _Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("fp64_top_levels", C.c_int32),
                 ("refine_tol", C.c_double), ("max_refine_iters", C.c_int32),
-                ("reserved0", C.c_int32)]
+                ("tune", C.c_int32), ("leaf_lu_panel", C.c_int32),
+                ("leaf_trsm_cols", C.c_int32), ("reserved0", C.c_int32)]
+
+
+TUNE_AUTO, TUNE_OFF = 0, 1
+
+
+class _TileConfig(C.Structure):
+    _fields_ = [("leaf_lu_panel", C.c_int32), ("leaf_trsm_cols", C.c_int32),
+                ("tuned", C.c_int32), ("reserved0", C.c_int32),
+                ("lu_ms", C.c_float * 2), ("trsm_ms", C.c_float * 2)]
 
 
 class SolveInfo(C.Structure):
@@ -64,6 +74,10 @@ def _load():
         "invaskit_matvec": (C.c_int, [vp, vp, i64, i64, vp, i64]),
         "invaskit_device_bytes": (C.c_int, [vp, vp]),
         "invaskit_phase_times": (C.c_int, [vp, vp, i32]),
+        "invaskit_tile_config_get": (C.c_int, [vp, vp]),
+        "invaskit_tuning_export": (C.c_int, [vp, C.c_size_t, vp]),
+        "invaskit_tuning_import": (C.c_int, [C.c_char_p]),
+        "invaskit_tuning_clear": (C.c_int, []),
         "invaskit_destroy": (C.c_int, [vp]),
         "invaskit_status_string": (C.c_char_p, [C.c_int]),
         "invaskit_last_error": (C.c_int, [vp, vp, C.c_size_t]),
@@ -85,7 +99,8 @@ _lib = _load()
 EXPORTED = ("invaskit_default_options", "invaskit_factor", "invaskit_factor_sweep",
             "invaskit_refactor", "invaskit_solve",
             "invaskit_matvec", "invaskit_device_bytes", "invaskit_phase_times",
-            "invaskit_destroy", "invaskit_status_string", "invaskit_last_error",
+            "invaskit_tile_config_get", "invaskit_tuning_export", "invaskit_tuning_import",
+            "invaskit_tuning_clear", "invaskit_destroy", "invaskit_status_string", "invaskit_last_error",
             "invaskit_getrf_batched", "invaskit_getrs_batched", "invaskit_kernel_blocks",
             "invaskit_gemm_batched")
 
@@ -131,9 +146,11 @@ class Factorization:
 
     def __init__(self, problem, lam: float, precision: str = "fp64",
                  fp64_top_levels: int = 4, refine_tol: float = 1e-10,
-                 max_refine_iters: int = 30, points=None, p_values=None):
+                 max_refine_iters: int = 30, points=None, p_values=None, tune: str = "auto",
+                 leaf_lu_panel: int = 0, leaf_trsm_cols: int = 0):
         pb, opt = self._prepare(problem, lam, precision, fp64_top_levels, refine_tol,
-                                max_refine_iters, points, p_values)
+                                max_refine_iters, points, p_values, tune, leaf_lu_panel,
+                                leaf_trsm_cols)
         self._handle = C.c_void_p()
         st = _lib.invaskit_factor(C.byref(pb), self.lam, C.byref(opt), _stream(),
                                   C.byref(self._handle))
@@ -145,7 +162,7 @@ class Factorization:
             raise InvaskitError(st, msg)
 
     def _prepare(self, problem, lam, precision, fp64_top_levels, refine_tol, max_refine_iters,
-                 points, p_values):
+                 points, p_values, tune="auto", leaf_lu_panel=0, leaf_trsm_cols=0):
         """Marshal the problem and options (the arrays stay alive with self)."""
         self.n = problem.n
         self.lam = float(lam)
@@ -172,6 +189,11 @@ class Factorization:
         opt.fp64_top_levels = int(fp64_top_levels)
         opt.refine_tol = float(refine_tol)
         opt.max_refine_iters = int(max_refine_iters)
+        if tune not in ("auto", "off"):
+            raise ValueError("tune must be 'auto' or 'off'")
+        opt.tune = TUNE_OFF if tune == "off" else TUNE_AUTO
+        opt.leaf_lu_panel = int(leaf_lu_panel)
+        opt.leaf_trsm_cols = int(leaf_trsm_cols)
         return pb, opt
 
     @property
@@ -219,6 +241,13 @@ class Factorization:
                 "leaf_projections", "skeleton_sweep", "unused", "reduced_systems",
                 "total"]
         return dict(zip(keys, list(out)))
+
+    def tile_config(self):
+        """Tile shapes of the last factor (invaskit_tile_config_get)."""
+        t = _TileConfig()
+        _check(_lib.invaskit_tile_config_get(self._handle, C.byref(t)), self._handle)
+        return {"leaf_lu_panel": t.leaf_lu_panel, "leaf_trsm_cols": t.leaf_trsm_cols,
+                "tuned": t.tuned, "lu_ms": list(t.lu_ms), "trsm_ms": list(t.trsm_ms)}
 
     def device_bytes(self):
         v = C.c_size_t()
@@ -368,13 +397,15 @@ def gemm_batched(problems, dtype=torch.float64, alpha=1.0, beta=0.0):
 
 def factor_sweep(problem, lams, precision: str = "fp64", fp64_top_levels: int = 4,
                  refine_tol: float = 1e-10, max_refine_iters: int = 30, points=None,
-                 p_values=None):
+                 p_values=None, tune: str = "auto", leaf_lu_panel: int = 0,
+                 leaf_trsm_cols: int = 0):
     """One Factorization per lambda in `lams` (invaskit_factor_sweep): the
     kernel blocks are evaluated once and shared by the handles."""
     lams = [float(v) for v in lams]
     objs = [Factorization.__new__(Factorization) for _ in lams]
     pb, opt = objs[0]._prepare(problem, lams[0], precision, fp64_top_levels, refine_tol,
-                               max_refine_iters, points, p_values)
+                               max_refine_iters, points, p_values, tune, leaf_lu_panel,
+                               leaf_trsm_cols)
     for o, lam in zip(objs[1:], lams[1:]):
         o.n, o.lam, o.precision = objs[0].n, lam, precision
         o._points, o._p = objs[0]._points, objs[0]._p
@@ -391,3 +422,54 @@ def factor_sweep(problem, lams, precision: str = "fp64", fp64_top_levels: int = 
             o.close()
         raise InvaskitError(st, msg)
     return objs
+
+
+# ------------------------------------------------------------- tuning table
+def tuning_table() -> dict:
+    """The process-wide tile tuning table as {shape class: choice}."""
+    need = C.c_size_t()
+    _check(_lib.invaskit_tuning_export(None, 0, C.byref(need)))
+    buf = C.create_string_buffer(need.value)
+    _check(_lib.invaskit_tuning_export(buf, need.value, C.byref(need)))
+    out = {}
+    for line in buf.value.decode().splitlines():
+        k, v = line.split()
+        out[k] = int(v)
+    return out
+
+
+def tuning_load(entries: dict):
+    """Add {shape class: choice} entries to the tuning table."""
+    text = "".join(f"{k} {int(v)}\n" for k, v in entries.items())
+    _check(_lib.invaskit_tuning_import(text.encode()))
+
+
+def tuning_clear():
+    _check(_lib.invaskit_tuning_clear())
+
+
+def _arch() -> str:
+    return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+
+
+def save_tuning(path: str):
+    """Write the tuning table to a JSON file, keyed by the GPU architecture
+    (other architectures' entries in the file are kept)."""
+    import json
+    data = {}
+    if os.path.exists(path):
+        with open(path) as f:
+            data = json.load(f)
+    data[_arch()] = tuning_table()
+    with open(path, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+
+
+def load_tuning(path: str) -> int:
+    """Load this architecture's entries of a save_tuning file; returns how
+    many were loaded."""
+    import json
+    with open(path) as f:
+        entries = json.load(f).get(_arch(), {})
+    tuning_load(entries)
+    return len(entries)

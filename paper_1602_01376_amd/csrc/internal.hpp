@@ -75,7 +75,7 @@ struct DiagInvProb {
   int32_t n, jb;
 };
 constexpr int kDiagBlock = 64;
-constexpr int kTrsmCols = 16;
+constexpr int kLdsBytes = 160 * 1024;  // LDS of one compute unit
 
 struct LuProb {
   void* a;
@@ -152,17 +152,24 @@ template <typename T>
 hipError_t launch_gemv(const GemmProb* probs, const GemmSeg* segs, int count, hipStream_t s);
 
 // kind: 0 leaf panels of the factorization, 1 reduced systems, 2 solve phase
-// (library factors, padded by 64 elements), 3 caller-owned factors
+// (library factors, padded by 64 elements), 3 caller-owned factors.  cols:
+// right-hand sides per workgroup, 16 or 32 (tile tn covers columns
+// [tn cols, (tn+1) cols)); hipErrorInvalidValue if the workgroup's LDS,
+// getrs_lds_bytes(nmax, sizeof(TZ), cols), exceeds kLdsBytes.
 template <typename TZ, typename TV>
 hipError_t launch_getrs(const TrsmProb* probs, const Tile2* tiles, int ntiles, int nmax, int kind,
-                        hipStream_t s);
-int getrs_cols_per_tile(bool tz64);
+                        int cols, hipStream_t s);
+size_t getrs_lds_bytes(int nmax, size_t tz_bytes, int cols);
+constexpr int kTrsmColsDefault = 16;
 template <typename TZ>
 hipError_t launch_diag_inv(const DiagInvProb* probs, int count, hipStream_t s);
 
-// kind: 0 leaf blocks, 1 reduced systems
+// kind: 0 leaf blocks, 1 reduced systems.  panel: the LU panel width, 0 for
+// the default (getrf_default_panel), or 16 / 32 for kind 0
 template <typename T>
-hipError_t launch_getrf(const LuProb* probs, int count, int nmax, int kind, hipStream_t s);
+hipError_t launch_getrf(const LuProb* probs, int count, int nmax, int kind, int panel,
+                        hipStream_t s);
+int getrf_default_panel(bool t64);
 
 // adds shift to the diagonal of each square block (rows x rows, leading
 // dimension ld) of the table: the lambda of a factorization that reuses

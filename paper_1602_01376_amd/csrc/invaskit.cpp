@@ -42,6 +42,8 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
+#include <sstream>
 #include <string>
 #include <unordered_set>
 #include <vector>
@@ -104,10 +106,14 @@ struct TrsmL {
   int ntiles = 0, nmax = 0;
   int tz64 = 1, tv64 = 1;
   int kind = 0;
+  int cols = kTrsmColsDefault;  // right-hand sides per workgroup
+  double work = 0;              // sum of n^2 nrhs (tuning key)
 };
 struct LuL {
   size_t probs = 0;
   int count = 0, nmax = 0, t64 = 1, kind = 0;
+  int panel = 0;    // LU panel width, 0 = the kernel's default
+  double work = 0;  // sum of n^3 (tuning key)
 };
 struct DinvL {
   size_t probs = 0;
@@ -143,7 +149,8 @@ struct FactorPlan {
   LuL leaf_lu;
   DinvL leaf_dinv;
   EvalL panels;      // skeleton blocks of every level
-  TrsmL leaf_trsm;   // leaf solves of every level's panel columns
+  TrsmL leaf_trsm[2];  // leaf solves of every level's panel columns, 16 and 32
+                       // right-hand sides per workgroup (ntiles < 0: no room)
   GemmL leaf_proj;   // leaf projections of every level's panel columns
   std::vector<ZformL> zform;   // index j: reduced systems of level j
   std::vector<LuL> zlu;
@@ -194,6 +201,8 @@ struct invaskit_handle_s {
   int top64 = 4;
   double tol = 1e-10;
   int maxit = 30;
+  int tune = INVASKIT_TUNE_AUTO;
+  int fix_lu_panel = 0, fix_trsm_cols = 0;  // 0: chosen by tuning
   hipStream_t stream = nullptr;
   // problem (device data borrowed)
   int64_t N = 0;
@@ -230,6 +239,7 @@ struct invaskit_handle_s {
   // blocks run on it beside the leaf block evaluation and LU
   hipStream_t side = nullptr;
   std::shared_ptr<KernelCache> kcache;  // set for the handles of a lambda sweep
+  invaskit_tile_config tiles{};         // tile shapes of the last factor
   std::string err;
 
   int level(int node) const {
@@ -339,6 +349,11 @@ int validate(H* h, const invaskit_problem* pb, double lambda, const invaskit_opt
     if (opt->fp64_top_levels < 0) return fail_h(h, INVASKIT_E_ARG, "fp64_top_levels < 0");
     if (!(opt->refine_tol > 0.0)) return fail_h(h, INVASKIT_E_ARG, "refine_tol must be > 0");
     if (opt->max_refine_iters < 1) return fail_h(h, INVASKIT_E_ARG, "max_refine_iters < 1");
+    if (opt->tune != INVASKIT_TUNE_AUTO && opt->tune != INVASKIT_TUNE_OFF)
+      return fail_h(h, INVASKIT_E_ARG, "tune must be INVASKIT_TUNE_AUTO or _OFF");
+    auto tile_ok = [](int v) { return v == 0 || v == 16 || v == 32; };
+    if (!tile_ok(opt->leaf_lu_panel) || !tile_ok(opt->leaf_trsm_cols))
+      return fail_h(h, INVASKIT_E_ARG, "leaf_lu_panel and leaf_trsm_cols must be 0, 16 or 32");
   }
   const int L = pb->depth;
   const int nleaves = 1 << L;
@@ -531,16 +546,21 @@ struct TrsmBuilder {
     probs.push_back(p);
     nmax = std::max(nmax, n);
   }
-  TrsmL emit(Arena& ar, int tz64, int tv64, int kind) {
+  TrsmL emit(Arena& ar, int tz64, int tv64, int kind, int cols = kTrsmColsDefault) {
+    TrsmL l;
+    if (getrs_lds_bytes(nmax, tz64 ? 8 : 4, cols) > (size_t)kLdsBytes) {
+      l.ntiles = -1;  // the workgroup's right-hand sides do not fit in LDS
+      return l;
+    }
     std::vector<Tile2> tiles;
-    const int rt = getrs_cols_per_tile(tz64 != 0);
-    for (size_t i = 0; i < probs.size(); ++i)
-      for (int tn = 0; tn < (probs[i].nrhs + rt - 1) / rt; ++tn) tiles.push_back({(int)i, tn});
+    for (size_t i = 0; i < probs.size(); ++i) {
+      for (int tn = 0; tn < (probs[i].nrhs + cols - 1) / cols; ++tn) tiles.push_back({(int)i, tn});
+      l.work += (double)probs[i].n * probs[i].n * probs[i].nrhs;
+    }
     // largest systems first (stable: a system's tiles stay consecutive)
     std::stable_sort(tiles.begin(), tiles.end(), [&](const Tile2& x, const Tile2& y) {
       return probs[x.prob].n > probs[y.prob].n;
     });
-    TrsmL l;
     l.probs = ar.add(probs);
     l.tiles = ar.add(tiles);
     l.ntiles = (int)tiles.size();
@@ -548,6 +568,7 @@ struct TrsmBuilder {
     l.tz64 = tz64;
     l.tv64 = tv64;
     l.kind = kind;
+    l.cols = cols;
     return l;
   }
 };
@@ -739,6 +760,7 @@ int plan_factor(H* h) {
       p.n = m;
       lus.push_back(p);
       nmax = std::max(nmax, m);
+      fp.leaf_lu.work += (double)m * m * m;
       for (int jb = 0; jb < m; jb += kDiagBlock) {
         DiagInvProb d{};
         d.lu = b.out;
@@ -789,7 +811,8 @@ int plan_factor(H* h) {
     fp.panels.blocks = ar.add(pblocks);
     fp.panels.tiles = ar.add(ptiles);
     fp.panels.ntiles = (int)ptiles.size();
-    fp.leaf_trsm = tb.emit(ar, T64, T64, 0);
+    fp.leaf_trsm[0] = tb.emit(ar, T64, T64, 0, 16);
+    fp.leaf_trsm[1] = tb.emit(ar, T64, T64, 0, 32);
     fp.leaf_proj = proj.emit(ar);
   }
   // wavefront over levels j = L-1 .. 0
@@ -887,17 +910,20 @@ hipError_t run_gemm(const DevBuf& tb, const GemmL& l, bool f64, hipStream_t s) {
 
 hipError_t run_trsm(const DevBuf& tb, const TrsmL& l, hipStream_t s) {
   if (l.ntiles == 0) return hipSuccess;
+  if (l.ntiles < 0) return hipErrorInvalidValue;
   const TrsmProb* p = at<TrsmProb>(tb, l.probs);
   const Tile2* t = at<Tile2>(tb, l.tiles);
-  if (l.tz64 && l.tv64) return launch_getrs<double, double>(p, t, l.ntiles, l.nmax, l.kind, s);
-  if (l.tz64) return launch_getrs<double, float>(p, t, l.ntiles, l.nmax, l.kind, s);
-  return launch_getrs<float, float>(p, t, l.ntiles, l.nmax, l.kind, s);
+  if (l.tz64 && l.tv64)
+    return launch_getrs<double, double>(p, t, l.ntiles, l.nmax, l.kind, l.cols, s);
+  if (l.tz64) return launch_getrs<double, float>(p, t, l.ntiles, l.nmax, l.kind, l.cols, s);
+  return launch_getrs<float, float>(p, t, l.ntiles, l.nmax, l.kind, l.cols, s);
 }
 
 hipError_t run_lu(const DevBuf& tb, const LuL& l, hipStream_t s) {
   if (l.count == 0) return hipSuccess;
-  if (l.t64) return launch_getrf<double>(at<LuProb>(tb, l.probs), l.count, l.nmax, l.kind, s);
-  return launch_getrf<float>(at<LuProb>(tb, l.probs), l.count, l.nmax, l.kind, s);
+  if (l.t64)
+    return launch_getrf<double>(at<LuProb>(tb, l.probs), l.count, l.nmax, l.kind, l.panel, s);
+  return launch_getrf<float>(at<LuProb>(tb, l.probs), l.count, l.nmax, l.kind, l.panel, s);
 }
 
 hipError_t run_dinv(const DevBuf& tb, const DinvL& l, hipStream_t s) {
@@ -929,6 +955,122 @@ hipError_t run_eval(H* h, const DevBuf& tb, const EvalL& l, double shift, hipStr
              : launch_eval<float, float>(X, h->d, h->h, shift, b, t, l.ntiles, s);
 }
 
+// ---------------------------------------------------------------- autotuning
+// Process-wide table: shape class of a launch -> chosen tile parameter.
+struct TuneTable {
+  std::mutex mu;
+  std::map<std::string, int> choice;
+};
+TuneTable& tune_table() {
+  static TuneTable t;
+  return t;
+}
+
+// half-octave bin of a positive count
+int tune_bin(double x) { return x > 0 ? (int)std::lround(2.0 * std::log2(x)) : -1; }
+
+std::string lu_key(const LuL& l) {
+  return std::string("getrf.") + (l.t64 ? "f64" : "f32") + ".n" + std::to_string(l.nmax) + ".c" +
+         std::to_string(tune_bin(l.count)) + ".w" + std::to_string(tune_bin(l.work));
+}
+std::string trsm_key(const TrsmL& l) {
+  return std::string("getrs.") + (l.tz64 ? "f64" : "f32") + ".k" + std::to_string(l.kind) +
+         ".n" + std::to_string(l.nmax) + ".w" + std::to_string(tune_bin(l.work));
+}
+
+// Settles the leaf LU panel width and the leaf solves' right-hand sides per
+// workgroup for this factor: fixed by the options, found in the table, or
+// timed.  A trial re-evaluates its launch's inputs first (both launches work
+// in place) and is timed by events on the factor's stream; each candidate
+// runs twice and keeps its faster time.  The trials leave the factor buffers
+// in an arbitrary state: the factorization that follows rebuilds them.
+int tune_factor(H* h) {
+  const FactorPlan& fp = h->fp;
+  const DevBuf& tb = h->ftables;
+  const bool f64 = h->prec == INVASKIT_PREC_FP64;
+  hipStream_t s = h->stream;
+  invaskit_tile_config& tc = h->tiles;
+  tc = invaskit_tile_config{};
+  const bool has32 = fp.leaf_trsm[1].ntiles >= 0;
+  const bool has_trsm = h->L > 0 && fp.leaf_trsm[0].ntiles > 0;
+  // the LU panel matters only for the four-wave kernel (FP32 orders above 192)
+  const bool lu_choice = fp.leaf_lu.t64 || fp.leaf_lu.nmax > 192;
+  const std::string klu = lu_key(fp.leaf_lu), ktr = trsm_key(fp.leaf_trsm[0]);
+  int lu = h->fix_lu_panel, tr = h->fix_trsm_cols;
+  if (tr == 32 && !has32)
+    return fail_h(h, INVASKIT_E_ARG,
+                  "leaf_trsm_cols = 32 needs more than 160 KiB of LDS at this leaf size");
+  if (!lu && !lu_choice) lu = getrf_default_panel(f64);
+  if (!tr && (!has32 || !has_trsm)) tr = kTrsmColsDefault;
+  if (h->tune == INVASKIT_TUNE_OFF) {
+    if (!lu) lu = getrf_default_panel(f64);
+    if (!tr) tr = kTrsmColsDefault;
+  }
+  {
+    std::lock_guard<std::mutex> g(tune_table().mu);
+    auto& t = tune_table().choice;
+    if (!lu && t.count(klu)) lu = t[klu];
+    if (!tr && t.count(ktr)) tr = t[ktr];
+  }
+  if (!lu || !tr) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(h, hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+      hipEventDestroy(e0);
+      return fail_h(h, INVASKIT_E_HIP, "hipEventCreate failed");
+    }
+    hipError_t e = hipSuccess;
+    // best of two runs of `launch`, each after `prepare`
+    auto trial = [&](auto&& prepare, auto&& launch, float& best) {
+      best = 0.f;
+      for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
+        e = prepare();
+        if (e == hipSuccess) e = hipEventRecord(e0, s);
+        if (e == hipSuccess) e = launch();
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e == hipSuccess && (best == 0.f || ms < best)) best = ms;
+      }
+    };
+    auto eval_leaves = [&]() { return run_eval(h, tb, fp.leaf_eval, h->lam, s); };
+    auto lu_with = [&](int panel) {
+      LuL l = fp.leaf_lu;
+      l.panel = panel;
+      return run_lu(tb, l, s);
+    };
+    if (!lu) {
+      trial(eval_leaves, [&]() { return lu_with(16); }, tc.lu_ms[0]);
+      trial(eval_leaves, [&]() { return lu_with(32); }, tc.lu_ms[1]);
+      lu = tc.lu_ms[1] < tc.lu_ms[0] ? 32 : 16;
+    }
+    if (!tr && e == hipSuccess) {
+      // the solves need the leaf factors and their diagonal-block inverses
+      e = eval_leaves();
+      if (e == hipSuccess) e = lu_with(lu);
+      if (e == hipSuccess) e = run_dinv(tb, fp.leaf_dinv, s);
+      auto eval_panels = [&]() { return run_eval(h, tb, fp.panels, 0.0, s); };
+      trial(eval_panels, [&]() { return run_trsm(tb, fp.leaf_trsm[0], s); }, tc.trsm_ms[0]);
+      trial(eval_panels, [&]() { return run_trsm(tb, fp.leaf_trsm[1], s); }, tc.trsm_ms[1]);
+      tr = tc.trsm_ms[1] < tc.trsm_ms[0] ? 32 : 16;
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (e != hipSuccess)
+      return fail_h(h, INVASKIT_E_HIP, std::string("tile tuning: ") + hipGetErrorString(e));
+    tc.tuned = 1;
+    std::lock_guard<std::mutex> g(tune_table().mu);
+    auto& t = tune_table().choice;
+    if (!h->fix_lu_panel && lu_choice) t[klu] = lu;
+    if (!h->fix_trsm_cols && has32 && has_trsm) t[ktr] = tr;
+  }
+  tc.leaf_lu_panel = lu;
+  tc.leaf_trsm_cols = tr;
+  return INVASKIT_OK;
+}
+
 int run_factor(H* h) {
   hipStream_t s = h->stream;
   const bool f64 = h->prec == INVASKIT_PREC_FP64;
@@ -939,6 +1081,7 @@ int run_factor(H* h) {
   }
   if (!h->side) HIP_TRY(h, hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
   hipStream_t s2 = h->side;
+  if (int rc = tune_factor(h)) return rc;
   // Phase timing: each phase is bracketed by two events on the stream it
   // runs on; phases on the two streams overlap, so they need not sum to the
   // total.  `sync` events order the streams.
@@ -1031,7 +1174,11 @@ int run_factor(H* h) {
   }
   STEP(close(s));
   STEP(open(1, s));
-  STEP(run_lu(tb, fp.leaf_lu, s));
+  {
+    LuL lu = fp.leaf_lu;
+    lu.panel = h->tiles.leaf_lu_panel;
+    STEP(run_lu(tb, lu, s));
+  }
   STEP(close(s));
   STEP(open(2, s));
   STEP(run_dinv(tb, fp.leaf_dinv, s));
@@ -1039,7 +1186,7 @@ int run_factor(H* h) {
   if (L > 0) {
     STEP(join(s2, s));  // skeleton blocks done
     STEP(open(4, s));
-    STEP(run_trsm(tb, fp.leaf_trsm, s));
+    STEP(run_trsm(tb, fp.leaf_trsm[h->tiles.leaf_trsm_cols == 32 ? 1 : 0], s));
     STEP(close(s));
     STEP(open(5, s));
     STEP(run_gemm(tb, fp.leaf_proj, f64, s));
@@ -1430,6 +1577,9 @@ int invaskit_default_options(invaskit_options* opt) {
   opt->fp64_top_levels = 4;
   opt->refine_tol = 1e-10;
   opt->max_refine_iters = 30;
+  opt->tune = INVASKIT_TUNE_AUTO;
+  opt->leaf_lu_panel = 0;
+  opt->leaf_trsm_cols = 0;
   opt->reserved0 = 0;
   return INVASKIT_OK;
 }
@@ -1452,6 +1602,9 @@ int make_handle(const invaskit_problem* pb, double lambda, const invaskit_option
   h->top64 = o.fp64_top_levels;
   h->tol = o.refine_tol;
   h->maxit = o.max_refine_iters;
+  h->tune = o.tune;
+  h->fix_lu_panel = o.leaf_lu_panel;
+  h->fix_trsm_cols = o.leaf_trsm_cols;
   h->stream = static_cast<hipStream_t>(hip_stream);
   h->N = pb->n;
   h->d = pb->d;
@@ -1571,6 +1724,55 @@ int invaskit_phase_times(invaskit_handle h, double* ms, int32_t n) {
   return INVASKIT_OK;
 }
 
+int invaskit_tile_config_get(invaskit_handle h, invaskit_tile_config* out) {
+  if (!h || !out) return fail_h(h, INVASKIT_E_ARG, "handle and out are required");
+  *out = h->tiles;
+  return INVASKIT_OK;
+}
+
+int invaskit_tuning_export(char* buf, size_t n, size_t* needed) {
+  if (!needed || (n > 0 && !buf)) return fail_h(nullptr, INVASKIT_E_ARG, "needed is required");
+  std::string text;
+  {
+    std::lock_guard<std::mutex> g(tune_table().mu);
+    for (const auto& kv : tune_table().choice)
+      text += kv.first + " " + std::to_string(kv.second) + "\n";
+  }
+  *needed = text.size() + 1;
+  if (n > 0) {
+    const size_t k = std::min(n - 1, text.size());
+    std::memcpy(buf, text.data(), k);
+    buf[k] = '\0';
+  }
+  return INVASKIT_OK;
+}
+
+int invaskit_tuning_import(const char* text) {
+  if (!text) return fail_h(nullptr, INVASKIT_E_ARG, "text is NULL");
+  std::vector<std::pair<std::string, int>> add;
+  std::istringstream in(text);
+  std::string line;
+  while (std::getline(in, line)) {
+    if (line.find_first_not_of(" \t\r") == std::string::npos) continue;
+    std::istringstream ls(line);
+    std::string key, rest;
+    int v = 0;
+    if (!(ls >> key >> v) || (ls >> rest) || (v != 16 && v != 32) ||
+        (key.rfind("getrf.", 0) != 0 && key.rfind("getrs.", 0) != 0))
+      return fail_h(nullptr, INVASKIT_E_ARG, "malformed tuning line: " + line);
+    add.emplace_back(key, v);
+  }
+  std::lock_guard<std::mutex> g(tune_table().mu);
+  for (const auto& kv : add) tune_table().choice[kv.first] = kv.second;
+  return INVASKIT_OK;
+}
+
+int invaskit_tuning_clear(void) {
+  std::lock_guard<std::mutex> g(tune_table().mu);
+  tune_table().choice.clear();
+  return INVASKIT_OK;
+}
+
 int invaskit_destroy(invaskit_handle h) {
   if (!h) return INVASKIT_OK;
   (void)hipStreamSynchronize(h->stream);
@@ -1627,8 +1829,9 @@ int invaskit_getrf_batched(int32_t dtype, void* a, const int64_t* a_offsets, con
   if (rc) return rc;
   hipError_t e = hipMemcpy(t.p, probs.data(), sizeof(LuProb) * count, hipMemcpyHostToDevice);
   if (e == hipSuccess)
-    e = (dtype == INVASKIT_F64) ? launch_getrf<double>(static_cast<LuProb*>(t.p), count, nmax, 1, s)
-                                : launch_getrf<float>(static_cast<LuProb*>(t.p), count, nmax, 1, s);
+    e = (dtype == INVASKIT_F64)
+            ? launch_getrf<double>(static_cast<LuProb*>(t.p), count, nmax, 1, 0, s)
+            : launch_getrf<float>(static_cast<LuProb*>(t.p), count, nmax, 1, 0, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   t.release();
   if (e != hipSuccess) return fail_h(nullptr, INVASKIT_E_HIP, hipGetErrorString(e));

@@ -606,8 +606,17 @@ hipError_t run_getrf(const LuProb* probs, int count, int nmax, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <typename T, int W, int KIND>
+hipError_t run_block(const LuProb* probs, int count, int nmax, hipStream_t s) {
+  if (nmax <= 256) return run_getrf<T, W, 1, KIND>(probs, count, nmax, s);
+  if (nmax <= 512) return run_getrf<T, W, 2, KIND>(probs, count, nmax, s);
+  return run_getrf<T, W, 4, KIND>(probs, count, nmax, s);
+}
+
+// panel: 0 = the default width (32 in FP32, 16 in FP64), else 16 or 32 (leaf
+// blocks only; the reduced systems always take the default)
 template <typename T, int KIND>
-hipError_t pick(const LuProb* probs, int count, int nmax, hipStream_t s) {
+hipError_t pick(const LuProb* probs, int count, int nmax, int panel, hipStream_t s) {
   constexpr int W = sizeof(T) == 8 ? 16 : 32;
   // one wave per matrix for small FP32 orders; FP64's longer per-column chain
   // (64-bit keys and reciprocal) is better spread over four waves
@@ -616,20 +625,27 @@ hipError_t pick(const LuProb* probs, int count, int nmax, hipStream_t s) {
     if (nmax <= 128) return run_getrf_w<T, W, 2, KIND>(probs, count, nmax, s);
     if (nmax <= 192) return run_getrf_w<T, W, 3, KIND>(probs, count, nmax, s);
   }
-  if (nmax <= 256) return run_getrf<T, W, 1, KIND>(probs, count, nmax, s);
-  if (nmax <= 512) return run_getrf<T, W, 2, KIND>(probs, count, nmax, s);
-  return run_getrf<T, W, 4, KIND>(probs, count, nmax, s);
+  if (panel == 0 || panel == W) return run_block<T, W, KIND>(probs, count, nmax, s);
+  if constexpr (KIND == 0) {
+    if (panel == 16 || panel == 32)
+      return run_block<T, (W == 16 ? 32 : 16), KIND>(probs, count, nmax, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 }  // namespace
 
+int getrf_default_panel(bool t64) { return t64 ? 16 : 32; }
+
 template <typename T>
-hipError_t launch_getrf(const LuProb* probs, int count, int nmax, int kind, hipStream_t s) {
+hipError_t launch_getrf(const LuProb* probs, int count, int nmax, int kind, int panel,
+                        hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  return kind == 0 ? pick<T, 0>(probs, count, nmax, s) : pick<T, 1>(probs, count, nmax, s);
+  return kind == 0 ? pick<T, 0>(probs, count, nmax, panel, s)
+                   : pick<T, 1>(probs, count, nmax, panel, s);
 }
 
-template hipError_t launch_getrf<double>(const LuProb*, int, int, int, hipStream_t);
-template hipError_t launch_getrf<float>(const LuProb*, int, int, int, hipStream_t);
+template hipError_t launch_getrf<double>(const LuProb*, int, int, int, int, hipStream_t);
+template hipError_t launch_getrf<float>(const LuProb*, int, int, int, int, hipStream_t);
 
 }  // namespace invaskit

@@ -11,9 +11,10 @@
 // the upper block of U (column by column against the identity, one wave per
 // 16 columns, the diagonal of U inverted once), stored row-major.
 //
-// k_getrs: one workgroup (4 waves) takes 16 right-hand-side columns of one
-// system; the permuted right-hand sides live in LDS (row stride 17 to spread
-// the banks).  Forward substitution with L and back substitution with U go
+// k_getrs: one workgroup (4 waves) takes 16 CT right-hand-side columns of
+// one system (CT = 1 or 2); the permuted right-hand sides live in LDS (row
+// stride 16 CT + 1 to spread the banks).  At CT = 2 every factor tile read
+// serves two 16-column MFMA tiles, for twice the LDS per workgroup.  Forward substitution with L and back substitution with U go
 // by 64-row blocks, both steps on the matrix cores:
 //   diagonal block:  X_b = inv(L_bb) X_b   (inv(U_bb) going back),
 //   off-diagonal:    X_rows -= L[rows, block] X_b   (U[rows, block] going back),
@@ -33,8 +34,6 @@ namespace invaskit {
 namespace {
 
 constexpr int NBK = kDiagBlock;  // 64-row block
-constexpr int RT = kTrsmCols;    // right-hand sides per workgroup
-constexpr int RTP = RT + 1;      // LDS row stride
 
 // ------------------------------------------------------------ block inverses
 template <typename TZ>
@@ -89,10 +88,12 @@ __global__ __launch_bounds__(256) void k_diag_inv(const DiagInvProb* __restrict_
 }
 
 // ------------------------------------------------------------------- solves
-template <typename TZ, typename TV, int KIND>
+template <typename TZ, typename TV, int KIND, int CT>
 __global__ __launch_bounds__(256) void k_getrs(const TrsmProb* __restrict__ probs,
                                                const Tile2* __restrict__ tiles) {
   using V4 = typename Vec4<TZ>::type;
+  constexpr int RT = 16 * CT;  // right-hand sides of the workgroup
+  constexpr int RTP = RT + 1;  // LDS row stride
   const Tile2 t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
   const TrsmProb pr = probs[t.prob];
   const int n = pr.n;
@@ -127,18 +128,22 @@ __global__ __launch_bounds__(256) void k_getrs(const TrsmProb* __restrict__ prob
   };
   load_d(0);
 
-  // gather the permuted right-hand sides: one thread per row, the row's RT
-  // column loads in flight together
+  // gather the permuted right-hand sides: one thread per row, 16 column
+  // loads of the row in flight together
   for (int i = tid; i < n; i += 256) {
     const int src = pr.perm[i];
     Pm[i] = src;
     const TV* base = (src < pr.split) ? in0 + src : in1 + (src - pr.split);
     const int64_t ld = (src < pr.split) ? pr.ldin0 : pr.ldin1;
-    TZ v[RT];
+#pragma unroll 1
+    for (int ct = 0; ct < CT; ++ct) {
+      TZ v[16];
 #pragma unroll
-    for (int c = 0; c < RT; ++c) v[c] = (c < nc) ? (TZ)base[(int64_t)(c0 + c) * ld] : TZ(0);
+      for (int c = 0; c < 16; ++c)
+        v[c] = (16 * ct + c < nc) ? (TZ)base[(int64_t)(c0 + 16 * ct + c) * ld] : TZ(0);
 #pragma unroll
-    for (int c = 0; c < RT; ++c) X[i * RTP + c] = v[c];
+      for (int c = 0; c < 16; ++c) X[i * RTP + 16 * ct + c] = v[c];
+    }
   }
   __syncthreads();
 
@@ -162,43 +167,59 @@ __global__ __launch_bounds__(256) void k_getrs(const TrsmProb* __restrict__ prob
     };
     TZ fa[NBK / 4], fb[NBK / 4];
     if (wave < nrt) load_f(wave, fa);
-    // X_b = inv(diagonal block) X_b: wave w computes rows 16w .. 16w+15
+    // X_b = inv(diagonal block) X_b: wave w computes rows 16w .. 16w+15 of
+    // each 16-column tile
     {
-      V4 acc = V4{0, 0, 0, 0};
+      V4 acc[CT];
 #pragma unroll
-      for (int kk = 0; kk < NBK / 4; ++kk) {
-        const int k = sigma_k<TZ>(kk, lg);
-        const TZ bb = (k < nb) ? X[(jb + k) * RTP + lr] : TZ(0);
-        acc = mfma16(da[kk], bb, acc);
+      for (int ct = 0; ct < CT; ++ct) {
+        acc[ct] = V4{0, 0, 0, 0};
+#pragma unroll
+        for (int kk = 0; kk < NBK / 4; ++kk) {
+          const int k = sigma_k<TZ>(kk, lg);
+          const TZ bb = (k < nb) ? X[(jb + k) * RTP + 16 * ct + lr] : TZ(0);
+          acc[ct] = mfma16(da[kk], bb, acc[ct]);
+        }
       }
       __syncthreads();
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int r = 16 * wave + acc_row(TZ(0), lg, v);
-        if (r < nb) X[(jb + r) * RTP + lr] = acc[v];
-      }
+      for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = 16 * wave + acc_row(TZ(0), lg, v);
+          if (r < nb) X[(jb + r) * RTP + 16 * ct + lr] = acc[ct][v];
+        }
     }
     __syncthreads();
     if (q + 1 < nsteps) load_d(q + 1);
     // X_rows -= F[rows, block] X_b.  X_b is not written here, so its MFMA
     // operands are read once; the next tile's factor rows are in flight
-    // while the current one computes.
-    TZ xb[NBK / 4];
+    // while the current one computes, and each factor tile serves all CT
+    // column tiles.
+    TZ xb[CT][NBK / 4];
 #pragma unroll
-    for (int kk = 0; kk < NBK / 4; ++kk) {
-      const int j = sigma_k<TZ>(kk, lg);
-      xb[kk] = (j < nb) ? X[(jb + j) * RTP + lr] : TZ(0);
-    }
+    for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+      for (int kk = 0; kk < NBK / 4; ++kk) {
+        const int j = sigma_k<TZ>(kk, lg);
+        xb[ct][kk] = (j < nb) ? X[(jb + j) * RTP + 16 * ct + lr] : TZ(0);
+      }
     auto update = [&](int item, const TZ (&a)[NBK / 4]) {
-      V4 acc = V4{0, 0, 0, 0};
+      V4 acc[CT];
 #pragma unroll
-      for (int kk = 0; kk < NBK / 4; ++kk) acc = mfma16(a[kk], xb[kk], acc);
+      for (int ct = 0; ct < CT; ++ct) {
+        acc[ct] = V4{0, 0, 0, 0};
+#pragma unroll
+        for (int kk = 0; kk < NBK / 4; ++kk) acc[ct] = mfma16(a[kk], xb[ct][kk], acc[ct]);
+      }
       const int i0 = r0 + item * 16;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int rr = i0 + acc_row(TZ(0), lg, v);
-        if (rr < r1) X[rr * RTP + lr] -= acc[v];
-      }
+      for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int rr = i0 + acc_row(TZ(0), lg, v);
+          if (rr < r1) X[rr * RTP + 16 * ct + lr] -= acc[ct][v];
+        }
     };
     for (int item = wave; item < nrt; item += 8) {
       if (item + 4 < nrt) load_f(item + 4, fb);
@@ -210,25 +231,39 @@ __global__ __launch_bounds__(256) void k_getrs(const TrsmProb* __restrict__ prob
   }
 
   for (int i = tid; i < n; i += 256) {
+#pragma unroll 1
+    for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
-    for (int c = 0; c < RT; ++c)
-      if (c < nc) out[(int64_t)(c0 + c) * pr.ldout + i] = (TV)X[i * RTP + c];
+      for (int c = 0; c < 16; ++c)
+        if (16 * ct + c < nc)
+          out[(int64_t)(c0 + 16 * ct + c) * pr.ldout + i] = (TV)X[i * RTP + 16 * ct + c];
   }
 }
 
-template <typename TZ, typename TV, int KIND>
+template <typename TZ, typename TV, int KIND, int CT>
 hipError_t run(const TrsmProb* probs, const Tile2* tiles, int ntiles, int nmax, hipStream_t s) {
-  const size_t sm = (size_t)nmax * (RTP * sizeof(TZ) + sizeof(int));
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_getrs<TZ, TV, KIND>),
+  const size_t sm = getrs_lds_bytes(nmax, sizeof(TZ), 16 * CT);
+  if (sm > (size_t)kLdsBytes) return hipErrorInvalidValue;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_getrs<TZ, TV, KIND, CT>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_getrs<TZ, TV, KIND>), dim3(ntiles), dim3(256), sm, s, probs, tiles);
+  hipLaunchKernelGGL((k_getrs<TZ, TV, KIND, CT>), dim3(ntiles), dim3(256), sm, s, probs, tiles);
   return hipGetLastError();
+}
+
+template <typename TZ, typename TV, int KIND>
+hipError_t run_ct(const TrsmProb* probs, const Tile2* tiles, int ntiles, int nmax, int cols,
+                  hipStream_t s) {
+  if (cols == 32) return run<TZ, TV, KIND, 2>(probs, tiles, ntiles, nmax, s);
+  if (cols == 16) return run<TZ, TV, KIND, 1>(probs, tiles, ntiles, nmax, s);
+  return hipErrorInvalidValue;
 }
 
 }  // namespace
 
-int getrs_cols_per_tile(bool) { return RT; }
+size_t getrs_lds_bytes(int nmax, size_t tz_bytes, int cols) {
+  return (size_t)nmax * ((cols + 1) * tz_bytes + sizeof(int));
+}
 
 template <typename TZ>
 hipError_t launch_diag_inv(const DiagInvProb* probs, int count, hipStream_t s) {
@@ -239,23 +274,23 @@ hipError_t launch_diag_inv(const DiagInvProb* probs, int count, hipStream_t s) {
 
 template <typename TZ, typename TV>
 hipError_t launch_getrs(const TrsmProb* probs, const Tile2* tiles, int ntiles, int nmax, int kind,
-                        hipStream_t s) {
+                        int cols, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
   switch (kind) {
-    case 0: return run<TZ, TV, 0>(probs, tiles, ntiles, nmax, s);
-    case 1: return run<TZ, TV, 1>(probs, tiles, ntiles, nmax, s);
-    case 2: return run<TZ, TV, 2>(probs, tiles, ntiles, nmax, s);
-    default: return run<TZ, TV, 3>(probs, tiles, ntiles, nmax, s);
+    case 0: return run_ct<TZ, TV, 0>(probs, tiles, ntiles, nmax, cols, s);
+    case 1: return run_ct<TZ, TV, 1>(probs, tiles, ntiles, nmax, cols, s);
+    case 2: return run_ct<TZ, TV, 2>(probs, tiles, ntiles, nmax, cols, s);
+    default: return run_ct<TZ, TV, 3>(probs, tiles, ntiles, nmax, cols, s);
   }
 }
 
 template hipError_t launch_diag_inv<double>(const DiagInvProb*, int, hipStream_t);
 template hipError_t launch_diag_inv<float>(const DiagInvProb*, int, hipStream_t);
 template hipError_t launch_getrs<double, double>(const TrsmProb*, const Tile2*, int, int, int,
-                                                 hipStream_t);
-template hipError_t launch_getrs<float, float>(const TrsmProb*, const Tile2*, int, int, int,
+                                                 int, hipStream_t);
+template hipError_t launch_getrs<float, float>(const TrsmProb*, const Tile2*, int, int, int, int,
                                                hipStream_t);
-template hipError_t launch_getrs<double, float>(const TrsmProb*, const Tile2*, int, int, int,
+template hipError_t launch_getrs<double, float>(const TrsmProb*, const Tile2*, int, int, int, int,
                                                 hipStream_t);
 
 }  // namespace invaskit

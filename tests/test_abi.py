@@ -141,6 +141,55 @@ def test_bad_options_rejected(small_problem):
     opt.max_refine_iters = 0
     st, msg = _factor_status(raw, opt=opt)
     assert st == -1
+    binding.library().invaskit_default_options(C.byref(opt))
+    assert opt.tune == binding.TUNE_AUTO and opt.leaf_lu_panel == 0 and opt.leaf_trsm_cols == 0
+    opt.tune = 7
+    st, msg = _factor_status(raw, opt=opt)
+    assert st == -1 and "tune" in msg
+    for field, v in (("leaf_lu_panel", 24), ("leaf_trsm_cols", 64), ("leaf_trsm_cols", -16)):
+        binding.library().invaskit_default_options(C.byref(opt))
+        setattr(opt, field, v)
+        st, msg = _factor_status(raw, opt=opt)
+        assert st == -1 and "leaf_lu_panel and leaf_trsm_cols" in msg, (field, v)
+
+
+def test_options_struct_layout():
+    """The binding's mirror of invaskit_options has the header's size and
+    field offsets (4 + 4 + 8 + 5 x 4 bytes, padded to 40)."""
+    from paper_1602_01376_amd import binding
+    O = binding._Options
+    assert C.sizeof(O) == 40
+    assert O.refine_tol.offset == 8 and O.max_refine_iters.offset == 16
+    assert O.tune.offset == 20 and O.leaf_lu_panel.offset == 24
+    assert O.leaf_trsm_cols.offset == 28 and O.reserved0.offset == 32
+    T = binding._TileConfig
+    assert C.sizeof(T) == 32 and T.lu_ms.offset == 16 and T.trsm_ms.offset == 24
+
+
+def test_tuning_table_text_round_trip():
+    """Export, import and clear of the process-wide tuning table (host only);
+    a malformed import changes nothing."""
+    from paper_1602_01376_amd import binding
+    binding.tuning_clear()
+    assert binding.tuning_table() == {}
+    entries = {"getrf.f32.n512.c24.w67": 16, "getrs.f64.k0.n256.w60": 32}
+    binding.tuning_load(entries)
+    assert binding.tuning_table() == entries
+    lib = binding.library()
+    for bad in (b"getrf.f32.n1 24\n", b"getrs.f32 16 extra\n", b"other.key 16\n",
+                b"getrf.f32.n1\n"):
+        assert lib.invaskit_tuning_import(bad) == -1, bad
+    assert binding.tuning_table() == entries
+    need = C.c_size_t()
+    assert lib.invaskit_tuning_export(None, 0, C.byref(need)) == 0
+    full = "".join(f"{k} {v}\n" for k, v in sorted(entries.items()))
+    assert need.value == len(full) + 1
+    small = C.create_string_buffer(8)
+    assert lib.invaskit_tuning_export(small, 8, C.byref(need)) == 0
+    assert small.value == full[:7].encode()
+    assert lib.invaskit_tuning_export(None, 0, None) == -1
+    binding.tuning_clear()
+    assert binding.tuning_table() == {}
 
 
 def test_nonfinite_lambda_rejected(small_problem):

@@ -155,9 +155,10 @@ CASES = [
     ("mnist", dict(n=2048, depth=2), 2),          # d = 784, FP32 points, s = 256
     ("normal", dict(n=4096, depth=3), 2),         # d = 64, s = 256
     ("susy", dict(n=4096, depth=4), 64),          # 64 right-hand sides
+    ("tiny", dict(n=2048, depth=1), 2),           # leaves of 1024: the largest order
 ]
-# the matvec and mixed-precision checks: the first four cases and the last three
-MV_CASES = CASES[:4] + CASES[-3:]
+# the matvec and mixed-precision checks: the first four cases and the last four
+MV_CASES = CASES[:4] + CASES[-4:]
 # Mixed path: the refined residual is <= 1e-10, so x can differ from the
 # oracle's by up to kappa * 1e-10; kappa(lambda I + K~) is about 1e4 for the
 # 784-dimensional case (dense estimate at this size) and below 30 elsewhere.
@@ -264,6 +265,80 @@ def test_lambda_sweep(bind, problems, prec):
     check(facs[2], lams[2])
     for f in facs:
         f.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("lu,tr", [(16, 16), (32, 32), (16, 32), (32, 16)])
+def test_fixed_tiles_match_oracle(bind, problems, prec, lu, tr):
+    """Every leaf LU panel width and leaf-solve column count the tuner can
+    choose gives the oracle's solution (uneven leaves 64..512)."""
+    _say("fixed tiles", prec, lu, tr)
+    pb, F = problems("susy", dict(n=8192, depth=5))
+    b = rhs_for(pb, nrhs=2)
+    x_ref = oracle.solve(F, b)
+    fac = bind.Factorization(pb, pb.lam, precision=prec, leaf_lu_panel=lu, leaf_trsm_cols=tr)
+    tc = fac.tile_config()
+    assert (tc["leaf_lu_panel"], tc["leaf_trsm_cols"], tc["tuned"]) == (lu, tr, 0)
+    x, info, st = fac.solve(torch.from_numpy(b), return_info=True)
+    assert st == 0 and info["final_rel_residual"] <= 1e-10
+    rel = _rel(x.cpu().numpy(), x_ref)
+    _say("  rel vs oracle", rel, "unrefined", info["unrefined_rel_residual"])
+    assert rel <= (1e-10 if prec == "fp64" else 1e-7)
+    fac.close()
+
+
+def test_wide_leaf_solves_at_largest_leaf(bind, problems):
+    """Leaves of 1024: 32 right-hand sides per workgroup fit in LDS in FP32
+    (and match the oracle) but not in FP64, where asking for them is an
+    argument error and the tuner keeps 16."""
+    _say("wide leaf solves, leaves of 1024")
+    pb, F = problems("tiny", dict(n=2048, depth=1))
+    b = rhs_for(pb, nrhs=2)
+    x_ref = oracle.solve(F, b)
+    fac = bind.Factorization(pb, pb.lam, precision="mixed", leaf_trsm_cols=32)
+    x, info, st = fac.solve(torch.from_numpy(b), return_info=True)
+    assert st == 0 and info["final_rel_residual"] <= 1e-10
+    assert _rel(x.cpu().numpy(), x_ref) <= 1e-7
+    fac.close()
+    with pytest.raises(bind.InvaskitError) as ei:
+        bind.Factorization(pb, pb.lam, precision="fp64", leaf_trsm_cols=32)
+    assert ei.value.status == bind.E_ARG and "LDS" in str(ei.value)
+    fac = bind.Factorization(pb, pb.lam, precision="fp64")
+    assert fac.tile_config()["leaf_trsm_cols"] == 16
+    fac.close()
+
+
+def test_autotune_times_candidates_once(bind, problems):
+    """AUTO: the first factor of a shape class times both candidates of each
+    launch and keeps the faster; later factors (new handles, refactor) reuse
+    the table; OFF takes the defaults; the result matches the oracle."""
+    _say("autotune")
+    bind.tuning_clear()
+    pb, F = problems("susy", dict(n=8192, depth=5))
+    b = rhs_for(pb, nrhs=2)
+    fac = bind.Factorization(pb, pb.lam, precision="mixed")
+    tc = fac.tile_config()
+    _say("  tile config", tc)
+    assert tc["tuned"] == 1 and min(tc["lu_ms"] + tc["trsm_ms"]) > 0
+    assert tc["leaf_lu_panel"] == (32 if tc["lu_ms"][1] < tc["lu_ms"][0] else 16)
+    assert tc["leaf_trsm_cols"] == (32 if tc["trsm_ms"][1] < tc["trsm_ms"][0] else 16)
+    table = bind.tuning_table()
+    assert sorted(table.values()) == sorted([tc["leaf_lu_panel"], tc["leaf_trsm_cols"]])
+    x = fac.solve(torch.from_numpy(b)).cpu().numpy()
+    assert _rel(x, oracle.solve(F, b)) <= 1e-7
+    fac.refactor(3e-3)
+    tc2 = fac.tile_config()
+    assert tc2["tuned"] == 0 and tc2["leaf_lu_panel"] == tc["leaf_lu_panel"]
+    assert tc2["leaf_trsm_cols"] == tc["leaf_trsm_cols"]
+    fac.close()
+    fac = bind.Factorization(pb, pb.lam, precision="mixed")
+    assert fac.tile_config()["tuned"] == 0
+    fac.close()
+    fac = bind.Factorization(pb, pb.lam, precision="mixed", tune="off")
+    tc3 = fac.tile_config()
+    assert (tc3["leaf_lu_panel"], tc3["leaf_trsm_cols"], tc3["tuned"]) == (32, 16, 0)
+    fac.close()
+    bind.tuning_clear()
 
 
 def test_singular_leaf_is_reported(bind):
