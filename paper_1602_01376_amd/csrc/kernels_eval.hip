@@ -12,9 +12,22 @@
 // (Section II-B, Evaluate): one thread per target point keeps its
 // coordinates in registers (d <= 64); source points and their weights are
 // staged through LDS 64 at a time and K(x_i, x_j) is consumed immediately,
-// so the kernel matrix is never stored.  k_mv_eval_wide covers d > 64.
+// so the kernel matrix is never stored.
+//
+// Above d = 64 the squared distances are a dense contraction over the
+// coordinates, so both kernels switch to the Gram form on the matrix cores
+// (k_eval_gram, k_mv_eval_gram): |x - y|^2 = |x'|^2 + |y'|^2 - 2 x'.y' with
+// x' = x - z, y' = y - z for a reference point z of the tile (its first row
+// point; the distance does not depend on z, and the shift keeps the norms,
+// and so the cancellation, at the scale of the distances).  The products run
+// in FP64 on the matrix cores whatever the output precision: an FP32 Gram
+// over hundreds of coordinates would carry distance errors about sqrt(d)
+// times FP32 rounding, well above the FP32 rounding of the stored kernel
+// value.  The norms are summed from the same operands, and a point against
+// itself gets distance 0 exactly.
 #include <cmath>
 
+#include "device_util.hpp"
 #include "internal.hpp"
 
 namespace invaskit {
@@ -91,6 +104,144 @@ __global__ __launch_bounds__(256) void k_eval(const PT* __restrict__ X, int d, d
       if (b.diag && r == c) v += shift;
       out[(int64_t)c * b.ld + r] = (T)v;
     }
+  }
+}
+
+// ---------------------------------------------------------------- Gram form
+constexpr int GK = 32;       // coordinates per LDS stage
+constexpr int GKP = GK + 4;  // LDS row stride (spreads the operand reads over the banks)
+
+// The 64 x 64 Gram tile G[c][r] = (y_c - z) . (x_r - z), z = X[ref], over
+// all d coordinates in FP64: row points rowi[p] and column points coli[p]
+// (LDS, -1 for none: zero operands), staged GK coordinates at a time through
+// sr / sc with the next stage prefetched into registers.  Wave w holds rows
+// 32 (w & 1) .. +32 and columns 32 (w >> 1) .. +32 as 2 x 2 MFMA 16 x 16
+// tiles, the MFMA row index being the column point c (so the lanes of an
+// accumulator run along r).  Threads 0..63 also return the squared norm of
+// row point tid, threads 64..127 that of column point tid - 64.  Starts and
+// ends with a barrier.
+template <typename PT>
+__device__ __forceinline__ void gram_tile(const PT* __restrict__ X, int d, int64_t ref,
+                                          const int64_t* rowi, const int64_t* coli,
+                                          double (*sr)[GKP], double (*sc)[GKP],
+                                          f64x4 (&acc)[2][2], double& nrm) {
+  using T = double;
+  using V4 = f64x4;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lg = lane >> 4;
+  const int wr = wave & 1, wc = wave >> 1;
+  const int k = tid % GK;   // this thread's coordinate within a stage
+  const int p0 = tid / GK;  // and its points p0 + 8 i
+  constexpr int NP = 64 * GK / 256;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = V4{0, 0, 0, 0};
+  nrm = 0.0;
+  __syncthreads();  // rowi / coli written by the caller
+  int64_t gr[NP], gc[NP];
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+    gr[i] = rowi[p0 + 8 * i];
+    gc[i] = coli[p0 + 8 * i];
+  }
+  T vr[NP], vc[NP];
+  auto load = [&](int dd) {
+    const int kk = dd + k;
+    const bool kin = kk < d;
+    const double z = kin ? (double)X[ref * d + kk] : 0.0;
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+      vr[i] = (gr[i] >= 0 && kin) ? (double)X[gr[i] * d + kk] - z : 0.0;
+      vc[i] = (gc[i] >= 0 && kin) ? (double)X[gc[i] * d + kk] - z : 0.0;
+    }
+  };
+  load(0);
+  for (int dd = 0; dd < d; dd += GK) {
+    __syncthreads();  // the previous stage's operands are consumed
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+      sr[p0 + 8 * i][k] = vr[i];
+      sc[p0 + 8 * i][k] = vc[i];
+    }
+    __syncthreads();
+    if (dd + GK < d) load(dd + GK);
+    if (tid < 128) {
+      const T* q = tid < 64 ? sr[tid] : sc[tid - 64];
+#pragma unroll
+      for (int kq = 0; kq < GK; ++kq) nrm = fma(q[kq], q[kq], nrm);
+    }
+#pragma unroll
+    for (int ks = 0; ks < GK / 4; ++ks) {
+      T a[2], b[2];
+#pragma unroll
+      for (int ci = 0; ci < 2; ++ci) a[ci] = sc[32 * wc + 16 * ci + lr][4 * ks + lg];
+#pragma unroll
+      for (int ri = 0; ri < 2; ++ri) b[ri] = sr[32 * wr + 16 * ri + lr][4 * ks + lg];
+#pragma unroll
+      for (int ci = 0; ci < 2; ++ci)
+#pragma unroll
+        for (int ri = 0; ri < 2; ++ri) acc[ci][ri] = mfma16(a[ci], b[ri], acc[ci][ri]);
+    }
+  }
+  __syncthreads();
+}
+
+// k_eval for d > 64: the same 64 x 64 tiles and stores, distances in the Gram
+// form on the matrix cores (FP64), kernel values stored in T.
+template <typename PT, typename T>
+__global__ __launch_bounds__(256) void k_eval_gram(const PT* __restrict__ X, int d,
+                                                   double nhalf_inv_h2, double shift,
+                                                   const EvalBlock* __restrict__ blocks,
+                                                   const Tile3* __restrict__ tiles) {
+  __shared__ double sr[ET][GKP];
+  __shared__ double sc[ET][GKP];
+  __shared__ int64_t rowi[ET], coli[ET];
+  __shared__ double nr[ET], nc[ET];
+  const Tile3 t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
+  const EvalBlock b = blocks[t.prob];
+  const int r0 = t.tm * ET, c0 = t.tn * ET;
+  const int tid = threadIdx.x;
+  if (tid < ET) {
+    const int r = r0 + tid;
+    rowi[tid] = (r < b.rows) ? b.row0 + r : -1;
+  } else if (tid < 2 * ET) {
+    const int c = c0 + tid - ET;
+    int64_t g = -1;
+    if (c < b.ncols) g = b.cols ? (int64_t)b.cols[c] : b.col0 + c;
+    coli[tid - ET] = g;
+  }
+  f64x4 acc[2][2];
+  double nrm;
+  gram_tile<PT>(X, d, b.row0 + r0, rowi, coli, sr, sc, acc, nrm);
+  if (tid < ET)
+    nr[tid] = nrm;
+  else if (tid < 2 * ET)
+    nc[tid - ET] = nrm;
+  __syncthreads();
+  const int lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lg = lane >> 4;
+  const int wr = wave & 1, wc = wave >> 1;
+  T* __restrict__ out = static_cast<T*>(b.out);
+#pragma unroll
+  for (int ri = 0; ri < 2; ++ri) {
+    const int rl = 32 * wr + 16 * ri + lr;
+    const int r = r0 + rl;
+#pragma unroll
+    for (int ci = 0; ci < 2; ++ci)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int cl = 32 * wc + 16 * ci + acc_row(0.0, lg, v);
+        const int c = c0 + cl;
+        if (r < b.rows && c < b.ncols) {
+          double r2 = fmax(nr[rl] + nc[cl] - 2.0 * acc[ci][ri][v], 0.0);
+          if (rowi[rl] == coli[cl]) r2 = 0.0;
+          double val = exp(r2 * nhalf_inv_h2);
+          if (b.diag && r == c) val += shift;
+          out[(int64_t)c * b.ld + r] = (T)val;
+        }
+      }
   }
 }
 
@@ -196,108 +347,89 @@ __global__ __launch_bounds__(MB / TPT) void k_mv_eval(const PT* __restrict__ X, 
   }
 }
 
-// Wide form for d > 64: a workgroup takes kMvWideRows = 64 targets against
-// 64 sources at a time; squared distances accumulate by direct differences
-// over coordinate chunks of 16 staged through LDS (4 x 4 pairs per thread, as
-// in k_eval), then exp and the weights are applied in registers and the 16
-// threads that share a target are summed through LDS at the end.
-constexpr int WT = kMvWideRows;  // targets per workgroup
+constexpr int WT = kMvWideRows;  // targets per workgroup of the d > 64 form
 constexpr int WS = 64;           // sources per stage
-constexpr int WD = 16;           // coordinates per LDS chunk
 
+// k_mv_eval for d > 64, in the Gram form (FP64 MFMA): a workgroup takes 64 targets
+// against 64 sources at a time; each lane turns its Gram entries into kernel
+// values and accumulates K w for its targets over the sources it holds, and
+// the eight partial sums of a target (four lane groups times two waves) are
+// added through LDS at the end.
 template <typename PT>
-__global__ __launch_bounds__(256) void k_mv_eval_wide(
+__global__ __launch_bounds__(256) void k_mv_eval_gram(
     const PT* __restrict__ X, int d, double nhalf_inv_h2, double lam,
     const MvTile* __restrict__ tiles, const MvSeg* __restrict__ segs,
     const double* __restrict__ x, int64_t ldx, double* __restrict__ y, int64_t ldy,
     const double* __restrict__ bsub, int64_t ldb, int nrhs) {
-  __shared__ double xt[WD][WT + 1];
-  __shared__ double xs[WD][WS + 1];
+  __shared__ double sr[WT][GKP];
+  __shared__ double sc[WS][GKP];
+  __shared__ int64_t rowi[WT], coli[WS];
+  __shared__ double nr[WT], nc[WS];
   __shared__ double sw[WS][RC];
-  __shared__ int64_t sidx[WS];
-  __shared__ double red[16][WT][RC];
+  __shared__ double red[8][WT][RC];
   const MvTile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
   const int tid = threadIdx.x;
-  const int tr = tid & 15, tc = tid >> 4;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lg = lane >> 4;
+  const int wr = wave & 1, wc = wave >> 1;
+  if (tid < WT) rowi[tid] = (tid < t.rows) ? t.row0 + tid : -1;
 
   for (int cb = 0; cb < nrhs; cb += RC) {
     const int ncol = min(RC, nrhs - cb);
-    double acc[4][RC];
+    double acc[2][RC];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int ri = 0; ri < 2; ++ri)
 #pragma unroll
-      for (int c = 0; c < RC; ++c) acc[i][c] = 0.0;
+      for (int c = 0; c < RC; ++c) acc[ri][c] = 0.0;
     for (int sg = t.seg0; sg < t.seg0 + t.nseg; ++sg) {
       const MvSeg g = segs[sg];
       for (int j0 = 0; j0 < g.count; j0 += WS) {
         const int nj = min(WS, g.count - j0);
-        __syncthreads();
+        __syncthreads();  // the previous stage's coli, sw, nr, nc are consumed
         if (tid < WS)
-          sidx[tid] = (tid < nj) ? (g.idx ? (int64_t)g.idx[j0 + tid] : g.p0 + j0 + tid) : -1;
+          coli[tid] = (tid < nj) ? (g.idx ? (int64_t)g.idx[j0 + tid] : g.p0 + j0 + tid) : -1;
         for (int idx = tid; idx < WS * RC; idx += 256) {
           const int j = idx / RC, c = idx % RC;
           sw[j][c] = (j < nj && c < ncol) ? g.w[(int64_t)(cb + c) * g.ldw + j0 + j] : 0.0;
         }
-        double d2[4][4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) d2[i][j] = 0.0;
-        for (int dd = 0; dd < d; dd += WD) {
-          __syncthreads();
-          for (int idx = tid; idx < WT * WD; idx += 256) {
-            const int p = idx / WD, k = idx % WD;
-            xt[k][p] = (p < t.rows && dd + k < d) ? (double)X[(t.row0 + p) * d + dd + k] : 0.0;
-          }
-          for (int idx = tid; idx < WS * WD; idx += 256) {
-            const int p = idx / WD, k = idx % WD;
-            const int64_t gp = sidx[p];
-            xs[k][p] = (gp >= 0 && dd + k < d) ? (double)X[gp * d + dd + k] : 0.0;
-          }
-          __syncthreads();
-#pragma unroll
-          for (int k = 0; k < WD; ++k) {
-            double a[4], b[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) a[i] = xt[k][tr + 16 * i];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) b[j] = xs[k][tc + 16 * j];
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-              for (int j = 0; j < 4; ++j) {
-                const double df = a[i] - b[j];
-                d2[i][j] = fma(df, df, d2[i][j]);
-              }
-          }
-        }
+        f64x4 gm[2][2];
+        double nrm;
+        gram_tile<PT>(X, d, t.row0, rowi, coli, sr, sc, gm, nrm);
+        if (tid < WT)
+          nr[tid] = nrm;
+        else if (tid < WT + WS)
+          nc[tid - WT] = nrm;
+        __syncthreads();
         // sources past nj carry zero weight
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          double wv[RC];
+        for (int ri = 0; ri < 2; ++ri) {
+          const int rl = 32 * wr + 16 * ri + lr;
 #pragma unroll
-          for (int c = 0; c < RC; ++c) wv[c] = sw[tc + 16 * j][c];
+          for (int ci = 0; ci < 2; ++ci)
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const double kv = exp(d2[i][j] * nhalf_inv_h2);
+            for (int v = 0; v < 4; ++v) {
+              const int cl = 32 * wc + 16 * ci + acc_row(0.0, lg, v);
+              double r2 = fmax(nr[rl] + nc[cl] - 2.0 * gm[ci][ri][v], 0.0);
+              if (rowi[rl] == coli[cl]) r2 = 0.0;
+              const double kv = exp(r2 * nhalf_inv_h2);
 #pragma unroll
-            for (int c = 0; c < RC; ++c) acc[i][c] = fma(kv, wv[c], acc[i][c]);
-          }
+              for (int c = 0; c < RC; ++c) acc[ri][c] = fma(kv, sw[cl][c], acc[ri][c]);
+            }
         }
       }
     }
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int ri = 0; ri < 2; ++ri)
 #pragma unroll
-      for (int c = 0; c < RC; ++c) red[tc][tr + 16 * i][c] = acc[i][c];
+      for (int c = 0; c < RC; ++c) red[4 * wc + lg][32 * wr + 16 * ri + lr][c] = acc[ri][c];
     __syncthreads();
     if (tid < t.rows) {
       const int64_t i = t.row0 + tid;
       for (int c = 0; c < ncol; ++c) {
         double sum = 0.0;
 #pragma unroll
-        for (int q = 0; q < 16; ++q) sum += red[q][tid][c];
+        for (int q = 0; q < 8; ++q) sum += red[q][tid][c];
         const double ax = lam * x[(int64_t)(cb + c) * ldx + i] + sum;
         y[(int64_t)(cb + c) * ldy + i] = bsub ? bsub[(int64_t)(cb + c) * ldb + i] - ax : ax;
       }
@@ -330,8 +462,12 @@ hipError_t launch_eval(const PT* X, int d, double h, double shift, const EvalBlo
                        const Tile3* tiles, int ntiles, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
   const double c = -0.5 / (h * h);
-  hipLaunchKernelGGL((k_eval<PT, T>), dim3(ntiles), dim3(256), 0, s, X, d, c, shift, blocks,
-                     tiles);
+  if (d > kMvMaxDim)
+    hipLaunchKernelGGL((k_eval_gram<PT, T>), dim3(ntiles), dim3(256), 0, s, X, d, c, shift,
+                       blocks, tiles);
+  else
+    hipLaunchKernelGGL((k_eval<PT, T>), dim3(ntiles), dim3(256), 0, s, X, d, c, shift, blocks,
+                       tiles);
   return hipGetLastError();
 }
 
@@ -355,7 +491,7 @@ hipError_t launch_mv_eval(const PT* X, int d, double h, double lam, const MvTile
   else if (d <= 64)
     INVASKIT_MV(64);
   else
-    hipLaunchKernelGGL((k_mv_eval_wide<PT>), dim3(ntiles), dim3(256), 0, s, X, d, c, lam, tiles,
+    hipLaunchKernelGGL((k_mv_eval_gram<PT>), dim3(ntiles), dim3(256), 0, s, X, d, c, lam, tiles,
                        segs, x, ldx, y, ldy, b, ldb, nrhs);
 #undef INVASKIT_MV
   return hipGetLastError();

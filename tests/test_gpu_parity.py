@@ -37,7 +37,10 @@ def _rel(a, b):
 
 
 # ---------------------------------------------------------------- building blocks
+# d > 64 takes the Gram form on the matrix cores: 100 and 130 leave ragged
+# 32-coordinate stages, 784 is the image-like workload's dimension
 @pytest.mark.parametrize("pdt,odt,d", [("f64", "f64", 8), ("f64", "f32", 8), ("f64", "f64", 54),
+                                       ("f64", "f64", 100), ("f64", "f32", 130),
                                        ("f32", "f64", 784), ("f32", "f32", 784)])
 def test_kernel_blocks(bind, pdt, odt, d):
     _say("kernel_blocks", pdt, odt, d)
@@ -156,12 +159,14 @@ CASES = [
     ("normal", dict(n=4096, depth=3), 2),         # d = 64, s = 256
     ("susy", dict(n=4096, depth=4), 64),          # 64 right-hand sides
     ("tiny", dict(n=2048, depth=1), 2),           # leaves of 1024: the largest order
+    ("mnist", dict(n=2048, depth=2, d=100, h=1.0), 2),   # d = 100: ragged Gram stages
 ]
-# the matvec and mixed-precision checks: the first four cases and the last four
-MV_CASES = CASES[:4] + CASES[-4:]
+# the matvec and mixed-precision checks: the first four cases and the last five
+MV_CASES = CASES[:4] + CASES[-5:]
 # Mixed path: the refined residual is <= 1e-10, so x can differ from the
-# oracle's by up to kappa * 1e-10; kappa(lambda I + K~) is about 1e4 for the
-# 784-dimensional case (dense estimate at this size) and below 30 elsewhere.
+# oracle's by up to kappa * 1e-10; kappa(lambda I + K) is about 1.7e3 for the
+# 784-dimensional case and 1.3e4 for the 100-dimensional one (dense estimates
+# at these sizes), below 30 elsewhere.
 MIXED_XTOL = {"mnist": 1e-5}
 
 
