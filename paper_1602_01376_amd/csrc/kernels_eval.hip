@@ -140,12 +140,6 @@ __device__ __forceinline__ void gram_tile(const PT* __restrict__ X, int d, int64
     for (int b = 0; b < 2; ++b) acc[a][b] = V4{0, 0, 0, 0};
   nrm = 0.0;
   __syncthreads();  // rowi / coli written by the caller
-  int64_t gr[NP], gc[NP];
-#pragma unroll
-  for (int i = 0; i < NP; ++i) {
-    gr[i] = rowi[p0 + 8 * i];
-    gc[i] = coli[p0 + 8 * i];
-  }
   T vr[NP], vc[NP];
   auto load = [&](int dd) {
     const int kk = dd + k;
@@ -153,8 +147,9 @@ __device__ __forceinline__ void gram_tile(const PT* __restrict__ X, int d, int64
     const double z = kin ? (double)X[ref * d + kk] : 0.0;
 #pragma unroll
     for (int i = 0; i < NP; ++i) {
-      vr[i] = (gr[i] >= 0 && kin) ? (double)X[gr[i] * d + kk] - z : 0.0;
-      vc[i] = (gc[i] >= 0 && kin) ? (double)X[gc[i] * d + kk] - z : 0.0;
+      const int64_t gr = rowi[p0 + 8 * i], gc = coli[p0 + 8 * i];
+      vr[i] = (gr >= 0 && kin) ? (double)X[gr * d + kk] - z : 0.0;
+      vc[i] = (gc >= 0 && kin) ? (double)X[gc * d + kk] - z : 0.0;
     }
   };
   load(0);
@@ -247,13 +242,16 @@ __global__ __launch_bounds__(256) void k_eval_gram(const PT* __restrict__ X, int
 
 constexpr int MB = kMvBlock;  // targets per workgroup
 constexpr int MS = 64;        // sources per LDS stage
-constexpr int RC = 4;         // right-hand sides per pass
+// RC right-hand sides per pass over the sources: 4, or 16 when there are
+// more than 4, so that every kernel value serves 16 columns and the
+// distances are computed a quarter as often (the Gram form keeps 4: its
+// registers also hold the MFMA tiles)
 
 // TPT targets per thread (2 for d <= 16: two independent distance/exp
 // chains per thread and half the LDS reads per pair), MB / TPT threads.
 // Source rows are read by all lanes at once (LDS broadcast), so they are
 // stored unpadded and read as 16-byte vectors.
-template <typename PT, int DM, int TPT>
+template <typename PT, int DM, int TPT, int RC>
 __global__ __launch_bounds__(MB / TPT) void k_mv_eval(const PT* __restrict__ X, int d,
                                                       double nhalf_inv_h2, double lam,
                                                       const MvTile* __restrict__ tiles,
@@ -352,10 +350,10 @@ constexpr int WS = 64;           // sources per stage
 
 // k_mv_eval for d > 64, in the Gram form (FP64 MFMA): a workgroup takes 64 targets
 // against 64 sources at a time; each lane turns its Gram entries into kernel
-// values and accumulates K w for its targets over the sources it holds, and
-// the eight partial sums of a target (four lane groups times two waves) are
-// added through LDS at the end.
-template <typename PT>
+// values and accumulates K w for its targets over the sources it holds; at
+// the end the four lane groups of a target are summed across lanes and the
+// two waves that share it through LDS.
+template <typename PT, int RC>
 __global__ __launch_bounds__(256) void k_mv_eval_gram(
     const PT* __restrict__ X, int d, double nhalf_inv_h2, double lam,
     const MvTile* __restrict__ tiles, const MvSeg* __restrict__ segs,
@@ -366,7 +364,7 @@ __global__ __launch_bounds__(256) void k_mv_eval_gram(
   __shared__ int64_t rowi[WT], coli[WS];
   __shared__ double nr[WT], nc[WS];
   __shared__ double sw[WS][RC];
-  __shared__ double red[8][WT][RC];
+  __shared__ double red[2][WT][RC];
   const MvTile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -422,14 +420,17 @@ __global__ __launch_bounds__(256) void k_mv_eval_gram(
 #pragma unroll
     for (int ri = 0; ri < 2; ++ri)
 #pragma unroll
-      for (int c = 0; c < RC; ++c) red[4 * wc + lg][32 * wr + 16 * ri + lr][c] = acc[ri][c];
+      for (int c = 0; c < RC; ++c) {
+        double v = acc[ri][c];
+        v += __shfl_xor(v, 16);
+        v += __shfl_xor(v, 32);
+        if (lg == 0) red[wc][32 * wr + 16 * ri + lr][c] = v;
+      }
     __syncthreads();
     if (tid < t.rows) {
       const int64_t i = t.row0 + tid;
       for (int c = 0; c < ncol; ++c) {
-        double sum = 0.0;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) sum += red[q][tid][c];
+        const double sum = red[0][tid][c] + red[1][tid][c];
         const double ax = lam * x[(int64_t)(cb + c) * ldx + i] + sum;
         y[(int64_t)(cb + c) * ldy + i] = bsub ? bsub[(int64_t)(cb + c) * ldb + i] - ax : ax;
       }
@@ -478,21 +479,28 @@ hipError_t launch_mv_eval(const PT* X, int d, double h, double lam, const MvTile
                           hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
   const double c = -0.5 / (h * h);
-#define INVASKIT_MV(DMV)                                                                    \
-  hipLaunchKernelGGL((k_mv_eval<PT, DMV, (DMV <= 16 ? 2 : 1)>), dim3(ntiles),              \
+#define INVASKIT_MV(DMV, RCV)                                                                \
+  hipLaunchKernelGGL((k_mv_eval<PT, DMV, (DMV <= 16 ? 2 : 1), RCV>), dim3(ntiles),          \
                      dim3(MB / (DMV <= 16 ? 2 : 1)), 0, s, X, d, c, lam, tiles, segs, x, ldx, y, \
                      ldy, b, ldb, nrhs)
-  if (d <= 8)
-    INVASKIT_MV(8);
-  else if (d <= 16)
-    INVASKIT_MV(16);
-  else if (d <= 32)
-    INVASKIT_MV(32);
-  else if (d <= 64)
-    INVASKIT_MV(64);
-  else
-    hipLaunchKernelGGL((k_mv_eval_gram<PT>), dim3(ntiles), dim3(256), 0, s, X, d, c, lam, tiles,
-                       segs, x, ldx, y, ldy, b, ldb, nrhs);
+#define INVASKIT_MV_RC(RCV)                                                                  \
+  if (d <= 8)                                                                                \
+    INVASKIT_MV(8, RCV);                                                                     \
+  else if (d <= 16)                                                                          \
+    INVASKIT_MV(16, RCV);                                                                    \
+  else if (d <= 32)                                                                          \
+    INVASKIT_MV(32, RCV);                                                                    \
+  else if (d <= 64)                                                                          \
+    INVASKIT_MV(64, RCV);                                                                    \
+  else                                                                                       \
+    hipLaunchKernelGGL((k_mv_eval_gram<PT, 4>), dim3(ntiles), dim3(256), 0, s, X, d, c, lam,   \
+                       tiles, segs, x, ldx, y, ldy, b, ldb, nrhs)
+  if (nrhs <= 4) {
+    INVASKIT_MV_RC(4);
+  } else {
+    INVASKIT_MV_RC(16);
+  }
+#undef INVASKIT_MV_RC
 #undef INVASKIT_MV
   return hipGetLastError();
 }
