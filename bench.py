@@ -58,10 +58,18 @@ CSRC = os.path.join(ROOT, "paper_1602_01376_amd", "csrc")
 COPY_KERNEL = "k_copy_cols<double, double>"
 # phases whose time is one launch of a uniquely named kernel: name pattern
 # (t = element type) and the source file that holds it
+# the phase's kernel; {p} is its tile parameter (LU panel width, or 16-column
+# tiles per workgroup of the solves)
 PHASE_KERNEL = {
-    "leaf_lu": (r"k_getrf<{t}, \d+, \d+, 0>", "kernels_lu.hip"),
-    "leaf_solves": (r"k_getrs<{t}, {t}, 0>", "kernels_trsm.hip"),
+    "leaf_lu": (r"k_getrf<{t}, {p}, \d+, 0>", "kernels_lu.hip"),
+    "leaf_solves": (r"k_getrs<{t}, {t}, 0, {p}>", "kernels_trsm.hip"),
 }
+
+
+def phase_tile_param(phase, tiles):
+    if phase == "leaf_lu":
+        return str(tiles["leaf_lu_panel"])
+    return str(tiles["leaf_trsm_cols"] // 16)
 
 
 def source_digest(src):
@@ -104,7 +112,7 @@ def write_traffic(fetch_csv, write_csv, copy_bytes, command):
     entries = {}
     for phase, (pat, src) in PHASE_KERNEL.items():
         for t in ("float", "double"):
-            rx = re.compile(pat.format(t=t) + "$")
+            rx = re.compile(pat.format(t=t, p=r"\d+") + "$")
             names = [k for k in fetch if rx.match(k)]
             for k in names:
                 fk, wk = float(np.mean(fetch[k])), float(np.mean(write.get(k, [0.0])))
@@ -123,13 +131,14 @@ def write_traffic(fetch_csv, write_csv, copy_bytes, command):
     return out
 
 
-def traffic_for(phase, t):
-    """Scaled HBM bytes per launch of the phase's kernel, or None when no
-    counters were taken or the kernel's sources changed since."""
+def traffic_for(phase, t, tiles):
+    """Scaled HBM bytes per launch of the phase's kernel (the tile variant
+    the factorization used), or None when no counters were taken for it or
+    the kernel's sources changed since."""
     if phase not in PHASE_KERNEL or not os.path.exists(TRAFFIC_FILE):
         return None
     pat, src = PHASE_KERNEL[phase]
-    rx = re.compile(pat.format(t=t) + "$")
+    rx = re.compile(pat.format(t=t, p=phase_tile_param(phase, tiles)) + "$")
     with open(TRAFFIC_FILE) as fh:
         data = json.load(fh)
     digest = source_digest(src)
@@ -413,8 +422,8 @@ def main():
     dom = max(cand, key=cand.get)
     wk = work[dom]
     per_launch_ms = ph[dom] / max(wk["launches"], 1)
-    traffic = (traffic_for(dom, ctype) if (headline and args.n is None and args.nrhs == 1)
-               else None)
+    traffic = (traffic_for(dom, ctype, head["tiles"])
+               if (headline and args.n is None and args.nrhs == 1) else None)
     if wk["flops"] > 0:
         achieved = wk["flops"] / wk["launches"] / (per_launch_ms * 1e-3) / 1e12
         # the kernel blocks' Gram products run in FP64 in both precisions
