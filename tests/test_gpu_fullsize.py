@@ -72,3 +72,28 @@ def test_full_size_solutions(bind):
     # kappa(lambda I + K~) is about 13 at N = 65,536 on this generator; 1e-8
     # leaves room for a hundredfold larger kappa at full size
     assert diff <= 1e-8
+
+
+def test_full_size_covtype_16_rhs(bind):
+    """The 65,536-point d = 54 workload at full size with its 16 right-hand
+    sides: the oracle's independent product gives the whole residual."""
+    _say("setup covtype full size")
+    pb = make_problem("covtype")
+    assert pb.n == 1 << 16 and pb.d == 54 and pb.depth == 8
+    b = rhs_for(pb, nrhs=16)
+    xs = {}
+    for mode in ("mixed", "fp64"):
+        _say("factor + solve", mode)
+        fac = bind.Factorization(pb, pb.lam, precision=mode)
+        x, info, st = fac.solve(torch.from_numpy(b), return_info=True)
+        _say("  info", info)
+        assert st == 0 and info["final_rel_residual"] <= 1e-10
+        x = x.cpu().numpy()
+        res = np.linalg.norm(b - oracle.matvec(pb, pb.lam, x)) / np.linalg.norm(b)
+        _say("  oracle residual", res)
+        assert res <= (1e-10 if mode == "mixed" else 1e-12)
+        xs[mode] = x
+        fac.close()
+    diff = np.linalg.norm(xs["mixed"] - xs["fp64"]) / np.linalg.norm(xs["fp64"])
+    _say("mixed vs fp64", diff)
+    assert diff <= 1e-8

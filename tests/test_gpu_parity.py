@@ -346,6 +346,33 @@ def test_autotune_times_candidates_once(bind, problems):
     bind.tuning_clear()
 
 
+def test_lambda_sweep_eight_lambdas_32_rhs(bind):
+    """The sweep workload's shape at reduced N (d = 64, leaves of 512,
+    s = 256, 32 right-hand sides): eight lambdas in logspace(-6, -1), factored
+    as sweeps of 3, 3 and 2 handles that share their kernel blocks, in
+    mixed precision.  Every lambda's solution is checked by the oracle's
+    product; three are also compared with the oracle's solution."""
+    _say("eight-lambda sweep, 32 rhs")
+    pb = make_problem("normal", n=8192, depth=4)
+    assert pb.d == 64 and pb.s(1) == 256
+    b = rhs_for(pb, nrhs=32)
+    lams = list(np.logspace(-6, -1, 8))
+    done = 0
+    for group in (lams[0:3], lams[3:6], lams[6:8]):
+        facs = bind.factor_sweep(pb, group, precision="mixed")
+        for lam, fac in zip(group, facs):
+            x, info, st = fac.solve(torch.from_numpy(b), return_info=True)
+            assert st == 0 and info["final_rel_residual"] <= 1e-10, (lam, info)
+            x = x.cpu().numpy()
+            assert _rel(oracle.matvec(pb, lam, x), b) <= 1e-10, lam
+            if done in (0, 4, 7):
+                assert _rel(x, oracle.solve(oracle.factorize(pb, lam), b)) <= 1e-7, lam
+            done += 1
+        for f in facs:
+            f.close()
+    assert done == 8
+
+
 def test_singular_leaf_is_reported(bind):
     _say("singular leaf")
     pb = make_problem("tiny", n=256, depth=2)
