@@ -296,6 +296,8 @@ def main():
                     help="tile autotuning of the leaf LU and leaf solves")
     ap.add_argument("--lu-panel", type=int, default=0, choices=[0, 16, 32],
                     help="fix the leaf LU panel width (0: per --tune)")
+    ap.add_argument("--lu-waves", type=int, default=0, choices=[0, 4, 8],
+                    help="fix the leaf LU's waves per matrix (0: per --tune)")
     ap.add_argument("--trsm-cols", type=int, default=0, choices=[0, 16, 32],
                     help="fix the leaf solves' right-hand sides per workgroup (0: per --tune)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -375,7 +377,8 @@ def main():
     for mode in modes:
         fac = binding.Factorization(pb, lam, precision=mode, points=X, p_values=P,
                                     tune=args.tune, leaf_lu_panel=args.lu_panel,
-                                    leaf_trsm_cols=args.trsm_cols)
+                                    leaf_trsm_cols=args.trsm_cols,
+                                    leaf_lu_waves=args.lu_waves)
         tiles = fac.tile_config()  # the first factor's trials, if it tuned
         log(f"{mode}: device bytes {fac.device_bytes() / 2**30:.2f} GiB, tiles {tiles}")
         for _ in range(args.warmup):

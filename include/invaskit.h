@@ -103,15 +103,18 @@ typedef struct invaskit_options {
   int32_t leaf_trsm_cols;   /* 0 (default): per `tune`; 16 or 32: right-hand
                                sides per workgroup in the leaf solves of the
                                factorization                                      */
-  int32_t reserved0;        /* set to 0                                          */
+  int32_t leaf_lu_waves;    /* 0 (default): per `tune`; 4 or 8: waves (of 64
+                               lanes) per matrix in the leaf LU                   */
 } invaskit_options;
 
 /*
  * Tile autotuning.  The two largest launches of a factorization, the LU of
  * the leaf blocks (Algorithm 1's leaf factorization) and the leaf solves of
  * every level's panel columns (Algorithm 2 at the leaves), each have two
- * tile shapes: an LU panel width of 16 or 32, and 16 or 32 right-hand sides
- * per workgroup (32 reuses each factor tile for twice the columns but needs
+ * tile shapes: for the LU a panel width of 16 or 32 and 4 or 8 waves per
+ * matrix (8 halves each thread's panel rows and doubles the waves sharing a
+ * matrix's trailing update), for the solves 16 or 32 right-hand sides per
+ * workgroup (32 reuses each factor tile for twice the columns but needs
  * twice the LDS, so fewer workgroups share a compute unit).  Which is faster
  * depends on the leaf sizes, the ranks and the precision.
  *
@@ -123,12 +126,16 @@ typedef struct invaskit_options {
  *                      before every trial: both launches work in place);
  *                      the faster is recorded and used from then on by every
  *                      handle.  The first factorization of a new shape class
- *                      therefore takes longer (about four extra leaf LUs and
- *                      leaf solves).
+ *                      therefore takes longer (up to eight extra leaf LUs
+ *                      and four extra leaf solves).
  *  INVASKIT_TUNE_OFF   the built-in defaults (LU panel 32 in FP32 and 16 in
- *                      FP64; 16 right-hand sides), no timing.
- * A nonzero leaf_lu_panel or leaf_trsm_cols fixes that choice whatever
- * `tune` says.  32 right-hand sides need (32 + 1) * elem + 4 bytes of LDS
+ *                      FP64, 4 waves; 16 right-hand sides), no timing.
+ * A nonzero leaf_lu_panel, leaf_lu_waves or leaf_trsm_cols fixes that choice
+ * whatever `tune` says (the LU's candidates are the pairs that agree with
+ * the fixed ones).  Leaf LUs of FP32 orders up to 192 always take the
+ * one-wave kernel, for which the LU choices do not apply.  FP64 has no LU
+ * with panel 32 at 8 waves (it would spill registers): asking for both is
+ * INVASKIT_E_ARG, and the tuner leaves that pair out.  32 right-hand sides need (32 + 1) * elem + 4 bytes of LDS
  * per row of the largest leaf; if that exceeds 160 KiB (FP64 leaves above
  * 611 points) AUTO keeps 16 and a fixed 32 fails with INVASKIT_E_ARG.
  */
@@ -239,22 +246,25 @@ int invaskit_phase_times(invaskit_handle handle, double* ms, int32_t n);
 /* The tile shapes the last factor of `handle` used (see Tile autotuning). */
 typedef struct invaskit_tile_config {
   int32_t leaf_lu_panel;   /* 16 or 32                                          */
+  int32_t leaf_lu_waves;   /* 4 or 8                                            */
   int32_t leaf_trsm_cols;  /* 16 or 32                                          */
-  int32_t tuned;           /* 1 if that factor timed the candidates itself      */
-  int32_t reserved0;
-  float lu_ms[2];          /* its trial times (best of two) for panels 16, 32   */
+  int32_t tuned;           /* 1 if that factor timed candidates itself          */
+  float lu_ms[4];          /* its trial times (best of two) for the LU with
+                              (panel, waves) = (16,4), (32,4), (16,8), (32,8)   */
   float trsm_ms[2];        /* and for 16, 32 right-hand sides; 0 if not timed   */
 } invaskit_tile_config;
 int invaskit_tile_config_get(invaskit_handle handle, invaskit_tile_config* out);
 
 /*
  * The process-wide tuning table as text, one "key value" line per entry
- * (key: shape class, value: the chosen tile parameter), so that a caller can
- * keep it across processes.  export: writes at most `n` bytes including the
+ * (key: shape class, value: the chosen tile parameter: 16 or 32, or for the
+ * "getrfw." keys the LU's waves, 4 or 8), so that a caller can keep it
+ * across processes.  export: writes at most `n` bytes including the
  * terminating NUL into buf (buf may be NULL when n == 0) and sets *needed to
  * the full size including the NUL.  import: adds (or replaces) the entries of
- * `text` in that format; a malformed line or a value other than 16 or 32
- * fails with INVASKIT_E_ARG and changes nothing.  clear: empties the table.
+ * `text` in that format; a malformed line, an unknown key prefix or a value
+ * out of its key's set fails with INVASKIT_E_ARG and changes nothing.
+ * clear: empties the table.
  */
 int invaskit_tuning_export(char* buf, size_t n, size_t* needed);
 int invaskit_tuning_import(const char* text);

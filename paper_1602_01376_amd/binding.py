@@ -39,16 +39,16 @@ class _Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("fp64_top_levels", C.c_int32),
                 ("refine_tol", C.c_double), ("max_refine_iters", C.c_int32),
                 ("tune", C.c_int32), ("leaf_lu_panel", C.c_int32),
-                ("leaf_trsm_cols", C.c_int32), ("reserved0", C.c_int32)]
+                ("leaf_trsm_cols", C.c_int32), ("leaf_lu_waves", C.c_int32)]
 
 
 TUNE_AUTO, TUNE_OFF = 0, 1
 
 
 class _TileConfig(C.Structure):
-    _fields_ = [("leaf_lu_panel", C.c_int32), ("leaf_trsm_cols", C.c_int32),
-                ("tuned", C.c_int32), ("reserved0", C.c_int32),
-                ("lu_ms", C.c_float * 2), ("trsm_ms", C.c_float * 2)]
+    _fields_ = [("leaf_lu_panel", C.c_int32), ("leaf_lu_waves", C.c_int32),
+                ("leaf_trsm_cols", C.c_int32), ("tuned", C.c_int32),
+                ("lu_ms", C.c_float * 4), ("trsm_ms", C.c_float * 2)]
 
 
 class SolveInfo(C.Structure):
@@ -147,10 +147,10 @@ class Factorization:
     def __init__(self, problem, lam: float, precision: str = "fp64",
                  fp64_top_levels: int = 4, refine_tol: float = 1e-10,
                  max_refine_iters: int = 30, points=None, p_values=None, tune: str = "auto",
-                 leaf_lu_panel: int = 0, leaf_trsm_cols: int = 0):
+                 leaf_lu_panel: int = 0, leaf_trsm_cols: int = 0, leaf_lu_waves: int = 0):
         pb, opt = self._prepare(problem, lam, precision, fp64_top_levels, refine_tol,
                                 max_refine_iters, points, p_values, tune, leaf_lu_panel,
-                                leaf_trsm_cols)
+                                leaf_trsm_cols, leaf_lu_waves)
         self._handle = C.c_void_p()
         st = _lib.invaskit_factor(C.byref(pb), self.lam, C.byref(opt), _stream(),
                                   C.byref(self._handle))
@@ -162,7 +162,8 @@ class Factorization:
             raise InvaskitError(st, msg)
 
     def _prepare(self, problem, lam, precision, fp64_top_levels, refine_tol, max_refine_iters,
-                 points, p_values, tune="auto", leaf_lu_panel=0, leaf_trsm_cols=0):
+                 points, p_values, tune="auto", leaf_lu_panel=0, leaf_trsm_cols=0,
+                 leaf_lu_waves=0):
         """Marshal the problem and options (the arrays stay alive with self)."""
         self.n = problem.n
         self.lam = float(lam)
@@ -194,6 +195,7 @@ class Factorization:
         opt.tune = TUNE_OFF if tune == "off" else TUNE_AUTO
         opt.leaf_lu_panel = int(leaf_lu_panel)
         opt.leaf_trsm_cols = int(leaf_trsm_cols)
+        opt.leaf_lu_waves = int(leaf_lu_waves)
         return pb, opt
 
     @property
@@ -246,8 +248,9 @@ class Factorization:
         """Tile shapes of the last factor (invaskit_tile_config_get)."""
         t = _TileConfig()
         _check(_lib.invaskit_tile_config_get(self._handle, C.byref(t)), self._handle)
-        return {"leaf_lu_panel": t.leaf_lu_panel, "leaf_trsm_cols": t.leaf_trsm_cols,
-                "tuned": t.tuned, "lu_ms": list(t.lu_ms), "trsm_ms": list(t.trsm_ms)}
+        return {"leaf_lu_panel": t.leaf_lu_panel, "leaf_lu_waves": t.leaf_lu_waves,
+                "leaf_trsm_cols": t.leaf_trsm_cols, "tuned": t.tuned, "lu_ms": list(t.lu_ms),
+                "trsm_ms": list(t.trsm_ms)}
 
     def device_bytes(self):
         v = C.c_size_t()
@@ -398,14 +401,14 @@ def gemm_batched(problems, dtype=torch.float64, alpha=1.0, beta=0.0):
 def factor_sweep(problem, lams, precision: str = "fp64", fp64_top_levels: int = 4,
                  refine_tol: float = 1e-10, max_refine_iters: int = 30, points=None,
                  p_values=None, tune: str = "auto", leaf_lu_panel: int = 0,
-                 leaf_trsm_cols: int = 0):
+                 leaf_trsm_cols: int = 0, leaf_lu_waves: int = 0):
     """One Factorization per lambda in `lams` (invaskit_factor_sweep): the
     kernel blocks are evaluated once and shared by the handles."""
     lams = [float(v) for v in lams]
     objs = [Factorization.__new__(Factorization) for _ in lams]
     pb, opt = objs[0]._prepare(problem, lams[0], precision, fp64_top_levels, refine_tol,
                                max_refine_iters, points, p_values, tune, leaf_lu_panel,
-                               leaf_trsm_cols)
+                               leaf_trsm_cols, leaf_lu_waves)
     for o, lam in zip(objs[1:], lams[1:]):
         o.n, o.lam, o.precision = objs[0].n, lam, precision
         o._points, o._p = objs[0]._points, objs[0]._p

@@ -165,9 +165,10 @@ template <typename TZ>
 hipError_t launch_diag_inv(const DiagInvProb* probs, int count, hipStream_t s);
 
 // kind: 0 leaf blocks, 1 reduced systems.  panel: the LU panel width, 0 for
-// the default (getrf_default_panel), or 16 / 32 for kind 0
+// the default (getrf_default_panel), or 16 / 32 for kind 0; waves: waves per
+// matrix of the block kernel, 0 for the default (4), or 4 / 8 for kind 0
 template <typename T>
-hipError_t launch_getrf(const LuProb* probs, int count, int nmax, int kind, int panel,
+hipError_t launch_getrf(const LuProb* probs, int count, int nmax, int kind, int panel, int waves,
                         hipStream_t s);
 int getrf_default_panel(bool t64);
 

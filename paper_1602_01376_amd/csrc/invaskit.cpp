@@ -113,6 +113,7 @@ struct LuL {
   size_t probs = 0;
   int count = 0, nmax = 0, t64 = 1, kind = 0;
   int panel = 0;    // LU panel width, 0 = the kernel's default
+  int waves = 0;    // waves per matrix, 0 = the kernel's default (4)
   double work = 0;  // sum of n^3 (tuning key)
 };
 struct DinvL {
@@ -202,7 +203,7 @@ struct invaskit_handle_s {
   double tol = 1e-10;
   int maxit = 30;
   int tune = INVASKIT_TUNE_AUTO;
-  int fix_lu_panel = 0, fix_trsm_cols = 0;  // 0: chosen by tuning
+  int fix_lu_panel = 0, fix_lu_waves = 0, fix_trsm_cols = 0;  // 0: chosen by tuning
   hipStream_t stream = nullptr;
   // problem (device data borrowed)
   int64_t N = 0;
@@ -354,6 +355,8 @@ int validate(H* h, const invaskit_problem* pb, double lambda, const invaskit_opt
     auto tile_ok = [](int v) { return v == 0 || v == 16 || v == 32; };
     if (!tile_ok(opt->leaf_lu_panel) || !tile_ok(opt->leaf_trsm_cols))
       return fail_h(h, INVASKIT_E_ARG, "leaf_lu_panel and leaf_trsm_cols must be 0, 16 or 32");
+    if (opt->leaf_lu_waves != 0 && opt->leaf_lu_waves != 4 && opt->leaf_lu_waves != 8)
+      return fail_h(h, INVASKIT_E_ARG, "leaf_lu_waves must be 0, 4 or 8");
   }
   const int L = pb->depth;
   const int nleaves = 1 << L;
@@ -922,8 +925,10 @@ hipError_t run_trsm(const DevBuf& tb, const TrsmL& l, hipStream_t s) {
 hipError_t run_lu(const DevBuf& tb, const LuL& l, hipStream_t s) {
   if (l.count == 0) return hipSuccess;
   if (l.t64)
-    return launch_getrf<double>(at<LuProb>(tb, l.probs), l.count, l.nmax, l.kind, l.panel, s);
-  return launch_getrf<float>(at<LuProb>(tb, l.probs), l.count, l.nmax, l.kind, l.panel, s);
+    return launch_getrf<double>(at<LuProb>(tb, l.probs), l.count, l.nmax, l.kind, l.panel,
+                                l.waves, s);
+  return launch_getrf<float>(at<LuProb>(tb, l.probs), l.count, l.nmax, l.kind, l.panel, l.waves,
+                             s);
 }
 
 hipError_t run_dinv(const DevBuf& tb, const DinvL& l, hipStream_t s) {
@@ -978,12 +983,13 @@ std::string trsm_key(const TrsmL& l) {
          ".n" + std::to_string(l.nmax) + ".w" + std::to_string(tune_bin(l.work));
 }
 
-// Settles the leaf LU panel width and the leaf solves' right-hand sides per
-// workgroup for this factor: fixed by the options, found in the table, or
-// timed.  A trial re-evaluates its launch's inputs first (both launches work
-// in place) and is timed by events on the factor's stream; each candidate
-// runs twice and keeps its faster time.  The trials leave the factor buffers
-// in an arbitrary state: the factorization that follows rebuilds them.
+// Settles the leaf LU's panel width and waves per matrix and the leaf
+// solves' right-hand sides per workgroup for this factor: fixed by the
+// options, found in the table, or timed.  A trial re-evaluates its launch's
+// inputs first (both launches work in place) and is timed by events on the
+// factor's stream; each candidate runs twice and keeps its faster time.  The
+// trials leave the factor buffers in an arbitrary state: the factorization
+// that follows rebuilds them.
 int tune_factor(H* h) {
   const FactorPlan& fp = h->fp;
   const DevBuf& tb = h->ftables;
@@ -993,26 +999,36 @@ int tune_factor(H* h) {
   tc = invaskit_tile_config{};
   const bool has32 = fp.leaf_trsm[1].ntiles >= 0;
   const bool has_trsm = h->L > 0 && fp.leaf_trsm[0].ntiles > 0;
-  // the LU panel matters only for the four-wave kernel (FP32 orders above 192)
+  // panel width and waves matter only for the block kernel (FP64, and FP32
+  // orders above 192)
   const bool lu_choice = fp.leaf_lu.t64 || fp.leaf_lu.nmax > 192;
   const std::string klu = lu_key(fp.leaf_lu), ktr = trsm_key(fp.leaf_trsm[0]);
-  int lu = h->fix_lu_panel, tr = h->fix_trsm_cols;
+  const std::string klw = "getrfw" + klu.substr(5);
+  int lu = h->fix_lu_panel, lw = h->fix_lu_waves, tr = h->fix_trsm_cols;
   if (tr == 32 && !has32)
     return fail_h(h, INVASKIT_E_ARG,
                   "leaf_trsm_cols = 32 needs more than 160 KiB of LDS at this leaf size");
+  if (fp.leaf_lu.t64 && h->fix_lu_panel == 32 && h->fix_lu_waves == 8)
+    return fail_h(h, INVASKIT_E_ARG, "the FP64 leaf LU has no panel 32 at 8 waves");
   if (!lu && !lu_choice) lu = getrf_default_panel(f64);
+  if (!lw && !lu_choice) lw = 4;
   if (!tr && (!has32 || !has_trsm)) tr = kTrsmColsDefault;
   if (h->tune == INVASKIT_TUNE_OFF) {
     if (!lu) lu = getrf_default_panel(f64);
+    if (!lw) lw = 4;
     if (!tr) tr = kTrsmColsDefault;
   }
   {
     std::lock_guard<std::mutex> g(tune_table().mu);
     auto& t = tune_table().choice;
-    if (!lu && t.count(klu)) lu = t[klu];
+    // a shape class's LU entry stands only as a pair (panel, waves)
+    if (!lu && !lw && t.count(klu) && t.count(klw)) {
+      lu = t[klu];
+      lw = t[klw];
+    }
     if (!tr && t.count(ktr)) tr = t[ktr];
   }
-  if (!lu || !tr) {
+  if (!lu || !lw || !tr) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIP_TRY(h, hipEventCreate(&e0));
     if (hipEventCreate(&e1) != hipSuccess) {
@@ -1035,20 +1051,36 @@ int tune_factor(H* h) {
       }
     };
     auto eval_leaves = [&]() { return run_eval(h, tb, fp.leaf_eval, h->lam, s); };
-    auto lu_with = [&](int panel) {
+    auto lu_with = [&](int panel, int waves) {
       LuL l = fp.leaf_lu;
       l.panel = panel;
+      l.waves = waves;
       return run_lu(tb, l, s);
     };
-    if (!lu) {
-      trial(eval_leaves, [&]() { return lu_with(16); }, tc.lu_ms[0]);
-      trial(eval_leaves, [&]() { return lu_with(32); }, tc.lu_ms[1]);
-      lu = tc.lu_ms[1] < tc.lu_ms[0] ? 32 : 16;
+    if (!lu || !lw) {
+      // candidates (panel, waves) in the order of lu_ms; a fixed one of the
+      // two restricts the others
+      const int cp[4] = {16, 32, 16, 32}, cw[4] = {4, 4, 8, 8};
+      float best = 0.f;
+      int bi = -1;
+      for (int i = 0; i < 4 && e == hipSuccess; ++i) {
+        if ((lu && cp[i] != lu) || (lw && cw[i] != lw)) continue;
+        if (fp.leaf_lu.t64 && cp[i] == 32 && cw[i] == 8) continue;  // not built
+        trial(eval_leaves, [&]() { return lu_with(cp[i], cw[i]); }, tc.lu_ms[i]);
+        if (e == hipSuccess && (bi < 0 || tc.lu_ms[i] < best)) {
+          best = tc.lu_ms[i];
+          bi = i;
+        }
+      }
+      if (bi >= 0) {
+        lu = cp[bi];
+        lw = cw[bi];
+      }
     }
     if (!tr && e == hipSuccess) {
       // the solves need the leaf factors and their diagonal-block inverses
       e = eval_leaves();
-      if (e == hipSuccess) e = lu_with(lu);
+      if (e == hipSuccess) e = lu_with(lu, lw);
       if (e == hipSuccess) e = run_dinv(tb, fp.leaf_dinv, s);
       auto eval_panels = [&]() { return run_eval(h, tb, fp.panels, 0.0, s); };
       trial(eval_panels, [&]() { return run_trsm(tb, fp.leaf_trsm[0], s); }, tc.trsm_ms[0]);
@@ -1063,10 +1095,14 @@ int tune_factor(H* h) {
     tc.tuned = 1;
     std::lock_guard<std::mutex> g(tune_table().mu);
     auto& t = tune_table().choice;
-    if (!h->fix_lu_panel && lu_choice) t[klu] = lu;
+    if (!h->fix_lu_panel && !h->fix_lu_waves && lu_choice) {
+      t[klu] = lu;
+      t[klw] = lw;
+    }
     if (!h->fix_trsm_cols && has32 && has_trsm) t[ktr] = tr;
   }
   tc.leaf_lu_panel = lu;
+  tc.leaf_lu_waves = lw;
   tc.leaf_trsm_cols = tr;
   return INVASKIT_OK;
 }
@@ -1177,6 +1213,7 @@ int run_factor(H* h) {
   {
     LuL lu = fp.leaf_lu;
     lu.panel = h->tiles.leaf_lu_panel;
+    lu.waves = h->tiles.leaf_lu_waves;
     STEP(run_lu(tb, lu, s));
   }
   STEP(close(s));
@@ -1579,8 +1616,8 @@ int invaskit_default_options(invaskit_options* opt) {
   opt->max_refine_iters = 30;
   opt->tune = INVASKIT_TUNE_AUTO;
   opt->leaf_lu_panel = 0;
+  opt->leaf_lu_waves = 0;
   opt->leaf_trsm_cols = 0;
-  opt->reserved0 = 0;
   return INVASKIT_OK;
 }
 
@@ -1604,6 +1641,7 @@ int make_handle(const invaskit_problem* pb, double lambda, const invaskit_option
   h->maxit = o.max_refine_iters;
   h->tune = o.tune;
   h->fix_lu_panel = o.leaf_lu_panel;
+  h->fix_lu_waves = o.leaf_lu_waves;
   h->fix_trsm_cols = o.leaf_trsm_cols;
   h->stream = static_cast<hipStream_t>(hip_stream);
   h->N = pb->n;
@@ -1757,8 +1795,11 @@ int invaskit_tuning_import(const char* text) {
     std::istringstream ls(line);
     std::string key, rest;
     int v = 0;
-    if (!(ls >> key >> v) || (ls >> rest) || (v != 16 && v != 32) ||
-        (key.rfind("getrf.", 0) != 0 && key.rfind("getrs.", 0) != 0))
+    const bool parsed = (ls >> key >> v) && !(ls >> rest);
+    const bool waves = key.rfind("getrfw.", 0) == 0;
+    const bool tile = key.rfind("getrf.", 0) == 0 || key.rfind("getrs.", 0) == 0;
+    if (!parsed || !(waves || tile) || (waves && v != 4 && v != 8) ||
+        (tile && v != 16 && v != 32))
       return fail_h(nullptr, INVASKIT_E_ARG, "malformed tuning line: " + line);
     add.emplace_back(key, v);
   }
@@ -1830,8 +1871,8 @@ int invaskit_getrf_batched(int32_t dtype, void* a, const int64_t* a_offsets, con
   hipError_t e = hipMemcpy(t.p, probs.data(), sizeof(LuProb) * count, hipMemcpyHostToDevice);
   if (e == hipSuccess)
     e = (dtype == INVASKIT_F64)
-            ? launch_getrf<double>(static_cast<LuProb*>(t.p), count, nmax, 1, 0, s)
-            : launch_getrf<float>(static_cast<LuProb*>(t.p), count, nmax, 1, 0, s);
+            ? launch_getrf<double>(static_cast<LuProb*>(t.p), count, nmax, 1, 0, 0, s)
+            : launch_getrf<float>(static_cast<LuProb*>(t.p), count, nmax, 1, 0, 0, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   t.release();
   if (e != hipSuccess) return fail_h(nullptr, INVASKIT_E_HIP, hipGetErrorString(e));

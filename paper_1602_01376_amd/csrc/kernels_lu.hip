@@ -1,6 +1,7 @@
 // Batched LU with partial pivoting for square matrices of uneven order (the
 // leaf LU of Algorithm 1 and the LU of the reduced systems of eq. (11)), one
-// workgroup of four waves per matrix, every matrix of a launch in one grid.
+// workgroup of NW waves per matrix (4, or 8 for the leaf blocks when the
+// tuner finds it faster), every matrix of a launch in one grid.
 //
 // Matrices are row-major and rows never move: P A = L U is stored with
 // logical row j of the packed L\U (unit-lower L below the diagonal, U on and
@@ -10,11 +11,11 @@
 // row interchange from the factorization.  Right-looking blocked algorithm
 // with panels of W columns (32 in FP32, 16 in FP64):
 //   1. Panel.  The panel's rows are gathered into registers across the
-//      workgroup (logical row j0 + r in thread r % 256, slot r / 256), each
+//      workgroup (logical row j0 + r in thread r % NT, slot r / NT), each
 //      carrying its logical position.  Per column: every wave finds its
 //      candidate (the first row of largest magnitude: LAPACK getrf
 //      semantics) and the owning lane publishes that row in LDS; one
-//      barrier; every thread picks the winner of the four, exchanges the two
+//      barrier; every thread picks the winner of the NW, exchanges the two
 //      logical positions, scales by the pivot's reciprocal and updates its
 //      rows -- one barrier per column (the candidate rows are
 //      double-buffered).
@@ -117,10 +118,12 @@ __device__ __forceinline__ void static_for(F&& f) {
   static_for_impl(f, std::make_integer_sequence<int, N>{});
 }
 
-template <typename T, int W, int RPS, int KIND>
-__global__ __launch_bounds__(256) void k_getrf(const LuProb* __restrict__ probs) {
+template <typename T, int W, int RPS, int KIND, int NW>
+__global__ __launch_bounds__(64 * NW) void k_getrf(const LuProb* __restrict__ probs) {
   using V4 = typename Vec4<T>::type;
   constexpr int W2 = 2 * W;
+  constexpr int NT = 64 * NW;  // threads
+  static_assert(W % NW == 0, "inv(L11) gives each wave W / NW columns");
   const LuProb pr = probs[blockIdx.x];
   T* __restrict__ A = static_cast<T*>(pr.a);
   const int n = pr.n;
@@ -131,15 +134,15 @@ __global__ __launch_bounds__(256) void k_getrf(const LuProb* __restrict__ probs)
 
   extern __shared__ __align__(16) unsigned char smem[];
   int* Ps = reinterpret_cast<int*>(smem);  // logical row -> physical row, n entries
-  __shared__ T s_row[2][4][W];             // each wave's candidate pivot row
-  __shared__ key_t<T> s_bk[2][4];
-  __shared__ uint32_t s_bl[2][4];
+  __shared__ T s_row[2][NW][W];            // each wave's candidate pivot row
+  __shared__ key_t<T> s_bk[2][NW];
+  __shared__ uint32_t s_bl[2][NW];
   __shared__ T L11[W][W + 1];              // a panel's unit-lower block, then L21_ab
   __shared__ T Lsup[W2][W2 + 1];           // inverse of the 2W superpanel's unit-lower block
   __shared__ T Uc[W2][CH];                 // U12 chunk
   __shared__ int s_info;
 
-  for (int i = tid; i < n; i += 256) Ps[i] = i;
+  for (int i = tid; i < n; i += NT) Ps[i] = i;
   if (tid == 0) s_info = 0;
   __syncthreads();
 
@@ -153,7 +156,7 @@ __global__ __launch_bounds__(256) void k_getrf(const LuProb* __restrict__ probs)
     int lpos[RPS], ph[RPS];
 #pragma unroll
     for (int t = 0; t < RPS; ++t) {
-      const int r = tid + 256 * t;
+      const int r = tid + NT * t;
       lpos[t] = (r < mr) ? r : -1;
       ph[t] = (r < mr) ? Ps[j0 + r] : 0;
 #pragma unroll
@@ -198,7 +201,7 @@ __global__ __launch_bounds__(256) void k_getrf(const LuProb* __restrict__ probs)
       key_t<T> kv = s_bk[buf][0];
       uint32_t plu = s_bl[buf][0];
 #pragma unroll
-      for (int ww = 1; ww < 4; ++ww) {
+      for (int ww = 1; ww < NW; ++ww) {
         const key_t<T> k = s_bk[buf][ww];
         const uint32_t l = s_bl[buf][ww];
         if (k > kv || (k == kv && l < plu)) {
@@ -251,10 +254,10 @@ __global__ __launch_bounds__(256) void k_getrf(const LuProb* __restrict__ probs)
       }
     }
     __syncthreads();
-    // inv(L11) (unit lower): wave w solves identity columns w*W/4 .. +W/4,
+    // inv(L11) (unit lower): wave w solves identity columns w*W/NW .. +W/NW,
     // lane = row, the solved row value broadcast across lanes
     {
-      constexpr int CQ = W / 4;
+      constexpr int CQ = W / NW;
       T x[CQ];
 #pragma unroll
       for (int q = 0; q < CQ; ++q) x[q] = (lane == wave * CQ + q) ? T(1) : T(0);
@@ -283,7 +286,7 @@ __global__ __launch_bounds__(256) void k_getrf(const LuProb* __restrict__ probs)
     const int c0 = r0 + KW;
     const int ntr = (n - c0 + 15) / 16;
     for (int cb = cs; cb < ce; cb += CH) {
-      for (int it = wave; it < (KW / 16) * (CH / 16); it += 4) {
+      for (int it = wave; it < (KW / 16) * (CH / 16); it += NW) {
         const int rt = it % (KW / 16), ct = it / (KW / 16);
         const int cc = cb + 16 * ct + lr;
         V4 acc = V4{0, 0, 0, 0};
@@ -298,12 +301,12 @@ __global__ __launch_bounds__(256) void k_getrf(const LuProb* __restrict__ probs)
       }
       __syncthreads();
       // write U12 back (logical rows r0+1 .. r0+KW-1; row r0 is unchanged)
-      for (int idx = tid; idx < KW * CH; idx += 256) {
+      for (int idx = tid; idx < KW * CH; idx += NT) {
         const int i = idx / CH, cl = idx % CH;
         const int cc = cb + cl;
         if (i >= 1 && cc < ce) A[(int64_t)Ps[r0 + i] * n + cc] = Uc[i][cl];
       }
-      for (int it = wave; it < ntr; it += 4) {
+      for (int it = wave; it < ntr; it += NW) {
         const int t0 = c0 + 16 * it;
         const int row = t0 + lr;
         T a[KG];
@@ -364,13 +367,13 @@ __global__ __launch_bounds__(256) void k_getrf(const LuProb* __restrict__ probs)
     // X = -inv(L_b) L_ab inv(L_a), with L_ab = panel b's rows in panel a's
     // columns.
     const int J0 = j0 - W;
-    for (int idx = tid; idx < W * W; idx += 256) {
+    for (int idx = tid; idx < W * W; idx += NT) {
       const int i = idx / W, c = idx % W;
       L11[i][c] = A[(int64_t)Ps[J0 + W + i] * n + J0 + c];
       Lsup[i][W + c] = T(0);
     }
     __syncthreads();
-    for (int it = wave; it < (W / 16) * (W / 16); it += 4) {  // Uc = L_ab inv(L_a)
+    for (int it = wave; it < (W / 16) * (W / 16); it += NW) {  // Uc = L_ab inv(L_a)
       const int rt = it % (W / 16), ct = it / (W / 16);
       V4 acc = V4{0, 0, 0, 0};
 #pragma unroll
@@ -380,7 +383,7 @@ __global__ __launch_bounds__(256) void k_getrf(const LuProb* __restrict__ probs)
       for (int v = 0; v < 4; ++v) Uc[16 * rt + acc_row(T(0), lg, v)][16 * ct + lr] = acc[v];
     }
     __syncthreads();
-    for (int it = wave; it < (W / 16) * (W / 16); it += 4) {  // X = -inv(L_b) Uc
+    for (int it = wave; it < (W / 16) * (W / 16); it += NW) {  // X = -inv(L_b) Uc
       const int rt = it % (W / 16), ct = it / (W / 16);
       V4 acc = V4{0, 0, 0, 0};
 #pragma unroll
@@ -393,7 +396,7 @@ __global__ __launch_bounds__(256) void k_getrf(const LuProb* __restrict__ probs)
     update(std::integral_constant<int, W2>{}, J0, J0 + W2, n);
   }
 
-  for (int i = tid; i < n; i += 256) pr.perm[i] = Ps[i];
+  for (int i = tid; i < n; i += NT) pr.perm[i] = Ps[i];
   if (tid == 0) *pr.info = s_info;
 }
 
@@ -599,36 +602,49 @@ hipError_t run_getrf_w(const LuProb* probs, int count, int nmax, hipStream_t s) 
   return hipGetLastError();
 }
 
-template <typename T, int W, int RPS, int KIND>
+template <typename T, int W, int RPS, int KIND, int NW>
 hipError_t run_getrf(const LuProb* probs, int count, int nmax, hipStream_t s) {
   const size_t sm = (size_t)nmax * sizeof(int);
-  hipLaunchKernelGGL((k_getrf<T, W, RPS, KIND>), dim3(count), dim3(256), sm, s, probs);
+  hipLaunchKernelGGL((k_getrf<T, W, RPS, KIND, NW>), dim3(count), dim3(64 * NW), sm, s, probs);
   return hipGetLastError();
 }
 
-template <typename T, int W, int KIND>
+// RPS rows of the panel per thread: orders up to 64 NW RPS
+template <typename T, int W, int KIND, int NW>
 hipError_t run_block(const LuProb* probs, int count, int nmax, hipStream_t s) {
-  if (nmax <= 256) return run_getrf<T, W, 1, KIND>(probs, count, nmax, s);
-  if (nmax <= 512) return run_getrf<T, W, 2, KIND>(probs, count, nmax, s);
-  return run_getrf<T, W, 4, KIND>(probs, count, nmax, s);
+  constexpr int NT = 64 * NW;
+  if (nmax <= NT) return run_getrf<T, W, 1, KIND, NW>(probs, count, nmax, s);
+  if (nmax <= 2 * NT) return run_getrf<T, W, 2, KIND, NW>(probs, count, nmax, s);
+  if constexpr (NW == 4) {
+    if (nmax <= 4 * NT) return run_getrf<T, W, 4, KIND, NW>(probs, count, nmax, s);
+  }
+  return hipErrorInvalidValue;
 }
 
-// panel: 0 = the default width (32 in FP32, 16 in FP64), else 16 or 32 (leaf
-// blocks only; the reduced systems always take the default)
+// panel: 0 = the default width (32 in FP32, 16 in FP64), else 16 or 32;
+// waves: 0 or 4 = four waves per matrix, 8 = eight (leaf blocks only; the
+// reduced systems always take the defaults; FP64 has no panel 32 at eight
+// waves)
 template <typename T, int KIND>
-hipError_t pick(const LuProb* probs, int count, int nmax, int panel, hipStream_t s) {
+hipError_t pick(const LuProb* probs, int count, int nmax, int panel, int waves, hipStream_t s) {
   constexpr int W = sizeof(T) == 8 ? 16 : 32;
+  constexpr int WA = W == 16 ? 32 : 16;  // the other panel width
   // one wave per matrix for small FP32 orders; FP64's longer per-column chain
-  // (64-bit keys and reciprocal) is better spread over four waves
+  // (64-bit keys and reciprocal) is better spread over several waves
   if constexpr (sizeof(T) == 4) {
     if (nmax <= 64) return run_getrf_w<T, W, 1, KIND>(probs, count, nmax, s);
     if (nmax <= 128) return run_getrf_w<T, W, 2, KIND>(probs, count, nmax, s);
     if (nmax <= 192) return run_getrf_w<T, W, 3, KIND>(probs, count, nmax, s);
   }
-  if (panel == 0 || panel == W) return run_block<T, W, KIND>(probs, count, nmax, s);
+  const bool alt = panel != 0 && panel != W;
+  if (alt && panel != WA) return hipErrorInvalidValue;
+  if (waves != 0 && waves != 4 && waves != 8) return hipErrorInvalidValue;
+  if (!alt && waves != 8) return run_block<T, W, KIND, 4>(probs, count, nmax, s);
   if constexpr (KIND == 0) {
-    if (panel == 16 || panel == 32)
-      return run_block<T, (W == 16 ? 32 : 16), KIND>(probs, count, nmax, s);
+    if (!alt) return run_block<T, W, KIND, 8>(probs, count, nmax, s);
+    if (waves != 8) return run_block<T, WA, KIND, 4>(probs, count, nmax, s);
+    // FP64 with panel 32 at eight waves would spill registers: not built
+    if constexpr (sizeof(T) == 4) return run_block<T, WA, KIND, 8>(probs, count, nmax, s);
   }
   return hipErrorInvalidValue;
 }
@@ -638,14 +654,14 @@ hipError_t pick(const LuProb* probs, int count, int nmax, int panel, hipStream_t
 int getrf_default_panel(bool t64) { return t64 ? 16 : 32; }
 
 template <typename T>
-hipError_t launch_getrf(const LuProb* probs, int count, int nmax, int kind, int panel,
+hipError_t launch_getrf(const LuProb* probs, int count, int nmax, int kind, int panel, int waves,
                         hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  return kind == 0 ? pick<T, 0>(probs, count, nmax, panel, s)
-                   : pick<T, 1>(probs, count, nmax, panel, s);
+  return kind == 0 ? pick<T, 0>(probs, count, nmax, panel, waves, s)
+                   : pick<T, 1>(probs, count, nmax, panel, waves, s);
 }
 
-template hipError_t launch_getrf<double>(const LuProb*, int, int, int, int, hipStream_t);
-template hipError_t launch_getrf<float>(const LuProb*, int, int, int, int, hipStream_t);
+template hipError_t launch_getrf<double>(const LuProb*, int, int, int, int, int, hipStream_t);
+template hipError_t launch_getrf<float>(const LuProb*, int, int, int, int, int, hipStream_t);
 
 }  // namespace invaskit

@@ -143,6 +143,7 @@ def test_bad_options_rejected(small_problem):
     assert st == -1
     binding.library().invaskit_default_options(C.byref(opt))
     assert opt.tune == binding.TUNE_AUTO and opt.leaf_lu_panel == 0 and opt.leaf_trsm_cols == 0
+    assert opt.leaf_lu_waves == 0
     opt.tune = 7
     st, msg = _factor_status(raw, opt=opt)
     assert st == -1 and "tune" in msg
@@ -151,6 +152,11 @@ def test_bad_options_rejected(small_problem):
         setattr(opt, field, v)
         st, msg = _factor_status(raw, opt=opt)
         assert st == -1 and "leaf_lu_panel and leaf_trsm_cols" in msg, (field, v)
+    for v in (2, 16, -4):
+        binding.library().invaskit_default_options(C.byref(opt))
+        opt.leaf_lu_waves = v
+        st, msg = _factor_status(raw, opt=opt)
+        assert st == -1 and "leaf_lu_waves" in msg, v
 
 
 def test_options_struct_layout():
@@ -161,9 +167,9 @@ def test_options_struct_layout():
     assert C.sizeof(O) == 40
     assert O.refine_tol.offset == 8 and O.max_refine_iters.offset == 16
     assert O.tune.offset == 20 and O.leaf_lu_panel.offset == 24
-    assert O.leaf_trsm_cols.offset == 28 and O.reserved0.offset == 32
+    assert O.leaf_trsm_cols.offset == 28 and O.leaf_lu_waves.offset == 32
     T = binding._TileConfig
-    assert C.sizeof(T) == 32 and T.lu_ms.offset == 16 and T.trsm_ms.offset == 24
+    assert C.sizeof(T) == 40 and T.lu_ms.offset == 16 and T.trsm_ms.offset == 32
 
 
 def test_tuning_table_text_round_trip():
@@ -172,12 +178,13 @@ def test_tuning_table_text_round_trip():
     from paper_1602_01376_amd import binding
     binding.tuning_clear()
     assert binding.tuning_table() == {}
-    entries = {"getrf.f32.n512.c24.w67": 16, "getrs.f64.k0.n256.w60": 32}
+    entries = {"getrf.f32.n512.c24.w67": 16, "getrfw.f32.n512.c24.w67": 8,
+               "getrs.f64.k0.n256.w60": 32}
     binding.tuning_load(entries)
     assert binding.tuning_table() == entries
     lib = binding.library()
     for bad in (b"getrf.f32.n1 24\n", b"getrs.f32 16 extra\n", b"other.key 16\n",
-                b"getrf.f32.n1\n"):
+                b"getrf.f32.n1\n", b"getrfw.f32.n1 16\n", b"getrf.f32.n1 8\n"):
         assert lib.invaskit_tuning_import(bad) == -1, bad
     assert binding.tuning_table() == entries
     need = C.c_size_t()

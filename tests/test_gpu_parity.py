@@ -273,17 +273,24 @@ def test_lambda_sweep(bind, problems, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-@pytest.mark.parametrize("lu,tr", [(16, 16), (32, 32), (16, 32), (32, 16)])
-def test_fixed_tiles_match_oracle(bind, problems, prec, lu, tr):
-    """Every leaf LU panel width and leaf-solve column count the tuner can
-    choose gives the oracle's solution (uneven leaves 64..512)."""
-    _say("fixed tiles", prec, lu, tr)
+@pytest.mark.parametrize("lu,lw,tr", [(16, 4, 16), (32, 4, 32), (16, 8, 32), (32, 8, 16)])
+def test_fixed_tiles_match_oracle(bind, problems, prec, lu, lw, tr):
+    """Every leaf LU panel width and wave count and leaf-solve column count
+    the tuner can choose gives the oracle's solution (uneven leaves 64..512)."""
+    _say("fixed tiles", prec, lu, lw, tr)
     pb, F = problems("susy", dict(n=8192, depth=5))
     b = rhs_for(pb, nrhs=2)
     x_ref = oracle.solve(F, b)
-    fac = bind.Factorization(pb, pb.lam, precision=prec, leaf_lu_panel=lu, leaf_trsm_cols=tr)
+    if prec == "fp64" and (lu, lw) == (32, 8):  # not built: it would spill registers
+        with pytest.raises(bind.InvaskitError) as ei:
+            bind.Factorization(pb, pb.lam, precision=prec, leaf_lu_panel=lu, leaf_lu_waves=lw)
+        assert ei.value.status == bind.E_ARG
+        return
+    fac = bind.Factorization(pb, pb.lam, precision=prec, leaf_lu_panel=lu, leaf_trsm_cols=tr,
+                             leaf_lu_waves=lw)
     tc = fac.tile_config()
-    assert (tc["leaf_lu_panel"], tc["leaf_trsm_cols"], tc["tuned"]) == (lu, tr, 0)
+    assert (tc["leaf_lu_panel"], tc["leaf_lu_waves"], tc["leaf_trsm_cols"], tc["tuned"]) == \
+        (lu, lw, tr, 0)
     x, info, st = fac.solve(torch.from_numpy(b), return_info=True)
     assert st == 0 and info["final_rel_residual"] <= 1e-10
     rel = _rel(x.cpu().numpy(), x_ref)
@@ -295,7 +302,8 @@ def test_fixed_tiles_match_oracle(bind, problems, prec, lu, tr):
 def test_wide_leaf_solves_at_largest_leaf(bind, problems):
     """Leaves of 1024: 32 right-hand sides per workgroup fit in LDS in FP32
     (and match the oracle) but not in FP64, where asking for them is an
-    argument error and the tuner keeps 16."""
+    argument error and the tuner keeps 16; the eight-wave LU at this order
+    matches the oracle in both precisions."""
     _say("wide leaf solves, leaves of 1024")
     pb, F = problems("tiny", dict(n=2048, depth=1))
     b = rhs_for(pb, nrhs=2)
@@ -311,6 +319,13 @@ def test_wide_leaf_solves_at_largest_leaf(bind, problems):
     fac = bind.Factorization(pb, pb.lam, precision="fp64")
     assert fac.tile_config()["leaf_trsm_cols"] == 16
     fac.close()
+    # eight waves per matrix: two panel rows per thread at order 1024
+    for prec in ("fp64", "mixed"):
+        fac = bind.Factorization(pb, pb.lam, precision=prec, leaf_lu_waves=8)
+        x, info, st = fac.solve(torch.from_numpy(b), return_info=True)
+        assert st == 0 and info["final_rel_residual"] <= 1e-10
+        assert _rel(x.cpu().numpy(), x_ref) <= (1e-10 if prec == "fp64" else 1e-7)
+        fac.close()
 
 
 def test_autotune_times_candidates_once(bind, problems):
@@ -325,15 +340,18 @@ def test_autotune_times_candidates_once(bind, problems):
     tc = fac.tile_config()
     _say("  tile config", tc)
     assert tc["tuned"] == 1 and min(tc["lu_ms"] + tc["trsm_ms"]) > 0
-    assert tc["leaf_lu_panel"] == (32 if tc["lu_ms"][1] < tc["lu_ms"][0] else 16)
+    best = int(np.argmin(tc["lu_ms"]))
+    assert (tc["leaf_lu_panel"], tc["leaf_lu_waves"]) == ((16, 4), (32, 4), (16, 8), (32, 8))[best]
     assert tc["leaf_trsm_cols"] == (32 if tc["trsm_ms"][1] < tc["trsm_ms"][0] else 16)
     table = bind.tuning_table()
-    assert sorted(table.values()) == sorted([tc["leaf_lu_panel"], tc["leaf_trsm_cols"]])
+    assert sorted(table.values()) == sorted([tc["leaf_lu_panel"], tc["leaf_lu_waves"],
+                                             tc["leaf_trsm_cols"]])
     x = fac.solve(torch.from_numpy(b)).cpu().numpy()
     assert _rel(x, oracle.solve(F, b)) <= 1e-7
     fac.refactor(3e-3)
     tc2 = fac.tile_config()
     assert tc2["tuned"] == 0 and tc2["leaf_lu_panel"] == tc["leaf_lu_panel"]
+    assert tc2["leaf_lu_waves"] == tc["leaf_lu_waves"]
     assert tc2["leaf_trsm_cols"] == tc["leaf_trsm_cols"]
     fac.close()
     fac = bind.Factorization(pb, pb.lam, precision="mixed")
@@ -341,7 +359,8 @@ def test_autotune_times_candidates_once(bind, problems):
     fac.close()
     fac = bind.Factorization(pb, pb.lam, precision="mixed", tune="off")
     tc3 = fac.tile_config()
-    assert (tc3["leaf_lu_panel"], tc3["leaf_trsm_cols"], tc3["tuned"]) == (32, 16, 0)
+    assert (tc3["leaf_lu_panel"], tc3["leaf_lu_waves"], tc3["leaf_trsm_cols"], tc3["tuned"]) == \
+        (32, 4, 16, 0)
     fac.close()
     bind.tuning_clear()
 
