@@ -58,18 +58,18 @@ CSRC = os.path.join(ROOT, "paper_1602_01376_amd", "csrc")
 COPY_KERNEL = "k_copy_cols<double, double>"
 # phases whose time is one launch of a uniquely named kernel: name pattern
 # (t = element type) and the source file that holds it
-# the phase's kernel; {p} is its tile parameter (LU panel width, or 16-column
-# tiles per workgroup of the solves)
+# the phase's kernel; {p} and {w} are its tile parameters (LU panel width and
+# waves per matrix, or 16-column tiles per workgroup of the solves)
 PHASE_KERNEL = {
-    "leaf_lu": (r"k_getrf<{t}, {p}, \d+, 0>", "kernels_lu.hip"),
+    "leaf_lu": (r"k_getrf<{t}, {p}, \d+, 0, {w}>", "kernels_lu.hip"),
     "leaf_solves": (r"k_getrs<{t}, {t}, 0, {p}>", "kernels_trsm.hip"),
 }
 
 
-def phase_tile_param(phase, tiles):
+def phase_tile_params(phase, tiles):
     if phase == "leaf_lu":
-        return str(tiles["leaf_lu_panel"])
-    return str(tiles["leaf_trsm_cols"] // 16)
+        return dict(p=str(tiles["leaf_lu_panel"]), w=str(tiles["leaf_lu_waves"]))
+    return dict(p=str(tiles["leaf_trsm_cols"] // 16), w="")
 
 
 def source_digest(src):
@@ -112,7 +112,7 @@ def write_traffic(fetch_csv, write_csv, copy_bytes, command):
     entries = {}
     for phase, (pat, src) in PHASE_KERNEL.items():
         for t in ("float", "double"):
-            rx = re.compile(pat.format(t=t, p=r"\d+") + "$")
+            rx = re.compile(pat.format(t=t, p=r"\d+", w=r"\d+") + "$")
             names = [k for k in fetch if rx.match(k)]
             for k in names:
                 fk, wk = float(np.mean(fetch[k])), float(np.mean(write.get(k, [0.0])))
@@ -138,7 +138,7 @@ def traffic_for(phase, t, tiles):
     if phase not in PHASE_KERNEL or not os.path.exists(TRAFFIC_FILE):
         return None
     pat, src = PHASE_KERNEL[phase]
-    rx = re.compile(pat.format(t=t, p=phase_tile_param(phase, tiles)) + "$")
+    rx = re.compile(pat.format(t=t, **phase_tile_params(phase, tiles)) + "$")
     with open(TRAFFIC_FILE) as fh:
         data = json.load(fh)
     digest = source_digest(src)
