@@ -36,6 +36,19 @@ namespace {
 constexpr int ET = kEvalTile;  // 64
 constexpr int DC = 8;          // coordinates per LDS chunk
 
+// exp(a) for a kernel value stored as T (a = -|x-y|^2 / (2h^2) <= 0, from
+// FP64 distances): FP64 exp for FP64 blocks; for FP32 blocks the FP32 exp of
+// the rounded argument, whose absolute error, at most about u32 max(a e^a)
+// = u32 / e, is below the FP32 rounding of values near 1/e, at a fraction
+// of the cost of the FP64 exp
+template <typename T>
+__device__ __forceinline__ double kernel_value(double a) {
+  if constexpr (sizeof(T) == 4)
+    return (double)expf((float)a);
+  else
+    return exp(a);
+}
+
 template <typename PT, typename T>
 __global__ __launch_bounds__(256) void k_eval(const PT* __restrict__ X, int d, double nhalf_inv_h2,
                                               double shift, const EvalBlock* __restrict__ blocks,
@@ -100,7 +113,7 @@ __global__ __launch_bounds__(256) void k_eval(const PT* __restrict__ X, int d, d
     for (int i = 0; i < 4; ++i) {
       const int r = r0 + tr + 16 * i;
       if (r >= b.rows) continue;
-      double v = exp(acc[i][j] * nhalf_inv_h2);
+      double v = kernel_value<T>(acc[i][j] * nhalf_inv_h2);
       if (b.diag && r == c) v += shift;
       out[(int64_t)c * b.ld + r] = (T)v;
     }
@@ -232,7 +245,7 @@ __global__ __launch_bounds__(256) void k_eval_gram(const PT* __restrict__ X, int
         if (r < b.rows && c < b.ncols) {
           double r2 = fmax(nr[rl] + nc[cl] - 2.0 * acc[ci][ri][v], 0.0);
           if (rowi[rl] == coli[cl]) r2 = 0.0;
-          double val = exp(r2 * nhalf_inv_h2);
+          double val = kernel_value<T>(r2 * nhalf_inv_h2);
           if (b.diag && r == c) val += shift;
           out[(int64_t)c * b.ld + r] = (T)val;
         }

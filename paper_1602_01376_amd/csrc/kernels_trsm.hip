@@ -46,8 +46,9 @@ __global__ __launch_bounds__(256) void k_diag_inv(const DiagInvProb* __restrict_
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   __shared__ TZ B[NBK][NBK + 1];  // B[c][r] = block entry (row r, column c)
   __shared__ TZ rdiag[NBK];
+  // consecutive threads read consecutive columns of a factor row
   for (int idx = tid; idx < NBK * NBK; idx += 256) {
-    const int r = idx % NBK, c = idx / NBK;
+    const int c = idx % NBK, r = idx / NBK;
     B[c][r] = (r < nb && c < nb) ? LU[(int64_t)p.perm[jb + r] * n + jb + c] : TZ(0);
   }
   __syncthreads();
@@ -55,36 +56,38 @@ __global__ __launch_bounds__(256) void k_diag_inv(const DiagInvProb* __restrict_
   __syncthreads();
   constexpr int CQ = NBK / 4;  // identity columns per wave
   // inv(L): L X = I, L unit lower
-  {
-    TZ x[CQ];
+  TZ xl[CQ];
 #pragma unroll
-    for (int q = 0; q < CQ; ++q) x[q] = (lane == wave * CQ + q && lane < nb) ? TZ(1) : TZ(0);
-    for (int j = 0; j < nb - 1; ++j) {
-      const TZ l = (lane > j) ? B[j][lane] : TZ(0);
+  for (int q = 0; q < CQ; ++q) xl[q] = (lane == wave * CQ + q && lane < nb) ? TZ(1) : TZ(0);
+  for (int j = 0; j < nb - 1; ++j) {
+    const TZ l = (lane > j) ? B[j][lane] : TZ(0);
 #pragma unroll
-      for (int q = 0; q < CQ; ++q) x[q] -= l * lane_bcast(x[q], j);
-    }
-#pragma unroll
-    for (int q = 0; q < CQ; ++q) out[lane * NBK + wave * CQ + q] = (lane < nb) ? x[q] : TZ(0);
+    for (int q = 0; q < CQ; ++q) xl[q] -= l * lane_bcast(xl[q], j);
   }
   // inv(U): U X = I, U upper
-  {
-    TZ x[CQ];
+  TZ xu[CQ];
 #pragma unroll
-    for (int q = 0; q < CQ; ++q) x[q] = (lane == wave * CQ + q && lane < nb) ? TZ(1) : TZ(0);
-    for (int j = nb - 1; j >= 0; --j) {
-      const TZ u = (lane < j) ? B[j][lane] : TZ(0);
-      const TZ rd = rdiag[j];
+  for (int q = 0; q < CQ; ++q) xu[q] = (lane == wave * CQ + q && lane < nb) ? TZ(1) : TZ(0);
+  for (int j = nb - 1; j >= 0; --j) {
+    const TZ u = (lane < j) ? B[j][lane] : TZ(0);
+    const TZ rd = rdiag[j];
 #pragma unroll
-      for (int q = 0; q < CQ; ++q) {
-        if (lane == j) x[q] *= rd;
-        x[q] -= u * lane_bcast(x[q], j);
-      }
+    for (int q = 0; q < CQ; ++q) {
+      if (lane == j) xu[q] *= rd;
+      xu[q] -= u * lane_bcast(xu[q], j);
     }
-#pragma unroll
-    for (int q = 0; q < CQ; ++q)
-      out[NBK * NBK + lane * NBK + wave * CQ + q] = (lane < nb) ? x[q] : TZ(0);
   }
+  // both inverses leave through B (no longer read), row-major, so that the
+  // stores coalesce
+  auto store = [&](const TZ (&x)[CQ], TZ* dst) {
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < CQ; ++q) B[lane][wave * CQ + q] = (lane < nb) ? x[q] : TZ(0);
+    __syncthreads();
+    for (int idx = tid; idx < NBK * NBK; idx += 256) dst[idx] = B[idx / NBK][idx % NBK];
+  };
+  store(xl, out);
+  store(xu, out + NBK * NBK);
 }
 
 // ------------------------------------------------------------------- solves
