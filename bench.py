@@ -308,6 +308,10 @@ def main():
                     help="instead of the headline step: time a mixed-precision factorization "
                          "of G lambdas (logspace(-6, -1, G)) as one sweep sharing the kernel "
                          "blocks, against G independent factorizations")
+    ap.add_argument("--sweep-group", type=int, default=0, metavar="S",
+                    help="with --sweep: factor the lambdas in sweeps of S handles at a time "
+                         "(each group shares its kernel blocks; for workloads whose handles "
+                         "do not all fit in HBM together)")
     args = ap.parse_args()
     headline = args.workload == "susy"
     if args.nrhs is None:
@@ -331,7 +335,8 @@ def main():
 
     torch.cuda.set_device(0)
     t0 = time.perf_counter()
-    pb = make_problem(args.workload, n=args.n, depth=args.depth)
+    pb = make_problem(args.workload, n=args.n, depth=args.depth,
+                      progress=lambda text: log(f"setup: {text}"))
     sizes = np.diff(pb.leaf_offsets)
     ranks = np.diff(pb.skel_offsets)[1:]
     leaf_min, leaf_max = int(sizes.min()), int(sizes.max())
@@ -345,29 +350,52 @@ def main():
 
     if args.sweep > 0:
         lams = list(np.logspace(-6, -1, args.sweep))
+        group = args.sweep_group or len(lams)
         fac = binding.Factorization(pb, lams[0], precision="mixed", points=X, p_values=P)
-        fac.close()  # warm-up (kernel loads, allocator)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        facs = binding.factor_sweep(pb, lams, precision="mixed", points=X, p_values=P)
-        torch.cuda.synchronize()
-        t_sweep = time.perf_counter() - t0
-        res = [f.solve(b, return_info=True, check=False)[1]["final_rel_residual"] for f in facs]
-        for f in facs:
-            f.close()
-        del facs
+        log(f"sweep warm-up: {fac.device_bytes() / 2**30:.1f} GiB per handle, "
+            f"tiles {fac.tile_config()}")
+        fac.close()  # warm-up (kernel loads, tile tuning, allocator)
+        del fac
         torch.cuda.empty_cache()
+        torch.cuda.synchronize()
+        t_sweep, t_solve, res, iters = 0.0, 0.0, [], []
+        for g0 in range(0, len(lams), group):
+            part = lams[g0:g0 + group]
+            t0 = time.perf_counter()
+            facs = binding.factor_sweep(pb, part, precision="mixed", points=X, p_values=P)
+            torch.cuda.synchronize()
+            t_sweep += time.perf_counter() - t0
+            for f in facs:
+                t0 = time.perf_counter()
+                _, info, _ = f.solve(b, return_info=True, check=False)
+                torch.cuda.synchronize()
+                t_solve += time.perf_counter() - t0
+                res.append(info["final_rel_residual"])
+                iters.append(info["iterations"])
+            log(f"sweep of {len(part)} lambdas from {part[0]:.1e} factored and solved "
+                f"(residuals {res[-len(part):]})")
+            for f in facs:
+                f.close()
+            del facs
+            torch.cuda.empty_cache()
         t0 = time.perf_counter()
         for lam in lams:
             f = binding.Factorization(pb, lam, precision="mixed", points=X, p_values=P)
             f.close()
+            del f
+            torch.cuda.empty_cache()
         torch.cuda.synchronize()
         t_sep = time.perf_counter() - t0
+        log("independent factorizations done")
         print(json.dumps({"metric": "lambda-sweep factorization seconds", "lambdas": lams,
+                          "workload": args.workload, "sweep_group": group,
                           "sweep_s": t_sweep, "separate_s": t_sep,
                           "per_lambda_sweep_ms": 1e3 * t_sweep / len(lams),
                           "per_lambda_separate_ms": 1e3 * t_sep / len(lams),
-                          "max_refined_residual": max(res), "n": pb.n, "precision": "mixed",
+                          "per_lambda_solve_ms": 1e3 * t_solve / len(lams), "nrhs": args.nrhs,
+                          "refinement_iterations": iters,
+                          "max_refined_residual": max(res), "n": pb.n, "d": pb.d,
+                          "precision": "mixed",
                           "note": "host-side allocation of each handle's factor storage is "
                                   "inside both timings"}), flush=True)
         return

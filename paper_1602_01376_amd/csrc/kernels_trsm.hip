@@ -55,26 +55,25 @@ __global__ __launch_bounds__(256) void k_diag_inv(const DiagInvProb* __restrict_
   if (tid < NBK) rdiag[tid] = (tid < nb) ? TZ(1) / B[tid][tid] : TZ(0);
   __syncthreads();
   constexpr int CQ = NBK / 4;  // identity columns per wave
-  // inv(L): L X = I, L unit lower
-  TZ xl[CQ];
+  // inv(L) (L X = I, L unit lower, forward) and inv(U) (U X = I, backward)
+  // in one loop: the two substitution chains are independent, so each step
+  // carries both and their latencies overlap
+  TZ xl[CQ], xu[CQ];
 #pragma unroll
-  for (int q = 0; q < CQ; ++q) xl[q] = (lane == wave * CQ + q && lane < nb) ? TZ(1) : TZ(0);
-  for (int j = 0; j < nb - 1; ++j) {
-    const TZ l = (lane > j) ? B[j][lane] : TZ(0);
-#pragma unroll
-    for (int q = 0; q < CQ; ++q) xl[q] -= l * lane_bcast(xl[q], j);
+  for (int q = 0; q < CQ; ++q) {
+    xl[q] = (lane == wave * CQ + q && lane < nb) ? TZ(1) : TZ(0);
+    xu[q] = xl[q];
   }
-  // inv(U): U X = I, U upper
-  TZ xu[CQ];
-#pragma unroll
-  for (int q = 0; q < CQ; ++q) xu[q] = (lane == wave * CQ + q && lane < nb) ? TZ(1) : TZ(0);
-  for (int j = nb - 1; j >= 0; --j) {
-    const TZ u = (lane < j) ? B[j][lane] : TZ(0);
-    const TZ rd = rdiag[j];
+  for (int i = 0; i < nb; ++i) {
+    const int jl = i, ju = nb - 1 - i;  // forward and backward pivots
+    const TZ l = (lane > jl) ? B[jl][lane] : TZ(0);
+    const TZ u = (lane < ju) ? B[ju][lane] : TZ(0);
+    const TZ rd = rdiag[ju];
 #pragma unroll
     for (int q = 0; q < CQ; ++q) {
-      if (lane == j) xu[q] *= rd;
-      xu[q] -= u * lane_bcast(xu[q], j);
+      if (lane == ju) xu[q] *= rd;
+      xl[q] -= l * lane_bcast(xl[q], jl);
+      xu[q] -= u * lane_bcast(xu[q], ju);
     }
   }
   // both inverses leave through B (no longer read), row-major, so that the

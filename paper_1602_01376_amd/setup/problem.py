@@ -101,13 +101,13 @@ WORKLOADS = {
 
 def make_problem(workload: str = "tiny", *, n: int | None = None, depth: int | None = None,
                  full_skeletons: bool = False, s_fixed: int | None = None,
-                 h: float | None = None, workers=None, **overrides) -> Problem:
+                 h: float | None = None, workers=None, progress=None, **overrides) -> Problem:
     """Generate a seeded problem.
 
     `n`/`depth` scale a workload down while keeping its structure (leaf size
     bounds, rank rule, value distribution).  `full_skeletons=True` makes
     every node's skeleton its full candidate set (P a permutation), which
-    turns K~ into K exactly.
+    turns K~ into K exactly.  `progress(text)`, if given, reports each step.
     """
     cfg = dict(WORKLOADS[workload])
     cfg.update(overrides)
@@ -130,13 +130,15 @@ def make_problem(workload: str = "tiny", *, n: int | None = None, depth: int | N
         X, L, split=cfg["split"], leaf_min=cfg.get("leaf_min", 0),
         leaf_max=cfg.get("leaf_max", 0), seed=2000 + i)
     X = np.ascontiguousarray(X[perm])
+    if progress is not None:
+        progress(f"points and ball tree done (N={N}, d={d}, depth {L})")
     if "s_fixed" in cfg and cfg["s_fixed"] is not None:
         rank = dict(s_fixed=cfg["s_fixed"])
     else:
         rank = dict(s_min=cfg["s_min"], s_max=cfg["s_max"], tau=cfg["tau"])
     so, si, po, pv = skeleton.skeletonize(
         X, L, leaf_offsets, cfg["h"], n_samp=cfg["n_samp"], seed=2000 + i,
-        full=full_skeletons, workers=workers, **rank)
+        full=full_skeletons, workers=workers, progress=progress, **rank)
     return Problem(X=X, perm=perm, depth=L, leaf_offsets=leaf_offsets,
                    skel_offsets=so, skel_index=si, p_offsets=po, p_values=pv,
                    h=float(cfg["h"]), name=workload, lam=float(cfg["lam"]),

@@ -82,8 +82,10 @@ def _node_skeleton(node, cand, lo, hi, X, h, n_samp, rank_rule, seed, full):
 
 
 def skeletonize(X, depth, leaf_offsets, h, *, s_fixed=None, s_min=1, s_max=None,
-                tau=None, n_samp=256, seed=0, full=False, workers=None):
+                tau=None, n_samp=256, seed=0, full=False, workers=None, progress=None):
     """Build skeletons and P for every non-root node, bottom-up.
+
+    `progress(text)`, if given, is called after each level.
 
     Returns (skel_offsets, skel_index, p_offsets, p_values) in heap node
     order (root = 0, children of i are 2i+1 and 2i+2).  The root has no
@@ -139,6 +141,8 @@ def skeletonize(X, depth, leaf_offsets, h, *, s_fixed=None, s_min=1, s_max=None,
         for j, (sk, P) in enumerate(run_level(jobs)):
             skel[first + j] = sk
             pmat[first + j] = P
+        if progress is not None:
+            progress(f"skeletons of level {k} done ({1 << k} nodes)")
 
     skel[0] = np.zeros(0, dtype=np.int64)
     pmat[0] = np.zeros((0, 0))
