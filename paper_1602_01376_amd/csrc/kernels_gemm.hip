@@ -4,8 +4,9 @@
 // of different shapes (the level-synchronous GEMMs of the SMW updates,
 // eq. (11), and the interpolation products of eq. (12) and
 // the Skeletonize pass).  A product may have several K segments whose B
-// operands live at unrelated addresses: that is how the deferred correction
-// gathers the per-level y blocks of a leaf's ancestors without copying them.
+// operands live at unrelated addresses: that is how the solve's final
+// product x = v - W~ e gathers the e blocks of a leaf's ancestors, and its
+// W~ blocks of every level, without copying them.
 //
 // Tiles: 128 rows (four waves of 32 rows, each 2 x c MFMA 16x16x4 blocks,
 // f64 or f32 accumulate) by 16 c columns, c <= 5 chosen per tile from the
