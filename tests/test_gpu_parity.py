@@ -328,7 +328,7 @@ def test_wide_leaf_solves_at_largest_leaf(bind, problems):
         fac.close()
 
 
-def test_autotune_times_candidates_once(bind, problems):
+def test_autotune_times_candidates_once(bind, problems, tmp_path):
     """AUTO: the first factor of a shape class times both candidates of each
     launch and keeps the faster; later factors (new handles, refactor) reuse
     the table; OFF takes the defaults; the result matches the oracle."""
@@ -357,6 +357,11 @@ def test_autotune_times_candidates_once(bind, problems):
     fac = bind.Factorization(pb, pb.lam, precision="mixed")
     assert fac.tile_config()["tuned"] == 0
     fac.close()
+    # the table survives a save / clear / load round trip through JSON
+    path = str(tmp_path / "tuning.json")
+    bind.save_tuning(path)
+    bind.tuning_clear()
+    assert bind.load_tuning(path) == len(table) and bind.tuning_table() == table
     fac = bind.Factorization(pb, pb.lam, precision="mixed", tune="off")
     tc3 = fac.tile_config()
     assert (tc3["leaf_lu_panel"], tc3["leaf_lu_waves"], tc3["leaf_trsm_cols"], tc3["tuned"]) == \
