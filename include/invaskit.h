@@ -211,9 +211,11 @@ int invaskit_refactor(invaskit_handle handle, double lambda);
  * iterative refinement: FP32 solves against the FP32 factors, residuals
  * b - (lambda*I + K~) x by the FP64 hierarchical product (invaskit_matvec),
  * FP64 updates, until every column satisfies refine_tol; E_NOT_CONVERGED if
- * the cap is hit or the residual stops shrinking (x then holds the best
- * iterate).  In FP64 mode the solve is direct and info->final_rel_residual
- * is computed with the same FP64 product.  info may be NULL.
+ * the cap is hit or the residual stops halving over three iterations (x
+ * then holds the iterate with the smallest residual, worst column, and
+ * info->final_rel_residual that residual).  In FP64 mode the solve is
+ * direct and info->final_rel_residual is computed with the same FP64
+ * product.  info may be NULL.
  */
 int invaskit_solve(invaskit_handle handle, const double* b, int64_t nrhs, int64_t ldb,
                    double* x, int64_t ldx, invaskit_solve_info* info);

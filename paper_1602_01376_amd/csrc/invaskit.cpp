@@ -1563,7 +1563,7 @@ int do_solve(H* h, const double* b, int64_t r64v, int64_t ldb, double* x, int64_
   HIP_TRY(h, launch_fill_zero(x64, sizeof(double) * h->N * r, s));
   HIP_TRY(h, launch_copy_cols<double, double>(b, ldb, r64, h->N, h->N, r, nullptr, false, s));
   rn = bn;
-  double best = INFINITY, hist[3] = {INFINITY, INFINITY, INFINITY};
+  double best = INFINITY, last = NAN, hist[3] = {INFINITY, INFINITY, INFINITY};
   int it = 0;
   bool conv = false;
   for (it = 1; it <= h->maxit; ++it) {
@@ -1578,8 +1578,14 @@ int do_solve(H* h, const double* b, int64_t r64v, int64_t ldb, double* x, int64_
     for (int c = 0; c < r; ++c)
       worst = std::max(worst, bn[c] > 0 ? std::sqrt(rn[c] / bn[c]) : std::sqrt(rn[c]));
     if (it == 1) loc.unrefined_rel_residual = worst;
-    loc.final_rel_residual = worst;
-    best = std::min(best, worst);
+    last = worst;
+    // the caller's x keeps the best iterate so far (the one returned if the
+    // refinement stops short; on convergence the last iterate is the best)
+    if (worst < best) {
+      best = worst;
+      loc.final_rel_residual = worst;
+      HIP_TRY(h, launch_copy_cols<double, double>(x64, h->N, x, ldx, h->N, r, nullptr, false, s));
+    }
     if (worst <= h->tol) {
       conv = true;
       break;
@@ -1593,7 +1599,10 @@ int do_solve(H* h, const double* b, int64_t r64v, int64_t ldb, double* x, int64_
   }
   loc.iterations = std::min(it, h->maxit);
   loc.converged = conv ? 1 : 0;
-  HIP_TRY(h, launch_copy_cols<double, double>(x64, h->N, x, ldx, h->N, r, nullptr, false, s));
+  if (!(best < INFINITY)) {  // no finite iterate: return the last one
+    loc.final_rel_residual = last;
+    HIP_TRY(h, launch_copy_cols<double, double>(x64, h->N, x, ldx, h->N, r, nullptr, false, s));
+  }
   HIP_TRY(h, hipStreamSynchronize(s));
   if (info) *info = loc;
   if (!conv)

@@ -397,6 +397,39 @@ def test_lambda_sweep_eight_lambdas_32_rhs(bind):
     assert done == 8
 
 
+def test_refinement_that_stops_short_returns_its_best_iterate(bind, problems):
+    """Refinement forced to stop from the host: an iteration cap below what
+    the tolerance needs, and a tolerance below FP64 rounding (the stall
+    rule ends it).  Both report E_NOT_CONVERGED, return the iterate with the
+    smallest residual and report that residual, which the oracle's product
+    confirms."""
+    _say("refinement stopping short")
+    pb, F = problems("susy", dict(n=8192, depth=5))
+    b = rhs_for(pb, nrhs=2)
+    x_ref = oracle.solve(F, b)
+    for kw, iters in ((dict(max_refine_iters=1, refine_tol=1e-12), 1),
+                      (dict(refine_tol=1e-30), None)):
+        fac = bind.Factorization(pb, pb.lam, precision="mixed", **kw)
+        x, info, st = fac.solve(torch.from_numpy(b), return_info=True, check=False)
+        _say("  ", kw, info)
+        assert st == bind.E_NOT_CONVERGED and info["converged"] == 0
+        if iters is not None:
+            assert info["iterations"] == iters
+            assert info["final_rel_residual"] == info["unrefined_rel_residual"]
+        else:  # stalled at FP64 rounding, well before the cap of 30
+            assert 3 < info["iterations"] < 30 and info["final_rel_residual"] <= 1e-12
+        x = x.cpu().numpy()
+        # the reported residual is that of the worst column
+        r = b - oracle.matvec(pb, pb.lam, x)
+        res = float(np.max(np.linalg.norm(r, axis=0) / np.linalg.norm(b, axis=0)))
+        if iters == 1:  # well above rounding: the two products agree closely
+            assert abs(res - info["final_rel_residual"]) <= 1e-3 * info["final_rel_residual"]
+            assert _rel(x, x_ref) <= 1e-4
+        else:  # at rounding level both products only bound it
+            assert res <= 1e-12 and _rel(x, x_ref) <= 1e-9
+        fac.close()
+
+
 def test_singular_leaf_is_reported(bind):
     _say("singular leaf")
     pb = make_problem("tiny", n=256, depth=2)
