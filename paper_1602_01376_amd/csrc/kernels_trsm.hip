@@ -8,8 +8,8 @@
 //
 // k_diag_inv runs once per factorization: for every 64 x 64 diagonal block
 // of every factor it forms the inverses of the unit-lower block of L and of
-// the upper block of U (column by column against the identity, one wave per
-// 16 columns, the diagonal of U inverted once), stored row-major.
+// the upper block of U (one wave each, one column of the inverse per lane,
+// the diagonal of U inverted once), stored row-major.
 //
 // k_getrs: one workgroup (4 waves) takes 16 CT right-hand-side columns of
 // one system (CT = 1 or 2); the permuted right-hand sides live in LDS (row
@@ -36,57 +36,58 @@ namespace {
 constexpr int NBK = kDiagBlock;  // 64-row block
 
 // ------------------------------------------------------------ block inverses
+// Two waves per block, lane = column c of the inverse: wave 0 solves
+// L x = e_c (unit lower, forward), wave 1 U x = e_c (backward, the diagonal
+// of U inverted once).  Each lane keeps its whole column in registers and
+// substitutes column-oriented: once x_k is final, x_i -= F[i][k] x_k for the
+// rest, with F[.][k] read from LDS at one address for the whole wave (a
+// broadcast).  No value crosses lanes, so the 64 steps are a chain of
+// independent FMAs rather than of cross-lane broadcasts.
+constexpr int DIP = NBK + 4;  // LDS row stride: 16-byte aligned rows
+
 template <typename TZ>
-__global__ __launch_bounds__(256) void k_diag_inv(const DiagInvProb* __restrict__ probs) {
+__global__ __launch_bounds__(128, 2) void k_diag_inv(const DiagInvProb* __restrict__ probs) {
   const DiagInvProb p = probs[blockIdx.x];
   const TZ* __restrict__ LU = static_cast<const TZ*>(p.lu);
   TZ* __restrict__ out = static_cast<TZ*>(p.out);  // inv(L_bb) then inv(U_bb), 64 x 64 each
   const int n = p.n, jb = p.jb;
   const int nb = min(NBK, n - jb);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  __shared__ TZ B[NBK][NBK + 1];  // B[c][r] = block entry (row r, column c)
+  __shared__ __align__(16) TZ B[NBK][DIP];  // B[k][i] = block entry (row i, column k)
   __shared__ TZ rdiag[NBK];
   // consecutive threads read consecutive columns of a factor row
-  for (int idx = tid; idx < NBK * NBK; idx += 256) {
-    const int c = idx % NBK, r = idx / NBK;
-    B[c][r] = (r < nb && c < nb) ? LU[(int64_t)p.perm[jb + r] * n + jb + c] : TZ(0);
+  for (int idx = tid; idx < NBK * NBK; idx += 128) {
+    const int k = idx % NBK, i = idx / NBK;
+    B[k][i] = (i < nb && k < nb) ? LU[(int64_t)p.perm[jb + i] * n + jb + k] : TZ(0);
   }
   __syncthreads();
   if (tid < NBK) rdiag[tid] = (tid < nb) ? TZ(1) / B[tid][tid] : TZ(0);
   __syncthreads();
-  constexpr int CQ = NBK / 4;  // identity columns per wave
-  // inv(L) (L X = I, L unit lower, forward) and inv(U) (U X = I, backward)
-  // in one loop: the two substitution chains are independent, so each step
-  // carries both and their latencies overlap
-  TZ xl[CQ], xu[CQ];
+  const int c = lane;
+  TZ x[NBK];
 #pragma unroll
-  for (int q = 0; q < CQ; ++q) {
-    xl[q] = (lane == wave * CQ + q && lane < nb) ? TZ(1) : TZ(0);
-    xu[q] = xl[q];
-  }
-  for (int i = 0; i < nb; ++i) {
-    const int jl = i, ju = nb - 1 - i;  // forward and backward pivots
-    const TZ l = (lane > jl) ? B[jl][lane] : TZ(0);
-    const TZ u = (lane < ju) ? B[ju][lane] : TZ(0);
-    const TZ rd = rdiag[ju];
+  for (int i = 0; i < NBK; ++i) x[i] = (i == c && c < nb) ? TZ(1) : TZ(0);
+  if (wave == 0) {
+    // inv(L): forward, L unit lower
 #pragma unroll
-    for (int q = 0; q < CQ; ++q) {
-      if (lane == ju) xu[q] *= rd;
-      xl[q] -= l * lane_bcast(xl[q], jl);
-      xu[q] -= u * lane_bcast(xu[q], ju);
+    for (int k = 0; k < NBK - 1; ++k) {
+      const TZ xk = x[k];
+#pragma unroll
+      for (int i = k + 1; i < NBK; ++i) x[i] -= B[k][i] * xk;
+    }
+  } else {
+    // inv(U): backward
+#pragma unroll
+    for (int k = NBK - 1; k >= 0; --k) {
+      x[k] *= rdiag[k];
+      const TZ xk = x[k];
+#pragma unroll
+      for (int i = 0; i < k; ++i) x[i] -= B[k][i] * xk;
     }
   }
-  // both inverses leave through B (no longer read), row-major, so that the
-  // stores coalesce
-  auto store = [&](const TZ (&x)[CQ], TZ* dst) {
-    __syncthreads();
+  TZ* dst = out + wave * NBK * NBK;  // row-major: lanes of a row store consecutive columns
 #pragma unroll
-    for (int q = 0; q < CQ; ++q) B[lane][wave * CQ + q] = (lane < nb) ? x[q] : TZ(0);
-    __syncthreads();
-    for (int idx = tid; idx < NBK * NBK; idx += 256) dst[idx] = B[idx / NBK][idx % NBK];
-  };
-  store(xl, out);
-  store(xu, out + NBK * NBK);
+  for (int i = 0; i < NBK; ++i) dst[i * NBK + c] = (i < nb && c < nb) ? x[i] : TZ(0);
 }
 
 // ------------------------------------------------------------------- solves
@@ -270,7 +271,7 @@ size_t getrs_lds_bytes(int nmax, size_t tz_bytes, int cols) {
 template <typename TZ>
 hipError_t launch_diag_inv(const DiagInvProb* probs, int count, hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_diag_inv<TZ>), dim3(count), dim3(256), 0, s, probs);
+  hipLaunchKernelGGL((k_diag_inv<TZ>), dim3(count), dim3(128), 0, s, probs);
   return hipGetLastError();
 }
 
