@@ -306,41 +306,57 @@ __global__ __launch_bounds__(64 * NW) void k_getrf(const LuProb* __restrict__ pr
         const int cc = cb + cl;
         if (i >= 1 && cc < ce) A[(int64_t)Ps[r0 + i] * n + cc] = Uc[i][cl];
       }
-      for (int it = wave; it < ntr; it += NW) {
+      // two row tiles per iteration (it and it + NW): both tiles' operand
+      // loads are in flight before either computes.  A second tile past the
+      // last row reads nothing and stores nothing (rows >= n are masked), so
+      // the loop has no divergent path.
+      constexpr int CTB = (CH / 16) * W / KW;  // 16-column blocks per pass
+      auto row_tile = [&](int it, T (&a)[KG], int (&pr4)[4]) {
         const int t0 = c0 + 16 * it;
         const int row = t0 + lr;
-        T a[KG];
         // r0 + KW <= n here: whole row segments, branch-free
-        load_row_sigma_full(A + (int64_t)(row < n ? Ps[row] : 0) * n + r0, row < n ? KW : 0, lg, a);
-        int pr4[4];
+        load_row_sigma_full(A + (int64_t)(row < n ? Ps[row] : 0) * n + r0, row < n ? KW : 0, lg,
+                            a);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int rr = t0 + acc_row(T(0), lg, v);
           pr4[v] = (rr < n) ? Ps[rr] : -1;
         }
+      };
+      for (int it = wave; it < ntr; it += 2 * NW) {
+        T a0[KG], a1[KG];
+        int p0[4], p1[4];
+        row_tile(it, a0, p0);
+        row_tile(it + NW, a1, p1);
         // the chunk's 16-column blocks in passes of CTB, so that K = 2W keeps
         // about as many operands live as K = W
-        constexpr int CTB = (CH / 16) * W / KW;
 #pragma unroll
         for (int c1 = 0; c1 < CH / 16; c1 += CTB) {
-          V4 cur[CTB];
+          V4 cur0[CTB], cur1[CTB];
 #pragma unroll
           for (int q = 0; q < CTB; ++q) {
             const int cc = cb + 16 * (c1 + q) + lr;
 #pragma unroll
-            for (int v = 0; v < 4; ++v)
-              cur[q][v] = (pr4[v] >= 0 && cc < ce) ? A[(int64_t)pr4[v] * n + cc] : T(0);
+            for (int v = 0; v < 4; ++v) {
+              cur0[q][v] = (p0[v] >= 0 && cc < ce) ? A[(int64_t)p0[v] * n + cc] : T(0);
+              cur1[q][v] = (p1[v] >= 0 && cc < ce) ? A[(int64_t)p1[v] * n + cc] : T(0);
+            }
           }
 #pragma unroll
           for (int q = 0; q < CTB; ++q) {
-            V4 acc = V4{0, 0, 0, 0};
+            V4 acc0 = V4{0, 0, 0, 0}, acc1 = V4{0, 0, 0, 0};
 #pragma unroll
-            for (int kk = 0; kk < KG; ++kk)
-              acc = mfma16(a[kk], Uc[sigma_k<T>(kk, lg)][16 * (c1 + q) + lr], acc);
+            for (int kk = 0; kk < KG; ++kk) {
+              const T u = Uc[sigma_k<T>(kk, lg)][16 * (c1 + q) + lr];
+              acc0 = mfma16(a0[kk], u, acc0);
+              acc1 = mfma16(a1[kk], u, acc1);
+            }
             const int cc = cb + 16 * (c1 + q) + lr;
 #pragma unroll
-            for (int v = 0; v < 4; ++v)
-              if (pr4[v] >= 0 && cc < ce) A[(int64_t)pr4[v] * n + cc] = cur[q][v] - acc[v];
+            for (int v = 0; v < 4; ++v) {
+              if (p0[v] >= 0 && cc < ce) A[(int64_t)p0[v] * n + cc] = cur0[q][v] - acc0[v];
+              if (p1[v] >= 0 && cc < ce) A[(int64_t)p1[v] * n + cc] = cur1[q][v] - acc1[v];
+            }
           }
         }
       }
