@@ -286,18 +286,22 @@ __global__ __launch_bounds__(64 * NW) void k_getrf(const LuProb* __restrict__ pr
     const int c0 = r0 + KW;
     const int ntr = (n - c0 + 15) / 16;
     for (int cb = cs; cb < ce; cb += CH) {
-      for (int it = wave; it < (KW / 16) * (CH / 16); it += NW) {
-        const int rt = it % (KW / 16), ct = it / (KW / 16);
+      // wave w takes the chunk's 16-column blocks w, w + NW, ...: it loads
+      // a block's KW rows of A12 once and applies every row block of Lsup
+      for (int ct = wave; ct < CH / 16; ct += NW) {
         const int cc = cb + 16 * ct + lr;
-        V4 acc = V4{0, 0, 0, 0};
+        T b[KG];
 #pragma unroll
-        for (int kk = 0; kk < KG; ++kk) {
-          const T a = Lsup[16 * rt + lr][4 * kk + lg];
-          const T b = (cc < ce) ? A[(int64_t)Ps[r0 + 4 * kk + lg] * n + cc] : T(0);
-          acc = mfma16(a, b, acc);
+        for (int kk = 0; kk < KG; ++kk)
+          b[kk] = (cc < ce) ? A[(int64_t)Ps[r0 + 4 * kk + lg] * n + cc] : T(0);
+#pragma unroll
+        for (int rt = 0; rt < KW / 16; ++rt) {
+          V4 acc = V4{0, 0, 0, 0};
+#pragma unroll
+          for (int kk = 0; kk < KG; ++kk) acc = mfma16(Lsup[16 * rt + lr][4 * kk + lg], b[kk], acc);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) Uc[16 * rt + acc_row(T(0), lg, v)][16 * ct + lr] = acc[v];
         }
-#pragma unroll
-        for (int v = 0; v < 4; ++v) Uc[16 * rt + acc_row(T(0), lg, v)][16 * ct + lr] = acc[v];
       }
       __syncthreads();
       // write U12 back (logical rows r0+1 .. r0+KW-1; row r0 is unchanged)
@@ -550,19 +554,23 @@ __global__ __launch_bounds__(64) void k_getrf_w(const LuProb* __restrict__ probs
     __builtin_amdgcn_wave_barrier();
     const int c0 = j0 + jb;
     for (int cb = c0; cb < n; cb += CH) {
-      for (int it = 0; it < (W / 16) * (CH / 16); ++it) {
-        const int rt = it % (W / 16), ct = it / (W / 16);
+      // each 16-column block of A12 is loaded once for both row blocks
+      for (int ct = 0; ct < CH / 16; ++ct) {
         const int cc = cb + 16 * ct + lr;
-        V4 acc = V4{0, 0, 0, 0};
+        T b[W / 4];
 #pragma unroll
         for (int kk = 0; kk < W / 4; ++kk) {
           const int k = 4 * kk + lg;
-          const T a = Li[16 * rt + lr][k];
-          const T b = (cc < n && k < jb) ? A[(int64_t)uph[kk] * n + cc] : T(0);
-          acc = mfma16(a, b, acc);
+          b[kk] = (cc < n && k < jb) ? A[(int64_t)uph[kk] * n + cc] : T(0);
         }
 #pragma unroll
-        for (int v = 0; v < 4; ++v) Uc[16 * rt + acc_row(T(0), lg, v)][16 * ct + lr] = acc[v];
+        for (int rt = 0; rt < W / 16; ++rt) {
+          V4 acc = V4{0, 0, 0, 0};
+#pragma unroll
+          for (int kk = 0; kk < W / 4; ++kk) acc = mfma16(Li[16 * rt + lr][4 * kk + lg], b[kk], acc);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) Uc[16 * rt + acc_row(T(0), lg, v)][16 * ct + lr] = acc[v];
+        }
       }
       __builtin_amdgcn_wave_barrier();
       for (int idx = lane; idx < W * CH; idx += 64) {
