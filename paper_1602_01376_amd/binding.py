@@ -141,7 +141,10 @@ class Factorization:
     """A factored lambda*I + K~ on the GPU (one library handle).
 
     `points` and `p_values` are borrowed by the library: this object keeps
-    the device tensors alive for as long as the handle exists.
+    the device tensors alive for as long as the handle exists.  `tune`
+    ("auto" or "off") and `leaf_lu_panel`, `leaf_lu_waves`, `leaf_trsm_cols`
+    (0 = per `tune`) map to the tile options of invaskit_options;
+    `tile_config()` reports what the factorization used.
     """
 
     def __init__(self, problem, lam: float, precision: str = "fp64",
