@@ -239,8 +239,9 @@ int invaskit_device_bytes(invaskit_handle handle, size_t* bytes);
  * not add up to the total): [0] leaf block evaluation, [1] leaf LU, [2]
  * inverses of the factors' 64 x 64 diagonal blocks (leaves), [3] skeleton
  * blocks, [4] leaf solves, [5] leaf projections, [6] skeleton sweep, [7]
- * unused (0: the N-sized corrections of W are applied inside each solve),
- * [8] reduced systems (assembly, LU, diagonal-block inverses), [9] total.
+ * host planning and allocation of the handle when it was created (wall
+ * clock; not part of [9], the same on every refactor), [8] reduced systems
+ * (assembly, LU, diagonal-block inverses), [9] total.
  * Writes min(n, 10) values.
  */
 int invaskit_phase_times(invaskit_handle handle, double* ms, int32_t n);

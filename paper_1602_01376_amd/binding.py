@@ -243,7 +243,7 @@ class Factorization:
         out = (C.c_double * 10)()
         _check(_lib.invaskit_phase_times(self._handle, out, 10), self._handle)
         keys = ["leaf_blocks", "leaf_lu", "leaf_diag_inverses", "skeleton_blocks", "leaf_solves",
-                "leaf_projections", "skeleton_sweep", "unused", "reduced_systems",
+                "leaf_projections", "skeleton_sweep", "handle_planning", "reduced_systems",
                 "total"]
         return dict(zip(keys, list(out)))
 

@@ -37,6 +37,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -234,6 +235,7 @@ struct invaskit_handle_s {
   std::map<int, std::unique_ptr<SolvePlan>> solve_plans;
   std::map<int, std::unique_ptr<MatvecPlan>> mv_plans;
   double phase_ms[kPhases] = {0};
+  double plan_ms = 0;  // host planning and allocation of the handle (wall clock)
   hipEvent_t ev[kEvents + 2] = {};
   bool have_events = false;
   // second stream of the factorization (default priority): the skeleton
@@ -1247,6 +1249,7 @@ int run_factor(H* h) {
   STEP(hipStreamSynchronize(s));
   if (kc) kc->valid = true;
   for (double& v : h->phase_ms) v = 0.0;
+  h->phase_ms[7] = h->plan_ms;
   for (const Bracket& br : brackets) {
     float ms = 0.f;
     if (br.a && br.b && hipEventElapsedTime(&ms, br.a, br.b) == hipSuccess)
@@ -1668,7 +1671,10 @@ int make_handle(const invaskit_problem* pb, double lambda, const invaskit_option
   h->p_off.assign(pb->p_offsets, pb->p_offsets + h->nn + 1);
   if (h->skel_off[h->nn] > 0)
     h->skel_idx.assign(pb->skel_index, pb->skel_index + h->skel_off[h->nn]);
+  const auto t0 = std::chrono::steady_clock::now();
   if ((rc = plan_factor(h.get()))) return rc;
+  h->plan_ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   rc = run_factor(h.get());
   *out = h.release();
   return rc;
