@@ -490,6 +490,7 @@ struct GemmBuilder {
     // that needs fewer padded tile elements (few rows, many columns).
     std::vector<Tile3> tiles, tiles_t;
     std::vector<int64_t> cost(probs.size(), 0);
+    std::vector<char> trans(probs.size(), 0);
     auto padded = [](int M, int N) {
       return (int64_t)((M + kGemmTileM - 1) / kGemmTileM) * kGemmTileM * gemm_cols_padded(N);
     };
@@ -509,16 +510,21 @@ struct GemmBuilder {
           g.a_rm = 1;  // B (column-major K x N) read as the row-major N x K operand
         }
         std::swap(p.M, p.N);
-        gemm_tiles(tiles_t, (int)i, p.M, p.N);
-      } else {
-        gemm_tiles(tiles, (int)i, p.M, p.N);
+        trans[i] = 1;
       }
     }
-    // longest products first, so the launch does not end on a long tile;
-    // stable, so a product's tiles stay consecutive
-    auto by_cost = [&](const Tile3& x, const Tile3& y) { return cost[x.prob] > cost[y.prob]; };
-    std::stable_sort(tiles.begin(), tiles.end(), by_cost);
-    std::stable_sort(tiles_t.begin(), tiles_t.end(), by_cost);
+    // longest products first, so the launch does not end on a long tile; a
+    // product's tiles stay consecutive (the products are sorted, stably, and
+    // their tiles emitted in that order)
+    std::vector<int> order(probs.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int x, int y) { return cost[x] > cost[y]; });
+    for (int i : order) {
+      const GemmProb& p = probs[i];
+      if (p.M <= 0 || p.N <= 0) continue;
+      gemm_tiles(trans[i] ? tiles_t : tiles, i, p.M, p.N);
+    }
     GemmL l;
     l.probs = ar.add(probs);
     l.segs = ar.add(segs);
@@ -557,15 +563,17 @@ struct TrsmBuilder {
       l.ntiles = -1;  // the workgroup's right-hand sides do not fit in LDS
       return l;
     }
+    // largest systems first (the systems are sorted, stably, and their
+    // tiles emitted in that order, so a system's tiles stay consecutive)
+    std::vector<int> order(probs.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int x, int y) { return probs[x].n > probs[y].n; });
     std::vector<Tile2> tiles;
-    for (size_t i = 0; i < probs.size(); ++i) {
-      for (int tn = 0; tn < (probs[i].nrhs + cols - 1) / cols; ++tn) tiles.push_back({(int)i, tn});
+    for (int i : order) {
+      for (int tn = 0; tn < (probs[i].nrhs + cols - 1) / cols; ++tn) tiles.push_back({i, tn});
       l.work += (double)probs[i].n * probs[i].n * probs[i].nrhs;
     }
-    // largest systems first (stable: a system's tiles stay consecutive)
-    std::stable_sort(tiles.begin(), tiles.end(), [&](const Tile2& x, const Tile2& y) {
-      return probs[x.prob].n > probs[y.prob].n;
-    });
     l.probs = ar.add(probs);
     l.tiles = ar.add(tiles);
     l.ntiles = (int)tiles.size();
