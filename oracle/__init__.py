@@ -1,5 +1,4 @@
 """FP64 CPU oracle (test infrastructure only; see invaskit_oracle)."""
 from .invaskit_oracle import (  # noqa: F401
     OracleSingular, Factorization, factorize, solve, solve_node, matvec,
-    matvec_rows, skeletonize_weights, dense_assemble, dense_solve, gaussian,
-    panel_blocks, leaf_blocks)
+    matvec_rows, skeletonize_weights, dense_assemble, gaussian)

@@ -288,33 +288,3 @@ def dense_assemble(pb):
         Kt[la:lb, ra:rb] = gaussian(X[la:lb], X[_skel(pb, r)], pb.h) @ pf[r]
         Kt[ra:rb, la:lb] = gaussian(X[ra:rb], X[_skel(pb, l)], pb.h) @ pf[l]
     return Kt
-
-
-def dense_solve(pb, lam, b):
-    """(lambda*I + K~)^-1 b by dense LU (LAPACK getrf/getrs) of the assembled
-    matrix; tiny N only."""
-    A = dense_assemble(pb)
-    A[np.diag_indices_from(A)] += lam
-    return np.linalg.solve(A, np.asarray(b, dtype=np.float64))
-
-
-def panel_blocks(pb, level):
-    """For every node c at `level` (>= 1), the skeleton block
-    K(X_c, X_{sibling~}) of eq. (7); returns {node: block}."""
-    out = {}
-    for c in range((1 << level) - 1, (1 << (level + 1)) - 1):
-        sib = c + 1 if c % 2 == 1 else c - 1
-        a, b = _range(pb, c)
-        out[c] = gaussian(pb.X[a:b], pb.X[_skel(pb, sib)], pb.h)
-    return out
-
-
-def leaf_blocks(pb, lam):
-    """lambda*I + K_aa for every leaf a; returns {node: block}."""
-    out = {}
-    for node in range((1 << pb.depth) - 1, (1 << (pb.depth + 1)) - 1):
-        a, b = _range(pb, node)
-        A = gaussian(pb.X[a:b], pb.X[a:b], pb.h)
-        A[np.diag_indices_from(A)] += lam
-        out[node] = A
-    return out

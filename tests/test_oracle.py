@@ -178,6 +178,23 @@ def test_matvec_rows_match_matvec():
     np.testing.assert_allclose(oracle.matvec_rows(pb, 1e-3, x, rows), y[rows], rtol=1e-12)
 
 
+def test_skeletonize_weights_select_points_with_full_skeletons():
+    # With s = |node| at every node each P is a permutation onto the node's
+    # skeleton order, so the Skeletonize weights are the values of x at the
+    # skeleton points themselves: q_c = x[skel(c)] (leaf and internal nodes).
+    pb = make_problem("tiny", n=256, depth=3, full_skeletons=True)
+    x = np.random.default_rng(8).standard_normal((256, 2))
+    q = oracle.skeletonize_weights(pb, x)
+    for node in range(1, pb.n_nodes):
+        np.testing.assert_allclose(q[node], x[pb.skel(node)], rtol=0, atol=1e-15)
+    # the hand problem: one skeleton point per leaf, P written out
+    hp = _hand_problem()
+    xh = np.arange(1.0, 7.0)
+    qh = oracle.skeletonize_weights(hp, xh)
+    assert abs(qh[1][0] - (0.7 * 1 + 1.0 * 2 - 0.2 * 3)) < 1e-14
+    assert abs(qh[2][0] - (0.3 * 4 + 1.0 * 5 + 0.9 * 6)) < 1e-14
+
+
 def test_skeleton_projection_of_corrected_solution():
     # After w = v - W Z V v at node a, the children's skeleton projections of
     # w equal y = Z (V v):  V w = V v - V W y = V v - (Z^-1 - I) y = y.
