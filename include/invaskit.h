@@ -90,13 +90,39 @@ typedef struct invaskit_problem {
   double h;
 } invaskit_problem;
 
+/*
+ * Refinement modes (invaskit_options.refine).  Every mode measures residuals
+ * r = b - (lambda*I + K~) x with the FP64 hierarchical product
+ * (invaskit_matvec) and updates x in FP64; the factors (FP32 in mixed mode,
+ * FP64 in FP64 mode) serve as the approximate inverse M^-1.
+ *  AUTO   iterative refinement x += M^-1 r while every step at least halves
+ *         the worst column's residual; if a step does not, restarted
+ *         flexible GMRES on A, right-preconditioned by M^-1, continues from
+ *         the best iterate (GMRES-based refinement: it converges in cases
+ *         where M^-1 is too inaccurate for plain refinement, e.g. FP32
+ *         factors of an ill-conditioned lambda*I + K~).  In FP64 mode the
+ *         first step is the direct solve, so a well-conditioned problem
+ *         costs one solve and one product.
+ *  IR     iterative refinement only; stops on convergence, at the cap, or
+ *         when the residual has not halved over three iterations.
+ *  GMRES  restarted flexible GMRES from x = 0.
+ *  NONE   one direct solve, no refinement.  The residual is computed (one
+ *         product) only when info is requested; then a residual above
+ *         refine_tol returns INVASKIT_E_NOT_CONVERGED like the other modes.
+ */
+#define INVASKIT_REFINE_AUTO  0
+#define INVASKIT_REFINE_IR    1
+#define INVASKIT_REFINE_GMRES 2
+#define INVASKIT_REFINE_NONE  3
+
 typedef struct invaskit_options {
   int32_t precision;        /* INVASKIT_PREC_FP64 (default) or _MIXED            */
   int32_t fp64_top_levels;  /* mixed mode: reduced systems at levels < this are
                                factored in FP64 (default 4)                       */
-  double refine_tol;        /* mixed mode: stop when |b - A x|_2 / |b|_2 <= tol
-                               for every column (default 1e-10)                   */
-  int32_t max_refine_iters; /* mixed mode: iteration cap (default 30)             */
+  double refine_tol;        /* stop when |b - A x|_2 / |b|_2 <= tol for every
+                               column (default 1e-10)                             */
+  int32_t max_refine_iters; /* cap on refinement steps x += M^-1 r, the first
+                               (direct) solve included (default 30)              */
   int32_t tune;             /* INVASKIT_TUNE_AUTO (default) or _OFF, see below   */
   int32_t leaf_lu_panel;    /* 0 (default): per `tune`; 16 or 32: LU panel width
                                of the leaf blocks                                 */
@@ -105,6 +131,10 @@ typedef struct invaskit_options {
                                factorization                                      */
   int32_t leaf_lu_waves;    /* 0 (default): per `tune`; 4 or 8: waves (of 64
                                lanes) per matrix in the leaf LU                   */
+  int32_t refine;           /* INVASKIT_REFINE_* (default AUTO)                   */
+  int32_t gmres_restart;    /* Krylov vectors per GMRES cycle, 2..64 (default 20) */
+  int32_t max_gmres_iters;  /* cap on GMRES steps over all cycles (default 300)  */
+  int32_t reserved1;
 } invaskit_options;
 
 /*
@@ -143,10 +173,15 @@ typedef struct invaskit_options {
 #define INVASKIT_TUNE_OFF  1
 
 typedef struct invaskit_solve_info {
-  int32_t iterations;            /* refinement iterations taken (0 in FP64 mode) */
-  int32_t converged;             /* 1 when every column met refine_tol           */
+  int32_t iterations;            /* refinement steps x += M^-1 r, the first
+                                    (direct) solve included                      */
+  int32_t converged;             /* 1 when every column met refine_tol, as
+                                    measured by the FP64 product                 */
   double final_rel_residual;     /* max over columns of |b - A x| / |b|, FP64   */
-  double unrefined_rel_residual; /* same after the first low-precision solve     */
+  double unrefined_rel_residual; /* same after the first solve x = M^-1 b       */
+  int32_t gmres_iterations;      /* GMRES steps (one M^-1 and one product each) */
+  int32_t method;                /* INVASKIT_REFINE_* that produced x: NONE,
+                                    IR, or GMRES when GMRES ran                  */
 } invaskit_solve_info;
 
 typedef struct invaskit_handle_s* invaskit_handle;

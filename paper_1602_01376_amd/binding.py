@@ -39,10 +39,13 @@ class _Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("fp64_top_levels", C.c_int32),
                 ("refine_tol", C.c_double), ("max_refine_iters", C.c_int32),
                 ("tune", C.c_int32), ("leaf_lu_panel", C.c_int32),
-                ("leaf_trsm_cols", C.c_int32), ("leaf_lu_waves", C.c_int32)]
+                ("leaf_trsm_cols", C.c_int32), ("leaf_lu_waves", C.c_int32),
+                ("refine", C.c_int32), ("gmres_restart", C.c_int32),
+                ("max_gmres_iters", C.c_int32), ("reserved1", C.c_int32)]
 
 
 TUNE_AUTO, TUNE_OFF = 0, 1
+REFINE = {"auto": 0, "ir": 1, "gmres": 2, "none": 3}
 
 
 class _TileConfig(C.Structure):
@@ -53,10 +56,13 @@ class _TileConfig(C.Structure):
 
 class SolveInfo(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("converged", C.c_int32),
-                ("final_rel_residual", C.c_double), ("unrefined_rel_residual", C.c_double)]
+                ("final_rel_residual", C.c_double), ("unrefined_rel_residual", C.c_double),
+                ("gmres_iterations", C.c_int32), ("method", C.c_int32)]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_}
+        d = {f: getattr(self, f) for f, _ in self._fields_}
+        d["method"] = {v: k for k, v in REFINE.items()}.get(d["method"], d["method"])
+        return d
 
 
 def _load():
@@ -150,10 +156,12 @@ class Factorization:
     def __init__(self, problem, lam: float, precision: str = "fp64",
                  fp64_top_levels: int = 4, refine_tol: float = 1e-10,
                  max_refine_iters: int = 30, points=None, p_values=None, tune: str = "auto",
-                 leaf_lu_panel: int = 0, leaf_trsm_cols: int = 0, leaf_lu_waves: int = 0):
+                 leaf_lu_panel: int = 0, leaf_trsm_cols: int = 0, leaf_lu_waves: int = 0,
+                 refine: str = "auto", gmres_restart: int = 20, max_gmres_iters: int = 300):
         pb, opt = self._prepare(problem, lam, precision, fp64_top_levels, refine_tol,
                                 max_refine_iters, points, p_values, tune, leaf_lu_panel,
-                                leaf_trsm_cols, leaf_lu_waves)
+                                leaf_trsm_cols, leaf_lu_waves, refine, gmres_restart,
+                                max_gmres_iters)
         self._handle = C.c_void_p()
         st = _lib.invaskit_factor(C.byref(pb), self.lam, C.byref(opt), _stream(),
                                   C.byref(self._handle))
@@ -166,7 +174,7 @@ class Factorization:
 
     def _prepare(self, problem, lam, precision, fp64_top_levels, refine_tol, max_refine_iters,
                  points, p_values, tune="auto", leaf_lu_panel=0, leaf_trsm_cols=0,
-                 leaf_lu_waves=0):
+                 leaf_lu_waves=0, refine="auto", gmres_restart=20, max_gmres_iters=300):
         """Marshal the problem and options (the arrays stay alive with self)."""
         self.n = problem.n
         self.lam = float(lam)
@@ -199,6 +207,11 @@ class Factorization:
         opt.leaf_lu_panel = int(leaf_lu_panel)
         opt.leaf_trsm_cols = int(leaf_trsm_cols)
         opt.leaf_lu_waves = int(leaf_lu_waves)
+        if refine not in REFINE:
+            raise ValueError(f"refine must be one of {sorted(REFINE)}")
+        opt.refine = REFINE[refine]
+        opt.gmres_restart = int(gmres_restart)
+        opt.max_gmres_iters = int(max_gmres_iters)
         return pb, opt
 
     @property
@@ -404,14 +417,16 @@ def gemm_batched(problems, dtype=torch.float64, alpha=1.0, beta=0.0):
 def factor_sweep(problem, lams, precision: str = "fp64", fp64_top_levels: int = 4,
                  refine_tol: float = 1e-10, max_refine_iters: int = 30, points=None,
                  p_values=None, tune: str = "auto", leaf_lu_panel: int = 0,
-                 leaf_trsm_cols: int = 0, leaf_lu_waves: int = 0):
+                 leaf_trsm_cols: int = 0, leaf_lu_waves: int = 0, refine: str = "auto",
+                 gmres_restart: int = 20, max_gmres_iters: int = 300):
     """One Factorization per lambda in `lams` (invaskit_factor_sweep): the
     kernel blocks are evaluated once and shared by the handles."""
     lams = [float(v) for v in lams]
     objs = [Factorization.__new__(Factorization) for _ in lams]
     pb, opt = objs[0]._prepare(problem, lams[0], precision, fp64_top_levels, refine_tol,
                                max_refine_iters, points, p_values, tune, leaf_lu_panel,
-                               leaf_trsm_cols, leaf_lu_waves)
+                               leaf_trsm_cols, leaf_lu_waves, refine, gmres_restart,
+                               max_gmres_iters)
     for o, lam in zip(objs[1:], lams[1:]):
         o.n, o.lam, o.precision = objs[0].n, lam, precision
         o._points, o._p = objs[0]._points, objs[0]._p

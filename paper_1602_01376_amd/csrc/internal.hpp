@@ -203,11 +203,29 @@ template <typename TI, typename TO>
 hipError_t launch_copy_cols(const TI* in, int64_t ldi, TO* out, int64_t ldo, int64_t n,
                             int ncols, const double* scale, bool invert_scale, hipStream_t s);
 // x[i + c*ldx] += scale[c] * d[i + c*ldd]
-hipError_t launch_axpy_cols(double* x, int64_t ldx, const float* d, int64_t ldd, int64_t n,
+template <typename TD>
+hipError_t launch_axpy_cols(double* x, int64_t ldx, const TD* d, int64_t ldd, int64_t n,
                             int ncols, const double* scale, hipStream_t s);
 // out[c] = sum_i v[i + c*ld]^2 (out must be zeroed by the launcher)
 hipError_t launch_colsumsq(const double* v, int64_t ld, int64_t n, int ncols, double* out,
                            hipStream_t s);
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
+// v[i + c*ld] *= scale[c] (scale on the device); v[i + c*ld] = 0
+hipError_t launch_scale_cols(double* v, int64_t ld, int64_t n, int ncols, const double* scale,
+                             hipStream_t s);
+hipError_t launch_zero_cols(double* v, int64_t ld, int64_t n, int ncols, hipStream_t s);
+// out[k * ncols + c] = sum_i V_k[i, c] w[i, c] for k < nk, c < ncols, with
+// V_k = V + k * vstride and column c at + c * ldv (w: + c * ldw); two
+// passes through part (dots_part_doubles(n, nk, ncols) doubles), summed in
+// a fixed order
+size_t dots_part_doubles(int64_t n, int nk, int ncols);
+hipError_t launch_dots(const double* V, int64_t vstride, int64_t ldv, int nk, const double* w,
+                       int64_t ldw, int64_t n, int ncols, double* part, double* out,
+                       hipStream_t s);
+// out[i, c] += alpha * sum_k coef[k * ncols + c] V_k[i, c]  (coef on the device)
+hipError_t launch_lincomb(double* out, int64_t ldo, const double* V, int64_t vstride,
+                          int64_t ldv, int nk, const double* coef, int ncols, double alpha,
+                          int64_t n, hipStream_t s);
+
 
 }  // namespace invaskit

@@ -164,7 +164,11 @@ struct FactorPlan {
 struct SolvePlan {
   int r = 0;
   DevBuf tables, xbuf, sbuf;  // xbuf/sbuf in the factor precision
-  DevBuf x64, r64, sc;        // refinement vectors (mixed mode)
+  DevBuf x64, r64, sc;        // refinement: iterate, residual, column scales
+  DevBuf gpart, gsmall;       // reduction partials; small per-column vectors
+  DevBuf gmV, gmZ;            // GMRES bases (allocated when GMRES first runs)
+  int gm_m = 0;               // Krylov vectors per GMRES cycle
+  std::vector<double> host_scale;
   TrsmL leaf_trsm;
   GemmL leaf_proj;
   std::vector<TrsmL> zsolve;  // levels L-1 .. 0
@@ -178,12 +182,16 @@ struct SolvePlan {
     x64.release();
     r64.release();
     sc.release();
+    gpart.release();
+    gsmall.release();
+    gmV.release();
+    gmZ.release();
   }
 };
 
 struct MatvecPlan {
   int r = 0;
-  DevBuf tables, xm, q, nrm;
+  DevBuf tables, xm, q;
   std::vector<GemmL> skel;  // levels L .. 1
   size_t mv_tiles = 0, mv_segs = 0;
   int n_mv_tiles = 0;
@@ -191,7 +199,6 @@ struct MatvecPlan {
     tables.release();
     xm.release();
     q.release();
-    nrm.release();
   }
 };
 
@@ -205,6 +212,8 @@ struct invaskit_handle_s {
   int maxit = 30;
   int tune = INVASKIT_TUNE_AUTO;
   int fix_lu_panel = 0, fix_lu_waves = 0, fix_trsm_cols = 0;  // 0: chosen by tuning
+  int refine = INVASKIT_REFINE_AUTO;
+  int gm_restart = 20, gm_maxit = 300;
   hipStream_t stream = nullptr;
   // problem (device data borrowed)
   int64_t N = 0;
@@ -359,6 +368,11 @@ int validate(H* h, const invaskit_problem* pb, double lambda, const invaskit_opt
       return fail_h(h, INVASKIT_E_ARG, "leaf_lu_panel and leaf_trsm_cols must be 0, 16 or 32");
     if (opt->leaf_lu_waves != 0 && opt->leaf_lu_waves != 4 && opt->leaf_lu_waves != 8)
       return fail_h(h, INVASKIT_E_ARG, "leaf_lu_waves must be 0, 4 or 8");
+    if (opt->refine < INVASKIT_REFINE_AUTO || opt->refine > INVASKIT_REFINE_NONE)
+      return fail_h(h, INVASKIT_E_ARG, "refine must be one of INVASKIT_REFINE_*");
+    if (opt->gmres_restart < 2 || opt->gmres_restart > 64)
+      return fail_h(h, INVASKIT_E_ARG, "gmres_restart must be in [2, 64]");
+    if (opt->max_gmres_iters < 1) return fail_h(h, INVASKIT_E_ARG, "max_gmres_iters < 1");
   }
   const int L = pb->depth;
   const int nleaves = 1 << L;
@@ -1312,11 +1326,14 @@ int build_solve_plan(H* h, int r, SolvePlan*& out) {
   int rc;
   if ((rc = dev_alloc(h, sp->xbuf, (size_t)h->N * r * es))) return rc;
   if ((rc = dev_alloc(h, sp->sbuf, std::max<int64_t>(off, 1) * es))) return rc;
-  if (!T64) {
-    if ((rc = dev_alloc(h, sp->x64, (size_t)h->N * r * 8))) return rc;
-    if ((rc = dev_alloc(h, sp->r64, (size_t)h->N * r * 8))) return rc;
-  }
+  if ((rc = dev_alloc(h, sp->x64, (size_t)h->N * r * 8))) return rc;
+  if ((rc = dev_alloc(h, sp->r64, (size_t)h->N * r * 8))) return rc;
   if ((rc = dev_alloc(h, sp->sc, sizeof(double) * r))) return rc;
+  if ((rc = dev_alloc(h, sp->gpart,
+                      sizeof(double) * dots_part_doubles(h->N, h->gm_restart + 1, r))))
+    return rc;
+  if ((rc = dev_alloc(h, sp->gsmall, sizeof(double) * (size_t)r * (4 * h->gm_restart + 3))))
+    return rc;
   void* xb = sp->xbuf.p;
   void* sb = sp->sbuf.p;
   const int32_t* lperm = static_cast<const int32_t*>(h->leafPerm.p);
@@ -1434,7 +1451,6 @@ int build_mv_plan(H* h, int r, MatvecPlan*& out) {
   int rc;
   if ((rc = dev_alloc(h, mp->xm, (size_t)h->N * r * 8))) return rc;
   if ((rc = dev_alloc(h, mp->q, std::max<int64_t>(off, 1) * 8))) return rc;
-  if ((rc = dev_alloc(h, mp->nrm, 2 * sizeof(double) * r))) return rc;
   double* xm = static_cast<double*>(mp->xm.p);
   double* q = static_cast<double*>(mp->q.p);
   const int32_t* skd = static_cast<const int32_t*>(h->skel_d.p);
@@ -1520,106 +1536,324 @@ int run_matvec(H* h, MatvecPlan* mp, const double* x, int64_t ldx, double* y, in
   return INVASKIT_OK;
 }
 
-int col_norms2(H* h, const double* v, int64_t ld, int r, double* dev_out, std::vector<double>& host) {
-  HIP_TRY(h, launch_colsumsq(v, ld, h->N, r, dev_out, h->stream));
+// ------------------------------------------------------------ refinement
+// Column norms^2 of an N x r FP64 block (deterministic two-pass sums), read
+// back to the host.
+int col_norms2(H* h, SolvePlan* sp, const double* v, int64_t ld, int r, std::vector<double>& host) {
+  double* part = static_cast<double*>(sp->gpart.p);
+  double* out = static_cast<double*>(sp->gsmall.p);
+  HIP_TRY(h, launch_dots(v, 0, ld, 1, v, ld, h->N, r, part, out, h->stream));
   host.assign(r, 0.0);
-  HIP_TRY(h, hipMemcpyAsync(host.data(), dev_out, sizeof(double) * r, hipMemcpyDeviceToHost,
+  HIP_TRY(h, hipMemcpyAsync(host.data(), out, sizeof(double) * r, hipMemcpyDeviceToHost,
                             h->stream));
   HIP_TRY(h, hipStreamSynchronize(h->stream));
+  return INVASKIT_OK;
+}
+
+// max over columns of |r_c| / |b_c| from squared norms (NaN propagates)
+double worst_rel(const std::vector<double>& rn, const std::vector<double>& bn) {
+  double worst = 0.0;
+  for (size_t c = 0; c < rn.size(); ++c) {
+    const double v = bn[c] > 0 ? std::sqrt(rn[c] / bn[c]) : std::sqrt(rn[c]);
+    if (!(v <= worst)) worst = v;
+  }
+  return worst;
+}
+
+// One refinement step x64 += M^-1 r64, with M^-1 the factors' direct solve
+// (FP32 in mixed mode).  Each residual column is divided by its norm before
+// the solve (so FP32 holds it at full relative precision) and the
+// correction multiplied back.
+int ir_step(H* h, SolvePlan* sp, const std::vector<double>& rn) {
+  hipStream_t s = h->stream;
+  const int r = sp->r;
+  const int64_t N = h->N;
+  double* x64 = static_cast<double*>(sp->x64.p);
+  double* r64 = static_cast<double*>(sp->r64.p);
+  double* sc = static_cast<double*>(sp->sc.p);
+  sp->host_scale.resize(r);
+  for (int c = 0; c < r; ++c) sp->host_scale[c] = std::sqrt(rn[c]);
+  HIP_TRY(h, hipMemcpyAsync(sc, sp->host_scale.data(), sizeof(double) * r, hipMemcpyHostToDevice,
+                            s));
+  if (h->prec == INVASKIT_PREC_FP64) {
+    double* xb = static_cast<double*>(sp->xbuf.p);
+    HIP_TRY(h, launch_copy_cols<double, double>(r64, N, xb, N, N, r, sc, true, s));
+    if (int rc = run_solve_plan(h, sp)) return rc;
+    HIP_TRY(h, launch_axpy_cols<double>(x64, N, xb, N, N, r, sc, s));
+  } else {
+    float* xb = static_cast<float*>(sp->xbuf.p);
+    HIP_TRY(h, launch_copy_cols<double, float>(r64, N, xb, N, N, r, sc, true, s));
+    if (int rc = run_solve_plan(h, sp)) return rc;
+    HIP_TRY(h, launch_axpy_cols<float>(x64, N, xb, N, N, r, sc, s));
+  }
+  // the host vector must outlive the asynchronous copy: the caller's next
+  // step synchronizes (the residual norms) before it is rewritten
+  return INVASKIT_OK;
+}
+
+// out = M^-1 in for unit-norm FP64 columns (a GMRES basis vector)
+int apply_precond(H* h, SolvePlan* sp, const double* in, double* out) {
+  hipStream_t s = h->stream;
+  const int r = sp->r;
+  const int64_t N = h->N;
+  if (h->prec == INVASKIT_PREC_FP64) {
+    double* xb = static_cast<double*>(sp->xbuf.p);
+    HIP_TRY(h, launch_copy_cols<double, double>(in, N, xb, N, N, r, nullptr, false, s));
+    if (int rc = run_solve_plan(h, sp)) return rc;
+    HIP_TRY(h, launch_copy_cols<double, double>(xb, N, out, N, N, r, nullptr, false, s));
+  } else {
+    float* xb = static_cast<float*>(sp->xbuf.p);
+    HIP_TRY(h, launch_copy_cols<double, float>(in, N, xb, N, N, r, nullptr, false, s));
+    if (int rc = run_solve_plan(h, sp)) return rc;
+    HIP_TRY(h, launch_copy_cols<float, double>(xb, N, out, N, N, r, nullptr, false, s));
+  }
+  return INVASKIT_OK;
+}
+
+// One cycle of restarted flexible GMRES (Saad's FGMRES) on A d = r64,
+// right-preconditioned by M^-1, from d = 0, for every column at once (each
+// column has its own Krylov space; they advance in lockstep).  Arnoldi with
+// classical Gram-Schmidt applied twice.  Adds d to x64.  A column stops
+// expanding its space when its least-squares residual estimate drops below
+// est_tol[c] or the space becomes invariant.  Returns the steps taken in
+// *steps (at most max_steps).
+int gmres_cycle(H* h, SolvePlan* sp, MatvecPlan* mp, const std::vector<double>& rn,
+                const std::vector<double>& est_tol, int max_steps, int* steps) {
+  hipStream_t s = h->stream;
+  const int r = sp->r;
+  const int m = std::min(sp->gm_m, max_steps);
+  const int64_t N = h->N;
+  const int64_t blk = N * r;  // one basis block: N x r, leading dimension N
+  double* V = static_cast<double*>(sp->gmV.p);
+  double* Zb = static_cast<double*>(sp->gmZ.p);
+  double* x64 = static_cast<double*>(sp->x64.p);
+  double* r64 = static_cast<double*>(sp->r64.p);
+  double* part = static_cast<double*>(sp->gpart.p);
+  double* small = static_cast<double*>(sp->gsmall.p);  // [h1 | h2 | nrm2 | coef]
+  const int M1 = sp->gm_m + 1;
+  double* h1d = small;
+  double* h2d = small + (size_t)M1 * r;
+  double* nrd = small + 2 * (size_t)M1 * r;
+  double* cfd = small + 3 * (size_t)M1 * r;
+  std::vector<double> H((size_t)r * M1 * m, 0.0), cs((size_t)r * m), sn((size_t)r * m);
+  std::vector<double> g((size_t)r * M1, 0.0);
+  std::vector<int> k(r, 0);
+  std::vector<char> active(r, 0);
+  std::vector<double> scale(r), hbuf(3 * (size_t)M1 * r);
+  auto Hc = [&](int c, int i, int j) -> double& { return H[((size_t)c * M1 + i) * m + j]; };
+  for (int c = 0; c < r; ++c) {
+    const double beta = std::sqrt(rn[c]);
+    g[(size_t)c * M1] = beta;
+    active[c] = beta > est_tol[c];
+    scale[c] = beta > 0 ? 1.0 / beta : 0.0;
+  }
+  HIP_TRY(h, hipMemcpyAsync(nrd, scale.data(), sizeof(double) * r, hipMemcpyHostToDevice, s));
+  HIP_TRY(h, launch_copy_cols<double, double>(r64, N, V, N, N, r, nrd, false, s));
+  HIP_TRY(h, hipStreamSynchronize(s));  // scale[] is rewritten below
+  int j = 0;
+  for (; j < m; ++j) {
+    bool any = false;
+    for (int c = 0; c < r; ++c) any = any || active[c];
+    if (!any) break;
+    double* vj = V + (size_t)j * blk;
+    double* vn = V + (size_t)(j + 1) * blk;
+    double* zj = Zb + (size_t)j * blk;
+    if (int rc = apply_precond(h, sp, vj, zj)) return rc;
+    if (int rc = run_matvec(h, mp, zj, N, vn, N, nullptr, 0)) return rc;
+    // classical Gram-Schmidt, twice
+    HIP_TRY(h, launch_dots(V, blk, N, j + 1, vn, N, N, r, part, h1d, s));
+    HIP_TRY(h, launch_lincomb(vn, N, V, blk, N, j + 1, h1d, r, -1.0, N, s));
+    HIP_TRY(h, launch_dots(V, blk, N, j + 1, vn, N, N, r, part, h2d, s));
+    HIP_TRY(h, launch_lincomb(vn, N, V, blk, N, j + 1, h2d, r, -1.0, N, s));
+    HIP_TRY(h, launch_dots(vn, 0, N, 1, vn, N, N, r, part, nrd, s));
+    HIP_TRY(h, hipMemcpyAsync(hbuf.data(), small, sizeof(double) * 3 * M1 * r,
+                              hipMemcpyDeviceToHost, s));
+    HIP_TRY(h, hipStreamSynchronize(s));
+    for (int c = 0; c < r; ++c) {
+      scale[c] = 0.0;
+      if (!active[c]) continue;
+      double hn2 = 0.0;
+      for (int i = 0; i <= j; ++i) {
+        const double v = hbuf[(size_t)i * r + c] + hbuf[(size_t)M1 * r + (size_t)i * r + c];
+        Hc(c, i, j) = v;
+        hn2 += v * v;
+      }
+      const double hnext = std::sqrt(hbuf[2 * (size_t)M1 * r + c]);
+      // rotations of the earlier columns, then a new one for row j + 1
+      for (int i = 0; i < j; ++i) {
+        const double a = Hc(c, i, j), b2 = Hc(c, i + 1, j);
+        Hc(c, i, j) = cs[(size_t)c * m + i] * a + sn[(size_t)c * m + i] * b2;
+        Hc(c, i + 1, j) = -sn[(size_t)c * m + i] * a + cs[(size_t)c * m + i] * b2;
+      }
+      const double a = Hc(c, j, j);
+      const double dd = std::hypot(a, hnext);
+      const double cj = dd > 0 ? a / dd : 1.0, sj = dd > 0 ? hnext / dd : 0.0;
+      cs[(size_t)c * m + j] = cj;
+      sn[(size_t)c * m + j] = sj;
+      Hc(c, j, j) = dd;
+      const double gj = g[(size_t)c * M1 + j];
+      g[(size_t)c * M1 + j] = cj * gj;
+      g[(size_t)c * M1 + j + 1] = -sj * gj;
+      k[c] = j + 1;
+      const bool invariant = !(hnext > 1e-14 * std::sqrt(hn2 + hnext * hnext));
+      if (dd == 0.0 || !std::isfinite(dd)) {
+        k[c] = j;  // no usable direction at this step
+        active[c] = 0;
+      } else if (invariant || std::fabs(g[(size_t)c * M1 + j + 1]) <= est_tol[c]) {
+        active[c] = 0;
+      } else {
+        scale[c] = 1.0 / hnext;
+      }
+    }
+    HIP_TRY(h, hipMemcpyAsync(nrd, scale.data(), sizeof(double) * r, hipMemcpyHostToDevice, s));
+    HIP_TRY(h, launch_scale_cols(vn, N, N, r, nrd, s));
+    HIP_TRY(h, hipStreamSynchronize(s));  // scale[] is rewritten next step
+  }
+  *steps = j;
+  if (j == 0) return INVASKIT_OK;
+  // y_c = R_c^-1 g_c (k_c x k_c upper triangle); zero beyond k_c
+  std::vector<double> y((size_t)j * r, 0.0);
+  for (int c = 0; c < r; ++c) {
+    for (int i = k[c] - 1; i >= 0; --i) {
+      double v = g[(size_t)c * M1 + i];
+      for (int q = i + 1; q < k[c]; ++q) v -= Hc(c, i, q) * y[(size_t)q * r + c];
+      y[(size_t)i * r + c] = v / Hc(c, i, i);
+    }
+  }
+  HIP_TRY(h, hipMemcpyAsync(cfd, y.data(), sizeof(double) * y.size(), hipMemcpyHostToDevice, s));
+  HIP_TRY(h, launch_lincomb(x64, N, Zb, blk, N, j, cfd, r, 1.0, N, s));
+  HIP_TRY(h, hipStreamSynchronize(s));  // y[] goes out of scope
+  return INVASKIT_OK;
+}
+
+int ensure_gmres_space(H* h, SolvePlan* sp) {
+  if (sp->gmV.p) return INVASKIT_OK;
+  const size_t blk = (size_t)h->N * sp->r * sizeof(double);
+  sp->gm_m = h->gm_restart;
+  int rc;
+  if ((rc = dev_alloc(h, sp->gmV, blk * (sp->gm_m + 1)))) return rc;
+  if ((rc = dev_alloc(h, sp->gmZ, blk * sp->gm_m))) return rc;
   return INVASKIT_OK;
 }
 
 int do_solve(H* h, const double* b, int64_t r64v, int64_t ldb, double* x, int64_t ldx,
              invaskit_solve_info* info) {
   const int r = (int)r64v;
+  const int64_t N = h->N;
   hipStream_t s = h->stream;
   SolvePlan* sp = nullptr;
   int rc;
   if ((rc = build_solve_plan(h, r, sp))) return rc;
-  const bool need_res = (h->prec == INVASKIT_PREC_MIXED) || info != nullptr;
+  const int mode = h->refine;
+  const bool need_res = mode != INVASKIT_REFINE_NONE || info != nullptr;
   MatvecPlan* mp = nullptr;
   if (need_res && (rc = build_mv_plan(h, r, mp))) return rc;
-  invaskit_solve_info loc{};
-  if (h->prec == INVASKIT_PREC_FP64) {
-    double* xb = static_cast<double*>(sp->xbuf.p);
-    HIP_TRY(h, launch_copy_cols<double, double>(b, ldb, xb, h->N, h->N, r, nullptr, false, s));
-    if ((rc = run_solve_plan(h, sp))) return rc;
-    HIP_TRY(h, launch_copy_cols<double, double>(xb, h->N, x, ldx, h->N, r, nullptr, false, s));
-    if (info) {
-      // residual b - A x with the FP64 hierarchical product, into xbuf
-      double* nrm = static_cast<double*>(mp->nrm.p);
-      std::vector<double> bn, rn;
-      if ((rc = col_norms2(h, b, ldb, r, nrm, bn))) return rc;
-      if ((rc = run_matvec(h, mp, x, ldx, xb, h->N, b, ldb))) return rc;
-      if ((rc = col_norms2(h, xb, h->N, r, nrm + r, rn))) return rc;
-      double worst = 0.0;
-      for (int c = 0; c < r; ++c)
-        worst = std::max(worst, bn[c] > 0 ? std::sqrt(rn[c] / bn[c]) : std::sqrt(rn[c]));
-      loc.iterations = 0;
-      loc.converged = 1;
-      loc.final_rel_residual = worst;
-      loc.unrefined_rel_residual = worst;
-      *info = loc;
-    }
-    return INVASKIT_OK;
-  }
-  // mixed precision: iterative refinement
   double* x64 = static_cast<double*>(sp->x64.p);
   double* r64 = static_cast<double*>(sp->r64.p);
-  float* xb = static_cast<float*>(sp->xbuf.p);
-  double* sc = static_cast<double*>(sp->sc.p);
-  double* nrm = static_cast<double*>(mp->nrm.p);
-  std::vector<double> bn, rn, scale(r);
-  if ((rc = col_norms2(h, b, ldb, r, nrm, bn))) return rc;
-  HIP_TRY(h, launch_fill_zero(x64, sizeof(double) * h->N * r, s));
-  HIP_TRY(h, launch_copy_cols<double, double>(b, ldb, r64, h->N, h->N, r, nullptr, false, s));
+  invaskit_solve_info loc{};
+  loc.method = mode == INVASKIT_REFINE_NONE ? INVASKIT_REFINE_NONE : INVASKIT_REFINE_IR;
+  std::vector<double> bn, rn;
+  if ((rc = col_norms2(h, sp, b, ldb, r, bn))) return rc;
+  HIP_TRY(h, launch_zero_cols(x64, N, N, r, s));
+  HIP_TRY(h, launch_copy_cols<double, double>(b, ldb, r64, N, N, r, nullptr, false, s));
   rn = bn;
-  double best = INFINITY, last = NAN, hist[3] = {INFINITY, INFINITY, INFINITY};
-  int it = 0;
-  bool conv = false;
-  for (it = 1; it <= h->maxit; ++it) {
-    for (int c = 0; c < r; ++c) scale[c] = std::sqrt(rn[c]);
-    HIP_TRY(h, hipMemcpyAsync(sc, scale.data(), sizeof(double) * r, hipMemcpyHostToDevice, s));
-    HIP_TRY(h, launch_copy_cols<double, float>(r64, h->N, xb, h->N, h->N, r, sc, true, s));
-    if ((rc = run_solve_plan(h, sp))) return rc;
-    HIP_TRY(h, launch_axpy_cols(x64, h->N, xb, h->N, h->N, r, sc, s));
-    if ((rc = run_matvec(h, mp, x64, h->N, r64, h->N, b, ldb))) return rc;
-    if ((rc = col_norms2(h, r64, h->N, r, nrm + r, rn))) return rc;
-    double worst = 0.0;
-    for (int c = 0; c < r; ++c)
-      worst = std::max(worst, bn[c] > 0 ? std::sqrt(rn[c] / bn[c]) : std::sqrt(rn[c]));
-    if (it == 1) loc.unrefined_rel_residual = worst;
-    last = worst;
-    // the caller's x keeps the best iterate so far (the one returned if the
-    // refinement stops short; on convergence the last iterate is the best)
-    if (worst < best) {
+  // x = 0 is the first candidate (relative residual 1); the caller's x
+  // always holds the best iterate so far
+  double best = 1.0, prev = 1.0, hist[3] = {INFINITY, INFINITY, INFINITY};
+  bool x_is_best_zero = true, last_is_best = true, conv = false, to_gmres = false;
+  auto residual = [&]() -> int {  // r64 = b - A x64 and its norms
+    int e = run_matvec(h, mp, x64, N, r64, N, b, ldb);
+    if (e) return e;
+    return col_norms2(h, sp, r64, N, r, rn);
+  };
+  auto keep_if_best = [&](double worst) -> int {
+    last_is_best = worst < best;
+    if (last_is_best) {
       best = worst;
-      loc.final_rel_residual = worst;
-      HIP_TRY(h, launch_copy_cols<double, double>(x64, h->N, x, ldx, h->N, r, nullptr, false, s));
+      x_is_best_zero = false;
+      HIP_TRY(h, launch_copy_cols<double, double>(x64, N, x, ldx, N, r, nullptr, false, s));
     }
-    if (worst <= h->tol) {
-      conv = true;
-      break;
+    return INVASKIT_OK;
+  };
+  int it = 0;
+  if (mode != INVASKIT_REFINE_GMRES) {
+    const int cap = mode == INVASKIT_REFINE_NONE ? 1 : h->maxit;
+    for (it = 1; it <= cap; ++it) {
+      if ((rc = ir_step(h, sp, rn))) return rc;
+      if (mode == INVASKIT_REFINE_NONE && !info) {
+        HIP_TRY(h, launch_copy_cols<double, double>(x64, N, x, ldx, N, r, nullptr, false, s));
+        return INVASKIT_OK;
+      }
+      if ((rc = residual())) return rc;
+      const double worst = worst_rel(rn, bn);
+      if (it == 1) loc.unrefined_rel_residual = worst;
+      if ((rc = keep_if_best(worst))) return rc;
+      if (worst <= h->tol) {
+        conv = true;
+        break;
+      }
+      if (mode == INVASKIT_REFINE_NONE) break;
+      if (mode == INVASKIT_REFINE_AUTO) {
+        if (!(worst <= 0.5 * prev)) {  // not halved (or not finite): GMRES takes over
+          to_gmres = true;
+          break;
+        }
+      } else {
+        if (!std::isfinite(worst)) break;
+        // stall: no halving over the last three iterations
+        if (it > 3 && worst > 0.5 * hist[0]) break;
+        hist[0] = hist[1];
+        hist[1] = hist[2];
+        hist[2] = worst;
+      }
+      prev = worst;
     }
-    if (!std::isfinite(worst)) break;
-    // stall: no halving over the last three iterations
-    if (it > 3 && worst > 0.5 * hist[0]) break;
-    hist[0] = hist[1];
-    hist[1] = hist[2];
-    hist[2] = worst;
+    loc.iterations = std::min(it, cap);
   }
-  loc.iterations = std::min(it, h->maxit);
-  loc.converged = conv ? 1 : 0;
-  if (!(best < INFINITY)) {  // no finite iterate: return the last one
-    loc.final_rel_residual = last;
-    HIP_TRY(h, launch_copy_cols<double, double>(x64, h->N, x, ldx, h->N, r, nullptr, false, s));
+  if (!conv && (mode == INVASKIT_REFINE_GMRES || to_gmres)) {
+    loc.method = INVASKIT_REFINE_GMRES;
+    if ((rc = ensure_gmres_space(h, sp))) return rc;
+    // restart from the best iterate
+    if (x_is_best_zero) {
+      HIP_TRY(h, launch_zero_cols(x64, N, N, r, s));
+      HIP_TRY(h, launch_copy_cols<double, double>(b, ldb, r64, N, N, r, nullptr, false, s));
+      rn = bn;
+    } else if (!last_is_best) {
+      HIP_TRY(h, launch_copy_cols<double, double>(x, ldx, x64, N, N, r, nullptr, false, s));
+      if ((rc = residual())) return rc;
+    }
+    std::vector<double> est_tol(r);
+    for (int c = 0; c < r; ++c) est_tol[c] = 0.1 * h->tol * std::sqrt(bn[c]);
+    double cyc_prev = worst_rel(rn, bn);
+    while (loc.gmres_iterations < h->gm_maxit) {
+      int steps = 0;
+      if ((rc = gmres_cycle(h, sp, mp, rn, est_tol, h->gm_maxit - loc.gmres_iterations, &steps)))
+        return rc;
+      loc.gmres_iterations += steps;
+      if ((rc = residual())) return rc;
+      const double worst = worst_rel(rn, bn);
+      if (mode == INVASKIT_REFINE_GMRES && loc.gmres_iterations == steps)
+        loc.unrefined_rel_residual = worst;
+      if ((rc = keep_if_best(worst))) return rc;
+      if (worst <= h->tol) {
+        conv = true;
+        break;
+      }
+      // a cycle that gains less than 10% (or made no step) ends the solve
+      if (steps == 0 || !(worst <= 0.9 * cyc_prev)) break;
+      cyc_prev = worst;
+    }
   }
+  if (x_is_best_zero) HIP_TRY(h, launch_zero_cols(x, ldx, N, r, s));
   HIP_TRY(h, hipStreamSynchronize(s));
+  loc.converged = conv ? 1 : 0;
+  loc.final_rel_residual = best;
   if (info) *info = loc;
   if (!conv)
     return fail_h(h, INVASKIT_E_NOT_CONVERGED,
-                  "refinement stopped after " + std::to_string(loc.iterations) +
-                      " iterations at relative residual " + std::to_string(loc.final_rel_residual));
+                  "refinement stopped after " + std::to_string(loc.iterations) + " steps and " +
+                      std::to_string(loc.gmres_iterations) +
+                      " GMRES steps at relative residual " + std::to_string(best));
   return INVASKIT_OK;
 }
 
@@ -1638,6 +1872,10 @@ int invaskit_default_options(invaskit_options* opt) {
   opt->leaf_lu_panel = 0;
   opt->leaf_lu_waves = 0;
   opt->leaf_trsm_cols = 0;
+  opt->refine = INVASKIT_REFINE_AUTO;
+  opt->gmres_restart = 20;
+  opt->max_gmres_iters = 300;
+  opt->reserved1 = 0;
   return INVASKIT_OK;
 }
 
@@ -1663,6 +1901,9 @@ int make_handle(const invaskit_problem* pb, double lambda, const invaskit_option
   h->fix_lu_panel = o.leaf_lu_panel;
   h->fix_lu_waves = o.leaf_lu_waves;
   h->fix_trsm_cols = o.leaf_trsm_cols;
+  h->refine = o.refine;
+  h->gm_restart = o.gmres_restart;
+  h->gm_maxit = o.max_gmres_iters;
   h->stream = static_cast<hipStream_t>(hip_stream);
   h->N = pb->n;
   h->d = pb->d;
@@ -1770,10 +2011,11 @@ int invaskit_device_bytes(invaskit_handle h, size_t* bytes) {
     t += b->bytes;
   for (auto& kv : h->solve_plans)
     for (const DevBuf* b : {&kv.second->tables, &kv.second->xbuf, &kv.second->sbuf,
-                            &kv.second->x64, &kv.second->r64, &kv.second->sc})
+                            &kv.second->x64, &kv.second->r64, &kv.second->sc, &kv.second->gpart,
+                            &kv.second->gsmall, &kv.second->gmV, &kv.second->gmZ})
       t += b->bytes;
   for (auto& kv : h->mv_plans)
-    for (const DevBuf* b : {&kv.second->tables, &kv.second->xm, &kv.second->q, &kv.second->nrm})
+    for (const DevBuf* b : {&kv.second->tables, &kv.second->xm, &kv.second->q})
       t += b->bytes;
   *bytes = t;
   return INVASKIT_OK;

@@ -42,7 +42,8 @@ __global__ void k_copy_cols(const TI* __restrict__ in, int64_t ldi, TO* __restri
     out[c * ldo + i] = (TO)((double)in[c * ldi + i] * s);
 }
 
-__global__ void k_axpy_cols(double* __restrict__ x, int64_t ldx, const float* __restrict__ d,
+template <typename TD>
+__global__ void k_axpy_cols(double* __restrict__ x, int64_t ldx, const TD* __restrict__ d,
                             int64_t ldd, int64_t n, const double* __restrict__ scale) {
   const int c = blockIdx.y;
   const double s = scale[c];
@@ -65,6 +66,71 @@ __global__ __launch_bounds__(256) void k_colsumsq(const double* __restrict__ v, 
   if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
   __syncthreads();
   if (threadIdx.x == 0) atomicAdd(out + c, part[0] + part[1] + part[2] + part[3]);
+}
+
+// Multi-dot, first pass: the rows of column c are cut into nblk chunks;
+// block (b, c, k) sums V_k[i, c] * w[i, c] over chunk b and writes
+// part[(k * ncols + c) * nblk + b].  V_k = V + k * vstride, column c at
+// + c * ldv.  The four waves' sums are added in a fixed order, so the result
+// does not depend on scheduling.
+__global__ __launch_bounds__(256) void k_dots_part(const double* __restrict__ V, int64_t vstride,
+                                                   int64_t ldv, const double* __restrict__ w,
+                                                   int64_t ldw, int64_t n, int64_t chunk,
+                                                   double* __restrict__ part) {
+  __shared__ double wsum[4];
+  const int b = blockIdx.x, c = blockIdx.y, k = blockIdx.z;
+  const int nblk = gridDim.x, ncols = gridDim.y;
+  const double* __restrict__ v = V + k * vstride + c * ldv;
+  const double* __restrict__ x = w + c * ldw;
+  const int64_t i1 = min(n, (int64_t)(b + 1) * chunk);
+  double acc = 0.0;
+  for (int64_t i = (int64_t)b * chunk + threadIdx.x; i < i1; i += 256) acc = fma(v[i], x[i], acc);
+  for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    part[((int64_t)k * ncols + c) * nblk + b] = (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
+}
+
+// Multi-dot, second pass: out[t] = sum over b of part[t * nblk + b], in order.
+__global__ void k_dots_sum(const double* __restrict__ part, int nblk, int count,
+                           double* __restrict__ out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= count) return;
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s += part[(int64_t)t * nblk + b];
+  out[t] = s;
+}
+
+// out[i, c] += alpha * sum_k coef[k * ncols + c] * V_k[i, c]
+__global__ void k_lincomb(double* __restrict__ out, int64_t ldo, const double* __restrict__ V,
+                          int64_t vstride, int64_t ldv, int nk, const double* __restrict__ coef,
+                          double alpha, int64_t n) {
+  const int c = blockIdx.y, ncols = gridDim.y;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int k = 0; k < nk; ++k) acc = fma(coef[k * ncols + c], V[k * vstride + c * ldv + i], acc);
+    out[c * ldo + i] += alpha * acc;
+  }
+}
+
+// v[i, c] *= scale[c], in place
+__global__ void k_scale_cols(double* __restrict__ v, int64_t ld, int64_t n,
+                             const double* __restrict__ scale) {
+  const int c = blockIdx.y;
+  const double s = scale[c];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    v[c * ld + i] *= s;
+}
+
+// v[i, c] = 0
+__global__ void k_zero_cols(double* __restrict__ v, int64_t ld, int64_t n) {
+  const int c = blockIdx.y;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    v[c * ld + i] = 0.0;
 }
 
 __global__ void k_zero(unsigned char* __restrict__ p, size_t bytes) {
@@ -117,13 +183,18 @@ template hipError_t launch_copy_cols<float, double>(const float*, int64_t, doubl
                                                     int64_t, int, const double*, bool,
                                                     hipStream_t);
 
-hipError_t launch_axpy_cols(double* x, int64_t ldx, const float* d, int64_t ldd, int64_t n,
+template <typename TD>
+hipError_t launch_axpy_cols(double* x, int64_t ldx, const TD* d, int64_t ldd, int64_t n,
                             int ncols, const double* scale, hipStream_t s) {
   if (n <= 0 || ncols <= 0) return hipSuccess;
   const int g = (grid_for(n) + ncols - 1) / ncols + 1;
-  hipLaunchKernelGGL(k_axpy_cols, dim3(g, ncols), dim3(256), 0, s, x, ldx, d, ldd, n, scale);
+  hipLaunchKernelGGL(k_axpy_cols<TD>, dim3(g, ncols), dim3(256), 0, s, x, ldx, d, ldd, n, scale);
   return hipGetLastError();
 }
+template hipError_t launch_axpy_cols<float>(double*, int64_t, const float*, int64_t, int64_t, int,
+                                            const double*, hipStream_t);
+template hipError_t launch_axpy_cols<double>(double*, int64_t, const double*, int64_t, int64_t,
+                                             int, const double*, hipStream_t);
 
 hipError_t launch_colsumsq(const double* v, int64_t ld, int64_t n, int ncols, double* out,
                            hipStream_t s) {
@@ -132,6 +203,58 @@ hipError_t launch_colsumsq(const double* v, int64_t ld, int64_t n, int ncols, do
   if (e != hipSuccess || n <= 0) return e;
   const int g = (grid_for(n) + ncols - 1) / ncols + 1;
   hipLaunchKernelGGL(k_colsumsq, dim3(g, ncols), dim3(256), 0, s, v, ld, n, out);
+  return hipGetLastError();
+}
+
+int dots_blocks(int64_t n) {
+  int64_t nb = (n + 4095) / 4096;
+  if (nb > 256) nb = 256;
+  if (nb < 1) nb = 1;
+  return (int)nb;
+}
+
+size_t dots_part_doubles(int64_t n, int nk, int ncols) {
+  return (size_t)dots_blocks(n) * nk * ncols;
+}
+
+hipError_t launch_dots(const double* V, int64_t vstride, int64_t ldv, int nk, const double* w,
+                       int64_t ldw, int64_t n, int ncols, double* part, double* out,
+                       hipStream_t s) {
+  if (nk <= 0 || ncols <= 0) return hipSuccess;
+  const int nblk = dots_blocks(n);
+  const int64_t chunk = (n + nblk - 1) / nblk;
+  hipLaunchKernelGGL(k_dots_part, dim3(nblk, ncols, nk), dim3(256), 0, s, V, vstride, ldv, w,
+                     ldw, n, chunk, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int count = nk * ncols;
+  hipLaunchKernelGGL(k_dots_sum, dim3((count + 255) / 256), dim3(256), 0, s, part, nblk, count,
+                     out);
+  return hipGetLastError();
+}
+
+hipError_t launch_lincomb(double* out, int64_t ldo, const double* V, int64_t vstride,
+                          int64_t ldv, int nk, const double* coef, int ncols, double alpha,
+                          int64_t n, hipStream_t s) {
+  if (nk <= 0 || ncols <= 0 || n <= 0) return hipSuccess;
+  const int g = (grid_for(n) + ncols - 1) / ncols + 1;
+  hipLaunchKernelGGL(k_lincomb, dim3(g, ncols), dim3(256), 0, s, out, ldo, V, vstride, ldv, nk,
+                     coef, alpha, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_cols(double* v, int64_t ld, int64_t n, int ncols, const double* scale,
+                             hipStream_t s) {
+  if (n <= 0 || ncols <= 0) return hipSuccess;
+  const int g = (grid_for(n) + ncols - 1) / ncols + 1;
+  hipLaunchKernelGGL(k_scale_cols, dim3(g, ncols), dim3(256), 0, s, v, ld, n, scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_cols(double* v, int64_t ld, int64_t n, int ncols, hipStream_t s) {
+  if (n <= 0 || ncols <= 0) return hipSuccess;
+  const int g = (grid_for(n) + ncols - 1) / ncols + 1;
+  hipLaunchKernelGGL(k_zero_cols, dim3(g, ncols), dim3(256), 0, s, v, ld, n);
   return hipGetLastError();
 }
 

@@ -157,17 +157,34 @@ def test_bad_options_rejected(small_problem):
         opt.leaf_lu_waves = v
         st, msg = _factor_status(raw, opt=opt)
         assert st == -1 and "leaf_lu_waves" in msg, v
+    binding.library().invaskit_default_options(C.byref(opt))
+    assert opt.refine == binding.REFINE["auto"] and opt.gmres_restart == 20
+    assert opt.max_gmres_iters == 300
+    for field, v, word in (("refine", 4, "refine"), ("refine", -1, "refine"),
+                           ("gmres_restart", 1, "gmres_restart"),
+                           ("gmres_restart", 65, "gmres_restart"),
+                           ("max_gmres_iters", 0, "max_gmres_iters")):
+        binding.library().invaskit_default_options(C.byref(opt))
+        setattr(opt, field, v)
+        st, msg = _factor_status(raw, opt=opt)
+        assert st == -1 and word in msg, (field, v)
 
 
 def test_options_struct_layout():
-    """The binding's mirror of invaskit_options has the header's size and
-    field offsets (4 + 4 + 8 + 5 x 4 bytes, padded to 40)."""
+    """The binding's mirrors of invaskit_options and invaskit_solve_info have
+    the header's sizes and field offsets (options: 4 + 4 + 8 + 9 x 4 bytes,
+    padded to 56)."""
     from paper_1602_01376_amd import binding
     O = binding._Options
-    assert C.sizeof(O) == 40
+    assert C.sizeof(O) == 56
     assert O.refine_tol.offset == 8 and O.max_refine_iters.offset == 16
     assert O.tune.offset == 20 and O.leaf_lu_panel.offset == 24
     assert O.leaf_trsm_cols.offset == 28 and O.leaf_lu_waves.offset == 32
+    assert O.refine.offset == 36 and O.gmres_restart.offset == 40
+    assert O.max_gmres_iters.offset == 44
+    S = binding.SolveInfo
+    assert C.sizeof(S) == 32 and S.final_rel_residual.offset == 8
+    assert S.gmres_iterations.offset == 24 and S.method.offset == 28
     T = binding._TileConfig
     assert C.sizeof(T) == 40 and T.lu_ms.offset == 16 and T.trsm_ms.offset == 32
 

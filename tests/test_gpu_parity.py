@@ -432,8 +432,8 @@ def test_refinement_that_stops_short_returns_its_best_iterate(bind, problems):
     pb, F = problems("susy", dict(n=8192, depth=5))
     b = rhs_for(pb, nrhs=2)
     x_ref = oracle.solve(F, b)
-    for kw, iters in ((dict(max_refine_iters=1, refine_tol=1e-12), 1),
-                      (dict(refine_tol=1e-30), None)):
+    for kw, iters in ((dict(max_refine_iters=1, refine_tol=1e-12, refine="ir"), 1),
+                      (dict(refine_tol=1e-30, refine="ir"), None)):
         fac = bind.Factorization(pb, pb.lam, precision="mixed", **kw)
         x, info, st = fac.solve(torch.from_numpy(b), return_info=True, check=False)
         _say("  ", kw, info)
@@ -463,3 +463,99 @@ def test_singular_leaf_is_reported(bind):
         bind.Factorization(pb, 0.0)
     assert ei.value.status == bind.E_SINGULAR
     assert "node 3" in str(ei.value)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_auto_refinement_that_cannot_converge_reports_it(bind, problems, prec):
+    """A tolerance below FP64 rounding, forced from the host: both precisions
+    (FP64's direct solve included) report E_NOT_CONVERGED with converged = 0,
+    after plain refinement stops halving and GMRES gains nothing more, and
+    return their best iterate, whose residual the oracle's product bounds."""
+    _say("auto refinement below rounding", prec)
+    pb, F = problems("susy", dict(n=8192, depth=5))
+    b = rhs_for(pb, nrhs=2)
+    fac = bind.Factorization(pb, pb.lam, precision=prec, refine_tol=1e-30, max_gmres_iters=40)
+    x, info, st = fac.solve(torch.from_numpy(b), return_info=True, check=False)
+    _say("  ", info)
+    assert st == bind.E_NOT_CONVERGED and info["converged"] == 0
+    assert info["method"] == "gmres" and 1 <= info["gmres_iterations"] <= 40
+    assert info["final_rel_residual"] <= 1e-12
+    assert _col_residual(pb, pb.lam, x.cpu().numpy(), b) <= 1e-12
+    fac.close()
+
+
+def test_fp64_direct_solve_reports_its_residual(bind, problems):
+    """refine = "none": one direct FP64 solve.  With info requested its
+    residual is measured and `converged` says whether it meets refine_tol;
+    a tolerance it cannot meet returns E_NOT_CONVERGED."""
+    _say("fp64 direct solve")
+    pb, F = problems("susy", dict(n=8192, depth=5))
+    b = rhs_for(pb, nrhs=2)
+    x_ref = oracle.solve(F, b)
+    fac = bind.Factorization(pb, pb.lam, precision="fp64", refine="none")
+    x = fac.solve(torch.from_numpy(b)).cpu().numpy()
+    _assert_close(x, x_ref, 1e-10, "no info")
+    x, info, st = fac.solve(torch.from_numpy(b), return_info=True)
+    assert st == 0 and info["converged"] == 1 and info["iterations"] == 1
+    assert info["method"] == "none" and info["final_rel_residual"] <= 1e-12
+    assert info["final_rel_residual"] == info["unrefined_rel_residual"]
+    fac.close()
+    fac = bind.Factorization(pb, pb.lam, precision="fp64", refine="none", refine_tol=1e-30)
+    x, info, st = fac.solve(torch.from_numpy(b), return_info=True, check=False)
+    assert st == bind.E_NOT_CONVERGED and info["converged"] == 0
+    _assert_close(x.cpu().numpy(), x_ref, 1e-10, "tolerance below rounding")
+    fac.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_gmres_refinement_matches_oracle(bind, problems, prec):
+    """refine = "gmres": flexible GMRES from x = 0, preconditioned by the
+    factors, on the uneven-leaf workload with three right-hand sides."""
+    _say("gmres refinement", prec)
+    pb, F = problems("susy", dict(n=8192, depth=5))
+    b = rhs_for(pb, nrhs=3)
+    x_ref = oracle.solve(F, b)
+    fac = bind.Factorization(pb, pb.lam, precision=prec, refine="gmres", gmres_restart=8)
+    x, info, st = fac.solve(torch.from_numpy(b), return_info=True)
+    _say("  ", info)
+    assert st == 0 and info["converged"] == 1 and info["method"] == "gmres"
+    assert info["iterations"] == 0 and info["gmres_iterations"] >= 1
+    x = x.cpu().numpy()
+    assert _col_residual(pb, pb.lam, x, b) <= 1e-10
+    _assert_close(x, x_ref, 1e-9 if prec == "fp64" else 1e-7)
+    fac.close()
+
+
+def test_ill_conditioned_784_dimensional_workload(bind):
+    """The image-like workload (d = 784, FP32 points, leaves of 512,
+    s = 256, h = 4, lambda = 1e-2) at N = 16,384: the recursive solve is
+    not accurate to 1e-10 here even in FP64 (the oracle's own direct
+    residual is about 4e-10), so both GPU paths must refine.  The oracle's
+    solution is refined the classical way with its own solve and product
+    (two steps bring it to about 1e-12).  Both GPU paths must reach an
+    oracle-measured residual <= 1e-10 and agree with the refined oracle
+    solution to within kappa times that residual."""
+    _say("ill-conditioned d = 784 workload, N = 16384")
+    pb = make_problem("mnist", n=16384, depth=5)
+    F = oracle.factorize(pb, pb.lam)
+    b = rhs_for(pb, nrhs=1)
+    x_ref = oracle.solve(F, b)
+    for _ in range(2):
+        x_ref = x_ref + oracle.solve(F, b - oracle.matvec(pb, pb.lam, x_ref))
+    res_ref = _col_residual(pb, pb.lam, x_ref, b)
+    _say("  refined oracle residual", res_ref)
+    assert res_ref <= 1e-11
+    for prec in ("fp64", "mixed"):
+        fac = bind.Factorization(pb, pb.lam, precision=prec)
+        x, info, st = fac.solve(torch.from_numpy(b), return_info=True)
+        _say("  ", prec, info)
+        assert st == 0 and info["converged"] == 1
+        x = x.cpu().numpy()
+        res = _col_residual(pb, pb.lam, x, b)
+        _say("  oracle-measured residual", res)
+        assert res <= 1e-10
+        # kappa(lambda I + K~) is about 1e4 at this size (lambda = 1e-2 against
+        # |K| of about 2e3): x agrees with the refined oracle to kappa * 1e-10
+        _assert_close(x, x_ref, 1e-5, prec)
+        fac.close()
+
