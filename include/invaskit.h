@@ -22,6 +22,12 @@
  *    calls that must read results back (factor: pivot status; solve: refine
  *    residuals) synchronize that stream before returning.
  *  - One handle may be used by one host thread at a time.
+ *  - The library allocates no device memory.  The caller allocates a
+ *    factorization's workspace (size: invaskit_factor_workspace_bytes) and
+ *    a solve's or product's scratch (invaskit_solve_workspace_bytes,
+ *    invaskit_matvec_workspace_bytes), all DEVICE, 256-byte aligned, and
+ *    frees them after the handle is destroyed.  A workspace or scratch that
+ *    is too small fails with INVASKIT_E_WORKSPACE before any launch.
  */
 #ifndef INVASKIT_H
 #define INVASKIT_H
@@ -36,7 +42,8 @@ extern "C" {
 /* status codes */
 #define INVASKIT_OK               0
 #define INVASKIT_E_ARG           -1 /* invalid argument; nothing was launched  */
-#define INVASKIT_E_MEMORY        -2 /* device allocation failed                */
+#define INVASKIT_E_WORKSPACE     -2 /* workspace or scratch too small; nothing
+                                       was launched                            */
 #define INVASKIT_E_HIP           -3 /* a HIP runtime call failed               */
 #define INVASKIT_E_SINGULAR      -4 /* zero or non-finite pivot (node named)   */
 #define INVASKIT_E_NOT_CONVERGED -5 /* refinement stalled or hit its cap       */
@@ -60,14 +67,16 @@ extern "C" {
  *                invaskit_destroy(), because solve/matvec re-read it.
  *  leaf_offsets  HOST, 2^L + 1 entries: leaf j owns points
  *                [leaf_offsets[j], leaf_offsets[j+1]); [0] = 0, last = n,
- *                every leaf non-empty and at most 4096 points.  Copied.
+ *                every leaf non-empty and at most 1024 points.  Copied.
  *  skel_offsets  HOST, 2^(L+1) entries (n_nodes + 1): node c's skeleton is
  *                skel_index[skel_offsets[c] .. skel_offsets[c+1]).  The root
- *                has none; every other node has 1..1024 skeleton points.
+ *                has none; every other node has 1..512 skeleton points.
  *                Copied.
  *  skel_index    HOST, tree-order point ids.  A leaf's skeleton lies in the
  *                leaf; an internal node's skeleton is a subset of its
- *                children's skeletons (nested skeletons).  Copied.
+ *                children's skeletons (nested skeletons).  HOST because the
+ *                nesting is checked before any launch; copied into the
+ *                workspace.
  *  p_offsets     HOST, n_nodes + 1 entries into p_values.  Copied.
  *  p_values      DEVICE, FP64.  Leaf c: P_{c~ c}, s_c x |c| row-major, columns
  *                in the leaf's point order.  Internal c: P_{c~ [l~ r~]},
@@ -134,7 +143,8 @@ typedef struct invaskit_options {
   int32_t refine;           /* INVASKIT_REFINE_* (default AUTO)                   */
   int32_t gmres_restart;    /* Krylov vectors per GMRES cycle, 2..64 (default 20) */
   int32_t max_gmres_iters;  /* cap on GMRES steps over all cycles (default 300)  */
-  int32_t reserved1;
+  int32_t lambda_group;     /* invaskit_factor_sweep: lambdas per batched launch
+                               (0, the default: all of them)                      */
 } invaskit_options;
 
 /*
@@ -190,6 +200,18 @@ typedef struct invaskit_handle_s* invaskit_handle;
 int invaskit_default_options(invaskit_options* opt);
 
 /*
+ * Workspace of a factorization, in bytes: n_lambda = 0 for
+ * invaskit_factor, n_lambda >= 1 for invaskit_factor_sweep with that many
+ * lambdas (options->lambda_group as it will be passed).  Host only: plans
+ * the layout (the factors, W storage, reduced systems, skeleton sweep
+ * blocks, descriptor tables) without touching the device.  Same argument
+ * checks as invaskit_factor.
+ */
+int invaskit_factor_workspace_bytes(const invaskit_problem* problem,
+                                    const invaskit_options* options, int32_t n_lambda,
+                                    size_t* bytes);
+
+/*
  * Factor lambda*I + K~ (Algorithm 1, Factorize, done level by level
  * bottom-up): LU with partial pivoting of every leaf block
  * lambda*I + K_{aa}; for every level k = L..1 the skeleton blocks
@@ -198,74 +220,98 @@ int invaskit_default_options(invaskit_options* opt);
  * [[I, P_{r~r} W_{r l~}], [P_{l~l} W_{l r~}, I]] of eq. (11) and
  * their LU.  lambda enters only the leaf diagonal blocks.
  *
- * Validates every input on the host before any launch (E_ARG).  Allocates
- * the factorization's device memory itself (its size: invaskit_device_bytes);
- * the handle owns it until invaskit_destroy().  hip_stream may be NULL (the
- * null stream).  Part of the work runs on a second stream the handle owns
- * (default priority), ordered after everything already enqueued on
- * hip_stream and joined back into it before the factor's end.  Synchronizes
- * the stream once at the end to read the pivot status: a zero or
- * non-finite pivot returns E_SINGULAR, names the node in
- * invaskit_last_error(), and still returns the handle in *out.
+ * workspace: DEVICE, ws_bytes >= invaskit_factor_workspace_bytes(problem,
+ * options, 0), 256-byte aligned.  The handle keeps its factors and
+ * descriptor tables there: the caller must leave it untouched and allocated
+ * until invaskit_destroy().  Validates every input on the host before any
+ * launch (E_ARG, E_WORKSPACE).  hip_stream may be NULL (the null stream).
+ * Part of the work runs on a second stream the handle owns (default
+ * priority), ordered after everything already enqueued on hip_stream and
+ * joined back into it before the factor's end.  Synchronizes the stream
+ * once at the end to read the pivot status: a zero or non-finite pivot
+ * returns E_SINGULAR, names the node in invaskit_last_error(), and still
+ * returns the handle in *out.
  */
 int invaskit_factor(const invaskit_problem* problem, double lambda,
-                    const invaskit_options* options, void* hip_stream,
-                    invaskit_handle* out);
+                    const invaskit_options* options, void* workspace, size_t ws_bytes,
+                    void* hip_stream, invaskit_handle* out);
 
 /*
  * Factor lambda_i I + K~ for n_lambda values of lambda (Section II-C: only
  * the leaf LU, W and the reduced systems depend on lambda).  The kernel
  * blocks -- the leaf blocks K_aa and the skeleton blocks of every level --
- * are evaluated once, without lambda, and reused for every lambda (and by
- * invaskit_refactor on these handles); lambda_i is added to the leaf
- * diagonals.  out[i] receives the handle for lambdas[i]; each owns its
- * factors (invaskit_device_bytes) and the handles share the evaluated
- * blocks (leaf blocks plus skeleton blocks, the size of one handle's leaf
- * factors and W storage), which are freed with the last of them.
- * Arguments, streams and errors as invaskit_factor; every lambda is
- * validated before any work.  Returns the first non-OK status; a handle
- * whose factorization reported E_SINGULAR is still returned, but if a
- * handle cannot be created at all, the ones already made are destroyed and
- * every out[i] is NULL.
+ * are evaluated once, without lambda, into the workspace and shared: each
+ * lambda's leaf blocks are copied from them with lambda_i on the diagonal,
+ * and its leaf solves read the skeleton blocks from them.  The lambdas are
+ * factored in batches of options->lambda_group (0: all at once): every
+ * launch of a batch covers all of its lambdas (their leaf LUs in one LU
+ * launch, and so on).  out[i] receives the handle for lambdas[i].
+ * workspace: ws_bytes >= invaskit_factor_workspace_bytes(problem, options,
+ * n_lambda), owned as for invaskit_factor until every handle of the sweep
+ * is destroyed.  Arguments, streams and errors as invaskit_factor; every
+ * lambda is validated before any work.  Returns the first non-OK status; a
+ * handle whose factorization reported E_SINGULAR is still returned, but on
+ * any other error no handle is returned (every out[i] is NULL).
  */
 int invaskit_factor_sweep(const invaskit_problem* problem, const double* lambdas,
-                          int32_t n_lambda, const invaskit_options* options, void* hip_stream,
-                          invaskit_handle* out);
+                          int32_t n_lambda, const invaskit_options* options, void* workspace,
+                          size_t ws_bytes, void* hip_stream, invaskit_handle* out);
 
 /*
  * Refactor an existing handle for a new lambda (Section II-C, refactoring
  * for a different lambda): skeletons and P are reused, leaf LU, W and the
- * reduced systems are recomputed.  Same errors as invaskit_factor.
+ * reduced systems are recomputed in the handle's workspace.  A handle of a
+ * sweep starts from the sweep's shared kernel blocks (no evaluation).  Same
+ * errors as invaskit_factor.
  */
 int invaskit_refactor(invaskit_handle handle, double lambda);
 
 /*
- * x = (lambda*I + K~)^-1 b (Algorithm 2, Solve, done bottom-up).
- * b, x: DEVICE, FP64, n x nrhs column-major with leading dimensions
- * ldb, ldx >= n; they must not overlap.  In mixed mode the solve is
- * iterative refinement: FP32 solves against the FP32 factors, residuals
- * b - (lambda*I + K~) x by the FP64 hierarchical product (invaskit_matvec),
- * FP64 updates, until every column satisfies refine_tol; E_NOT_CONVERGED if
- * the cap is hit or the residual stops halving over three iterations (x
- * then holds the iterate with the smallest residual, worst column, and
- * info->final_rel_residual that residual).  In FP64 mode the solve is
- * direct and info->final_rel_residual is computed with the same FP64
- * product.  info may be NULL.
+ * Scratch of invaskit_solve with nrhs right-hand sides, in bytes: *bytes
+ * includes the GMRES bases (gmres_restart + 1 and gmres_restart vectors of
+ * n x nrhs FP64), *min_bytes (may be NULL) leaves them out.  invaskit_solve
+ * accepts any size from *min_bytes up; GMRES then runs with the longest
+ * restart that fits (at least 2), or not at all (refine = GMRES then fails
+ * with E_WORKSPACE; AUTO stops where plain refinement stops).  Host only.
+ */
+int invaskit_solve_workspace_bytes(invaskit_handle handle, int64_t nrhs, size_t* bytes,
+                                   size_t* min_bytes);
+
+/*
+ * x = (lambda*I + K~)^-1 b (Algorithm 2, Solve, done bottom-up), refined
+ * per options->refine (see Refinement modes) until every column satisfies
+ * refine_tol.  b, x: DEVICE, FP64, n x nrhs column-major with leading
+ * dimensions ldb, ldx >= n; they must not overlap.  E_NOT_CONVERGED if the
+ * refinement stops short: x then holds the iterate with the smallest
+ * residual (worst column) and info->final_rel_residual that residual.
+ * scratch: DEVICE, 256-byte aligned, scratch_bytes as described under
+ * invaskit_solve_workspace_bytes, not overlapping b or x.  The first bytes of
+ * scratch receive the solve's descriptor tables, which a later call with the
+ * same handle, nrhs and scratch pointer reuses without copying them again:
+ * between such calls nothing else may write to that scratch (use another
+ * buffer for other handles and for invaskit_matvec).  info may be NULL.
  */
 int invaskit_solve(invaskit_handle handle, const double* b, int64_t nrhs, int64_t ldb,
-                   double* x, int64_t ldx, invaskit_solve_info* info);
+                   double* x, int64_t ldx, void* scratch, size_t scratch_bytes,
+                   invaskit_solve_info* info);
+
+/* Scratch of invaskit_matvec with nrhs columns, in bytes.  Host only. */
+int invaskit_matvec_workspace_bytes(invaskit_handle handle, int64_t nrhs, size_t* bytes);
 
 /*
  * y = (lambda*I + K~) x in FP64, by the ASKIT Skeletonize upward pass and
  * the Evaluate traversal with separation "i not in node" (Section II-B):
  * exact leaf blocks plus K_{i, c~} P_{c~ c} x_c for every node c that
  * does not contain i but whose parent does.  x, y: DEVICE FP64,
- * n x nrhs column-major, must not overlap.
+ * n x nrhs column-major, must not overlap.  scratch: DEVICE, 256-byte
+ * aligned, scratch_bytes >= invaskit_matvec_workspace_bytes; its descriptor
+ * tables are reused as for invaskit_solve.
  */
 int invaskit_matvec(invaskit_handle handle, const double* x, int64_t nrhs, int64_t ldx,
-                    double* y, int64_t ldy);
+                    double* y, int64_t ldy, void* scratch, size_t scratch_bytes);
 
-/* Device bytes held by the handle (factors, tables, scratch). */
+/* Bytes of the workspace the handle's own buffers span (for a handle of a
+ * sweep: its region, without the shared kernel blocks). */
 int invaskit_device_bytes(invaskit_handle handle, size_t* bytes);
 
 /*
@@ -274,8 +320,8 @@ int invaskit_device_bytes(invaskit_handle handle, size_t* bytes);
  * not add up to the total): [0] leaf block evaluation, [1] leaf LU, [2]
  * inverses of the factors' 64 x 64 diagonal blocks (leaves), [3] skeleton
  * blocks, [4] leaf solves, [5] leaf projections, [6] skeleton sweep, [7]
- * host planning and allocation of the handle when it was created (wall
- * clock; not part of [9], the same on every refactor), [8] reduced systems
+ * host planning of the handle (descriptor tables built and uploaded; wall
+ * clock; not part of [9]), [8] reduced systems
  * (assembly, LU, diagonal-block inverses), [9] total.
  * Writes min(n, 10) values.
  */
@@ -308,7 +354,8 @@ int invaskit_tuning_export(char* buf, size_t n, size_t* needed);
 int invaskit_tuning_import(const char* text);
 int invaskit_tuning_clear(void);
 
-/* Release the handle and its device memory.  Borrowed buffers are untouched. */
+/* Release the handle (host memory, its second stream and events).  The
+ * caller's workspace and borrowed buffers are untouched. */
 int invaskit_destroy(invaskit_handle handle);
 
 /* Static text for a status code. */
@@ -320,8 +367,12 @@ int invaskit_last_error(invaskit_handle handle, char* buf, size_t n);
 
 /* ---------------------------------------------------------------------------
  * Batched building blocks, exposed for unit testing and for callers that
- * assemble their own hierarchy.  All run on `hip_stream` and return after
- * enqueueing (no synchronization) unless noted.
+ * assemble their own hierarchy.  Each takes a DEVICE workspace for its
+ * descriptor tables (and, for the solves, the diagonal-block inverses):
+ * called with workspace == NULL it only stores the bytes it needs in
+ * *ws_needed and launches nothing; otherwise ws_bytes must be at least that
+ * (E_WORKSPACE), and ws_needed may be NULL.  All run on `hip_stream` and
+ * synchronize it before returning.
  * ------------------------------------------------------------------------- */
 
 /*
@@ -343,35 +394,42 @@ int invaskit_last_error(invaskit_handle handle, char* buf, size_t n);
  */
 int invaskit_getrf_batched(int32_t dtype, void* a, const int64_t* a_offsets,
                            const int32_t* n, int32_t count, int32_t* perm,
-                           int32_t* info, void* hip_stream);
+                           int32_t* info, void* workspace, size_t ws_bytes,
+                           size_t* ws_needed, void* hip_stream);
 
 /*
  * Solve A_i X_i = B_i in place with the row-major factors of
  * invaskit_getrf_batched (row permutation, unit-lower L, upper U); the
- * inverses of the factors' 64 x 64 diagonal blocks are formed first.  b: DEVICE, element type dtype;
- * system i has nrhs[i] columns with leading dimension ldb[i] >= n[i] and
- * starts at element b_offsets[i].  a_offsets, n, nrhs, ldb, b_offsets: HOST.
+ * inverses of the factors' 64 x 64 diagonal blocks are formed first, in the
+ * workspace.  b: DEVICE, element type dtype; system i has nrhs[i] columns
+ * with leading dimension ldb[i] >= n[i] and starts at element b_offsets[i].
+ * a_offsets, n, nrhs, ldb, b_offsets: HOST.
  */
 int invaskit_getrs_batched(int32_t dtype, const void* a, const int64_t* a_offsets,
                            const int32_t* n, const int32_t* perm, void* b,
                            const int64_t* b_offsets, const int32_t* nrhs,
-                           const int64_t* ldb, int32_t count, void* hip_stream);
+                           const int64_t* ldb, int32_t count, void* workspace,
+                           size_t ws_bytes, size_t* ws_needed, void* hip_stream);
 
 /*
  * Gaussian kernel blocks (eq. (1)): out_i[r, c] =
  * K(x[row0_i + r], x[col_i(c)]) + (diag_i && r == c ? shift : 0), where
- * col_i(c) = cols[cols_offsets[i] + c].  Squared distances are formed by
- * direct differences in FP64.  points: DEVICE n x d row-major of
- * points_dtype; cols: DEVICE int32; out: DEVICE element type out_dtype,
- * block i is rows_i x ncols_i column-major (ld = rows_i) at element
- * out_offsets[i].  All other arrays HOST, count entries.
+ * col_i(c) = cols[cols_offsets[i] + c].  For d <= 64 the squared distances
+ * are direct differences in FP64; for d > 64 they come from the Gram form
+ * |x'|^2 + |y'|^2 - 2 x'.y' on the FP64 matrix cores, with x' and y'
+ * shifted by the tile's first row point (a point against itself gets
+ * exactly 0).  points: DEVICE n x d row-major of points_dtype; cols: DEVICE
+ * int32; out: DEVICE element type out_dtype, block i is rows_i x ncols_i
+ * column-major (ld = rows_i) at element out_offsets[i].  All other arrays
+ * HOST, count entries.
  */
 int invaskit_kernel_blocks(int32_t points_dtype, const void* points, int32_t d, double h,
                            int32_t out_dtype, void* out, const int64_t* out_offsets,
                            const int64_t* row0, const int32_t* rows,
                            const int32_t* cols, const int64_t* cols_offsets,
                            const int32_t* ncols, const int32_t* diag, double shift,
-                           int32_t count, void* hip_stream);
+                           int32_t count, void* workspace, size_t ws_bytes,
+                           size_t* ws_needed, void* hip_stream);
 
 /*
  * Grouped GEMM on the matrix cores, C_i = beta*C_i + alpha*A_i B_i for
@@ -382,13 +440,13 @@ int invaskit_kernel_blocks(int32_t points_dtype, const void* points, int32_t d, 
  * != 0, lda = row stride); B_i is k[i] x n[i] column-major (ldb[i]); C_i is
  * m[i] x n[i] column-major (ldc[i]); element offsets a_off, b_off, c_off.
  * beta == 0 never reads C.  All size arrays HOST, count entries.
- * Synchronizes the stream before returning.
  */
 int invaskit_gemm_batched(int32_t dtype, const void* a, const void* b, void* c,
                           const int64_t* a_off, const int64_t* b_off, const int64_t* c_off,
                           const int32_t* m, const int32_t* n, const int32_t* k,
                           const int64_t* lda, const int32_t* a_rowmajor, const int64_t* ldb,
                           const int64_t* ldc, double alpha, double beta, int32_t count,
+                          void* workspace, size_t ws_bytes, size_t* ws_needed,
                           void* hip_stream);
 
 #ifdef __cplusplus

@@ -2,8 +2,10 @@
 
 Argument marshalling only: every step of the factorization, solve and
 product runs in the library's HIP kernels.  PyTorch supplies device memory
-and the current HIP stream.  Importing this module loads the library and
-fails loudly if it has not been built.
+(the factor workspace, solve and product scratch, building-block workspaces:
+uint8 tensors sized by the library's *_workspace_bytes queries) and the
+current HIP stream.  Importing this module loads the library and fails
+loudly if it has not been built.
 """
 from __future__ import annotations
 
@@ -16,7 +18,7 @@ import torch
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libinvaskit.so")
 
 OK = 0
-E_ARG, E_MEMORY, E_HIP, E_SINGULAR, E_NOT_CONVERGED, E_DEVICE = -1, -2, -3, -4, -5, -6
+E_ARG, E_WORKSPACE, E_HIP, E_SINGULAR, E_NOT_CONVERGED, E_DEVICE = -1, -2, -3, -4, -5, -6
 F64, F32 = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
 
@@ -41,7 +43,7 @@ class _Options(C.Structure):
                 ("tune", C.c_int32), ("leaf_lu_panel", C.c_int32),
                 ("leaf_trsm_cols", C.c_int32), ("leaf_lu_waves", C.c_int32),
                 ("refine", C.c_int32), ("gmres_restart", C.c_int32),
-                ("max_gmres_iters", C.c_int32), ("reserved1", C.c_int32)]
+                ("max_gmres_iters", C.c_int32), ("lambda_group", C.c_int32)]
 
 
 TUNE_AUTO, TUNE_OFF = 0, 1
@@ -71,14 +73,18 @@ def _load():
                           "`python -m paper_1602_01376_amd.build` (hipcc, gfx950)")
     lib = C.CDLL(_LIB_PATH)
     vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    sz, szp = C.c_size_t, C.POINTER(C.c_size_t)
     sig = {
         "invaskit_default_options": (C.c_int, [vp]),
-        "invaskit_factor": (C.c_int, [vp, dbl, vp, vp, vp]),
-        "invaskit_factor_sweep": (C.c_int, [vp, vp, i32, vp, vp, vp]),
+        "invaskit_factor_workspace_bytes": (C.c_int, [vp, vp, i32, szp]),
+        "invaskit_factor": (C.c_int, [vp, dbl, vp, vp, sz, vp, vp]),
+        "invaskit_factor_sweep": (C.c_int, [vp, vp, i32, vp, vp, sz, vp, vp]),
         "invaskit_refactor": (C.c_int, [vp, dbl]),
-        "invaskit_solve": (C.c_int, [vp, vp, i64, i64, vp, i64, vp]),
-        "invaskit_matvec": (C.c_int, [vp, vp, i64, i64, vp, i64]),
-        "invaskit_device_bytes": (C.c_int, [vp, vp]),
+        "invaskit_solve_workspace_bytes": (C.c_int, [vp, i64, szp, szp]),
+        "invaskit_solve": (C.c_int, [vp, vp, i64, i64, vp, i64, vp, sz, vp]),
+        "invaskit_matvec_workspace_bytes": (C.c_int, [vp, i64, szp]),
+        "invaskit_matvec": (C.c_int, [vp, vp, i64, i64, vp, i64, vp, sz]),
+        "invaskit_device_bytes": (C.c_int, [vp, szp]),
         "invaskit_phase_times": (C.c_int, [vp, vp, i32]),
         "invaskit_tile_config_get": (C.c_int, [vp, vp]),
         "invaskit_tuning_export": (C.c_int, [vp, C.c_size_t, vp]),
@@ -87,12 +93,13 @@ def _load():
         "invaskit_destroy": (C.c_int, [vp]),
         "invaskit_status_string": (C.c_char_p, [C.c_int]),
         "invaskit_last_error": (C.c_int, [vp, vp, C.c_size_t]),
-        "invaskit_getrf_batched": (C.c_int, [i32, vp, vp, vp, i32, vp, vp, vp]),
-        "invaskit_getrs_batched": (C.c_int, [i32, vp, vp, vp, vp, vp, vp, vp, vp, i32, vp]),
+        "invaskit_getrf_batched": (C.c_int, [i32, vp, vp, vp, i32, vp, vp, vp, sz, szp, vp]),
+        "invaskit_getrs_batched": (C.c_int, [i32, vp, vp, vp, vp, vp, vp, vp, vp, i32, vp, sz,
+                                             szp, vp]),
         "invaskit_kernel_blocks": (C.c_int, [i32, vp, i32, dbl, i32, vp, vp, vp, vp, vp, vp,
-                                             vp, vp, dbl, i32, vp]),
+                                             vp, vp, dbl, i32, vp, sz, szp, vp]),
         "invaskit_gemm_batched": (C.c_int, [i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
-                                            vp, dbl, dbl, i32, vp]),
+                                            vp, dbl, dbl, i32, vp, sz, szp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -102,13 +109,24 @@ def _load():
 
 
 _lib = _load()
-EXPORTED = ("invaskit_default_options", "invaskit_factor", "invaskit_factor_sweep",
-            "invaskit_refactor", "invaskit_solve",
-            "invaskit_matvec", "invaskit_device_bytes", "invaskit_phase_times",
-            "invaskit_tile_config_get", "invaskit_tuning_export", "invaskit_tuning_import",
-            "invaskit_tuning_clear", "invaskit_destroy", "invaskit_status_string", "invaskit_last_error",
+EXPORTED = ("invaskit_default_options", "invaskit_factor_workspace_bytes", "invaskit_factor",
+            "invaskit_factor_sweep", "invaskit_refactor", "invaskit_solve_workspace_bytes",
+            "invaskit_solve", "invaskit_matvec_workspace_bytes", "invaskit_matvec",
+            "invaskit_device_bytes", "invaskit_phase_times", "invaskit_tile_config_get",
+            "invaskit_tuning_export", "invaskit_tuning_import", "invaskit_tuning_clear",
+            "invaskit_destroy", "invaskit_status_string", "invaskit_last_error",
             "invaskit_getrf_batched", "invaskit_getrs_batched", "invaskit_kernel_blocks",
             "invaskit_gemm_batched")
+
+# Above this many bytes of GMRES bases, a solve's scratch holds a shorter
+# restart (the library uses the longest that fits; at least 2).
+GMRES_SCRATCH_CAP = 4 << 30
+
+
+def _device_buffer(nbytes: int) -> torch.Tensor:
+    """Caller-owned device memory for the library: a uint8 tensor (the
+    caching allocator aligns it to at least 256 bytes)."""
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device="cuda")
 
 
 def library():
@@ -163,7 +181,12 @@ class Factorization:
                                 leaf_trsm_cols, leaf_lu_waves, refine, gmres_restart,
                                 max_gmres_iters)
         self._handle = C.c_void_p()
-        st = _lib.invaskit_factor(C.byref(pb), self.lam, C.byref(opt), _stream(),
+        need = C.c_size_t()
+        _check(_lib.invaskit_factor_workspace_bytes(C.byref(pb), C.byref(opt), 0,
+                                                    C.byref(need)))
+        self._ws = _device_buffer(need.value)
+        st = _lib.invaskit_factor(C.byref(pb), self.lam, C.byref(opt),
+                                  C.c_void_p(self._ws.data_ptr()), self._ws.numel(), _stream(),
                                   C.byref(self._handle))
         if st != OK:
             msg = last_error(self._handle if self._handle.value else None)
@@ -186,6 +209,7 @@ class Factorization:
             p_values = torch.from_numpy(np.ascontiguousarray(problem.p_values, dtype=np.float64)).cuda()
         self._points = points
         self._p = p_values
+        self._scratch = {}  # (kind, nrhs) -> caller-owned scratch of solves and products
         self._leaf = np.ascontiguousarray(problem.leaf_offsets, dtype=np.int64)
         self._so = np.ascontiguousarray(problem.skel_offsets, dtype=np.int64)
         self._si = np.ascontiguousarray(problem.skel_index, dtype=np.int32)
@@ -222,6 +246,25 @@ class Factorization:
         self.lam = float(lam)
         _check(_lib.invaskit_refactor(self._handle, self.lam), self._handle)
 
+    def scratch(self, kind: str, r: int) -> torch.Tensor:
+        """The scratch this object passes to invaskit_solve ("solve") or
+        invaskit_matvec ("matvec") for r columns: allocated on first use and
+        kept, so the library reuses the descriptor tables it left there."""
+        key = (kind, int(r))
+        if key not in self._scratch:
+            full, low = C.c_size_t(), C.c_size_t()
+            if kind == "solve":
+                _check(_lib.invaskit_solve_workspace_bytes(self._handle, r, C.byref(full),
+                                                           C.byref(low)), self._handle)
+                nbytes = full.value if full.value - low.value <= GMRES_SCRATCH_CAP \
+                    else low.value + GMRES_SCRATCH_CAP
+            else:
+                _check(_lib.invaskit_matvec_workspace_bytes(self._handle, r, C.byref(full)),
+                       self._handle)
+                nbytes = full.value
+            self._scratch[key] = _device_buffer(nbytes)
+        return self._scratch[key]
+
     def solve(self, b: torch.Tensor, return_info: bool = False, check: bool = True):
         """x = (lambda I + K~)^-1 b for b of shape (N,) or (N, r) (tree order)."""
         vec = b.dim() == 1
@@ -229,9 +272,10 @@ class Factorization:
         r = bc.shape[0]
         xc = torch.empty_like(bc)
         info = SolveInfo()
+        sc = self.scratch("solve", r)
         st = _lib.invaskit_solve(self._handle, C.c_void_p(bc.data_ptr()), r, self.n,
-                                 C.c_void_p(xc.data_ptr()), self.n,
-                                 C.byref(info) if return_info else None)
+                                 C.c_void_p(xc.data_ptr()), self.n, C.c_void_p(sc.data_ptr()),
+                                 sc.numel(), C.byref(info) if return_info else None)
         if check:
             _check(st, self._handle)
         x = xc.t()
@@ -247,8 +291,10 @@ class Factorization:
         xc = _colmajor(x)
         r = xc.shape[0]
         yc = torch.empty_like(xc)
+        sc = self.scratch("matvec", r)
         _check(_lib.invaskit_matvec(self._handle, C.c_void_p(xc.data_ptr()), r, self.n,
-                                    C.c_void_p(yc.data_ptr()), self.n), self._handle)
+                                    C.c_void_p(yc.data_ptr()), self.n, C.c_void_p(sc.data_ptr()),
+                                    sc.numel()), self._handle)
         y = yc.t()
         return y[:, 0] if vec else y
 
@@ -269,6 +315,7 @@ class Factorization:
                 "trsm_ms": list(t.trsm_ms)}
 
     def device_bytes(self):
+        """Bytes of the factor workspace this handle's buffers span."""
         v = C.c_size_t()
         _check(_lib.invaskit_device_bytes(self._handle, C.byref(v)), self._handle)
         return v.value
@@ -277,6 +324,9 @@ class Factorization:
         if getattr(self, "_handle", None) is not None and self._handle.value:
             _lib.invaskit_destroy(self._handle)
             self._handle = C.c_void_p()
+        # the workspace and scratch go after the handle that used them
+        self._scratch = {}
+        self._ws = None
 
     def __del__(self):
         try:
@@ -286,6 +336,14 @@ class Factorization:
 
 
 # ------------------------------------------------------ batched building blocks
+def _block_workspace(fn, args):
+    """Query a building block's workspace size (workspace = NULL) and
+    allocate it."""
+    need = C.c_size_t()
+    _check(fn(*args, None, 0, C.byref(need), _stream()))
+    return _device_buffer(need.value)
+
+
 def getrf_batched(mats, dtype=torch.float64):
     """LU with partial pivoting of a list of square matrices (numpy or torch,
     any size 1..1024) in one launch.  Returns (packed row-major factors,
@@ -303,9 +361,11 @@ def getrf_batched(mats, dtype=torch.float64):
     info = torch.empty(len(mats), dtype=torch.int32, device="cuda")
     n_arr = np.asarray(ns, dtype=np.int32)
     dt = F64 if dtype == torch.float64 else F32
-    _check(_lib.invaskit_getrf_batched(dt, C.c_void_p(buf.data_ptr()), _ptr(offs), _ptr(n_arr),
-                                       len(mats), C.c_void_p(perm.data_ptr()),
-                                       C.c_void_p(info.data_ptr()), _stream()))
+    args = (dt, C.c_void_p(buf.data_ptr()), _ptr(offs), _ptr(n_arr), len(mats),
+            C.c_void_p(perm.data_ptr()), C.c_void_p(info.data_ptr()))
+    ws = _block_workspace(_lib.invaskit_getrf_batched, args)
+    _check(_lib.invaskit_getrf_batched(*args, C.c_void_p(ws.data_ptr()), ws.numel(), None,
+                                       _stream()))
     return buf, offs, n_arr, perm, info
 
 
@@ -327,9 +387,11 @@ def getrs_batched(buf, offs, n_arr, perm, rhs_list, dtype=torch.float64):
         parts.append(bt.t().contiguous().reshape(-1))
     bb = torch.cat(parts).cuda()
     dt = F64 if dtype == torch.float64 else F32
-    _check(_lib.invaskit_getrs_batched(dt, C.c_void_p(buf.data_ptr()), _ptr(offs), _ptr(n_arr),
-                                       C.c_void_p(perm.data_ptr()), C.c_void_p(bb.data_ptr()),
-                                       _ptr(boffs), _ptr(nr), _ptr(ld), len(rhs_list), _stream()))
+    args = (dt, C.c_void_p(buf.data_ptr()), _ptr(offs), _ptr(n_arr), C.c_void_p(perm.data_ptr()),
+            C.c_void_p(bb.data_ptr()), _ptr(boffs), _ptr(nr), _ptr(ld), len(rhs_list))
+    ws = _block_workspace(_lib.invaskit_getrs_batched, args)
+    _check(_lib.invaskit_getrs_batched(*args, C.c_void_p(ws.data_ptr()), ws.numel(), None,
+                                       _stream()))
     out = []
     for i in range(len(rhs_list)):
         seg = bb[boffs[i]:boffs[i] + nr[i] * ld[i]].reshape(int(nr[i]), int(ld[i])).t()
@@ -358,10 +420,12 @@ def kernel_blocks(points: torch.Tensor, h: float, blocks, out_dtype=torch.float6
         cols.append(np.asarray(cid, dtype=np.int32))
     cols_t = torch.from_numpy(np.concatenate(cols) if cols else np.zeros(1, np.int32)).cuda()
     out = torch.empty(max(o, 1), dtype=out_dtype, device="cuda")
-    _check(_lib.invaskit_kernel_blocks(pdt, C.c_void_p(points.data_ptr()), d, float(h), odt,
-                                       C.c_void_p(out.data_ptr()), _ptr(out_off), _ptr(row0),
-                                       _ptr(rows), C.c_void_p(cols_t.data_ptr()), _ptr(coff),
-                                       _ptr(ncols), _ptr(diag), float(shift), cnt, _stream()))
+    args = (pdt, C.c_void_p(points.data_ptr()), d, float(h), odt, C.c_void_p(out.data_ptr()),
+            _ptr(out_off), _ptr(row0), _ptr(rows), C.c_void_p(cols_t.data_ptr()), _ptr(coff),
+            _ptr(ncols), _ptr(diag), float(shift), cnt)
+    ws = _block_workspace(_lib.invaskit_kernel_blocks, args)
+    _check(_lib.invaskit_kernel_blocks(*args, C.c_void_p(ws.data_ptr()), ws.numel(), None,
+                                       _stream()))
     res = []
     for i in range(cnt):
         res.append(out[out_off[i]:out_off[i] + rows[i] * ncols[i]]
@@ -403,10 +467,11 @@ def gemm_batched(problems, dtype=torch.float64, alpha=1.0, beta=0.0):
     tb = torch.cat(pb_ + [torch.zeros(1, dtype=dtype)]).cuda()
     tc = torch.cat(pc + [torch.zeros(1, dtype=dtype)]).cuda()
     dt = F64 if dtype == torch.float64 else F32
-    _check(_lib.invaskit_gemm_batched(dt, C.c_void_p(ta.data_ptr()), C.c_void_p(tb.data_ptr()),
-                                      C.c_void_p(tc.data_ptr()), _ptr(a_off), _ptr(b_off),
-                                      _ptr(c_off), _ptr(m), _ptr(n), _ptr(k), _ptr(lda), _ptr(arm),
-                                      _ptr(ldb), _ptr(ldc), float(alpha), float(beta), cnt,
+    args = (dt, C.c_void_p(ta.data_ptr()), C.c_void_p(tb.data_ptr()), C.c_void_p(tc.data_ptr()),
+            _ptr(a_off), _ptr(b_off), _ptr(c_off), _ptr(m), _ptr(n), _ptr(k), _ptr(lda), _ptr(arm),
+            _ptr(ldb), _ptr(ldc), float(alpha), float(beta), cnt)
+    ws = _block_workspace(_lib.invaskit_gemm_batched, args)
+    _check(_lib.invaskit_gemm_batched(*args, C.c_void_p(ws.data_ptr()), ws.numel(), None,
                                       _stream()))
     out = []
     for i in range(cnt):
@@ -418,23 +483,33 @@ def factor_sweep(problem, lams, precision: str = "fp64", fp64_top_levels: int = 
                  refine_tol: float = 1e-10, max_refine_iters: int = 30, points=None,
                  p_values=None, tune: str = "auto", leaf_lu_panel: int = 0,
                  leaf_trsm_cols: int = 0, leaf_lu_waves: int = 0, refine: str = "auto",
-                 gmres_restart: int = 20, max_gmres_iters: int = 300):
+                 gmres_restart: int = 20, max_gmres_iters: int = 300, lambda_group: int = 0):
     """One Factorization per lambda in `lams` (invaskit_factor_sweep): the
-    kernel blocks are evaluated once and shared by the handles."""
+    kernel blocks are evaluated once into the sweep's workspace and shared
+    by the handles; the lambdas are factored in batches of `lambda_group`
+    (0: all together), each batch in one set of launches."""
     lams = [float(v) for v in lams]
     objs = [Factorization.__new__(Factorization) for _ in lams]
     pb, opt = objs[0]._prepare(problem, lams[0], precision, fp64_top_levels, refine_tol,
                                max_refine_iters, points, p_values, tune, leaf_lu_panel,
                                leaf_trsm_cols, leaf_lu_waves, refine, gmres_restart,
                                max_gmres_iters)
+    opt.lambda_group = int(lambda_group)
+    need = C.c_size_t()
+    _check(_lib.invaskit_factor_workspace_bytes(C.byref(pb), C.byref(opt), len(lams),
+                                                C.byref(need)))
+    ws = _device_buffer(need.value)
     for o, lam in zip(objs[1:], lams[1:]):
         o.n, o.lam, o.precision = objs[0].n, lam, precision
         o._points, o._p = objs[0]._points, objs[0]._p
         o._keep = objs[0]
+        o._scratch = {}
+    for o in objs:
+        o._ws = ws  # shared: freed with the last of them
     arr = (C.c_double * len(lams))(*lams)
     handles = (C.c_void_p * len(lams))()
-    st = _lib.invaskit_factor_sweep(C.byref(pb), arr, len(lams), C.byref(opt), _stream(),
-                                    handles)
+    st = _lib.invaskit_factor_sweep(C.byref(pb), arr, len(lams), C.byref(opt),
+                                    C.c_void_p(ws.data_ptr()), ws.numel(), _stream(), handles)
     for o, hnd in zip(objs, handles):
         o._handle = C.c_void_p(hnd)
     if st != OK:

@@ -105,6 +105,15 @@ struct ZformProb {
   int32_t sr, sl;
 };
 
+// dst = src + shift * I, square blocks of order m (the leaf blocks of one
+// factorization of a lambda sweep, copied from the shared lambda-free ones)
+struct CopyShiftProb {
+  const void* src;
+  void* dst;
+  int32_t m, pad;
+  double shift;
+};
+
 // Fused FP64 kernel-times-weights evaluation for one block of targets:
 // y[i] (+)= sum over segments of sum_j K(x_i, x_src(j)) w[j, :].
 struct MvSeg {
@@ -182,6 +191,9 @@ template <typename PT, typename T>
 hipError_t launch_eval(const PT* X, int d, double h, double shift, const EvalBlock* blocks,
                        const Tile3* tiles, int ntiles, hipStream_t s);
 constexpr int kEvalTile = 64;
+
+template <typename T>
+hipError_t launch_copy_shift(const CopyShiftProb* probs, int count, hipStream_t s);
 
 template <typename TZ, typename TV>
 hipError_t launch_zform(const ZformProb* probs, int count, hipStream_t s);

@@ -1,5 +1,6 @@
-// libinvaskit host side: input validation, memory plan, level-synchronous
-// launch schedule and the C ABI of include/invaskit.h.
+// libinvaskit host side: input validation, the memory plan over the caller's
+// workspace, the level-synchronous launch schedule and the C ABI of
+// include/invaskit.h.
 //
 // Factorization (Algorithm 1), bottom-up, each step one batched launch over
 // every node it touches instead of a recursion.  Notation: L = depth, c' =
@@ -34,6 +35,17 @@
 // and then x = v - W~ e.  The solve (Algorithm 2) runs: leaf solves, leaf
 // projections, the sweep for j = L-1 .. 0, the top-down pass for e, and one
 // grouped GEMM per leaf.
+//
+// Memory.  The library allocates no device memory.  A factorization lives in
+// a workspace the caller allocates (its size from
+// invaskit_factor_workspace_bytes): the handle's buffers are carved from it
+// at 256-byte boundaries, with the launch descriptor tables last.  A lambda
+// sweep's workspace holds the lambda-free kernel blocks shared by its
+// handles, the tables of its lambda-batched launches, and one region per
+// handle.  Solves and products carve their vectors and tables from the
+// caller's scratch.  The sizes come from the same planning code the
+// factorization runs (host only, no device access), built against a
+// placeholder base address: table sizes do not depend on the addresses.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -41,12 +53,12 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <list>
 #include <map>
 #include <memory>
 #include <mutex>
 #include <sstream>
 #include <string>
-#include <unordered_set>
 #include <vector>
 
 #include "../../include/invaskit.h"
@@ -63,34 +75,46 @@ constexpr int kMaxSkel = 512;
 constexpr int kMaxDepth = 24;
 constexpr int kEvents = 8;
 constexpr int kPhases = 10;  // see invaskit_phase_times
+constexpr size_t kAlign = 256;
+// placeholder base of the planning runs that only measure sizes; never
+// dereferenced
+unsigned char* const kPlanBase = reinterpret_cast<unsigned char*>(uintptr_t(1) << 40);
 
 // -------------------------------------------------------------- small utils
-struct DevBuf {
+// A piece of caller-owned device memory.
+struct Buf {
   void* p = nullptr;
   size_t bytes = 0;
-  void release() {
-    if (p) hipFree(p);
-    p = nullptr;
-    bytes = 0;
-  }
 };
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Assigns aligned offsets in a region, in the order pieces are taken.
+struct Carve {
+  size_t size = 0;
+  size_t take(size_t bytes) {
+    const size_t o = align_up(size, kAlign);
+    size = o + std::max<size_t>(bytes, 1);
+    return o;
+  }
+  size_t total() const { return align_up(size, kAlign); }
+};
 
 // Host staging area for descriptor tables; uploaded to one device buffer.
 struct Arena {
   std::vector<unsigned char> host;
   template <typename T>
   size_t add(const std::vector<T>& v) {
-    const size_t off = align_up(host.size(), 256);
+    const size_t off = align_up(host.size(), kAlign);
     host.resize(off + v.size() * sizeof(T));
     if (!v.empty()) std::memcpy(host.data() + off, v.data(), v.size() * sizeof(T));
     return off;
   }
+  size_t bytes() const { return std::max<size_t>(align_up(host.size(), kAlign), kAlign); }
 };
 
 template <typename T>
-const T* at(const DevBuf& b, size_t off) {
+const T* at(const Buf& b, size_t off) {
   return reinterpret_cast<const T*>(static_cast<unsigned char*>(b.p) + off);
 }
 
@@ -125,81 +149,79 @@ struct EvalL {
   size_t blocks = 0, tiles = 0;
   int ntiles = 0, nblocks = 0;
 };
-
-// Kernel blocks of a problem evaluated without lambda (leaf blocks K_aa and
-// the skeleton blocks of every level, in the layout of the factor storage),
-// shared by the handles of a lambda sweep: only the leaf LU, W and the
-// reduced systems depend on lambda.
-struct KernelCache {
-  DevBuf leaf, slab;
-  bool valid = false;
-  ~KernelCache() {
-    leaf.release();
-    slab.release();
-  }
-};
 struct ZformL {
   size_t probs = 0;
   int count = 0, tz64 = 1, tv64 = 1;
 };
+struct CopyShiftL {
+  size_t probs = 0;
+  int count = 0;
+};
+
+// Kernel blocks of a problem evaluated without lambda (leaf blocks K_aa and
+// the skeleton blocks of every level, in the layout of the factor storage),
+// shared by the handles of a lambda sweep: only the leaf LU, W and the
+// reduced systems depend on lambda.  The sweep's handles also share the
+// device copy of the skeleton indices and, in mixed precision, the FP32
+// copy of P.  All of it lives in the sweep's workspace.
+struct KernelCache {
+  Buf leaf, slab, skel, P32;
+  bool valid = false;
+};
 
 // The factorization schedule: leaf-level passes over every tree level at
 // once, then one wavefront step per level for the reduced systems and the
-// skeleton sweep.
+// skeleton sweep.  A plan covers one or several handles (the lambdas of a
+// sweep, batched into the same launches).
 struct FactorPlan {
-  EvalL leaf_eval;
+  bool cached = false;  // kernel blocks come from a KernelCache
+  EvalL leaf_eval;      // leaf blocks: into the factor storage, or the cache
+  CopyShiftL leaf_copy; // cached plans: cache -> factor storage, + lambda I
   LuL leaf_lu;
   DinvL leaf_dinv;
-  EvalL panels;      // skeleton blocks of every level
-  TrsmL leaf_trsm[2];  // leaf solves of every level's panel columns, 16 and 32
-                       // right-hand sides per workgroup (ntiles < 0: no room)
-  GemmL leaf_proj;   // leaf projections of every level's panel columns
-  std::vector<ZformL> zform;   // index j: reduced systems of level j
+  EvalL panels;         // skeleton blocks of every level (into W storage or the cache)
+  TrsmL leaf_trsm[2];   // leaf solves of every level's panel columns, 16 and 32
+                        // right-hand sides per workgroup (ntiles < 0: no room)
+  GemmL leaf_proj;      // leaf projections of every level's panel columns
+  std::vector<ZformL> zform;  // index j: reduced systems of level j
   std::vector<LuL> zlu;
   std::vector<DinvL> zdinv;
-  std::vector<TrsmL> zsolve;   // index j >= 1: sweep step at level j
+  std::vector<TrsmL> zsolve;  // index j >= 1: sweep step at level j
   std::vector<GemmL> pgemm;
+  Buf tables;                 // device copy of the descriptor tables
 };
 
-struct SolvePlan {
-  int r = 0;
-  DevBuf tables, xbuf, sbuf;  // xbuf/sbuf in the factor precision
-  DevBuf x64, r64, sc;        // refinement: iterate, residual, column scales
-  DevBuf gpart, gsmall;       // reduction partials; small per-column vectors
-  DevBuf gmV, gmZ;            // GMRES bases (allocated when GMRES first runs)
-  int gm_m = 0;               // Krylov vectors per GMRES cycle
-  std::vector<double> host_scale;
-  TrsmL leaf_trsm;
-  GemmL leaf_proj;
-  std::vector<TrsmL> zsolve;  // levels L-1 .. 0
-  std::vector<GemmL> pgemm;   // levels L-1 .. 1
-  std::vector<GemmL> topdown; // e = (I + U)^-1 y^, levels 2 .. L
-  GemmL final_;
-  ~SolvePlan() {
-    tables.release();
-    xbuf.release();
-    sbuf.release();
-    x64.release();
-    r64.release();
-    sc.release();
-    gpart.release();
-    gsmall.release();
-    gmV.release();
-    gmZ.release();
-  }
-};
-
+// A matvec's buffers and launches; its tables sit inside the solve's (or
+// the matvec's own) table buffer.
 struct MatvecPlan {
   int r = 0;
-  DevBuf tables, xm, q;
+  Buf xm, q;
   std::vector<GemmL> skel;  // levels L .. 1
   size_t mv_tiles = 0, mv_segs = 0;
   int n_mv_tiles = 0;
-  ~MatvecPlan() {
-    tables.release();
-    xm.release();
-    q.release();
-  }
+};
+
+// Buffers and launches of a solve with r right-hand sides, carved from the
+// caller's scratch at `base`; `blob` is the host copy of the tables.
+struct SolvePlan {
+  int r = 0;
+  bool solve = true;           // false: a matvec-only plan
+  void* base = nullptr;
+  size_t min_bytes = 0, full_bytes = 0;  // scratch without / with the GMRES bases
+  std::vector<unsigned char> blob;
+  Buf tables, xbuf, sbuf;      // xbuf/sbuf in the factor precision
+  Buf x64, r64, sc;            // refinement: iterate, residual, column scales
+  Buf gpart, gsmall;           // reduction partials; small per-column vectors
+  Buf gmV, gmZ;                // GMRES bases (present when the scratch holds them)
+  int gm_m = 0;                // Krylov vectors per GMRES cycle (0: no room)
+  TrsmL leaf_trsm;
+  GemmL leaf_proj;
+  std::vector<TrsmL> zsolve;   // levels L-1 .. 0
+  std::vector<GemmL> pgemm;    // levels L-1 .. 1
+  std::vector<GemmL> topdown;  // e = (I + U)^-1 y^, levels 2 .. L
+  GemmL final_;
+  MatvecPlan mv;
+  std::vector<double> host_scale;
 };
 
 }  // namespace
@@ -235,23 +257,32 @@ struct invaskit_handle_s {
   std::vector<std::vector<int>> colp;  // [node][k]: first column of factor level k
   std::vector<int> Ssw;                // sweep columns of a node (sum of its w over k)
   std::vector<int64_t> psw_off, ysw_off;
-  // device buffers
-  DevBuf skel_d, P32, leafLU, leafPerm, leafInfo, slab, Z64, ZT, zperm, zinfo, psw, ysw, ftables;
-  DevBuf dinvLeaf, dinvZ64, dinvZT;   // inverses of the 64 x 64 diagonal blocks
   std::vector<int64_t> dleaf_off, dz_off;
+  int64_t z64n = 0, zTn = 0, zpn = 0, dz64n = 0, dzTn = 0, pswn = 0, yswn = 0;
+  // buffers in the caller's workspace
+  void* region = nullptr;  // this handle's region
+  size_t region_bytes = 0;
+  Buf leafLU, leafPerm, leafInfo, slab, Z64, ZT, zperm, zinfo, psw, ysw;
+  Buf dinvLeaf, dinvZ64, dinvZT;  // inverses of the 64 x 64 diagonal blocks
+  Buf skel_own, P32_own;          // own copies (plain handles)
+  const int32_t* skd = nullptr;   // device skeleton indices (own or the sweep's)
+  const void* Pf = nullptr;       // P in the factor precision
   // schedule
-  FactorPlan fp;
-  std::map<int, std::unique_ptr<SolvePlan>> solve_plans;
-  std::map<int, std::unique_ptr<MatvecPlan>> mv_plans;
+  FactorPlan fp;                  // this handle's own plan
+  bool fp_ready = false;          // fp built and its tables uploaded
+  std::shared_ptr<KernelCache> kcache;  // set for the handles of a lambda sweep
+  // solve and matvec plans, most recently used first (host memory only)
+  std::list<std::unique_ptr<SolvePlan>> plans;
+  const void* up_base = nullptr;  // scratch whose tables are current
+  const SolvePlan* up_plan = nullptr;
   double phase_ms[kPhases] = {0};
-  double plan_ms = 0;  // host planning and allocation of the handle (wall clock)
+  double plan_ms = 0;  // host planning of the handle (wall clock)
   hipEvent_t ev[kEvents + 2] = {};
   bool have_events = false;
   // second stream of the factorization (default priority): the skeleton
   // blocks run on it beside the leaf block evaluation and LU
   hipStream_t side = nullptr;
-  std::shared_ptr<KernelCache> kcache;  // set for the handles of a lambda sweep
-  invaskit_tile_config tiles{};         // tile shapes of the last factor
+  invaskit_tile_config tiles{};   // tile shapes of the last factor
   std::string err;
 
   int level(int node) const {
@@ -268,18 +299,16 @@ struct invaskit_handle_s {
   }
   int leaf_node(int j) const { return (1 << L) - 1 + j; }
   size_t tsize() const { return prec == INVASKIT_PREC_FP64 ? 8 : 4; }
-  const void* Pt() const {  // P in the factor precision
-    return prec == INVASKIT_PREC_FP64 ? static_cast<const void*>(P64) : P32.p;
-  }
+  const void* Pt() const { return Pf; }
   const void* Z(int node) const {
     const int k = level(node);
-    const DevBuf& b = zis64[k] ? Z64 : ZT;
+    const Buf& b = zis64[k] ? Z64 : ZT;
     return static_cast<unsigned char*>(b.p) + z_off[node] * (zis64[k] ? 8 : 4);
   }
   void* Zm(int node) { return const_cast<void*>(Z(node)); }
   const void* DZ(int node) const {  // diagonal-block inverses of a reduced system
     const int k = level(node);
-    const DevBuf& b = zis64[k] ? dinvZ64 : dinvZT;
+    const Buf& b = zis64[k] ? dinvZ64 : dinvZT;
     return static_cast<unsigned char*>(b.p) + dz_off[node] * (zis64[k] ? 8 : 4);
   }
   const void* DL(int leaf) const {
@@ -287,11 +316,6 @@ struct invaskit_handle_s {
   }
 
   ~invaskit_handle_s() {
-    solve_plans.clear();
-    mv_plans.clear();
-    for (DevBuf* b : {&skel_d, &P32, &leafLU, &leafPerm, &leafInfo, &slab, &Z64, &ZT, &zperm,
-                      &zinfo, &psw, &ysw, &ftables, &dinvLeaf, &dinvZ64, &dinvZT})
-      b->release();
     if (have_events)
       for (auto& e : ev) hipEventDestroy(e);
     if (side) hipStreamDestroy(side);
@@ -316,19 +340,6 @@ int fail_h(H* h, int code, const std::string& msg) {
                     std::string(#__VA_ARGS__) + ": " + hipGetErrorString(e_));           \
   } while (0)
 
-int dev_alloc(H* h, DevBuf& b, size_t bytes) {
-  b.release();
-  if (bytes == 0) bytes = 256;
-  hipError_t e = hipMalloc(&b.p, bytes);
-  if (e != hipSuccess) {
-    b.p = nullptr;
-    return fail_h(h, INVASKIT_E_MEMORY,
-                  "hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
-  }
-  b.bytes = bytes;
-  return INVASKIT_OK;
-}
-
 int check_device(H* h) {
   int dev = 0;
   HIP_TRY(h, hipGetDevice(&dev));
@@ -337,6 +348,17 @@ int check_device(H* h) {
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
     return fail_h(h, INVASKIT_E_DEVICE,
                   std::string("device is ") + prop.gcnArchName + ", this library is built for gfx950");
+  return INVASKIT_OK;
+}
+
+int check_workspace(H* h, const void* ws, size_t have, size_t need, const char* what) {
+  if (!ws) return fail_h(h, INVASKIT_E_ARG, std::string(what) + " is NULL");
+  if (reinterpret_cast<uintptr_t>(ws) % kAlign != 0)
+    return fail_h(h, INVASKIT_E_ARG, std::string(what) + " must be 256-byte aligned");
+  if (have < need)
+    return fail_h(h, INVASKIT_E_WORKSPACE,
+                  std::string(what) + " holds " + std::to_string(have) + " bytes; " +
+                      std::to_string(need) + " are needed");
   return INVASKIT_OK;
 }
 
@@ -373,6 +395,7 @@ int validate(H* h, const invaskit_problem* pb, double lambda, const invaskit_opt
     if (opt->gmres_restart < 2 || opt->gmres_restart > 64)
       return fail_h(h, INVASKIT_E_ARG, "gmres_restart must be in [2, 64]");
     if (opt->max_gmres_iters < 1) return fail_h(h, INVASKIT_E_ARG, "max_gmres_iters < 1");
+    if (opt->lambda_group < 0) return fail_h(h, INVASKIT_E_ARG, "lambda_group < 0");
   }
   const int L = pb->depth;
   const int nleaves = 1 << L;
@@ -409,6 +432,8 @@ int validate(H* h, const invaskit_problem* pb, double lambda, const invaskit_opt
     a = lo[idx * span];
     b = lo[(idx + 1) * span];
   };
+  // nesting: stamp[i] = c marks the children's skeleton points of node c
+  std::vector<int32_t> stamp(L > 0 ? pb->n : 0, -1);
   for (int c = nn - 1; c >= 1; --c) {
     int64_t a, b;
     range(c, a, b);
@@ -424,13 +449,16 @@ int validate(H* h, const invaskit_problem* pb, double lambda, const invaskit_opt
     } else {
       const int l = 2 * c + 1, r = 2 * c + 2;
       cols = (so[l + 1] - so[l]) + (so[r + 1] - so[r]);
-      std::unordered_set<int32_t> child;
-      for (int64_t t = so[l]; t < so[r + 1]; ++t) child.insert(pb->skel_index[t]);
-      for (int64_t t = so[c]; t < so[c + 1]; ++t)
-        if (!child.count(pb->skel_index[t]))
+      // the children's skeletons lie in their ranges (checked first, going
+      // bottom-up), so every index is a valid point id
+      for (int64_t t = so[l]; t < so[r + 1]; ++t) stamp[pb->skel_index[t]] = c;
+      for (int64_t t = so[c]; t < so[c + 1]; ++t) {
+        const int32_t i = pb->skel_index[t];
+        if (i < a || i >= b || stamp[i] != c)
           return fail_h(h, INVASKIT_E_ARG,
                         "skeleton of node " + std::to_string(c) +
                             " is not nested in its children's skeletons");
+      }
     }
     if (po[c + 1] - po[c] != sc * cols)
       return fail_h(h, INVASKIT_E_ARG,
@@ -600,19 +628,20 @@ struct TrsmBuilder {
   }
 };
 
+
 template <typename T>
 T* offp(void* base, int64_t elems) {
   return static_cast<T*>(base) + elems;
 }
-inline void* offv(void* base, int64_t elems, size_t esz) {
-  return static_cast<unsigned char*>(base) + elems * esz;
+inline void* offv(const void* base, int64_t elems, size_t esz) {
+  return const_cast<unsigned char*>(static_cast<const unsigned char*>(base)) + elems * esz;
 }
 
 // ----------------------------------------------------------------- planning
-int plan_factor(H* h) {
+// Tree-derived sizes and element offsets of every factor buffer (host only).
+void layout_factor(H* h) {
   const int L = h->L;
   const int nn = h->nn;
-  const size_t es = h->tsize();
   h->na.assign(nn, 0);
   h->nb.assign(nn, 0);
   h->s.assign(nn, 0);
@@ -710,120 +739,186 @@ int plan_factor(H* h) {
       yn += (int64_t)h->z[c] * h->Ssw[c];
     }
   }
+  h->z64n = z64n;
+  h->zTn = zTn;
+  h->zpn = zpn;
+  h->dz64n = dz64;
+  h->dzTn = dzT;
+  h->pswn = pn;
+  h->yswn = yn;
+}
 
-  // allocations
-  int rc;
+// Carves the handle's buffers from the region at `base` (kPlanBase when only
+// sizes are wanted); the descriptor tables come last, table_bytes long.
+// Plain handles keep their own device copies of the skeleton indices and (in
+// mixed precision) of P in FP32; a sweep's handles use the sweep's
+// (shared != nullptr).  Returns the region's size.
+size_t carve_factor(H* h, unsigned char* base, const KernelCache* shared, size_t table_bytes) {
+  Carve cv;
+  const size_t es = h->tsize();
+  auto put = [&](Buf& b, size_t bytes) {
+    const size_t o = cv.take(bytes);
+    b.p = base + o;
+    b.bytes = bytes;
+  };
+  const int ninternal = (1 << h->L) - 1;
   // factor storage is padded by one 64-column block: the solves read factor
   // rows as whole vectors past the last partial block
-  if ((rc = dev_alloc(h, h->leafLU, (h->lu_off[h->nleaves] + kDiagBlock) * es))) return rc;
-  if ((rc = dev_alloc(h, h->leafPerm, sizeof(int32_t) * h->N))) return rc;
-  if ((rc = dev_alloc(h, h->leafInfo, sizeof(int32_t) * h->nleaves))) return rc;
-  if ((rc = dev_alloc(h, h->slab, h->slab_off[h->nleaves] * es))) return rc;
-  if (h->kcache && !h->kcache->leaf.p) {
-    if ((rc = dev_alloc(h, h->kcache->leaf, h->lu_off[h->nleaves] * es))) return rc;
-    if ((rc = dev_alloc(h, h->kcache->slab, std::max<int64_t>(h->slab_off[h->nleaves], 1) * es)))
-      return rc;
+  put(h->leafLU, (h->lu_off[h->nleaves] + kDiagBlock) * es);
+  put(h->leafPerm, sizeof(int32_t) * h->N);
+  put(h->leafInfo, sizeof(int32_t) * h->nleaves);
+  put(h->slab, std::max<int64_t>(h->slab_off[h->nleaves], 1) * es);
+  put(h->Z64, (h->z64n + kDiagBlock) * 8);
+  put(h->ZT, (h->zTn + kDiagBlock) * es);
+  put(h->zperm, sizeof(int32_t) * std::max<int64_t>(h->zpn, 1));
+  put(h->zinfo, sizeof(int32_t) * std::max(ninternal, 1));
+  put(h->dinvLeaf, h->dleaf_off[h->nleaves] * es);
+  put(h->dinvZ64, std::max<int64_t>(h->dz64n, 1) * 8);
+  put(h->dinvZT, std::max<int64_t>(h->dzTn, 1) * es);
+  put(h->psw, std::max<int64_t>(h->pswn, 1) * es);
+  put(h->ysw, std::max<int64_t>(h->yswn, 1) * es);
+  const bool mixed = h->prec == INVASKIT_PREC_MIXED;
+  if (!shared) {
+    put(h->skel_own, sizeof(int32_t) * std::max<size_t>(h->skel_idx.size(), 1));
+    if (mixed) put(h->P32_own, sizeof(float) * std::max<int64_t>(h->p_off[h->nn], 1));
+    h->skd = static_cast<const int32_t*>(h->skel_own.p);
+    h->Pf = mixed ? h->P32_own.p : static_cast<const void*>(h->P64);
+  } else {
+    h->skd = static_cast<const int32_t*>(shared->skel.p);
+    h->Pf = mixed ? shared->P32.p : static_cast<const void*>(h->P64);
   }
-  if ((rc = dev_alloc(h, h->Z64, (z64n + kDiagBlock) * 8))) return rc;
-  if ((rc = dev_alloc(h, h->ZT, (zTn + kDiagBlock) * es))) return rc;
-  if ((rc = dev_alloc(h, h->zperm, sizeof(int32_t) * std::max<int64_t>(zpn, 1)))) return rc;
-  if ((rc = dev_alloc(h, h->zinfo, sizeof(int32_t) * std::max(ninternal, 1)))) return rc;
-  if ((rc = dev_alloc(h, h->dinvLeaf, h->dleaf_off[h->nleaves] * es))) return rc;
-  if ((rc = dev_alloc(h, h->dinvZ64, dz64 * 8))) return rc;
-  if ((rc = dev_alloc(h, h->dinvZT, dzT * es))) return rc;
-  if ((rc = dev_alloc(h, h->psw, pn * es))) return rc;
-  if ((rc = dev_alloc(h, h->ysw, yn * es))) return rc;
-  if ((rc = dev_alloc(h, h->skel_d, sizeof(int32_t) * std::max<size_t>(h->skel_idx.size(), 1))))
-    return rc;
-  if (!h->skel_idx.empty())
-    HIP_TRY(h, hipMemcpy(h->skel_d.p, h->skel_idx.data(), sizeof(int32_t) * h->skel_idx.size(),
-                         hipMemcpyHostToDevice));
-  if (h->prec == INVASKIT_PREC_MIXED) {
-    const int64_t np = h->p_off[nn];
-    if ((rc = dev_alloc(h, h->P32, sizeof(float) * std::max<int64_t>(np, 1)))) return rc;
-  }
+  put(h->fp.tables, table_bytes);
+  h->region = base;
+  h->region_bytes = cv.total();
+  return h->region_bytes;
+}
 
-  // ---- tables
-  Arena ar;
-  FactorPlan& fp = h->fp;
-  fp = FactorPlan();
+// The shared part of a sweep's workspace: lambda-free kernel blocks in the
+// factor storage layout, skeleton indices and FP32 P.
+size_t carve_cache(const H* h, KernelCache& kc, unsigned char* base) {
+  Carve cv;
+  const size_t es = h->tsize();
+  auto put = [&](Buf& b, size_t bytes) {
+    const size_t o = cv.take(bytes);
+    b.p = base + o;
+    b.bytes = bytes;
+  };
+  put(kc.leaf, h->lu_off[h->nleaves] * es);
+  put(kc.slab, std::max<int64_t>(h->slab_off[h->nleaves], 1) * es);
+  put(kc.skel, sizeof(int32_t) * std::max<size_t>(h->skel_idx.size(), 1));
+  if (h->prec == INVASKIT_PREC_MIXED)
+    put(kc.P32, sizeof(float) * std::max<int64_t>(h->p_off[h->nn], 1));
+  return cv.total();
+}
+
+// Descriptor tables of the factorization of the handles `hs` (identical
+// layouts; several handles: the lambdas of a sweep batched into the same
+// launches).  kc != nullptr: the kernel blocks are evaluated once into the
+// cache and read from it (leaf blocks copied with each handle's lambda on
+// the diagonal; the leaf solves read the skeleton blocks from the cache and
+// write each handle's W storage).
+void build_factor_tables(const std::vector<H*>& hs, const KernelCache* kc, Arena& ar,
+                         FactorPlan& fp) {
+  H* h = hs[0];
+  const int L = h->L;
+  const size_t es = h->tsize();
   const int T64 = (h->prec == INVASKIT_PREC_FP64) ? 1 : 0;
-  const int32_t* skd = static_cast<const int32_t*>(h->skel_d.p);
-  const int32_t* lperm = static_cast<const int32_t*>(h->leafPerm.p);
-  int32_t* zpm = static_cast<int32_t*>(h->zperm.p);
-  void* PS = h->psw.p;
-  void* YS = h->ysw.p;
-  void* Pt = const_cast<void*>(h->Pt());
+  const Buf tables = fp.tables;
+  fp = FactorPlan();
+  fp.tables = tables;
+  fp.cached = kc != nullptr;
+  constexpr int64_t kDB2 = 2 * kDiagBlock * kDiagBlock;
+  const int32_t* skd = h->skd;
   // leaf blocks and their LU; skeleton blocks, leaf solves and leaf
   // projections of every level
   {
     std::vector<EvalBlock> lblocks, pblocks;
     std::vector<Tile3> ltiles, ptiles;
+    std::vector<CopyShiftProb> copies;
     std::vector<LuProb> lus;
     std::vector<DiagInvProb> dis;
     TrsmBuilder tb;
     GemmBuilder proj;
     int nmax = 0;
-    for (int j = 0; j < h->nleaves; ++j) {
-      const int lf = h->leaf_node(j);
-      const int m = (int)(h->nb[lf] - h->na[lf]);
-      EvalBlock b{};
-      b.out = offv(h->leafLU.p, h->lu_off[j], es);
-      b.ld = m;
-      b.row0 = h->na[lf];
-      b.cols = nullptr;
-      b.col0 = h->na[lf];
-      b.rows = m;
-      b.ncols = m;
-      b.diag = 1;
-      lblocks.push_back(b);
-      for (int tn = 0; tn < (m + kEvalTile - 1) / kEvalTile; ++tn)
-        for (int tm = 0; tm < (m + kEvalTile - 1) / kEvalTile; ++tm)
-          ltiles.push_back({(int)lblocks.size() - 1, tm, tn});
-      LuProb p{};
-      p.a = b.out;
-      p.perm = static_cast<int32_t*>(h->leafPerm.p) + h->na[lf];
-      p.info = static_cast<int32_t*>(h->leafInfo.p) + j;
-      p.n = m;
-      lus.push_back(p);
-      nmax = std::max(nmax, m);
-      fp.leaf_lu.work += (double)m * m * m;
-      for (int jb = 0; jb < m; jb += kDiagBlock) {
-        DiagInvProb d{};
-        d.lu = b.out;
-        d.perm = p.perm;
-        d.out = offv(h->dinvLeaf.p, h->dleaf_off[j] + (jb / kDiagBlock) * kDB2, es);
-        d.n = m;
-        d.jb = jb;
-        dis.push_back(d);
+    for (size_t g = 0; g < hs.size(); ++g) {
+      H* hg = hs[g];
+      for (int j = 0; j < h->nleaves; ++j) {
+        const int lf = h->leaf_node(j);
+        const int m = (int)(h->nb[lf] - h->na[lf]);
+        void* lu = offv(hg->leafLU.p, h->lu_off[j], es);
+        if (g == 0) {
+          EvalBlock b{};
+          b.out = kc ? offv(kc->leaf.p, h->lu_off[j], es) : lu;
+          b.ld = m;
+          b.row0 = h->na[lf];
+          b.cols = nullptr;
+          b.col0 = h->na[lf];
+          b.rows = m;
+          b.ncols = m;
+          b.diag = 1;
+          lblocks.push_back(b);
+          for (int tn = 0; tn < (m + kEvalTile - 1) / kEvalTile; ++tn)
+            for (int tm = 0; tm < (m + kEvalTile - 1) / kEvalTile; ++tm)
+              ltiles.push_back({(int)lblocks.size() - 1, tm, tn});
+        }
+        if (kc) {
+          CopyShiftProb c{};
+          c.src = offv(kc->leaf.p, h->lu_off[j], es);
+          c.dst = lu;
+          c.m = m;
+          c.shift = hg->lam;
+          copies.push_back(c);
+        }
+        LuProb p{};
+        p.a = lu;
+        p.perm = static_cast<int32_t*>(hg->leafPerm.p) + h->na[lf];
+        p.info = static_cast<int32_t*>(hg->leafInfo.p) + j;
+        p.n = m;
+        lus.push_back(p);
+        nmax = std::max(nmax, m);
+        fp.leaf_lu.work += (double)m * m * m;
+        for (int jb = 0; jb < m; jb += kDiagBlock) {
+          DiagInvProb d{};
+          d.lu = lu;
+          d.perm = p.perm;
+          d.out = offv(hg->dinvLeaf.p, h->dleaf_off[j] + (jb / kDiagBlock) * kDB2, es);
+          d.n = m;
+          d.jb = jb;
+          dis.push_back(d);
+        }
+        if (L == 0) continue;
+        void* slab = offv(hg->slab.p, h->slab_off[j], es);
+        void* kin = kc ? offv(kc->slab.p, h->slab_off[j], es) : slab;
+        if (g == 0) {
+          for (int k = L; k >= 1; --k) {
+            const int c = h->anc(lf, k);
+            const int wk = h->w[c];
+            EvalBlock e{};
+            e.out = offv(kin, (int64_t)h->colk[j][k] * m, es);
+            e.ld = m;
+            e.row0 = h->na[lf];
+            e.cols = skd + h->skel_off[h->sib(c)];
+            e.rows = m;
+            e.ncols = wk;
+            e.diag = 0;
+            pblocks.push_back(e);
+            for (int tn = 0; tn < (wk + kEvalTile - 1) / kEvalTile; ++tn)
+              for (int tm = 0; tm < (m + kEvalTile - 1) / kEvalTile; ++tm)
+                ptiles.push_back({(int)pblocks.size() - 1, tm, tn});
+          }
+        }
+        tb.add(lu, hg->DL(j), static_cast<const int32_t*>(hg->leafPerm.p) + h->na[lf], m,
+               h->S[j], kin, m, m, kin, m, slab, m);
+        proj.begin(offv(hg->psw.p, h->psw_off[lf], es), h->s[lf], h->s[lf], h->S[j], 1.0, 0.0);
+        proj.seg(offv(hg->Pt(), h->p_off[lf], es), m, true, slab, m, m);
       }
-      if (L == 0) continue;
-      void* slab = offv(h->slab.p, h->slab_off[j], es);
-      for (int k = L; k >= 1; --k) {
-        const int c = h->anc(lf, k);
-        const int wk = h->w[c];
-        EvalBlock e{};
-        e.out = offv(slab, (int64_t)h->colk[j][k] * m, es);
-        e.ld = m;
-        e.row0 = h->na[lf];
-        e.cols = skd + h->skel_off[h->sib(c)];
-        e.rows = m;
-        e.ncols = wk;
-        e.diag = 0;
-        pblocks.push_back(e);
-        for (int tn = 0; tn < (wk + kEvalTile - 1) / kEvalTile; ++tn)
-          for (int tm = 0; tm < (m + kEvalTile - 1) / kEvalTile; ++tm)
-            ptiles.push_back({(int)pblocks.size() - 1, tm, tn});
-      }
-      tb.add(offv(h->leafLU.p, h->lu_off[j], es), h->DL(j), lperm + h->na[lf], m, h->S[j], slab, m,
-             m, slab, m, slab, m);
-      proj.begin(offv(PS, h->psw_off[lf], es), h->s[lf], h->s[lf], h->S[j], 1.0, 0.0);
-      proj.seg(offv(Pt, h->p_off[lf], es), m, true, slab, m, m);
     }
     fp.leaf_eval.blocks = ar.add(lblocks);
     fp.leaf_eval.tiles = ar.add(ltiles);
     fp.leaf_eval.ntiles = (int)ltiles.size();
     fp.leaf_eval.nblocks = (int)lblocks.size();
+    fp.leaf_copy.probs = ar.add(copies);
+    fp.leaf_copy.count = (int)copies.size();
     // largest matrices first: one workgroup per matrix, so the launch's tail
     // is set by the matrices dispatched last
     auto by_order = [](const LuProb& x, const LuProb& y) { return x.n > y.n; };
@@ -838,6 +933,7 @@ int plan_factor(H* h) {
     fp.panels.blocks = ar.add(pblocks);
     fp.panels.tiles = ar.add(ptiles);
     fp.panels.ntiles = (int)ptiles.size();
+    fp.panels.nblocks = (int)pblocks.size();
     fp.leaf_trsm[0] = tb.emit(ar, T64, T64, 0, 16);
     fp.leaf_trsm[1] = tb.emit(ar, T64, T64, 0, 32);
     fp.leaf_proj = proj.emit(ar);
@@ -856,41 +952,48 @@ int plan_factor(H* h) {
     GemmBuilder pg;
     int nmax = 0;
     const size_t zes = h->zis64[jl] ? 8 : es;
-    for (int a = (1 << jl) - 1; a < (2 << jl) - 1; ++a) {
-      for (int jb = 0; jb < h->z[a]; jb += kDiagBlock) {
-        DiagInvProb d{};
-        d.lu = h->Z(a);
-        d.perm = zpm + h->zperm_off[a];
-        d.out = offv(const_cast<void*>(h->DZ(a)), (jb / kDiagBlock) * kDB2, zes);
-        d.n = h->z[a];
-        d.jb = jb;
-        zd.push_back(d);
-      }
-      const int l = 2 * a + 1, r = 2 * a + 2;
-      ZformProb p{};
-      p.Z = h->Zm(a);
-      p.pr = offv(PS, h->psw_off[r], es);  // first columns: factor level jl+1
-      p.pl = offv(PS, h->psw_off[l], es);
-      p.sr = h->s[r];
-      p.sl = h->s[l];
-      zf.push_back(p);
-      LuProb q{};
-      q.a = h->Zm(a);
-      q.perm = zpm + h->zperm_off[a];
-      q.info = static_cast<int32_t*>(h->zinfo.p) + a;
-      q.n = h->z[a];
-      zl.push_back(q);
-      nmax = std::max(nmax, h->z[a]);
-      if (jl >= 1) {
-        void* y = offv(YS, h->ysw_off[a], es);
-        zs.add(h->Z(a), h->DZ(a), zpm + h->zperm_off[a], h->z[a], h->Ssw[a],
-               offv(PS, h->psw_off[r] + (int64_t)h->colp[r][jl] * h->s[r], es), h->s[r], h->s[r],
-               offv(PS, h->psw_off[l] + (int64_t)h->colp[l][jl] * h->s[l], es), h->s[l], y,
-               h->z[a]);
-        pg.begin(offv(PS, h->psw_off[a], es), h->s[a], h->s[a], h->Ssw[a], 1.0, 0.0);
-        const void* Pa = offv(Pt, h->p_off[a], es);
-        pg.seg(Pa, h->z[a], true, offv(y, h->s[r], es), h->z[a], h->s[l]);
-        pg.seg(offv(const_cast<void*>(Pa), h->s[l], es), h->z[a], true, y, h->z[a], h->s[r]);
+    for (size_t g = 0; g < hs.size(); ++g) {
+      H* hg = hs[g];
+      int32_t* zpm = static_cast<int32_t*>(hg->zperm.p);
+      void* PS = hg->psw.p;
+      void* YS = hg->ysw.p;
+      const void* Pt = hg->Pt();
+      for (int a = (1 << jl) - 1; a < (2 << jl) - 1; ++a) {
+        for (int jb = 0; jb < h->z[a]; jb += kDiagBlock) {
+          DiagInvProb d{};
+          d.lu = hg->Z(a);
+          d.perm = zpm + h->zperm_off[a];
+          d.out = offv(hg->DZ(a), (jb / kDiagBlock) * kDB2, zes);
+          d.n = h->z[a];
+          d.jb = jb;
+          zd.push_back(d);
+        }
+        const int l = 2 * a + 1, r = 2 * a + 2;
+        ZformProb p{};
+        p.Z = hg->Zm(a);
+        p.pr = offv(PS, h->psw_off[r], es);  // first columns: factor level jl+1
+        p.pl = offv(PS, h->psw_off[l], es);
+        p.sr = h->s[r];
+        p.sl = h->s[l];
+        zf.push_back(p);
+        LuProb q{};
+        q.a = hg->Zm(a);
+        q.perm = zpm + h->zperm_off[a];
+        q.info = static_cast<int32_t*>(hg->zinfo.p) + a;
+        q.n = h->z[a];
+        zl.push_back(q);
+        nmax = std::max(nmax, h->z[a]);
+        if (jl >= 1) {
+          void* y = offv(YS, h->ysw_off[a], es);
+          zs.add(hg->Z(a), hg->DZ(a), zpm + h->zperm_off[a], h->z[a], h->Ssw[a],
+                 offv(PS, h->psw_off[r] + (int64_t)h->colp[r][jl] * h->s[r], es), h->s[r],
+                 h->s[r], offv(PS, h->psw_off[l] + (int64_t)h->colp[l][jl] * h->s[l], es),
+                 h->s[l], y, h->z[a]);
+          pg.begin(offv(PS, h->psw_off[a], es), h->s[a], h->s[a], h->Ssw[a], 1.0, 0.0);
+          const void* Pa = offv(Pt, h->p_off[a], es);
+          pg.seg(Pa, h->z[a], true, offv(y, h->s[r], es), h->z[a], h->s[l]);
+          pg.seg(offv(Pa, h->s[l], es), h->z[a], true, y, h->z[a], h->s[r]);
+        }
       }
     }
     ZformL& zfl = fp.zform[jl];
@@ -914,13 +1017,18 @@ int plan_factor(H* h) {
       fp.pgemm[jl] = pg.emit(ar);
     }
   }
-  if ((rc = dev_alloc(h, h->ftables, ar.host.size()))) return rc;
-  HIP_TRY(h, hipMemcpy(h->ftables.p, ar.host.data(), ar.host.size(), hipMemcpyHostToDevice));
-  return INVASKIT_OK;
+}
+
+// Size of one handle's factor tables (a placeholder-base planning run).
+size_t factor_table_bytes(H* h, const KernelCache* kc) {
+  Arena ar;
+  FactorPlan fp;
+  build_factor_tables({h}, kc, ar, fp);
+  return ar.bytes();
 }
 
 // ---------------------------------------------------------------- launching
-hipError_t run_gemm(const DevBuf& tb, const GemmL& l, bool f64, hipStream_t s) {
+hipError_t run_gemm(const Buf& tb, const GemmL& l, bool f64, hipStream_t s) {
   const GemmProb* p = at<GemmProb>(tb, l.probs);
   const GemmSeg* g = at<GemmSeg>(tb, l.segs);
   if (l.gemv)
@@ -935,7 +1043,7 @@ hipError_t run_gemm(const DevBuf& tb, const GemmL& l, bool f64, hipStream_t s) {
   return e;
 }
 
-hipError_t run_trsm(const DevBuf& tb, const TrsmL& l, hipStream_t s) {
+hipError_t run_trsm(const Buf& tb, const TrsmL& l, hipStream_t s) {
   if (l.ntiles == 0) return hipSuccess;
   if (l.ntiles < 0) return hipErrorInvalidValue;
   const TrsmProb* p = at<TrsmProb>(tb, l.probs);
@@ -946,7 +1054,7 @@ hipError_t run_trsm(const DevBuf& tb, const TrsmL& l, hipStream_t s) {
   return launch_getrs<float, float>(p, t, l.ntiles, l.nmax, l.kind, l.cols, s);
 }
 
-hipError_t run_lu(const DevBuf& tb, const LuL& l, hipStream_t s) {
+hipError_t run_lu(const Buf& tb, const LuL& l, hipStream_t s) {
   if (l.count == 0) return hipSuccess;
   if (l.t64)
     return launch_getrf<double>(at<LuProb>(tb, l.probs), l.count, l.nmax, l.kind, l.panel,
@@ -955,13 +1063,13 @@ hipError_t run_lu(const DevBuf& tb, const LuL& l, hipStream_t s) {
                              s);
 }
 
-hipError_t run_dinv(const DevBuf& tb, const DinvL& l, hipStream_t s) {
+hipError_t run_dinv(const Buf& tb, const DinvL& l, hipStream_t s) {
   if (l.count == 0) return hipSuccess;
   if (l.t64) return launch_diag_inv<double>(at<DiagInvProb>(tb, l.probs), l.count, s);
   return launch_diag_inv<float>(at<DiagInvProb>(tb, l.probs), l.count, s);
 }
 
-hipError_t run_zform(const DevBuf& tb, const ZformL& l, hipStream_t s) {
+hipError_t run_zform(const Buf& tb, const ZformL& l, hipStream_t s) {
   if (l.count == 0) return hipSuccess;
   const ZformProb* p = at<ZformProb>(tb, l.probs);
   if (l.tz64 && l.tv64) return launch_zform<double, double>(p, l.count, s);
@@ -969,7 +1077,7 @@ hipError_t run_zform(const DevBuf& tb, const ZformL& l, hipStream_t s) {
   return launch_zform<float, float>(p, l.count, s);
 }
 
-hipError_t run_eval(H* h, const DevBuf& tb, const EvalL& l, double shift, hipStream_t s) {
+hipError_t run_eval(H* h, const Buf& tb, const EvalL& l, double shift, hipStream_t s) {
   if (l.ntiles == 0) return hipSuccess;
   const EvalBlock* b = at<EvalBlock>(tb, l.blocks);
   const Tile3* t = at<Tile3>(tb, l.tiles);
@@ -982,6 +1090,13 @@ hipError_t run_eval(H* h, const DevBuf& tb, const EvalL& l, double shift, hipStr
   const float* X = static_cast<const float*>(h->X);
   return f64 ? launch_eval<float, double>(X, h->d, h->h, shift, b, t, l.ntiles, s)
              : launch_eval<float, float>(X, h->d, h->h, shift, b, t, l.ntiles, s);
+}
+
+hipError_t run_copy_shift(H* h, const Buf& tb, const CopyShiftL& l, hipStream_t s) {
+  if (l.count == 0) return hipSuccess;
+  const CopyShiftProb* p = at<CopyShiftProb>(tb, l.probs);
+  return h->prec == INVASKIT_PREC_FP64 ? launch_copy_shift<double>(p, l.count, s)
+                                       : launch_copy_shift<float>(p, l.count, s);
 }
 
 // ---------------------------------------------------------------- autotuning
@@ -1014,9 +1129,8 @@ std::string trsm_key(const TrsmL& l) {
 // factor's stream; each candidate runs twice and keeps its faster time.  The
 // trials leave the factor buffers in an arbitrary state: the factorization
 // that follows rebuilds them.
-int tune_factor(H* h) {
-  const FactorPlan& fp = h->fp;
-  const DevBuf& tb = h->ftables;
+int tune_factor(H* h, const FactorPlan& fp) {
+  const Buf& tb = fp.tables;
   const bool f64 = h->prec == INVASKIT_PREC_FP64;
   hipStream_t s = h->stream;
   invaskit_tile_config& tc = h->tiles;
@@ -1074,7 +1188,12 @@ int tune_factor(H* h) {
         if (e == hipSuccess && (best == 0.f || ms < best)) best = ms;
       }
     };
-    auto eval_leaves = [&]() { return run_eval(h, tb, fp.leaf_eval, h->lam, s); };
+    // the LU works in place: every trial starts from fresh leaf blocks (a
+    // cached plan copies them from the evaluated cache)
+    auto eval_leaves = [&]() {
+      return fp.cached ? run_copy_shift(h, tb, fp.leaf_copy, s)
+                       : run_eval(h, tb, fp.leaf_eval, h->lam, s);
+    };
     auto lu_with = [&](int panel, int waves) {
       LuL l = fp.leaf_lu;
       l.panel = panel;
@@ -1106,7 +1225,10 @@ int tune_factor(H* h) {
       e = eval_leaves();
       if (e == hipSuccess) e = lu_with(lu, lw);
       if (e == hipSuccess) e = run_dinv(tb, fp.leaf_dinv, s);
-      auto eval_panels = [&]() { return run_eval(h, tb, fp.panels, 0.0, s); };
+      // in place unless the solves read the cache
+      auto eval_panels = [&]() {
+        return fp.cached ? hipSuccess : run_eval(h, tb, fp.panels, 0.0, s);
+      };
       trial(eval_panels, [&]() { return run_trsm(tb, fp.leaf_trsm[0], s); }, tc.trsm_ms[0]);
       trial(eval_panels, [&]() { return run_trsm(tb, fp.leaf_trsm[1], s); }, tc.trsm_ms[1]);
       tr = tc.trsm_ms[1] < tc.trsm_ms[0] ? 32 : 16;
@@ -1131,20 +1253,24 @@ int tune_factor(H* h) {
   return INVASKIT_OK;
 }
 
-int run_factor(H* h) {
+// Runs the factorization plan `fp` over the handles `hs` (hs[0] leads: its
+// stream, second stream, events and tile choices serve the launches).  A
+// cached plan first makes sure the sweep's lambda-free kernel blocks are
+// evaluated.  Phase times are recorded in every member.
+int run_factor(const std::vector<H*>& hs, const FactorPlan& fp, KernelCache* kc) {
+  H* h = hs[0];
   hipStream_t s = h->stream;
   const bool f64 = h->prec == INVASKIT_PREC_FP64;
-  const DevBuf& tb = h->ftables;
+  const Buf& tb = fp.tables;
   if (!h->have_events) {
     for (auto& e : h->ev) HIP_TRY(h, hipEventCreate(&e));
     h->have_events = true;
   }
   if (!h->side) HIP_TRY(h, hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
   hipStream_t s2 = h->side;
-  if (int rc = tune_factor(h)) return rc;
   // Phase timing: each phase is bracketed by two events on the stream it
   // runs on; phases on the two streams overlap, so they need not sum to the
-  // total.  `sync` events order the streams.
+  // total.  `join` events order the streams.
   struct Bracket {
     hipEvent_t a, b;
     int phase;
@@ -1159,6 +1285,7 @@ int run_factor(H* h) {
   };
   auto cleanup = [&]() {
     for (auto e : pool) hipEventDestroy(e);
+    pool.clear();
   };
 #define STEP(...)                                                                 \
   do {                                                                            \
@@ -1188,51 +1315,46 @@ int run_factor(H* h) {
     hipError_t r = hipEventRecord(e, from);
     return r == hipSuccess ? hipStreamWaitEvent(to, e, 0) : r;
   };
-
-  const FactorPlan& fp = h->fp;
   const int L = h->L;
+  // a plain plan settles its tiles first: the trials work in place on the
+  // factor storage, and the factorization below starts from fresh blocks
+  if (!fp.cached)
+    if (int rc = tune_factor(h, fp)) return rc;
   hipEvent_t t_begin = new_event(hipEventDefault), t_end = new_event(hipEventDefault);
   if (!t_begin || !t_end) STEP(hipErrorOutOfMemory);
   STEP(hipEventRecord(t_begin, s));
   // the side stream starts after everything already on the caller's stream
   STEP(join(s, s2));
-  // Kernel blocks.  A sweep handle evaluates them without lambda once into
-  // the shared cache and afterwards copies them back; lambda is then added
-  // to the leaf diagonals.
-  KernelCache* kc = h->kcache.get();
-  const bool cached = kc && kc->valid;
-  const size_t es = h->tsize();
-  if (L > 0) {
-    STEP(open(3, s2));
-    if (cached) {
-      STEP(hipMemcpyAsync(h->slab.p, kc->slab.p, h->slab_off[h->nleaves] * es,
-                          hipMemcpyDeviceToDevice, s2));
-    } else {
+  const bool eval_now = !fp.cached || !kc->valid;
+  if (eval_now) {
+    // kernel blocks (into the factor storage, or once into a sweep's cache)
+    if (L > 0) {
+      STEP(open(3, s2));
       STEP(run_eval(h, tb, fp.panels, 0.0, s2));
-      if (kc)
-        STEP(hipMemcpyAsync(kc->slab.p, h->slab.p, h->slab_off[h->nleaves] * es,
-                            hipMemcpyDeviceToDevice, s2));
+      STEP(close(s2));
     }
-    STEP(close(s2));
+    if (!f64 && h->p_off[h->nn] > 0)
+      STEP(launch_convert_f64_f32(h->P64, static_cast<float*>(const_cast<void*>(h->Pf)),
+                                  h->p_off[h->nn], s));
+    STEP(open(0, s));
+    STEP(run_eval(h, tb, fp.leaf_eval, fp.cached ? 0.0 : h->lam, s));
+    STEP(close(s));
   }
-  if (!f64 && h->P32.p && h->p_off[h->nn] > 0)
-    STEP(launch_convert_f64_f32(h->P64, static_cast<float*>(h->P32.p), h->p_off[h->nn], s));
-  STEP(open(0, s));
-  if (!kc) {
-    STEP(run_eval(h, tb, fp.leaf_eval, h->lam, s));
-  } else {
-    const size_t lb = h->lu_off[h->nleaves] * es;
-    if (cached) {
-      STEP(hipMemcpyAsync(h->leafLU.p, kc->leaf.p, lb, hipMemcpyDeviceToDevice, s));
-    } else {
-      STEP(run_eval(h, tb, fp.leaf_eval, 0.0, s));
-      STEP(hipMemcpyAsync(kc->leaf.p, h->leafLU.p, lb, hipMemcpyDeviceToDevice, s));
+  if (fp.cached) {
+    if (eval_now) {
+      STEP(join(s2, s));
+      STEP(hipStreamSynchronize(s));
+      kc->valid = true;
     }
-    const EvalBlock* lbk = at<EvalBlock>(tb, fp.leaf_eval.blocks);
-    STEP(f64 ? launch_shift_diag<double>(lbk, fp.leaf_eval.nblocks, h->lam, s)
-             : launch_shift_diag<float>(lbk, fp.leaf_eval.nblocks, h->lam, s));
+    // the tile choices need the evaluated cache (their trials copy from it)
+    if (int rc = tune_factor(h, fp)) {
+      cleanup();
+      return rc;
+    }
+    STEP(open(0, s));
+    STEP(run_copy_shift(h, tb, fp.leaf_copy, s));
+    STEP(close(s));
   }
-  STEP(close(s));
   STEP(open(1, s));
   {
     LuL lu = fp.leaf_lu;
@@ -1269,193 +1391,60 @@ int run_factor(H* h) {
   }
   STEP(hipEventRecord(t_end, s));
   STEP(hipStreamSynchronize(s));
-  if (kc) kc->valid = true;
-  for (double& v : h->phase_ms) v = 0.0;
-  h->phase_ms[7] = h->plan_ms;
+  double ms_ph[kPhases] = {0};
   for (const Bracket& br : brackets) {
     float ms = 0.f;
-    if (br.a && br.b && hipEventElapsedTime(&ms, br.a, br.b) == hipSuccess)
-      h->phase_ms[br.phase] += ms;
+    if (br.a && br.b && hipEventElapsedTime(&ms, br.a, br.b) == hipSuccess) ms_ph[br.phase] += ms;
   }
   {
     float ms = 0.f;
-    if (hipEventElapsedTime(&ms, t_begin, t_end) == hipSuccess) h->phase_ms[kPhases - 1] = ms;
+    if (hipEventElapsedTime(&ms, t_begin, t_end) == hipSuccess) ms_ph[kPhases - 1] = ms;
   }
   cleanup();
 #undef STEP
-  // pivot status
-  std::vector<int32_t> li(h->nleaves), zi(std::max((1 << h->L) - 1, 0));
-  HIP_TRY(h, hipMemcpy(li.data(), h->leafInfo.p, sizeof(int32_t) * li.size(), hipMemcpyDeviceToHost));
-  if (!zi.empty())
-    HIP_TRY(h, hipMemcpy(zi.data(), h->zinfo.p, sizeof(int32_t) * zi.size(), hipMemcpyDeviceToHost));
-  for (int j = 0; j < h->nleaves; ++j)
-    if (li[j])
-      return fail_h(h, INVASKIT_E_SINGULAR,
-                    "zero pivot: leaf block of node " + std::to_string(h->leaf_node(j)) + " column " +
-                        std::to_string(li[j] - 1));
-  for (size_t a = 0; a < zi.size(); ++a)
-    if (zi[a])
-      return fail_h(h, INVASKIT_E_SINGULAR,
+  // pivot status of every member
+  int status = INVASKIT_OK;
+  for (H* hg : hs) {
+    for (int i = 0; i < kPhases; ++i) hg->phase_ms[i] = ms_ph[i];
+    hg->phase_ms[7] = hg->plan_ms;
+    hg->tiles = h->tiles;
+    std::vector<int32_t> li(hg->nleaves), zi(std::max((1 << hg->L) - 1, 0));
+    HIP_TRY(h, hipMemcpy(li.data(), hg->leafInfo.p, sizeof(int32_t) * li.size(),
+                         hipMemcpyDeviceToHost));
+    if (!zi.empty())
+      HIP_TRY(h, hipMemcpy(zi.data(), hg->zinfo.p, sizeof(int32_t) * zi.size(),
+                           hipMemcpyDeviceToHost));
+    int rc = INVASKIT_OK;
+    for (int j = 0; j < hg->nleaves && !rc; ++j)
+      if (li[j])
+        rc = fail_h(hg, INVASKIT_E_SINGULAR,
+                    "zero pivot: leaf block of node " + std::to_string(hg->leaf_node(j)) +
+                        " column " + std::to_string(li[j] - 1));
+    for (size_t a = 0; a < zi.size() && !rc; ++a)
+      if (zi[a])
+        rc = fail_h(hg, INVASKIT_E_SINGULAR,
                     "zero pivot: reduced system of node " + std::to_string(a) + " column " +
                         std::to_string(zi[a] - 1));
-  return INVASKIT_OK;
+    if (rc && status == INVASKIT_OK) status = rc;
+  }
+  return status;
 }
 
 // ------------------------------------------------------------ solve plans
-int build_solve_plan(H* h, int r, SolvePlan*& out) {
-  auto it = h->solve_plans.find(r);
-  if (it != h->solve_plans.end()) {
-    out = it->second.get();
-    return INVASKIT_OK;
-  }
-  auto sp = std::make_unique<SolvePlan>();
-  sp->r = r;
+// Matvec tables (Skeletonize weights q = P [q_l; q_r] up the tree, then the
+// fused Evaluate pass) for the plan's r columns, appended to `ar`.
+void build_mv_tables(H* h, MatvecPlan& mp, Arena& ar) {
   const int L = h->L;
-  const size_t es = h->tsize();
-  const int T64 = (h->prec == INVASKIT_PREC_FP64) ? 1 : 0;
-  std::vector<int64_t> sp_off(h->nn, 0), sy_off(h->nn, 0);
-  int64_t off = 0;
-  for (int c = 1; c < h->nn; ++c) {
-    sp_off[c] = off;
-    off += (int64_t)h->s[c] * r;
-  }
-  for (int c = 0; c < (1 << L) - 1; ++c) {
-    sy_off[c] = off;
-    off += (int64_t)h->z[c] * r;
-  }
-  int rc;
-  if ((rc = dev_alloc(h, sp->xbuf, (size_t)h->N * r * es))) return rc;
-  if ((rc = dev_alloc(h, sp->sbuf, std::max<int64_t>(off, 1) * es))) return rc;
-  if ((rc = dev_alloc(h, sp->x64, (size_t)h->N * r * 8))) return rc;
-  if ((rc = dev_alloc(h, sp->r64, (size_t)h->N * r * 8))) return rc;
-  if ((rc = dev_alloc(h, sp->sc, sizeof(double) * r))) return rc;
-  if ((rc = dev_alloc(h, sp->gpart,
-                      sizeof(double) * dots_part_doubles(h->N, h->gm_restart + 1, r))))
-    return rc;
-  if ((rc = dev_alloc(h, sp->gsmall, sizeof(double) * (size_t)r * (4 * h->gm_restart + 3))))
-    return rc;
-  void* xb = sp->xbuf.p;
-  void* sb = sp->sbuf.p;
-  const int32_t* lperm = static_cast<const int32_t*>(h->leafPerm.p);
-  int32_t* zpm = static_cast<int32_t*>(h->zperm.p);
-  Arena ar;
-  TrsmBuilder lt;
-  GemmBuilder lpj, fin;
-  for (int j = 0; j < h->nleaves; ++j) {
-    const int lf = h->leaf_node(j);
-    const int m = (int)(h->nb[lf] - h->na[lf]);
-    void* xr = offv(xb, h->na[lf], es);
-    lt.add(offv(h->leafLU.p, h->lu_off[j], es), h->DL(j), lperm + h->na[lf], m, r, xr, h->N, m, xr,
-           h->N, xr,
-           h->N);
-    if (L > 0) {
-      lpj.begin(offv(sb, sp_off[lf], es), h->s[lf], h->s[lf], r, 1.0, 0.0);
-      lpj.seg(offv(const_cast<void*>(h->Pt()), h->p_off[lf], es), m, true, xr, h->N, m);
-      fin.begin(xr, h->N, m, r, -1.0, 1.0);
-      for (int jl = L; jl >= 1; --jl) {
-        const int cj = h->anc(lf, jl);
-        const int par = h->anc(lf, jl - 1);
-        const int yoff = (cj & 1) ? 0 : h->s[cj];
-        fin.seg(offv(h->slab.p, h->slab_off[j] + (int64_t)h->colk[j][jl] * m, es), m, false,
-                offv(sb, sy_off[par] + yoff, es), h->z[par], h->w[cj]);
-      }
-    }
-  }
-  sp->leaf_trsm = lt.emit(ar, T64, T64, 2);
-  sp->leaf_proj = lpj.emit(ar);
-  for (int jl = L - 1; jl >= 0; --jl) {
-    TrsmBuilder zs;
-    GemmBuilder pg;
-    for (int bnode = (1 << jl) - 1; bnode < (2 << jl) - 1; ++bnode) {
-      const int l = 2 * bnode + 1, rr = 2 * bnode + 2;
-      void* y = offv(sb, sy_off[bnode], es);
-      zs.add(h->Z(bnode), h->DZ(bnode), zpm + h->zperm_off[bnode], h->z[bnode], r,
-             offv(sb, sp_off[rr], es),
-             h->s[rr], h->s[rr], offv(sb, sp_off[l], es), h->s[l], y, h->z[bnode]);
-      if (jl > 0) {
-        pg.begin(offv(sb, sp_off[bnode], es), h->s[bnode], h->s[bnode], r, 1.0, 0.0);
-        const void* Pb = offv(const_cast<void*>(h->Pt()), h->p_off[bnode], es);
-        pg.seg(Pb, h->z[bnode], true, offv(y, h->s[rr], es), h->z[bnode], h->s[l]);
-        pg.seg(offv(const_cast<void*>(Pb), h->s[l], es), h->z[bnode], true, y, h->z[bnode],
-               h->s[rr]);
-      }
-    }
-    sp->zsolve.push_back(zs.emit(ar, h->zis64[jl], T64, 2));
-    sp->pgemm.push_back(pg.emit(ar));
-  }
-  // Top-down pass, levels i = 2 .. L: e_c = y^_c - sum_{j<i} Y^(i,j) e_{anc_j(c)},
-  // in place of y^_c (the segment of the parent's solve y paired with the
-  // sibling's skeleton).  Y^(i,j): rows of c in the parent's factor sweep
-  // solution, columns of factor level j.  Level 1 needs no correction.
-  const void* YS = h->ysw.p;
-  auto yseg = [&](int c) {  // offset of c's segment inside its parent's y
-    return (c & 1) ? 0 : h->s[c];
-  };
-  for (int i = 2; i <= L; ++i) {
-    GemmBuilder td;
-    for (int c = (1 << i) - 1; c < (2 << i) - 1; ++c) {
-      const int par = (c - 1) / 2;
-      const int wc = h->w[c];
-      td.begin(offv(sb, sy_off[par] + yseg(c), es), h->z[par], wc, r, -1.0, 1.0);
-      for (int j = 1; j < i; ++j) {
-        const int cj = h->anc(c, j);
-        const int pj = h->anc(c, j - 1);
-        td.seg(offv(const_cast<void*>(YS),
-                    h->ysw_off[par] + (int64_t)h->colp[par][j] * h->z[par] + yseg(c), es),
-               h->z[par], false, offv(sb, sy_off[pj] + yseg(cj), es), h->z[pj], h->w[cj]);
-      }
-    }
-    sp->topdown.push_back(td.emit(ar));
-  }
-  sp->final_ = fin.emit(ar);
-  if ((rc = dev_alloc(h, sp->tables, ar.host.size()))) return rc;
-  HIP_TRY(h, hipMemcpy(sp->tables.p, ar.host.data(), ar.host.size(), hipMemcpyHostToDevice));
-  out = sp.get();
-  h->solve_plans[r] = std::move(sp);
-  return INVASKIT_OK;
-}
-
-// the direct solve on sp->xbuf, in place, in the factor precision
-int run_solve_plan(H* h, SolvePlan* sp) {
-  hipStream_t s = h->stream;
-  const bool f64 = h->prec == INVASKIT_PREC_FP64;
-  const DevBuf& tb = sp->tables;
-  HIP_TRY(h, run_trsm(tb, sp->leaf_trsm, s));
-  if (h->L == 0) return INVASKIT_OK;
-  HIP_TRY(h, run_gemm(tb, sp->leaf_proj, f64, s));
-  for (size_t q = 0; q < sp->zsolve.size(); ++q) {
-    HIP_TRY(h, run_trsm(tb, sp->zsolve[q], s));
-    HIP_TRY(h, run_gemm(tb, sp->pgemm[q], f64, s));
-  }
-  for (const GemmL& g : sp->topdown) HIP_TRY(h, run_gemm(tb, g, f64, s));
-  HIP_TRY(h, run_gemm(tb, sp->final_, f64, s));
-  return INVASKIT_OK;
-}
-
-// ------------------------------------------------------------ matvec plans
-int build_mv_plan(H* h, int r, MatvecPlan*& out) {
-  auto it = h->mv_plans.find(r);
-  if (it != h->mv_plans.end()) {
-    out = it->second.get();
-    return INVASKIT_OK;
-  }
-  auto mp = std::make_unique<MatvecPlan>();
-  mp->r = r;
-  const int L = h->L;
+  const int r = mp.r;
   std::vector<int64_t> q_off(h->nn, 0);
   int64_t off = 0;
   for (int c = 1; c < h->nn; ++c) {
     q_off[c] = off;
     off += (int64_t)h->s[c] * r;
   }
-  int rc;
-  if ((rc = dev_alloc(h, mp->xm, (size_t)h->N * r * 8))) return rc;
-  if ((rc = dev_alloc(h, mp->q, std::max<int64_t>(off, 1) * 8))) return rc;
-  double* xm = static_cast<double*>(mp->xm.p);
-  double* q = static_cast<double*>(mp->q.p);
-  const int32_t* skd = static_cast<const int32_t*>(h->skel_d.p);
-  Arena ar;
-  // Skeletonize (weight part), levels L .. 1
+  double* xm = static_cast<double*>(mp.xm.p);
+  double* q = static_cast<double*>(mp.q.p);
+  mp.skel.clear();
   for (int k = L; k >= 1; --k) {
     GemmBuilder gb;
     for (int c = (1 << k) - 1; c < (2 << k) - 1; ++c) {
@@ -1470,7 +1459,7 @@ int build_mv_plan(H* h, int r, MatvecPlan*& out) {
         gb.seg(Pc + h->s[l], h->z[c], true, q + q_off[rr], h->s[rr], h->s[rr]);
       }
     }
-    mp->skel.push_back(gb.emit(ar));
+    mp.skel.push_back(gb.emit(ar));
   }
   // Evaluate: per leaf, its own block plus one skeleton segment per level
   std::vector<MvSeg> segs;
@@ -1490,7 +1479,7 @@ int build_mv_plan(H* h, int r, MatvecPlan*& out) {
       const int c = h->anc(lf, k);
       const int cs = h->sib(c);
       MvSeg t{};
-      t.idx = skd + h->skel_off[cs];
+      t.idx = h->skd + h->skel_off[cs];
       t.p0 = 0;
       t.w = q + q_off[cs];
       t.ldw = h->s[cs];
@@ -1507,32 +1496,221 @@ int build_mv_plan(H* h, int r, MatvecPlan*& out) {
       tiles.push_back(t);
     }
   }
-  mp->mv_segs = ar.add(segs);
-  mp->mv_tiles = ar.add(tiles);
-  mp->n_mv_tiles = (int)tiles.size();
-  if ((rc = dev_alloc(h, mp->tables, ar.host.size()))) return rc;
-  HIP_TRY(h, hipMemcpy(mp->tables.p, ar.host.data(), ar.host.size(), hipMemcpyHostToDevice));
-  out = mp.get();
-  h->mv_plans[r] = std::move(mp);
+  mp.mv_segs = ar.add(segs);
+  mp.mv_tiles = ar.add(tiles);
+  mp.n_mv_tiles = (int)tiles.size();
+}
+
+int64_t skel_entries(const H* h) {  // sum of s_c over the non-root nodes
+  int64_t t = 0;
+  for (int c = 1; c < h->nn; ++c) t += h->s[c];
+  return t;
+}
+
+// The plan of a solve (or, solve == false, of a matvec) with r right-hand
+// sides whose scratch starts at `base`.  Scratch order: vectors, descriptor
+// tables, then (solves) the GMRES bases, which a smaller scratch may leave
+// out.
+std::unique_ptr<SolvePlan> make_solve_plan(H* h, int r, bool solve, unsigned char* base) {
+  auto sp = std::make_unique<SolvePlan>();
+  sp->r = r;
+  sp->solve = solve;
+  sp->base = base;
+  const int L = h->L;
+  const size_t es = h->tsize();
+  const int T64 = (h->prec == INVASKIT_PREC_FP64) ? 1 : 0;
+  Carve cv;
+  auto put = [&](Buf& b, size_t bytes) {
+    const size_t o = cv.take(bytes);
+    b.p = base + o;
+    b.bytes = bytes;
+  };
+  const size_t nr = (size_t)h->N * r;
+  std::vector<int64_t> sp_off(h->nn, 0), sy_off(h->nn, 0);
+  int64_t off = 0;
+  for (int c = 1; c < h->nn; ++c) {
+    sp_off[c] = off;
+    off += (int64_t)h->s[c] * r;
+  }
+  for (int c = 0; c < (1 << L) - 1; ++c) {
+    sy_off[c] = off;
+    off += (int64_t)h->z[c] * r;
+  }
+  if (solve) {
+    put(sp->xbuf, nr * es);
+    put(sp->sbuf, std::max<int64_t>(off, 1) * es);
+    put(sp->x64, nr * 8);
+    put(sp->r64, nr * 8);
+    put(sp->sc, sizeof(double) * r);
+    put(sp->gpart, sizeof(double) * dots_part_doubles(h->N, h->gm_restart + 1, r));
+    put(sp->gsmall, sizeof(double) * (size_t)r * (4 * h->gm_restart + 3));
+  }
+  sp->mv.r = r;
+  put(sp->mv.xm, nr * 8);
+  put(sp->mv.q, std::max<int64_t>(skel_entries(h) * r, 1) * 8);
+  Arena ar;
+  if (solve) {
+    void* xb = sp->xbuf.p;
+    void* sb = sp->sbuf.p;
+    const int32_t* lperm = static_cast<const int32_t*>(h->leafPerm.p);
+    const int32_t* zpm = static_cast<const int32_t*>(h->zperm.p);
+    TrsmBuilder lt;
+    GemmBuilder lpj, fin;
+    for (int j = 0; j < h->nleaves; ++j) {
+      const int lf = h->leaf_node(j);
+      const int m = (int)(h->nb[lf] - h->na[lf]);
+      void* xr = offv(xb, h->na[lf], es);
+      lt.add(offv(h->leafLU.p, h->lu_off[j], es), h->DL(j), lperm + h->na[lf], m, r, xr, h->N, m,
+             xr, h->N, xr, h->N);
+      if (L > 0) {
+        lpj.begin(offv(sb, sp_off[lf], es), h->s[lf], h->s[lf], r, 1.0, 0.0);
+        lpj.seg(offv(h->Pt(), h->p_off[lf], es), m, true, xr, h->N, m);
+        fin.begin(xr, h->N, m, r, -1.0, 1.0);
+        for (int jl = L; jl >= 1; --jl) {
+          const int cj = h->anc(lf, jl);
+          const int par = h->anc(lf, jl - 1);
+          const int yoff = (cj & 1) ? 0 : h->s[cj];
+          fin.seg(offv(h->slab.p, h->slab_off[j] + (int64_t)h->colk[j][jl] * m, es), m, false,
+                  offv(sb, sy_off[par] + yoff, es), h->z[par], h->w[cj]);
+        }
+      }
+    }
+    sp->leaf_trsm = lt.emit(ar, T64, T64, 2);
+    sp->leaf_proj = lpj.emit(ar);
+    for (int jl = L - 1; jl >= 0; --jl) {
+      TrsmBuilder zs;
+      GemmBuilder pg;
+      for (int bnode = (1 << jl) - 1; bnode < (2 << jl) - 1; ++bnode) {
+        const int l = 2 * bnode + 1, rr = 2 * bnode + 2;
+        void* y = offv(sb, sy_off[bnode], es);
+        zs.add(h->Z(bnode), h->DZ(bnode), zpm + h->zperm_off[bnode], h->z[bnode], r,
+               offv(sb, sp_off[rr], es), h->s[rr], h->s[rr], offv(sb, sp_off[l], es), h->s[l], y,
+               h->z[bnode]);
+        if (jl > 0) {
+          pg.begin(offv(sb, sp_off[bnode], es), h->s[bnode], h->s[bnode], r, 1.0, 0.0);
+          const void* Pb = offv(h->Pt(), h->p_off[bnode], es);
+          pg.seg(Pb, h->z[bnode], true, offv(y, h->s[rr], es), h->z[bnode], h->s[l]);
+          pg.seg(offv(Pb, h->s[l], es), h->z[bnode], true, y, h->z[bnode], h->s[rr]);
+        }
+      }
+      sp->zsolve.push_back(zs.emit(ar, h->zis64[jl], T64, 2));
+      sp->pgemm.push_back(pg.emit(ar));
+    }
+    // Top-down pass, levels i = 2 .. L: e_c = y^_c - sum_{j<i} Y^(i,j) e_{anc_j(c)},
+    // in place of y^_c (the segment of the parent's solve y paired with the
+    // sibling's skeleton).  Y^(i,j): rows of c in the parent's factor sweep
+    // solution, columns of factor level j.  Level 1 needs no correction.
+    const void* YS = h->ysw.p;
+    auto yseg = [&](int c) {  // offset of c's segment inside its parent's y
+      return (c & 1) ? 0 : h->s[c];
+    };
+    for (int i = 2; i <= L; ++i) {
+      GemmBuilder td;
+      for (int c = (1 << i) - 1; c < (2 << i) - 1; ++c) {
+        const int par = (c - 1) / 2;
+        const int wc = h->w[c];
+        td.begin(offv(sb, sy_off[par] + yseg(c), es), h->z[par], wc, r, -1.0, 1.0);
+        for (int j = 1; j < i; ++j) {
+          const int cj = h->anc(c, j);
+          const int pj = h->anc(c, j - 1);
+          td.seg(offv(YS, h->ysw_off[par] + (int64_t)h->colp[par][j] * h->z[par] + yseg(c), es),
+                 h->z[par], false, offv(sb, sy_off[pj] + yseg(cj), es), h->z[pj], h->w[cj]);
+        }
+      }
+      sp->topdown.push_back(td.emit(ar));
+    }
+    sp->final_ = fin.emit(ar);
+  }
+  build_mv_tables(h, sp->mv, ar);
+  put(sp->tables, ar.bytes());
+  sp->blob = std::move(ar.host);
+  sp->blob.resize(sp->tables.bytes, 0);
+  sp->min_bytes = cv.total();
+  if (solve) {
+    sp->gm_m = h->gm_restart;
+    put(sp->gmV, nr * 8 * (sp->gm_m + 1));
+    put(sp->gmZ, nr * 8 * sp->gm_m);
+  }
+  sp->full_bytes = cv.total();
+  return sp;
+}
+
+// The handle's plan for (r, solve) at scratch `base`, most recently used
+// first; at most four are kept.
+SolvePlan* get_solve_plan(H* h, int r, bool solve, unsigned char* base) {
+  for (auto it = h->plans.begin(); it != h->plans.end(); ++it)
+    if ((*it)->r == r && (*it)->solve == solve && (*it)->base == base) {
+      if (it != h->plans.begin()) h->plans.splice(h->plans.begin(), h->plans, it);
+      return h->plans.front().get();
+    }
+  h->plans.push_front(make_solve_plan(h, r, solve, base));
+  while (h->plans.size() > 4) {
+    if (h->up_plan == h->plans.back().get()) h->up_plan = nullptr;
+    h->plans.pop_back();
+  }
+  return h->plans.front().get();
+}
+
+// Puts the plan's tables into the scratch unless they are already there
+// (the previous call of this handle used the same plan and scratch).  For a
+// solve, sets the GMRES bases the scratch has room for.
+int bind_scratch(H* h, SolvePlan* sp, size_t scratch_bytes, bool force_upload) {
+  if (sp->solve) {
+    const size_t nr8 = (size_t)h->N * sp->r * 8;
+    const size_t v0 = static_cast<unsigned char*>(sp->gmV.p) - static_cast<unsigned char*>(sp->base);
+    sp->gm_m = 0;
+    for (int m = h->gm_restart; m >= 2; --m) {
+      const size_t need = v0 + align_up(nr8 * (m + 1), kAlign) + nr8 * m;
+      if (need <= scratch_bytes) {
+        sp->gm_m = m;
+        break;
+      }
+    }
+    if (sp->gm_m > 0)
+      sp->gmZ.p = static_cast<unsigned char*>(sp->gmV.p) + align_up(nr8 * (sp->gm_m + 1), kAlign);
+  }
+  if (force_upload || h->up_plan != sp || h->up_base != sp->base) {
+    HIP_TRY(h, hipMemcpyAsync(sp->tables.p, sp->blob.data(), sp->blob.size(),
+                              hipMemcpyHostToDevice, h->stream));
+    h->up_plan = force_upload ? nullptr : sp;
+    h->up_base = sp->base;
+  }
+  return INVASKIT_OK;
+}
+
+// the direct solve on sp->xbuf, in place, in the factor precision
+int run_solve_plan(H* h, SolvePlan* sp) {
+  hipStream_t s = h->stream;
+  const bool f64 = h->prec == INVASKIT_PREC_FP64;
+  const Buf& tb = sp->tables;
+  HIP_TRY(h, run_trsm(tb, sp->leaf_trsm, s));
+  if (h->L == 0) return INVASKIT_OK;
+  HIP_TRY(h, run_gemm(tb, sp->leaf_proj, f64, s));
+  for (size_t q = 0; q < sp->zsolve.size(); ++q) {
+    HIP_TRY(h, run_trsm(tb, sp->zsolve[q], s));
+    HIP_TRY(h, run_gemm(tb, sp->pgemm[q], f64, s));
+  }
+  for (const GemmL& g : sp->topdown) HIP_TRY(h, run_gemm(tb, g, f64, s));
+  HIP_TRY(h, run_gemm(tb, sp->final_, f64, s));
   return INVASKIT_OK;
 }
 
 // y = (lam I + K~) x  (or b - that when b != nullptr); x is copied first
-int run_matvec(H* h, MatvecPlan* mp, const double* x, int64_t ldx, double* y, int64_t ldy,
-               const double* b, int64_t ldb) {
+int run_matvec(H* h, const Buf& tb, const MatvecPlan& mp, const double* x, int64_t ldx, double* y,
+               int64_t ldy, const double* b, int64_t ldb) {
   hipStream_t s = h->stream;
-  const int r = mp->r;
-  double* xm = static_cast<double*>(mp->xm.p);
+  const int r = mp.r;
+  double* xm = static_cast<double*>(mp.xm.p);
   HIP_TRY(h, launch_copy_cols<double, double>(x, ldx, xm, h->N, h->N, r, nullptr, false, s));
-  for (const GemmL& g : mp->skel) HIP_TRY(h, run_gemm(mp->tables, g, true, s));
-  const MvTile* t = at<MvTile>(mp->tables, mp->mv_tiles);
-  const MvSeg* g = at<MvSeg>(mp->tables, mp->mv_segs);
+  for (const GemmL& g : mp.skel) HIP_TRY(h, run_gemm(tb, g, true, s));
+  const MvTile* t = at<MvTile>(tb, mp.mv_tiles);
+  const MvSeg* g = at<MvSeg>(tb, mp.mv_segs);
   if (h->pdt == INVASKIT_F64)
     HIP_TRY(h, launch_mv_eval<double>(static_cast<const double*>(h->X), h->d, h->h, h->lam, t,
-                                      mp->n_mv_tiles, g, xm, h->N, y, ldy, b, ldb, r, s));
+                                      mp.n_mv_tiles, g, xm, h->N, y, ldy, b, ldb, r, s));
   else
     HIP_TRY(h, launch_mv_eval<float>(static_cast<const float*>(h->X), h->d, h->h, h->lam, t,
-                                     mp->n_mv_tiles, g, xm, h->N, y, ldy, b, ldb, r, s));
+                                     mp.n_mv_tiles, g, xm, h->N, y, ldy, b, ldb, r, s));
   return INVASKIT_OK;
 }
 
@@ -1617,7 +1795,7 @@ int apply_precond(H* h, SolvePlan* sp, const double* in, double* out) {
 // expanding its space when its least-squares residual estimate drops below
 // est_tol[c] or the space becomes invariant.  Returns the steps taken in
 // *steps (at most max_steps).
-int gmres_cycle(H* h, SolvePlan* sp, MatvecPlan* mp, const std::vector<double>& rn,
+int gmres_cycle(H* h, SolvePlan* sp, const std::vector<double>& rn,
                 const std::vector<double>& est_tol, int max_steps, int* steps) {
   hipStream_t s = h->stream;
   const int r = sp->r;
@@ -1659,7 +1837,7 @@ int gmres_cycle(H* h, SolvePlan* sp, MatvecPlan* mp, const std::vector<double>& 
     double* vn = V + (size_t)(j + 1) * blk;
     double* zj = Zb + (size_t)j * blk;
     if (int rc = apply_precond(h, sp, vj, zj)) return rc;
-    if (int rc = run_matvec(h, mp, zj, N, vn, N, nullptr, 0)) return rc;
+    if (int rc = run_matvec(h, sp->tables, sp->mv, zj, N, vn, N, nullptr, 0)) return rc;
     // classical Gram-Schmidt, twice
     HIP_TRY(h, launch_dots(V, blk, N, j + 1, vn, N, N, r, part, h1d, s));
     HIP_TRY(h, launch_lincomb(vn, N, V, blk, N, j + 1, h1d, r, -1.0, N, s));
@@ -1726,28 +1904,14 @@ int gmres_cycle(H* h, SolvePlan* sp, MatvecPlan* mp, const std::vector<double>& 
   return INVASKIT_OK;
 }
 
-int ensure_gmres_space(H* h, SolvePlan* sp) {
-  if (sp->gmV.p) return INVASKIT_OK;
-  const size_t blk = (size_t)h->N * sp->r * sizeof(double);
-  sp->gm_m = h->gm_restart;
-  int rc;
-  if ((rc = dev_alloc(h, sp->gmV, blk * (sp->gm_m + 1)))) return rc;
-  if ((rc = dev_alloc(h, sp->gmZ, blk * sp->gm_m))) return rc;
-  return INVASKIT_OK;
-}
-
-int do_solve(H* h, const double* b, int64_t r64v, int64_t ldb, double* x, int64_t ldx,
+// The solve on a plan already bound to its scratch (bind_scratch).
+int do_solve(H* h, SolvePlan* sp, const double* b, int64_t ldb, double* x, int64_t ldx,
              invaskit_solve_info* info) {
-  const int r = (int)r64v;
+  const int r = sp->r;
   const int64_t N = h->N;
   hipStream_t s = h->stream;
-  SolvePlan* sp = nullptr;
   int rc;
-  if ((rc = build_solve_plan(h, r, sp))) return rc;
   const int mode = h->refine;
-  const bool need_res = mode != INVASKIT_REFINE_NONE || info != nullptr;
-  MatvecPlan* mp = nullptr;
-  if (need_res && (rc = build_mv_plan(h, r, mp))) return rc;
   double* x64 = static_cast<double*>(sp->x64.p);
   double* r64 = static_cast<double*>(sp->r64.p);
   invaskit_solve_info loc{};
@@ -1762,7 +1926,7 @@ int do_solve(H* h, const double* b, int64_t r64v, int64_t ldb, double* x, int64_
   double best = 1.0, prev = 1.0, hist[3] = {INFINITY, INFINITY, INFINITY};
   bool x_is_best_zero = true, last_is_best = true, conv = false, to_gmres = false;
   auto residual = [&]() -> int {  // r64 = b - A x64 and its norms
-    int e = run_matvec(h, mp, x64, N, r64, N, b, ldb);
+    int e = run_matvec(h, sp->tables, sp->mv, x64, N, r64, N, b, ldb);
     if (e) return e;
     return col_norms2(h, sp, r64, N, r, rn);
   };
@@ -1810,9 +1974,11 @@ int do_solve(H* h, const double* b, int64_t r64v, int64_t ldb, double* x, int64_
     }
     loc.iterations = std::min(it, cap);
   }
-  if (!conv && (mode == INVASKIT_REFINE_GMRES || to_gmres)) {
+  // without room for the GMRES bases (a scratch smaller than
+  // invaskit_solve_workspace_bytes) AUTO ends with the refinement's best
+  const bool no_room = sp->gm_m < 2;
+  if (!conv && (mode == INVASKIT_REFINE_GMRES || to_gmres) && !no_room) {
     loc.method = INVASKIT_REFINE_GMRES;
-    if ((rc = ensure_gmres_space(h, sp))) return rc;
     // restart from the best iterate
     if (x_is_best_zero) {
       HIP_TRY(h, launch_zero_cols(x64, N, N, r, s));
@@ -1827,7 +1993,7 @@ int do_solve(H* h, const double* b, int64_t r64v, int64_t ldb, double* x, int64_
     double cyc_prev = worst_rel(rn, bn);
     while (loc.gmres_iterations < h->gm_maxit) {
       int steps = 0;
-      if ((rc = gmres_cycle(h, sp, mp, rn, est_tol, h->gm_maxit - loc.gmres_iterations, &steps)))
+      if ((rc = gmres_cycle(h, sp, rn, est_tol, h->gm_maxit - loc.gmres_iterations, &steps)))
         return rc;
       loc.gmres_iterations += steps;
       if ((rc = residual())) return rc;
@@ -1853,7 +2019,8 @@ int do_solve(H* h, const double* b, int64_t r64v, int64_t ldb, double* x, int64_
     return fail_h(h, INVASKIT_E_NOT_CONVERGED,
                   "refinement stopped after " + std::to_string(loc.iterations) + " steps and " +
                       std::to_string(loc.gmres_iterations) +
-                      " GMRES steps at relative residual " + std::to_string(best));
+                      " GMRES steps at relative residual " + std::to_string(best) +
+                      (to_gmres && no_room ? " (no scratch for the GMRES bases)" : ""));
   return INVASKIT_OK;
 }
 
@@ -1875,21 +2042,18 @@ int invaskit_default_options(invaskit_options* opt) {
   opt->refine = INVASKIT_REFINE_AUTO;
   opt->gmres_restart = 20;
   opt->max_gmres_iters = 300;
-  opt->reserved1 = 0;
+  opt->lambda_group = 0;
   return INVASKIT_OK;
 }
 
 }  // extern "C"
 
 namespace {
-// a handle for a validated problem, planned and factored; *out is set
-// whenever the handle was created (also when the factorization reports a
-// zero pivot)
-int make_handle(const invaskit_problem* pb, double lambda, const invaskit_options* opt,
-                void* hip_stream, std::shared_ptr<KernelCache> cache, invaskit_handle* out) {
-  int rc;
+// A handle holding the validated problem's host description and options; no
+// device access.
+std::unique_ptr<H> new_handle(const invaskit_problem* pb, double lambda,
+                              const invaskit_options* opt, void* hip_stream) {
   std::unique_ptr<H> h(new H());
-  h->kcache = std::move(cache);
   invaskit_options o;
   invaskit_default_options(&o);
   if (opt) o = *opt;
@@ -1920,30 +2084,122 @@ int make_handle(const invaskit_problem* pb, double lambda, const invaskit_option
   h->p_off.assign(pb->p_offsets, pb->p_offsets + h->nn + 1);
   if (h->skel_off[h->nn] > 0)
     h->skel_idx.assign(pb->skel_index, pb->skel_index + h->skel_off[h->nn]);
-  const auto t0 = std::chrono::steady_clock::now();
-  if ((rc = plan_factor(h.get()))) return rc;
-  h->plan_ms =
-      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-  rc = run_factor(h.get());
-  *out = h.release();
-  return rc;
+  layout_factor(h.get());
+  return h;
+}
+
+// Sizes of one handle's region and of its own factor tables (placeholder
+// base; shared: the sweep's cache, also at placeholder addresses).
+void plan_region(H* h, const KernelCache* shared, size_t* region, size_t* tables) {
+  carve_factor(h, kPlanBase, shared, 0);
+  *tables = factor_table_bytes(h, shared);
+  *region = carve_factor(h, kPlanBase, shared, *tables);
+}
+
+struct SweepSizes {
+  size_t cache = 0, group_tables = 0, region = 0, single = 0, total = 0;
+  int group = 1;
+};
+// Layout of a sweep's workspace: the shared cache, the tables of every
+// lambda-batched group of two or more handles, then one region per handle.
+SweepSizes sweep_sizes(H* h, int n_lambda, int lambda_group) {
+  SweepSizes z;
+  KernelCache kc;
+  z.cache = carve_cache(h, kc, kPlanBase);
+  plan_region(h, &kc, &z.region, &z.single);
+  z.group = lambda_group > 0 ? std::min(lambda_group, n_lambda) : n_lambda;
+  for (int i0 = 0; i0 < n_lambda; i0 += z.group) {
+    const int g = std::min(z.group, n_lambda - i0);
+    if (g >= 2) z.group_tables += align_up((size_t)g * z.single, kAlign);
+  }
+  z.total = z.cache + z.group_tables + (size_t)n_lambda * z.region;
+  return z;
+}
+
+// Builds and uploads a handle's own factor plan (its tables in its region).
+int ready_own_plan(H* h) {
+  if (h->fp_ready) return INVASKIT_OK;
+  Arena ar;
+  build_factor_tables({h}, h->kcache.get(), ar, h->fp);
+  if (ar.bytes() > h->fp.tables.bytes)
+    return fail_h(h, INVASKIT_E_WORKSPACE, "internal: factor tables exceed their planned size");
+  HIP_TRY(h, hipMemcpyAsync(h->fp.tables.p, ar.host.data(), ar.host.size(),
+                            hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(h, hipStreamSynchronize(h->stream));  // ar goes out of scope
+  h->fp_ready = true;
+  return INVASKIT_OK;
+}
+
+// a cached plan carries lambda in its leaf copies: rewrite them
+int set_plan_lambda(H* h) {
+  const CopyShiftL& l = h->fp.leaf_copy;
+  if (!h->fp.cached || l.count == 0) return INVASKIT_OK;
+  std::vector<CopyShiftProb> c(l.count);
+  CopyShiftProb* dev =
+      reinterpret_cast<CopyShiftProb*>(static_cast<unsigned char*>(h->fp.tables.p) + l.probs);
+  HIP_TRY(h, hipMemcpy(c.data(), dev, sizeof(CopyShiftProb) * c.size(), hipMemcpyDeviceToHost));
+  for (auto& e : c) e.shift = h->lam;
+  HIP_TRY(h, hipMemcpy(dev, c.data(), sizeof(CopyShiftProb) * c.size(), hipMemcpyHostToDevice));
+  return INVASKIT_OK;
 }
 }  // namespace
 
 extern "C" {
 
+int invaskit_factor_workspace_bytes(const invaskit_problem* pb, const invaskit_options* opt,
+                                    int32_t n_lambda, size_t* bytes) {
+  if (!bytes) return fail_h(nullptr, INVASKIT_E_ARG, "bytes is NULL");
+  if (n_lambda < 0) return fail_h(nullptr, INVASKIT_E_ARG, "n_lambda < 0");
+  int rc = validate(nullptr, pb, 0.0, opt);
+  if (rc) return rc;
+  std::unique_ptr<H> h = new_handle(pb, 0.0, opt, nullptr);
+  if (n_lambda == 0) {
+    size_t region = 0, tables = 0;
+    plan_region(h.get(), nullptr, &region, &tables);
+    *bytes = region;
+  } else {
+    *bytes = sweep_sizes(h.get(), n_lambda, opt ? opt->lambda_group : 0).total;
+  }
+  return INVASKIT_OK;
+}
+
 int invaskit_factor(const invaskit_problem* pb, double lambda, const invaskit_options* opt,
-                    void* hip_stream, invaskit_handle* out) {
+                    void* workspace, size_t ws_bytes, void* hip_stream, invaskit_handle* out) {
   if (!out) return fail_h(nullptr, INVASKIT_E_ARG, "out is NULL");
   *out = nullptr;
   int rc = validate(nullptr, pb, lambda, opt);
   if (rc) return rc;
+  const auto t0 = std::chrono::steady_clock::now();
+  std::unique_ptr<H> h = new_handle(pb, lambda, opt, hip_stream);
+  // the tables come last in the region, so the other buffers' addresses are
+  // final before the tables are built (once, with those addresses)
+  unsigned char* base = static_cast<unsigned char*>(workspace);
+  if (!base) return fail_h(nullptr, INVASKIT_E_ARG, "workspace is NULL");
+  carve_factor(h.get(), base, nullptr, 0);
+  Arena ar;
+  build_factor_tables({h.get()}, nullptr, ar, h->fp);
+  const size_t region = carve_factor(h.get(), base, nullptr, ar.bytes());
+  if ((rc = check_workspace(nullptr, workspace, ws_bytes, region, "workspace"))) return rc;
   if ((rc = check_device(nullptr))) return rc;
-  return make_handle(pb, lambda, opt, hip_stream, nullptr, out);
+  if (!h->skel_idx.empty())
+    HIP_TRY(nullptr, hipMemcpyAsync(h->skel_own.p, h->skel_idx.data(),
+                                    sizeof(int32_t) * h->skel_idx.size(), hipMemcpyHostToDevice,
+                                    h->stream));
+  HIP_TRY(nullptr, hipMemcpyAsync(h->fp.tables.p, ar.host.data(), ar.host.size(),
+                                  hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(nullptr, hipStreamSynchronize(h->stream));  // ar goes out of scope
+  h->fp_ready = true;
+  h->plan_ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  H* hp = h.get();
+  rc = run_factor({hp}, hp->fp, nullptr);
+  *out = h.release();
+  return rc;
 }
 
 int invaskit_factor_sweep(const invaskit_problem* pb, const double* lambdas, int32_t n_lambda,
-                          const invaskit_options* opt, void* hip_stream, invaskit_handle* out) {
+                          const invaskit_options* opt, void* workspace, size_t ws_bytes,
+                          void* hip_stream, invaskit_handle* out) {
   if (!out || !lambdas || n_lambda < 1)
     return fail_h(nullptr, INVASKIT_E_ARG, "out, lambdas and n_lambda >= 1 are required");
   for (int32_t i = 0; i < n_lambda; ++i) out[i] = nullptr;
@@ -1951,21 +2207,75 @@ int invaskit_factor_sweep(const invaskit_problem* pb, const double* lambdas, int
     int rc = validate(nullptr, pb, lambdas[i], opt);
     if (rc) return rc;
   }
-  int rc = check_device(nullptr);
+  std::vector<std::unique_ptr<H>> hs;
+  for (int32_t i = 0; i < n_lambda; ++i) hs.push_back(new_handle(pb, lambdas[i], opt, hip_stream));
+  const SweepSizes z = sweep_sizes(hs[0].get(), n_lambda, opt ? opt->lambda_group : 0);
+  int rc = check_workspace(nullptr, workspace, ws_bytes, z.total, "workspace");
   if (rc) return rc;
-  auto cache = std::make_shared<KernelCache>();
-  int first = INVASKIT_OK;
+  if ((rc = check_device(nullptr))) return rc;
+  unsigned char* base = static_cast<unsigned char*>(workspace);
+  auto kc = std::make_shared<KernelCache>();
+  carve_cache(hs[0].get(), *kc, base);
+  unsigned char* gtab = base + z.cache;
+  unsigned char* regions = gtab + z.group_tables;
   for (int32_t i = 0; i < n_lambda; ++i) {
-    rc = make_handle(pb, lambdas[i], opt, hip_stream, cache, &out[i]);
-    if (rc != INVASKIT_OK && first == INVASKIT_OK) first = rc;
-    if (!out[i]) {  // not created: release the others
-      for (int32_t k = 0; k < i; ++k) {
-        delete out[k];
-        out[k] = nullptr;
-      }
-      return rc;
-    }
+    carve_factor(hs[i].get(), regions + (size_t)i * z.region, kc.get(), z.single);
+    hs[i]->kcache = kc;
   }
+  H* h0 = hs[0].get();
+  if (!h0->skel_idx.empty())
+    HIP_TRY(nullptr, hipMemcpyAsync(kc->skel.p, h0->skel_idx.data(),
+                                    sizeof(int32_t) * h0->skel_idx.size(), hipMemcpyHostToDevice,
+                                    h0->stream));
+  int first = INVASKIT_OK;
+  for (int32_t i0 = 0; i0 < n_lambda; i0 += z.group) {
+    const int g = std::min(z.group, n_lambda - i0);
+    const auto tb = std::chrono::steady_clock::now();
+    std::vector<H*> members;
+    for (int k = 0; k < g; ++k) members.push_back(hs[i0 + k].get());
+    if (g == 1) {
+      if ((rc = ready_own_plan(members[0]))) {
+        first = rc;
+        break;
+      }
+      members[0]->plan_ms =
+          std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tb).count();
+      rc = run_factor(members, members[0]->fp, kc.get());
+    } else {
+      FactorPlan gp;
+      gp.tables.p = gtab;
+      gp.tables.bytes = align_up((size_t)g * z.single, kAlign);
+      gtab += gp.tables.bytes;
+      Arena ar;
+      build_factor_tables(members, kc.get(), ar, gp);
+      if (ar.bytes() > gp.tables.bytes) {
+        first = fail_h(nullptr, INVASKIT_E_WORKSPACE,
+                       "internal: sweep tables exceed their planned size");
+        break;
+      }
+      hipError_t e = hipMemcpyAsync(gp.tables.p, ar.host.data(), ar.host.size(),
+                                    hipMemcpyHostToDevice, h0->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(h0->stream);
+      if (e != hipSuccess) {
+        first = fail_h(nullptr, INVASKIT_E_HIP, hipGetErrorString(e));
+        break;
+      }
+      const double ms =
+          std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tb).count();
+      for (H* m : members) m->plan_ms = ms / g;
+      rc = run_factor(members, gp, kc.get());
+    }
+    if (rc != INVASKIT_OK && first == INVASKIT_OK) first = rc;
+    if (rc != INVASKIT_OK && rc != INVASKIT_E_SINGULAR) break;
+  }
+  if (first != INVASKIT_OK && first != INVASKIT_E_SINGULAR) {
+    g_last_error = hs[0]->err.empty() ? g_last_error : hs[0]->err;
+    return first;  // every handle is released
+  }
+  for (int32_t i = 0; i < n_lambda; ++i) out[i] = hs[i].release();
+  if (first == INVASKIT_E_SINGULAR)
+    for (int32_t i = 0; i < n_lambda; ++i)
+      if (!out[i]->err.empty()) g_last_error = out[i]->err;
   return first;
 }
 
@@ -1973,11 +2283,31 @@ int invaskit_refactor(invaskit_handle h, double lambda) {
   if (!h) return fail_h(nullptr, INVASKIT_E_ARG, "handle is NULL");
   if (!std::isfinite(lambda)) return fail_h(h, INVASKIT_E_ARG, "lambda must be finite");
   h->lam = lambda;
-  return run_factor(h);
+  int rc = ready_own_plan(h);
+  if (!rc) rc = set_plan_lambda(h);
+  if (rc) return rc;
+  return run_factor({h}, h->fp, h->kcache.get());
+}
+
+int invaskit_solve_workspace_bytes(invaskit_handle h, int64_t nrhs, size_t* bytes,
+                                   size_t* min_bytes) {
+  if (!h || !bytes) return fail_h(h, INVASKIT_E_ARG, "handle and bytes are required");
+  if (nrhs < 1 || nrhs > 4096) return fail_h(h, INVASKIT_E_ARG, "nrhs must be in [1, 4096]");
+  const SolvePlan* sp = get_solve_plan(h, (int)nrhs, true, kPlanBase);
+  *bytes = sp->full_bytes;
+  if (min_bytes) *min_bytes = sp->min_bytes;
+  return INVASKIT_OK;
+}
+
+int invaskit_matvec_workspace_bytes(invaskit_handle h, int64_t nrhs, size_t* bytes) {
+  if (!h || !bytes) return fail_h(h, INVASKIT_E_ARG, "handle and bytes are required");
+  if (nrhs < 1 || nrhs > 4096) return fail_h(h, INVASKIT_E_ARG, "nrhs must be in [1, 4096]");
+  *bytes = get_solve_plan(h, (int)nrhs, false, kPlanBase)->full_bytes;
+  return INVASKIT_OK;
 }
 
 int invaskit_solve(invaskit_handle h, const double* b, int64_t nrhs, int64_t ldb, double* x,
-                   int64_t ldx, invaskit_solve_info* info) {
+                   int64_t ldx, void* scratch, size_t scratch_bytes, invaskit_solve_info* info) {
   if (!h) return fail_h(nullptr, INVASKIT_E_ARG, "handle is NULL");
   if (!b || !x) return fail_h(h, INVASKIT_E_ARG, "b and x are required");
   if (nrhs < 1 || nrhs > 4096) return fail_h(h, INVASKIT_E_ARG, "nrhs must be in [1, 4096]");
@@ -1987,37 +2317,37 @@ int invaskit_solve(invaskit_handle h, const double* b, int64_t nrhs, int64_t ldb
   const char* x0 = reinterpret_cast<const char*>(x);
   const char* x1 = reinterpret_cast<const char*>(x + (nrhs - 1) * ldx + h->N);
   if (b0 < x1 && x0 < b1) return fail_h(h, INVASKIT_E_ARG, "b and x overlap");
-  return do_solve(h, b, nrhs, ldb, x, ldx, info);
+  if (!scratch) return fail_h(h, INVASKIT_E_ARG, "scratch is NULL");
+  SolvePlan* sp = get_solve_plan(h, (int)nrhs, true, static_cast<unsigned char*>(scratch));
+  int rc = check_workspace(h, scratch, scratch_bytes, sp->min_bytes, "scratch");
+  if (rc) return rc;
+  const char* s0 = static_cast<const char*>(scratch);
+  if ((s0 < x1 && x0 < s0 + scratch_bytes) || (s0 < b1 && b0 < s0 + scratch_bytes))
+    return fail_h(h, INVASKIT_E_ARG, "scratch overlaps b or x");
+  if ((rc = bind_scratch(h, sp, scratch_bytes, false))) return rc;
+  if (h->refine == INVASKIT_REFINE_GMRES && sp->gm_m < 2)
+    return fail_h(h, INVASKIT_E_WORKSPACE,
+                  "refine = GMRES needs the scratch size of invaskit_solve_workspace_bytes");
+  return do_solve(h, sp, b, ldb, x, ldx, info);
 }
 
 int invaskit_matvec(invaskit_handle h, const double* x, int64_t nrhs, int64_t ldx, double* y,
-                    int64_t ldy) {
+                    int64_t ldy, void* scratch, size_t scratch_bytes) {
   if (!h) return fail_h(nullptr, INVASKIT_E_ARG, "handle is NULL");
   if (!x || !y) return fail_h(h, INVASKIT_E_ARG, "x and y are required");
   if (nrhs < 1 || nrhs > 4096) return fail_h(h, INVASKIT_E_ARG, "nrhs must be in [1, 4096]");
   if (ldx < h->N || ldy < h->N) return fail_h(h, INVASKIT_E_ARG, "ldx and ldy must be >= n");
-  MatvecPlan* mp = nullptr;
-  int rc = build_mv_plan(h, (int)nrhs, mp);
+  if (!scratch) return fail_h(h, INVASKIT_E_ARG, "scratch is NULL");
+  SolvePlan* sp = get_solve_plan(h, (int)nrhs, false, static_cast<unsigned char*>(scratch));
+  int rc = check_workspace(h, scratch, scratch_bytes, sp->min_bytes, "scratch");
   if (rc) return rc;
-  return run_matvec(h, mp, x, ldx, y, ldy, nullptr, 0);
+  if ((rc = bind_scratch(h, sp, scratch_bytes, false))) return rc;
+  return run_matvec(h, sp->tables, sp->mv, x, ldx, y, ldy, nullptr, 0);
 }
 
 int invaskit_device_bytes(invaskit_handle h, size_t* bytes) {
   if (!h || !bytes) return fail_h(h, INVASKIT_E_ARG, "handle and bytes are required");
-  size_t t = 0;
-  for (const DevBuf* b : {&h->skel_d, &h->P32, &h->leafLU, &h->leafPerm, &h->leafInfo, &h->slab,
-                          &h->Z64, &h->ZT, &h->zperm, &h->zinfo, &h->psw, &h->ysw, &h->ftables,
-                          &h->dinvLeaf, &h->dinvZ64, &h->dinvZT})
-    t += b->bytes;
-  for (auto& kv : h->solve_plans)
-    for (const DevBuf* b : {&kv.second->tables, &kv.second->xbuf, &kv.second->sbuf,
-                            &kv.second->x64, &kv.second->r64, &kv.second->sc, &kv.second->gpart,
-                            &kv.second->gsmall, &kv.second->gmV, &kv.second->gmZ})
-      t += b->bytes;
-  for (auto& kv : h->mv_plans)
-    for (const DevBuf* b : {&kv.second->tables, &kv.second->xm, &kv.second->q})
-      t += b->bytes;
-  *bytes = t;
+  *bytes = h->region_bytes;
   return INVASKIT_OK;
 }
 
@@ -2090,7 +2420,7 @@ const char* invaskit_status_string(int status) {
   switch (status) {
     case INVASKIT_OK: return "ok";
     case INVASKIT_E_ARG: return "invalid argument";
-    case INVASKIT_E_MEMORY: return "device allocation failed";
+    case INVASKIT_E_WORKSPACE: return "workspace too small";
     case INVASKIT_E_HIP: return "HIP runtime error";
     case INVASKIT_E_SINGULAR: return "singular pivot";
     case INVASKIT_E_NOT_CONVERGED: return "refinement did not converge";
@@ -2109,14 +2439,39 @@ int invaskit_last_error(invaskit_handle h, char* buf, size_t n) {
 }
 
 // ----------------------------------------------------- batched building blocks
+}  // extern "C"
+
+namespace {
+// A building block's device memory: `need` bytes of the caller's workspace.
+// With workspace == NULL the call only reports the size (*ws_needed).
+int block_workspace(void* ws, size_t ws_bytes, size_t* ws_needed, size_t need, bool* query) {
+  if (ws_needed) *ws_needed = need;
+  *query = ws == nullptr;
+  if (!ws)
+    return ws_needed ? INVASKIT_OK
+                     : fail_h(nullptr, INVASKIT_E_ARG, "workspace and ws_needed are both NULL");
+  return check_workspace(nullptr, ws, ws_bytes, need, "workspace");
+}
+
+int upload_and_sync(const Arena& ar, void* dst, hipStream_t s) {
+  hipError_t e = hipMemcpyAsync(dst, ar.host.data(), ar.host.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail_h(nullptr, INVASKIT_E_HIP, hipGetErrorString(e));
+  return INVASKIT_OK;
+}
+}  // namespace
+
+extern "C" {
+
 int invaskit_getrf_batched(int32_t dtype, void* a, const int64_t* a_offsets, const int32_t* n,
-                           int32_t count, int32_t* perm, int32_t* info, void* hip_stream) {
+                           int32_t count, int32_t* perm, int32_t* info, void* workspace,
+                           size_t ws_bytes, size_t* ws_needed, void* hip_stream) {
   if (count < 0 || (count > 0 && (!a || !a_offsets || !n || !perm || !info)))
     return fail_h(nullptr, INVASKIT_E_ARG, "invalid getrf_batched arguments");
   if (dtype != INVASKIT_F64 && dtype != INVASKIT_F32)
     return fail_h(nullptr, INVASKIT_E_ARG, "dtype must be INVASKIT_F64 or INVASKIT_F32");
-  if (count == 0) return INVASKIT_OK;
   const size_t es = dtype == INVASKIT_F64 ? 8 : 4;
+  Arena ar;
   std::vector<LuProb> probs(count);
   int nmax = 0;
   int64_t poff = 0;
@@ -2129,31 +2484,29 @@ int invaskit_getrf_batched(int32_t dtype, void* a, const int64_t* a_offsets, con
     poff += n[i];
     nmax = std::max(nmax, n[i]);
   }
+  const size_t off = ar.add(probs);
+  bool query = false;
+  int rc = block_workspace(workspace, ws_bytes, ws_needed, ar.bytes(), &query);
+  if (rc || query || count == 0) return rc;
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  DevBuf t;
-  int rc = dev_alloc(nullptr, t, sizeof(LuProb) * count);
-  if (rc) return rc;
-  hipError_t e = hipMemcpy(t.p, probs.data(), sizeof(LuProb) * count, hipMemcpyHostToDevice);
-  if (e == hipSuccess)
-    e = (dtype == INVASKIT_F64)
-            ? launch_getrf<double>(static_cast<LuProb*>(t.p), count, nmax, 1, 0, 0, s)
-            : launch_getrf<float>(static_cast<LuProb*>(t.p), count, nmax, 1, 0, 0, s);
+  if ((rc = upload_and_sync(ar, workspace, s))) return rc;
+  const LuProb* t = reinterpret_cast<const LuProb*>(static_cast<unsigned char*>(workspace) + off);
+  hipError_t e = (dtype == INVASKIT_F64) ? launch_getrf<double>(t, count, nmax, 1, 0, 0, s)
+                                         : launch_getrf<float>(t, count, nmax, 1, 0, 0, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  t.release();
   if (e != hipSuccess) return fail_h(nullptr, INVASKIT_E_HIP, hipGetErrorString(e));
   return INVASKIT_OK;
 }
 
-int invaskit_getrs_batched(int32_t dtype, const void* a, const int64_t* a_offsets,
-                           const int32_t* n, const int32_t* perm, void* b,
-                           const int64_t* b_offsets, const int32_t* nrhs, const int64_t* ldb,
-                           int32_t count, void* hip_stream) {
-  if (count < 0 || (count > 0 && (!a || !a_offsets || !n || !perm || !b || !b_offsets || !nrhs ||
-                                  !ldb)))
-    return fail_h(nullptr, INVASKIT_E_ARG, "invalid getrs_batched arguments");
-  if (dtype != INVASKIT_F64 && dtype != INVASKIT_F32)
-    return fail_h(nullptr, INVASKIT_E_ARG, "dtype must be INVASKIT_F64 or INVASKIT_F32");
-  if (count == 0) return INVASKIT_OK;
+}  // extern "C"
+
+namespace {
+// Tables of a batched solve with caller-owned factors; the diagonal-block
+// inverses go at the start of `base`, the tables after them.
+int getrs_tables(int32_t dtype, const void* a, const int64_t* a_offsets, const int32_t* n,
+                 const int32_t* perm, void* b, const int64_t* b_offsets, const int32_t* nrhs,
+                 const int64_t* ldb, int32_t count, unsigned char* base, Arena& ar, size_t* tables,
+                 TrsmL* l, DinvL* dl) {
   const size_t es = dtype == INVASKIT_F64 ? 8 : 4;
   constexpr int64_t kDB2 = 2 * kDiagBlock * kDiagBlock;
   int64_t dn = 0;
@@ -2162,15 +2515,13 @@ int invaskit_getrs_batched(int32_t dtype, const void* a, const int64_t* a_offset
       return fail_h(nullptr, INVASKIT_E_ARG, "getrs_batched sizes out of range");
     dn += (n[i] + kDiagBlock - 1) / kDiagBlock * kDB2;
   }
-  DevBuf dinv;
-  int rc = dev_alloc(nullptr, dinv, dn * es);
-  if (rc) return rc;
+  *tables = align_up(std::max<int64_t>(dn, 1) * es, kAlign);
   TrsmBuilder tb;
   std::vector<DiagInvProb> dis;
   int64_t poff = 0, doff = 0;
   for (int i = 0; i < count; ++i) {
     const unsigned char* ai = static_cast<const unsigned char*>(a) + a_offsets[i] * es;
-    void* di = static_cast<unsigned char*>(dinv.p) + doff * es;
+    void* di = base + doff * es;
     for (int jb = 0; jb < n[i]; jb += kDiagBlock) {
       DiagInvProb d{};
       d.lu = ai;
@@ -2185,26 +2536,46 @@ int invaskit_getrs_batched(int32_t dtype, const void* a, const int64_t* a_offset
     poff += n[i];
     doff += (n[i] + kDiagBlock - 1) / kDiagBlock * kDB2;
   }
-  Arena ar;
   const int f = dtype == INVASKIT_F64 ? 1 : 0;
-  TrsmL l = tb.emit(ar, f, f, 3);  // caller-owned factors: checked loads
+  *l = tb.emit(ar, f, f, 3);  // caller-owned factors: checked loads
+  dl->probs = ar.add(dis);
+  dl->count = (int)dis.size();
+  dl->t64 = f;
+  return INVASKIT_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int invaskit_getrs_batched(int32_t dtype, const void* a, const int64_t* a_offsets,
+                           const int32_t* n, const int32_t* perm, void* b,
+                           const int64_t* b_offsets, const int32_t* nrhs, const int64_t* ldb,
+                           int32_t count, void* workspace, size_t ws_bytes, size_t* ws_needed,
+                           void* hip_stream) {
+  if (count < 0 || (count > 0 && (!a || !a_offsets || !n || !perm || !b || !b_offsets || !nrhs ||
+                                  !ldb)))
+    return fail_h(nullptr, INVASKIT_E_ARG, "invalid getrs_batched arguments");
+  if (dtype != INVASKIT_F64 && dtype != INVASKIT_F32)
+    return fail_h(nullptr, INVASKIT_E_ARG, "dtype must be INVASKIT_F64 or INVASKIT_F32");
+  unsigned char* base = workspace ? static_cast<unsigned char*>(workspace) : kPlanBase;
+  Arena ar;
+  size_t dbytes = 0;
+  TrsmL l;
   DinvL dl;
-  dl.probs = ar.add(dis);
-  dl.count = (int)dis.size();
-  dl.t64 = f;
+  int rc = getrs_tables(dtype, a, a_offsets, n, perm, b, b_offsets, nrhs, ldb, count, base, ar,
+                        &dbytes, &l, &dl);
+  if (rc) return rc;
+  bool query = false;
+  rc = block_workspace(workspace, ws_bytes, ws_needed, dbytes + ar.bytes(), &query);
+  if (rc || query || count == 0) return rc;
+  if (l.ntiles < 0)
+    return fail_h(nullptr, INVASKIT_E_ARG, "getrs_batched: the largest system needs too much LDS");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  DevBuf t;
-  rc = dev_alloc(nullptr, t, ar.host.size());
-  if (rc) {
-    dinv.release();
-    return rc;
-  }
-  hipError_t e = hipMemcpy(t.p, ar.host.data(), ar.host.size(), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = run_dinv(t, dl, s);
+  Buf t{base + dbytes, ar.bytes()};
+  if ((rc = upload_and_sync(ar, t.p, s))) return rc;
+  hipError_t e = run_dinv(t, dl, s);
   if (e == hipSuccess) e = run_trsm(t, l, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  t.release();
-  dinv.release();
   if (e != hipSuccess) return fail_h(nullptr, INVASKIT_E_HIP, hipGetErrorString(e));
   return INVASKIT_OK;
 }
@@ -2213,7 +2584,8 @@ int invaskit_kernel_blocks(int32_t points_dtype, const void* points, int32_t d, 
                            int32_t out_dtype, void* out, const int64_t* out_offsets,
                            const int64_t* row0, const int32_t* rows, const int32_t* cols,
                            const int64_t* cols_offsets, const int32_t* ncols, const int32_t* diag,
-                           double shift, int32_t count, void* hip_stream) {
+                           double shift, int32_t count, void* workspace, size_t ws_bytes,
+                           size_t* ws_needed, void* hip_stream) {
   if (count < 0 || d < 1 || !(hbw > 0) ||
       (count > 0 && (!points || !out || !out_offsets || !row0 || !rows || !cols ||
                      !cols_offsets || !ncols || !diag)))
@@ -2221,7 +2593,6 @@ int invaskit_kernel_blocks(int32_t points_dtype, const void* points, int32_t d, 
   if ((points_dtype != INVASKIT_F64 && points_dtype != INVASKIT_F32) ||
       (out_dtype != INVASKIT_F64 && out_dtype != INVASKIT_F32))
     return fail_h(nullptr, INVASKIT_E_ARG, "dtypes must be INVASKIT_F64 or INVASKIT_F32");
-  if (count == 0) return INVASKIT_OK;
   const size_t es = out_dtype == INVASKIT_F64 ? 8 : 4;
   std::vector<EvalBlock> blocks(count);
   std::vector<Tile3> tiles;
@@ -2241,27 +2612,26 @@ int invaskit_kernel_blocks(int32_t points_dtype, const void* points, int32_t d, 
   }
   Arena ar;
   const size_t ob = ar.add(blocks), ot = ar.add(tiles);
+  bool query = false;
+  int rc = block_workspace(workspace, ws_bytes, ws_needed, ar.bytes(), &query);
+  if (rc || query || count == 0) return rc;
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  DevBuf t;
-  int rc = dev_alloc(nullptr, t, ar.host.size());
-  if (rc) return rc;
-  hipError_t e = hipMemcpy(t.p, ar.host.data(), ar.host.size(), hipMemcpyHostToDevice);
+  if ((rc = upload_and_sync(ar, workspace, s))) return rc;
+  Buf t{workspace, ar.bytes()};
   const int nt = (int)tiles.size();
-  if (e == hipSuccess) {
-    const EvalBlock* pb = at<EvalBlock>(t, ob);
-    const Tile3* pt = at<Tile3>(t, ot);
-    if (points_dtype == INVASKIT_F64) {
-      const double* X = static_cast<const double*>(points);
-      e = out_dtype == INVASKIT_F64 ? launch_eval<double, double>(X, d, hbw, shift, pb, pt, nt, s)
-                                    : launch_eval<double, float>(X, d, hbw, shift, pb, pt, nt, s);
-    } else {
-      const float* X = static_cast<const float*>(points);
-      e = out_dtype == INVASKIT_F64 ? launch_eval<float, double>(X, d, hbw, shift, pb, pt, nt, s)
-                                    : launch_eval<float, float>(X, d, hbw, shift, pb, pt, nt, s);
-    }
+  const EvalBlock* pb = at<EvalBlock>(t, ob);
+  const Tile3* pt = at<Tile3>(t, ot);
+  hipError_t e;
+  if (points_dtype == INVASKIT_F64) {
+    const double* X = static_cast<const double*>(points);
+    e = out_dtype == INVASKIT_F64 ? launch_eval<double, double>(X, d, hbw, shift, pb, pt, nt, s)
+                                  : launch_eval<double, float>(X, d, hbw, shift, pb, pt, nt, s);
+  } else {
+    const float* X = static_cast<const float*>(points);
+    e = out_dtype == INVASKIT_F64 ? launch_eval<float, double>(X, d, hbw, shift, pb, pt, nt, s)
+                                  : launch_eval<float, float>(X, d, hbw, shift, pb, pt, nt, s);
   }
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  t.release();
   if (e != hipSuccess) return fail_h(nullptr, INVASKIT_E_HIP, hipGetErrorString(e));
   return INVASKIT_OK;
 }
@@ -2271,13 +2641,12 @@ int invaskit_gemm_batched(int32_t dtype, const void* a, const void* b, void* c,
                           const int32_t* m, const int32_t* n, const int32_t* k,
                           const int64_t* lda, const int32_t* a_rm, const int64_t* ldb,
                           const int64_t* ldc, double alpha, double beta, int32_t count,
-                          void* hip_stream) {
+                          void* workspace, size_t ws_bytes, size_t* ws_needed, void* hip_stream) {
   if (count < 0 || (count > 0 && (!a || !b || !c || !a_off || !b_off || !c_off || !m || !n ||
                                   !k || !lda || !a_rm || !ldb || !ldc)))
     return fail_h(nullptr, INVASKIT_E_ARG, "invalid gemm_batched arguments");
   if (dtype != INVASKIT_F64 && dtype != INVASKIT_F32)
     return fail_h(nullptr, INVASKIT_E_ARG, "dtype must be INVASKIT_F64 or INVASKIT_F32");
-  if (count == 0) return INVASKIT_OK;
   const size_t es = dtype == INVASKIT_F64 ? 8 : 4;
   GemmBuilder gb;
   for (int i = 0; i < count; ++i) {
@@ -2290,16 +2659,17 @@ int invaskit_gemm_batched(int32_t dtype, const void* a, const void* b, void* c,
   }
   Arena ar;
   GemmL l = gb.emit(ar);
+  bool query = false;
+  int rc = block_workspace(workspace, ws_bytes, ws_needed, ar.bytes(), &query);
+  if (rc || query || count == 0) return rc;
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  DevBuf t;
-  int rc = dev_alloc(nullptr, t, ar.host.size());
-  if (rc) return rc;
-  hipError_t e = hipMemcpy(t.p, ar.host.data(), ar.host.size(), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = run_gemm(t, l, dtype == INVASKIT_F64, s);
+  if ((rc = upload_and_sync(ar, workspace, s))) return rc;
+  Buf t{workspace, ar.bytes()};
+  hipError_t e = run_gemm(t, l, dtype == INVASKIT_F64, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  t.release();
   if (e != hipSuccess) return fail_h(nullptr, INVASKIT_E_HIP, hipGetErrorString(e));
   return INVASKIT_OK;
 }
 
 }  // extern "C"
+

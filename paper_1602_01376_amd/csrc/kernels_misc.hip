@@ -25,6 +25,19 @@ __global__ __launch_bounds__(256) void k_zform(const ZformProb* __restrict__ pro
   }
 }
 
+// dst = src + shift * I for one square block of order m (either storage
+// order: the diagonal is every (m+1)-th element), one workgroup per block
+template <typename T>
+__global__ __launch_bounds__(256) void k_copy_shift(const CopyShiftProb* __restrict__ probs) {
+  const CopyShiftProb p = probs[blockIdx.x];
+  const T* __restrict__ src = static_cast<const T*>(p.src);
+  T* __restrict__ dst = static_cast<T*>(p.dst);
+  const int64_t mm = (int64_t)p.m * p.m;
+  const T sh = (T)p.shift;
+  for (int64_t e = threadIdx.x; e < mm; e += 256)
+    dst[e] = src[e] + ((e % (p.m + 1)) == 0 ? sh : T(0));
+}
+
 __global__ void k_convert(const double* __restrict__ in, float* __restrict__ out, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -157,6 +170,15 @@ hipError_t launch_zform(const ZformProb* probs, int count, hipStream_t s) {
 template hipError_t launch_zform<double, double>(const ZformProb*, int, hipStream_t);
 template hipError_t launch_zform<float, float>(const ZformProb*, int, hipStream_t);
 template hipError_t launch_zform<double, float>(const ZformProb*, int, hipStream_t);
+
+template <typename T>
+hipError_t launch_copy_shift(const CopyShiftProb* probs, int count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_copy_shift<T>), dim3(count), dim3(256), 0, s, probs);
+  return hipGetLastError();
+}
+template hipError_t launch_copy_shift<double>(const CopyShiftProb*, int, hipStream_t);
+template hipError_t launch_copy_shift<float>(const CopyShiftProb*, int, hipStream_t);
 
 hipError_t launch_convert_f64_f32(const double* in, float* out, int64_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;

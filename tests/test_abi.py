@@ -65,11 +65,11 @@ def small_problem():
     return make_problem("tiny", n=512, depth=2)
 
 
-def _factor_status(raw, lam=1e-2, opt=None):
+def _factor_status(raw, lam=1e-2, opt=None, ws=None, ws_bytes=0):
     from paper_1602_01376_amd import binding
     h = C.c_void_p()
     st = binding.library().invaskit_factor(C.byref(raw), lam, C.byref(opt) if opt else None,
-                                           None, C.byref(h))
+                                           ws, ws_bytes, None, C.byref(h))
     return st, binding.last_error()
 
 
@@ -230,20 +230,111 @@ def test_sweep_arguments_rejected(small_problem):
     raw, keep = _raw_problem(small_problem)
     out = (C.c_void_p * 3)()
     lams = (C.c_double * 3)(1e-2, float("inf"), 1e-1)
-    assert lib.invaskit_factor_sweep(C.byref(raw), lams, 3, None, None, out) == -1
+    assert lib.invaskit_factor_sweep(C.byref(raw), lams, 3, None, None, 0, None, out) == -1
     assert "lambda" in binding.last_error()
     assert all(v is None for v in out)
-    assert lib.invaskit_factor_sweep(C.byref(raw), lams, 0, None, None, out) == -1
-    assert lib.invaskit_factor_sweep(C.byref(raw), None, 3, None, None, out) == -1
+    assert lib.invaskit_factor_sweep(C.byref(raw), lams, 0, None, None, 0, None, out) == -1
+    assert lib.invaskit_factor_sweep(C.byref(raw), None, 3, None, None, 0, None, out) == -1
     bad, keep2 = _raw_problem(small_problem, d=0)
     ok = (C.c_double * 2)(1e-2, 1e-1)
-    assert lib.invaskit_factor_sweep(C.byref(bad), ok, 2, None, None, out) == -1
+    assert lib.invaskit_factor_sweep(C.byref(bad), ok, 2, None, None, 0, None, out) == -1
 
 
 def test_null_handle_calls_are_rejected():
     from paper_1602_01376_amd import binding
     lib = binding.library()
-    assert lib.invaskit_solve(None, None, 1, 1, None, 1, None) == -1
-    assert lib.invaskit_matvec(None, None, 1, 1, None, 1) == -1
+    assert lib.invaskit_solve(None, None, 1, 1, None, 1, None, 0, None) == -1
+    assert lib.invaskit_matvec(None, None, 1, 1, None, 1, None, 0) == -1
+    need = C.c_size_t()
+    assert lib.invaskit_solve_workspace_bytes(None, 1, C.byref(need), None) == -1
+    assert lib.invaskit_matvec_workspace_bytes(None, 1, C.byref(need)) == -1
     assert lib.invaskit_refactor(None, 1.0) == -1
     assert lib.invaskit_destroy(None) == 0
+
+
+def _ws_bytes(raw, n_lambda, precision=0, lambda_group=0):
+    from paper_1602_01376_amd import binding
+    opt = binding._Options()
+    binding.library().invaskit_default_options(C.byref(opt))
+    opt.precision = precision
+    opt.lambda_group = lambda_group
+    out = C.c_size_t()
+    st = binding.library().invaskit_factor_workspace_bytes(C.byref(raw), C.byref(opt), n_lambda,
+                                                           C.byref(out))
+    assert st == 0, binding.last_error()
+    return out.value, opt
+
+
+def test_factor_workspace_sizes(small_problem):
+    """Workspace queries are host-only (they run here, without a GPU): a
+    sweep needs more than one factorization and grows with its lambdas;
+    FP32 factors need less than FP64; lambda groups of one need no batched
+    tables; and the size covers at least the leaf factors and W storage."""
+    raw, keep = _raw_problem(small_problem)
+    single, _ = _ws_bytes(raw, 0)
+    one, _ = _ws_bytes(raw, 1)
+    three, _ = _ws_bytes(raw, 3)
+    three_g1, _ = _ws_bytes(raw, 3, lambda_group=1)
+    mixed, _ = _ws_bytes(raw, 0, precision=1)
+    assert single < one < three and three_g1 < three
+    assert mixed < single
+    m = np.diff(small_problem.leaf_offsets)
+    assert single > 8 * int(np.sum(m * m))
+    from paper_1602_01376_amd import binding
+    out = C.c_size_t()
+    assert binding.library().invaskit_factor_workspace_bytes(C.byref(raw), None, -1,
+                                                             C.byref(out)) == -1
+    bad, keep2 = _raw_problem(small_problem, d=0)
+    assert binding.library().invaskit_factor_workspace_bytes(C.byref(bad), None, 0,
+                                                             C.byref(out)) == -1
+
+
+def test_small_or_misaligned_workspace_rejected_before_any_launch(small_problem):
+    """A workspace one byte short fails with INVASKIT_E_WORKSPACE and a
+    misaligned one with INVASKIT_E_ARG, both before the library looks for a
+    device (the addresses here are placeholders that nothing dereferences);
+    one of the full size passes those checks and only then needs the GPU."""
+    from paper_1602_01376_amd import binding
+    raw, keep = _raw_problem(small_problem)
+    need, opt = _ws_bytes(raw, 0)
+    fake = C.c_void_p(1 << 20)
+    st, msg = _factor_status(raw, opt=opt, ws=fake, ws_bytes=need - 1)
+    assert st == binding.E_WORKSPACE and str(need) in msg
+    st, msg = _factor_status(raw, opt=opt, ws=C.c_void_p((1 << 20) + 8), ws_bytes=need)
+    assert st == binding.E_ARG and "aligned" in msg
+    st, msg = _factor_status(raw, opt=opt, ws=None, ws_bytes=need)
+    assert st == binding.E_ARG and "NULL" in msg
+    need3, opt3 = _ws_bytes(raw, 3)
+    out = (C.c_void_p * 3)()
+    lams = (C.c_double * 3)(1e-2, 1e-1, 1.0)
+    st = binding.library().invaskit_factor_sweep(C.byref(raw), lams, 3, C.byref(opt3), fake,
+                                                 need3 - 256, None, out)
+    assert st == binding.E_WORKSPACE and all(v is None for v in out)
+
+
+def test_building_block_workspace_queries():
+    """With workspace = NULL a building block reports its workspace size and
+    launches nothing (host only)."""
+    from paper_1602_01376_amd import binding
+    lib = binding.library()
+    n = np.array([5, 70, 130], np.int32)
+    offs = np.array([0, 25, 25 + 4900], np.int64)
+    need = C.c_size_t()
+    fake = C.c_void_p(1 << 20)
+    assert lib.invaskit_getrf_batched(0, fake, binding._ptr(offs), binding._ptr(n), 3, fake, fake,
+                                      None, 0, C.byref(need), None) == 0
+    assert need.value >= 3 * 32
+    nr = np.array([1, 16, 40], np.int32)
+    ld = n.astype(np.int64)
+    boffs = np.array([0, 5, 5 + 70 * 16], np.int64)
+    assert lib.invaskit_getrs_batched(0, fake, binding._ptr(offs), binding._ptr(n), fake, fake,
+                                      binding._ptr(boffs), binding._ptr(nr), binding._ptr(ld), 3,
+                                      None, 0, C.byref(need), None) == 0
+    # the diagonal-block inverses: 1 + 2 + 3 blocks of 2 x 64 x 64 doubles
+    assert need.value >= 6 * 2 * 64 * 64 * 8
+    assert lib.invaskit_getrs_batched(0, fake, binding._ptr(offs), binding._ptr(n), fake, fake,
+                                      binding._ptr(boffs), binding._ptr(nr), binding._ptr(ld), 3,
+                                      fake, need.value - 1, None, None) == binding.E_WORKSPACE
+    assert lib.invaskit_getrf_batched(0, fake, binding._ptr(offs), binding._ptr(n), 3, fake, fake,
+                                      None, 0, None, None) == binding.E_ARG
+
