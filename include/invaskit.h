@@ -310,6 +310,22 @@ int invaskit_matvec_workspace_bytes(invaskit_handle handle, int64_t nrhs, size_t
 int invaskit_matvec(invaskit_handle handle, const double* x, int64_t nrhs, int64_t ldx,
                     double* y, int64_t ldy, void* scratch, size_t scratch_bytes);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * product of invaskit_matvec with its scratch taken from a static device
+ * array of INVASKIT_STATIC_SCRATCH_BYTES inside the library (one per GPU,
+ * held until the process ends) instead of a caller buffer.  Allocates
+ * nothing.  A product whose scratch (invaskit_matvec_workspace_bytes) exceeds
+ * the array fails with INVASKIT_E_WORKSPACE before any launch.  Every call on
+ * a GPU, from any handle, shares that GPU's array and rewrites its
+ * descriptor tables: calls that overlap on one GPU (other streams, other
+ * threads) race.  Arguments and results as invaskit_matvec.
+ */
+#define INVASKIT_STATIC_SCRATCH_BYTES (64u << 20)
+int invaskit_matvec_noalloc(invaskit_handle handle, const double* x, int64_t nrhs, int64_t ldx,
+                            double* y, int64_t ldy);
+
 /* Bytes of the workspace the handle's own buffers span (for a handle of a
  * sweep: its region, without the shared kernel blocks). */
 int invaskit_device_bytes(invaskit_handle handle, size_t* bytes);

@@ -84,6 +84,7 @@ def _load():
         "invaskit_solve": (C.c_int, [vp, vp, i64, i64, vp, i64, vp, sz, vp]),
         "invaskit_matvec_workspace_bytes": (C.c_int, [vp, i64, szp]),
         "invaskit_matvec": (C.c_int, [vp, vp, i64, i64, vp, i64, vp, sz]),
+        "invaskit_matvec_noalloc": (C.c_int, [vp, vp, i64, i64, vp, i64]),
         "invaskit_device_bytes": (C.c_int, [vp, szp]),
         "invaskit_phase_times": (C.c_int, [vp, vp, i32]),
         "invaskit_tile_config_get": (C.c_int, [vp, vp]),
@@ -112,6 +113,7 @@ _lib = _load()
 EXPORTED = ("invaskit_default_options", "invaskit_factor_workspace_bytes", "invaskit_factor",
             "invaskit_factor_sweep", "invaskit_refactor", "invaskit_solve_workspace_bytes",
             "invaskit_solve", "invaskit_matvec_workspace_bytes", "invaskit_matvec",
+            "invaskit_matvec_noalloc",
             "invaskit_device_bytes", "invaskit_phase_times", "invaskit_tile_config_get",
             "invaskit_tuning_export", "invaskit_tuning_import", "invaskit_tuning_clear",
             "invaskit_destroy", "invaskit_status_string", "invaskit_last_error",

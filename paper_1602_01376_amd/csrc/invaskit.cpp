@@ -66,6 +66,12 @@
 
 using namespace invaskit;
 
+// Device scratch of invaskit_matvec_noalloc, for callers that cannot
+// allocate: one copy per GPU, held until the process ends.  Host code never
+// uses this name as an address: the per-device address comes from
+// hipGetSymbolAddress (static_scratch below).
+static __device__ __align__(256) unsigned char scratch[INVASKIT_STATIC_SCRATCH_BYTES];
+
 namespace {
 
 thread_local std::string g_last_error;
@@ -2024,6 +2030,28 @@ int do_solve(H* h, SolvePlan* sp, const double* b, int64_t ldb, double* x, int64
   return INVASKIT_OK;
 }
 
+// Address of this device's copy of `scratch`, looked up once per device
+// with that device current.
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_ptr;  // by device id
+
+int static_scratch(H* h, unsigned char** out) {
+  int dev = 0;
+  HIP_TRY(h, hipGetDevice(&dev));
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail_h(h, INVASKIT_E_HIP,
+                    std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = static_cast<unsigned char*>(g_scratch_ptr[dev]);
+  return INVASKIT_OK;
+}
+
 }  // namespace
 
 // ===================================================================== C ABI
@@ -2342,6 +2370,26 @@ int invaskit_matvec(invaskit_handle h, const double* x, int64_t nrhs, int64_t ld
   int rc = check_workspace(h, scratch, scratch_bytes, sp->min_bytes, "scratch");
   if (rc) return rc;
   if ((rc = bind_scratch(h, sp, scratch_bytes, false))) return rc;
+  return run_matvec(h, sp->tables, sp->mv, x, ldx, y, ldy, nullptr, 0);
+}
+
+int invaskit_matvec_noalloc(invaskit_handle h, const double* x, int64_t nrhs, int64_t ldx,
+                            double* y, int64_t ldy) {
+  if (!h) return fail_h(nullptr, INVASKIT_E_ARG, "handle is NULL");
+  if (!x || !y) return fail_h(h, INVASKIT_E_ARG, "x and y are required");
+  if (nrhs < 1 || nrhs > 4096) return fail_h(h, INVASKIT_E_ARG, "nrhs must be in [1, 4096]");
+  if (ldx < h->N || ldy < h->N) return fail_h(h, INVASKIT_E_ARG, "ldx and ldy must be >= n");
+  unsigned char* base = nullptr;
+  int rc = static_scratch(h, &base);
+  if (rc) return rc;
+  SolvePlan* sp = get_solve_plan(h, (int)nrhs, false, base);
+  if (sp->min_bytes > (size_t)INVASKIT_STATIC_SCRATCH_BYTES)
+    return fail_h(h, INVASKIT_E_WORKSPACE,
+                  "this product needs " + std::to_string(sp->min_bytes) +
+                      " bytes of scratch; the static scratch holds " +
+                      std::to_string((size_t)INVASKIT_STATIC_SCRATCH_BYTES));
+  // other handles may have used the array since: always copy the tables
+  if ((rc = bind_scratch(h, sp, INVASKIT_STATIC_SCRATCH_BYTES, true))) return rc;
   return run_matvec(h, sp->tables, sp->mv, x, ldx, y, ldy, nullptr, 0);
 }
 
