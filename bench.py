@@ -2,24 +2,34 @@
 
 One step = refactor (every factorization phase: leaf blocks and LU, skeleton
 blocks, leaf solves, projections, skeleton sweep, reduced systems and their
-LU) + solve of the right-hand sides, in the
-precision under test, to relative residual <= 1e-10 checked with the FP64
-hierarchical product.  The headline `value` is the mixed-precision path
-(FP32 factors, FP64 top-level reduced systems, FP64 refinement); the plain
-FP64 path is timed on the same inputs and reported beside it.
+LU) + solve of the right-hand sides to relative residual <= 1e-10, checked
+with the FP64 hierarchical product (both precisions verify it; FP64 refines
+with its own factors if its direct solve misses).  The headline `value` is
+the mixed-precision path (FP32 factors, FP64 top-level reduced systems, FP64
+refinement); the plain FP64 path is timed on the same inputs beside it, and
+its unverified direct solve alone for reference.  Each path also reports the
+wall time of its first factorization from nothing (workspace query and
+allocation, host planning, tile trials, factorization), cold and with the
+tuning table warm.
 
 Workload (default): N = 1,048,576 points in d = 8 from a 16-component unit
 Gaussian mixture, depth-12 ball tree with uneven leaves of 64..512 points,
-adaptive skeleton ranks 32..256 (ID tolerance 1e-5), h = 0.5, lambda = 1e-4,
-one right-hand side.  All inputs are seeded and synthetic and resident in
-HBM before the timed region.
+adaptive skeleton ranks (ID tolerance 1e-5, clamped to 32..256; the line
+states the realized range), h = 0.5, lambda = 1e-4, one right-hand side.
+All inputs are seeded and synthetic and resident in HBM before the timed
+region.
 
     python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--nrhs 1]
 
-`--workload NAME` times one of the other synthetic workloads instead (tiny:
-N = 4,096 d = 8; covtype: N = 65,536 d = 54; mnist: N = 262,144 d = 784
-sparse; normal: N = 4,194,304 d = 64), under a metric line of its own; the
-headline line is always the default workload.
+`--workload NAME` times one of the other synthetic workloads instead
+(susy-wide: the same points with ranks spread over 32..256; tiny: N = 4,096
+d = 8; covtype: N = 65,536 d = 54; mnist: N = 262,144 d = 784 sparse; normal:
+N = 4,194,304 d = 64), under a metric line of its own; the headline line is
+always the default workload.  `--sweep G` times a lambda sweep instead:
+`--sweep-mode batched` factors all G lambdas in one sweep (launches batched
+over --sweep-group lambdas) against G independent factorizations;
+`--sweep-mode refactor` refactors one sweep handle per lambda (the 4M-point
+workload holds one lambda at a time).
 """
 from __future__ import annotations
 
@@ -256,7 +266,11 @@ def paper_literal_flops(pb):
 
 
 # --------------------------------------------------------------- CPU baseline
-def cpu_baseline(full_pb, n_sample=65536, depth_sample=8):
+def cpu_baseline(full_pb, samples=((32768, 7), (65536, 8))):
+    """The FP64 oracle (Algorithms 1-2 with NumPy/SciPy LAPACK, untuned) timed
+    on the host cores on bounded samples of the same generator, each scaled
+    to the full workload by the paper-literal flop ratio; the two samples'
+    estimates check that scaling law."""
     import oracle
     from paper_1602_01376_amd.setup import make_problem, rhs_for
     try:
@@ -264,20 +278,149 @@ def cpu_baseline(full_pb, n_sample=65536, depth_sample=8):
         cores = max([t.get("num_threads", 1) for t in threadpool_info()] or [os.cpu_count() or 1])
     except Exception:
         cores = os.cpu_count() or 1
-    pb = make_problem("susy", n=n_sample, depth=depth_sample)
-    b = rhs_for(pb, nrhs=1)
-    t0 = time.perf_counter()
-    F = oracle.factorize(pb, pb.lam)
-    oracle.solve(F, b)
-    t = time.perf_counter() - t0
-    ratio = paper_literal_flops(full_pb) / paper_literal_flops(pb)
-    return {"value": t * ratio, "unit": "s", "cores": int(cores), "kind": "oracle",
+    name = full_pb.name if full_pb.name else "susy"
+    runs = []
+    for n, depth in samples:
+        pb = make_problem(name, n=n, depth=depth)
+        b = rhs_for(pb, nrhs=1)
+        t0 = time.perf_counter()
+        F = oracle.factorize(pb, pb.lam)
+        oracle.solve(F, b)
+        t = time.perf_counter() - t0
+        ratio = paper_literal_flops(full_pb) / paper_literal_flops(pb)
+        runs.append(dict(n=n, depth=depth, seconds=t, flop_ratio=ratio, estimate_s=t * ratio))
+        log(f"cpu baseline sample N={n}: {t:.2f} s, estimate {t * ratio:.1f} s")
+    est = runs[-1]["estimate_s"]
+    return {"value": est, "unit": "s", "cores": int(cores), "kind": "oracle",
             "sample": (f"FP64 oracle factor+solve (Algorithms 1-2, NumPy/SciPy LAPACK) on the same "
-                       f"generator at N={n_sample}, depth {depth_sample}: {t:.2f} s, scaled by the "
-                       f"paper-literal flop ratio {ratio:.1f} of the full workload")}
+                       f"generator at N={runs[-1]['n']} (depth {runs[-1]['depth']}): "
+                       f"{runs[-1]['seconds']:.2f} s, scaled by the paper-literal flop ratio "
+                       f"{runs[-1]['flop_ratio']:.1f}; the N={runs[0]['n']} sample scales to "
+                       f"{runs[0]['estimate_s']:.0f} s"),
+            "samples": runs,
+            "scaling_check": runs[0]["estimate_s"] / runs[-1]["estimate_s"]}
+
+
+def rank_summary(pb):
+    ranks = np.diff(pb.skel_offsets)[1:]
+    sizes = np.diff(pb.leaf_offsets)
+    return dict(leaf_min=int(sizes.min()), leaf_max=int(sizes.max()), rank_min=int(ranks.min()),
+                rank_max=int(ranks.max()), rank_median=float(np.median(ranks)),
+                at_floor=float(np.mean(ranks == ranks.min())))
+
+
+def power_estimate(apply, n, iters, seed=5):
+    """|largest eigenvalue| of a linear map by power iteration."""
+    import torch
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    x = torch.randn(n, generator=g, dtype=torch.float64).cuda()
+    x /= x.norm()
+    lam = 0.0
+    for _ in range(iters):
+        y = apply(x)
+        lam = float(y.norm())
+        x = y / lam
+    return lam
+
+
+def kappa_estimate(fac, n, iters=25):
+    """kappa(lambda I + K~) estimated as rho(A) rho(A^-1), both by power
+    iteration with the library's FP64 product and solve (a lower estimate of
+    the 2-norm condition number for this nearly symmetric matrix)."""
+    rho = power_estimate(lambda v: fac.matvec(v), n, iters)
+    rinv = power_estimate(lambda v: fac.solve(v, check=False), n, iters)
+    return dict(rho_A=rho, rho_Ainv=rinv, kappa=rho * rinv, iterations=iters)
 
 
 # ----------------------------------------------------------------------- main
+def time_first_factor(binding, pb, lam, mode, X, P, kw):
+    """Wall time of a Factorization from nothing: workspace query, workspace
+    allocation (PyTorch), host planning, table upload and the factorization
+    (tile trials included when the tuning table misses)."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fac = binding.Factorization(pb, lam, precision=mode, points=X, p_values=P, **kw)
+    torch.cuda.synchronize()
+    return fac, time.perf_counter() - t0
+
+
+def run_sweep(args, binding, pb, X, P, b):
+    import torch
+    lams = list(np.logspace(-6, -1, args.sweep))
+    kw = dict(precision=args.sweep_precision, points=X, p_values=P,
+              fp64_top_levels=args.fp64_top_levels)
+    per = []
+    if args.sweep_mode == "batched":
+        # every lambda in one sweep workspace, batched launches of
+        # --sweep-group lambdas (0: all)
+        fac = binding.Factorization(pb, lams[0], **kw)
+        fac.close()  # warm-up: kernel loads and tile trials
+        del fac
+        torch.cuda.empty_cache()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        facs = binding.factor_sweep(pb, lams, lambda_group=args.sweep_group, **kw)
+        torch.cuda.synchronize()
+        t_sweep = time.perf_counter() - t0
+        for lam, f in zip(lams, facs):
+            t1 = time.perf_counter()
+            _, info, st = f.solve(b, return_info=True, check=False)
+            torch.cuda.synchronize()
+            per.append(dict(lam=lam, solve_s=time.perf_counter() - t1, status=st, **info))
+        ws = facs[0]._ws.numel()
+        for f in facs:
+            f.close()
+        del facs
+        torch.cuda.empty_cache()
+        t0 = time.perf_counter()
+        for lam in lams:
+            f = binding.Factorization(pb, lam, **kw)
+            f.close()
+            del f
+        torch.cuda.synchronize()
+        t_sep = time.perf_counter() - t0
+        out = dict(sweep_s=t_sweep, separate_s=t_sep,
+                   per_lambda_sweep_ms=1e3 * t_sweep / len(lams),
+                   per_lambda_separate_ms=1e3 * t_sep / len(lams))
+    else:
+        # one handle of a sweep (the lambda-free kernel blocks evaluated once
+        # into its workspace), refactored for every lambda; each factor is
+        # solved right away (the workload's memory holds one lambda at a time)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        f = binding.factor_sweep(pb, lams[:1], **kw)[0]
+        torch.cuda.synchronize()
+        first = time.perf_counter() - t0
+        ws = f._ws.numel()
+        log(f"sweep handle: workspace {ws / 1e9:.1f} GB, first factor {first:.2f} s")
+        for i, lam in enumerate(lams):
+            t1 = time.perf_counter()
+            if i > 0:
+                f.refactor(lam)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            _, info, st = f.solve(b, return_info=True, check=False)
+            torch.cuda.synchronize()
+            t3 = time.perf_counter()
+            per.append(dict(lam=lam, factor_s=(t2 - t1) if i > 0 else first, solve_s=t3 - t2,
+                            status=st, factor_phase_ms=f.phase_times(), **info))
+            log(f"lambda {lam:.1e}: factor {per[-1]['factor_s']:.3f} s, solve {t3 - t2:.3f} s, "
+                f"residual {info['final_rel_residual']:.2e} ({info['iterations']} steps)")
+        f.close()
+        out = dict(first_factor_s=first,
+                   per_lambda_refactor_ms=1e3 * float(np.mean([p["factor_s"] for p in per[1:]]))
+                   if len(per) > 1 else None)
+    print(json.dumps({"metric": "lambda-sweep factorization seconds", "lambdas": lams,
+                      "workload": args.workload, "n": pb.n, "d": pb.d, "mode": args.sweep_mode,
+                      "sweep_group": args.sweep_group, "nrhs": args.nrhs,
+                      "precision": args.sweep_precision, "workspace_gb": ws / 1e9,
+                      "per_lambda": per,
+                      "per_lambda_solve_ms": 1e3 * float(np.mean([p["solve_s"] for p in per])),
+                      "max_refined_residual": max(p["final_rel_residual"] for p in per),
+                      **out}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -286,12 +429,16 @@ def main():
     ap.add_argument("--nrhs", type=int, default=None,
                     help="right-hand sides (default: 1 for the headline, else the workload's)")
     ap.add_argument("--workload", default="susy",
-                    choices=["susy", "tiny", "covtype", "mnist", "normal"],
+                    choices=["susy", "susy-wide", "tiny", "covtype", "mnist", "normal"],
                     help="synthetic workload (default susy: the headline configuration)")
     ap.add_argument("--n", type=int, default=None, help="scale the workload down (testing)")
     ap.add_argument("--depth", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-kappa", action="store_true",
+                    help="skip the power-iteration condition estimate")
     ap.add_argument("--only", choices=["mixed", "fp64", "both"], default="both")
+    ap.add_argument("--fp64-top-levels", type=int, default=4,
+                    help="mixed precision: reduced systems of the levels above this are FP64")
     ap.add_argument("--tune", choices=["auto", "off"], default="auto",
                     help="tile autotuning of the leaf LU and leaf solves")
     ap.add_argument("--lu-panel", type=int, default=0, choices=[0, 16, 32],
@@ -305,13 +452,16 @@ def main():
                          "this script (FETCH_SIZE, WRITE_SIZE) and exit")
     ap.add_argument("--traffic-command", default="", help="the counter command, recorded")
     ap.add_argument("--sweep", type=int, default=0, metavar="G",
-                    help="instead of the headline step: time a mixed-precision factorization "
-                         "of G lambdas (logspace(-6, -1, G)) as one sweep sharing the kernel "
-                         "blocks, against G independent factorizations")
+                    help="instead of the headline step: factor G lambdas (logspace(-6, -1, G)) "
+                         "sharing one evaluation of the kernel blocks, and solve each")
+    ap.add_argument("--sweep-mode", choices=["batched", "refactor"], default="batched",
+                    help="batched: all G handles of one sweep, launches batched over "
+                         "--sweep-group lambdas, timed against G independent factorizations; "
+                         "refactor: one sweep handle refactored for each lambda (for workloads "
+                         "whose memory holds one lambda at a time)")
     ap.add_argument("--sweep-group", type=int, default=0, metavar="S",
-                    help="with --sweep: factor the lambdas in sweeps of S handles at a time "
-                         "(each group shares its kernel blocks; for workloads whose handles "
-                         "do not all fit in HBM together)")
+                    help="with --sweep-mode batched: lambdas per batched launch (0: all)")
+    ap.add_argument("--sweep-precision", choices=["mixed", "fp64"], default="mixed")
     args = ap.parse_args()
     headline = args.workload == "susy"
     if args.nrhs is None:
@@ -337,78 +487,32 @@ def main():
     t0 = time.perf_counter()
     pb = make_problem(args.workload, n=args.n, depth=args.depth,
                       progress=lambda text: log(f"setup: {text}"))
-    sizes = np.diff(pb.leaf_offsets)
-    ranks = np.diff(pb.skel_offsets)[1:]
-    leaf_min, leaf_max = int(sizes.min()), int(sizes.max())
-    rank_min, rank_max = int(ranks.min()), int(ranks.max())
-    log(f"setup {time.perf_counter() - t0:.1f} s: N={pb.n} d={pb.d} L={pb.depth} "
-        f"ranks {np.diff(pb.skel_offsets)[1:].min()}..{np.diff(pb.skel_offsets)[1:].max()}")
+    rs = rank_summary(pb)
+    log(f"setup {time.perf_counter() - t0:.1f} s: N={pb.n} d={pb.d} L={pb.depth} {rs}")
     X = torch.from_numpy(pb.X).cuda()
     P = torch.from_numpy(pb.p_values).cuda()
     b = torch.from_numpy(rhs_for(pb, nrhs=args.nrhs)).cuda()
     lam = pb.lam
 
     if args.sweep > 0:
-        lams = list(np.logspace(-6, -1, args.sweep))
-        group = args.sweep_group or len(lams)
-        fac = binding.Factorization(pb, lams[0], precision="mixed", points=X, p_values=P)
-        log(f"sweep warm-up: {fac.device_bytes() / 2**30:.1f} GiB per handle, "
-            f"tiles {fac.tile_config()}")
-        fac.close()  # warm-up (kernel loads, tile tuning, allocator)
-        del fac
-        torch.cuda.empty_cache()
-        torch.cuda.synchronize()
-        t_sweep, t_solve, res, iters = 0.0, 0.0, [], []
-        for g0 in range(0, len(lams), group):
-            part = lams[g0:g0 + group]
-            t0 = time.perf_counter()
-            facs = binding.factor_sweep(pb, part, precision="mixed", points=X, p_values=P)
-            torch.cuda.synchronize()
-            t_sweep += time.perf_counter() - t0
-            for f in facs:
-                t0 = time.perf_counter()
-                _, info, _ = f.solve(b, return_info=True, check=False)
-                torch.cuda.synchronize()
-                t_solve += time.perf_counter() - t0
-                res.append(info["final_rel_residual"])
-                iters.append(info["iterations"])
-            log(f"sweep of {len(part)} lambdas from {part[0]:.1e} factored and solved "
-                f"(residuals {res[-len(part):]})")
-            for f in facs:
-                f.close()
-            del facs
-            torch.cuda.empty_cache()
-        t0 = time.perf_counter()
-        for lam in lams:
-            f = binding.Factorization(pb, lam, precision="mixed", points=X, p_values=P)
-            f.close()
-            del f
-            torch.cuda.empty_cache()
-        torch.cuda.synchronize()
-        t_sep = time.perf_counter() - t0
-        log("independent factorizations done")
-        print(json.dumps({"metric": "lambda-sweep factorization seconds", "lambdas": lams,
-                          "workload": args.workload, "sweep_group": group,
-                          "sweep_s": t_sweep, "separate_s": t_sep,
-                          "per_lambda_sweep_ms": 1e3 * t_sweep / len(lams),
-                          "per_lambda_separate_ms": 1e3 * t_sep / len(lams),
-                          "per_lambda_solve_ms": 1e3 * t_solve / len(lams), "nrhs": args.nrhs,
-                          "refinement_iterations": iters,
-                          "max_refined_residual": max(res), "n": pb.n, "d": pb.d,
-                          "precision": "mixed",
-                          "note": "host-side allocation of each handle's factor storage is "
-                                  "inside both timings"}), flush=True)
+        run_sweep(args, binding, pb, X, P, b)
         return
 
     results = {}
+    kappa = None
     modes = ["mixed", "fp64"] if args.only == "both" else [args.only]
     for mode in modes:
-        fac = binding.Factorization(pb, lam, precision=mode, points=X, p_values=P,
-                                    tune=args.tune, leaf_lu_panel=args.lu_panel,
-                                    leaf_trsm_cols=args.trsm_cols,
-                                    leaf_lu_waves=args.lu_waves)
+        kw = dict(tune=args.tune, leaf_lu_panel=args.lu_panel, leaf_trsm_cols=args.trsm_cols,
+                  leaf_lu_waves=args.lu_waves, fp64_top_levels=args.fp64_top_levels)
+        fac, first = time_first_factor(binding, pb, lam, mode, X, P, kw)
         tiles = fac.tile_config()  # the first factor's trials, if it tuned
-        log(f"{mode}: device bytes {fac.device_bytes() / 2**30:.2f} GiB, tiles {tiles}")
+        # a second handle from nothing, the tuning table now warm
+        fac2, first_warm = time_first_factor(binding, pb, lam, mode, X, P, kw)
+        plan_ms = fac2.phase_times()["handle_planning"]
+        fac2.close()
+        del fac2
+        log(f"{mode}: workspace {fac.device_bytes() / 2**30:.2f} GiB, first factor {first:.3f} s "
+            f"(tuning table warm: {first_warm:.3f} s, planning {plan_ms:.1f} ms), tiles {tiles}")
         for _ in range(args.warmup):
             fac.refactor(lam)
             fac.solve(b, return_info=True, check=False)
@@ -434,12 +538,31 @@ def main():
             seconds=wall, factor_s=tf / args.steps, solve_s=ts / args.steps,
             final_rel_residual=info["final_rel_residual"],
             unrefined_rel_residual=info["unrefined_rel_residual"],
-            iterations=info["iterations"], converged=bool(info["converged"] or mode == "fp64"),
-            status=st, phase_ms={k: v / args.steps for k, v in phases.items()},
-            device_gib=fac.device_bytes() / 2**30, tiles=tiles)
-        log(mode, json.dumps(results[mode]))
+            iterations=info["iterations"], gmres_iterations=info["gmres_iterations"],
+            method=info["method"], converged=bool(info["converged"]), status=st,
+            first_factor_s=first, first_factor_warm_s=first_warm, planning_ms=plan_ms,
+            phase_ms={k: v / args.steps for k, v in phases.items()},
+            workspace_gib=fac.device_bytes() / 2**30, tiles=tiles)
+        if mode == "fp64" and not args.no_kappa:
+            kappa = kappa_estimate(fac, pb.n)
+            log(f"kappa estimate {kappa}")
         fac.close()
         del fac
+        if mode == "fp64":
+            # the direct solve alone (refine = none, no residual check), for
+            # reference: the headline FP64 time above verifies the residual
+            facn = binding.Factorization(pb, lam, precision="fp64", points=X, p_values=P,
+                                         refine="none", **kw)
+            facn.solve(b)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(args.steps):
+                facn.solve(b)
+            torch.cuda.synchronize()
+            results[mode]["direct_solve_s"] = (time.perf_counter() - t1) / args.steps
+            facn.close()
+            del facn
+        log(mode, json.dumps(results[mode]))
         torch.cuda.empty_cache()
 
     head = results.get("mixed") or results["fp64"]
@@ -461,12 +584,17 @@ def main():
         peak = PEAK_TFLOPS["f64" if dom in ("leaf_blocks", "skeleton_blocks") else dtype]
         roof = {"bound": "mfma", "achieved": achieved, "peak": peak,
                 "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
-                "kernel": dom, "launches": wk["launches"], "avg_launch_ms": per_launch_ms}
+                "kernel": dom, "launches": wk["launches"], "avg_launch_ms": per_launch_ms,
+                "algorithmic_tflop": wk["flops"] / 1e12, "algorithmic_gb": wk["bytes"] / 1e9}
     else:
         achieved = wk["bytes"] / wk["launches"] / (per_launch_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom,
-                "launches": wk["launches"], "avg_launch_ms": per_launch_ms}
+                "launches": wk["launches"], "avg_launch_ms": per_launch_ms,
+                "algorithmic_gb": wk["bytes"] / 1e9}
+    ranks = (f"leaves {rs['leaf_min']}..{rs['leaf_max']}, adaptive ranks (ID tolerance "
+             f"{'1e-5' if headline else 'per workload'}) realized {rs['rank_min']}..{rs['rank_max']}, "
+             f"median {rs['rank_median']:.0f}, {100 * rs['at_floor']:.1f}% at the floor")
     out = {
         "metric": METRIC if headline else (
             f"factor+solve sec, FP32+refine vs FP64, {args.workload} N={pb.n} d={pb.d}, "
@@ -482,17 +610,18 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64" if "mixed" in results else "f64",
         "data": "synthetic",
-        "config": {"workload": (f"gaussian-mixture N={pb.n} d={pb.d} (16 unit Gaussians), "
-                                f"ball tree depth {pb.depth}, leaves 64..512, adaptive ranks "
-                                f"32..256 tau=1e-5, h={pb.h}, lambda={lam}") if headline else (
-                                f"{args.workload}: N={pb.n} d={pb.d}, ball tree depth "
-                                f"{pb.depth}, leaves {leaf_min}..{leaf_max}, ranks "
-                                f"{rank_min}..{rank_max}, h={pb.h}, lambda={lam}"),
-                   "nrhs": args.nrhs, "precision": "mixed" if "mixed" in results else "fp64"},
+        "config": {"workload": (f"{args.workload}: gaussian-mixture N={pb.n} d={pb.d}, ball tree "
+                                f"depth {pb.depth}, {ranks}, h={pb.h}, lambda={lam}"),
+                   "nrhs": args.nrhs, "precision": "mixed" if "mixed" in results else "fp64",
+                   "fp64_top_levels": args.fp64_top_levels},
         "roofline": roof,
         "paths": results,
         "work_tflop": {k: v["flops"] / 1e12 for k, v in work.items()},
+        "kappa_estimate": kappa,
     }
+    if "mixed" in results:
+        out["first_factor_s"] = results["mixed"]["first_factor_s"]
+        out["first_factor_warm_s"] = results["mixed"]["first_factor_warm_s"]
     if "mixed" in results and "fp64" in results:
         out["speedup_vs_fp64"] = results["fp64"]["seconds"] / results["mixed"]["seconds"]
     if not args.no_cpu_baseline and headline:

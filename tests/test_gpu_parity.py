@@ -5,6 +5,7 @@ Bars: FP64 path within 1e-10 relative of the oracle's solution; mixed path
 solution close to the oracle's); kernel blocks to FP64 rounding; batched LU
 checked by P A = L U reconstruction and by solves against LAPACK.
 """
+import ctypes as C
 import sys
 
 import numpy as np
@@ -269,15 +270,17 @@ def test_refactor_new_lambda(bind, problems):
     fac.close()
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_lambda_sweep(bind, problems, prec):
-    """Section II-C: one evaluation of the kernel blocks, one factorization
-    per lambda; every handle against the oracle at its own lambda."""
-    _say("lambda sweep", prec)
+@pytest.mark.parametrize("prec,group", [("fp64", 0), ("mixed", 0), ("fp64", 2)])
+def test_lambda_sweep(bind, problems, prec, group):
+    """Section II-C: one evaluation of the kernel blocks, shared by the
+    factorizations of every lambda; the lambdas of a batch share every
+    launch (group 0: all three in one batch; group 2: a batch of two and a
+    batch of one).  Every handle against the oracle at its own lambda."""
+    _say("lambda sweep", prec, group)
     pb, _ = problems("susy", dict(n=8192, depth=5))
     b = rhs_for(pb, nrhs=2)
     lams = [1e-4, 1e-2, 0.3]
-    facs = bind.factor_sweep(pb, lams, precision=prec)
+    facs = bind.factor_sweep(pb, lams, precision=prec, lambda_group=group)
     tol = 1e-10 if prec == "fp64" else 1e-7
 
     def check(fac, lam):
@@ -557,5 +560,60 @@ def test_ill_conditioned_784_dimensional_workload(bind):
         # kappa(lambda I + K~) is about 1e4 at this size (lambda = 1e-2 against
         # |K| of about 2e3): x agrees with the refined oracle to kappa * 1e-10
         _assert_close(x, x_ref, 1e-5, prec)
+        fac.close()
+
+
+def test_sweep_handle_refactored_for_each_lambda(bind):
+    """The memory plan of the large sweep workload: one handle of a sweep
+    (the lambda-free kernel blocks evaluated once into its workspace), then
+    refactored for each further lambda, each solved for 32 right-hand sides
+    right away.  Reduced N, the workload's leaves of 512 and s = 256."""
+    _say("sweep handle refactored per lambda")
+    pb = make_problem("normal", n=8192, depth=4)
+    b = rhs_for(pb, nrhs=32)
+    lams = [1e-6, 1e-3, 1e-1]
+    fac = bind.factor_sweep(pb, lams[:1], precision="mixed")[0]
+    for i, lam in enumerate(lams):
+        if i:
+            fac.refactor(lam)
+        x, info, st = fac.solve(torch.from_numpy(b), return_info=True)
+        assert st == 0 and info["final_rel_residual"] <= 1e-10, (lam, info)
+        x = x.cpu().numpy()
+        assert _col_residual(pb, lam, x, b) <= 1e-10, lam
+        if i == 1:
+            _assert_close(x, oracle.solve(oracle.factorize(pb, lam), b), 1e-7, lam)
+    fac.close()
+
+
+def test_solve_scratch_sizes(bind, problems):
+    """The solve's scratch: the size without the GMRES bases suffices for
+    plain refinement; refine = GMRES then fails with E_WORKSPACE; one byte
+    short of that size fails before any launch; a shorter GMRES restart
+    fits between the two sizes and converges."""
+    _say("solve scratch sizes")
+    pb, F = problems("susy", dict(n=8192, depth=5))
+    b = rhs_for(pb, nrhs=2)
+    x_ref = oracle.solve(F, b)
+    lib = bind.library()
+    bc = bind._colmajor(torch.from_numpy(b))
+    for refine in ("auto", "gmres"):
+        fac = bind.Factorization(pb, pb.lam, precision="mixed", refine=refine)
+        full, low = C.c_size_t(), C.c_size_t()
+        assert lib.invaskit_solve_workspace_bytes(fac.handle, 2, C.byref(full), C.byref(low)) == 0
+        assert low.value < full.value
+        blk = 8 * pb.n * 2
+        for nbytes, expect in ((low.value - 1, bind.E_WORKSPACE),
+                               (low.value, 0 if refine == "auto" else bind.E_WORKSPACE),
+                               (low.value + 8 * blk, 0), (full.value, 0)):
+            sc = bind._device_buffer(nbytes)
+            xc = torch.zeros_like(bc)
+            info = bind.SolveInfo()
+            st = lib.invaskit_solve(fac.handle, C.c_void_p(bc.data_ptr()), 2, pb.n,
+                                    C.c_void_p(xc.data_ptr()), pb.n, C.c_void_p(sc.data_ptr()),
+                                    nbytes, C.byref(info))
+            _say("  ", refine, nbytes - low.value, st, info.as_dict())
+            assert st == expect, (refine, nbytes, bind.last_error(fac.handle))
+            if st == 0:
+                _assert_close(xc.t().cpu().numpy(), x_ref, 1e-7, (refine, nbytes))
         fac.close()
 
