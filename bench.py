@@ -354,10 +354,13 @@ def run_sweep(args, binding, pb, X, P, b):
     if args.sweep_mode == "batched":
         # every lambda in one sweep workspace, batched launches of
         # --sweep-group lambdas (0: all)
+        # warm-up of both forms: kernel loads, tile trials of the batched
+        # and of the single launches, and PyTorch's cached blocks
+        for f in binding.factor_sweep(pb, lams, lambda_group=args.sweep_group, **kw):
+            f.close()
         fac = binding.Factorization(pb, lams[0], **kw)
-        fac.close()  # warm-up: kernel loads and tile trials
+        fac.close()
         del fac
-        torch.cuda.empty_cache()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         facs = binding.factor_sweep(pb, lams, lambda_group=args.sweep_group, **kw)
@@ -369,10 +372,10 @@ def run_sweep(args, binding, pb, X, P, b):
             torch.cuda.synchronize()
             per.append(dict(lam=lam, solve_s=time.perf_counter() - t1, status=st, **info))
         ws = facs[0]._ws.numel()
+        phase = facs[0].phase_times()
         for f in facs:
             f.close()
         del facs
-        torch.cuda.empty_cache()
         t0 = time.perf_counter()
         for lam in lams:
             f = binding.Factorization(pb, lam, **kw)
@@ -380,7 +383,7 @@ def run_sweep(args, binding, pb, X, P, b):
             del f
         torch.cuda.synchronize()
         t_sep = time.perf_counter() - t0
-        out = dict(sweep_s=t_sweep, separate_s=t_sep,
+        out = dict(sweep_s=t_sweep, separate_s=t_sep, sweep_phase_ms=phase,
                    per_lambda_sweep_ms=1e3 * t_sweep / len(lams),
                    per_lambda_separate_ms=1e3 * t_sep / len(lams))
     else:
@@ -462,6 +465,7 @@ def main():
     ap.add_argument("--sweep-group", type=int, default=0, metavar="S",
                     help="with --sweep-mode batched: lambdas per batched launch (0: all)")
     ap.add_argument("--sweep-precision", choices=["mixed", "fp64"], default="mixed")
+    ap.add_argument("--lam", type=float, default=None, help="override the workload's lambda")
     args = ap.parse_args()
     headline = args.workload == "susy"
     if args.nrhs is None:
@@ -492,6 +496,8 @@ def main():
     X = torch.from_numpy(pb.X).cuda()
     P = torch.from_numpy(pb.p_values).cuda()
     b = torch.from_numpy(rhs_for(pb, nrhs=args.nrhs)).cuda()
+    if args.lam is not None:
+        pb.lam = args.lam
     lam = pb.lam
 
     if args.sweep > 0:

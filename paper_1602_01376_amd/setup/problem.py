@@ -9,8 +9,8 @@ are not available, so these are synthetic stand-ins):
            (L=8), s=128, h=2.0, lambda=1e-3, 16 RHS
   susy     N=1,048,576 d=8 16 unit Gaussians, L=12, uneven leaves 64..512,
            adaptive s in [32,256] at tau=1e-5, h=0.5, lambda=1e-4, 1 or 64 RHS
-  susy-wide  the susy points and tree with h=1.0 and tau=1e-13: ranks spread
-           over 32..256 (median about 50, top levels above 200)
+  susy-wide  the susy points and tree with h=1.0, tau=1e-13, lambda=1e-2:
+           ranks spread over 32..256 (median about 50, top levels above 200)
   mnist    N=262,144 d=784 sparse [0,1] coordinates stored fp32, m=512 (L=9),
            s=256, h=4.0, lambda=1e-2
   normal   N=4,194,304 d=64 32 unit Gaussians, m=512 (L=13), s=256, h=1.5,
@@ -98,7 +98,7 @@ WORKLOADS = {
     # ID tolerance, so that the adaptive ranks spread over 32..256
     "susy-wide": dict(idx=3, n=1 << 20, d=8, mixture=16, scale_range=None, depth=12,
                       split="random", leaf_min=64, leaf_max=512, s_min=32, s_max=256,
-                      tau=1e-13, n_samp=320, h=1.0, lam=1e-4, nrhs=1),
+                      tau=1e-13, n_samp=320, h=1.0, lam=1e-2, nrhs=1),
     "mnist": dict(idx=4, n=1 << 18, d=784, sparse=True, depth=9, split="median",
                   s_fixed=256, n_samp=320, h=4.0, lam=1e-2, nrhs=1),
     "normal": dict(idx=5, n=1 << 22, d=64, mixture=32, scale_range=None, depth=13,

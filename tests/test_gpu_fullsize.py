@@ -97,3 +97,60 @@ def test_full_size_covtype_16_rhs(bind):
     diff = np.linalg.norm(xs["mixed"] - xs["fp64"]) / np.linalg.norm(xs["fp64"])
     _say("mixed vs fp64", diff)
     assert diff <= 1e-8
+
+
+def test_full_size_64_rhs(bind):
+    """The benchmark workload at full size with 64 right-hand sides: every
+    column's sampled residual (oracle rows) within the tolerance."""
+    _say("setup susy full size, 64 rhs")
+    pb = make_problem("susy")
+    b = rhs_for(pb, nrhs=64)
+    rows = np.random.default_rng(7).choice(pb.n, 256, replace=False)
+    fac = bind.Factorization(pb, pb.lam, precision="mixed")
+    x, info, st = fac.solve(torch.from_numpy(b), return_info=True)
+    _say("  info", info)
+    assert st == 0 and info["final_rel_residual"] <= 1e-10
+    x = x.cpu().numpy()
+    q = oracle.skeletonize_weights(pb, x)
+    y = oracle.matvec_rows(pb, pb.lam, x, rows, q=q)
+    r = b[rows] - y
+    est = np.sqrt(np.mean(r ** 2, axis=0) * pb.n) / np.linalg.norm(b, axis=0)
+    _say("  worst column's sampled residual", est.max())
+    assert est.shape == (64,) and est.max() <= 1e-10
+    fac.close()
+
+
+def test_full_size_wide_ranks(bind):
+    """The benchmark's points and tree with ranks spread over 32..256 (h = 1,
+    ID tolerance 1e-13, lambda = 1e-2): uneven ranks at every level in the
+    batched launches, both precisions, at full size.  kappa is about 4e6
+    here (K~ has eigenvalues near -lambda), so the two solutions agree to
+    kappa times their residuals."""
+    _say("setup susy-wide full size")
+    pb = make_problem("susy-wide")
+    ranks = np.diff(pb.skel_offsets)[1:]
+    assert ranks.min() == 32 and ranks.max() == 256 and np.mean(ranks == 32) < 0.5
+    b = rhs_for(pb, nrhs=1)
+    X = torch.from_numpy(pb.X).cuda()
+    P = torch.from_numpy(pb.p_values).cuda()
+    bt = torch.from_numpy(b).cuda()
+    rows = np.random.default_rng(9).choice(pb.n, 1024, replace=False)
+    xs = {}
+    for mode in ("fp64", "mixed"):
+        _say("factor + solve", mode)
+        fac = bind.Factorization(pb, pb.lam, precision=mode, points=X, p_values=P)
+        x, info, st = fac.solve(bt, return_info=True)
+        _say("  info", info)
+        assert st == 0 and info["final_rel_residual"] <= 1e-10
+        x = x.cpu().numpy()
+        q = oracle.skeletonize_weights(pb, x)
+        est, rmax = _sampled_residual(pb, x, b, rows, q)
+        _say("  sampled relative residual", est, "max row", rmax)
+        assert est <= 1e-10
+        xs[mode] = x
+        fac.close()
+        del fac
+        torch.cuda.empty_cache()
+    diff = np.linalg.norm(xs["mixed"] - xs["fp64"]) / np.linalg.norm(xs["fp64"])
+    _say("mixed vs fp64", diff)
+    assert diff <= 1e-3
