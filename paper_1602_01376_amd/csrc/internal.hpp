@@ -181,12 +181,6 @@ hipError_t launch_getrf(const LuProb* probs, int count, int nmax, int kind, int 
                         hipStream_t s);
 int getrf_default_panel(bool t64);
 
-// adds shift to the diagonal of each square block (rows x rows, leading
-// dimension ld) of the table: the lambda of a factorization that reuses
-// kernel blocks evaluated without it
-template <typename T>
-hipError_t launch_shift_diag(const EvalBlock* blocks, int count, double shift, hipStream_t s);
-
 template <typename PT, typename T>
 hipError_t launch_eval(const PT* X, int d, double h, double shift, const EvalBlock* blocks,
                        const Tile3* tiles, int ntiles, hipStream_t s);
@@ -218,10 +212,6 @@ hipError_t launch_copy_cols(const TI* in, int64_t ldi, TO* out, int64_t ldo, int
 template <typename TD>
 hipError_t launch_axpy_cols(double* x, int64_t ldx, const TD* d, int64_t ldd, int64_t n,
                             int ncols, const double* scale, hipStream_t s);
-// out[c] = sum_i v[i + c*ld]^2 (out must be zeroed by the launcher)
-hipError_t launch_colsumsq(const double* v, int64_t ld, int64_t n, int ncols, double* out,
-                           hipStream_t s);
-hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 // v[i + c*ld] *= scale[c] (scale on the device); v[i + c*ld] = 0
 hipError_t launch_scale_cols(double* v, int64_t ld, int64_t n, int ncols, const double* scale,
                              hipStream_t s);

@@ -451,25 +451,7 @@ __global__ __launch_bounds__(256) void k_mv_eval_gram(
   }
 }
 
-// lambda shift of the diagonal of every (square) block of a table
-template <typename T>
-__global__ __launch_bounds__(256) void k_shift_diag(const EvalBlock* __restrict__ blocks,
-                                                     double shift) {
-  const EvalBlock b = blocks[blockIdx.x];
-  T* __restrict__ out = static_cast<T*>(b.out);
-  for (int i = threadIdx.x; i < b.rows; i += 256) out[(int64_t)i * b.ld + i] += (T)shift;
-}
-
 }  // namespace
-
-template <typename T>
-hipError_t launch_shift_diag(const EvalBlock* blocks, int count, double shift, hipStream_t s) {
-  if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_shift_diag<T>), dim3(count), dim3(256), 0, s, blocks, shift);
-  return hipGetLastError();
-}
-template hipError_t launch_shift_diag<double>(const EvalBlock*, int, double, hipStream_t);
-template hipError_t launch_shift_diag<float>(const EvalBlock*, int, double, hipStream_t);
 
 template <typename PT, typename T>
 hipError_t launch_eval(const PT* X, int d, double h, double shift, const EvalBlock* blocks,

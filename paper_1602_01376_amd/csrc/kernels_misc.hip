@@ -65,22 +65,6 @@ __global__ void k_axpy_cols(double* __restrict__ x, int64_t ldx, const TD* __res
     x[c * ldx + i] += s * (double)d[c * ldd + i];
 }
 
-__global__ __launch_bounds__(256) void k_colsumsq(const double* __restrict__ v, int64_t ld,
-                                                  int64_t n, double* __restrict__ out) {
-  __shared__ double part[4];
-  const int c = blockIdx.y;
-  double acc = 0.0;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const double a = v[c * ld + i];
-    acc = fma(a, a, acc);
-  }
-  for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
-  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
-  __syncthreads();
-  if (threadIdx.x == 0) atomicAdd(out + c, part[0] + part[1] + part[2] + part[3]);
-}
-
 // Multi-dot, first pass: the rows of column c are cut into nblk chunks;
 // block (b, c, k) sums V_k[i, c] * w[i, c] over chunk b and writes
 // part[(k * ncols + c) * nblk + b].  V_k = V + k * vstride, column c at
@@ -105,14 +89,18 @@ __global__ __launch_bounds__(256) void k_dots_part(const double* __restrict__ V,
     part[((int64_t)k * ncols + c) * nblk + b] = (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
 }
 
-// Multi-dot, second pass: out[t] = sum over b of part[t * nblk + b], in order.
-__global__ void k_dots_sum(const double* __restrict__ part, int nblk, int count,
-                           double* __restrict__ out) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= count) return;
-  double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += part[(int64_t)t * nblk + b];
-  out[t] = s;
+// Multi-dot, second pass: out[t] = sum over b of part[t * nblk + b], one
+// workgroup per output (nblk <= 256): one partial per thread, summed by the
+// same butterfly in every wave and the four waves in a fixed order.
+__global__ __launch_bounds__(256) void k_dots_sum(const double* __restrict__ part, int nblk,
+                                                  double* __restrict__ out) {
+  __shared__ double wsum[4];
+  const int t = blockIdx.x;
+  double v = (int)threadIdx.x < nblk ? part[(int64_t)t * nblk + threadIdx.x] : 0.0;
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) out[t] = (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
 }
 
 // out[i, c] += alpha * sum_k coef[k * ncols + c] * V_k[i, c]
@@ -144,12 +132,6 @@ __global__ void k_zero_cols(double* __restrict__ v, int64_t ld, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
     v[c * ld + i] = 0.0;
-}
-
-__global__ void k_zero(unsigned char* __restrict__ p, size_t bytes) {
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < bytes;
-       i += (size_t)gridDim.x * blockDim.x)
-    p[i] = 0;
 }
 
 int grid_for(int64_t n) {
@@ -218,16 +200,6 @@ template hipError_t launch_axpy_cols<float>(double*, int64_t, const float*, int6
 template hipError_t launch_axpy_cols<double>(double*, int64_t, const double*, int64_t, int64_t,
                                              int, const double*, hipStream_t);
 
-hipError_t launch_colsumsq(const double* v, int64_t ld, int64_t n, int ncols, double* out,
-                           hipStream_t s) {
-  if (ncols <= 0) return hipSuccess;
-  hipError_t e = launch_fill_zero(out, sizeof(double) * ncols, s);
-  if (e != hipSuccess || n <= 0) return e;
-  const int g = (grid_for(n) + ncols - 1) / ncols + 1;
-  hipLaunchKernelGGL(k_colsumsq, dim3(g, ncols), dim3(256), 0, s, v, ld, n, out);
-  return hipGetLastError();
-}
-
 int dots_blocks(int64_t n) {
   int64_t nb = (n + 4095) / 4096;
   if (nb > 256) nb = 256;
@@ -249,9 +221,7 @@ hipError_t launch_dots(const double* V, int64_t vstride, int64_t ldv, int nk, co
                      ldw, n, chunk, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int count = nk * ncols;
-  hipLaunchKernelGGL(k_dots_sum, dim3((count + 255) / 256), dim3(256), 0, s, part, nblk, count,
-                     out);
+  hipLaunchKernelGGL(k_dots_sum, dim3(nk * ncols), dim3(256), 0, s, part, nblk, out);
   return hipGetLastError();
 }
 
@@ -277,14 +247,6 @@ hipError_t launch_zero_cols(double* v, int64_t ld, int64_t n, int ncols, hipStre
   if (n <= 0 || ncols <= 0) return hipSuccess;
   const int g = (grid_for(n) + ncols - 1) / ncols + 1;
   hipLaunchKernelGGL(k_zero_cols, dim3(g, ncols), dim3(256), 0, s, v, ld, n);
-  return hipGetLastError();
-}
-
-hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s) {
-  if (bytes == 0) return hipSuccess;
-  int64_t g = (int64_t)((bytes + 255) / 256);
-  if (g > 4096) g = 4096;
-  hipLaunchKernelGGL(k_zero, dim3((int)g), dim3(256), 0, s, static_cast<unsigned char*>(p), bytes);
   return hipGetLastError();
 }
 
