@@ -71,13 +71,16 @@ COPY_KERNEL = "k_copy_cols<double, double>"
 # the phase's kernel; {p} and {w} are its tile parameters (LU panel width and
 # waves per matrix, or 16-column tiles per workgroup of the solves)
 PHASE_KERNEL = {
-    "leaf_lu": (r"k_getrf<{t}, {p}, \d+, 0, {w}>", "kernels_lu.hip"),
-    "leaf_solves": (r"k_getrs<{t}, {t}, 0, {p}>", "kernels_trsm.hip"),
+    "leaf_lu_large": (r"k_getrf<{t}, {p}, \d+, 0, {w}>", "kernels_lu.hip"),
+    "leaf_solves_large": (r"k_getrs<{t}, {t}, 0, {p}>", "kernels_trsm.hip"),
 }
+# leaves of at most this order form the library's small class (FP32, FP64),
+# factored and solved on its second stream
+SMALL_LEAF = {4: 192, 8: 256}
 
 
 def phase_tile_params(phase, tiles):
-    if phase == "leaf_lu":
+    if phase == "leaf_lu_large":
         return dict(p=str(tiles["leaf_lu_panel"]), w=str(tiles["leaf_lu_waves"]))
     return dict(p=str(tiles["leaf_trsm_cols"] // 16), w="")
 
@@ -193,18 +196,29 @@ def algorithmic_work(pb, esize):
         z[c] = s[2 * c + 1] + s[2 * c + 2]
     W = {k: dict(flops=0.0, bytes=0.0, launches=0) for k in
          ("leaf_blocks", "leaf_lu", "leaf_diag_inverses", "skeleton_blocks", "leaf_solves",
-          "leaf_projections", "skeleton_sweep", "reduced_systems")}
+          "leaf_projections", "skeleton_sweep", "reduced_systems", "leaf_lu_large",
+          "leaf_solves_large")}
+    small = SMALL_LEAF[esize]
     for lf in leaves:
         m = size[lf]
         W["leaf_blocks"]["bytes"] += m * m * esize
         W["leaf_blocks"]["flops"] += gram * m * m
         W["leaf_lu"]["flops"] += 2.0 / 3.0 * m ** 3
         W["leaf_lu"]["bytes"] += 2.0 * m * m * esize
+        if m > small:
+            W["leaf_lu_large"]["flops"] += 2.0 / 3.0 * m ** 3
+            W["leaf_lu_large"]["bytes"] += 2.0 * m * m * esize
         nb = -(-m // 64)
         W["leaf_diag_inverses"]["flops"] += nb * 2.0 * 64 ** 3 / 3.0
         W["leaf_diag_inverses"]["bytes"] += nb * 3 * 64 * 64 * esize
-    for key in ("leaf_blocks", "leaf_lu", "leaf_diag_inverses"):
-        W[key]["launches"] = 1
+    # one launch each, except the leaf LU, inverses and solves: one per size
+    # class (the large class's own launches are the *_large entries)
+    has_small = bool(np.any(size[first_leaf:] <= small))
+    has_large = bool(np.any(size[first_leaf:] > small))
+    W["leaf_blocks"]["launches"] = 1
+    for key in ("leaf_lu", "leaf_diag_inverses"):
+        W[key]["launches"] = int(has_small) + int(has_large)
+    W["leaf_lu_large"]["launches"] = int(has_large)
     for k in range(L, 0, -1):
         for lf in leaves:
             m = size[lf]
@@ -214,6 +228,9 @@ def algorithmic_work(pb, esize):
             W["skeleton_blocks"]["flops"] += gram * m * wk
             W["leaf_solves"]["flops"] += 2.0 * m * m * wk
             W["leaf_solves"]["bytes"] += 2 * m * wk * esize
+            if m > small:
+                W["leaf_solves_large"]["flops"] += 2.0 * m * m * wk
+                W["leaf_solves_large"]["bytes"] += 2 * m * wk * esize
             W["leaf_projections"]["flops"] += 2.0 * s[lf] * m * wk
             W["leaf_projections"]["bytes"] += (s[lf] * m + m * wk + s[lf] * wk) * esize
         for j in range(L - 1, k - 1, -1):
@@ -226,8 +243,10 @@ def algorithmic_work(pb, esize):
             W["reduced_systems"]["bytes"] += 3.0 * z[a] ** 2 * esize
     # one launch each over every level's columns; the sweep and the reduced
     # systems run as one wavefront step (two launches) per level
-    for key in ("skeleton_blocks", "leaf_solves", "leaf_projections"):
+    for key in ("skeleton_blocks", "leaf_projections"):
         W[key]["launches"] = 1
+    W["leaf_solves"]["launches"] = int(has_small) + int(has_large)
+    W["leaf_solves_large"]["launches"] = int(has_large) if L > 0 else 0
     # the reduced-system factor is read once per sweep step (all factor levels)
     for j in range(1, L):
         for bn in range((1 << j) - 1, (2 << j) - 1):
@@ -236,6 +255,8 @@ def algorithmic_work(pb, esize):
     W["reduced_systems"]["launches"] = 3 * L
     for lf in leaves:  # the leaf LU is read once by the all-level leaf solve
         W["leaf_solves"]["bytes"] += size[lf] ** 2 * esize
+        if size[lf] > small:
+            W["leaf_solves_large"]["bytes"] += size[lf] ** 2 * esize
     return W
 
 

@@ -148,10 +148,13 @@ typedef struct invaskit_options {
 } invaskit_options;
 
 /*
- * Tile autotuning.  The two largest launches of a factorization, the LU of
- * the leaf blocks (Algorithm 1's leaf factorization) and the leaf solves of
- * every level's panel columns (Algorithm 2 at the leaves), each have two
- * tile shapes: for the LU a panel width of 16 or 32 and 4 or 8 waves per
+ * Tile autotuning.  The leaves are factored and solved in two size classes
+ * (orders up to 192 in FP32, 256 in FP64, and the rest), the small class on
+ * the factorization's second stream beside the large one.  The two largest
+ * launches of a factorization, the LU of the leaf blocks (Algorithm 1's leaf
+ * factorization; the large class, or the small one without large leaves)
+ * and the leaf solves of every level's panel columns (Algorithm 2 at the
+ * leaves; each class on its own), each have two tile shapes: for the LU a panel width of 16 or 32 and 4 or 8 waves per
  * matrix (8 halves each thread's panel rows and doubles the waves sharing a
  * matrix's trailing update), for the solves 16 or 32 right-hand sides per
  * workgroup (32 reuses each factor tile for twice the columns but needs
@@ -338,8 +341,10 @@ int invaskit_device_bytes(invaskit_handle handle, size_t* bytes);
  * blocks, [4] leaf solves, [5] leaf projections, [6] skeleton sweep, [7]
  * host planning of the handle (descriptor tables built and uploaded; wall
  * clock; not part of [9]), [8] reduced systems
- * (assembly, LU, diagonal-block inverses), [9] total.
- * Writes min(n, 10) values.
+ * (assembly, LU, diagonal-block inverses), [9] total, [10] the leaf LU of
+ * the large leaves alone (one launch on the caller's stream; [1] adds the
+ * small leaves' LU on the second stream), [11] the leaf solves of the large
+ * leaves alone (likewise part of [4]).  Writes min(n, 12) values.
  */
 int invaskit_phase_times(invaskit_handle handle, double* ms, int32_t n);
 
@@ -347,11 +352,15 @@ int invaskit_phase_times(invaskit_handle handle, double* ms, int32_t n);
 typedef struct invaskit_tile_config {
   int32_t leaf_lu_panel;   /* 16 or 32                                          */
   int32_t leaf_lu_waves;   /* 4 or 8                                            */
-  int32_t leaf_trsm_cols;  /* 16 or 32                                          */
+  int32_t leaf_trsm_cols;  /* 16 or 32: the solves of the large leaves          */
   int32_t tuned;           /* 1 if that factor timed candidates itself          */
   float lu_ms[4];          /* its trial times (best of two) for the LU with
                               (panel, waves) = (16,4), (32,4), (16,8), (32,8)   */
   float trsm_ms[2];        /* and for 16, 32 right-hand sides; 0 if not timed   */
+  int32_t leaf_trsm_cols_small; /* 16 or 32: the solves of the small leaves
+                              (orders up to 192 in FP32, 256 in FP64); 0 if
+                              there are none                                     */
+  float trsm_small_ms[2];  /* their trial times for 16, 32; 0 if not timed      */
 } invaskit_tile_config;
 int invaskit_tile_config_get(invaskit_handle handle, invaskit_tile_config* out);
 

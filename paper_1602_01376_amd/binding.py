@@ -53,7 +53,8 @@ REFINE = {"auto": 0, "ir": 1, "gmres": 2, "none": 3}
 class _TileConfig(C.Structure):
     _fields_ = [("leaf_lu_panel", C.c_int32), ("leaf_lu_waves", C.c_int32),
                 ("leaf_trsm_cols", C.c_int32), ("tuned", C.c_int32),
-                ("lu_ms", C.c_float * 4), ("trsm_ms", C.c_float * 2)]
+                ("lu_ms", C.c_float * 4), ("trsm_ms", C.c_float * 2),
+                ("leaf_trsm_cols_small", C.c_int32), ("trsm_small_ms", C.c_float * 2)]
 
 
 class SolveInfo(C.Structure):
@@ -301,11 +302,11 @@ class Factorization:
         return y[:, 0] if vec else y
 
     def phase_times(self):
-        out = (C.c_double * 10)()
-        _check(_lib.invaskit_phase_times(self._handle, out, 10), self._handle)
+        out = (C.c_double * 12)()
+        _check(_lib.invaskit_phase_times(self._handle, out, 12), self._handle)
         keys = ["leaf_blocks", "leaf_lu", "leaf_diag_inverses", "skeleton_blocks", "leaf_solves",
                 "leaf_projections", "skeleton_sweep", "handle_planning", "reduced_systems",
-                "total"]
+                "total", "leaf_lu_large", "leaf_solves_large"]
         return dict(zip(keys, list(out)))
 
     def tile_config(self):
@@ -314,7 +315,8 @@ class Factorization:
         _check(_lib.invaskit_tile_config_get(self._handle, C.byref(t)), self._handle)
         return {"leaf_lu_panel": t.leaf_lu_panel, "leaf_lu_waves": t.leaf_lu_waves,
                 "leaf_trsm_cols": t.leaf_trsm_cols, "tuned": t.tuned, "lu_ms": list(t.lu_ms),
-                "trsm_ms": list(t.trsm_ms)}
+                "trsm_ms": list(t.trsm_ms), "leaf_trsm_cols_small": t.leaf_trsm_cols_small,
+                "trsm_small_ms": list(t.trsm_small_ms)}
 
     def device_bytes(self):
         """Bytes of the factor workspace this handle's buffers span."""

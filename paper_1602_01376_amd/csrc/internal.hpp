@@ -153,12 +153,17 @@ __device__ __host__ __forceinline__ int xcd_tile(int b, int nb) {
 template <typename T>
 hipError_t launch_gemm(const GemmProb* probs, const GemmSeg* segs, const Tile3* tiles,
                        int ntiles, bool transposed, hipStream_t s);
-// skinny form: N <= kGemvCols, M <= kGemvRows and every A column-major; one
-// workgroup per problem
+// skinny forms, one workgroup per problem, every N <= kGemvCols:
+// kGemvSplitK: M <= kGemvRows, A column-major, the four waves split K;
+// kGemvRowMajor: A row-major, one wave per row (chosen for a mean K of at
+// least kGemvRmMinK)
 constexpr int kGemvCols = 4;
 constexpr int kGemvRows = 128;
+constexpr int kGemvRmMinK = 128;
+constexpr int kGemvSplitK = 1, kGemvRowMajor = 3;
 template <typename T>
-hipError_t launch_gemv(const GemmProb* probs, const GemmSeg* segs, int count, hipStream_t s);
+hipError_t launch_gemv(const GemmProb* probs, const GemmSeg* segs, int count, int form,
+                       hipStream_t s);
 
 // kind: 0 leaf panels of the factorization, 1 reduced systems, 2 solve phase
 // (library factors, padded by 64 elements), 3 caller-owned factors.  cols:

@@ -80,8 +80,10 @@ constexpr int kMaxLeaf = 1024;
 constexpr int kMaxSkel = 512;
 constexpr int kMaxDepth = 24;
 constexpr int kEvents = 8;
-constexpr int kPhases = 10;  // see invaskit_phase_times
+constexpr int kPhases = 12;  // see invaskit_phase_times
 constexpr size_t kAlign = 256;
+// leaves of at most this order form the small class (FP32, FP64)
+constexpr int kSmallLeaf32 = 192, kSmallLeaf64 = 256;
 // placeholder base of the planning runs that only measure sizes; never
 // dereferenced
 unsigned char* const kPlanBase = reinterpret_cast<unsigned char*>(uintptr_t(1) << 40);
@@ -183,11 +185,16 @@ struct FactorPlan {
   bool cached = false;  // kernel blocks come from a KernelCache
   EvalL leaf_eval;      // leaf blocks: into the factor storage, or the cache
   CopyShiftL leaf_copy; // cached plans: cache -> factor storage, + lambda I
-  LuL leaf_lu;
-  DinvL leaf_dinv;
+  // The leaves in two size classes: [0] the large ones, on the caller's
+  // stream; [1] the small ones (orders up to kSmallLeaf: the one-wave LU in
+  // FP32, one panel row per thread in FP64), whose LU, diagonal-block
+  // inverses and solves run on the second stream beside the large leaves'
+  // LU.  Each class's solves have their own LDS size and tile choice.
+  LuL leaf_lu[2];
+  DinvL leaf_dinv[2];
   EvalL panels;         // skeleton blocks of every level (into W storage or the cache)
-  TrsmL leaf_trsm[2];   // leaf solves of every level's panel columns, 16 and 32
-                        // right-hand sides per workgroup (ntiles < 0: no room)
+  TrsmL leaf_trsm[2][2];  // [class][16 or 32 right-hand sides per workgroup]
+                          // (ntiles < 0: no room in LDS)
   GemmL leaf_proj;      // leaf projections of every level's panel columns
   std::vector<ZformL> zform;  // index j: reduced systems of level j
   std::vector<LuL> zlu;
@@ -515,17 +522,28 @@ struct GemmBuilder {
     probs.back().nseg++;
   }
   GemmL emit(Arena& ar) {
-    // Skinny launches (every N <= kGemvCols, M <= kGemvRows, every A
-    // column-major) take the GEMV form: one workgroup per product.
+    // Skinny launches (every N <= kGemvCols) take a GEMV form, one workgroup
+    // per product, when it pays (measured): column-major A with M <=
+    // kGemvRows (the waves split K), or row-major A with long rows (mean K of
+    // at least kGemvRmMinK: one wave per row).  Others take the tiles.
     {
-      bool skinny = !probs.empty();
+      bool skinny = !probs.empty(), all_cm = true, all_rm = true;
+      int mmax = 0;
+      double ksum = 0.0;
       for (const GemmProb& p : probs) {
-        skinny = skinny && p.N <= kGemvCols && p.M <= kGemvRows;
-        for (int q = 0; q < p.nseg && skinny; ++q) skinny = segs[p.seg0 + q].a_rm == 0;
+        skinny = skinny && p.N <= kGemvCols;
+        mmax = std::max(mmax, p.M);
+        for (int q = 0; q < p.nseg; ++q) {
+          all_cm = all_cm && segs[p.seg0 + q].a_rm == 0;
+          all_rm = all_rm && segs[p.seg0 + q].a_rm != 0;
+          ksum += segs[p.seg0 + q].k;
+        }
       }
-      if (skinny) {
+      const bool cm_ok = all_cm && mmax <= kGemvRows;
+      const bool rm_ok = all_rm && ksum >= (double)kGemvRmMinK * probs.size();
+      if (skinny && (cm_ok || rm_ok)) {
         GemmL l;
-        l.gemv = 1;
+        l.gemv = cm_ok ? kGemvSplitK : kGemvRowMajor;
         l.nprobs = (int)probs.size();
         l.probs = ar.add(probs);
         l.segs = ar.add(segs);
@@ -841,11 +859,12 @@ void build_factor_tables(const std::vector<H*>& hs, const KernelCache* kc, Arena
     std::vector<EvalBlock> lblocks, pblocks;
     std::vector<Tile3> ltiles, ptiles;
     std::vector<CopyShiftProb> copies;
-    std::vector<LuProb> lus;
-    std::vector<DiagInvProb> dis;
-    TrsmBuilder tb;
+    std::vector<LuProb> lus[2];
+    std::vector<DiagInvProb> dis[2];
+    TrsmBuilder tb[2];
     GemmBuilder proj;
-    int nmax = 0;
+    int nmax[2] = {0, 0};
+    const int small_leaf = T64 ? kSmallLeaf64 : kSmallLeaf32;
     for (size_t g = 0; g < hs.size(); ++g) {
       H* hg = hs[g];
       for (int j = 0; j < h->nleaves; ++j) {
@@ -875,14 +894,15 @@ void build_factor_tables(const std::vector<H*>& hs, const KernelCache* kc, Arena
           c.shift = hg->lam;
           copies.push_back(c);
         }
+        const int cls = m <= small_leaf ? 1 : 0;
         LuProb p{};
         p.a = lu;
         p.perm = static_cast<int32_t*>(hg->leafPerm.p) + h->na[lf];
         p.info = static_cast<int32_t*>(hg->leafInfo.p) + j;
         p.n = m;
-        lus.push_back(p);
-        nmax = std::max(nmax, m);
-        fp.leaf_lu.work += (double)m * m * m;
+        lus[cls].push_back(p);
+        nmax[cls] = std::max(nmax[cls], m);
+        fp.leaf_lu[cls].work += (double)m * m * m;
         for (int jb = 0; jb < m; jb += kDiagBlock) {
           DiagInvProb d{};
           d.lu = lu;
@@ -890,7 +910,7 @@ void build_factor_tables(const std::vector<H*>& hs, const KernelCache* kc, Arena
           d.out = offv(hg->dinvLeaf.p, h->dleaf_off[j] + (jb / kDiagBlock) * kDB2, es);
           d.n = m;
           d.jb = jb;
-          dis.push_back(d);
+          dis[cls].push_back(d);
         }
         if (L == 0) continue;
         void* slab = offv(hg->slab.p, h->slab_off[j], es);
@@ -913,8 +933,8 @@ void build_factor_tables(const std::vector<H*>& hs, const KernelCache* kc, Arena
                 ptiles.push_back({(int)pblocks.size() - 1, tm, tn});
           }
         }
-        tb.add(lu, hg->DL(j), static_cast<const int32_t*>(hg->leafPerm.p) + h->na[lf], m,
-               h->S[j], kin, m, m, kin, m, slab, m);
+        tb[cls].add(lu, hg->DL(j), static_cast<const int32_t*>(hg->leafPerm.p) + h->na[lf], m,
+                    h->S[j], kin, m, m, kin, m, slab, m);
         proj.begin(offv(hg->psw.p, h->psw_off[lf], es), h->s[lf], h->s[lf], h->S[j], 1.0, 0.0);
         proj.seg(offv(hg->Pt(), h->p_off[lf], es), m, true, slab, m, m);
       }
@@ -928,20 +948,24 @@ void build_factor_tables(const std::vector<H*>& hs, const KernelCache* kc, Arena
     // largest matrices first: one workgroup per matrix, so the launch's tail
     // is set by the matrices dispatched last
     auto by_order = [](const LuProb& x, const LuProb& y) { return x.n > y.n; };
-    std::stable_sort(lus.begin(), lus.end(), by_order);
-    fp.leaf_lu.probs = ar.add(lus);
-    fp.leaf_lu.count = (int)lus.size();
-    fp.leaf_lu.nmax = nmax;
-    fp.leaf_lu.t64 = T64;
-    fp.leaf_dinv.probs = ar.add(dis);
-    fp.leaf_dinv.count = (int)dis.size();
-    fp.leaf_dinv.t64 = T64;
+    for (int c = 0; c < 2; ++c) {
+      std::stable_sort(lus[c].begin(), lus[c].end(), by_order);
+      fp.leaf_lu[c].probs = ar.add(lus[c]);
+      fp.leaf_lu[c].count = (int)lus[c].size();
+      fp.leaf_lu[c].nmax = nmax[c];
+      fp.leaf_lu[c].t64 = T64;
+      fp.leaf_dinv[c].probs = ar.add(dis[c]);
+      fp.leaf_dinv[c].count = (int)dis[c].size();
+      fp.leaf_dinv[c].t64 = T64;
+    }
     fp.panels.blocks = ar.add(pblocks);
     fp.panels.tiles = ar.add(ptiles);
     fp.panels.ntiles = (int)ptiles.size();
     fp.panels.nblocks = (int)pblocks.size();
-    fp.leaf_trsm[0] = tb.emit(ar, T64, T64, 0, 16);
-    fp.leaf_trsm[1] = tb.emit(ar, T64, T64, 0, 32);
+    for (int c = 0; c < 2; ++c) {
+      fp.leaf_trsm[c][0] = tb[c].emit(ar, T64, T64, 0, 16);
+      fp.leaf_trsm[c][1] = tb[c].emit(ar, T64, T64, 0, 32);
+    }
     fp.leaf_proj = proj.emit(ar);
   }
   // wavefront over levels j = L-1 .. 0
@@ -1038,7 +1062,8 @@ hipError_t run_gemm(const Buf& tb, const GemmL& l, bool f64, hipStream_t s) {
   const GemmProb* p = at<GemmProb>(tb, l.probs);
   const GemmSeg* g = at<GemmSeg>(tb, l.segs);
   if (l.gemv)
-    return f64 ? launch_gemv<double>(p, g, l.nprobs, s) : launch_gemv<float>(p, g, l.nprobs, s);
+    return f64 ? launch_gemv<double>(p, g, l.nprobs, l.gemv, s)
+               : launch_gemv<float>(p, g, l.nprobs, l.gemv, s);
   hipError_t e = hipSuccess;
   if (l.ntiles > 0)
     e = f64 ? launch_gemm<double>(p, g, at<Tile3>(tb, l.tiles), l.ntiles, false, s)
@@ -1141,26 +1166,35 @@ int tune_factor(H* h, const FactorPlan& fp) {
   hipStream_t s = h->stream;
   invaskit_tile_config& tc = h->tiles;
   tc = invaskit_tile_config{};
-  const bool has32 = fp.leaf_trsm[1].ntiles >= 0;
-  const bool has_trsm = h->L > 0 && fp.leaf_trsm[0].ntiles > 0;
-  // panel width and waves matter only for the block kernel (FP64, and FP32
-  // orders above 192)
-  const bool lu_choice = fp.leaf_lu.t64 || fp.leaf_lu.nmax > 192;
-  const std::string klu = lu_key(fp.leaf_lu), ktr = trsm_key(fp.leaf_trsm[0]);
-  const std::string klw = "getrfw" + klu.substr(5);
-  int lu = h->fix_lu_panel, lw = h->fix_lu_waves, tr = h->fix_trsm_cols;
-  if (tr == 32 && !has32)
-    return fail_h(h, INVASKIT_E_ARG,
-                  "leaf_trsm_cols = 32 needs more than 160 KiB of LDS at this leaf size");
-  if (fp.leaf_lu.t64 && h->fix_lu_panel == 32 && h->fix_lu_waves == 8)
+  // the LU tiles are timed on the class that runs the block kernel: the
+  // large leaves, or the small ones when there are no large ones
+  const int luc = fp.leaf_lu[0].count > 0 ? 0 : 1;
+  const LuL& LU = fp.leaf_lu[luc];
+  const bool lu_choice = LU.count > 0 && (LU.t64 || LU.nmax > kSmallLeaf32);
+  const std::string klu = lu_key(LU), klw = "getrfw" + klu.substr(5);
+  bool has32[2], has_trsm[2];
+  std::string ktr[2];
+  int tr[2];
+  for (int c = 0; c < 2; ++c) {
+    has32[c] = fp.leaf_trsm[c][1].ntiles >= 0;
+    has_trsm[c] = h->L > 0 && fp.leaf_trsm[c][0].ntiles > 0;
+    ktr[c] = trsm_key(fp.leaf_trsm[c][0]);
+    tr[c] = h->fix_trsm_cols;
+    if (tr[c] == 32 && has_trsm[c] && !has32[c])
+      return fail_h(h, INVASKIT_E_ARG,
+                    "leaf_trsm_cols = 32 needs more than 160 KiB of LDS at this leaf size");
+    if (!tr[c] && (!has32[c] || !has_trsm[c])) tr[c] = kTrsmColsDefault;
+  }
+  int lu = h->fix_lu_panel, lw = h->fix_lu_waves;
+  if (f64 && h->fix_lu_panel == 32 && h->fix_lu_waves == 8)
     return fail_h(h, INVASKIT_E_ARG, "the FP64 leaf LU has no panel 32 at 8 waves");
   if (!lu && !lu_choice) lu = getrf_default_panel(f64);
   if (!lw && !lu_choice) lw = 4;
-  if (!tr && (!has32 || !has_trsm)) tr = kTrsmColsDefault;
   if (h->tune == INVASKIT_TUNE_OFF) {
     if (!lu) lu = getrf_default_panel(f64);
     if (!lw) lw = 4;
-    if (!tr) tr = kTrsmColsDefault;
+    for (int& t : tr)
+      if (!t) t = kTrsmColsDefault;
   }
   {
     std::lock_guard<std::mutex> g(tune_table().mu);
@@ -1170,9 +1204,10 @@ int tune_factor(H* h, const FactorPlan& fp) {
       lu = t[klu];
       lw = t[klw];
     }
-    if (!tr && t.count(ktr)) tr = t[ktr];
+    for (int c = 0; c < 2; ++c)
+      if (!tr[c] && t.count(ktr[c])) tr[c] = t[ktr[c]];
   }
-  if (!lu || !lw || !tr) {
+  if (!lu || !lw || !tr[0] || !tr[1]) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIP_TRY(h, hipEventCreate(&e0));
     if (hipEventCreate(&e1) != hipSuccess) {
@@ -1200,8 +1235,8 @@ int tune_factor(H* h, const FactorPlan& fp) {
       return fp.cached ? run_copy_shift(h, tb, fp.leaf_copy, s)
                        : run_eval(h, tb, fp.leaf_eval, h->lam, s);
     };
-    auto lu_with = [&](int panel, int waves) {
-      LuL l = fp.leaf_lu;
+    auto lu_with = [&](const LuL& base, int panel, int waves) {
+      LuL l = base;
       l.panel = panel;
       l.waves = waves;
       return run_lu(tb, l, s);
@@ -1214,8 +1249,8 @@ int tune_factor(H* h, const FactorPlan& fp) {
       int bi = -1;
       for (int i = 0; i < 4 && e == hipSuccess; ++i) {
         if ((lu && cp[i] != lu) || (lw && cw[i] != lw)) continue;
-        if (fp.leaf_lu.t64 && cp[i] == 32 && cw[i] == 8) continue;  // not built
-        trial(eval_leaves, [&]() { return lu_with(cp[i], cw[i]); }, tc.lu_ms[i]);
+        if (f64 && cp[i] == 32 && cw[i] == 8) continue;  // not built
+        trial(eval_leaves, [&]() { return lu_with(LU, cp[i], cw[i]); }, tc.lu_ms[i]);
         if (e == hipSuccess && (bi < 0 || tc.lu_ms[i] < best)) {
           best = tc.lu_ms[i];
           bi = i;
@@ -1226,18 +1261,24 @@ int tune_factor(H* h, const FactorPlan& fp) {
         lw = cw[bi];
       }
     }
-    if (!tr && e == hipSuccess) {
+    if ((!tr[0] || !tr[1]) && e == hipSuccess) {
       // the solves need the leaf factors and their diagonal-block inverses
       e = eval_leaves();
-      if (e == hipSuccess) e = lu_with(lu, lw);
-      if (e == hipSuccess) e = run_dinv(tb, fp.leaf_dinv, s);
+      for (int c = 0; c < 2 && e == hipSuccess; ++c) {
+        e = lu_with(fp.leaf_lu[c], lu, lw);
+        if (e == hipSuccess) e = run_dinv(tb, fp.leaf_dinv[c], s);
+      }
       // in place unless the solves read the cache
       auto eval_panels = [&]() {
         return fp.cached ? hipSuccess : run_eval(h, tb, fp.panels, 0.0, s);
       };
-      trial(eval_panels, [&]() { return run_trsm(tb, fp.leaf_trsm[0], s); }, tc.trsm_ms[0]);
-      trial(eval_panels, [&]() { return run_trsm(tb, fp.leaf_trsm[1], s); }, tc.trsm_ms[1]);
-      tr = tc.trsm_ms[1] < tc.trsm_ms[0] ? 32 : 16;
+      for (int c = 0; c < 2; ++c) {
+        if (tr[c]) continue;
+        float* ms = c == 0 ? tc.trsm_ms : tc.trsm_small_ms;
+        trial(eval_panels, [&]() { return run_trsm(tb, fp.leaf_trsm[c][0], s); }, ms[0]);
+        trial(eval_panels, [&]() { return run_trsm(tb, fp.leaf_trsm[c][1], s); }, ms[1]);
+        tr[c] = ms[1] < ms[0] ? 32 : 16;
+      }
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     hipEventDestroy(e0);
@@ -1251,11 +1292,13 @@ int tune_factor(H* h, const FactorPlan& fp) {
       t[klu] = lu;
       t[klw] = lw;
     }
-    if (!h->fix_trsm_cols && has32 && has_trsm) t[ktr] = tr;
+    for (int c = 0; c < 2; ++c)
+      if (!h->fix_trsm_cols && has32[c] && has_trsm[c]) t[ktr[c]] = tr[c];
   }
   tc.leaf_lu_panel = lu;
   tc.leaf_lu_waves = lw;
-  tc.leaf_trsm_cols = tr;
+  tc.leaf_trsm_cols = tr[0];
+  tc.leaf_trsm_cols_small = fp.leaf_lu[1].count > 0 ? tr[1] : 0;
   return INVASKIT_OK;
 }
 
@@ -1282,6 +1325,7 @@ int run_factor(const std::vector<H*>& hs, const FactorPlan& fp, KernelCache* kc)
     int phase;
   };
   std::vector<Bracket> brackets;
+  int open_on[2] = {-1, -1};
   std::vector<hipEvent_t> pool;
   auto new_event = [&](unsigned flags) -> hipEvent_t {
     hipEvent_t e = nullptr;
@@ -1302,17 +1346,26 @@ int run_factor(const std::vector<H*>& hs, const FactorPlan& fp, KernelCache* kc)
                     std::string(#__VA_ARGS__) + ": " + hipGetErrorString(e_));    \
     }                                                                             \
   } while (0)
+  // open(phase, stream) starts a bracket on a stream; close(stream) ends the
+  // latest open bracket of that stream
   auto open = [&](int phase, hipStream_t st) -> hipError_t {
     hipEvent_t e = new_event(hipEventDefault);
     if (!e) return hipErrorOutOfMemory;
     brackets.push_back({e, nullptr, phase});
+    open_on[st == s ? 0 : 1] = (int)brackets.size() - 1;
     return hipEventRecord(e, st);
   };
   auto close = [&](hipStream_t st) -> hipError_t {
     hipEvent_t e = new_event(hipEventDefault);
     if (!e) return hipErrorOutOfMemory;
-    brackets.back().b = e;
+    brackets[open_on[st == s ? 0 : 1]].b = e;
     return hipEventRecord(e, st);
+  };
+  // an event recorded on `st` now
+  auto mark = [&](hipStream_t st, hipEvent_t* out) -> hipError_t {
+    *out = new_event(hipEventDisableTiming);
+    if (!*out) return hipErrorOutOfMemory;
+    return hipEventRecord(*out, st);
   };
   // stream `to` waits for the work enqueued so far on `from`
   auto join = [&](hipStream_t from, hipStream_t to) -> hipError_t {
@@ -1332,12 +1385,14 @@ int run_factor(const std::vector<H*>& hs, const FactorPlan& fp, KernelCache* kc)
   // the side stream starts after everything already on the caller's stream
   STEP(join(s, s2));
   const bool eval_now = !fp.cached || !kc->valid;
+  hipEvent_t ev_panels = nullptr, ev_leaf = nullptr, ev_side = nullptr;
   if (eval_now) {
     // kernel blocks (into the factor storage, or once into a sweep's cache)
     if (L > 0) {
       STEP(open(3, s2));
       STEP(run_eval(h, tb, fp.panels, 0.0, s2));
       STEP(close(s2));
+      STEP(mark(s2, &ev_panels));
     }
     if (!f64 && h->p_off[h->nn] > 0)
       STEP(launch_convert_f64_f32(h->P64, static_cast<float*>(const_cast<void*>(h->Pf)),
@@ -1351,6 +1406,7 @@ int run_factor(const std::vector<H*>& hs, const FactorPlan& fp, KernelCache* kc)
       STEP(join(s2, s));
       STEP(hipStreamSynchronize(s));
       kc->valid = true;
+      ev_panels = nullptr;  // complete
     }
     // the tile choices need the evaluated cache (their trials copy from it)
     if (int rc = tune_factor(h, fp)) {
@@ -1361,22 +1417,48 @@ int run_factor(const std::vector<H*>& hs, const FactorPlan& fp, KernelCache* kc)
     STEP(run_copy_shift(h, tb, fp.leaf_copy, s));
     STEP(close(s));
   }
-  STEP(open(1, s));
-  {
-    LuL lu = fp.leaf_lu;
-    lu.panel = h->tiles.leaf_lu_panel;
-    lu.waves = h->tiles.leaf_lu_waves;
-    STEP(run_lu(tb, lu, s));
+  STEP(mark(s, &ev_leaf));  // every leaf block is in place
+  auto lu_of = [&](const LuL& base) {
+    LuL l = base;
+    l.panel = h->tiles.leaf_lu_panel;
+    l.waves = h->tiles.leaf_lu_waves;
+    return l;
+  };
+  // small leaves on the second stream: LU, inverses and solves beside the
+  // large leaves' LU (their skeleton blocks were evaluated earlier on it)
+  if (fp.leaf_lu[1].count > 0) {
+    STEP(hipStreamWaitEvent(s2, ev_leaf, 0));
+    STEP(open(1, s2));
+    STEP(run_lu(tb, lu_of(fp.leaf_lu[1]), s2));
+    STEP(close(s2));
+    STEP(open(2, s2));
+    STEP(run_dinv(tb, fp.leaf_dinv[1], s2));
+    STEP(close(s2));
+    if (L > 0) {
+      STEP(open(4, s2));
+      STEP(run_trsm(tb, fp.leaf_trsm[1][h->tiles.leaf_trsm_cols_small == 32 ? 1 : 0], s2));
+      STEP(close(s2));
+    }
   }
-  STEP(close(s));
-  STEP(open(2, s));
-  STEP(run_dinv(tb, fp.leaf_dinv, s));
-  STEP(close(s));
-  if (L > 0) {
-    STEP(join(s2, s));  // skeleton blocks done
-    STEP(open(4, s));
-    STEP(run_trsm(tb, fp.leaf_trsm[h->tiles.leaf_trsm_cols == 32 ? 1 : 0], s));
+  STEP(mark(s2, &ev_side));
+  if (fp.leaf_lu[0].count > 0) {
+    STEP(open(10, s));  // added into [1] below
+    STEP(run_lu(tb, lu_of(fp.leaf_lu[0]), s));
     STEP(close(s));
+    STEP(open(2, s));
+    STEP(run_dinv(tb, fp.leaf_dinv[0], s));
+    STEP(close(s));
+  }
+  if (L > 0) {
+    if (ev_panels) STEP(hipStreamWaitEvent(s, ev_panels, 0));  // skeleton blocks done
+    if (fp.leaf_lu[0].count > 0) {
+      STEP(open(11, s));  // added into [4] below
+      STEP(run_trsm(tb, fp.leaf_trsm[0][h->tiles.leaf_trsm_cols == 32 ? 1 : 0], s));
+      STEP(close(s));
+    }
+  }
+  STEP(hipStreamWaitEvent(s, ev_side, 0));  // the small leaves are done
+  if (L > 0) {
     STEP(open(5, s));
     STEP(run_gemm(tb, fp.leaf_proj, f64, s));
     STEP(close(s));
@@ -1404,8 +1486,11 @@ int run_factor(const std::vector<H*>& hs, const FactorPlan& fp, KernelCache* kc)
   }
   {
     float ms = 0.f;
-    if (hipEventElapsedTime(&ms, t_begin, t_end) == hipSuccess) ms_ph[kPhases - 1] = ms;
+    if (hipEventElapsedTime(&ms, t_begin, t_end) == hipSuccess) ms_ph[9] = ms;
   }
+  // [1] and [4] cover both size classes; [10] and [11] the large leaves alone
+  ms_ph[1] += ms_ph[10];
+  ms_ph[4] += ms_ph[11];
   cleanup();
 #undef STEP
   // pivot status of every member

@@ -490,7 +490,11 @@ hipError_t launch_mv_eval(const PT* X, int d, double h, double lam, const MvTile
   else                                                                                       \
     hipLaunchKernelGGL((k_mv_eval_gram<PT, 4>), dim3(ntiles), dim3(256), 0, s, X, d, c, lam,   \
                        tiles, segs, x, ldx, y, ldy, b, ldb, nrhs)
-  if (nrhs <= 4) {
+  // columns per pass: one for a single right-hand side (no idle
+  // accumulators), four, or sixteen
+  if (nrhs == 1) {
+    INVASKIT_MV_RC(1);
+  } else if (nrhs <= 4) {
     INVASKIT_MV_RC(4);
   } else {
     INVASKIT_MV_RC(16);

@@ -215,16 +215,62 @@ __global__ __launch_bounds__(256) void k_gemv(const GemmProb* __restrict__ probs
   }
 }
 
+// Skinny products with row-major A (the projections by P): one wave per
+// output row, lanes striding along the row (coalesced) and a butterfly sum
+// across the wave.
+template <typename T>
+__global__ __launch_bounds__(256) void k_gemv_rm(const GemmProb* __restrict__ probs,
+                                                 const GemmSeg* __restrict__ segs) {
+  const GemmProb P = probs[blockIdx.x];
+  T* __restrict__ C = static_cast<T*>(P.C);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int row = wave; row < P.M; row += 4) {
+    T acc[kGemvCols];
+#pragma unroll
+    for (int c = 0; c < kGemvCols; ++c) acc[c] = T(0);
+    for (int sg = P.seg0; sg < P.seg0 + P.nseg; ++sg) {
+      const GemmSeg g = segs[sg];
+      const T* __restrict__ A = static_cast<const T*>(g.A) + (int64_t)row * g.lda;
+      const T* __restrict__ B = static_cast<const T*>(g.B);
+#pragma unroll 4
+      for (int k = lane; k < g.k; k += 64) {
+        const T a = A[k];
+#pragma unroll
+        for (int c = 0; c < kGemvCols; ++c)
+          if (c < P.N) acc[c] = fma(a, B[(int64_t)c * g.ldb + k], acc[c]);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < kGemvCols; ++c)
+      if (c < P.N)
+        for (int off = 32; off >= 1; off >>= 1) acc[c] += __shfl_xor(acc[c], off, 64);
+    if (lane == 0) {
+#pragma unroll
+      for (int c = 0; c < kGemvCols; ++c) {
+        if (c < P.N) {
+          T* out = C + (int64_t)c * P.ldc + row;
+          const T r = (T)P.alpha * acc[c];
+          *out = (P.beta != 0.0) ? (T)P.beta * (*out) + r : r;
+        }
+      }
+    }
+  }
+}
+
 }  // namespace
 
 template <typename T>
-hipError_t launch_gemv(const GemmProb* probs, const GemmSeg* segs, int count, hipStream_t s) {
+hipError_t launch_gemv(const GemmProb* probs, const GemmSeg* segs, int count, int form,
+                       hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_gemv<T>), dim3(count), dim3(256), 0, s, probs, segs);
+  if (form == kGemvRowMajor)
+    hipLaunchKernelGGL((k_gemv_rm<T>), dim3(count), dim3(256), 0, s, probs, segs);
+  else
+    hipLaunchKernelGGL((k_gemv<T>), dim3(count), dim3(256), 0, s, probs, segs);
   return hipGetLastError();
 }
-template hipError_t launch_gemv<double>(const GemmProb*, const GemmSeg*, int, hipStream_t);
-template hipError_t launch_gemv<float>(const GemmProb*, const GemmSeg*, int, hipStream_t);
+template hipError_t launch_gemv<double>(const GemmProb*, const GemmSeg*, int, int, hipStream_t);
+template hipError_t launch_gemv<float>(const GemmProb*, const GemmSeg*, int, int, hipStream_t);
 
 template <typename T>
 hipError_t launch_gemm(const GemmProb* probs, const GemmSeg* segs, const Tile3* tiles,

@@ -186,7 +186,8 @@ def test_options_struct_layout():
     assert C.sizeof(S) == 32 and S.final_rel_residual.offset == 8
     assert S.gmres_iterations.offset == 24 and S.method.offset == 28
     T = binding._TileConfig
-    assert C.sizeof(T) == 40 and T.lu_ms.offset == 16 and T.trsm_ms.offset == 32
+    assert C.sizeof(T) == 52 and T.lu_ms.offset == 16 and T.trsm_ms.offset == 32
+    assert T.leaf_trsm_cols_small.offset == 40 and T.trsm_small_ms.offset == 44
 
 
 def test_tuning_table_text_round_trip():

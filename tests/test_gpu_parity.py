@@ -133,9 +133,15 @@ def test_batched_lu_and_solve(bind, dtype, sizes_name):
 
 
 # (M, N, K, A row-major).  "tiles": the matrix-core kernel (row-major A with
-# M < N runs transposed); "skinny": every N <= 4 with column-major A, which
-# and M <= 128 takes the one-workgroup-per-product GEMV form
+# M < N runs transposed); "skinny": every N <= 4 with column-major A and
+# M <= 128, the GEMV form whose waves split K; "tall": N <= 4, column-major
+# A, some M above 128 (the tiles); "rowmajor": N <= 4 with row-major A and
+# a mean K of at least 128, one wave per row
 GEMM_SHAPES = {
+    "tall": [(512, 1, 420, False), (300, 4, 64, False), (129, 2, 7, False), (64, 1, 5, False),
+             (257, 3, 0, False), (1000, 1, 1, False)],
+    "rowmajor": [(35, 1, 256, True), (71, 4, 513, True), (1, 1, 1, True), (200, 2, 300, True),
+                 (5, 3, 0, True), (130, 1, 64, True)],
     "tiles": [(1, 1, 1, False), (16, 16, 4, False), (64, 64, 16, True), (65, 63, 17, False),
               (200, 37, 129, True), (32, 256, 300, False), (257, 5, 64, True), (3, 70, 0, False),
               (40, 300, 70, True), (3, 81, 50, True), (71, 500, 33, True), (130, 79, 200, False)],
@@ -145,7 +151,7 @@ GEMM_SHAPES = {
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-@pytest.mark.parametrize("kind", ["tiles", "skinny"])
+@pytest.mark.parametrize("kind", ["tiles", "skinny", "tall", "rowmajor"])
 def test_grouped_gemm(bind, dtype, kind):
     _say("gemm_batched", dtype, kind)
     rng = np.random.default_rng(13)
@@ -318,8 +324,8 @@ def test_fixed_tiles_match_oracle(bind, problems, prec, lu, lw, tr):
     fac = bind.Factorization(pb, pb.lam, precision=prec, leaf_lu_panel=lu, leaf_trsm_cols=tr,
                              leaf_lu_waves=lw)
     tc = fac.tile_config()
-    assert (tc["leaf_lu_panel"], tc["leaf_lu_waves"], tc["leaf_trsm_cols"], tc["tuned"]) == \
-        (lu, lw, tr, 0)
+    assert (tc["leaf_lu_panel"], tc["leaf_lu_waves"], tc["leaf_trsm_cols"], tc["tuned"],
+            tc["leaf_trsm_cols_small"]) == (lu, lw, tr, 0, tr)
     x, info, st = fac.solve(torch.from_numpy(b), return_info=True)
     assert st == 0 and info["final_rel_residual"] <= 1e-10
     _say("  unrefined", info["unrefined_rel_residual"])
@@ -346,6 +352,7 @@ def test_wide_leaf_solves_at_largest_leaf(bind, problems):
     assert ei.value.status == bind.E_ARG and "LDS" in str(ei.value)
     fac = bind.Factorization(pb, pb.lam, precision="fp64")
     assert fac.tile_config()["leaf_trsm_cols"] == 16
+    assert fac.tile_config()["leaf_trsm_cols_small"] == 0  # no small leaves here
     fac.close()
     # eight waves per matrix: two panel rows per thread at order 1024
     for prec in ("fp64", "mixed"):
@@ -371,9 +378,13 @@ def test_autotune_times_candidates_once(bind, problems, tmp_path):
     best = int(np.argmin(tc["lu_ms"]))
     assert (tc["leaf_lu_panel"], tc["leaf_lu_waves"]) == ((16, 4), (32, 4), (16, 8), (32, 8))[best]
     assert tc["leaf_trsm_cols"] == (32 if tc["trsm_ms"][1] < tc["trsm_ms"][0] else 16)
+    # the small leaves' solves (orders up to 192 in FP32) are tuned on their own
+    assert min(tc["trsm_small_ms"]) > 0
+    assert tc["leaf_trsm_cols_small"] == \
+        (32 if tc["trsm_small_ms"][1] < tc["trsm_small_ms"][0] else 16)
     table = bind.tuning_table()
     assert sorted(table.values()) == sorted([tc["leaf_lu_panel"], tc["leaf_lu_waves"],
-                                             tc["leaf_trsm_cols"]])
+                                             tc["leaf_trsm_cols"], tc["leaf_trsm_cols_small"]])
     x = fac.solve(torch.from_numpy(b)).cpu().numpy()
     _assert_close(x, oracle.solve(F, b), 1e-7)
     fac.refactor(3e-3)
@@ -381,6 +392,7 @@ def test_autotune_times_candidates_once(bind, problems, tmp_path):
     assert tc2["tuned"] == 0 and tc2["leaf_lu_panel"] == tc["leaf_lu_panel"]
     assert tc2["leaf_lu_waves"] == tc["leaf_lu_waves"]
     assert tc2["leaf_trsm_cols"] == tc["leaf_trsm_cols"]
+    assert tc2["leaf_trsm_cols_small"] == tc["leaf_trsm_cols_small"]
     fac.close()
     fac = bind.Factorization(pb, pb.lam, precision="mixed")
     assert fac.tile_config()["tuned"] == 0
@@ -392,8 +404,8 @@ def test_autotune_times_candidates_once(bind, problems, tmp_path):
     assert bind.load_tuning(path) == len(table) and bind.tuning_table() == table
     fac = bind.Factorization(pb, pb.lam, precision="mixed", tune="off")
     tc3 = fac.tile_config()
-    assert (tc3["leaf_lu_panel"], tc3["leaf_lu_waves"], tc3["leaf_trsm_cols"], tc3["tuned"]) == \
-        (32, 4, 16, 0)
+    assert (tc3["leaf_lu_panel"], tc3["leaf_lu_waves"], tc3["leaf_trsm_cols"], tc3["tuned"],
+            tc3["leaf_trsm_cols_small"]) == (32, 4, 16, 0, 16)
     fac.close()
     bind.tuning_clear()
 
