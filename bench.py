@@ -107,36 +107,45 @@ def short_kernel_name(name):
 
 
 def read_counter_csv(path, counter):
+    """Counter values per (kernel, grid size): the two leaf size classes
+    launch the same kernel with different grids."""
     per = {}
     with open(path) as fh:
         for r in csv.DictReader(fh):
             if r["Counter_Name"] != counter:
                 continue
-            per.setdefault(short_kernel_name(r["Kernel_Name"]), []).append(float(r["Counter_Value"]))
+            key = (short_kernel_name(r["Kernel_Name"]), int(r["Grid_Size"]))
+            per.setdefault(key, []).append(float(r["Counter_Value"]))
     return per
+
+
+def _by_name(per, name):
+    return [v for (k, _), vals in per.items() if k == name for v in vals]
 
 
 def write_traffic(fetch_csv, write_csv, copy_bytes, command):
     fetch = read_counter_csv(fetch_csv, "FETCH_SIZE")
     write = read_counter_csv(write_csv, "WRITE_SIZE")
     kib = copy_bytes / 1024.0
-    f_scale = kib / np.mean(fetch[COPY_KERNEL])
-    w_scale = kib / np.mean(write[COPY_KERNEL])
+    copy_f, copy_w = np.mean(_by_name(fetch, COPY_KERNEL)), np.mean(_by_name(write, COPY_KERNEL))
+    f_scale, w_scale = kib / copy_f, kib / copy_w
     entries = {}
     for phase, (pat, src) in PHASE_KERNEL.items():
         for t in ("float", "double"):
             rx = re.compile(pat.format(t=t, p=r"\d+", w=r"\d+") + "$")
-            names = [k for k in fetch if rx.match(k)]
-            for k in names:
-                fk, wk = float(np.mean(fetch[k])), float(np.mean(write.get(k, [0.0])))
-                entries[k] = {"phase": phase, "dispatches": len(fetch[k]),
-                              "fetch_kib": fk, "write_kib": wk,
-                              "bytes": float((fk * f_scale + wk * w_scale) * 1024.0),
-                              "source": src, "sha256": source_digest(src)}
+            for (k, grid), vals in fetch.items():
+                if not rx.match(k):
+                    continue
+                fk = float(np.mean(vals))
+                wk = float(np.mean(write.get((k, grid), [0.0])))
+                entries[f"{k} grid {grid}"] = {
+                    "kernel": k, "grid": grid, "phase": phase, "dispatches": len(vals),
+                    "fetch_kib": fk, "write_kib": wk,
+                    "bytes": float((fk * f_scale + wk * w_scale) * 1024.0),
+                    "source": src, "sha256": source_digest(src)}
     out = {"command": command, "calibration": {
         "kernel": COPY_KERNEL, "bytes_each_way": copy_bytes,
-        "fetch_kib": float(np.mean(fetch[COPY_KERNEL])),
-        "write_kib": float(np.mean(write[COPY_KERNEL])),
+        "fetch_kib": float(copy_f), "write_kib": float(copy_w),
         "fetch_scale": float(f_scale), "write_scale": float(w_scale)}, "kernels": entries}
     os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
     with open(TRAFFIC_FILE, "w") as fh:
@@ -147,7 +156,9 @@ def write_traffic(fetch_csv, write_csv, copy_bytes, command):
 def traffic_for(phase, t, tiles):
     """Scaled HBM bytes per launch of the phase's kernel (the tile variant
     the factorization used), or None when no counters were taken for it or
-    the kernel's sources changed since."""
+    the kernel's sources changed since.  Of that kernel's launch grids the
+    largest-traffic one is the large leaf class's launch (the small class
+    and the tuner's trials on small sizes move fewer bytes)."""
     if phase not in PHASE_KERNEL or not os.path.exists(TRAFFIC_FILE):
         return None
     pat, src = PHASE_KERNEL[phase]
@@ -155,10 +166,9 @@ def traffic_for(phase, t, tiles):
     with open(TRAFFIC_FILE) as fh:
         data = json.load(fh)
     digest = source_digest(src)
-    for name, e in data.get("kernels", {}).items():
-        if rx.match(name) and e.get("sha256") == digest:
-            return e["bytes"]
-    return None
+    found = [e["bytes"] for e in data.get("kernels", {}).values()
+             if rx.match(e.get("kernel", "")) and e.get("sha256") == digest]
+    return max(found) if found else None
 
 
 # ----------------------------------------------------------- work accounting

@@ -134,9 +134,9 @@ __global__ __launch_bounds__(64 * NW) void k_getrf(const LuProb* __restrict__ pr
 
   extern __shared__ __align__(16) unsigned char smem[];
   int* Ps = reinterpret_cast<int*>(smem);  // logical row -> physical row, n entries
-  __shared__ T s_row[2][NW][W];            // each wave's candidate pivot row
-  __shared__ key_t<T> s_bk[2][NW];
-  __shared__ uint32_t s_bl[2][NW];
+  __shared__ __align__(16) T s_row[2][NW][W];  // each wave's candidate pivot row
+  __shared__ __align__(16) key_t<T> s_bk[2][NW];
+  __shared__ __align__(16) uint32_t s_bl[2][NW];
   __shared__ T L11[W][W + 1];              // a panel's unit-lower block, then L21_ab
   __shared__ T Lsup[W2][W2 + 1];           // inverse of the 2W superpanel's unit-lower block
   __shared__ T Uc[W2][CH];                 // U12 chunk
@@ -197,21 +197,30 @@ __global__ __launch_bounds__(64 * NW) void k_getrf(const LuProb* __restrict__ pr
         s_bl[buf][wave] = wl;
       }
       __syncthreads();
+      // every wave's candidate in one round of LDS reads, the winner (largest
+      // key, then the smaller logical row) by selects, then its row in one
+      // more round: two dependent LDS latencies per column
+      key_t<T> kv[NW];
+      uint32_t lv[NW];
+#pragma unroll
+      for (int ww = 0; ww < NW; ++ww) {
+        kv[ww] = s_bk[buf][ww];
+        lv[ww] = s_bl[buf][ww];
+      }
       int w = 0;
-      key_t<T> kv = s_bk[buf][0];
-      uint32_t plu = s_bl[buf][0];
+      key_t<T> kbest = kv[0];
+      uint32_t plu = lv[0];
 #pragma unroll
       for (int ww = 1; ww < NW; ++ww) {
-        const key_t<T> k = s_bk[buf][ww];
-        const uint32_t l = s_bl[buf][ww];
-        if (k > kv || (k == kv && l < plu)) {
-          kv = k;
-          plu = l;
-          w = ww;
-        }
+        const bool better = kv[ww] > kbest || (kv[ww] == kbest && lv[ww] < plu);
+        kbest = better ? kv[ww] : kbest;
+        plu = better ? lv[ww] : plu;
+        w = better ? ww : w;
       }
       const int pl = (int)plu;
-      const T* prow = s_row[buf][w];
+      T prow[W];
+#pragma unroll
+      for (int c = 0; c < W; ++c) prow[c] = (c >= jj) ? s_row[buf][w][c] : T(0);
       const T pv = prow[jj];
       const bool ok = (pv != T(0)) && isfinite(pv);
       if (!ok && info == 0) info = j0 + jj + 1;

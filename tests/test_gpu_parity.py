@@ -629,3 +629,32 @@ def test_solve_scratch_sizes(bind, problems):
                 _assert_close(xc.t().cpu().numpy(), x_ref, 1e-7, (refine, nbytes))
         fac.close()
 
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_factor_and_solve_are_bitwise_reproducible(bind, problems, prec):
+    """Every reduction runs in a fixed order (no atomics; the two streams of
+    a factorization write disjoint buffers), so a second factorization of
+    the same problem, a refactor of the first handle at the same lambda,
+    repeated solves and repeated products all reproduce the first result
+    bit for bit.  Uneven leaves put work on both size classes."""
+    _say("bitwise reproducibility", prec)
+    pb, _ = problems("susy", dict(n=16384, depth=5))
+    b = torch.from_numpy(rhs_for(pb, nrhs=3))
+    a = bind.Factorization(pb, pb.lam, precision=prec)
+    x0, info0, _ = a.solve(b, return_info=True)
+    x0 = x0.cpu().numpy()
+    y0 = a.matvec(b).cpu().numpy()
+    runs = {"second solve": a.solve(b).cpu().numpy()}
+    c = bind.Factorization(pb, pb.lam, precision=prec)
+    x1, info1, _ = c.solve(b, return_info=True)
+    runs["second factorization"] = x1.cpu().numpy()
+    assert info1["iterations"] == info0["iterations"]
+    a.refactor(pb.lam)
+    runs["refactor at the same lambda"] = a.solve(b).cpu().numpy()
+    for what, x in runs.items():
+        assert x.tobytes() == x0.tobytes(), (what, np.abs(x - x0).max())
+    assert a.matvec(b).cpu().numpy().tobytes() == y0.tobytes()
+    assert c.matvec(b).cpu().numpy().tobytes() == y0.tobytes()
+    a.close()
+    c.close()
