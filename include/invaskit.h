@@ -145,7 +145,14 @@ typedef struct invaskit_options {
   int32_t max_gmres_iters;  /* cap on GMRES steps over all cycles (default 300)  */
   int32_t lambda_group;     /* invaskit_factor_sweep: lambdas per batched launch
                                (0, the default: all of them)                      */
+  int32_t zlu_form;         /* 0 (default): per `tune`; INVASKIT_ZLU_ONE_WAVE or
+                               INVASKIT_ZLU_BLOCK: the LU form of the reduced
+                               systems of order up to 192 on every level          */
+  int32_t zsolve_cols;      /* 0 (default): per `tune`; 16 or 32: right-hand sides
+                               per workgroup in the sweep's reduced-system solves */
 } invaskit_options;
+#define INVASKIT_ZLU_ONE_WAVE 1
+#define INVASKIT_ZLU_BLOCK    2
 
 /*
  * Tile autotuning.  The leaves are factored and solved in two size classes
@@ -181,6 +188,18 @@ typedef struct invaskit_options {
  * INVASKIT_E_ARG, and the tuner leaves that pair out.  32 right-hand sides need (32 + 1) * elem + 4 bytes of LDS
  * per row of the largest leaf; if that exceeds 160 KiB (FP64 leaves above
  * 611 points) AUTO keeps 16 and a fixed 32 fails with INVASKIT_E_ARG.
+ *
+ * The level wavefront of Algorithm 1 (the reduced systems of eq. (11) and
+ * the sweep that applies them) is tuned per level the same way.  The LU of
+ * a level's reduced systems of order up to 192 has two forms: one wave per
+ * system (no workgroup barriers, the shorter per-column chain; the FP32
+ * default) or four waves per system (the block kernel; the FP64 default),
+ * and which wins depends on how many systems the level has; the solves of
+ * the sweep take 16 or 32 right-hand sides per workgroup.  Trials rebuild
+ * the level's reduced systems before each LU and leave the sweep's inputs
+ * untouched, so they run inside the first factorization of a shape class;
+ * keys "zgetrf.*" (value 1 one wave, 2 block) and "getrs.*.k1.*".  A
+ * nonzero zlu_form or zsolve_cols fixes that choice on every level.
  */
 #define INVASKIT_TUNE_AUTO 0
 #define INVASKIT_TUNE_OFF  1
@@ -361,13 +380,18 @@ typedef struct invaskit_tile_config {
                               (orders up to 192 in FP32, 256 in FP64); 0 if
                               there are none                                     */
   float trsm_small_ms[2];  /* their trial times for 16, 32; 0 if not timed      */
+  int32_t zlu_one_wave_levels; /* bit j set: level j's reduced systems were
+                              factored by the one-wave kernel                    */
+  int32_t zsolve32_levels; /* bit j set: the sweep at level j took 32
+                              right-hand sides per workgroup                     */
 } invaskit_tile_config;
 int invaskit_tile_config_get(invaskit_handle handle, invaskit_tile_config* out);
 
 /*
  * The process-wide tuning table as text, one "key value" line per entry
- * (key: shape class, value: the chosen tile parameter: 16 or 32, or for the
- * "getrfw." keys the LU's waves, 4 or 8), so that a caller can keep it
+ * (key: shape class, value: the chosen tile parameter: 16 or 32, for the
+ * "getrfw." keys the LU's waves, 4 or 8, for the "zgetrf." keys the reduced
+ * systems' LU form, 1 or 2), so that a caller can keep it
  * across processes.  export: writes at most `n` bytes including the
  * terminating NUL into buf (buf may be NULL when n == 0) and sets *needed to
  * the full size including the NUL.  import: adds (or replaces) the entries of

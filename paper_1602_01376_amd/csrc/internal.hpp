@@ -180,10 +180,15 @@ hipError_t launch_diag_inv(const DiagInvProb* probs, int count, hipStream_t s);
 
 // kind: 0 leaf blocks, 1 reduced systems.  panel: the LU panel width, 0 for
 // the default (getrf_default_panel), or 16 / 32 for kind 0; waves: waves per
-// matrix of the block kernel, 0 for the default (4), or 4 / 8 for kind 0
+// matrix of the block kernel, 0 for the default (4), or 4 / 8 for kind 0.
+// form (orders up to kOneWaveMax): kLuFormAuto takes the one-wave kernel in
+// FP32 and the block kernel in FP64; kLuFormOneWave and kLuFormBlock force
+// one of them.
+constexpr int kLuFormAuto = 0, kLuFormOneWave = 1, kLuFormBlock = 2;
+constexpr int kOneWaveMax = 192;
 template <typename T>
 hipError_t launch_getrf(const LuProb* probs, int count, int nmax, int kind, int panel, int waves,
-                        hipStream_t s);
+                        hipStream_t s, int form = kLuFormAuto);
 int getrf_default_panel(bool t64);
 
 template <typename PT, typename T>

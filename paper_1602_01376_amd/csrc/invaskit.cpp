@@ -147,6 +147,7 @@ struct LuL {
   int count = 0, nmax = 0, t64 = 1, kind = 0;
   int panel = 0;    // LU panel width, 0 = the kernel's default
   int waves = 0;    // waves per matrix, 0 = the kernel's default (4)
+  int form = 0;     // kLuForm*: one-wave or block kernel for small orders
   double work = 0;  // sum of n^3 (tuning key)
 };
 struct DinvL {
@@ -199,7 +200,8 @@ struct FactorPlan {
   std::vector<ZformL> zform;  // index j: reduced systems of level j
   std::vector<LuL> zlu;
   std::vector<DinvL> zdinv;
-  std::vector<TrsmL> zsolve;  // index j >= 1: sweep step at level j
+  std::vector<TrsmL> zsolve;    // index j >= 1: sweep step at level j
+  std::vector<TrsmL> zsolve32;  // the same with 32 right-hand sides per workgroup
   std::vector<GemmL> pgemm;
   Buf tables;                 // device copy of the descriptor tables
 };
@@ -247,6 +249,7 @@ struct invaskit_handle_s {
   int maxit = 30;
   int tune = INVASKIT_TUNE_AUTO;
   int fix_lu_panel = 0, fix_lu_waves = 0, fix_trsm_cols = 0;  // 0: chosen by tuning
+  int fix_zlu_form = 0, fix_zsolve_cols = 0;                   // likewise
   int refine = INVASKIT_REFINE_AUTO;
   int gm_restart = 20, gm_maxit = 300;
   hipStream_t stream = nullptr;
@@ -409,6 +412,11 @@ int validate(H* h, const invaskit_problem* pb, double lambda, const invaskit_opt
       return fail_h(h, INVASKIT_E_ARG, "gmres_restart must be in [2, 64]");
     if (opt->max_gmres_iters < 1) return fail_h(h, INVASKIT_E_ARG, "max_gmres_iters < 1");
     if (opt->lambda_group < 0) return fail_h(h, INVASKIT_E_ARG, "lambda_group < 0");
+    if (opt->zlu_form != 0 && opt->zlu_form != INVASKIT_ZLU_ONE_WAVE &&
+        opt->zlu_form != INVASKIT_ZLU_BLOCK)
+      return fail_h(h, INVASKIT_E_ARG, "zlu_form must be 0, INVASKIT_ZLU_ONE_WAVE or _BLOCK");
+    if (!tile_ok(opt->zsolve_cols))
+      return fail_h(h, INVASKIT_E_ARG, "zsolve_cols must be 0, 16 or 32");
   }
   const int L = pb->depth;
   const int nleaves = 1 << L;
@@ -973,6 +981,7 @@ void build_factor_tables(const std::vector<H*>& hs, const KernelCache* kc, Arena
   fp.zlu.assign(std::max(L, 1), LuL());
   fp.zdinv.assign(std::max(L, 1), DinvL());
   fp.zsolve.assign(std::max(L, 1), TrsmL());
+  fp.zsolve32.assign(std::max(L, 1), TrsmL());
   fp.pgemm.assign(std::max(L, 1), GemmL());
   for (int jl = L - 1; jl >= 0; --jl) {
     std::vector<ZformProb> zf;
@@ -1044,6 +1053,7 @@ void build_factor_tables(const std::vector<H*>& hs, const KernelCache* kc, Arena
     dl.t64 = h->zis64[jl];
     if (jl >= 1) {
       fp.zsolve[jl] = zs.emit(ar, h->zis64[jl], T64, 1);
+      fp.zsolve32[jl] = zs.emit(ar, h->zis64[jl], T64, 1, 32);
       fp.pgemm[jl] = pg.emit(ar);
     }
   }
@@ -1089,9 +1099,9 @@ hipError_t run_lu(const Buf& tb, const LuL& l, hipStream_t s) {
   if (l.count == 0) return hipSuccess;
   if (l.t64)
     return launch_getrf<double>(at<LuProb>(tb, l.probs), l.count, l.nmax, l.kind, l.panel,
-                                l.waves, s);
+                                l.waves, s, l.form);
   return launch_getrf<float>(at<LuProb>(tb, l.probs), l.count, l.nmax, l.kind, l.panel, l.waves,
-                             s);
+                             s, l.form);
 }
 
 hipError_t run_dinv(const Buf& tb, const DinvL& l, hipStream_t s) {
@@ -1151,6 +1161,109 @@ std::string lu_key(const LuL& l) {
 std::string trsm_key(const TrsmL& l) {
   return std::string("getrs.") + (l.tz64 ? "f64" : "f32") + ".k" + std::to_string(l.kind) +
          ".n" + std::to_string(l.nmax) + ".w" + std::to_string(tune_bin(l.work));
+}
+std::string zlu_key(const LuL& l) {
+  return std::string("zgetrf.") + (l.t64 ? "f64" : "f32") + ".n" + std::to_string(l.nmax) +
+         ".c" + std::to_string(tune_bin(l.count));
+}
+
+// Best of two timed runs of `launch` on stream s, each after `prepare`
+// (events e0 and e1 are the caller's).
+template <typename Prep, typename Launch>
+hipError_t best_of_two(hipStream_t s, hipEvent_t e0, hipEvent_t e1, Prep&& prepare,
+                       Launch&& launch, float& best) {
+  best = 0.f;
+  hipError_t e = hipSuccess;
+  for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
+    e = prepare();
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
+    if (e == hipSuccess) e = launch();
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e == hipSuccess && (best == 0.f || ms < best)) best = ms;
+  }
+  return e;
+}
+
+// The level wavefront's choices at level j: the LU form of the reduced
+// systems and the sweep solves' right-hand sides per workgroup, fixed by the
+// options, found in the table, or timed here, on stream s, before the
+// level's own launches.  Rebuilding Z from the children's projections makes
+// every LU trial start from the same matrices; the solves read the
+// projections and write Y only, so their trials change nothing else.
+int tune_level(H* h, const Buf& tb, const FactorPlan& fp, int j, hipStream_t s, int* form,
+               int* cols) {
+  const LuL& zl = fp.zlu[j];
+  const bool can_one = zl.count > 0 && zl.nmax <= kOneWaveMax;
+  const bool has_solve = j >= 1 && fp.zsolve[j].ntiles > 0;
+  const bool can32 = has_solve && fp.zsolve32[j].ntiles >= 0;
+  int f = can_one ? h->fix_zlu_form : kLuFormBlock;
+  int c = has_solve ? h->fix_zsolve_cols : kTrsmColsDefault;
+  if (c == 32 && !can32)
+    return fail_h(h, INVASKIT_E_ARG,
+                  "zsolve_cols = 32 needs more than 160 KiB of LDS at this reduced-system size");
+  if (!c && !can32) c = kTrsmColsDefault;
+  if (h->tune == INVASKIT_TUNE_OFF) {
+    if (!f) f = zl.t64 ? kLuFormBlock : kLuFormOneWave;
+    if (!c) c = kTrsmColsDefault;
+  }
+  const std::string kz = zlu_key(zl), ks = has_solve ? trsm_key(fp.zsolve[j]) : std::string();
+  {
+    std::lock_guard<std::mutex> g(tune_table().mu);
+    auto& t = tune_table().choice;
+    if (!f && t.count(kz)) f = t[kz];
+    if (!c && t.count(ks)) c = t[ks];
+  }
+  if (!f || !c) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(h, hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+      hipEventDestroy(e0);
+      return fail_h(h, INVASKIT_E_HIP, "hipEventCreate failed");
+    }
+    hipError_t e = hipSuccess;
+    auto lu_form = [&](int form_) {
+      LuL l = zl;
+      l.form = form_;
+      return run_lu(tb, l, s);
+    };
+    auto zform = [&]() { return run_zform(tb, fp.zform[j], s); };
+    const bool tuned_f = !f, tuned_c = !c;
+    if (!f) {
+      float t1 = 0.f, t2 = 0.f;
+      e = best_of_two(s, e0, e1, zform, [&]() { return lu_form(kLuFormOneWave); }, t1);
+      if (e == hipSuccess)
+        e = best_of_two(s, e0, e1, zform, [&]() { return lu_form(kLuFormBlock); }, t2);
+      f = t1 <= t2 ? kLuFormOneWave : kLuFormBlock;
+    }
+    if (!c && e == hipSuccess) {
+      // the solves read the level's factors and their diagonal-block inverses
+      e = zform();
+      if (e == hipSuccess) e = lu_form(f);
+      if (e == hipSuccess) e = run_dinv(tb, fp.zdinv[j], s);
+      float t16 = 0.f, t32 = 0.f;
+      auto none = []() { return hipSuccess; };
+      if (e == hipSuccess)
+        e = best_of_two(s, e0, e1, none, [&]() { return run_trsm(tb, fp.zsolve[j], s); }, t16);
+      if (e == hipSuccess)
+        e = best_of_two(s, e0, e1, none, [&]() { return run_trsm(tb, fp.zsolve32[j], s); }, t32);
+      c = t32 < t16 ? 32 : 16;
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (e != hipSuccess)
+      return fail_h(h, INVASKIT_E_HIP, std::string("level tuning: ") + hipGetErrorString(e));
+    std::lock_guard<std::mutex> g(tune_table().mu);
+    auto& t = tune_table().choice;
+    if (tuned_f) t[kz] = f;
+    if (tuned_c) t[ks] = c;
+  }
+  *form = f;
+  *cols = c;
+  return INVASKIT_OK;
 }
 
 // Settles the leaf LU's panel width and waves per matrix and the leaf
@@ -1464,14 +1577,25 @@ int run_factor(const std::vector<H*>& hs, const FactorPlan& fp, KernelCache* kc)
     STEP(close(s));
     // level wavefront
     for (int j = L - 1; j >= 0; --j) {
+      int zf = kLuFormBlock, zc = kTrsmColsDefault;
+      if (int rc = tune_level(h, tb, fp, j, s, &zf, &zc)) {
+        cleanup();
+        return rc;
+      }
+      for (H* hg : hs) {
+        if (zf == kLuFormOneWave) hg->tiles.zlu_one_wave_levels |= 1 << j;
+        if (j >= 1 && zc == 32) hg->tiles.zsolve32_levels |= 1 << j;
+      }
+      LuL zl = fp.zlu[j];
+      zl.form = zf;
       STEP(open(8, s));
       STEP(run_zform(tb, fp.zform[j], s));
-      STEP(run_lu(tb, fp.zlu[j], s));
+      STEP(run_lu(tb, zl, s));
       STEP(run_dinv(tb, fp.zdinv[j], s));
       STEP(close(s));
       if (j >= 1) {
         STEP(open(6, s));
-        STEP(run_trsm(tb, fp.zsolve[j], s));
+        STEP(run_trsm(tb, zc == 32 ? fp.zsolve32[j] : fp.zsolve[j], s));
         STEP(run_gemm(tb, fp.pgemm[j], f64, s));
         STEP(close(s));
       }
@@ -2156,6 +2280,8 @@ int invaskit_default_options(invaskit_options* opt) {
   opt->gmres_restart = 20;
   opt->max_gmres_iters = 300;
   opt->lambda_group = 0;
+  opt->zlu_form = 0;
+  opt->zsolve_cols = 0;
   return INVASKIT_OK;
 }
 
@@ -2178,6 +2304,8 @@ std::unique_ptr<H> new_handle(const invaskit_problem* pb, double lambda,
   h->fix_lu_panel = o.leaf_lu_panel;
   h->fix_lu_waves = o.leaf_lu_waves;
   h->fix_trsm_cols = o.leaf_trsm_cols;
+  h->fix_zlu_form = o.zlu_form;
+  h->fix_zsolve_cols = o.zsolve_cols;
   h->refine = o.refine;
   h->gm_restart = o.gmres_restart;
   h->gm_maxit = o.max_gmres_iters;
@@ -2526,8 +2654,10 @@ int invaskit_tuning_import(const char* text) {
     const bool parsed = (ls >> key >> v) && !(ls >> rest);
     const bool waves = key.rfind("getrfw.", 0) == 0;
     const bool tile = key.rfind("getrf.", 0) == 0 || key.rfind("getrs.", 0) == 0;
-    if (!parsed || !(waves || tile) || (waves && v != 4 && v != 8) ||
-        (tile && v != 16 && v != 32))
+    const bool zform = key.rfind("zgetrf.", 0) == 0;
+    if (!parsed || !(waves || tile || zform) || (waves && v != 4 && v != 8) ||
+        (tile && v != 16 && v != 32) ||
+        (zform && v != kLuFormOneWave && v != kLuFormBlock))
       return fail_h(nullptr, INVASKIT_E_ARG, "malformed tuning line: " + line);
     add.emplace_back(key, v);
   }

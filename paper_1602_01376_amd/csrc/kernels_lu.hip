@@ -429,7 +429,8 @@ __global__ __launch_bounds__(64 * NW) void k_getrf(const LuProb* __restrict__ pr
   if (tid == 0) *pr.info = s_info;
 }
 
-// One wave per matrix, for small FP32 orders (n <= 64 RPS): the same blocked
+// One wave per matrix, for small orders (n <= 64 RPS; panels of 32 columns
+// in FP32, 16 in FP64): the same blocked
 // algorithm and storage as k_getrf, but with no workgroup barriers -- the
 // pivot search is a wave reduction, the pivot row is broadcast by readlane
 // from the owning lane, and the panel inverse, U12 and the trailing update
@@ -657,17 +658,22 @@ hipError_t run_block(const LuProb* probs, int count, int nmax, hipStream_t s) {
 // panel: 0 = the default width (32 in FP32, 16 in FP64), else 16 or 32;
 // waves: 0 or 4 = four waves per matrix, 8 = eight (leaf blocks only; the
 // reduced systems always take the defaults; FP64 has no panel 32 at eight
-// waves)
+// waves).  Orders up to kOneWaveMax may take the one-wave kernel (panel 32
+// in FP32, 16 in FP64): by default in FP32, whose short per-column chain is
+// what bounds the small reduced systems near the root; FP64's longer chain
+// (64-bit keys and reciprocal) is spread over four waves unless `form` asks
+// for the one-wave kernel.
 template <typename T, int KIND>
-hipError_t pick(const LuProb* probs, int count, int nmax, int panel, int waves, hipStream_t s) {
+hipError_t pick(const LuProb* probs, int count, int nmax, int panel, int waves, int form,
+                hipStream_t s) {
   constexpr int W = sizeof(T) == 8 ? 16 : 32;
   constexpr int WA = W == 16 ? 32 : 16;  // the other panel width
-  // one wave per matrix for small FP32 orders; FP64's longer per-column chain
-  // (64-bit keys and reciprocal) is better spread over several waves
-  if constexpr (sizeof(T) == 4) {
+  const bool one = nmax <= kOneWaveMax &&
+                   (form == kLuFormOneWave || (form == kLuFormAuto && sizeof(T) == 4));
+  if (one) {
     if (nmax <= 64) return run_getrf_w<T, W, 1, KIND>(probs, count, nmax, s);
     if (nmax <= 128) return run_getrf_w<T, W, 2, KIND>(probs, count, nmax, s);
-    if (nmax <= 192) return run_getrf_w<T, W, 3, KIND>(probs, count, nmax, s);
+    return run_getrf_w<T, W, 3, KIND>(probs, count, nmax, s);
   }
   const bool alt = panel != 0 && panel != W;
   if (alt && panel != WA) return hipErrorInvalidValue;
@@ -688,13 +694,14 @@ int getrf_default_panel(bool t64) { return t64 ? 16 : 32; }
 
 template <typename T>
 hipError_t launch_getrf(const LuProb* probs, int count, int nmax, int kind, int panel, int waves,
-                        hipStream_t s) {
+                        hipStream_t s, int form) {
   if (count <= 0) return hipSuccess;
-  return kind == 0 ? pick<T, 0>(probs, count, nmax, panel, waves, s)
-                   : pick<T, 1>(probs, count, nmax, panel, waves, s);
+  if (form < kLuFormAuto || form > kLuFormBlock) return hipErrorInvalidValue;
+  return kind == 0 ? pick<T, 0>(probs, count, nmax, panel, waves, form, s)
+                   : pick<T, 1>(probs, count, nmax, panel, waves, form, s);
 }
 
-template hipError_t launch_getrf<double>(const LuProb*, int, int, int, int, int, hipStream_t);
-template hipError_t launch_getrf<float>(const LuProb*, int, int, int, int, int, hipStream_t);
+template hipError_t launch_getrf<double>(const LuProb*, int, int, int, int, int, hipStream_t, int);
+template hipError_t launch_getrf<float>(const LuProb*, int, int, int, int, int, hipStream_t, int);
 
 }  // namespace invaskit

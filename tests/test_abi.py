@@ -163,7 +163,9 @@ def test_bad_options_rejected(small_problem):
     for field, v, word in (("refine", 4, "refine"), ("refine", -1, "refine"),
                            ("gmres_restart", 1, "gmres_restart"),
                            ("gmres_restart", 65, "gmres_restart"),
-                           ("max_gmres_iters", 0, "max_gmres_iters")):
+                           ("max_gmres_iters", 0, "max_gmres_iters"),
+                           ("zlu_form", 3, "zlu_form"), ("zlu_form", -1, "zlu_form"),
+                           ("zsolve_cols", 24, "zsolve_cols")):
         binding.library().invaskit_default_options(C.byref(opt))
         setattr(opt, field, v)
         st, msg = _factor_status(raw, opt=opt)
@@ -172,22 +174,24 @@ def test_bad_options_rejected(small_problem):
 
 def test_options_struct_layout():
     """The binding's mirrors of invaskit_options and invaskit_solve_info have
-    the header's sizes and field offsets (options: 4 + 4 + 8 + 9 x 4 bytes,
-    padded to 56)."""
+    the header's sizes and field offsets (options: 4 + 4 + 8 + 11 x 4 bytes,
+    padded to 64)."""
     from paper_1602_01376_amd import binding
     O = binding._Options
-    assert C.sizeof(O) == 56
+    assert C.sizeof(O) == 64
     assert O.refine_tol.offset == 8 and O.max_refine_iters.offset == 16
     assert O.tune.offset == 20 and O.leaf_lu_panel.offset == 24
     assert O.leaf_trsm_cols.offset == 28 and O.leaf_lu_waves.offset == 32
     assert O.refine.offset == 36 and O.gmres_restart.offset == 40
-    assert O.max_gmres_iters.offset == 44
+    assert O.max_gmres_iters.offset == 44 and O.lambda_group.offset == 48
+    assert O.zlu_form.offset == 52 and O.zsolve_cols.offset == 56
     S = binding.SolveInfo
     assert C.sizeof(S) == 32 and S.final_rel_residual.offset == 8
     assert S.gmres_iterations.offset == 24 and S.method.offset == 28
     T = binding._TileConfig
-    assert C.sizeof(T) == 52 and T.lu_ms.offset == 16 and T.trsm_ms.offset == 32
+    assert C.sizeof(T) == 60 and T.lu_ms.offset == 16 and T.trsm_ms.offset == 32
     assert T.leaf_trsm_cols_small.offset == 40 and T.trsm_small_ms.offset == 44
+    assert T.zlu_one_wave_levels.offset == 52 and T.zsolve32_levels.offset == 56
 
 
 def test_tuning_table_text_round_trip():
@@ -197,12 +201,14 @@ def test_tuning_table_text_round_trip():
     binding.tuning_clear()
     assert binding.tuning_table() == {}
     entries = {"getrf.f32.n512.c24.w67": 16, "getrfw.f32.n512.c24.w67": 8,
-               "getrs.f64.k0.n256.w60": 32}
+               "getrs.f64.k0.n256.w60": 32, "zgetrf.f32.n142.c20": 1,
+               "zgetrf.f64.n128.c0": 2, "getrs.f32.k1.n142.w50": 16}
     binding.tuning_load(entries)
     assert binding.tuning_table() == entries
     lib = binding.library()
     for bad in (b"getrf.f32.n1 24\n", b"getrs.f32 16 extra\n", b"other.key 16\n",
-                b"getrf.f32.n1\n", b"getrfw.f32.n1 16\n", b"getrf.f32.n1 8\n"):
+                b"getrf.f32.n1\n", b"getrfw.f32.n1 16\n", b"getrf.f32.n1 8\n",
+                b"zgetrf.f32.n1 16\n", b"zgetrf.f32.n1 0\n"):
         assert lib.invaskit_tuning_import(bad) == -1, bad
     assert binding.tuning_table() == entries
     need = C.c_size_t()

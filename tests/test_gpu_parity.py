@@ -383,8 +383,16 @@ def test_autotune_times_candidates_once(bind, problems, tmp_path):
     assert tc["leaf_trsm_cols_small"] == \
         (32 if tc["trsm_small_ms"][1] < tc["trsm_small_ms"][0] else 16)
     table = bind.tuning_table()
-    assert sorted(table.values()) == sorted([tc["leaf_lu_panel"], tc["leaf_lu_waves"],
-                                             tc["leaf_trsm_cols"], tc["leaf_trsm_cols_small"]])
+    leaf = {k: v for k, v in table.items()
+            if k.startswith(("getrf.", "getrfw.")) or ".k0." in k}
+    assert sorted(leaf.values()) == sorted([tc["leaf_lu_panel"], tc["leaf_lu_waves"],
+                                            tc["leaf_trsm_cols"], tc["leaf_trsm_cols_small"]])
+    # the level wavefront: one LU-form entry per level shape class (values 1
+    # or 2) and one sweep-solve entry per level shape class (16 or 32)
+    zl = {k: v for k, v in table.items() if k.startswith("zgetrf.")}
+    zs = {k: v for k, v in table.items() if ".k1." in k}
+    assert zl and set(zl.values()) <= {1, 2} and zs and set(zs.values()) <= {16, 32}
+    assert len(table) == len(leaf) + len(zl) + len(zs)
     x = fac.solve(torch.from_numpy(b)).cpu().numpy()
     _assert_close(x, oracle.solve(F, b), 1e-7)
     fac.refactor(3e-3)
@@ -406,6 +414,9 @@ def test_autotune_times_candidates_once(bind, problems, tmp_path):
     tc3 = fac.tile_config()
     assert (tc3["leaf_lu_panel"], tc3["leaf_lu_waves"], tc3["leaf_trsm_cols"], tc3["tuned"],
             tc3["leaf_trsm_cols_small"]) == (32, 4, 16, 0, 16)
+    # OFF: one wave for the FP32 reduced systems (level 4 here), four for the
+    # FP64 top levels; 16 right-hand sides in the sweep
+    assert tc3["zlu_one_wave_levels"] == 1 << 4 and tc3["zsolve32_levels"] == 0
     fac.close()
     bind.tuning_clear()
 
@@ -658,3 +669,39 @@ def test_factor_and_solve_are_bitwise_reproducible(bind, problems, prec):
     assert c.matvec(b).cpu().numpy().tobytes() == y0.tobytes()
     a.close()
     c.close()
+
+
+def _one_wave_levels(pb):
+    """Levels whose reduced systems (order s_l + s_r) all fit the one-wave LU."""
+    s = np.diff(pb.skel_offsets)
+    mask = 0
+    for j in range(pb.depth):
+        z = [int(s[2 * a + 1] + s[2 * a + 2]) for a in range((1 << j) - 1, (2 << j) - 1)]
+        if max(z) <= 192:
+            mask |= 1 << j
+    return mask
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("zf,zc", [("one_wave", 16), ("block", 32), ("one_wave", 32),
+                                   ("block", 16)])
+@pytest.mark.parametrize("name,kw", [("susy", dict(n=8192, depth=5)),
+                                     ("covtype", dict(n=4096, depth=4))])
+def test_reduced_system_forms_match_oracle(bind, problems, prec, zf, zc, name, kw):
+    """Eq. (11)'s reduced systems factored by either LU form (one wave or
+    four per system, in FP32 and FP64) and solved in the sweep with 16 or 32
+    right-hand sides per workgroup give the oracle's solution.  Orders above
+    192 (covtype, s = 128) always take the four-wave form."""
+    _say("reduced-system forms", name, prec, zf, zc)
+    pb, F = problems(name, kw)
+    b = rhs_for(pb, nrhs=3)
+    x_ref = oracle.solve(F, b)
+    fac = bind.Factorization(pb, pb.lam, precision=prec, zlu_form=zf, zsolve_cols=zc)
+    tc = fac.tile_config()
+    one = _one_wave_levels(pb) if zf == "one_wave" else 0
+    assert tc["zlu_one_wave_levels"] == one, (tc, one)
+    assert tc["zsolve32_levels"] == (sum(1 << j for j in range(1, pb.depth)) if zc == 32 else 0)
+    x, info, st = fac.solve(torch.from_numpy(b), return_info=True)
+    assert st == 0 and info["final_rel_residual"] <= 1e-10, info
+    _assert_close(x.cpu().numpy(), x_ref, 1e-10 if prec == "fp64" else MIXED_XTOL.get(name, 1e-7))
+    fac.close()
