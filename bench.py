@@ -187,11 +187,13 @@ def tree_sizes(pb):
     return L, nn, s, size, w
 
 
-def algorithmic_work(pb, esize):
+def algorithmic_work(pb, esize, sym_leaves=False):
     """Flops and bytes per factorization phase for the schedule the library
     runs (exact sizes of this tree).  esize = bytes per factor element.  The
     kernel blocks count 2 d flops per entry (their FP64 Gram products on the
-    matrix cores) when d > 64; at d <= 64 they count bytes only."""
+    matrix cores) when d > 64; at d <= 64 they count bytes only.
+    sym_leaves: the large leaves were factored without row exchanges in the
+    symmetric form (LDL^T work, m^3 / 3 flops) instead of LU (2 m^3 / 3)."""
     gram = 2.0 * pb.d if pb.d > 64 else 0.0
     L, nn, s, size, w = tree_sizes(pb)
     first_leaf = (1 << L) - 1
@@ -213,10 +215,11 @@ def algorithmic_work(pb, esize):
         m = size[lf]
         W["leaf_blocks"]["bytes"] += m * m * esize
         W["leaf_blocks"]["flops"] += gram * m * m
-        W["leaf_lu"]["flops"] += 2.0 / 3.0 * m ** 3
+        lu_flops = (1.0 if sym_leaves and m > small else 2.0) / 3.0 * m ** 3
+        W["leaf_lu"]["flops"] += lu_flops
         W["leaf_lu"]["bytes"] += 2.0 * m * m * esize
         if m > small:
-            W["leaf_lu_large"]["flops"] += 2.0 / 3.0 * m ** 3
+            W["leaf_lu_large"]["flops"] += lu_flops
             W["leaf_lu_large"]["bytes"] += 2.0 * m * m * esize
         nb = -(-m // 64)
         W["leaf_diag_inverses"]["flops"] += nb * 2.0 * 64 ** 3 / 3.0
@@ -606,7 +609,7 @@ def main():
     esize = 4 if "mixed" in results else 8
     dtype = "f32" if "mixed" in results else "f64"
     ctype = "float" if dtype == "f32" else "double"
-    work = algorithmic_work(pb, esize)
+    work = algorithmic_work(pb, esize, sym_leaves=head["tiles"].get("leaf_pivoting") == 0)
     # dominant kernel: the single-launch phase with the largest measured time
     ph = head["phase_ms"]
     cand = {k: ph.get(k, 0.0) for k in work if work[k]["launches"] == 1}

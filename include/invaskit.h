@@ -150,9 +150,34 @@ typedef struct invaskit_options {
                                systems of order up to 192 on every level          */
   int32_t zsolve_cols;      /* 0 (default): per `tune`; 16 or 32: right-hand sides
                                per workgroup in the sweep's reduced-system solves */
+  int32_t leaf_pivoting;    /* INVASKIT_LEAF_PIVOT_AUTO (default) or _PARTIAL,
+                               see below                                          */
 } invaskit_options;
 #define INVASKIT_ZLU_ONE_WAVE 1
 #define INVASKIT_ZLU_BLOCK    2
+
+/*
+ * Leaf factorization.  The leaf blocks lambda*I + K_aa of Algorithm 1 are
+ * symmetric, and positive definite when lambda > 0 (the Gaussian kernel
+ * matrix is positive semidefinite): a symmetry the paper leaves unexploited
+ * (Section I, limitations).  For such matrices LU without row exchanges is
+ * backward stable (its pivots are the positive diagonal of the LDL^T
+ * factorization), and dropping the pivot search takes the per-column
+ * reduction and barrier out of the leaf LU's panel.
+ *  INVASKIT_LEAF_PIVOT_AUTO     when lambda > 0 (every lambda of a batched
+ *                               sweep group), the leaf blocks of orders above
+ *                               the one-wave limit are factored without row
+ *                               exchanges; if a pivot comes out not positive
+ *                               and finite (a block not numerically positive
+ *                               definite, e.g. a tiny lambda in FP32), the
+ *                               whole factorization runs again with partial
+ *                               pivoting.  With lambda <= 0, partial pivoting.
+ *  INVASKIT_LEAF_PIVOT_PARTIAL  always partial pivoting (LAPACK getrf).
+ * Either way the factors have the layout the solves read (a permutation,
+ * the identity without row exchanges, and packed L\U).
+ */
+#define INVASKIT_LEAF_PIVOT_AUTO    0
+#define INVASKIT_LEAF_PIVOT_PARTIAL 1
 
 /*
  * Tile autotuning.  The leaves are factored and solved in two size classes
@@ -384,6 +409,9 @@ typedef struct invaskit_tile_config {
                               factored by the one-wave kernel                    */
   int32_t zsolve32_levels; /* bit j set: the sweep at level j took 32
                               right-hand sides per workgroup                     */
+  int32_t leaf_pivoting;   /* 1 if the leaf LU used partial pivoting, 0 if the
+                              larger leaf blocks were factored without row
+                              exchanges                                          */
 } invaskit_tile_config;
 int invaskit_tile_config_get(invaskit_handle handle, invaskit_tile_config* out);
 

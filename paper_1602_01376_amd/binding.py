@@ -44,12 +44,14 @@ class _Options(C.Structure):
                 ("leaf_trsm_cols", C.c_int32), ("leaf_lu_waves", C.c_int32),
                 ("refine", C.c_int32), ("gmres_restart", C.c_int32),
                 ("max_gmres_iters", C.c_int32), ("lambda_group", C.c_int32),
-                ("zlu_form", C.c_int32), ("zsolve_cols", C.c_int32)]
+                ("zlu_form", C.c_int32), ("zsolve_cols", C.c_int32),
+                ("leaf_pivoting", C.c_int32)]
 
 
 TUNE_AUTO, TUNE_OFF = 0, 1
 REFINE = {"auto": 0, "ir": 1, "gmres": 2, "none": 3}
 ZLU_FORM = {"auto": 0, "one_wave": 1, "block": 2}
+LEAF_PIVOTING = {"auto": 0, "partial": 1}
 
 
 class _TileConfig(C.Structure):
@@ -57,7 +59,8 @@ class _TileConfig(C.Structure):
                 ("leaf_trsm_cols", C.c_int32), ("tuned", C.c_int32),
                 ("lu_ms", C.c_float * 4), ("trsm_ms", C.c_float * 2),
                 ("leaf_trsm_cols_small", C.c_int32), ("trsm_small_ms", C.c_float * 2),
-                ("zlu_one_wave_levels", C.c_int32), ("zsolve32_levels", C.c_int32)]
+                ("zlu_one_wave_levels", C.c_int32), ("zsolve32_levels", C.c_int32),
+                ("leaf_pivoting", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -182,11 +185,11 @@ class Factorization:
                  max_refine_iters: int = 30, points=None, p_values=None, tune: str = "auto",
                  leaf_lu_panel: int = 0, leaf_trsm_cols: int = 0, leaf_lu_waves: int = 0,
                  refine: str = "auto", gmres_restart: int = 20, max_gmres_iters: int = 300,
-                 zlu_form: str = "auto", zsolve_cols: int = 0):
+                 zlu_form: str = "auto", zsolve_cols: int = 0, leaf_pivoting: str = "auto"):
         pb, opt = self._prepare(problem, lam, precision, fp64_top_levels, refine_tol,
                                 max_refine_iters, points, p_values, tune, leaf_lu_panel,
                                 leaf_trsm_cols, leaf_lu_waves, refine, gmres_restart,
-                                max_gmres_iters, zlu_form, zsolve_cols)
+                                max_gmres_iters, zlu_form, zsolve_cols, leaf_pivoting)
         self._handle = C.c_void_p()
         need = C.c_size_t()
         _check(_lib.invaskit_factor_workspace_bytes(C.byref(pb), C.byref(opt), 0,
@@ -205,7 +208,7 @@ class Factorization:
     def _prepare(self, problem, lam, precision, fp64_top_levels, refine_tol, max_refine_iters,
                  points, p_values, tune="auto", leaf_lu_panel=0, leaf_trsm_cols=0,
                  leaf_lu_waves=0, refine="auto", gmres_restart=20, max_gmres_iters=300,
-                 zlu_form="auto", zsolve_cols=0):
+                 zlu_form="auto", zsolve_cols=0, leaf_pivoting="auto"):
         """Marshal the problem and options (the arrays stay alive with self)."""
         self.n = problem.n
         self.lam = float(lam)
@@ -248,6 +251,9 @@ class Factorization:
             raise ValueError(f"zlu_form must be one of {sorted(ZLU_FORM)}")
         opt.zlu_form = ZLU_FORM[zlu_form]
         opt.zsolve_cols = int(zsolve_cols)
+        if leaf_pivoting not in LEAF_PIVOTING:
+            raise ValueError(f"leaf_pivoting must be one of {sorted(LEAF_PIVOTING)}")
+        opt.leaf_pivoting = LEAF_PIVOTING[leaf_pivoting]
         return pb, opt
 
     @property
@@ -327,7 +333,7 @@ class Factorization:
                 "trsm_ms": list(t.trsm_ms), "leaf_trsm_cols_small": t.leaf_trsm_cols_small,
                 "trsm_small_ms": list(t.trsm_small_ms),
                 "zlu_one_wave_levels": t.zlu_one_wave_levels,
-                "zsolve32_levels": t.zsolve32_levels}
+                "zsolve32_levels": t.zsolve32_levels, "leaf_pivoting": t.leaf_pivoting}
 
     def device_bytes(self):
         """Bytes of the factor workspace this handle's buffers span."""
@@ -499,7 +505,7 @@ def factor_sweep(problem, lams, precision: str = "fp64", fp64_top_levels: int = 
                  p_values=None, tune: str = "auto", leaf_lu_panel: int = 0,
                  leaf_trsm_cols: int = 0, leaf_lu_waves: int = 0, refine: str = "auto",
                  gmres_restart: int = 20, max_gmres_iters: int = 300, lambda_group: int = 0,
-                 zlu_form: str = "auto", zsolve_cols: int = 0):
+                 zlu_form: str = "auto", zsolve_cols: int = 0, leaf_pivoting: str = "auto"):
     """One Factorization per lambda in `lams` (invaskit_factor_sweep): the
     kernel blocks are evaluated once into the sweep's workspace and shared
     by the handles; the lambdas are factored in batches of `lambda_group`
@@ -509,7 +515,7 @@ def factor_sweep(problem, lams, precision: str = "fp64", fp64_top_levels: int = 
     pb, opt = objs[0]._prepare(problem, lams[0], precision, fp64_top_levels, refine_tol,
                                max_refine_iters, points, p_values, tune, leaf_lu_panel,
                                leaf_trsm_cols, leaf_lu_waves, refine, gmres_restart,
-                               max_gmres_iters, zlu_form, zsolve_cols)
+                               max_gmres_iters, zlu_form, zsolve_cols, leaf_pivoting)
     opt.lambda_group = int(lambda_group)
     need = C.c_size_t()
     _check(_lib.invaskit_factor_workspace_bytes(C.byref(pb), C.byref(opt), len(lams),

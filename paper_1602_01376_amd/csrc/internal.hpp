@@ -183,12 +183,14 @@ hipError_t launch_diag_inv(const DiagInvProb* probs, int count, hipStream_t s);
 // matrix of the block kernel, 0 for the default (4), or 4 / 8 for kind 0.
 // form (orders up to kOneWaveMax): kLuFormAuto takes the one-wave kernel in
 // FP32 and the block kernel in FP64; kLuFormOneWave and kLuFormBlock force
-// one of them.
+// one of them.  nopiv (kind 0, block kernel): no row exchanges, for
+// symmetric positive definite blocks; info then flags the first pivot that
+// is not positive and finite.
 constexpr int kLuFormAuto = 0, kLuFormOneWave = 1, kLuFormBlock = 2;
 constexpr int kOneWaveMax = 192;
 template <typename T>
 hipError_t launch_getrf(const LuProb* probs, int count, int nmax, int kind, int panel, int waves,
-                        hipStream_t s, int form = kLuFormAuto);
+                        hipStream_t s, int form = kLuFormAuto, bool nopiv = false);
 int getrf_default_panel(bool t64);
 
 template <typename PT, typename T>

@@ -148,6 +148,7 @@ struct LuL {
   int panel = 0;    // LU panel width, 0 = the kernel's default
   int waves = 0;    // waves per matrix, 0 = the kernel's default (4)
   int form = 0;     // kLuForm*: one-wave or block kernel for small orders
+  bool nopiv = false;  // leaf blocks: the block kernel without row exchanges
   double work = 0;  // sum of n^3 (tuning key)
 };
 struct DinvL {
@@ -250,6 +251,8 @@ struct invaskit_handle_s {
   int tune = INVASKIT_TUNE_AUTO;
   int fix_lu_panel = 0, fix_lu_waves = 0, fix_trsm_cols = 0;  // 0: chosen by tuning
   int fix_zlu_form = 0, fix_zsolve_cols = 0;                   // likewise
+  int leaf_pivoting = INVASKIT_LEAF_PIVOT_AUTO;
+  bool leaf_nopiv = false;  // the next factor runs the leaf LU without row exchanges
   int refine = INVASKIT_REFINE_AUTO;
   int gm_restart = 20, gm_maxit = 300;
   hipStream_t stream = nullptr;
@@ -417,6 +420,9 @@ int validate(H* h, const invaskit_problem* pb, double lambda, const invaskit_opt
       return fail_h(h, INVASKIT_E_ARG, "zlu_form must be 0, INVASKIT_ZLU_ONE_WAVE or _BLOCK");
     if (!tile_ok(opt->zsolve_cols))
       return fail_h(h, INVASKIT_E_ARG, "zsolve_cols must be 0, 16 or 32");
+    if (opt->leaf_pivoting != INVASKIT_LEAF_PIVOT_AUTO &&
+        opt->leaf_pivoting != INVASKIT_LEAF_PIVOT_PARTIAL)
+      return fail_h(h, INVASKIT_E_ARG, "leaf_pivoting must be INVASKIT_LEAF_PIVOT_AUTO or _PARTIAL");
   }
   const int L = pb->depth;
   const int nleaves = 1 << L;
@@ -1099,9 +1105,9 @@ hipError_t run_lu(const Buf& tb, const LuL& l, hipStream_t s) {
   if (l.count == 0) return hipSuccess;
   if (l.t64)
     return launch_getrf<double>(at<LuProb>(tb, l.probs), l.count, l.nmax, l.kind, l.panel,
-                                l.waves, s, l.form);
+                                l.waves, s, l.form, l.nopiv);
   return launch_getrf<float>(at<LuProb>(tb, l.probs), l.count, l.nmax, l.kind, l.panel, l.waves,
-                             s, l.form);
+                             s, l.form, l.nopiv);
 }
 
 hipError_t run_dinv(const Buf& tb, const DinvL& l, hipStream_t s) {
@@ -1155,8 +1161,9 @@ TuneTable& tune_table() {
 int tune_bin(double x) { return x > 0 ? (int)std::lround(2.0 * std::log2(x)) : -1; }
 
 std::string lu_key(const LuL& l) {
-  return std::string("getrf.") + (l.t64 ? "f64" : "f32") + ".n" + std::to_string(l.nmax) + ".c" +
-         std::to_string(tune_bin(l.count)) + ".w" + std::to_string(tune_bin(l.work));
+  return std::string("getrf.") + (l.t64 ? "f64" : "f32") + (l.nopiv ? ".np" : "") + ".n" +
+         std::to_string(l.nmax) + ".c" + std::to_string(tune_bin(l.count)) + ".w" +
+         std::to_string(tune_bin(l.work));
 }
 std::string trsm_key(const TrsmL& l) {
   return std::string("getrs.") + (l.tz64 ? "f64" : "f32") + ".k" + std::to_string(l.kind) +
@@ -1282,7 +1289,8 @@ int tune_factor(H* h, const FactorPlan& fp) {
   // the LU tiles are timed on the class that runs the block kernel: the
   // large leaves, or the small ones when there are no large ones
   const int luc = fp.leaf_lu[0].count > 0 ? 0 : 1;
-  const LuL& LU = fp.leaf_lu[luc];
+  LuL LU = fp.leaf_lu[luc];
+  LU.nopiv = h->leaf_nopiv;
   const bool lu_choice = LU.count > 0 && (LU.t64 || LU.nmax > kSmallLeaf32);
   const std::string klu = lu_key(LU), klw = "getrfw" + klu.substr(5);
   bool has32[2], has_trsm[2];
@@ -1352,6 +1360,7 @@ int tune_factor(H* h, const FactorPlan& fp) {
       LuL l = base;
       l.panel = panel;
       l.waves = waves;
+      l.nopiv = h->leaf_nopiv;
       return run_lu(tb, l, s);
     };
     if (!lu || !lw) {
@@ -1419,7 +1428,8 @@ int tune_factor(H* h, const FactorPlan& fp) {
 // stream, second stream, events and tile choices serve the launches).  A
 // cached plan first makes sure the sweep's lambda-free kernel blocks are
 // evaluated.  Phase times are recorded in every member.
-int run_factor(const std::vector<H*>& hs, const FactorPlan& fp, KernelCache* kc) {
+int run_factor_once(const std::vector<H*>& hs, const FactorPlan& fp, KernelCache* kc,
+                    bool* repivot) {
   H* h = hs[0];
   hipStream_t s = h->stream;
   const bool f64 = h->prec == INVASKIT_PREC_FP64;
@@ -1535,6 +1545,7 @@ int run_factor(const std::vector<H*>& hs, const FactorPlan& fp, KernelCache* kc)
     LuL l = base;
     l.panel = h->tiles.leaf_lu_panel;
     l.waves = h->tiles.leaf_lu_waves;
+    l.nopiv = h->leaf_nopiv;
     return l;
   };
   // small leaves on the second stream: LU, inverses and solves beside the
@@ -1630,11 +1641,18 @@ int run_factor(const std::vector<H*>& hs, const FactorPlan& fp, KernelCache* kc)
       HIP_TRY(h, hipMemcpy(zi.data(), hg->zinfo.p, sizeof(int32_t) * zi.size(),
                            hipMemcpyDeviceToHost));
     int rc = INVASKIT_OK;
-    for (int j = 0; j < hg->nleaves && !rc; ++j)
-      if (li[j])
-        rc = fail_h(hg, INVASKIT_E_SINGULAR,
-                    "zero pivot: leaf block of node " + std::to_string(hg->leaf_node(j)) +
-                        " column " + std::to_string(li[j] - 1));
+    for (int j = 0; j < hg->nleaves && !rc; ++j) {
+      if (!li[j]) continue;
+      if (h->leaf_nopiv) {
+        // a pivot that is not positive: the block is not numerically
+        // positive definite; the caller factors again with pivoting
+        *repivot = true;
+        break;
+      }
+      rc = fail_h(hg, INVASKIT_E_SINGULAR,
+                  "zero pivot: leaf block of node " + std::to_string(hg->leaf_node(j)) +
+                      " column " + std::to_string(li[j] - 1));
+    }
     for (size_t a = 0; a < zi.size() && !rc; ++a)
       if (zi[a])
         rc = fail_h(hg, INVASKIT_E_SINGULAR,
@@ -1643,6 +1661,26 @@ int run_factor(const std::vector<H*>& hs, const FactorPlan& fp, KernelCache* kc)
     if (rc && status == INVASKIT_OK) status = rc;
   }
   return status;
+}
+
+// One factorization of the handles `hs` (one batched group): the leaf
+// blocks without row exchanges when that is safe to try (leaf_pivoting
+// AUTO and lambda > 0: lambda I + K_aa is then symmetric positive definite
+// for the Gaussian kernel), again with partial pivoting if a pivot came out
+// not positive.
+int run_factor(const std::vector<H*>& hs, const FactorPlan& fp, KernelCache* kc) {
+  bool nopiv = true;
+  for (H* hg : hs) nopiv = nopiv && hg->leaf_pivoting == INVASKIT_LEAF_PIVOT_AUTO && hg->lam > 0.0;
+  for (H* hg : hs) hg->leaf_nopiv = nopiv;
+  bool repivot = false;
+  int rc = run_factor_once(hs, fp, kc, &repivot);
+  if (rc == INVASKIT_OK && repivot) {
+    for (H* hg : hs) hg->leaf_nopiv = false;
+    repivot = false;
+    rc = run_factor_once(hs, fp, kc, &repivot);
+  }
+  for (H* hg : hs) hg->tiles.leaf_pivoting = hg->leaf_nopiv ? 0 : 1;
+  return rc;
 }
 
 // ------------------------------------------------------------ solve plans
@@ -2282,6 +2320,7 @@ int invaskit_default_options(invaskit_options* opt) {
   opt->lambda_group = 0;
   opt->zlu_form = 0;
   opt->zsolve_cols = 0;
+  opt->leaf_pivoting = INVASKIT_LEAF_PIVOT_AUTO;
   return INVASKIT_OK;
 }
 
@@ -2306,6 +2345,7 @@ std::unique_ptr<H> new_handle(const invaskit_problem* pb, double lambda,
   h->fix_trsm_cols = o.leaf_trsm_cols;
   h->fix_zlu_form = o.zlu_form;
   h->fix_zsolve_cols = o.zsolve_cols;
+  h->leaf_pivoting = o.leaf_pivoting;
   h->refine = o.refine;
   h->gm_restart = o.gmres_restart;
   h->gm_maxit = o.max_gmres_iters;

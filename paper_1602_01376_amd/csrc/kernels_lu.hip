@@ -31,6 +31,16 @@
 // is left unscaled and the factorization continues, as LAPACK does).  KIND
 // only separates the kernel names of the two uses (leaf blocks, reduced
 // systems).
+//
+// PIV = false (leaf blocks lambda I + K_aa, symmetric positive definite for
+// lambda > 0): no row exchanges.  The panel's W x W diagonal block is
+// factored by one wave in registers, the rows below solve against it on the
+// matrix cores, and the superpanel updates use the symmetry: only the rows
+// at or below each column chunk are updated, and U12 = D L21^T comes from
+// the final multipliers (D = the superpanel's pivots), which halves the
+// trailing products.  The packed L\U written is the same as with pivoting
+// (permutation = identity).  info flags the first pivot that is not
+// positive and finite; the caller then factors again with pivoting.
 #include <cmath>
 #include <utility>
 
@@ -118,7 +128,7 @@ __device__ __forceinline__ void static_for(F&& f) {
   static_for_impl(f, std::make_integer_sequence<int, N>{});
 }
 
-template <typename T, int W, int RPS, int KIND, int NW>
+template <typename T, int W, int RPS, int KIND, int NW, bool PIV>
 __global__ __launch_bounds__(64 * NW) void k_getrf(const LuProb* __restrict__ probs) {
   using V4 = typename Vec4<T>::type;
   constexpr int W2 = 2 * W;
@@ -140,11 +150,37 @@ __global__ __launch_bounds__(64 * NW) void k_getrf(const LuProb* __restrict__ pr
   __shared__ T L11[W][W + 1];              // a panel's unit-lower block, then L21_ab
   __shared__ T Lsup[W2][W2 + 1];           // inverse of the 2W superpanel's unit-lower block
   __shared__ T Uc[W2][CH];                 // U12 chunk
+  __shared__ T s_dinv[W];                  // without pivoting: 1 / U11's diagonal
+  __shared__ T Ui[W][W + 1];               // without pivoting: inv(U11)
+  __shared__ T s_dsup[W2];                 // without pivoting: the superpanel's pivots
   __shared__ int s_info;
 
   for (int i = tid; i < n; i += NT) Ps[i] = i;
   if (tid == 0) s_info = 0;
   __syncthreads();
+
+  // ---- inv(L11) (unit lower, from L11) into Lsup[off .. off+W)^2: wave w
+  // solves identity columns w*W/NW .. +W/NW, lane = row, the solved row
+  // value broadcast across lanes
+  auto l11_inverse = [&](int jb, int off) {
+    {
+      constexpr int CQ = W / NW;
+      T x[CQ];
+#pragma unroll
+      for (int q = 0; q < CQ; ++q) x[q] = (lane == wave * CQ + q) ? T(1) : T(0);
+      for (int j = 0; j < jb - 1; ++j) {
+        const T l = (lane > j && lane < jb) ? L11[lane][j] : T(0);
+#pragma unroll
+        for (int q = 0; q < CQ; ++q) x[q] -= l * lane_bcast(x[q], j);
+      }
+      if (lane < W) {
+#pragma unroll
+        for (int q = 0; q < CQ; ++q)
+          Lsup[off + lane][off + wave * CQ + q] = (lane < jb) ? x[q] : T(0);
+      }
+    }
+    __syncthreads();
+  };
 
   // ---- factor the W columns at j0 (rows >= j0), write them back in place,
   // give the panel's rows their logical positions, and put inv(L11) in
@@ -263,22 +299,115 @@ __global__ __launch_bounds__(64 * NW) void k_getrf(const LuProb* __restrict__ pr
       }
     }
     __syncthreads();
-    // inv(L11) (unit lower): wave w solves identity columns w*W/NW .. +W/NW,
-    // lane = row, the solved row value broadcast across lanes
+    l11_inverse(jb, off);
+    return jb;
+  };
+
+  // ---- the same panel without pivoting, for symmetric positive definite
+  // blocks (the leaf blocks lambda I + K_aa with lambda > 0), where LU with
+  // no row exchanges is backward stable and the pivots are the positive
+  // diagonal of the LDL^T factorization.  Rows keep their order (the
+  // permutation stays the identity).  Wave 0 factors the W x W diagonal
+  // block in registers (lane i = row i, the pivot row broadcast by
+  // readlane, no barrier); the waves form inv(U11) beside inv(L11); the rows
+  // below become L21 = A21 inv(U11) on the matrix cores, 16 rows per tile.
+  // No step waits on a barrier per column.  A pivot that is not positive
+  // and finite sets info (the caller then factors again with pivoting).
+  auto panel_np = [&](int j0, int off) -> int {
+    const int jb = min(W, n - j0);
+    if (wave == 0) {
+      T P0[W];
+      T* rowp = A + (int64_t)(j0 + (lane < jb ? lane : 0)) * n + j0;
+#pragma unroll
+      for (int c = 0; c < W; ++c) P0[c] = (lane < jb && c < jb) ? rowp[c] : T(0);
+      int info = 0;
+      static_for<W>([&](auto JJ) {
+        constexpr int jj = decltype(JJ)::value;
+        if (jj < jb) {
+          T prow[W];
+#pragma unroll
+          for (int c = 0; c < W; ++c) prow[c] = (c >= jj) ? lane_bcast(P0[c], jj) : T(0);
+          const T pv = prow[jj];
+          const bool ok = pv > T(0) && isfinite(pv);
+          if (!ok && info == 0) info = j0 + jj + 1;
+          if (lane > jj && lane < jb) {
+            const T l = P0[jj] * recip(pv);
+            P0[jj] = l;
+#pragma unroll
+            for (int c = jj + 1; c < W; ++c) P0[c] -= l * prow[c];
+          }
+        }
+      });
+      if (lane < jb) {
+#pragma unroll
+        for (int c = 0; c < W; ++c)
+          if (c < jb) rowp[c] = P0[c];
+      }
+      if (lane < W) {
+#pragma unroll
+        for (int c = 0; c < W; ++c) L11[lane][c] = (lane < jb) ? P0[c] : T(0);
+        // each lane reads back its own diagonal entry (same thread: ordered)
+        s_dinv[lane] = (lane < jb) ? recip(L11[lane][lane]) : T(0);
+        s_dsup[off + lane] = (lane < jb) ? L11[lane][lane] : T(0);
+      }
+      if (lane == 0 && info != 0 && s_info == 0) s_info = info;
+    }
+    __syncthreads();
+    // inv(U11) into Ui: wave w solves identity columns w*W/NW .. +W/NW by
+    // back substitution, lane = row; once row j is divided by u_jj it is
+    // final and is broadcast to the rows above
     {
       constexpr int CQ = W / NW;
       T x[CQ];
 #pragma unroll
       for (int q = 0; q < CQ; ++q) x[q] = (lane == wave * CQ + q) ? T(1) : T(0);
-      for (int j = 0; j < jb - 1; ++j) {
-        const T l = (lane > j && lane < jb) ? L11[lane][j] : T(0);
+      for (int j = jb - 1; j >= 0; --j) {
+        const T dj = s_dinv[j];
+        const T u = (lane < j) ? L11[lane < W ? lane : 0][j] : T(0);
 #pragma unroll
-        for (int q = 0; q < CQ; ++q) x[q] -= l * lane_bcast(x[q], j);
+        for (int q = 0; q < CQ; ++q) {
+          if (lane == j) x[q] *= dj;
+          x[q] -= u * lane_bcast(x[q], j);
+        }
       }
       if (lane < W) {
 #pragma unroll
-        for (int q = 0; q < CQ; ++q)
-          Lsup[off + lane][off + wave * CQ + q] = (lane < jb) ? x[q] : T(0);
+        for (int q = 0; q < CQ; ++q) Ui[lane][wave * CQ + q] = (lane < jb) ? x[q] : T(0);
+      }
+    }
+    l11_inverse(jb, off);  // ends with a barrier: Ui and Lsup are complete
+    // L21 = A21 inv(U11).  Rows below exist only when the panel is W wide,
+    // so a row's W panel entries are always inside the row.
+    // Each wave takes its tiles four at a time, all four loads in flight
+    // before the first product.
+    constexpr int NBT = 4;
+    const int r0 = j0 + jb;
+    const int ntr = (n - r0 + 15) / 16;
+    for (int it0 = wave; it0 < ntr; it0 += NBT * NW) {
+      T a[NBT][W / 4];
+#pragma unroll
+      for (int q = 0; q < NBT; ++q) {
+        const int row = r0 + 16 * (it0 + q * NW) + lr;
+        load_row_sigma_full(A + (int64_t)(row < n ? row : r0 - 1) * n + j0, row < n ? W : 0, lg,
+                            a[q]);
+      }
+#pragma unroll
+      for (int q = 0; q < NBT; ++q) {
+        const int t0 = r0 + 16 * (it0 + q * NW);
+        if (t0 < n) {
+#pragma unroll
+          for (int ct = 0; ct < W / 16; ++ct) {
+            V4 acc = V4{0, 0, 0, 0};
+#pragma unroll
+            for (int kk = 0; kk < W / 4; ++kk)
+              acc = mfma16(a[q][kk], Ui[sigma_k<T>(kk, lg)][16 * ct + lr], acc);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int rr = t0 + acc_row(T(0), lg, v);
+              if (rr < n) A[(int64_t)rr * n + j0 + 16 * ct + lr] = acc[v];
+            }
+          }
+        }
       }
     }
     __syncthreads();
@@ -292,12 +421,26 @@ __global__ __launch_bounds__(64 * NW) void k_getrf(const LuProb* __restrict__ pr
   auto update = [&](auto KWc, int r0, int cs, int ce) {
     constexpr int KW = decltype(KWc)::value;
     constexpr int KG = KW / 4;
+    // Without pivoting the trailing matrix stays symmetric: a superpanel
+    // updates only the rows at or below each column chunk (half the
+    // products), and its U12 rows, whose entries right of the chunk's
+    // diagonal are then stale, are formed from the final L21 instead:
+    // U12 = D L21^T (D = the superpanel's pivots).
+    constexpr bool SYM = !PIV && KW == W2;
     const int c0 = r0 + KW;
-    const int ntr = (n - c0 + 15) / 16;
     for (int cb = cs; cb < ce; cb += CH) {
+      const int rs = SYM ? cb : c0;  // first row of the chunk's update
+      const int ntr = (n - rs + 15) / 16;
+      if constexpr (SYM) {
+        for (int idx = tid; idx < KW * CH; idx += NT) {
+          const int cl = idx / KW, k = idx % KW;  // consecutive threads: one L row
+          const int cc = cb + cl;
+          Uc[k][cl] = (cc < ce) ? s_dsup[k] * A[(int64_t)cc * n + r0 + k] : T(0);
+        }
+      }
       // wave w takes the chunk's 16-column blocks w, w + NW, ...: it loads
       // a block's KW rows of A12 once and applies every row block of Lsup
-      for (int ct = wave; ct < CH / 16; ct += NW) {
+      if constexpr (!SYM) for (int ct = wave; ct < CH / 16; ct += NW) {
         const int cc = cb + 16 * ct + lr;
         T b[KG];
 #pragma unroll
@@ -313,11 +456,12 @@ __global__ __launch_bounds__(64 * NW) void k_getrf(const LuProb* __restrict__ pr
         }
       }
       __syncthreads();
-      // write U12 back (logical rows r0+1 .. r0+KW-1; row r0 is unchanged)
+      // write U12 back (logical rows r0+1 .. r0+KW-1; row r0 is unchanged,
+      // except in the symmetric form, where it is rewritten too)
       for (int idx = tid; idx < KW * CH; idx += NT) {
         const int i = idx / CH, cl = idx % CH;
         const int cc = cb + cl;
-        if (i >= 1 && cc < ce) A[(int64_t)Ps[r0 + i] * n + cc] = Uc[i][cl];
+        if ((SYM || i >= 1) && cc < ce) A[(int64_t)Ps[r0 + i] * n + cc] = Uc[i][cl];
       }
       // two row tiles per iteration (it and it + NW): both tiles' operand
       // loads are in flight before either computes.  A second tile past the
@@ -325,7 +469,7 @@ __global__ __launch_bounds__(64 * NW) void k_getrf(const LuProb* __restrict__ pr
       // the loop has no divergent path.
       constexpr int CTB = (CH / 16) * W / KW;  // 16-column blocks per pass
       auto row_tile = [&](int it, T (&a)[KG], int (&pr4)[4]) {
-        const int t0 = c0 + 16 * it;
+        const int t0 = rs + 16 * it;
         const int row = t0 + lr;
         // r0 + KW <= n here: whole row segments, branch-free
         load_row_sigma_full(A + (int64_t)(row < n ? Ps[row] : 0) * n + r0, row < n ? KW : 0, lg,
@@ -385,7 +529,10 @@ __global__ __launch_bounds__(64 * NW) void k_getrf(const LuProb* __restrict__ pr
   // panel code is inlined once).
   for (int j0 = 0; j0 < n; j0 += W) {
     const bool second = ((j0 / W) & 1) != 0;  // panel b of its superpanel
-    panel(j0, second ? W : 0);
+    if constexpr (PIV)
+      panel(j0, second ? W : 0);
+    else
+      panel_np(j0, second ? W : 0);
     if (j0 + W >= n) break;  // nothing to the right
     if (!second) {
       update(std::integral_constant<int, W>{}, j0, j0 + W, min(n, j0 + W2));
@@ -396,6 +543,11 @@ __global__ __launch_bounds__(64 * NW) void k_getrf(const LuProb* __restrict__ pr
     // X = -inv(L_b) L_ab inv(L_a), with L_ab = panel b's rows in panel a's
     // columns.
     const int J0 = j0 - W;
+    if constexpr (!PIV) {
+      // the symmetric update forms U12 from L21 and needs no inverse
+      update(std::integral_constant<int, W2>{}, J0, J0 + W2, n);
+      continue;
+    }
     for (int idx = tid; idx < W * W; idx += NT) {
       const int i = idx / W, c = idx % W;
       L11[i][c] = A[(int64_t)Ps[J0 + W + i] * n + J0 + c];
@@ -636,21 +788,22 @@ hipError_t run_getrf_w(const LuProb* probs, int count, int nmax, hipStream_t s) 
   return hipGetLastError();
 }
 
-template <typename T, int W, int RPS, int KIND, int NW>
+template <typename T, int W, int RPS, int KIND, int NW, bool PIV>
 hipError_t run_getrf(const LuProb* probs, int count, int nmax, hipStream_t s) {
   const size_t sm = (size_t)nmax * sizeof(int);
-  hipLaunchKernelGGL((k_getrf<T, W, RPS, KIND, NW>), dim3(count), dim3(64 * NW), sm, s, probs);
+  hipLaunchKernelGGL((k_getrf<T, W, RPS, KIND, NW, PIV>), dim3(count), dim3(64 * NW), sm, s,
+                     probs);
   return hipGetLastError();
 }
 
 // RPS rows of the panel per thread: orders up to 64 NW RPS
-template <typename T, int W, int KIND, int NW>
+template <typename T, int W, int KIND, int NW, bool PIV>
 hipError_t run_block(const LuProb* probs, int count, int nmax, hipStream_t s) {
   constexpr int NT = 64 * NW;
-  if (nmax <= NT) return run_getrf<T, W, 1, KIND, NW>(probs, count, nmax, s);
-  if (nmax <= 2 * NT) return run_getrf<T, W, 2, KIND, NW>(probs, count, nmax, s);
+  if (nmax <= NT) return run_getrf<T, W, 1, KIND, NW, PIV>(probs, count, nmax, s);
+  if (nmax <= 2 * NT) return run_getrf<T, W, 2, KIND, NW, PIV>(probs, count, nmax, s);
   if constexpr (NW == 4) {
-    if (nmax <= 4 * NT) return run_getrf<T, W, 4, KIND, NW>(probs, count, nmax, s);
+    if (nmax <= 4 * NT) return run_getrf<T, W, 4, KIND, NW, PIV>(probs, count, nmax, s);
   }
   return hipErrorInvalidValue;
 }
@@ -663,11 +816,30 @@ hipError_t run_block(const LuProb* probs, int count, int nmax, hipStream_t s) {
 // what bounds the small reduced systems near the root; FP64's longer chain
 // (64-bit keys and reciprocal) is spread over four waves unless `form` asks
 // for the one-wave kernel.
-template <typename T, int KIND>
-hipError_t pick(const LuProb* probs, int count, int nmax, int panel, int waves, int form,
-                hipStream_t s) {
+template <typename T, int KIND, bool PIV>
+hipError_t pick_block(const LuProb* probs, int count, int nmax, int panel, int waves,
+                      hipStream_t s) {
   constexpr int W = sizeof(T) == 8 ? 16 : 32;
   constexpr int WA = W == 16 ? 32 : 16;  // the other panel width
+  const bool alt = panel != 0 && panel != W;
+  if (alt && panel != WA) return hipErrorInvalidValue;
+  if (waves != 0 && waves != 4 && waves != 8) return hipErrorInvalidValue;
+  if (!alt && waves != 8) return run_block<T, W, KIND, 4, PIV>(probs, count, nmax, s);
+  if constexpr (KIND == 0) {
+    if (!alt) return run_block<T, W, KIND, 8, PIV>(probs, count, nmax, s);
+    if (waves != 8) return run_block<T, WA, KIND, 4, PIV>(probs, count, nmax, s);
+    // FP64 with panel 32 at eight waves would spill registers: not built
+    if constexpr (sizeof(T) == 4) return run_block<T, WA, KIND, 8, PIV>(probs, count, nmax, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+// nopiv (leaf blocks only): the block kernel without row exchanges; the
+// one-wave kernel always pivots
+template <typename T, int KIND>
+hipError_t pick(const LuProb* probs, int count, int nmax, int panel, int waves, int form,
+                bool nopiv, hipStream_t s) {
+  constexpr int W = sizeof(T) == 8 ? 16 : 32;
   const bool one = nmax <= kOneWaveMax &&
                    (form == kLuFormOneWave || (form == kLuFormAuto && sizeof(T) == 4));
   if (one) {
@@ -675,17 +847,10 @@ hipError_t pick(const LuProb* probs, int count, int nmax, int panel, int waves, 
     if (nmax <= 128) return run_getrf_w<T, W, 2, KIND>(probs, count, nmax, s);
     return run_getrf_w<T, W, 3, KIND>(probs, count, nmax, s);
   }
-  const bool alt = panel != 0 && panel != W;
-  if (alt && panel != WA) return hipErrorInvalidValue;
-  if (waves != 0 && waves != 4 && waves != 8) return hipErrorInvalidValue;
-  if (!alt && waves != 8) return run_block<T, W, KIND, 4>(probs, count, nmax, s);
   if constexpr (KIND == 0) {
-    if (!alt) return run_block<T, W, KIND, 8>(probs, count, nmax, s);
-    if (waves != 8) return run_block<T, WA, KIND, 4>(probs, count, nmax, s);
-    // FP64 with panel 32 at eight waves would spill registers: not built
-    if constexpr (sizeof(T) == 4) return run_block<T, WA, KIND, 8>(probs, count, nmax, s);
+    if (nopiv) return pick_block<T, KIND, false>(probs, count, nmax, panel, waves, s);
   }
-  return hipErrorInvalidValue;
+  return pick_block<T, KIND, true>(probs, count, nmax, panel, waves, s);
 }
 
 }  // namespace
@@ -694,14 +859,16 @@ int getrf_default_panel(bool t64) { return t64 ? 16 : 32; }
 
 template <typename T>
 hipError_t launch_getrf(const LuProb* probs, int count, int nmax, int kind, int panel, int waves,
-                        hipStream_t s, int form) {
+                        hipStream_t s, int form, bool nopiv) {
   if (count <= 0) return hipSuccess;
   if (form < kLuFormAuto || form > kLuFormBlock) return hipErrorInvalidValue;
-  return kind == 0 ? pick<T, 0>(probs, count, nmax, panel, waves, form, s)
-                   : pick<T, 1>(probs, count, nmax, panel, waves, form, s);
+  return kind == 0 ? pick<T, 0>(probs, count, nmax, panel, waves, form, nopiv, s)
+                   : pick<T, 1>(probs, count, nmax, panel, waves, form, false, s);
 }
 
-template hipError_t launch_getrf<double>(const LuProb*, int, int, int, int, int, hipStream_t, int);
-template hipError_t launch_getrf<float>(const LuProb*, int, int, int, int, int, hipStream_t, int);
+template hipError_t launch_getrf<double>(const LuProb*, int, int, int, int, int, hipStream_t, int,
+                                         bool);
+template hipError_t launch_getrf<float>(const LuProb*, int, int, int, int, int, hipStream_t, int,
+                                        bool);
 
 }  // namespace invaskit

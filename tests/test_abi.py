@@ -165,7 +165,8 @@ def test_bad_options_rejected(small_problem):
                            ("gmres_restart", 65, "gmres_restart"),
                            ("max_gmres_iters", 0, "max_gmres_iters"),
                            ("zlu_form", 3, "zlu_form"), ("zlu_form", -1, "zlu_form"),
-                           ("zsolve_cols", 24, "zsolve_cols")):
+                           ("zsolve_cols", 24, "zsolve_cols"),
+                           ("leaf_pivoting", 2, "leaf_pivoting")):
         binding.library().invaskit_default_options(C.byref(opt))
         setattr(opt, field, v)
         st, msg = _factor_status(raw, opt=opt)
@@ -174,8 +175,7 @@ def test_bad_options_rejected(small_problem):
 
 def test_options_struct_layout():
     """The binding's mirrors of invaskit_options and invaskit_solve_info have
-    the header's sizes and field offsets (options: 4 + 4 + 8 + 11 x 4 bytes,
-    padded to 64)."""
+    the header's sizes and field offsets (options: 4 + 4 + 8 + 12 x 4 bytes)."""
     from paper_1602_01376_amd import binding
     O = binding._Options
     assert C.sizeof(O) == 64
@@ -185,13 +185,15 @@ def test_options_struct_layout():
     assert O.refine.offset == 36 and O.gmres_restart.offset == 40
     assert O.max_gmres_iters.offset == 44 and O.lambda_group.offset == 48
     assert O.zlu_form.offset == 52 and O.zsolve_cols.offset == 56
+    assert O.leaf_pivoting.offset == 60
     S = binding.SolveInfo
     assert C.sizeof(S) == 32 and S.final_rel_residual.offset == 8
     assert S.gmres_iterations.offset == 24 and S.method.offset == 28
     T = binding._TileConfig
-    assert C.sizeof(T) == 60 and T.lu_ms.offset == 16 and T.trsm_ms.offset == 32
+    assert C.sizeof(T) == 64 and T.lu_ms.offset == 16 and T.trsm_ms.offset == 32
     assert T.leaf_trsm_cols_small.offset == 40 and T.trsm_small_ms.offset == 44
     assert T.zlu_one_wave_levels.offset == 52 and T.zsolve32_levels.offset == 56
+    assert T.leaf_pivoting.offset == 60
 
 
 def test_tuning_table_text_round_trip():

@@ -705,3 +705,54 @@ def test_reduced_system_forms_match_oracle(bind, problems, prec, zf, zc, name, k
     assert st == 0 and info["final_rel_residual"] <= 1e-10, info
     _assert_close(x.cpu().numpy(), x_ref, 1e-10 if prec == "fp64" else MIXED_XTOL.get(name, 1e-7))
     fac.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_leaf_pivoting_modes_match_oracle(bind, problems, prec):
+    """The leaf blocks lambda I + K_aa (symmetric positive definite for
+    lambda > 0) factored without row exchanges by default, or with partial
+    pivoting on request: both give the oracle's solution (uneven leaves, so
+    both size classes and every LU panel case run)."""
+    _say("leaf pivoting modes", prec)
+    pb, F = problems("susy", dict(n=8192, depth=5))
+    b = rhs_for(pb, nrhs=2)
+    x_ref = oracle.solve(F, b)
+    for mode, flag in (("auto", 0), ("partial", 1)):
+        fac = bind.Factorization(pb, pb.lam, precision=prec, leaf_pivoting=mode)
+        assert fac.tile_config()["leaf_pivoting"] == flag, mode
+        x, info, st = fac.solve(torch.from_numpy(b), return_info=True)
+        assert st == 0 and info["final_rel_residual"] <= 1e-10, (mode, info)
+        _assert_close(x.cpu().numpy(), x_ref, 1e-10 if prec == "fp64" else 1e-7, mode)
+        fac.close()
+
+
+def test_leaf_pivot_fallback_reproduces_partial_pivoting(bind):
+    """Leaves of 512 (the class factored without row exchanges), a very
+    smooth kernel (h = 16: the leaf blocks are numerically of low rank) and
+    lambda = 1e-9: FP32 rounding of the Schur complements (about 1e-5) swamps
+    lambda, so a pivot of the factorization without row exchanges comes out
+    not positive (a float32 simulation of these blocks gives about 170 per
+    block), and the factorization runs again with partial pivoting: the
+    result is bit for bit that of forced partial pivoting.  In FP64
+    (rounding about 3e-11, smallest pivot about 1.5e-9) the same lambda keeps
+    the faster path; a negative lambda pivots from the start."""
+    _say("leaf pivot fallback")
+    pb = make_problem("tiny", n=4096, depth=3, h=16.0)
+    lam = 1e-9
+    b = torch.from_numpy(rhs_for(pb, nrhs=1))
+    fa = bind.Factorization(pb, lam, precision="mixed", refine="none")
+    assert fa.tile_config()["leaf_pivoting"] == 1
+    xa = fa.solve(b, check=False).cpu().numpy()
+    fp = bind.Factorization(pb, lam, precision="mixed", refine="none", leaf_pivoting="partial")
+    xp = fp.solve(b, check=False).cpu().numpy()
+    assert xa.tobytes() == xp.tobytes()
+    fa.close()
+    fp.close()
+    f64 = bind.Factorization(pb, lam, precision="fp64")
+    assert f64.tile_config()["leaf_pivoting"] == 0
+    f64.close()
+    fn = bind.Factorization(pb, -0.5, precision="fp64", refine="none")
+    assert fn.tile_config()["leaf_pivoting"] == 1
+    x, info, st = fn.solve(b, return_info=True, check=False)
+    _say("  lambda -0.5 residual", info["final_rel_residual"])
+    fn.close()
