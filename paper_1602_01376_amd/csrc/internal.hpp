@@ -161,6 +161,13 @@ constexpr int kGemvCols = 4;
 constexpr int kGemvRows = 128;
 constexpr int kGemvRmMinK = 128;
 constexpr int kGemvSplitK = 1, kGemvRowMajor = 3;
+// kGemvTall: A column-major, M above kGemvRows: one row per thread,
+// workgroups of kGemvTallRows rows listed in a tile table (Tile3: prob, tm)
+constexpr int kGemvTall = 4;
+constexpr int kGemvTallRows = 256;
+template <typename T>
+hipError_t launch_gemv_tall(const GemmProb* probs, const GemmSeg* segs, const Tile3* tiles,
+                            int ntiles, hipStream_t s);
 template <typename T>
 hipError_t launch_gemv(const GemmProb* probs, const GemmSeg* segs, int count, int form,
                        hipStream_t s);

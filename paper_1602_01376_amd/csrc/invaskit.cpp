@@ -555,6 +555,28 @@ struct GemmBuilder {
       }
       const bool cm_ok = all_cm && mmax <= kGemvRows;
       const bool rm_ok = all_rm && ksum >= (double)kGemvRmMinK * probs.size();
+      if (skinny && all_cm && !cm_ok) {
+        // tall: workgroups of kGemvTallRows rows, longest products first
+        std::vector<int> order(probs.size());
+        std::vector<double> kk(probs.size(), 0.0);
+        for (size_t i = 0; i < probs.size(); ++i) {
+          order[i] = (int)i;
+          for (int q = 0; q < probs[i].nseg; ++q) kk[i] += segs[probs[i].seg0 + q].k;
+        }
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return kk[x] > kk[y]; });
+        std::vector<Tile3> tt;
+        for (int i : order)
+          for (int tm = 0; tm < (probs[i].M + kGemvTallRows - 1) / kGemvTallRows; ++tm)
+            if (probs[i].N > 0) tt.push_back({i, tm, 0});
+        GemmL l;
+        l.gemv = kGemvTall;
+        l.nprobs = (int)probs.size();
+        l.probs = ar.add(probs);
+        l.segs = ar.add(segs);
+        l.tiles = ar.add(tt);
+        l.ntiles = (int)tt.size();
+        return l;
+      }
       if (skinny && (cm_ok || rm_ok)) {
         GemmL l;
         l.gemv = cm_ok ? kGemvSplitK : kGemvRowMajor;
@@ -1077,6 +1099,9 @@ size_t factor_table_bytes(H* h, const KernelCache* kc) {
 hipError_t run_gemm(const Buf& tb, const GemmL& l, bool f64, hipStream_t s) {
   const GemmProb* p = at<GemmProb>(tb, l.probs);
   const GemmSeg* g = at<GemmSeg>(tb, l.segs);
+  if (l.gemv == kGemvTall)
+    return f64 ? launch_gemv_tall<double>(p, g, at<Tile3>(tb, l.tiles), l.ntiles, s)
+               : launch_gemv_tall<float>(p, g, at<Tile3>(tb, l.tiles), l.ntiles, s);
   if (l.gemv)
     return f64 ? launch_gemv<double>(p, g, l.nprobs, l.gemv, s)
                : launch_gemv<float>(p, g, l.nprobs, l.gemv, s);

@@ -168,50 +168,123 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmProb* __restrict__ probs
 }
 
 // Skinny products (N <= 4 columns, every A column-major, M <= 128): one
-// workgroup per product; lane = row of C (64 rows per pass), the four waves
-// take every fourth k, so each lane has a quarter of K in flight; the four
-// partial sums are added through LDS.  Used for the small right-hand-side
-// updates of the solve (the top-down pass).
+// workgroup per product.  The 256 threads cover R rows by 256 / R groups of
+// K, R the smallest power of two (16 .. 128) not below M, so that short
+// products (the solve's top-down pass: M = a skeleton rank, 32 .. 71) keep
+// every lane busy; consecutive threads read consecutive rows of a column
+// (coalesced), and the groups' partial sums are added through LDS in a fixed
+// order.
 template <typename T>
 __global__ __launch_bounds__(256) void k_gemv(const GemmProb* __restrict__ probs,
                                               const GemmSeg* __restrict__ segs) {
-  __shared__ T part[4][64][kGemvCols];
+  __shared__ T part[256][kGemvCols];
   const GemmProb P = probs[blockIdx.x];
   T* __restrict__ C = static_cast<T*>(P.C);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int r0 = 0; r0 < P.M; r0 += 64) {
-    const int row = r0 + lane;
-    const bool rin = row < P.M;
-    T acc[kGemvCols];
+  const int tid = threadIdx.x;
+  const int R = P.M <= 16 ? 16 : P.M <= 32 ? 32 : P.M <= 64 ? 64 : 128;
+  const int G = 256 / R;
+  const int row = tid & (R - 1), kg = tid / R;
+  const bool rin = row < P.M;
+  T acc[kGemvCols];
 #pragma unroll
-    for (int c = 0; c < kGemvCols; ++c) acc[c] = T(0);
-    for (int sg = P.seg0; sg < P.seg0 + P.nseg; ++sg) {
-      const GemmSeg g = segs[sg];
-      const T* __restrict__ A = static_cast<const T*>(g.A) + (rin ? row : 0);
-      const T* __restrict__ B = static_cast<const T*>(g.B);
+  for (int c = 0; c < kGemvCols; ++c) acc[c] = T(0);
+  for (int sg = P.seg0; sg < P.seg0 + P.nseg; ++sg) {
+    const GemmSeg g = segs[sg];
+    const T* __restrict__ A = static_cast<const T*>(g.A) + (rin ? row : 0);
+    const T* __restrict__ B = static_cast<const T*>(g.B);
 #pragma unroll 8
-      for (int k = wave; k < g.k; k += 4) {
-        const T a = A[(int64_t)k * g.lda];
+    for (int k = kg; k < g.k; k += G) {
+      const T a = A[(int64_t)k * g.lda];
 #pragma unroll
-        for (int c = 0; c < kGemvCols; ++c)
-          if (c < P.N) acc[c] = fma(a, B[(int64_t)c * g.ldb + k], acc[c]);
+      for (int c = 0; c < kGemvCols; ++c)
+        if (c < P.N) acc[c] = fma(a, B[(int64_t)c * g.ldb + k], acc[c]);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < kGemvCols; ++c) part[tid][c] = rin ? acc[c] : T(0);
+  __syncthreads();
+  if (tid < R && rin) {
+#pragma unroll
+    for (int c = 0; c < kGemvCols; ++c) {
+      if (c < P.N) {
+        T sum = part[tid][c];
+        for (int q = 1; q < G; ++q) sum += part[q * R + tid][c];
+        T* out = C + (int64_t)c * P.ldc + tid;
+        const T r = (T)P.alpha * sum;
+        *out = (P.beta != 0.0) ? (T)P.beta * (*out) + r : r;
       }
     }
+  }
+}
+
+// Skinny products (N <= 4, A column-major) taller than kGemvRows (the
+// solve's final product x = v - W~ e, a leaf's rows against every level's
+// W~ block): workgroups of kGemvTallRows = 256 rows from the tile list
+// (product, row block).  Lane l takes rows 4 l .. 4 l + 3 (one 16-byte load
+// per column in FP32, two in FP64) and the four waves split K; the waves'
+// partial sums are added through LDS in a fixed order.  A row group that
+// straddles the last row is read element by element, so no load passes the
+// product's last row.  B is the same for every lane (a broadcast load).
+template <typename T>
+__global__ __launch_bounds__(256) void k_gemv_tall(const GemmProb* __restrict__ probs,
+                                                   const GemmSeg* __restrict__ segs,
+                                                   const Tile3* __restrict__ tiles) {
+  typedef T vec4 __attribute__((ext_vector_type(4), aligned(sizeof(T))));
+  __shared__ T part[4][kGemvTallRows][kGemvCols];
+  const Tile3 t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
+  const GemmProb P = probs[t.prob];
+  T* __restrict__ C = static_cast<T*>(P.C);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lrow = 4 * lane;                       // first of the lane's rows in the block
+  const int row = t.tm * kGemvTallRows + lrow;     // in the product
+  const int nr = max(0, min(4, P.M - row));        // rows of the group inside the product
+  T acc[4][kGemvCols];
 #pragma unroll
-    for (int c = 0; c < kGemvCols; ++c) part[wave][lane][c] = rin ? acc[c] : T(0);
-    __syncthreads();
-    if (wave == 0 && rin) {
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int c = 0; c < kGemvCols; ++c) acc[i][c] = T(0);
+  for (int sg = P.seg0; sg < P.seg0 + P.nseg; ++sg) {
+    const GemmSeg g = segs[sg];
+    const T* __restrict__ A = static_cast<const T*>(g.A) + (nr > 0 ? row : 0);
+    const T* __restrict__ B = static_cast<const T*>(g.B);
+#pragma unroll 4
+    for (int k = wave; k < g.k; k += 4) {
+      const T* ak = A + (int64_t)k * g.lda;
+      vec4 a;
+      if (nr == 4) {
+        a = *reinterpret_cast<const vec4*>(ak);
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) a[i] = (i < nr) ? ak[i] : T(0);
+      }
 #pragma unroll
       for (int c = 0; c < kGemvCols; ++c) {
         if (c < P.N) {
-          const T sum = part[0][lane][c] + part[1][lane][c] + part[2][lane][c] + part[3][lane][c];
-          T* out = C + (int64_t)c * P.ldc + row;
-          const T r = (T)P.alpha * sum;
-          *out = (P.beta != 0.0) ? (T)P.beta * (*out) + r : r;
+          const T b = B[(int64_t)c * g.ldb + k];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) acc[i][c] = fma(a[i], b, acc[i][c]);
         }
       }
     }
-    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int c = 0; c < kGemvCols; ++c) part[wave][lrow + i][c] = acc[i][c];
+  __syncthreads();
+  // thread t finishes row t of the block
+  const int tr = threadIdx.x;
+  const int orow = t.tm * kGemvTallRows + tr;
+  if (orow < P.M) {
+#pragma unroll
+    for (int c = 0; c < kGemvCols; ++c) {
+      if (c < P.N) {
+        const T sum = (part[0][tr][c] + part[1][tr][c]) + (part[2][tr][c] + part[3][tr][c]);
+        T* out = C + (int64_t)c * P.ldc + orow;
+        const T r = (T)P.alpha * sum;
+        *out = (P.beta != 0.0) ? (T)P.beta * (*out) + r : r;
+      }
+    }
   }
 }
 
@@ -271,6 +344,19 @@ hipError_t launch_gemv(const GemmProb* probs, const GemmSeg* segs, int count, in
 }
 template hipError_t launch_gemv<double>(const GemmProb*, const GemmSeg*, int, int, hipStream_t);
 template hipError_t launch_gemv<float>(const GemmProb*, const GemmSeg*, int, int, hipStream_t);
+
+template <typename T>
+hipError_t launch_gemv_tall(const GemmProb* probs, const GemmSeg* segs, const Tile3* tiles,
+                            int ntiles, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_gemv_tall<T>), dim3(ntiles), dim3(kGemvTallRows), 0, s, probs, segs,
+                     tiles);
+  return hipGetLastError();
+}
+template hipError_t launch_gemv_tall<double>(const GemmProb*, const GemmSeg*, const Tile3*, int,
+                                             hipStream_t);
+template hipError_t launch_gemv_tall<float>(const GemmProb*, const GemmSeg*, const Tile3*, int,
+                                            hipStream_t);
 
 template <typename T>
 hipError_t launch_gemm(const GemmProb* probs, const GemmSeg* segs, const Tile3* tiles,
