@@ -71,7 +71,7 @@ COPY_KERNEL = "k_copy_cols<double, double>"
 # the phase's kernel; {p} and {w} are its tile parameters (LU panel width and
 # waves per matrix, or 16-column tiles per workgroup of the solves)
 PHASE_KERNEL = {
-    "leaf_lu_large": (r"k_getrf<{t}, {p}, \d+, 0, {w}>", "kernels_lu.hip"),
+    "leaf_lu_large": (r"k_getrf<{t}, {p}, \d+, 0, {w}, (?:true|false)>", "kernels_lu.hip"),
     "leaf_solves_large": (r"k_getrs<{t}, {t}, 0, {p}>", "kernels_trsm.hip"),
 }
 # leaves of at most this order form the library's small class (FP32, FP64),
