@@ -18,6 +18,20 @@ struct Vec4<float> {
   using type = f32x4;
 };
 
+// Global-memory pointers.  The kernels' problem descriptors hold generic
+// pointers, and loads through a generic pointer compile to FLAT
+// instructions, which count on the LDS counter as well: every wait for an
+// LDS result would then also wait for all global loads in flight, defeating
+// loads issued ahead.  Data pointers are therefore cast to the global
+// address space once, at kernel entry.
+#define INVASKIT_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+using gptr = T INVASKIT_GLOBAL*;
+template <typename T>
+__device__ __forceinline__ gptr<T> glb(T* p) {
+  return (gptr<T>)p;
+}
+
 // 16 x 16 x 4 MFMA.  Operand layout of both forms: lane l supplies
 // A[l % 16][l / 16] and B[l / 16][l % 16].
 __device__ __forceinline__ f64x4 mfma16(double a, double b, f64x4 c) {
@@ -87,6 +101,69 @@ __device__ __forceinline__ void load_row_sigma_full(const T* __restrict__ rowp, 
 #pragma unroll
     for (int e = 0; e < VE; ++e) a[VE * i + e] = (k0 + e < klim) ? v[e] : T(0);
   }
+}
+
+// load_row_sigma_full through a global pointer
+template <typename T, int KQ>
+__device__ __forceinline__ void load_row_sigma_full(gptr<const T> rowp, int klim, int g,
+                                                    T (&a)[KQ]) {
+  constexpr int VE = 16 / sizeof(T);
+  typedef T vec __attribute__((ext_vector_type(VE), aligned(sizeof(T))));
+#pragma unroll
+  for (int i = 0; i < KQ / VE; ++i) {
+    const int k0 = 4 * VE * i + VE * g;
+    const vec v = *(gptr<const vec>)(rowp + k0);
+#pragma unroll
+    for (int e = 0; e < VE; ++e) a[VE * i + e] = (k0 + e < klim) ? v[e] : T(0);
+  }
+}
+template <typename T, int KQ>
+__device__ __forceinline__ void load_row_sigma_full(gptr<T> rowp, int klim, int g, T (&a)[KQ]) {
+  load_row_sigma_full((gptr<const T>)rowp, klim, g, a);
+}
+
+// Unmasked global form: the four lane groups' 16-byte vectors of the
+// segment, nothing zeroed (the caller masks where the segment passes the
+// block, at the point of use, so the loads stay in flight until then).
+template <typename T, int KQ>
+__device__ __forceinline__ void load_row_sigma_raw(gptr<const T> rowp, int g, T (&a)[KQ]) {
+  constexpr int VE = 16 / sizeof(T);
+  typedef T vec __attribute__((ext_vector_type(VE), aligned(sizeof(T))));
+#pragma unroll
+  for (int i = 0; i < KQ / VE; ++i) {
+    const vec v = *(gptr<const vec>)(rowp + 4 * VE * i + VE * g);
+#pragma unroll
+    for (int e = 0; e < VE; ++e) a[VE * i + e] = v[e];
+  }
+}
+// Global form of load_row_sigma (never reads at or beyond rowp[klim]).
+template <typename T, int KQ>
+__device__ __forceinline__ void load_row_sigma_g(gptr<const T> rowp, int klim, int g,
+                                                 T (&a)[KQ]) {
+  constexpr int VE = 16 / sizeof(T);
+  typedef T vec __attribute__((ext_vector_type(VE), aligned(sizeof(T))));
+#pragma unroll
+  for (int i = 0; i < KQ / VE; ++i) {
+    const int k0 = 4 * VE * i + VE * g;
+    if (k0 + VE <= klim) {
+      const vec v = *(gptr<const vec>)(rowp + k0);
+#pragma unroll
+      for (int e = 0; e < VE; ++e) a[VE * i + e] = v[e];
+    } else {
+#pragma unroll
+      for (int e = 0; e < VE; ++e) a[VE * i + e] = (k0 + e < klim) ? rowp[k0 + e] : T(0);
+    }
+  }
+}
+// zero the elements at k >= klim of a segment loaded in sigma order
+template <typename T, int KQ>
+__device__ __forceinline__ void mask_sigma(int klim, int g, T (&a)[KQ]) {
+  constexpr int VE = 16 / sizeof(T);
+#pragma unroll
+  for (int i = 0; i < KQ / VE; ++i)
+#pragma unroll
+    for (int e = 0; e < VE; ++e)
+      if (4 * VE * i + VE * g + e >= klim) a[VE * i + e] = T(0);
 }
 
 }  // namespace invaskit

@@ -65,7 +65,7 @@ __global__ __launch_bounds__(256) void k_eval(const PT* __restrict__ X, int d, d
   if (tid < ET) {
     const int c = c0 + tid;
     int64_t g = -1;
-    if (c < b.ncols) g = b.cols ? (int64_t)b.cols[c] : b.col0 + c;
+    if (c < b.ncols) g = b.cols ? (int64_t)glb(b.cols)[c] : b.col0 + c;
     cidx[tid] = g;
   }
   __syncthreads();
@@ -104,7 +104,7 @@ __global__ __launch_bounds__(256) void k_eval(const PT* __restrict__ X, int d, d
     __syncthreads();
   }
 
-  T* __restrict__ out = static_cast<T*>(b.out);
+  const gptr<T> out = glb(static_cast<T*>(b.out));
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int c = c0 + tc + 16 * j;
@@ -217,7 +217,7 @@ __global__ __launch_bounds__(256) void k_eval_gram(const PT* __restrict__ X, int
   } else if (tid < 2 * ET) {
     const int c = c0 + tid - ET;
     int64_t g = -1;
-    if (c < b.ncols) g = b.cols ? (int64_t)b.cols[c] : b.col0 + c;
+    if (c < b.ncols) g = b.cols ? (int64_t)glb(b.cols)[c] : b.col0 + c;
     coli[tid - ET] = g;
   }
   f64x4 acc[2][2];
@@ -231,7 +231,7 @@ __global__ __launch_bounds__(256) void k_eval_gram(const PT* __restrict__ X, int
   const int lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lg = lane >> 4;
   const int wr = wave & 1, wc = wave >> 1;
-  T* __restrict__ out = static_cast<T*>(b.out);
+  const gptr<T> out = glb(static_cast<T*>(b.out));
 #pragma unroll
   for (int ri = 0; ri < 2; ++ri) {
     const int rl = 32 * wr + 16 * ri + lr;
@@ -304,14 +304,14 @@ __global__ __launch_bounds__(MB / TPT) void k_mv_eval(const PT* __restrict__ X, 
           const int j = idx / DM, k = idx % DM;
           double v = 0.0;
           if (j < nj && k < d) {
-            const int64_t p = g.idx ? (int64_t)g.idx[j0 + j] : g.p0 + j0 + j;
+            const int64_t p = g.idx ? (int64_t)glb(g.idx)[j0 + j] : g.p0 + j0 + j;
             v = (double)X[p * d + k];
           }
           sx[j][k] = v;
         }
         for (int idx = tid; idx < MS * RC; idx += NT) {
           const int j = idx / RC, c = idx % RC;
-          sw[j][c] = (j < nj && c < ncol) ? g.w[(int64_t)(cb + c) * g.ldw + j0 + j] : 0.0;
+          sw[j][c] = (j < nj && c < ncol) ? glb(g.w)[(int64_t)(cb + c) * g.ldw + j0 + j] : 0.0;
         }
         __syncthreads();
         for (int j = 0; j < nj; ++j) {
@@ -398,10 +398,10 @@ __global__ __launch_bounds__(256) void k_mv_eval_gram(
         const int nj = min(WS, g.count - j0);
         __syncthreads();  // the previous stage's coli, sw, nr, nc are consumed
         if (tid < WS)
-          coli[tid] = (tid < nj) ? (g.idx ? (int64_t)g.idx[j0 + tid] : g.p0 + j0 + tid) : -1;
+          coli[tid] = (tid < nj) ? (g.idx ? (int64_t)glb(g.idx)[j0 + tid] : g.p0 + j0 + tid) : -1;
         for (int idx = tid; idx < WS * RC; idx += 256) {
           const int j = idx / RC, c = idx % RC;
-          sw[j][c] = (j < nj && c < ncol) ? g.w[(int64_t)(cb + c) * g.ldw + j0 + j] : 0.0;
+          sw[j][c] = (j < nj && c < ncol) ? glb(g.w)[(int64_t)(cb + c) * g.ldw + j0 + j] : 0.0;
         }
         f64x4 gm[2][2];
         double nrm;

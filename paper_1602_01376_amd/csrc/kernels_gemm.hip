@@ -66,8 +66,8 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmProb* __restrict__ probs
   T av[NA], bv[NB];
   int arm = 0;
   auto fetch = [&](const GemmSeg& g, int k0) {
-    const T* __restrict__ A = static_cast<const T*>(g.A);
-    const T* __restrict__ B = static_cast<const T*>(g.B);
+    const gptr<const T> A = glb(static_cast<const T*>(g.A));
+    const gptr<const T> B = glb(static_cast<const T*>(g.B));
     arm = g.a_rm;
 #pragma unroll
     for (int q = 0; q < NA; ++q) {
@@ -139,7 +139,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmProb* __restrict__ probs
     }
   }
 
-  T* __restrict__ C = static_cast<T*>(P.C);
+  const gptr<T> C = glb(static_cast<T*>(P.C));
   const T alpha = (T)P.alpha;
   const T beta = (T)P.beta;
 #pragma unroll
@@ -158,7 +158,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmProb* __restrict__ probs
           col = 16 * j + acc_row(T(0), lk, v);
         }
         if (row < P.M && col < nw) {
-          T* c = CT ? C + (int64_t)row * P.ldc + n0 + col : C + (int64_t)(n0 + col) * P.ldc + row;
+          const gptr<T> c = CT ? C + (int64_t)row * P.ldc + n0 + col : C + (int64_t)(n0 + col) * P.ldc + row;
           const T r = alpha * acc[i][j][v];
           *c = (P.beta != 0.0) ? beta * (*c) + r : r;
         }
@@ -179,7 +179,7 @@ __global__ __launch_bounds__(256) void k_gemv(const GemmProb* __restrict__ probs
                                               const GemmSeg* __restrict__ segs) {
   __shared__ T part[256][kGemvCols];
   const GemmProb P = probs[blockIdx.x];
-  T* __restrict__ C = static_cast<T*>(P.C);
+  const gptr<T> C = glb(static_cast<T*>(P.C));
   const int tid = threadIdx.x;
   const int R = P.M <= 16 ? 16 : P.M <= 32 ? 32 : P.M <= 64 ? 64 : 128;
   const int G = 256 / R;
@@ -190,8 +190,8 @@ __global__ __launch_bounds__(256) void k_gemv(const GemmProb* __restrict__ probs
   for (int c = 0; c < kGemvCols; ++c) acc[c] = T(0);
   for (int sg = P.seg0; sg < P.seg0 + P.nseg; ++sg) {
     const GemmSeg g = segs[sg];
-    const T* __restrict__ A = static_cast<const T*>(g.A) + (rin ? row : 0);
-    const T* __restrict__ B = static_cast<const T*>(g.B);
+    const gptr<const T> A = glb(static_cast<const T*>(g.A)) + (rin ? row : 0);
+    const gptr<const T> B = glb(static_cast<const T*>(g.B));
 #pragma unroll 8
     for (int k = kg; k < g.k; k += G) {
       const T a = A[(int64_t)k * g.lda];
@@ -209,7 +209,7 @@ __global__ __launch_bounds__(256) void k_gemv(const GemmProb* __restrict__ probs
       if (c < P.N) {
         T sum = part[tid][c];
         for (int q = 1; q < G; ++q) sum += part[q * R + tid][c];
-        T* out = C + (int64_t)c * P.ldc + tid;
+        const gptr<T> out = C + (int64_t)c * P.ldc + tid;
         const T r = (T)P.alpha * sum;
         *out = (P.beta != 0.0) ? (T)P.beta * (*out) + r : r;
       }
@@ -233,7 +233,7 @@ __global__ __launch_bounds__(256) void k_gemv_tall(const GemmProb* __restrict__ 
   __shared__ T part[4][kGemvTallRows][kGemvCols];
   const Tile3 t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
   const GemmProb P = probs[t.prob];
-  T* __restrict__ C = static_cast<T*>(P.C);
+  const gptr<T> C = glb(static_cast<T*>(P.C));
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int lrow = 4 * lane;                       // first of the lane's rows in the block
   const int row = t.tm * kGemvTallRows + lrow;     // in the product
@@ -245,14 +245,14 @@ __global__ __launch_bounds__(256) void k_gemv_tall(const GemmProb* __restrict__ 
     for (int c = 0; c < kGemvCols; ++c) acc[i][c] = T(0);
   for (int sg = P.seg0; sg < P.seg0 + P.nseg; ++sg) {
     const GemmSeg g = segs[sg];
-    const T* __restrict__ A = static_cast<const T*>(g.A) + (nr > 0 ? row : 0);
-    const T* __restrict__ B = static_cast<const T*>(g.B);
+    const gptr<const T> A = glb(static_cast<const T*>(g.A)) + (nr > 0 ? row : 0);
+    const gptr<const T> B = glb(static_cast<const T*>(g.B));
 #pragma unroll 4
     for (int k = wave; k < g.k; k += 4) {
-      const T* ak = A + (int64_t)k * g.lda;
+      const gptr<const T> ak = A + (int64_t)k * g.lda;
       vec4 a;
       if (nr == 4) {
-        a = *reinterpret_cast<const vec4*>(ak);
+        a = *(gptr<const vec4>)ak;
       } else {
 #pragma unroll
         for (int i = 0; i < 4; ++i) a[i] = (i < nr) ? ak[i] : T(0);
@@ -280,7 +280,7 @@ __global__ __launch_bounds__(256) void k_gemv_tall(const GemmProb* __restrict__ 
     for (int c = 0; c < kGemvCols; ++c) {
       if (c < P.N) {
         const T sum = (part[0][tr][c] + part[1][tr][c]) + (part[2][tr][c] + part[3][tr][c]);
-        T* out = C + (int64_t)c * P.ldc + orow;
+        const gptr<T> out = C + (int64_t)c * P.ldc + orow;
         const T r = (T)P.alpha * sum;
         *out = (P.beta != 0.0) ? (T)P.beta * (*out) + r : r;
       }
@@ -295,7 +295,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_gemv_rm(const GemmProb* __restrict__ probs,
                                                  const GemmSeg* __restrict__ segs) {
   const GemmProb P = probs[blockIdx.x];
-  T* __restrict__ C = static_cast<T*>(P.C);
+  const gptr<T> C = glb(static_cast<T*>(P.C));
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int row = wave; row < P.M; row += 4) {
     T acc[kGemvCols];
@@ -303,8 +303,8 @@ __global__ __launch_bounds__(256) void k_gemv_rm(const GemmProb* __restrict__ pr
     for (int c = 0; c < kGemvCols; ++c) acc[c] = T(0);
     for (int sg = P.seg0; sg < P.seg0 + P.nseg; ++sg) {
       const GemmSeg g = segs[sg];
-      const T* __restrict__ A = static_cast<const T*>(g.A) + (int64_t)row * g.lda;
-      const T* __restrict__ B = static_cast<const T*>(g.B);
+      const gptr<const T> A = glb(static_cast<const T*>(g.A)) + (int64_t)row * g.lda;
+      const gptr<const T> B = glb(static_cast<const T*>(g.B));
 #pragma unroll 4
       for (int k = lane; k < g.k; k += 64) {
         const T a = A[k];
@@ -321,7 +321,7 @@ __global__ __launch_bounds__(256) void k_gemv_rm(const GemmProb* __restrict__ pr
 #pragma unroll
       for (int c = 0; c < kGemvCols; ++c) {
         if (c < P.N) {
-          T* out = C + (int64_t)c * P.ldc + row;
+          const gptr<T> out = C + (int64_t)c * P.ldc + row;
           const T r = (T)P.alpha * acc[c];
           *out = (P.beta != 0.0) ? (T)P.beta * (*out) + r : r;
         }

@@ -135,7 +135,7 @@ __global__ __launch_bounds__(64 * NW) void k_getrf(const LuProb* __restrict__ pr
   constexpr int NT = 64 * NW;  // threads
   static_assert(W % NW == 0, "inv(L11) gives each wave W / NW columns");
   const LuProb pr = probs[blockIdx.x];
-  T* __restrict__ A = static_cast<T*>(pr.a);
+  const gptr<T> A = glb(static_cast<T*>(pr.a));
   const int n = pr.n;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -317,7 +317,7 @@ __global__ __launch_bounds__(64 * NW) void k_getrf(const LuProb* __restrict__ pr
     const int jb = min(W, n - j0);
     if (wave == 0) {
       T P0[W];
-      T* rowp = A + (int64_t)(j0 + (lane < jb ? lane : 0)) * n + j0;
+      const gptr<T> rowp = A + (int64_t)(j0 + (lane < jb ? lane : 0)) * n + j0;
 #pragma unroll
       for (int c = 0; c < W; ++c) P0[c] = (lane < jb && c < jb) ? rowp[c] : T(0);
       int info = 0;
@@ -577,8 +577,8 @@ __global__ __launch_bounds__(64 * NW) void k_getrf(const LuProb* __restrict__ pr
     update(std::integral_constant<int, W2>{}, J0, J0 + W2, n);
   }
 
-  for (int i = tid; i < n; i += NT) pr.perm[i] = Ps[i];
-  if (tid == 0) *pr.info = s_info;
+  for (int i = tid; i < n; i += NT) glb(pr.perm)[i] = Ps[i];
+  if (tid == 0) *glb(pr.info) = s_info;
 }
 
 // One wave per matrix, for small orders (n <= 64 RPS; panels of 32 columns
@@ -592,7 +592,7 @@ template <typename T, int W, int RPS, int KIND>
 __global__ __launch_bounds__(64) void k_getrf_w(const LuProb* __restrict__ probs) {
   using V4 = typename Vec4<T>::type;
   const LuProb pr = probs[blockIdx.x];
-  T* __restrict__ A = static_cast<T*>(pr.a);
+  const gptr<T> A = glb(static_cast<T*>(pr.a));
   const int n = pr.n;
   const int lane = threadIdx.x;
   const int lr = lane & 15, lg = lane >> 4;
@@ -777,8 +777,8 @@ __global__ __launch_bounds__(64) void k_getrf_w(const LuProb* __restrict__ probs
     }
   }
 
-  for (int i = lane; i < n; i += 64) pr.perm[i] = Ps[i];
-  if (lane == 0) *pr.info = info;
+  for (int i = lane; i < n; i += 64) glb(pr.perm)[i] = Ps[i];
+  if (lane == 0) *glb(pr.info) = info;
 }
 
 template <typename T, int W, int RPS, int KIND>

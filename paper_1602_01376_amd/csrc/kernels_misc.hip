@@ -1,6 +1,7 @@
 // Small element-wise kernels: reduced-system assembly (eq. (11),
 // written row-major as the batched LU expects),
 // precision conversions and the FP64 vector steps of iterative refinement.
+#include "device_util.hpp"
 #include "internal.hpp"
 
 namespace invaskit {
@@ -10,9 +11,9 @@ template <typename TZ, typename TV>
 __global__ __launch_bounds__(256) void k_zform(const ZformProb* __restrict__ probs) {
   const ZformProb p = probs[blockIdx.x];
   const int n = p.sr + p.sl;
-  TZ* __restrict__ Z = static_cast<TZ*>(p.Z);
-  const TV* __restrict__ pr = static_cast<const TV*>(p.pr);
-  const TV* __restrict__ pl = static_cast<const TV*>(p.pl);
+  const gptr<TZ> Z = glb(static_cast<TZ*>(p.Z));
+  const gptr<const TV> pr = glb(static_cast<const TV*>(p.pr));
+  const gptr<const TV> pl = glb(static_cast<const TV*>(p.pl));
   for (int64_t idx = threadIdx.x; idx < (int64_t)n * n; idx += 256) {
     const int i = (int)(idx / n), j = (int)(idx % n);  // row-major
     TZ v;
@@ -30,8 +31,8 @@ __global__ __launch_bounds__(256) void k_zform(const ZformProb* __restrict__ pro
 template <typename T>
 __global__ __launch_bounds__(256) void k_copy_shift(const CopyShiftProb* __restrict__ probs) {
   const CopyShiftProb p = probs[blockIdx.x];
-  const T* __restrict__ src = static_cast<const T*>(p.src);
-  T* __restrict__ dst = static_cast<T*>(p.dst);
+  const gptr<const T> src = glb(static_cast<const T*>(p.src));
+  const gptr<T> dst = glb(static_cast<T*>(p.dst));
   const int64_t mm = (int64_t)p.m * p.m;
   const T sh = (T)p.shift;
   for (int64_t e = threadIdx.x; e < mm; e += 256)

@@ -48,8 +48,9 @@ constexpr int DIP = NBK + 4;  // LDS row stride: 16-byte aligned rows
 template <typename TZ>
 __global__ __launch_bounds__(128, 2) void k_diag_inv(const DiagInvProb* __restrict__ probs) {
   const DiagInvProb p = probs[blockIdx.x];
-  const TZ* __restrict__ LU = static_cast<const TZ*>(p.lu);
-  TZ* __restrict__ out = static_cast<TZ*>(p.out);  // inv(L_bb) then inv(U_bb), 64 x 64 each
+  const gptr<const TZ> LU = glb(static_cast<const TZ*>(p.lu));
+  const gptr<const int32_t> perm = glb(p.perm);
+  const gptr<TZ> out = glb(static_cast<TZ*>(p.out));  // inv(L_bb) then inv(U_bb), 64 x 64 each
   const int n = p.n, jb = p.jb;
   const int nb = min(NBK, n - jb);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -58,7 +59,7 @@ __global__ __launch_bounds__(128, 2) void k_diag_inv(const DiagInvProb* __restri
   // consecutive threads read consecutive columns of a factor row
   for (int idx = tid; idx < NBK * NBK; idx += 128) {
     const int k = idx % NBK, i = idx / NBK;
-    B[k][i] = (i < nb && k < nb) ? LU[(int64_t)p.perm[jb + i] * n + jb + k] : TZ(0);
+    B[k][i] = (i < nb && k < nb) ? LU[(int64_t)perm[jb + i] * n + jb + k] : TZ(0);
   }
   __syncthreads();
   if (tid < NBK) rdiag[tid] = (tid < nb) ? TZ(1) / B[tid][tid] : TZ(0);
@@ -85,7 +86,7 @@ __global__ __launch_bounds__(128, 2) void k_diag_inv(const DiagInvProb* __restri
       for (int i = 0; i < k; ++i) x[i] -= B[k][i] * xk;
     }
   }
-  TZ* dst = out + wave * NBK * NBK;  // row-major: lanes of a row store consecutive columns
+  const gptr<TZ> dst = out + wave * NBK * NBK;  // row-major: lanes of a row store consecutive columns
 #pragma unroll
   for (int i = 0; i < NBK; ++i) dst[i * NBK + c] = (i < nb && c < nb) ? x[i] : TZ(0);
 }
@@ -102,14 +103,17 @@ __global__ __launch_bounds__(256) void k_getrs(const TrsmProb* __restrict__ prob
   const int n = pr.n;
   const int c0 = t.tn * RT;
   const int nc = min(RT, pr.nrhs - c0);
-  const TZ* __restrict__ LU = static_cast<const TZ*>(pr.lu);
-  const TZ* __restrict__ DI = static_cast<const TZ*>(pr.dinv);
-  const TV* __restrict__ in0 = static_cast<const TV*>(pr.in0);
-  const TV* __restrict__ in1 = static_cast<const TV*>(pr.in1);
-  TV* __restrict__ out = static_cast<TV*>(pr.out);
+  const gptr<const TZ> LU = glb(static_cast<const TZ*>(pr.lu));
+  const gptr<const TZ> DI = glb(static_cast<const TZ*>(pr.dinv));
+  const gptr<const TV> in0 = glb(static_cast<const TV*>(pr.in0));
+  const gptr<const TV> in1 = glb(static_cast<const TV*>(pr.in1));
+  const gptr<const int32_t> perm = glb(pr.perm);
+  const gptr<TV> out = glb(static_cast<TV*>(pr.out));
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wave = tid >> 6;
+  // the wave index is uniform: kept in a scalar register, the item loops
+  // below branch on scalars and their loads need no divergent paths
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lr = lane & 15, lg = lane >> 4;
 
   extern __shared__ __align__(16) unsigned char smem[];
@@ -126,24 +130,27 @@ __global__ __launch_bounds__(256) void k_getrs(const TrsmProb* __restrict__ prob
   auto load_d = [&](int q) {
     const bool f = q < nblocks;
     const int bq = f ? q : nsteps - 1 - q;
-    const TZ* D = DI + (int64_t)(2 * bq + (f ? 0 : 1)) * NBK * NBK;
-    load_row_sigma_full(D + (16 * wave + lr) * NBK, NBK, lg, da);
+    const gptr<const TZ> D = DI + (int64_t)(2 * bq + (f ? 0 : 1)) * NBK * NBK;
+    load_row_sigma_raw(D + (16 * wave + lr) * NBK, lg, da);
   };
   load_d(0);
 
   // gather the permuted right-hand sides: one thread per row, 16 column
-  // loads of the row in flight together
+  // loads of the row in flight together (columns past the last read the
+  // last one again and are zeroed)
   for (int i = tid; i < n; i += 256) {
-    const int src = pr.perm[i];
+    const int src = perm[i];
     Pm[i] = src;
-    const TV* base = (src < pr.split) ? in0 + src : in1 + (src - pr.split);
+    const gptr<const TV> base = (src < pr.split) ? in0 + src : in1 + (src - pr.split);
     const int64_t ld = (src < pr.split) ? pr.ldin0 : pr.ldin1;
 #pragma unroll 1
     for (int ct = 0; ct < CT; ++ct) {
       TZ v[16];
 #pragma unroll
-      for (int c = 0; c < 16; ++c)
-        v[c] = (16 * ct + c < nc) ? (TZ)base[(int64_t)(c0 + 16 * ct + c) * ld] : TZ(0);
+      for (int c = 0; c < 16; ++c) {
+        const TZ e = (TZ)base[(int64_t)(c0 + min(16 * ct + c, nc - 1)) * ld];
+        v[c] = (16 * ct + c < nc) ? e : TZ(0);
+      }
 #pragma unroll
       for (int c = 0; c < 16; ++c) X[i * RTP + 16 * ct + c] = v[c];
     }
@@ -159,17 +166,20 @@ __global__ __launch_bounds__(256) void k_getrs(const TrsmProb* __restrict__ prob
     const int r0 = fwd ? jb + nb : 0;
     const int r1 = fwd ? n : jb;
     const int nrt = (r1 - r0 + 15) / 16;
+    // factor rows of one 16-row item.  Rows past r1 read row r1 - 1 (their
+    // products are discarded); the library's factors are padded by one
+    // block, so whole segments are read and the part past the block is
+    // zeroed where it is used (KIND 3 reads only inside the block).
     auto load_f = [&](int item, TZ (&a)[NBK / 4]) {
       const int row = r0 + item * 16 + lr;
-      const bool rin = row < r1;
-      const TZ* rowp = LU + (int64_t)(rin ? Pm[row] : 0) * n + jb;
+      const gptr<const TZ> rowp = LU + (int64_t)Pm[min(row, r1 - 1)] * n + jb;
       if constexpr (KIND == 3)
-        load_row_sigma(rowp, rin ? nb : 0, lg, a);
+        load_row_sigma_g(rowp, row < r1 ? nb : 0, lg, a);
       else
-        load_row_sigma_full(rowp, rin ? nb : 0, lg, a);
+        load_row_sigma_raw(rowp, lg, a);
     };
     TZ fa[NBK / 4], fb[NBK / 4];
-    if (wave < nrt) load_f(wave, fa);
+    if (nrt > 0) load_f(min(wave, nrt - 1), fa);
     // X_b = inv(diagonal block) X_b: wave w computes rows 16w .. 16w+15 of
     // each 16-column tile
     {
@@ -177,12 +187,15 @@ __global__ __launch_bounds__(256) void k_getrs(const TrsmProb* __restrict__ prob
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct) {
         acc[ct] = V4{0, 0, 0, 0};
+        TZ bb[NBK / 4];  // all LDS reads issued before the products
 #pragma unroll
         for (int kk = 0; kk < NBK / 4; ++kk) {
           const int k = sigma_k<TZ>(kk, lg);
-          const TZ bb = (k < nb) ? X[(jb + k) * RTP + 16 * ct + lr] : TZ(0);
-          acc[ct] = mfma16(da[kk], bb, acc[ct]);
+          const TZ v = X[min(jb + k, n - 1) * RTP + 16 * ct + lr];
+          bb[kk] = (k < nb) ? v : TZ(0);
         }
+#pragma unroll
+        for (int kk = 0; kk < NBK / 4; ++kk) acc[ct] = mfma16(da[kk], bb[kk], acc[ct]);
       }
       __syncthreads();
 #pragma unroll
@@ -205,9 +218,20 @@ __global__ __launch_bounds__(256) void k_getrs(const TrsmProb* __restrict__ prob
 #pragma unroll
       for (int kk = 0; kk < NBK / 4; ++kk) {
         const int j = sigma_k<TZ>(kk, lg);
-        xb[ct][kk] = (j < nb) ? X[(jb + j) * RTP + 16 * ct + lr] : TZ(0);
+        const TZ v = X[min(jb + j, n - 1) * RTP + 16 * ct + lr];
+        xb[ct][kk] = (j < nb) ? v : TZ(0);
       }
-    auto update = [&](int item, const TZ (&a)[NBK / 4]) {
+    auto update = [&](int item, TZ (&a)[NBK / 4]) {
+      const int i0 = r0 + item * 16;
+      // the item's rows are this wave's alone in this step: read them
+      // before the products so the LDS latency overlaps them
+      TZ xo[CT][4];
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          xo[ct][v] = X[min(i0 + acc_row(TZ(0), lg, v), r1 - 1) * RTP + 16 * ct + lr];
+      if (KIND != 3 && nb < NBK) mask_sigma(nb, lg, a);
       V4 acc[CT];
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct) {
@@ -215,19 +239,19 @@ __global__ __launch_bounds__(256) void k_getrs(const TrsmProb* __restrict__ prob
 #pragma unroll
         for (int kk = 0; kk < NBK / 4; ++kk) acc[ct] = mfma16(a[kk], xb[ct][kk], acc[ct]);
       }
-      const int i0 = r0 + item * 16;
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int rr = i0 + acc_row(TZ(0), lg, v);
-          if (rr < r1) X[rr * RTP + 16 * ct + lr] -= acc[ct][v];
+          if (rr < r1) X[rr * RTP + 16 * ct + lr] = xo[ct][v] - acc[ct][v];
         }
     };
+    // loads past the last item re-read it (no branch around a load)
     for (int item = wave; item < nrt; item += 8) {
-      if (item + 4 < nrt) load_f(item + 4, fb);
+      load_f(min(item + 4, nrt - 1), fb);
       update(item, fa);
-      if (item + 8 < nrt) load_f(item + 8, fa);
+      load_f(min(item + 8, nrt - 1), fa);
       if (item + 4 < nrt) update(item + 4, fb);
     }
     __syncthreads();
