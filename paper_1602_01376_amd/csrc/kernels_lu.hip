@@ -139,7 +139,7 @@ __global__ __launch_bounds__(64 * NW) void k_getrf(const LuProb* __restrict__ pr
   const int n = pr.n;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wave = tid >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: scalar branches
   const int lr = lane & 15, lg = lane >> 4;
 
   extern __shared__ __align__(16) unsigned char smem[];
@@ -463,28 +463,41 @@ __global__ __launch_bounds__(64 * NW) void k_getrf(const LuProb* __restrict__ pr
         const int cc = cb + cl;
         if ((SYM || i >= 1) && cc < ce) A[(int64_t)Ps[r0 + i] * n + cc] = Uc[i][cl];
       }
-      // two row tiles per iteration (it and it + NW): both tiles' operand
-      // loads are in flight before either computes.  A second tile past the
-      // last row reads nothing and stores nothing (rows >= n are masked), so
-      // the loop has no divergent path.
+      // two row tiles per iteration (it and it + NW), and in FP32 the next
+      // iteration's two tiles are loaded while this one computes (FP64
+      // has no registers to spare).  r0 + KW <= n here, so a row's segment
+      // lies inside the row; rows past the last read row Ps[0] instead
+      // (their products are never stored), so the loads are unmasked and
+      // wait only where the products use them, and the loop has no
+      // divergent path.
       constexpr int CTB = (CH / 16) * W / KW;  // 16-column blocks per pass
+      constexpr bool PREF = sizeof(T) == 4;
       auto row_tile = [&](int it, T (&a)[KG], int (&pr4)[4]) {
         const int t0 = rs + 16 * it;
         const int row = t0 + lr;
-        // r0 + KW <= n here: whole row segments, branch-free
-        load_row_sigma_full(A + (int64_t)(row < n ? Ps[row] : 0) * n + r0, row < n ? KW : 0, lg,
-                            a);
+        load_row_sigma_raw((gptr<const T>)(A + (int64_t)Ps[row < n ? row : 0] * n + r0), lg, a);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int rr = t0 + acc_row(T(0), lg, v);
           pr4[v] = (rr < n) ? Ps[rr] : -1;
         }
       };
+      T a0[KG], a1[KG];
+      int p0[4], p1[4];
+      if (wave < ntr) {
+        row_tile(wave, a0, p0);
+        row_tile(wave + NW, a1, p1);
+      }
       for (int it = wave; it < ntr; it += 2 * NW) {
-        T a0[KG], a1[KG];
-        int p0[4], p1[4];
-        row_tile(it, a0, p0);
-        row_tile(it + NW, a1, p1);
+        const bool more = it + 2 * NW < ntr;
+        T b0[PREF ? KG : 1], b1[PREF ? KG : 1];
+        int q0[4], q1[4];
+        if constexpr (PREF) {
+          if (more) {
+            row_tile(it + 2 * NW, b0, q0);
+            row_tile(it + 3 * NW, b1, q1);
+          }
+        }
         // the chunk's 16-column blocks in passes of CTB, so that K = 2W keeps
         // about as many operands live as K = W
 #pragma unroll
@@ -514,6 +527,23 @@ __global__ __launch_bounds__(64 * NW) void k_getrf(const LuProb* __restrict__ pr
               if (p0[v] >= 0 && cc < ce) A[(int64_t)p0[v] * n + cc] = cur0[q][v] - acc0[v];
               if (p1[v] >= 0 && cc < ce) A[(int64_t)p1[v] * n + cc] = cur1[q][v] - acc1[v];
             }
+          }
+        }
+        if (more) {
+          if constexpr (PREF) {
+#pragma unroll
+            for (int kk = 0; kk < KG; ++kk) {
+              a0[kk] = b0[kk];
+              a1[kk] = b1[kk];
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              p0[v] = q0[v];
+              p1[v] = q1[v];
+            }
+          } else {
+            row_tile(it + 2 * NW, a0, p0);
+            row_tile(it + 3 * NW, a1, p1);
           }
         }
       }
