@@ -298,6 +298,10 @@ struct invaskit_handle_s {
   double plan_ms = 0;  // host planning of the handle (wall clock)
   hipEvent_t ev[kEvents + 2] = {};
   bool have_events = false;
+  // the factorization schedule's events ([0] timed, [1] ordering only),
+  // created on first use and reused by every later factorization: creating
+  // some fifty events per call held the host behind the GPU
+  std::vector<hipEvent_t> fev[2];
   // second stream of the factorization (default priority): the skeleton
   // blocks run on it beside the leaf block evaluation and LU
   hipStream_t side = nullptr;
@@ -337,6 +341,8 @@ struct invaskit_handle_s {
   ~invaskit_handle_s() {
     if (have_events)
       for (auto& e : ev) hipEventDestroy(e);
+    for (auto& pool : fev)
+      for (auto& e : pool) hipEventDestroy(e);
     if (side) hipStreamDestroy(side);
   }
 };
@@ -1474,22 +1480,22 @@ int run_factor_once(const std::vector<H*>& hs, const FactorPlan& fp, KernelCache
   };
   std::vector<Bracket> brackets;
   int open_on[2] = {-1, -1};
-  std::vector<hipEvent_t> pool;
+  size_t used[2] = {0, 0};  // events of h->fev taken by this factorization
   auto new_event = [&](unsigned flags) -> hipEvent_t {
+    const int k = (flags & hipEventDisableTiming) ? 1 : 0;
+    if (used[k] < h->fev[k].size()) return h->fev[k][used[k]++];
     hipEvent_t e = nullptr;
     if (hipEventCreateWithFlags(&e, flags) != hipSuccess) return nullptr;
-    pool.push_back(e);
+    h->fev[k].push_back(e);
+    ++used[k];
     return e;
   };
-  auto cleanup = [&]() {
-    for (auto e : pool) hipEventDestroy(e);
-    pool.clear();
-  };
+  // (the events stay in the handle's pool: every one this factorization
+  // records is complete once the caller's stream has been synchronized)
 #define STEP(...)                                                                 \
   do {                                                                            \
     hipError_t e_ = (__VA_ARGS__);                                                \
     if (e_ != hipSuccess) {                                                       \
-      cleanup();                                                                  \
       return fail_h(h, INVASKIT_E_HIP,                                            \
                     std::string(#__VA_ARGS__) + ": " + hipGetErrorString(e_));    \
     }                                                                             \
@@ -1542,9 +1548,11 @@ int run_factor_once(const std::vector<H*>& hs, const FactorPlan& fp, KernelCache
       STEP(close(s2));
       STEP(mark(s2, &ev_panels));
     }
+    // the FP32 copy of P, first needed by the leaf projections, which wait
+    // for the side stream
     if (!f64 && h->p_off[h->nn] > 0)
       STEP(launch_convert_f64_f32(h->P64, static_cast<float*>(const_cast<void*>(h->Pf)),
-                                  h->p_off[h->nn], s));
+                                  h->p_off[h->nn], s2));
     STEP(open(0, s));
     STEP(run_eval(h, tb, fp.leaf_eval, fp.cached ? 0.0 : h->lam, s));
     STEP(close(s));
@@ -1557,10 +1565,7 @@ int run_factor_once(const std::vector<H*>& hs, const FactorPlan& fp, KernelCache
       ev_panels = nullptr;  // complete
     }
     // the tile choices need the evaluated cache (their trials copy from it)
-    if (int rc = tune_factor(h, fp)) {
-      cleanup();
-      return rc;
-    }
+    if (int rc = tune_factor(h, fp)) return rc;
     STEP(open(0, s));
     STEP(run_copy_shift(h, tb, fp.leaf_copy, s));
     STEP(close(s));
@@ -1614,10 +1619,7 @@ int run_factor_once(const std::vector<H*>& hs, const FactorPlan& fp, KernelCache
     // level wavefront
     for (int j = L - 1; j >= 0; --j) {
       int zf = kLuFormBlock, zc = kTrsmColsDefault;
-      if (int rc = tune_level(h, tb, fp, j, s, &zf, &zc)) {
-        cleanup();
-        return rc;
-      }
+      if (int rc = tune_level(h, tb, fp, j, s, &zf, &zc)) return rc;
       for (H* hg : hs) {
         if (zf == kLuFormOneWave) hg->tiles.zlu_one_wave_levels |= 1 << j;
         if (j >= 1 && zc == 32) hg->tiles.zsolve32_levels |= 1 << j;
@@ -1651,7 +1653,6 @@ int run_factor_once(const std::vector<H*>& hs, const FactorPlan& fp, KernelCache
   // [1] and [4] cover both size classes; [10] and [11] the large leaves alone
   ms_ph[1] += ms_ph[10];
   ms_ph[4] += ms_ph[11];
-  cleanup();
 #undef STEP
   // pivot status of every member
   int status = INVASKIT_OK;
