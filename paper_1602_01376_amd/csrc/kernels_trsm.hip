@@ -56,10 +56,25 @@ __global__ __launch_bounds__(128, 2) void k_diag_inv(const DiagInvProb* __restri
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   __shared__ __align__(16) TZ B[NBK][DIP];  // B[k][i] = block entry (row i, column k)
   __shared__ TZ rdiag[NBK];
-  // consecutive threads read consecutive columns of a factor row
-  for (int idx = tid; idx < NBK * NBK; idx += 128) {
+  __shared__ int s_perm[NBK];
+  if (tid < NBK) s_perm[tid] = perm[jb + min(tid, nb - 1)];
+  __syncthreads();
+  // consecutive threads read consecutive columns of a factor row; all 32
+  // loads of a thread are issued before any is stored (indices past the
+  // block read its last row or column and are zeroed)
+  constexpr int PER = NBK * NBK / 128;
+  TZ v[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int idx = tid + 128 * q;
     const int k = idx % NBK, i = idx / NBK;
-    B[k][i] = (i < nb && k < nb) ? LU[(int64_t)perm[jb + i] * n + jb + k] : TZ(0);
+    v[q] = LU[(int64_t)s_perm[min(i, nb - 1)] * n + jb + min(k, nb - 1)];
+  }
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int idx = tid + 128 * q;
+    const int k = idx % NBK, i = idx / NBK;
+    B[k][i] = (i < nb && k < nb) ? v[q] : TZ(0);
   }
   __syncthreads();
   if (tid < NBK) rdiag[tid] = (tid < nb) ? TZ(1) / B[tid][tid] : TZ(0);
