@@ -79,13 +79,27 @@ __global__ __launch_bounds__(256) void k_eval(const PT* __restrict__ X, int d, d
     for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
 
   for (int dd = 0; dd < d; dd += DC) {
-    for (int idx = tid; idx < ET * DC; idx += 256) {
+    // all of a thread's coordinate loads are issued before any is staged
+    // (indices past the tile read its first point and are zeroed)
+    constexpr int PER = ET * DC / 256;
+    double vr[PER], vc[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int idx = tid + 256 * q;
       const int p = idx / DC, k = idx % DC;
+      const int kk = min(dd + k, d - 1);
       const int r = r0 + p;
-      const bool kin = dd + k < d;
-      xr[k][p] = (r < b.rows && kin) ? (double)X[(b.row0 + r) * d + dd + k] : 0.0;
+      vr[q] = (double)X[(b.row0 + (r < b.rows ? r : 0)) * d + kk];
       const int64_t g = cidx[p];
-      xc[k][p] = (g >= 0 && kin) ? (double)X[g * d + dd + k] : 0.0;
+      vc[q] = (double)X[(g >= 0 ? g : b.row0) * d + kk];
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int idx = tid + 256 * q;
+      const int p = idx / DC, k = idx % DC;
+      const bool kin = dd + k < d;
+      xr[k][p] = (r0 + p < b.rows && kin) ? vr[q] : 0.0;
+      xc[k][p] = (cidx[p] >= 0 && kin) ? vc[q] : 0.0;
     }
     __syncthreads();
 #pragma unroll
