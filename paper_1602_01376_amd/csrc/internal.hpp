@@ -211,12 +211,18 @@ hipError_t launch_copy_shift(const CopyShiftProb* probs, int count, hipStream_t 
 template <typename TZ, typename TV>
 hipError_t launch_zform(const ZformProb* probs, int count, hipStream_t s);
 
-// y = lam*x + sum K w  (or b - that, when b != nullptr), columns [c0, c0+nc)
+// y = lam*x + sum K w  (or b - that, when b != nullptr), columns [c0, c0+nc).
+// mode kMvWhole sums every segment of a tile; kMvNear sums only its first
+// segment (the leaf's own block) and stores the raw sum in y; kMvFar starts
+// from that sum in y and adds the remaining segments, in the same order, so
+// the two halves give the same bits as one kMvWhole launch.  The halves are
+// for d <= kMvMaxDim only.
+constexpr int kMvWhole = 0, kMvNear = 1, kMvFar = 2;
 template <typename PT>
 hipError_t launch_mv_eval(const PT* X, int d, double h, double lam, const MvTile* tiles,
                           int ntiles, const MvSeg* segs, const double* x, int64_t ldx,
                           double* y, int64_t ldy, const double* b, int64_t ldb, int nrhs,
-                          hipStream_t s);
+                          int mode, hipStream_t s);
 constexpr int kMvBlock = 128;
 constexpr int kMvMaxDim = 64;    // register-resident targets up to this d
 constexpr int kMvWideRows = 64;  // targets per tile of the d > kMvMaxDim form

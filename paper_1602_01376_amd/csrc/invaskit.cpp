@@ -302,6 +302,8 @@ struct invaskit_handle_s {
   // created on first use and reused by every later factorization: creating
   // some fifty events per call held the host behind the GPU
   std::vector<hipEvent_t> fev[2];
+  // fork and join of the product's two halves (created with the side stream)
+  hipEvent_t mv_ev[2] = {};
   // second stream of the factorization (default priority): the skeleton
   // blocks run on it beside the leaf block evaluation and LU
   hipStream_t side = nullptr;
@@ -343,6 +345,8 @@ struct invaskit_handle_s {
       for (auto& e : ev) hipEventDestroy(e);
     for (auto& pool : fev)
       for (auto& e : pool) hipEventDestroy(e);
+    for (auto& e : mv_ev)
+      if (e) hipEventDestroy(e);
     if (side) hipStreamDestroy(side);
   }
 };
@@ -1974,22 +1978,44 @@ int run_solve_plan(H* h, SolvePlan* sp) {
   return INVASKIT_OK;
 }
 
-// y = (lam I + K~) x  (or b - that when b != nullptr); x is copied first
+// y = (lam I + K~) x  (or b - that when b != nullptr); x is copied first.
+// With `overlap` (and d <= kMvMaxDim), the leaves' own blocks are summed on
+// the side stream while the caller's stream forms the skeleton weights
+// (Skeletonize), which only the other segments need; their raw sums wait
+// in y and the second half continues from them in the same order, so the
+// result is that of one whole pass bit for bit.
 int run_matvec(H* h, const Buf& tb, const MatvecPlan& mp, const double* x, int64_t ldx, double* y,
-               int64_t ldy, const double* b, int64_t ldb) {
+               int64_t ldy, const double* b, int64_t ldb, bool overlap) {
   hipStream_t s = h->stream;
   const int r = mp.r;
   double* xm = static_cast<double*>(mp.xm.p);
   HIP_TRY(h, launch_copy_cols<double, double>(x, ldx, xm, h->N, h->N, r, nullptr, false, s));
-  for (const GemmL& g : mp.skel) HIP_TRY(h, run_gemm(tb, g, true, s));
   const MvTile* t = at<MvTile>(tb, mp.mv_tiles);
   const MvSeg* g = at<MvSeg>(tb, mp.mv_segs);
-  if (h->pdt == INVASKIT_F64)
-    HIP_TRY(h, launch_mv_eval<double>(static_cast<const double*>(h->X), h->d, h->h, h->lam, t,
-                                      mp.n_mv_tiles, g, xm, h->N, y, ldy, b, ldb, r, s));
-  else
-    HIP_TRY(h, launch_mv_eval<float>(static_cast<const float*>(h->X), h->d, h->h, h->lam, t,
-                                     mp.n_mv_tiles, g, xm, h->N, y, ldy, b, ldb, r, s));
+  auto eval = [&](int mode, hipStream_t st) -> hipError_t {
+    if (h->pdt == INVASKIT_F64)
+      return launch_mv_eval<double>(static_cast<const double*>(h->X), h->d, h->h, h->lam, t,
+                                    mp.n_mv_tiles, g, xm, h->N, y, ldy, b, ldb, r, mode, st);
+    return launch_mv_eval<float>(static_cast<const float*>(h->X), h->d, h->h, h->lam, t,
+                                 mp.n_mv_tiles, g, xm, h->N, y, ldy, b, ldb, r, mode, st);
+  };
+  const bool split = overlap && h->side && h->L > 0 && h->d <= kMvMaxDim;
+  if (split && !h->mv_ev[0]) {
+    for (auto& e : h->mv_ev) HIP_TRY(h, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
+  if (split) {
+    HIP_TRY(h, hipEventRecord(h->mv_ev[0], s));
+    HIP_TRY(h, hipStreamWaitEvent(h->side, h->mv_ev[0], 0));
+    HIP_TRY(h, eval(kMvNear, h->side));
+    HIP_TRY(h, hipEventRecord(h->mv_ev[1], h->side));
+  }
+  for (const GemmL& gl : mp.skel) HIP_TRY(h, run_gemm(tb, gl, true, s));
+  if (split) {
+    HIP_TRY(h, hipStreamWaitEvent(s, h->mv_ev[1], 0));
+    HIP_TRY(h, eval(kMvFar, s));
+  } else {
+    HIP_TRY(h, eval(kMvWhole, s));
+  }
   return INVASKIT_OK;
 }
 
@@ -2116,7 +2142,7 @@ int gmres_cycle(H* h, SolvePlan* sp, const std::vector<double>& rn,
     double* vn = V + (size_t)(j + 1) * blk;
     double* zj = Zb + (size_t)j * blk;
     if (int rc = apply_precond(h, sp, vj, zj)) return rc;
-    if (int rc = run_matvec(h, sp->tables, sp->mv, zj, N, vn, N, nullptr, 0)) return rc;
+    if (int rc = run_matvec(h, sp->tables, sp->mv, zj, N, vn, N, nullptr, 0, true)) return rc;
     // classical Gram-Schmidt, twice
     HIP_TRY(h, launch_dots(V, blk, N, j + 1, vn, N, N, r, part, h1d, s));
     HIP_TRY(h, launch_lincomb(vn, N, V, blk, N, j + 1, h1d, r, -1.0, N, s));
@@ -2205,7 +2231,7 @@ int do_solve(H* h, SolvePlan* sp, const double* b, int64_t ldb, double* x, int64
   double best = 1.0, prev = 1.0, hist[3] = {INFINITY, INFINITY, INFINITY};
   bool x_is_best_zero = true, last_is_best = true, conv = false, to_gmres = false;
   auto residual = [&]() -> int {  // r64 = b - A x64 and its norms
-    int e = run_matvec(h, sp->tables, sp->mv, x64, N, r64, N, b, ldb);
+    int e = run_matvec(h, sp->tables, sp->mv, x64, N, r64, N, b, ldb, true);
     if (e) return e;
     return col_norms2(h, sp, r64, N, r, rn);
   };
@@ -2649,7 +2675,7 @@ int invaskit_matvec(invaskit_handle h, const double* x, int64_t nrhs, int64_t ld
   int rc = check_workspace(h, scratch, scratch_bytes, sp->min_bytes, "scratch");
   if (rc) return rc;
   if ((rc = bind_scratch(h, sp, scratch_bytes, false))) return rc;
-  return run_matvec(h, sp->tables, sp->mv, x, ldx, y, ldy, nullptr, 0);
+  return run_matvec(h, sp->tables, sp->mv, x, ldx, y, ldy, nullptr, 0, true);
 }
 
 int invaskit_matvec_noalloc(invaskit_handle h, const double* x, int64_t nrhs, int64_t ldx,
@@ -2669,7 +2695,8 @@ int invaskit_matvec_noalloc(invaskit_handle h, const double* x, int64_t nrhs, in
                       std::to_string((size_t)INVASKIT_STATIC_SCRATCH_BYTES));
   // other handles may have used the array since: always copy the tables
   if ((rc = bind_scratch(h, sp, INVASKIT_STATIC_SCRATCH_BYTES, true))) return rc;
-  return run_matvec(h, sp->tables, sp->mv, x, ldx, y, ldy, nullptr, 0);
+  // one stream, one pass: nothing beyond the caller's stream is involved
+  return run_matvec(h, sp->tables, sp->mv, x, ldx, y, ldy, nullptr, 0, false);
 }
 
 int invaskit_device_bytes(invaskit_handle h, size_t* bytes) {

@@ -311,7 +311,7 @@ __global__ __launch_bounds__(MB / TPT) void k_mv_eval(const PT* __restrict__ X, 
                                                       const double* __restrict__ x, int64_t ldx,
                                                       double* __restrict__ y, int64_t ldy,
                                                       const double* __restrict__ bsub, int64_t ldb,
-                                                      int nrhs) {
+                                                      int nrhs, int mode) {
   constexpr int NT = MB / TPT;
   __shared__ __align__(16) double sx[MS][DM];  // source coordinates minus z
   __shared__ double sn[MS];                    // c |y - z|^2 of each source
@@ -350,10 +350,17 @@ __global__ __launch_bounds__(MB / TPT) void k_mv_eval(const PT* __restrict__ X, 
     const int ncol = min(RC, nrhs - cb);
     double acc[TPT][RC];
 #pragma unroll
-    for (int u = 0; u < TPT; ++u)
+    for (int u = 0; u < TPT; ++u) {
+      const int r = tid + NT * u;
 #pragma unroll
-      for (int c = 0; c < RC; ++c) acc[u][c] = 0.0;
-    for (int s = t.seg0; s < t.seg0 + t.nseg; ++s) {
+      for (int c = 0; c < RC; ++c)
+        acc[u][c] = (mode == kMvFar && r < t.rows && c < ncol)
+                        ? y[(int64_t)(cb + c) * ldy + t.row0 + r]
+                        : 0.0;
+    }
+    const int s_lo = t.seg0 + (mode == kMvFar ? 1 : 0);
+    const int s_hi = mode == kMvNear ? t.seg0 + 1 : t.seg0 + t.nseg;
+    for (int s = s_lo; s < s_hi; ++s) {
       const MvSeg g = segs[s];
       for (int j0 = 0; j0 < g.count; j0 += MS) {
         const int nj = min(MS, g.count - j0);
@@ -416,6 +423,10 @@ __global__ __launch_bounds__(MB / TPT) void k_mv_eval(const PT* __restrict__ X, 
       if (r < t.rows) {
         const int64_t i = t.row0 + r;
         for (int c = 0; c < ncol; ++c) {
+          if (mode == kMvNear) {
+            y[(int64_t)(cb + c) * ldy + i] = acc[u][c];
+            continue;
+          }
           const double ax = lam * x[(int64_t)(cb + c) * ldx + i] + acc[u][c];
           y[(int64_t)(cb + c) * ldy + i] = bsub ? bsub[(int64_t)(cb + c) * ldb + i] - ax : ax;
         }
@@ -537,13 +548,14 @@ template <typename PT>
 hipError_t launch_mv_eval(const PT* X, int d, double h, double lam, const MvTile* tiles,
                           int ntiles, const MvSeg* segs, const double* x, int64_t ldx,
                           double* y, int64_t ldy, const double* b, int64_t ldb, int nrhs,
-                          hipStream_t s) {
+                          int mode, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
+  if (mode != kMvWhole && d > kMvMaxDim) return hipErrorInvalidValue;
   const double c = -0.5 / (h * h);
 #define INVASKIT_MV(DMV, RCV)                                                                \
   hipLaunchKernelGGL((k_mv_eval<PT, DMV, (DMV <= 16 ? 2 : 1), RCV>), dim3(ntiles),          \
                      dim3(MB / (DMV <= 16 ? 2 : 1)), 0, s, X, d, c, lam, tiles, segs, x, ldx, y, \
-                     ldy, b, ldb, nrhs)
+                     ldy, b, ldb, nrhs, mode)
 #define INVASKIT_MV_RC(RCV)                                                                  \
   if (d <= 8)                                                                                \
     INVASKIT_MV(8, RCV);                                                                     \
@@ -580,9 +592,9 @@ template hipError_t launch_eval<float, float>(const float*, int, double, double,
                                               const EvalBlock*, const Tile3*, int, hipStream_t);
 template hipError_t launch_mv_eval<double>(const double*, int, double, double, const MvTile*,
                                            int, const MvSeg*, const double*, int64_t, double*,
-                                           int64_t, const double*, int64_t, int, hipStream_t);
+                                           int64_t, const double*, int64_t, int, int, hipStream_t);
 template hipError_t launch_mv_eval<float>(const float*, int, double, double, const MvTile*, int,
                                           const MvSeg*, const double*, int64_t, double*, int64_t,
-                                          const double*, int64_t, int, hipStream_t);
+                                          const double*, int64_t, int, int, hipStream_t);
 
 }  // namespace invaskit
