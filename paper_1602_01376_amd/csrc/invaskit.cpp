@@ -1544,19 +1544,30 @@ int run_factor_once(const std::vector<H*>& hs, const FactorPlan& fp, KernelCache
   STEP(join(s, s2));
   const bool eval_now = !fp.cached || !kc->valid;
   hipEvent_t ev_panels = nullptr, ev_leaf = nullptr, ev_side = nullptr;
+  // The skeleton blocks are first needed by the leaf solves.  A plain
+  // factorization evaluates them on the side stream after the leaf blocks,
+  // beside the large leaves' LU (latency-bound, it leaves the vector units
+  // mostly idle), rather than beside the leaf blocks, which start the
+  // critical path.  A sweep's cache is filled before anything else.
+  const bool panels_late = eval_now && !fp.cached && L > 0;
+  // the FP32 copy of P, first needed by the leaf projections, which wait
+  // for the side stream
+  auto convert_p = [&]() -> hipError_t {
+    if (f64 || h->p_off[h->nn] <= 0) return hipSuccess;
+    return launch_convert_f64_f32(h->P64, static_cast<float*>(const_cast<void*>(h->Pf)),
+                                  h->p_off[h->nn], s2);
+  };
+  auto eval_panels = [&]() -> hipError_t {
+    hipError_t e = open(3, s2);
+    if (e == hipSuccess) e = run_eval(h, tb, fp.panels, 0.0, s2);
+    if (e == hipSuccess) e = close(s2);
+    if (e == hipSuccess) e = mark(s2, &ev_panels);
+    return e == hipSuccess ? convert_p() : e;
+  };
   if (eval_now) {
     // kernel blocks (into the factor storage, or once into a sweep's cache)
-    if (L > 0) {
-      STEP(open(3, s2));
-      STEP(run_eval(h, tb, fp.panels, 0.0, s2));
-      STEP(close(s2));
-      STEP(mark(s2, &ev_panels));
-    }
-    // the FP32 copy of P, first needed by the leaf projections, which wait
-    // for the side stream
-    if (!f64 && h->p_off[h->nn] > 0)
-      STEP(launch_convert_f64_f32(h->P64, static_cast<float*>(const_cast<void*>(h->Pf)),
-                                  h->p_off[h->nn], s2));
+    if (L > 0 && !panels_late) STEP(eval_panels());
+    if (L == 0) STEP(convert_p());
     STEP(open(0, s));
     STEP(run_eval(h, tb, fp.leaf_eval, fp.cached ? 0.0 : h->lam, s));
     STEP(close(s));
@@ -1583,20 +1594,23 @@ int run_factor_once(const std::vector<H*>& hs, const FactorPlan& fp, KernelCache
     return l;
   };
   // small leaves on the second stream: LU, inverses and solves beside the
-  // large leaves' LU (their skeleton blocks were evaluated earlier on it)
-  if (fp.leaf_lu[1].count > 0) {
-    STEP(hipStreamWaitEvent(s2, ev_leaf, 0));
+  // large leaves' LU, with the skeleton blocks between them unless they
+  // were evaluated already
+  const bool small = fp.leaf_lu[1].count > 0;
+  if (small || panels_late) STEP(hipStreamWaitEvent(s2, ev_leaf, 0));
+  if (small) {
     STEP(open(1, s2));
     STEP(run_lu(tb, lu_of(fp.leaf_lu[1]), s2));
     STEP(close(s2));
     STEP(open(2, s2));
     STEP(run_dinv(tb, fp.leaf_dinv[1], s2));
     STEP(close(s2));
-    if (L > 0) {
-      STEP(open(4, s2));
-      STEP(run_trsm(tb, fp.leaf_trsm[1][h->tiles.leaf_trsm_cols_small == 32 ? 1 : 0], s2));
-      STEP(close(s2));
-    }
+  }
+  if (panels_late) STEP(eval_panels());
+  if (small && L > 0) {
+    STEP(open(4, s2));
+    STEP(run_trsm(tb, fp.leaf_trsm[1][h->tiles.leaf_trsm_cols_small == 32 ? 1 : 0], s2));
+    STEP(close(s2));
   }
   STEP(mark(s2, &ev_side));
   if (fp.leaf_lu[0].count > 0) {
