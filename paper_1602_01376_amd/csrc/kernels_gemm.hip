@@ -167,6 +167,20 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmProb* __restrict__ probs
   }
 }
 
+// Calls f(std::integral_constant<int, NC>) with NC = n (1 .. kGemvCols): the
+// skinny products' column loops get a compile-time trip count, so their
+// loads carry no per-column branch (a load under a branch was waited for
+// before the next one issued).
+template <typename F>
+__device__ __forceinline__ void with_cols(int n, F&& f) {
+  switch (n) {
+    case 1: f(std::integral_constant<int, 1>{}); break;
+    case 2: f(std::integral_constant<int, 2>{}); break;
+    case 3: f(std::integral_constant<int, 3>{}); break;
+    default: f(std::integral_constant<int, kGemvCols>{}); break;
+  }
+}
+
 // Skinny products (N <= 4 columns, every A column-major, M <= 128): one
 // workgroup per product.  The 256 threads cover R rows by 256 / R groups of
 // K, R the smallest power of two (16 .. 128) not below M, so that short
@@ -188,18 +202,20 @@ __global__ __launch_bounds__(256) void k_gemv(const GemmProb* __restrict__ probs
   T acc[kGemvCols];
 #pragma unroll
   for (int c = 0; c < kGemvCols; ++c) acc[c] = T(0);
-  for (int sg = P.seg0; sg < P.seg0 + P.nseg; ++sg) {
-    const GemmSeg g = segs[sg];
-    const gptr<const T> A = glb(static_cast<const T*>(g.A)) + (rin ? row : 0);
-    const gptr<const T> B = glb(static_cast<const T*>(g.B));
+  with_cols(P.N, [&](auto NCc) {
+    constexpr int NC = decltype(NCc)::value;
+    for (int sg = P.seg0; sg < P.seg0 + P.nseg; ++sg) {
+      const GemmSeg g = segs[sg];
+      const gptr<const T> A = glb(static_cast<const T*>(g.A)) + (rin ? row : 0);
+      const gptr<const T> B = glb(static_cast<const T*>(g.B));
 #pragma unroll 8
-    for (int k = kg; k < g.k; k += G) {
-      const T a = A[(int64_t)k * g.lda];
+      for (int k = kg; k < g.k; k += G) {
+        const T a = A[(int64_t)k * g.lda];
 #pragma unroll
-      for (int c = 0; c < kGemvCols; ++c)
-        if (c < P.N) acc[c] = fma(a, B[(int64_t)c * g.ldb + k], acc[c]);
+        for (int c = 0; c < NC; ++c) acc[c] = fma(a, B[(int64_t)c * g.ldb + k], acc[c]);
+      }
     }
-  }
+  });
 #pragma unroll
   for (int c = 0; c < kGemvCols; ++c) part[tid][c] = rin ? acc[c] : T(0);
   __syncthreads();
@@ -243,30 +259,31 @@ __global__ __launch_bounds__(256) void k_gemv_tall(const GemmProb* __restrict__ 
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int c = 0; c < kGemvCols; ++c) acc[i][c] = T(0);
-  for (int sg = P.seg0; sg < P.seg0 + P.nseg; ++sg) {
-    const GemmSeg g = segs[sg];
-    const gptr<const T> A = glb(static_cast<const T*>(g.A)) + (nr > 0 ? row : 0);
-    const gptr<const T> B = glb(static_cast<const T*>(g.B));
+  with_cols(P.N, [&](auto NCc) {
+    constexpr int NC = decltype(NCc)::value;
+    for (int sg = P.seg0; sg < P.seg0 + P.nseg; ++sg) {
+      const GemmSeg g = segs[sg];
+      const gptr<const T> A = glb(static_cast<const T*>(g.A)) + (nr > 0 ? row : 0);
+      const gptr<const T> B = glb(static_cast<const T*>(g.B));
 #pragma unroll 4
-    for (int k = wave; k < g.k; k += 4) {
-      const gptr<const T> ak = A + (int64_t)k * g.lda;
-      vec4 a;
-      if (nr == 4) {
-        a = *(gptr<const vec4>)ak;
-      } else {
+      for (int k = wave; k < g.k; k += 4) {
+        const gptr<const T> ak = A + (int64_t)k * g.lda;
+        vec4 a;
+        if (nr == 4) {
+          a = *(gptr<const vec4>)ak;
+        } else {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) a[i] = (i < nr) ? ak[i] : T(0);
-      }
+          for (int i = 0; i < 4; ++i) a[i] = (i < nr) ? ak[i] : T(0);
+        }
 #pragma unroll
-      for (int c = 0; c < kGemvCols; ++c) {
-        if (c < P.N) {
+        for (int c = 0; c < NC; ++c) {
           const T b = B[(int64_t)c * g.ldb + k];
 #pragma unroll
           for (int i = 0; i < 4; ++i) acc[i][c] = fma(a[i], b, acc[i][c]);
         }
       }
     }
-  }
+  });
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -301,18 +318,20 @@ __global__ __launch_bounds__(256) void k_gemv_rm(const GemmProb* __restrict__ pr
     T acc[kGemvCols];
 #pragma unroll
     for (int c = 0; c < kGemvCols; ++c) acc[c] = T(0);
-    for (int sg = P.seg0; sg < P.seg0 + P.nseg; ++sg) {
-      const GemmSeg g = segs[sg];
-      const gptr<const T> A = glb(static_cast<const T*>(g.A)) + (int64_t)row * g.lda;
-      const gptr<const T> B = glb(static_cast<const T*>(g.B));
+    with_cols(P.N, [&](auto NCc) {
+      constexpr int NC = decltype(NCc)::value;
+      for (int sg = P.seg0; sg < P.seg0 + P.nseg; ++sg) {
+        const GemmSeg g = segs[sg];
+        const gptr<const T> A = glb(static_cast<const T*>(g.A)) + (int64_t)row * g.lda;
+        const gptr<const T> B = glb(static_cast<const T*>(g.B));
 #pragma unroll 4
-      for (int k = lane; k < g.k; k += 64) {
-        const T a = A[k];
+        for (int k = lane; k < g.k; k += 64) {
+          const T a = A[k];
 #pragma unroll
-        for (int c = 0; c < kGemvCols; ++c)
-          if (c < P.N) acc[c] = fma(a, B[(int64_t)c * g.ldb + k], acc[c]);
+          for (int c = 0; c < NC; ++c) acc[c] = fma(a, B[(int64_t)c * g.ldb + k], acc[c]);
+        }
       }
-    }
+    });
 #pragma unroll
     for (int c = 0; c < kGemvCols; ++c)
       if (c < P.N)
