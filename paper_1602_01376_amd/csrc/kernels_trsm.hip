@@ -198,19 +198,25 @@ __global__ __launch_bounds__(256) void k_getrs(const TrsmProb* __restrict__ prob
     // X_b = inv(diagonal block) X_b: wave w computes rows 16w .. 16w+15 of
     // each 16-column tile
     {
-      V4 acc[CT];
+      // every column tile's LDS reads are issued before the first product
+      // (the scheduling barrier keeps the compiler from sinking each read
+      // next to its product, which serialized the reads' latencies)
+      TZ bb[CT][NBK / 4];
 #pragma unroll
-      for (int ct = 0; ct < CT; ++ct) {
-        acc[ct] = V4{0, 0, 0, 0};
-        TZ bb[NBK / 4];  // all LDS reads issued before the products
+      for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
         for (int kk = 0; kk < NBK / 4; ++kk) {
           const int k = sigma_k<TZ>(kk, lg);
           const TZ v = X[min(jb + k, n - 1) * RTP + 16 * ct + lr];
-          bb[kk] = (k < nb) ? v : TZ(0);
+          bb[ct][kk] = (k < nb) ? v : TZ(0);
         }
+      __builtin_amdgcn_sched_barrier(0);
+      V4 acc[CT];
 #pragma unroll
-        for (int kk = 0; kk < NBK / 4; ++kk) acc[ct] = mfma16(da[kk], bb[kk], acc[ct]);
+      for (int ct = 0; ct < CT; ++ct) {
+        acc[ct] = V4{0, 0, 0, 0};
+#pragma unroll
+        for (int kk = 0; kk < NBK / 4; ++kk) acc[ct] = mfma16(da[kk], bb[ct][kk], acc[ct]);
       }
       __syncthreads();
 #pragma unroll
