@@ -197,7 +197,7 @@ struct FactorPlan {
   EvalL panels;         // skeleton blocks of every level (into W storage or the cache)
   TrsmL leaf_trsm[2][2];  // [class][16 or 32 right-hand sides per workgroup]
                           // (ntiles < 0: no room in LDS)
-  GemmL leaf_proj;      // leaf projections of every level's panel columns
+  GemmL leaf_proj[2];   // leaf projections of every level's panel columns, by size class
   std::vector<ZformL> zform;  // index j: reduced systems of level j
   std::vector<LuL> zlu;
   std::vector<DinvL> zdinv;
@@ -908,7 +908,7 @@ void build_factor_tables(const std::vector<H*>& hs, const KernelCache* kc, Arena
     std::vector<LuProb> lus[2];
     std::vector<DiagInvProb> dis[2];
     TrsmBuilder tb[2];
-    GemmBuilder proj;
+    GemmBuilder proj[2];
     int nmax[2] = {0, 0};
     const int small_leaf = T64 ? kSmallLeaf64 : kSmallLeaf32;
     for (size_t g = 0; g < hs.size(); ++g) {
@@ -981,8 +981,9 @@ void build_factor_tables(const std::vector<H*>& hs, const KernelCache* kc, Arena
         }
         tb[cls].add(lu, hg->DL(j), static_cast<const int32_t*>(hg->leafPerm.p) + h->na[lf], m,
                     h->S[j], kin, m, m, kin, m, slab, m);
-        proj.begin(offv(hg->psw.p, h->psw_off[lf], es), h->s[lf], h->s[lf], h->S[j], 1.0, 0.0);
-        proj.seg(offv(hg->Pt(), h->p_off[lf], es), m, true, slab, m, m);
+        proj[cls].begin(offv(hg->psw.p, h->psw_off[lf], es), h->s[lf], h->s[lf], h->S[j], 1.0,
+                        0.0);
+        proj[cls].seg(offv(hg->Pt(), h->p_off[lf], es), m, true, slab, m, m);
       }
     }
     fp.leaf_eval.blocks = ar.add(lblocks);
@@ -1012,7 +1013,7 @@ void build_factor_tables(const std::vector<H*>& hs, const KernelCache* kc, Arena
       fp.leaf_trsm[c][0] = tb[c].emit(ar, T64, T64, 0, 16);
       fp.leaf_trsm[c][1] = tb[c].emit(ar, T64, T64, 0, 32);
     }
-    fp.leaf_proj = proj.emit(ar);
+    for (int c = 0; c < 2; ++c) fp.leaf_proj[c] = proj[c].emit(ar);
   }
   // wavefront over levels j = L-1 .. 0
   fp.zform.assign(std::max(L, 1), ZformL());
@@ -1561,8 +1562,8 @@ int run_factor_once(const std::vector<H*>& hs, const FactorPlan& fp, KernelCache
     hipError_t e = open(3, s2);
     if (e == hipSuccess) e = run_eval(h, tb, fp.panels, 0.0, s2);
     if (e == hipSuccess) e = close(s2);
-    if (e == hipSuccess) e = mark(s2, &ev_panels);
-    return e == hipSuccess ? convert_p() : e;
+    if (e == hipSuccess) e = convert_p();
+    return e == hipSuccess ? mark(s2, &ev_panels) : e;  // both are ready at ev_panels
   };
   if (eval_now) {
     // kernel blocks (into the factor storage, or once into a sweep's cache)
@@ -1611,6 +1612,10 @@ int run_factor_once(const std::vector<H*>& hs, const FactorPlan& fp, KernelCache
     STEP(open(4, s2));
     STEP(run_trsm(tb, fp.leaf_trsm[1][h->tiles.leaf_trsm_cols_small == 32 ? 1 : 0], s2));
     STEP(close(s2));
+    // the small leaves' projections, beside the large leaves' solves
+    STEP(open(5, s2));
+    STEP(run_gemm(tb, fp.leaf_proj[1], f64, s2));
+    STEP(close(s2));
   }
   STEP(mark(s2, &ev_side));
   if (fp.leaf_lu[0].count > 0) {
@@ -1629,11 +1634,13 @@ int run_factor_once(const std::vector<H*>& hs, const FactorPlan& fp, KernelCache
       STEP(close(s));
     }
   }
+  if (L > 0) {
+    STEP(open(12, s));  // added into [5] below
+    STEP(run_gemm(tb, fp.leaf_proj[0], f64, s));
+    STEP(close(s));
+  }
   STEP(hipStreamWaitEvent(s, ev_side, 0));  // the small leaves are done
   if (L > 0) {
-    STEP(open(5, s));
-    STEP(run_gemm(tb, fp.leaf_proj, f64, s));
-    STEP(close(s));
     // level wavefront
     for (int j = L - 1; j >= 0; --j) {
       int zf = kLuFormBlock, zc = kTrsmColsDefault;
@@ -1659,7 +1666,7 @@ int run_factor_once(const std::vector<H*>& hs, const FactorPlan& fp, KernelCache
   }
   STEP(hipEventRecord(t_end, s));
   STEP(hipStreamSynchronize(s));
-  double ms_ph[kPhases] = {0};
+  double ms_ph[kPhases + 1] = {0};  // [12]: the large leaves' projections
   for (const Bracket& br : brackets) {
     float ms = 0.f;
     if (br.a && br.b && hipEventElapsedTime(&ms, br.a, br.b) == hipSuccess) ms_ph[br.phase] += ms;
@@ -1668,9 +1675,11 @@ int run_factor_once(const std::vector<H*>& hs, const FactorPlan& fp, KernelCache
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, t_begin, t_end) == hipSuccess) ms_ph[9] = ms;
   }
-  // [1] and [4] cover both size classes; [10] and [11] the large leaves alone
+  // [1], [4] and [5] cover both size classes; [10], [11] and [12] the large
+  // leaves alone
   ms_ph[1] += ms_ph[10];
   ms_ph[4] += ms_ph[11];
+  ms_ph[5] += ms_ph[12];
 #undef STEP
   // pivot status of every member
   int status = INVASKIT_OK;
