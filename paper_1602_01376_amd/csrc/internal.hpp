@@ -161,8 +161,9 @@ constexpr int kGemvCols = 4;
 constexpr int kGemvRows = 128;
 constexpr int kGemvRmMinK = 128;
 constexpr int kGemvSplitK = 1, kGemvRowMajor = 3;
-// kGemvTall: A column-major, M above kGemvRows: one row per thread,
-// workgroups of kGemvTallRows rows listed in a tile table (Tile3: prob, tm)
+// kGemvTall: A column-major, M above kGemvRows: workgroups of kGemvTallRows
+// rows listed in a tile table (Tile3: prob, tm), four consecutive rows per
+// lane (one 16-byte load per column), the four waves splitting K
 constexpr int kGemvTall = 4;
 constexpr int kGemvTallRows = 256;
 template <typename T>
