@@ -27,7 +27,10 @@
  *    a solve's or product's scratch (invaskit_solve_workspace_bytes,
  *    invaskit_matvec_workspace_bytes), all DEVICE, 256-byte aligned, and
  *    frees them after the handle is destroyed.  A workspace or scratch that
- *    is too small fails with INVASKIT_E_WORKSPACE before any launch.
+ *    is too small fails with INVASKIT_E_WORKSPACE before any launch.  A
+ *    handle holds one small pinned HOST buffer (hipHostMalloc, freed by
+ *    invaskit_destroy) into which the pivot status and the refinement's
+ *    column norms are copied back with the stream.
  */
 #ifndef INVASKIT_H
 #define INVASKIT_H

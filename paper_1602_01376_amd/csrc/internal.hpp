@@ -234,6 +234,8 @@ hipError_t launch_convert_f64_f32(const double* in, float* out, int64_t n, hipSt
 template <typename TI, typename TO>
 hipError_t launch_copy_cols(const TI* in, int64_t ldi, TO* out, int64_t ldo, int64_t n,
                             int ncols, const double* scale, bool invert_scale, hipStream_t s);
+// scale[c] = sqrt(norm2[c]), c < ncols
+hipError_t launch_sqrt_cols(const double* norm2, double* scale, int ncols, hipStream_t s);
 // x[i + c*ldx] += scale[c] * d[i + c*ldd]
 template <typename TD>
 hipError_t launch_axpy_cols(double* x, int64_t ldx, const TD* d, int64_t ldd, int64_t n,

@@ -237,7 +237,6 @@ struct SolvePlan {
   std::vector<GemmL> topdown;  // e = (I + U)^-1 y^, levels 2 .. L
   GemmL final_;
   MatvecPlan mv;
-  std::vector<double> host_scale;
 };
 
 }  // namespace
@@ -307,6 +306,10 @@ struct invaskit_handle_s {
   // second stream of the factorization (default priority): the skeleton
   // blocks run on it beside the leaf block evaluation and LU
   hipStream_t side = nullptr;
+  // pinned host memory for the small readbacks (pivot status, column
+  // norms), so that they complete with the stream instead of blocking
+  void* pin = nullptr;
+  size_t pin_bytes = 0;
   invaskit_tile_config tiles{};   // tile shapes of the last factor
   std::string err;
 
@@ -348,6 +351,7 @@ struct invaskit_handle_s {
     for (auto& e : mv_ev)
       if (e) hipEventDestroy(e);
     if (side) hipStreamDestroy(side);
+    if (pin) hipHostFree(pin);
   }
 };
 
@@ -368,6 +372,21 @@ int fail_h(H* h, int code, const std::string& msg) {
       return fail_h((h), INVASKIT_E_HIP,                                                 \
                     std::string(#__VA_ARGS__) + ": " + hipGetErrorString(e_));           \
   } while (0)
+
+// The handle's pinned host buffer, grown to at least `bytes`.  Growing it
+// frees the old one, so callers reserve it while no copy into it is pending.
+int host_pinned(H* h, size_t bytes, void** out) {
+  if (h->pin_bytes < bytes) {
+    if (h->pin) HIP_TRY(h, hipHostFree(h->pin));
+    h->pin = nullptr;
+    h->pin_bytes = 0;
+    const size_t want = std::max(bytes, (size_t)4096);
+    HIP_TRY(h, hipHostMalloc(&h->pin, want, hipHostMallocDefault));
+    h->pin_bytes = want;
+  }
+  *out = h->pin;
+  return INVASKIT_OK;
+}
 
 int check_device(H* h) {
   int dev = 0;
@@ -1476,6 +1495,17 @@ int run_factor_once(const std::vector<H*>& hs, const FactorPlan& fp, KernelCache
   }
   if (!h->side) HIP_TRY(h, hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
   hipStream_t s2 = h->side;
+  // the members' pivot status (leaf blocks, reduced systems) is read back
+  // into the pinned buffer with the factorization
+  std::vector<size_t> info_at(hs.size() + 1, 0);
+  for (size_t g = 0; g < hs.size(); ++g)
+    info_at[g + 1] = info_at[g] + hs[g]->nleaves + std::max((1 << hs[g]->L) - 1, 0);
+  int32_t* info_host = nullptr;
+  {
+    void* p = nullptr;
+    if (int rc = host_pinned(h, sizeof(int32_t) * info_at.back(), &p)) return rc;
+    info_host = static_cast<int32_t*>(p);
+  }
   // Phase timing: each phase is bracketed by two events on the stream it
   // runs on; phases on the two streams overlap, so they need not sum to the
   // total.  `join` events order the streams.
@@ -1665,12 +1695,25 @@ int run_factor_once(const std::vector<H*>& hs, const FactorPlan& fp, KernelCache
     }
   }
   STEP(hipEventRecord(t_end, s));
-  STEP(hipStreamSynchronize(s));
+  for (size_t g = 0; g < hs.size(); ++g) {
+    H* hg = hs[g];
+    const size_t nz = info_at[g + 1] - info_at[g] - hg->nleaves;
+    STEP(hipMemcpyAsync(info_host + info_at[g], hg->leafInfo.p, sizeof(int32_t) * hg->nleaves,
+                        hipMemcpyDeviceToHost, s));
+    if (nz > 0)
+      STEP(hipMemcpyAsync(info_host + info_at[g] + hg->nleaves, hg->zinfo.p,
+                          sizeof(int32_t) * nz, hipMemcpyDeviceToHost, s));
+  }
+  // each phase's time is read as soon as it has ended, while the GPU works
+  // on the phases after it (the wavefront's levels), not all at the end
   double ms_ph[kPhases + 1] = {0};  // [12]: the large leaves' projections
   for (const Bracket& br : brackets) {
+    if (!br.a || !br.b) continue;
+    STEP(hipEventSynchronize(br.b));
     float ms = 0.f;
-    if (br.a && br.b && hipEventElapsedTime(&ms, br.a, br.b) == hipSuccess) ms_ph[br.phase] += ms;
+    if (hipEventElapsedTime(&ms, br.a, br.b) == hipSuccess) ms_ph[br.phase] += ms;
   }
+  STEP(hipStreamSynchronize(s));
   {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, t_begin, t_end) == hipSuccess) ms_ph[9] = ms;
@@ -1683,16 +1726,14 @@ int run_factor_once(const std::vector<H*>& hs, const FactorPlan& fp, KernelCache
 #undef STEP
   // pivot status of every member
   int status = INVASKIT_OK;
-  for (H* hg : hs) {
+  for (size_t g = 0; g < hs.size(); ++g) {
+    H* hg = hs[g];
     for (int i = 0; i < kPhases; ++i) hg->phase_ms[i] = ms_ph[i];
     hg->phase_ms[7] = hg->plan_ms;
     hg->tiles = h->tiles;
-    std::vector<int32_t> li(hg->nleaves), zi(std::max((1 << hg->L) - 1, 0));
-    HIP_TRY(h, hipMemcpy(li.data(), hg->leafInfo.p, sizeof(int32_t) * li.size(),
-                         hipMemcpyDeviceToHost));
-    if (!zi.empty())
-      HIP_TRY(h, hipMemcpy(zi.data(), hg->zinfo.p, sizeof(int32_t) * zi.size(),
-                           hipMemcpyDeviceToHost));
+    const int32_t* li = info_host + info_at[g];
+    const int32_t* zi = li + hg->nleaves;
+    const size_t nz = info_at[g + 1] - info_at[g] - hg->nleaves;
     int rc = INVASKIT_OK;
     for (int j = 0; j < hg->nleaves && !rc; ++j) {
       if (!li[j]) continue;
@@ -1706,7 +1747,7 @@ int run_factor_once(const std::vector<H*>& hs, const FactorPlan& fp, KernelCache
                   "zero pivot: leaf block of node " + std::to_string(hg->leaf_node(j)) +
                       " column " + std::to_string(li[j] - 1));
     }
-    for (size_t a = 0; a < zi.size() && !rc; ++a)
+    for (size_t a = 0; a < nz && !rc; ++a)
       if (zi[a])
         rc = fail_h(hg, INVASKIT_E_SINGULAR,
                     "zero pivot: reduced system of node " + std::to_string(a) + " column " +
@@ -2045,14 +2086,33 @@ int run_matvec(H* h, const Buf& tb, const MatvecPlan& mp, const double* x, int64
 // ------------------------------------------------------------ refinement
 // Column norms^2 of an N x r FP64 block (deterministic two-pass sums), read
 // back to the host.
-int col_norms2(H* h, SolvePlan* sp, const double* v, int64_t ld, int r, std::vector<double>& host) {
+// Squared 2-norms of the r columns of v into sp->gsmall[0, r) on the
+// device and, for slot 0 or 1, copied on into the handle's pinned buffer at
+// [slot * r, slot * r + r) (read after the stream is synchronized; slot -1:
+// no copy).  The pinned buffer is reserved for two slots first.
+int col_norms2_launch(H* h, SolvePlan* sp, const double* v, int64_t ld, int r, int slot) {
   double* part = static_cast<double*>(sp->gpart.p);
   double* out = static_cast<double*>(sp->gsmall.p);
   HIP_TRY(h, launch_dots(v, 0, ld, 1, v, ld, h->N, r, part, out, h->stream));
-  host.assign(r, 0.0);
-  HIP_TRY(h, hipMemcpyAsync(host.data(), out, sizeof(double) * r, hipMemcpyDeviceToHost,
-                            h->stream));
+  if (slot < 0) return INVASKIT_OK;
+  void* pin = nullptr;
+  if (int rc = host_pinned(h, sizeof(double) * 2 * r, &pin)) return rc;
+  HIP_TRY(h, hipMemcpyAsync(static_cast<double*>(pin) + (size_t)slot * r, out, sizeof(double) * r,
+                            hipMemcpyDeviceToHost, h->stream));
+  return INVASKIT_OK;
+}
+
+// the norms of slot `slot` once the stream has reached them
+void pinned_norms(H* h, int r, int slot, std::vector<double>& host) {
+  const double* p = static_cast<const double*>(h->pin) + (size_t)slot * r;
+  host.assign(p, p + r);
+}
+
+// col_norms2_launch into slot 1, then a wait for the stream
+int col_norms2(H* h, SolvePlan* sp, const double* v, int64_t ld, int r, std::vector<double>& host) {
+  if (int rc = col_norms2_launch(h, sp, v, ld, r, 1)) return rc;
   HIP_TRY(h, hipStreamSynchronize(h->stream));
+  pinned_norms(h, r, 1, host);
   return INVASKIT_OK;
 }
 
@@ -2069,18 +2129,16 @@ double worst_rel(const std::vector<double>& rn, const std::vector<double>& bn) {
 // One refinement step x64 += M^-1 r64, with M^-1 the factors' direct solve
 // (FP32 in mixed mode).  Each residual column is divided by its norm before
 // the solve (so FP32 holds it at full relative precision) and the
-// correction multiplied back.
-int ir_step(H* h, SolvePlan* sp, const std::vector<double>& rn) {
+// correction multiplied back.  The squared norms are those the last
+// col_norms2_launch left in sp->gsmall (the residual r64's).
+int ir_step(H* h, SolvePlan* sp) {
   hipStream_t s = h->stream;
   const int r = sp->r;
   const int64_t N = h->N;
   double* x64 = static_cast<double*>(sp->x64.p);
   double* r64 = static_cast<double*>(sp->r64.p);
   double* sc = static_cast<double*>(sp->sc.p);
-  sp->host_scale.resize(r);
-  for (int c = 0; c < r; ++c) sp->host_scale[c] = std::sqrt(rn[c]);
-  HIP_TRY(h, hipMemcpyAsync(sc, sp->host_scale.data(), sizeof(double) * r, hipMemcpyHostToDevice,
-                            s));
+  HIP_TRY(h, launch_sqrt_cols(static_cast<const double*>(sp->gsmall.p), sc, r, s));
   if (h->prec == INVASKIT_PREC_FP64) {
     double* xb = static_cast<double*>(sp->xbuf.p);
     HIP_TRY(h, launch_copy_cols<double, double>(r64, N, xb, N, N, r, sc, true, s));
@@ -2092,8 +2150,6 @@ int ir_step(H* h, SolvePlan* sp, const std::vector<double>& rn) {
     if (int rc = run_solve_plan(h, sp)) return rc;
     HIP_TRY(h, launch_axpy_cols<float>(x64, N, xb, N, N, r, sc, s));
   }
-  // the host vector must outlive the asynchronous copy: the caller's next
-  // step synchronizes (the residual norms) before it is rewritten
   return INVASKIT_OK;
 }
 
@@ -2245,7 +2301,18 @@ int do_solve(H* h, SolvePlan* sp, const double* b, int64_t ldb, double* x, int64
   invaskit_solve_info loc{};
   loc.method = mode == INVASKIT_REFINE_NONE ? INVASKIT_REFINE_NONE : INVASKIT_REFINE_IR;
   std::vector<double> bn, rn;
-  if ((rc = col_norms2(h, sp, b, ldb, r, bn))) return rc;
+  // The norms of b: the refinement reads them on the host only after its
+  // first residual, which waits for the stream anyway, so they are copied
+  // back without a wait of their own (slot 0); a direct solve that reports
+  // nothing never reads them.  GMRES from the start reads them at once.
+  const bool bn_now = mode == INVASKIT_REFINE_GMRES;
+  bool have_bn = bn_now;
+  if (bn_now) {
+    if ((rc = col_norms2(h, sp, b, ldb, r, bn))) return rc;
+  } else if ((rc = col_norms2_launch(h, sp, b, ldb, r,
+                                     mode == INVASKIT_REFINE_NONE && !info ? -1 : 0))) {
+    return rc;
+  }
   HIP_TRY(h, launch_zero_cols(x64, N, N, r, s));
   HIP_TRY(h, launch_copy_cols<double, double>(b, ldb, r64, N, N, r, nullptr, false, s));
   rn = bn;
@@ -2256,7 +2323,12 @@ int do_solve(H* h, SolvePlan* sp, const double* b, int64_t ldb, double* x, int64
   auto residual = [&]() -> int {  // r64 = b - A x64 and its norms
     int e = run_matvec(h, sp->tables, sp->mv, x64, N, r64, N, b, ldb, true);
     if (e) return e;
-    return col_norms2(h, sp, r64, N, r, rn);
+    if ((e = col_norms2(h, sp, r64, N, r, rn))) return e;
+    if (!have_bn) {  // the stream has passed the copy of b's norms
+      pinned_norms(h, r, 0, bn);
+      have_bn = true;
+    }
+    return INVASKIT_OK;
   };
   auto keep_if_best = [&](double worst) -> int {
     last_is_best = worst < best;
@@ -2271,7 +2343,7 @@ int do_solve(H* h, SolvePlan* sp, const double* b, int64_t ldb, double* x, int64
   if (mode != INVASKIT_REFINE_GMRES) {
     const int cap = mode == INVASKIT_REFINE_NONE ? 1 : h->maxit;
     for (it = 1; it <= cap; ++it) {
-      if ((rc = ir_step(h, sp, rn))) return rc;
+      if ((rc = ir_step(h, sp))) return rc;
       if (mode == INVASKIT_REFINE_NONE && !info) {
         HIP_TRY(h, launch_copy_cols<double, double>(x64, N, x, ldx, N, r, nullptr, false, s));
         return INVASKIT_OK;

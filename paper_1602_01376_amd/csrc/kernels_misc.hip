@@ -56,6 +56,12 @@ __global__ void k_copy_cols(const TI* __restrict__ in, int64_t ldi, TO* __restri
     out[c * ldo + i] = (TO)((double)in[c * ldi + i] * s);
 }
 
+__global__ void k_sqrt_cols(const double* __restrict__ norm2, double* __restrict__ scale,
+                            int ncols) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < ncols) scale[c] = sqrt(norm2[c]);
+}
+
 template <typename TD>
 __global__ void k_axpy_cols(double* __restrict__ x, int64_t ldx, const TD* __restrict__ d,
                             int64_t ldd, int64_t n, const double* __restrict__ scale) {
@@ -187,6 +193,12 @@ template hipError_t launch_copy_cols<double, float>(const double*, int64_t, floa
 template hipError_t launch_copy_cols<float, double>(const float*, int64_t, double*, int64_t,
                                                     int64_t, int, const double*, bool,
                                                     hipStream_t);
+
+hipError_t launch_sqrt_cols(const double* norm2, double* scale, int ncols, hipStream_t s) {
+  if (ncols <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sqrt_cols, dim3((ncols + 255) / 256), dim3(256), 0, s, norm2, scale, ncols);
+  return hipGetLastError();
+}
 
 template <typename TD>
 hipError_t launch_axpy_cols(double* x, int64_t ldx, const TD* d, int64_t ldd, int64_t n,
