@@ -2090,11 +2090,17 @@ int run_matvec(H* h, const Buf& tb, const MatvecPlan& mp, const double* x, int64
 // device and, for slot 0 or 1, copied on into the handle's pinned buffer at
 // [slot * r, slot * r + r) (read after the stream is synchronized; slot -1:
 // no copy).  The pinned buffer is reserved for two slots first.
+int norms_back(H* h, SolvePlan* sp, int r, int slot);
 int col_norms2_launch(H* h, SolvePlan* sp, const double* v, int64_t ld, int r, int slot) {
   double* part = static_cast<double*>(sp->gpart.p);
   double* out = static_cast<double*>(sp->gsmall.p);
   HIP_TRY(h, launch_dots(v, 0, ld, 1, v, ld, h->N, r, part, out, h->stream));
-  if (slot < 0) return INVASKIT_OK;
+  return slot < 0 ? INVASKIT_OK : norms_back(h, sp, r, slot);
+}
+
+// the copy of sp->gsmall[0, r) into slot `slot` of the pinned buffer
+int norms_back(H* h, SolvePlan* sp, int r, int slot) {
+  const double* out = static_cast<const double*>(sp->gsmall.p);
   void* pin = nullptr;
   if (int rc = host_pinned(h, sizeof(double) * 2 * r, &pin)) return rc;
   HIP_TRY(h, hipMemcpyAsync(static_cast<double*>(pin) + (size_t)slot * r, out, sizeof(double) * r,
@@ -2126,29 +2132,36 @@ double worst_rel(const std::vector<double>& rn, const std::vector<double>& bn) {
   return worst;
 }
 
-// One refinement step x64 += M^-1 r64, with M^-1 the factors' direct solve
-// (FP32 in mixed mode).  Each residual column is divided by its norm before
-// the solve (so FP32 holds it at full relative precision) and the
-// correction multiplied back.  The squared norms are those the last
-// col_norms2_launch left in sp->gsmall (the residual r64's).
-int ir_step(H* h, SolvePlan* sp) {
+// One refinement step x64 += M^-1 res, with M^-1 the factors' direct
+// solve (FP32 in mixed mode) and res the residual (r64; b itself for the
+// first step, which sets x64 = M^-1 b instead of adding to it).  Each
+// residual column is divided by its norm before the solve (so FP32 holds it
+// at full relative precision) and the correction multiplied back.  The
+// squared norms are those the last col_norms2_launch left in sp->gsmall
+// (the residual's).
+int ir_step(H* h, SolvePlan* sp, const double* res, int64_t ldres, bool first) {
   hipStream_t s = h->stream;
   const int r = sp->r;
   const int64_t N = h->N;
   double* x64 = static_cast<double*>(sp->x64.p);
-  double* r64 = static_cast<double*>(sp->r64.p);
   double* sc = static_cast<double*>(sp->sc.p);
   HIP_TRY(h, launch_sqrt_cols(static_cast<const double*>(sp->gsmall.p), sc, r, s));
   if (h->prec == INVASKIT_PREC_FP64) {
     double* xb = static_cast<double*>(sp->xbuf.p);
-    HIP_TRY(h, launch_copy_cols<double, double>(r64, N, xb, N, N, r, sc, true, s));
+    HIP_TRY(h, launch_copy_cols<double, double>(res, ldres, xb, N, N, r, sc, true, s));
     if (int rc = run_solve_plan(h, sp)) return rc;
-    HIP_TRY(h, launch_axpy_cols<double>(x64, N, xb, N, N, r, sc, s));
+    if (first)
+      HIP_TRY(h, launch_copy_cols<double, double>(xb, N, x64, N, N, r, sc, false, s));
+    else
+      HIP_TRY(h, launch_axpy_cols<double>(x64, N, xb, N, N, r, sc, s));
   } else {
     float* xb = static_cast<float*>(sp->xbuf.p);
-    HIP_TRY(h, launch_copy_cols<double, float>(r64, N, xb, N, N, r, sc, true, s));
+    HIP_TRY(h, launch_copy_cols<double, float>(res, ldres, xb, N, N, r, sc, true, s));
     if (int rc = run_solve_plan(h, sp)) return rc;
-    HIP_TRY(h, launch_axpy_cols<float>(x64, N, xb, N, N, r, sc, s));
+    if (first)
+      HIP_TRY(h, launch_copy_cols<float, double>(xb, N, x64, N, N, r, sc, false, s));
+    else
+      HIP_TRY(h, launch_axpy_cols<float>(x64, N, xb, N, N, r, sc, s));
   }
   return INVASKIT_OK;
 }
@@ -2303,18 +2316,20 @@ int do_solve(H* h, SolvePlan* sp, const double* b, int64_t ldb, double* x, int64
   std::vector<double> bn, rn;
   // The norms of b: the refinement reads them on the host only after its
   // first residual, which waits for the stream anyway, so they are copied
-  // back without a wait of their own (slot 0); a direct solve that reports
-  // nothing never reads them.  GMRES from the start reads them at once.
+  // back without a wait of their own (slot 0), enqueued behind the first
+  // step; a direct solve that reports nothing never reads them.  GMRES
+  // from the start reads them at once.  The first step reads b itself and
+  // sets x64 (GMRES sets up its own start).
   const bool bn_now = mode == INVASKIT_REFINE_GMRES;
+  const bool bn_back = !bn_now && !(mode == INVASKIT_REFINE_NONE && !info);
   bool have_bn = bn_now;
   if (bn_now) {
     if ((rc = col_norms2(h, sp, b, ldb, r, bn))) return rc;
-  } else if ((rc = col_norms2_launch(h, sp, b, ldb, r,
-                                     mode == INVASKIT_REFINE_NONE && !info ? -1 : 0))) {
-    return rc;
+  } else {
+    void* pin = nullptr;  // reserved before anything is in flight
+    if (bn_back && (rc = host_pinned(h, sizeof(double) * 2 * r, &pin))) return rc;
+    if ((rc = col_norms2_launch(h, sp, b, ldb, r, -1))) return rc;
   }
-  HIP_TRY(h, launch_zero_cols(x64, N, N, r, s));
-  HIP_TRY(h, launch_copy_cols<double, double>(b, ldb, r64, N, N, r, nullptr, false, s));
   rn = bn;
   // x = 0 is the first candidate (relative residual 1); the caller's x
   // always holds the best iterate so far
@@ -2343,7 +2358,8 @@ int do_solve(H* h, SolvePlan* sp, const double* b, int64_t ldb, double* x, int64
   if (mode != INVASKIT_REFINE_GMRES) {
     const int cap = mode == INVASKIT_REFINE_NONE ? 1 : h->maxit;
     for (it = 1; it <= cap; ++it) {
-      if ((rc = ir_step(h, sp))) return rc;
+      if ((rc = it == 1 ? ir_step(h, sp, b, ldb, true) : ir_step(h, sp, r64, N, false))) return rc;
+      if (it == 1 && bn_back && (rc = norms_back(h, sp, r, 0))) return rc;
       if (mode == INVASKIT_REFINE_NONE && !info) {
         HIP_TRY(h, launch_copy_cols<double, double>(x64, N, x, ldx, N, r, nullptr, false, s));
         return INVASKIT_OK;
