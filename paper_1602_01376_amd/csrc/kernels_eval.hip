@@ -313,6 +313,9 @@ __global__ __launch_bounds__(MB / TPT) void k_mv_eval(const PT* __restrict__ X, 
                                                       const double* __restrict__ bsub, int64_t ldb,
                                                       int nrhs, int mode) {
   constexpr int NT = MB / TPT;
+  constexpr int LIT = (MS * DM + NT - 1) / NT;  // source coordinates per thread and stage
+  constexpr int LCH = LIT < 4 ? LIT : 4;        // of them loaded together
+  static_assert(LIT % LCH == 0, "stage loads in whole chunks");
   __shared__ __align__(16) double sx[MS][DM];  // source coordinates minus z
   __shared__ double sn[MS];                    // c |y - z|^2 of each source
   __shared__ __align__(16) double sw[MS][RC];
@@ -332,14 +335,22 @@ __global__ __launch_bounds__(MB / TPT) void k_mv_eval(const PT* __restrict__ X, 
   __syncthreads();
   const double m2c = -2.0 * nhalf_inv_h2;
   double xi[TPT][DM], cx[TPT];
+  // the targets' coordinates: every load issued before the first is used
+  // (rows and coordinates clamped into range, masked afterwards), so that
+  // they are in flight together instead of one after another
 #pragma unroll
   for (int u = 0; u < TPT; ++u) {
-    const int r = tid + NT * u;
-    const bool active = r < t.rows;
+    const int64_t rr = t.row0 + min(tid + NT * u, t.rows - 1);
+#pragma unroll
+    for (int k = 0; k < DM; ++k) xi[u][k] = (double)X[rr * d + min(k, d - 1)];
+  }
+#pragma unroll
+  for (int u = 0; u < TPT; ++u) {
+    const bool active = tid + NT * u < t.rows;
     double nrm = 0.0;
 #pragma unroll
     for (int k = 0; k < DM; ++k) {
-      const double v = (active && k < d) ? (double)X[(t.row0 + r) * d + k] - zc[k] : 0.0;
+      const double v = (active && k < d) ? xi[u][k] - zc[k] : 0.0;
       nrm = fma(v, v, nrm);
       xi[u][k] = m2c * v;
     }
@@ -365,18 +376,36 @@ __global__ __launch_bounds__(MB / TPT) void k_mv_eval(const PT* __restrict__ X, 
       for (int j0 = 0; j0 < g.count; j0 += MS) {
         const int nj = min(MS, g.count - j0);
         __syncthreads();
-        for (int idx = tid; idx < MS * DM; idx += NT) {
-          const int j = idx / DM, k = idx % DM;
-          double v = 0.0;
-          if (j < nj && k < d) {
-            const int64_t p = g.idx ? (int64_t)glb(g.idx)[j0 + j] : g.p0 + j0 + j;
-            v = (double)X[p * d + k] - zc[k];
+        // the stage's source coordinates, LCH loads in flight at a time:
+        // first their point indices, then the coordinates (sources and
+        // coordinates clamped into range, masked when stored)
+        for (int i0 = 0; i0 < LIT; i0 += LCH) {
+          int64_t pp[LCH];
+          double xv[LCH];
+          if (g.idx) {  // (uniform: one branch around all the index loads)
+            const gptr<const int32_t> gi = glb(g.idx) + j0;
+#pragma unroll
+            for (int u = 0; u < LCH; ++u) pp[u] = gi[min((tid + NT * (i0 + u)) / DM, nj - 1)];
+          } else {
+#pragma unroll
+            for (int u = 0; u < LCH; ++u)
+              pp[u] = g.p0 + j0 + min((tid + NT * (i0 + u)) / DM, nj - 1);
           }
-          sx[j][k] = v;
+#pragma unroll
+          for (int u = 0; u < LCH; ++u)
+            xv[u] = (double)X[pp[u] * d + min((tid + NT * (i0 + u)) % DM, d - 1)];
+#pragma unroll
+          for (int u = 0; u < LCH; ++u) {
+            const int idx = tid + NT * (i0 + u);
+            const int j = idx / DM, k = idx % DM;
+            if (idx < MS * DM) sx[j][k] = (j < nj && k < d) ? xv[u] - zc[k] : 0.0;
+          }
         }
         for (int idx = tid; idx < MS * RC; idx += NT) {
           const int j = idx / RC, c = idx % RC;
-          sw[j][c] = (j < nj && c < ncol) ? glb(g.w)[(int64_t)(cb + c) * g.ldw + j0 + j] : 0.0;
+          const double v =
+              glb(g.w)[(int64_t)(cb + min(c, ncol - 1)) * g.ldw + j0 + min(j, nj - 1)];
+          sw[j][c] = (j < nj && c < ncol) ? v : 0.0;
         }
         __syncthreads();
         if (tid < MS) {
