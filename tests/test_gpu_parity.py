@@ -519,10 +519,12 @@ def test_fp64_direct_solve_reports_its_residual(bind, problems):
     b = rhs_for(pb, nrhs=2)
     x_ref = oracle.solve(F, b)
     fac = bind.Factorization(pb, pb.lam, precision="fp64", refine="none")
-    x = fac.solve(torch.from_numpy(b)).cpu().numpy()
-    _assert_close(x, x_ref, 1e-10, "no info")
+    x0 = fac.solve(torch.from_numpy(b)).cpu().numpy()
+    _assert_close(x0, x_ref, 1e-10, "no info")
     x, info, st = fac.solve(torch.from_numpy(b), return_info=True)
     assert st == 0 and info["converged"] == 1 and info["iterations"] == 1
+    # the same direct solve, whether or not its residual is read back
+    assert np.array_equal(x.cpu().numpy(), x0)
     assert info["method"] == "none" and info["final_rel_residual"] <= 1e-12
     assert info["final_rel_residual"] == info["unrefined_rel_residual"]
     fac.close()
