@@ -451,7 +451,11 @@ __global__ __launch_bounds__(MB / TPT) void k_mv_eval(const PT* __restrict__ X, 
       const int r = tid + NT * u;
       if (r < t.rows) {
         const int64_t i = t.row0 + r;
-        for (int c = 0; c < ncol; ++c) {
+        // unrolled over RC (guarded by ncol) so that acc stays in registers:
+        // a loop bound known only at run time would index it dynamically
+#pragma unroll
+        for (int c = 0; c < RC; ++c) {
+          if (c >= ncol) continue;
           if (mode == kMvNear) {
             y[(int64_t)(cb + c) * ldy + i] = acc[u][c];
             continue;
