@@ -2084,12 +2084,11 @@ int run_matvec(H* h, const Buf& tb, const MatvecPlan& mp, const double* x, int64
 }
 
 // ------------------------------------------------------------ refinement
-// Column norms^2 of an N x r FP64 block (deterministic two-pass sums), read
-// back to the host.
-// Squared 2-norms of the r columns of v into sp->gsmall[0, r) on the
-// device and, for slot 0 or 1, copied on into the handle's pinned buffer at
-// [slot * r, slot * r + r) (read after the stream is synchronized; slot -1:
-// no copy).  The pinned buffer is reserved for two slots first.
+// Squared 2-norms of the r columns of an N x r FP64 block v (deterministic
+// two-pass sums) into sp->gsmall[0, r) on the device and, for slot 0 or 1,
+// copied on into the handle's pinned buffer at [slot * r, slot * r + r)
+// (read after the stream is synchronized; slot -1: no copy).  The pinned
+// buffer is reserved for two slots first.
 int norms_back(H* h, SolvePlan* sp, int r, int slot);
 int col_norms2_launch(H* h, SolvePlan* sp, const double* v, int64_t ld, int r, int slot) {
   double* part = static_cast<double*>(sp->gpart.p);
